@@ -1,0 +1,202 @@
+/*
+ * nlsp.h - C ABI of the MI355X (gfx950) spectral two-level PCG library.
+ *
+ * The library solves A u = f for a sparse SPD operator A (Sec. 3, "PDE
+ * discretization and linear systems") with conjugate gradients preconditioned
+ * by the two-grid cycle of the NeuraLSP algorithm ("setup and one
+ * preconditioner application"): nu weighted-Jacobi sweeps, a Galerkin coarse
+ * correction with A_c = P^T A P, and nu more sweeps.  The prolongation P is the
+ * leading k-dimensional left singular subspace of relaxed random vectors
+ * S = (I - w D^-1 A)^{s1} S0 (Sec. 3, near-nullspace vectors and SVD-centric
+ * construction).
+ *
+ * Conventions shared by every entry point
+ *   - Buffers marked "device" are device pointers owned by the caller; the
+ *     library never frees them.  Host arrays are marked "host".
+ *   - Dense matrices are row-major.  Vectors of R right-hand sides are (n, R)
+ *     with the R values of one unknown contiguous.  Unknowns are numbered
+ *     x fastest: i = x + nx*(y + ny*z).
+ *   - Scratch memory comes from a caller-provided device workspace whose size
+ *     is returned by the matching *_workspace_bytes query (256-byte aligned
+ *     base required).  The library allocates no device memory.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *     Functions that must return a status computed on the device synchronise
+ *     that stream before returning; this is stated per function.
+ *   - Arguments are validated on the host before any HIP call; invalid
+ *     arguments return NLSP_E_INVALID and enqueue nothing.
+ *   - No function throws, aborts or exits.  Every function returns an
+ *     nlsp_status value (int).
+ */
+#ifndef NLSP_H
+#define NLSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum nlsp_status {
+  NLSP_OK = 0,
+  NLSP_NOT_CONVERGED = 1,   /* warning: maxit reached; outputs valid, info filled */
+  NLSP_E_INVALID = -1,      /* bad argument (checked on the host)               */
+  NLSP_E_NOT_SPD = -2,      /* Cholesky of A_c or of a Gram matrix failed       */
+  NLSP_E_BREAKDOWN = -3,    /* p^T A p <= 0 or r^T M^-1 r <= 0 in PCG           */
+  NLSP_E_NONFINITE = -4,    /* NaN/Inf in a PCG scalar                          */
+  NLSP_E_WORKSPACE = -5,    /* workspace too small or misaligned                */
+  NLSP_E_HIP = -6,          /* a HIP runtime call failed                        */
+  NLSP_E_RANK = -7          /* relaxed vectors numerically rank-deficient       */
+};
+
+/* Human-readable name of a status code (static string). */
+const char* nlsp_status_string(int status);
+
+/* ------------------------------------------------------------ operators */
+/* Matrix-free SPD operators on structured grids (the paper's PDE families are
+ * P1 FEM on meshes of the unit square; these are structured members of the
+ * same families, homogeneous Dirichlet boundary eliminated, no 1/h^2 scale). */
+enum nlsp_op_kind {
+  NLSP_OP_POISSON5 = 0,   /* 2-D 5-point Laplacian: 4 on the diagonal, -1 per neighbour; coef unused */
+  NLSP_OP_FV5 = 1,        /* 2-D cell-centred FV for -div(a grad u): face weight = harmonic mean
+                             2 a_P a_Q / (a_P + a_Q); wall face 2 a_P.  coef = a, (ny, nx) */
+  NLSP_OP_FV7 = 2,        /* the same in 3-D, 7-point; coef = a, (nz, ny, nx) */
+  NLSP_OP_STENCIL9 = 3    /* 2-D constant 9-point stencil; coef = 9 doubles c[(dy+1)*3 + (dx+1)],
+                             (A u)_(x,y) = sum c[..] u_(x+dx, y+dy), terms outside the grid dropped */
+};
+
+typedef struct {
+  int kind;               /* enum nlsp_op_kind */
+  int nx, ny, nz;         /* unknowns per axis; nz = 1 for 2-D kinds */
+  const double* coef;     /* device; see kind; NULL for NLSP_OP_POISSON5 */
+} nlsp_operator;
+
+/* Number of unknowns n = nx*ny*nz, or -1 for an invalid descriptor. */
+int64_t nlsp_operator_size(const nlsp_operator* A);
+
+/* Build the 9-point stencil of bilinear (Q1) finite elements for
+ * -div(K grad u), K = R(theta) diag(1, eps) R(theta)^T constant per system, on a
+ * uniform grid with the boundary eliminated (element stiffness by 2x2 Gauss
+ * quadrature; the anisotropic diffusion family of the paper's appendix, with
+ * one tensor per system).
+ *   eps_theta  device, (nsys, 2): eps > 0, theta
+ *   stencil    device, (nsys, 9): output, layout of NLSP_OP_STENCIL9
+ * Asynchronous. */
+int q1_aniso_stencil(int nsys, const double* eps_theta, double* stencil, void* stream);
+
+/* y = A x in float64 for R right-hand sides; x, y device (n, R).  Asynchronous. */
+int apply_operator(const nlsp_operator* A, const double* x, double* y, int R, void* stream);
+
+/* One weighted-Jacobi sweep y = x + w D^-1 (b - A x) for R right-hand sides,
+ * float32 vectors and arithmetic (the smoother of the algorithm's
+ * preconditioner application); b, x, y device (n, R) float32, x != y.
+ * Asynchronous. */
+int jacobi_sweep_f32(const nlsp_operator* A, double omega, const float* b, const float* x,
+                     float* y, int R, void* stream);
+
+/* --------------------------------------------------------------- precision */
+enum nlsp_precision {
+  NLSP_FP64 = 0,     /* everything in float64 */
+  NLSP_MIXED = 1     /* relaxation, smoother and P/Q products in float32; PCG
+                        recurrences, dot products, reductions, Cholesky and the
+                        orthonormalisation of P in float64 */
+};
+
+/* ------------------------------------------------------------ setup: P */
+/* Padded rank used by the solver's coarse-space buffers: the smallest power of
+ * two >= max(k, 16).  Returns -1 if k < 1 or k > 256. */
+int nlsp_padded_rank(int k);
+
+size_t setup_spectral_P_workspace_bytes(const nlsp_operator* A, int m, int k, int prec);
+
+/* Spectral prolongation (Sec. 3; algorithm setup):
+ *   S = (I - w D^-1 A)^{s1} S0               relaxation of m random vectors
+ *   G = S^T S, G = V diag(lambda) V^T         Gram matrix and its eigenpairs
+ *   P0 = S V_k diag(lambda_k)^{-1/2}          leading left singular vectors
+ *   P  = CholeskyQR2(P0)                      re-orthonormalised in float64
+ * Span(P) is the dominant k-dimensional left singular subspace of S
+ * (Eckart-Young); each column is signed so that its largest-magnitude entry
+ * is positive.
+ *   S0     device (n, m) float64, read only
+ *   m, k   1 <= k <= m <= 256, m <= n
+ *   omega  Jacobi damping, 0 < omega
+ *   s1     relaxation sweeps, s1 >= 0
+ *   prec   NLSP_FP64: S kept in float64; NLSP_MIXED: S relaxed in float32
+ *   P      device (n, k) float64, output, P^T P = I
+ *   sigma  device (m,) float64, output: singular values of S, descending
+ * Synchronises `stream`; returns NLSP_E_RANK when sigma_k <= 1e-13 sigma_1
+ * (P is then not meaningful) and NLSP_E_NOT_SPD when an orthonormalisation
+ * Gram matrix is not positive definite. */
+int setup_spectral_P(const nlsp_operator* A, const double* S0, int m, int k, double omega,
+                     int s1, int prec, double* P, double* sigma, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* ------------------------------------------------------- setup: coarse */
+size_t galerkin_coarse_workspace_bytes(const nlsp_operator* A, int k);
+
+/* Galerkin coarse operator and the solver's coarse-space factors (algorithm
+ * setup; appendix, two-level subspace correction):
+ *   A_c  = P^T A P (exactly symmetrised), A_c = L L^T (Cholesky)
+ *   Linv = L^{-1}, zero-padded to (kp, kp), kp = nlsp_padded_rank(k)
+ *   Q    = (I - w D^-1 A)^nu P, zero-padded to (n, kp)
+ * With these the two-grid preconditioner of the algorithm (nu pre- and nu
+ * post-sweeps, z = 0 start) equals, in exact arithmetic,
+ *   M^-1 r = J_{2nu} r + Q A_c^-1 Q^T r,
+ * where J_{2nu} r is 2 nu weighted-Jacobi sweeps on A z = r from z = 0.
+ *   P     device (n, k) float64, full column rank
+ *   Ac    device (k, k) float64, output
+ *   L     device (k, k) float64, output (lower triangle; upper set to 0)
+ *   Linv  device (kp, kp) float64, output
+ *   Q64   device (n, kp) float64 output, or NULL
+ *   Q32   device (n, kp) float32 output, or NULL (at least one of Q64/Q32)
+ * Synchronises `stream`; returns NLSP_E_NOT_SPD when A_c is not positive
+ * definite. */
+int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega, int nu,
+                    double* Ac, double* L, double* Linv, double* Q64, float* Q32,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- solve */
+typedef struct {
+  int k;                 /* coarse rank (k >= 1) */
+  int nu;                /* smoothing sweeps, nu1 = nu2 = nu >= 1 */
+  double omega;          /* Jacobi damping used to build Q */
+  int prec;              /* NLSP_FP64 reads Q64, NLSP_MIXED reads Q32 */
+  const double* Linv;    /* device (kp, kp) from galerkin_coarse */
+  const double* Q64;     /* device (n, kp) or NULL */
+  const float* Q32;      /* device (n, kp) or NULL */
+} nlsp_two_level;
+
+typedef struct {
+  double rtol;           /* stop when ||f - A u||_2 <= rtol ||f||_2 (per RHS) */
+  int maxit;             /* iteration cap (products A p), >= 1 */
+  int flexible;          /* 0: beta = r'z / r_old'z_old; 1: Polak-Ribiere beta */
+  int check_every;       /* iterations enqueued between host convergence polls (>= 1) */
+} nlsp_pcg_opts;
+
+typedef struct {
+  int iters;             /* number of products A p performed */
+  int status;            /* NLSP_OK, NLSP_NOT_CONVERGED, NLSP_E_BREAKDOWN or NLSP_E_NONFINITE */
+  double relres;         /* true ||f - A u||_2 / ||f||_2 at exit, float64 */
+} nlsp_rhs_info;
+
+size_t pcg_solve_workspace_bytes(const nlsp_operator* A, int k, int R);
+
+/* Preconditioned conjugate gradients (Hestenes-Stiefel; Sec. 4.1 two-grid
+ * solver evaluation) with the two-level preconditioner above, independently
+ * for each of R right-hand sides.  On meeting the tolerance with the
+ * recursive residual the true residual f - A u is formed; if it fails it
+ * replaces the recursive one and the iteration continues.
+ *   f     device (n, R) float64
+ *   u     device (n, R) float64: initial guess in, solution out
+ *   info  host array of R records, output
+ * Returns the worst per-RHS status (errors before NOT_CONVERGED before OK).
+ * Synchronises `stream` (convergence is polled from the host). */
+int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, double* u,
+              int R, const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws,
+              size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLSP_H */

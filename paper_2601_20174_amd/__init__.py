@@ -1,0 +1,16 @@
+"""MI355X (gfx950) spectral two-level preconditioned conjugate gradients.
+
+The method (NeuraLSP, SVD-derived basis): relax random vectors with weighted
+Jacobi, take the leading left singular subspace of the result as the
+prolongation P, form the Galerkin operator A_c = P^T A P and precondition CG
+with the two-grid cycle (Jacobi smoothing + coarse correction).  All
+arithmetic runs in the HIP library libnlsp.so (C ABI in include/nlsp.h); this
+package only marshals torch tensors into it.
+"""
+from .api import (  # noqa: F401
+    OK, NOT_CONVERGED, E_INVALID, E_NOT_SPD, E_BREAKDOWN, E_NONFINITE, E_WORKSPACE, E_HIP, E_RANK,
+    FP64, MIXED, OP_POISSON5, OP_FV5, OP_FV7, OP_STENCIL9, NlspError, Operator, TwoLevel, RhsInfo,
+    status_string, nlsp_operator_size, nlsp_padded_rank, q1_aniso_stencil, apply_operator,
+    jacobi_sweep_f32, setup_spectral_P_workspace_bytes, setup_spectral_P,
+    galerkin_coarse_workspace_bytes, galerkin_coarse, pcg_solve_workspace_bytes, pcg_solve,
+)

@@ -1,0 +1,75 @@
+"""ctypes declarations of the C ABI in include/nlsp.h.
+
+The shared library ``libnlsp.so`` is built in-tree by
+``paper_2601_20174_amd.build.build()``.  Loading fails loudly when it is
+missing: there is no CPU fallback anywhere in the package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnlsp.so")
+
+c_int, c_double, c_size_t, c_void_p, c_int64 = (ctypes.c_int, ctypes.c_double, ctypes.c_size_t,
+                                                 ctypes.c_void_p, ctypes.c_int64)
+
+
+class NlspOperator(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("coef", c_void_p)]
+
+
+class NlspTwoLevel(ctypes.Structure):
+    _fields_ = [("k", c_int), ("nu", c_int), ("omega", c_double), ("prec", c_int),
+                ("Linv", c_void_p), ("Q64", c_void_p), ("Q32", c_void_p)]
+
+
+class NlspPcgOpts(ctypes.Structure):
+    _fields_ = [("rtol", c_double), ("maxit", c_int), ("flexible", c_int), ("check_every", c_int)]
+
+
+class NlspRhsInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int), ("status", c_int), ("relres", c_double)]
+
+
+POP = ctypes.POINTER(NlspOperator)
+
+# name -> (restype, argtypes); every symbol declared in include/nlsp.h
+SIGNATURES = {
+    "nlsp_status_string": (ctypes.c_char_p, [c_int]),
+    "nlsp_operator_size": (c_int64, [POP]),
+    "nlsp_padded_rank": (c_int, [c_int]),
+    "q1_aniso_stencil": (c_int, [c_int, c_void_p, c_void_p, c_void_p]),
+    "apply_operator": (c_int, [POP, c_void_p, c_void_p, c_int, c_void_p]),
+    "jacobi_sweep_f32": (c_int, [POP, c_double, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "setup_spectral_P_workspace_bytes": (c_size_t, [POP, c_int, c_int, c_int]),
+    "setup_spectral_P": (c_int, [POP, c_void_p, c_int, c_int, c_double, c_int, c_int, c_void_p,
+                                 c_void_p, c_void_p, c_size_t, c_void_p]),
+    "galerkin_coarse_workspace_bytes": (c_size_t, [POP, c_int]),
+    "galerkin_coarse": (c_int, [POP, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pcg_solve_workspace_bytes": (c_size_t, [POP, c_int, c_int]),
+    "pcg_solve": (c_int, [POP, ctypes.POINTER(NlspTwoLevel), c_void_p, c_void_p, c_int,
+                          ctypes.POINTER(NlspPcgOpts), ctypes.POINTER(NlspRhsInfo), c_void_p,
+                          c_size_t, c_void_p]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load libnlsp.so once and declare every exported function."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2601_20174_amd.build.build() "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib

@@ -1,0 +1,230 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Every function has the name of its C entry point, takes torch tensors that
+live on the GPU, allocates outputs and workspace with torch (device memory
+only; torch provides memory and the current stream) and calls the library.
+No arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional
+
+import torch
+
+from . import _lib
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_NOT_SPD, E_BREAKDOWN, E_NONFINITE, E_WORKSPACE, E_HIP, E_RANK = -1, -2, -3, -4, -5, -6, -7
+FP64, MIXED = 0, 1
+OP_POISSON5, OP_FV5, OP_FV7, OP_STENCIL9 = 0, 1, 2, 3
+
+
+class NlspError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn}: {status_string(status)} ({status})")
+
+
+def _L():
+    return _lib.load()
+
+
+def status_string(status: int) -> str:
+    return _L().nlsp_status_string(int(status)).decode()
+
+
+def _check(fn: str, rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise NlspError(fn, rc)
+    return rc
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclasses.dataclass
+class Operator:
+    """Matrix-free operator descriptor (see nlsp_operator).  ``coef`` is a GPU
+    float64 tensor: the cell coefficient a for OP_FV5/OP_FV7, 9 stencil
+    values for OP_STENCIL9, None for OP_POISSON5."""
+    kind: int
+    nx: int
+    ny: int
+    nz: int = 1
+    coef: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def device(self):
+        return self.coef.device if self.coef is not None else torch.device("cuda", torch.cuda.current_device())
+
+    def c(self) -> _lib.NlspOperator:
+        ptr = _dev(self.coef, torch.float64, "coef") if self.coef is not None else None
+        return _lib.NlspOperator(self.kind, self.nx, self.ny, self.nz, ptr)
+
+
+def nlsp_operator_size(op: Operator) -> int:
+    return int(_L().nlsp_operator_size(ctypes.byref(op.c())))
+
+
+def nlsp_padded_rank(k: int) -> int:
+    return int(_L().nlsp_padded_rank(int(k)))
+
+
+def q1_aniso_stencil(eps_theta: torch.Tensor) -> torch.Tensor:
+    """(nsys, 2) [eps, theta] -> (nsys, 9) stencils."""
+    nsys = eps_theta.shape[0]
+    out = torch.empty((nsys, 9), dtype=torch.float64, device=eps_theta.device)
+    _check("q1_aniso_stencil", _L().q1_aniso_stencil(nsys, _dev(eps_theta, torch.float64, "eps_theta"),
+                                                     _dev(out, torch.float64, "stencil"), _stream()))
+    return out
+
+
+def apply_operator(op: Operator, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    R = 1 if x.dim() == 1 else x.shape[1]
+    if y is None:
+        y = torch.empty_like(x)
+    _check("apply_operator", _L().apply_operator(ctypes.byref(op.c()), _dev(x, torch.float64, "x"),
+                                                 _dev(y, torch.float64, "y"), R, _stream()))
+    return y
+
+
+def jacobi_sweep_f32(op: Operator, omega: float, b: torch.Tensor, x: torch.Tensor,
+                     y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    R = 1 if x.dim() == 1 else x.shape[1]
+    if y is None:
+        y = torch.empty_like(x)
+    _check("jacobi_sweep_f32", _L().jacobi_sweep_f32(
+        ctypes.byref(op.c()), float(omega), _dev(b, torch.float32, "b"), _dev(x, torch.float32, "x"),
+        _dev(y, torch.float32, "y"), R, _stream()))
+    return y
+
+
+def setup_spectral_P_workspace_bytes(op: Operator, m: int, k: int, prec: int) -> int:
+    return int(_L().setup_spectral_P_workspace_bytes(ctypes.byref(op.c()), m, k, prec))
+
+
+def setup_spectral_P(op: Operator, S0: torch.Tensor, k: int, omega: float, s1: int,
+                     prec: int = FP64, workspace: Optional[torch.Tensor] = None):
+    """Returns (P (n,k) float64, sigma (m,) float64)."""
+    n, m = S0.shape
+    P = torch.empty((n, k), dtype=torch.float64, device=S0.device)
+    sigma = torch.empty((m,), dtype=torch.float64, device=S0.device)
+    nb = setup_spectral_P_workspace_bytes(op, m, k, prec)
+    if nb == 0:
+        raise NlspError("setup_spectral_P_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(nb, S0.device)
+    rc = _L().setup_spectral_P(ctypes.byref(op.c()), _dev(S0, torch.float64, "S0"), m, k,
+                               float(omega), int(s1), int(prec), _dev(P, torch.float64, "P"),
+                               _dev(sigma, torch.float64, "sigma"), ws.data_ptr(), ws.numel(),
+                               _stream())
+    _check("setup_spectral_P", rc)
+    return P, sigma
+
+
+@dataclasses.dataclass
+class TwoLevel:
+    """The solver's coarse-space factors (nlsp_two_level) and A_c, L."""
+    k: int
+    nu: int
+    omega: float
+    Ac: torch.Tensor
+    L: torch.Tensor
+    Linv: torch.Tensor
+    Q64: Optional[torch.Tensor]
+    Q32: Optional[torch.Tensor]
+
+    def c(self, prec: int) -> _lib.NlspTwoLevel:
+        return _lib.NlspTwoLevel(
+            self.k, self.nu, float(self.omega), int(prec), _dev(self.Linv, torch.float64, "Linv"),
+            _dev(self.Q64, torch.float64, "Q64") if self.Q64 is not None else None,
+            _dev(self.Q32, torch.float32, "Q32") if self.Q32 is not None else None)
+
+
+def galerkin_coarse_workspace_bytes(op: Operator, k: int) -> int:
+    return int(_L().galerkin_coarse_workspace_bytes(ctypes.byref(op.c()), k))
+
+
+def galerkin_coarse(op: Operator, P: torch.Tensor, omega: float, nu: int = 1, q64: bool = True,
+                    q32: bool = True, workspace: Optional[torch.Tensor] = None) -> TwoLevel:
+    n, k = P.shape
+    kp = nlsp_padded_rank(k)
+    dev = P.device
+    Ac = torch.empty((k, k), dtype=torch.float64, device=dev)
+    L = torch.empty((k, k), dtype=torch.float64, device=dev)
+    Linv = torch.empty((kp, kp), dtype=torch.float64, device=dev)
+    Q64 = torch.empty((n, kp), dtype=torch.float64, device=dev) if q64 else None
+    Q32 = torch.empty((n, kp), dtype=torch.float32, device=dev) if q32 else None
+    nb = galerkin_coarse_workspace_bytes(op, k)
+    if nb == 0:
+        raise NlspError("galerkin_coarse_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(nb, dev)
+    rc = _L().galerkin_coarse(ctypes.byref(op.c()), _dev(P, torch.float64, "P"), k, float(omega),
+                              int(nu), Ac.data_ptr(), L.data_ptr(), Linv.data_ptr(),
+                              Q64.data_ptr() if Q64 is not None else None,
+                              Q32.data_ptr() if Q32 is not None else None, ws.data_ptr(),
+                              ws.numel(), _stream())
+    _check("galerkin_coarse", rc)
+    return TwoLevel(k, nu, omega, Ac, L, Linv, Q64, Q32)
+
+
+def pcg_solve_workspace_bytes(op: Operator, k: int, R: int) -> int:
+    return int(_L().pcg_solve_workspace_bytes(ctypes.byref(op.c()), k, R))
+
+
+@dataclasses.dataclass
+class RhsInfo:
+    iters: int
+    status: int
+    relres: float
+
+
+def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tensor] = None,
+              prec: int = FP64, rtol: float = 1e-8, maxit: int = 10000, flexible: Optional[bool] = None,
+              check_every: int = 32, workspace: Optional[torch.Tensor] = None):
+    """Returns (u, [RhsInfo per RHS], status).  ``f`` is (n,) or (n, R)."""
+    squeeze = f.dim() == 1
+    f2 = f.reshape(f.shape[0], -1)
+    R = f2.shape[1]
+    if u is None:
+        u = torch.zeros_like(f2)
+    else:
+        u = u.reshape(f2.shape)
+    if flexible is None:
+        flexible = prec == MIXED
+    nb = pcg_solve_workspace_bytes(op, M.k, R)
+    if nb == 0:
+        raise NlspError("pcg_solve_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(nb, f.device)
+    opts = _lib.NlspPcgOpts(float(rtol), int(maxit), 1 if flexible else 0, int(check_every))
+    info = (_lib.NlspRhsInfo * R)()
+    Mc = M.c(prec)
+    rc = _L().pcg_solve(ctypes.byref(op.c()), ctypes.byref(Mc), _dev(f2, torch.float64, "f"),
+                        _dev(u, torch.float64, "u"), R, ctypes.byref(opts), info, ws.data_ptr(),
+                        ws.numel(), _stream())
+    _check("pcg_solve", rc, allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    infos: List[RhsInfo] = [RhsInfo(info[i].iters, info[i].status, info[i].relres) for i in range(R)]
+    return (u.reshape(f.shape) if squeeze else u), infos, rc

@@ -1,0 +1,771 @@
+// Setup of the spectral two-level preconditioner on gfx950:
+//   relaxation S = (I - w D^-1 A)^{s1} S0       (Sec. 3, near-nullspace vectors)
+//   Gram G = S^T S (float64 MFMA), G = V L V^T   (Sec. 3, SVD-centric construction)
+//   P0 = S V_k L_k^{-1/2}, CholeskyQR2 -> P      (orthonormal basis, float64)
+//   A_c = P^T (A P), L = chol(A_c), L^-1, Q = (I - w D^-1 A)^nu P
+//                                                 (algorithm setup: Galerkin operator)
+#include <cmath>
+#include <vector>
+
+#include "device_common.hpp"
+#include "host_common.hpp"
+
+namespace nlsp {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ stencil rows
+// Coefficients of row i of A in nine fixed slots (slot 0 the diagonal for the
+// 5/7-point kinds, the stencil position for the 9-point kind); an absent
+// neighbour has weight 0 and column i, so every slot can be read unguarded.
+struct Row9 {
+  double c[9];
+  int64_t j[9];
+};
+
+NLSP_DEV void row_coeffs(const OpDev& op, int64_t i, Row9& rw) {
+  int x, y, z;
+  decompose(op, i, x, y, z);
+  const int nx = op.nx, ny = op.ny;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    rw.c[t] = 0.0;
+    rw.j[t] = i;
+  }
+  if (op.kind == NLSP_OP_STENCIL9) {
+    const double* c = op.coef;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int t = (dy + 1) * 3 + (dx + 1);
+        if (y + dy >= 0 && y + dy < ny && x + dx >= 0 && x + dx < nx) {
+          rw.c[t] = c[t];
+          rw.j[t] = i + dx + (int64_t)dy * nx;
+        }
+      }
+    return;
+  }
+  const int64_t sxy = (int64_t)nx * ny;
+  const bool in[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < op.nz - 1};
+  const int64_t nb[6] = {i - 1, i + 1, i - nx, i + nx, i - sxy, i + sxy};
+  const int nf = (op.kind == NLSP_OP_FV7) ? 6 : 4;
+  if (op.kind == NLSP_OP_POISSON5) {
+    rw.c[0] = 4.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      if (in[f]) {
+        rw.c[1 + f] = -1.0;
+        rw.j[1 + f] = nb[f];
+      }
+    return;
+  }
+  const double* a = op.coef;
+  const double aP = a[i];
+  double d = 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (f >= nf) break;
+    if (in[f]) {
+      const double t = harmonic<double>(aP, a[nb[f]]);
+      d += t;
+      rw.c[1 + f] = -t;
+      rw.j[1 + f] = nb[f];
+    } else {
+      d += 2.0 * aP;
+    }
+  }
+  rw.c[0] = d;
+}
+
+NLSP_DEV double row_diag(const OpDev& op, int64_t i) {
+  int x, y, z;
+  decompose(op, i, x, y, z);
+  return op_diag<double>(op, i, x, y, z);
+}
+
+// Multi-column stencil pass over (n, m) row-major blocks.  One wave per
+// unknown (the row's coefficients are computed once per wave), lanes over
+// the m columns (coalesced).
+//   mode 0: out = in - w D^-1 (A in)     (Jacobi relaxation of A s = 0)
+//   mode 1: out = A in
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_stencil_cols(OpDev op, int m, double omega, int mode,
+                                                      const TI* __restrict__ in,
+                                                      TO* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (i >= op.n) return;
+  Row9 rw;
+  row_coeffs(op, i, rw);
+  const double scale = (mode == 0) ? omega / row_diag(op, i) : 0.0;
+  for (int col = lane; col < m; col += 64) {
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s += rw.c[t] * (double)in[rw.j[t] * m + col];
+    const double v = (mode == 0) ? (double)in[i * m + col] - scale * s : s;
+    out[i * m + col] = (TO)v;
+  }
+}
+
+// --------------------------------------------------------------- MFMA Gram
+// Partial cross products C = X^T Y over a slice of rows, X (n, a), Y (n, b)
+// row-major, a and b multiples of 16.  v_mfma_f64_16x16x4f64: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] and receives D[4*v + l/16][l%16], v < 4
+// (the float64 variant interleaves output rows; checked on the device).
+// With A[i][kk] = X[r0+kk][16I+i] and B[kk][j] = Y[r0+kk][16J+j] both operands
+// are "row r0 + l/16, column l%16 of a 4 x 16 block".  Tiles are dealt
+// round-robin to the waves; `sym` keeps only tiles with I <= J (X == Y).
+template <typename T>
+__global__ __launch_bounds__(512) void k_gram_partial(const T* __restrict__ X,
+                                                      const T* __restrict__ Y, int64_t n, int a,
+                                                      int b, int sym, int64_t rows_per_wg,
+                                                      double* __restrict__ part) {
+  constexpr int MAXT = 18;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int TA = a / 16, TB = b / 16;
+  const int ntiles = sym ? TA * (TA + 1) / 2 : TA * TB;
+  int tI[MAXT], tJ[MAXT];
+  int nt = 0;
+  for (int tile = wave, cnt = 0; cnt < ntiles; ++cnt) {
+    // enumerate tiles in a fixed order; keep those dealt to this wave
+    int I, J;
+    if (sym) {
+      int rem = cnt, row = 0;
+      while (rem >= TA - row) { rem -= TA - row; ++row; }
+      I = row;
+      J = row + rem;
+    } else {
+      I = cnt / TB;
+      J = cnt % TB;
+    }
+    if (cnt == tile) {
+      if (nt < MAXT) { tI[nt] = I; tJ[nt] = J; ++nt; }
+      tile += nwave;
+    }
+  }
+  d4_t acc[MAXT];
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = min(n, r0 + rows_per_wg);
+  const int kr = lane >> 4, kc = lane & 15;
+  for (int64_t row = r0; row < r1; row += 4) {
+    const int64_t rr = row + kr;
+    const bool ok = rr < r1;
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+      if (q < nt) {
+        const double av = ok ? (double)X[rr * a + 16 * tI[q] + kc] : 0.0;
+        const double bv = ok ? (double)Y[rr * b + 16 * tJ[q] + kc] : 0.0;
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+      }
+    }
+  }
+  double* P = part + (int64_t)blockIdx.x * a * b;
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) {
+    if (q < nt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * tI[q] + 4 * v + kr, j = 16 * tJ[q] + kc;
+        P[(int64_t)i * b + j] = acc[q][v];
+      }
+    }
+  }
+}
+
+// Fixed-order sum of the partials; sym mirrors the upper triangle.
+__global__ void k_gram_reduce(const double* __restrict__ part, int nwg, int a, int b, int sym,
+                              double* __restrict__ out, int lda_out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a * b) return;
+  int i = idx / b, j = idx % b;
+  int si = i, sj = j;
+  if (sym && (i / 16) > (j / 16)) { si = j; sj = i; }
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * a * b + (int64_t)si * b + sj];
+  out[(int64_t)i * lda_out + j] = s;
+}
+
+// ------------------------------------------------- small dense, one WG
+// Workgroup barrier for data exchanged between waves.  LDS needs only the
+// barrier.  For global memory the stores must be complete and visible before
+// other waves read them: __syncthreads() alone emits no wait for outstanding
+// global stores on gfx950, so an agent-scope fence is added.
+template <bool LDS>
+NLSP_DEV void wg_sync() {
+  if (!LDS) __threadfence();
+  __syncthreads();
+}
+
+// Cyclic Jacobi eigensolver for a symmetric m x m matrix (Golub & Van Loan,
+// Sec. 8.5), parallel ("round-robin") ordering: m/2 disjoint rotations per
+// round, m-1 rounds per sweep.  The working copy of G lives in LDS when
+// LDS = true (m <= 128), else in Gg itself.  On exit Gg holds the rotated
+// matrix (its diagonal converges to the eigenvalues) and V the rotations.
+// m even.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, double* __restrict__ V,
+                                                     int m, int max_sweeps,
+                                                     double* __restrict__ offnorm) {
+  extern __shared__ double dyn[];
+  __shared__ double cs[128], sn[128];
+  __shared__ int pp[128], qq[128];
+  __shared__ double red[16];
+  const int t = threadIdx.x, nt = blockDim.x;
+  double* G = LDS ? dyn : Gg;
+  if (LDS)
+    for (int idx = t; idx < m * m; idx += nt) G[idx] = Gg[idx];
+  for (int idx = t; idx < m * m; idx += nt) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
+  wg_sync<LDS>();
+  const int half = m / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int idx = t; idx < m * m; idx += nt) {
+      const double g = G[idx];
+      tot += g * g;
+      if (idx / m != idx % m) off += g * g;
+    }
+    off = block_sum(off, red);
+    __syncthreads();
+    tot = block_sum(tot, red);
+    if (t == 0) offnorm[0] = sqrt(off / (tot > 0 ? tot : 1.0));
+    if (off <= 1e-30 * tot) break;
+    for (int rnd = 0; rnd < m - 1; ++rnd) {
+      if (t < half) {
+        int p, q;
+        if (t == 0) {
+          p = rnd;
+          q = m - 1;
+        } else {
+          p = (rnd + t) % (m - 1);
+          q = (rnd - t + (m - 1)) % (m - 1);
+        }
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        const double apq = G[p * m + q], app = G[p * m + p], aqq = G[q * m + q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-300) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+        }
+        cs[t] = c;
+        sn[t] = s;
+        pp[t] = p;
+        qq[t] = q;
+      }
+      __syncthreads();
+      // columns: G <- G J, V <- V J
+      for (int idx = t; idx < m * half; idx += nt) {
+        const int i = idx / half, k = idx % half;
+        const int p = pp[k], q = qq[k];
+        const double c = cs[k], s = sn[k];
+        const double gp = G[i * m + p], gq = G[i * m + q];
+        G[i * m + p] = c * gp - s * gq;
+        G[i * m + q] = s * gp + c * gq;
+        const double vp = V[i * m + p], vq = V[i * m + q];
+        V[i * m + p] = c * vp - s * vq;
+        V[i * m + q] = s * vp + c * vq;
+      }
+      wg_sync<LDS>();
+      // rows: G <- J^T G
+      for (int idx = t; idx < m * half; idx += nt) {
+        const int j = idx / half, k = idx % half;
+        const int p = pp[k], q = qq[k];
+        const double c = cs[k], s = sn[k];
+        const double gp = G[p * m + j], gq = G[q * m + j];
+        G[p * m + j] = c * gp - s * gq;
+        G[q * m + j] = s * gp + c * gq;
+      }
+      wg_sync<LDS>();
+    }
+  }
+  if (LDS)
+    for (int idx = t; idx < m * m; idx += nt) Gg[idx] = G[idx];
+}
+
+// Sort eigenpairs descending; sigma = sqrt(max(lambda, 0)); T = V_k diag(lambda_k^-1/2)
+// (m x k, padded columns zero); info[0] = 1 if lambda_k <= (1e-13 sigma_1)^2.
+__global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G,
+                                                    const double* __restrict__ V, int m, int mreal,
+                                                    int k, int kpad, double* __restrict__ sigma,
+                                                    double* __restrict__ T, int* info) {
+  __shared__ int order[256];
+  __shared__ double lam[256];
+  const int t = threadIdx.x;
+  for (int i = t; i < m; i += blockDim.x) lam[i] = G[i * m + i];
+  __syncthreads();
+  if (t == 0) {
+    // selection of the mreal largest, descending (stable: lower index first)
+    for (int i = 0; i < m; ++i) order[i] = i;
+    for (int i = 0; i < m; ++i) {
+      int best = i;
+      for (int j = i + 1; j < m; ++j)
+        if (lam[order[j]] > lam[order[best]]) best = j;
+      const int tmp = order[i];
+      order[i] = order[best];
+      order[best] = tmp;
+    }
+    const double l1 = lam[order[0]] > 0 ? lam[order[0]] : 0.0;
+    const double lk = lam[order[k - 1]];
+    info[0] = (lk <= 1e-26 * l1 || !(lk > 0)) ? 1 : 0;
+  }
+  __syncthreads();
+  for (int i = t; i < mreal; i += blockDim.x) {
+    const double l = lam[order[i]];
+    sigma[i] = sqrt(l > 0 ? l : 0.0);
+  }
+  for (int idx = t; idx < m * kpad; idx += blockDim.x) {
+    const int r = idx / kpad, j = idx % kpad;
+    double v = 0.0;
+    if (j < k) {
+      const double l = lam[order[j]];
+      v = (l > 0) ? V[r * m + order[j]] / sqrt(l) : 0.0;
+    }
+    T[idx] = v;
+  }
+}
+
+// Cholesky G = L L^T of an SPD k x k matrix (right-looking, one workgroup);
+// L lower (upper part zero).  Working copy in LDS when LDS = true (k <= 128).
+// info[0] = 1 if a pivot is not positive.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ G, int ldg, int k,
+                                                   double* __restrict__ Lg, int ldl, int* info) {
+  extern __shared__ double dyn[];
+  __shared__ double piv;
+  __shared__ int bad;
+  const int t = threadIdx.x, nt = blockDim.x;
+  double* L = LDS ? dyn : Lg;
+  const int ld = LDS ? k : ldl;
+  for (int idx = t; idx < k * k; idx += nt) {
+    const int i = idx / k, j = idx % k;
+    L[i * ld + j] = (j <= i) ? G[i * ldg + j] : 0.0;
+  }
+  if (t == 0) bad = 0;
+  wg_sync<LDS>();
+  for (int j = 0; j < k; ++j) {
+    if (t == 0) {
+      const double d = L[j * ld + j];
+      if (!(d > 0.0)) bad = 1;
+      piv = (d > 0.0) ? sqrt(d) : 1.0;
+      L[j * ld + j] = piv;
+    }
+    wg_sync<LDS>();
+    for (int i = j + 1 + t; i < k; i += nt) L[i * ld + j] /= piv;
+    wg_sync<LDS>();
+    const int rem = k - j - 1;
+    for (int idx = t; idx < rem * rem; idx += nt) {
+      const int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
+      if (c <= i) L[i * ld + c] -= L[i * ld + j] * L[c * ld + j];
+    }
+    wg_sync<LDS>();
+  }
+  if (LDS)
+    for (int idx = t; idx < k * k; idx += nt) Lg[(idx / k) * ldl + idx % k] = L[idx];
+  if (t == 0) info[0] = bad;
+}
+
+// Inverse of a lower-triangular k x k matrix L, written zero-padded to
+// (kp, kp): column j of L^-1 solves L x = e_j by forward substitution.
+__global__ __launch_bounds__(256) void k_tri_inv_lower(const double* __restrict__ L, int ldl, int k,
+                                                       double* __restrict__ Li, int kp) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kp) return;
+  for (int i = 0; i < kp; ++i) Li[i * kp + j] = 0.0;
+  if (j >= k) return;
+  for (int i = j; i < k; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int c = j; c < i; ++c) s -= L[i * ldl + c] * Li[c * kp + j];
+    Li[i * kp + j] = s / L[i * ldl + i];
+  }
+}
+
+// C (n, b) = X (n, a) * B (a, b) in float64, B small (dense, row-major).
+// One wave per 16 rows: v_mfma_f64_16x16x4f64 with A[i][kk] = X[r0+i][k0+kk],
+// B[kk][j] = B[k0+kk][16J+j].  a multiple of 4, b multiple of 16.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tsgemm(const T* __restrict__ X, int64_t n, int a,
+                                                const double* __restrict__ B, int b,
+                                                double* __restrict__ C, int ldc, int bcols_out) {
+  constexpr int MAXJ = 16;
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 16;
+  if (r0 >= n) return;
+  const int TB = b / 16;
+  d4_t acc[MAXJ];
+#pragma unroll
+  for (int q = 0; q < MAXJ; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t ra = r0 + li;
+  for (int k0 = 0; k0 < a; k0 += 4) {
+    const double av = (ra < n) ? (double)X[ra * a + k0 + lk] : 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+      if (q < TB) {
+        const double bv = B[(int64_t)(k0 + lk) * b + 16 * q + li];
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAXJ; ++q) {
+    if (q < TB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 4 * v + lk;   // float64 MFMA output row order
+        const int col = 16 * q + li;
+        if (row < n && col < bcols_out) C[row * ldc + col] = acc[q][v];
+      }
+    }
+  }
+}
+
+// Inverse of the upper-triangular R = L^T given L lower: Ri = L^-T, (kp x kp)
+// zero padded; reuses the lower inverse: (L^T)^-1 = (L^-1)^T.
+__global__ void k_transpose_pad(const double* __restrict__ A, int kp, double* __restrict__ B) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kp * kp) return;
+  const int i = idx / kp, j = idx % kp;
+  B[j * kp + i] = A[idx];
+}
+
+// Largest-magnitude entry of each column (lowest row on ties), then flip the
+// column so that entry is positive.  One workgroup per column.
+__global__ __launch_bounds__(256) void k_colsign(double* __restrict__ P, int64_t n, int ld, int k) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t i = t; i < n; i += blockDim.x) {
+    const double v = fabs(P[i * ld + j]);
+    if (v > best) { best = v; bidx = i; }
+  }
+  bv[t] = best;
+  bi[t] = bidx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      if (bv[t + s] > bv[t] || (bv[t + s] == bv[t] && bi[t + s] < bi[t])) {
+        bv[t] = bv[t + s];
+        bi[t] = bi[t + s];
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = P[bi[0] * ld + j] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int64_t i = t; i < n; i += blockDim.x) P[i * ld + j] = -P[i * ld + j];
+}
+
+// Copy (n, k) with leading dimension lda into (n, kout) row-major.
+__global__ void k_copy_cols(const double* __restrict__ A, int lda, int64_t n, int k,
+                            double* __restrict__ B, int ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * ldb) return;
+  const int64_t i = idx / ldb;
+  const int j = (int)(idx % ldb);
+  B[idx] = (j < k) ? A[i * lda + j] : 0.0;
+}
+
+__global__ void k_pad_square(const double* __restrict__ A, int lda, int k, double* __restrict__ B,
+                             int ldb, int kout) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kout * kout) return;
+  const int i = idx / kout, j = idx % kout;
+  B[i * ldb + j] = (i < k && j < k) ? A[i * lda + j] : 0.0;
+}
+
+__global__ void k_symmetrize(double* __restrict__ A, int k, int ld) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= k * k) return;
+  const int i = idx / k, j = idx % k;
+  if (j <= i) return;
+  const double v = 0.5 * (A[i * ld + j] + A[j * ld + i]);
+  A[i * ld + j] = v;
+  A[j * ld + i] = v;
+}
+
+__global__ void k_to_f32(const double* __restrict__ A, float* __restrict__ B, int64_t cnt) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < cnt) B[idx] = (float)A[idx];
+}
+
+// ------------------------------------------------------------ host helpers
+constexpr int LDS_DENSE_MAX = 128;   // m or k up to which the dense kernels work in LDS
+
+static int launch_eig(double* G, double* V, int m, double* off, hipStream_t s) {
+  if (m <= LDS_DENSE_MAX) {
+    const size_t sh = sizeof(double) * m * m;
+    NLSP_HIP(hipFuncSetAttribute((const void*)k_jacobi_eig<true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(1024), sh, s, G, V, m, 40, off);
+  } else {
+    hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(1024), 0, s, G, V, m, 40, off);
+  }
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+static int launch_chol(const double* G, int ldg, int k, double* L, int ldl, int* info,
+                       hipStream_t s) {
+  if (k <= LDS_DENSE_MAX) {
+    const size_t sh = sizeof(double) * k * k;
+    NLSP_HIP(hipFuncSetAttribute((const void*)k_cholesky<true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(1024), sh, s, G, ldg, k, L, ldl, info);
+  } else {
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(1024), 0, s, G, ldg, k, L, ldl, info);
+  }
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+struct GramPlan {
+  int nwg;
+  int64_t rows_per_wg;
+};
+
+inline GramPlan gram_plan(int64_t n) {
+  GramPlan g;
+  g.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256));
+  g.rows_per_wg = ((n + g.nwg - 1) / g.nwg + 3) / 4 * 4;
+  g.nwg = (int)((n + g.rows_per_wg - 1) / g.rows_per_wg);
+  return g;
+}
+
+// X^T Y (a x b, a, b multiples of 16) into out (leading dim ldo).  `part`
+// holds nwg*a*b doubles.
+template <typename T>
+static int gram(const T* X, const T* Y, int64_t n, int a, int b, int sym, double* part,
+                double* out, int ldo, hipStream_t s) {
+  const GramPlan g = gram_plan(n);
+  const int TA = a / 16, TB = b / 16;
+  const int ntiles = sym ? TA * (TA + 1) / 2 : TA * TB;
+  int threads = 64 * std::min(8, std::max(1, ntiles));
+  while (threads < 512 && (ntiles + threads / 64 - 1) / (threads / 64) > 18) threads += 64;
+  if ((ntiles + threads / 64 - 1) / (threads / 64) > 18) return NLSP_E_INVALID;
+  hipLaunchKernelGGL(k_gram_partial<T>, dim3(g.nwg), dim3(threads), 0, s, X, Y, n, a, b, sym,
+                     g.rows_per_wg, part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(a * b, 256)), dim3(256), 0, s, part, g.nwg, a, b,
+                     sym, out, ldo);
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+template <typename T>
+static void tsgemm(const T* X, int64_t n, int a, const double* B, int b, double* C, int ldc,
+                   int bcols_out, hipStream_t s) {
+  const int64_t tiles = (n + 15) / 16;
+  hipLaunchKernelGGL(k_tsgemm<T>, dim3(ceil_div(tiles, 4)), dim3(256), 0, s, X, n, a, B, b, C, ldc,
+                     bcols_out);
+}
+
+inline int pad16(int v) { return (v + 15) / 16 * 16; }
+
+struct SetupLayout {
+  void* S0buf;      // (n, mp) relaxation ping
+  void* S1buf;      // (n, mp) relaxation pong
+  double* P0;       // (n, kp16)
+  double* P1;       // (n, kp16)
+  double* part;     // Gram partials
+  double* G;        // (mp, mp)
+  double* V;        // (mp, mp)
+  double* T;        // (mp, kp16)
+  double* Rinv;     // (kp16, kp16)
+  double* Lk;       // (kp16, kp16)
+  double* off;      // 4
+  int* info;        // 4
+  size_t bytes;
+};
+
+inline SetupLayout carve_setup(void* ws, int64_t n, int m, int k, int prec) {
+  const int mp = pad16(m) + (pad16(m) % 2), kq = pad16(k);
+  const size_t es = (prec == NLSP_MIXED) ? 4 : 8;
+  Carver cv(ws);
+  SetupLayout L;
+  L.S0buf = cv.take<char>(n * mp * es);
+  L.S1buf = cv.take<char>(n * mp * es);
+  L.P0 = cv.take<double>(n * kq);
+  L.P1 = cv.take<double>(n * kq);
+  const GramPlan g = gram_plan(n);
+  L.part = cv.take<double>((size_t)g.nwg * mp * mp);
+  L.G = cv.take<double>((size_t)mp * mp);
+  L.V = cv.take<double>((size_t)mp * mp);
+  L.T = cv.take<double>((size_t)mp * kq);
+  L.Rinv = cv.take<double>((size_t)kq * kq);
+  L.Lk = cv.take<double>((size_t)kq * kq);
+  L.off = cv.take<double>(4);
+  L.info = cv.take<int>(4);
+  L.bytes = cv.bytes();
+  return L;
+}
+
+// Copies S0 (n, m) float64 into the padded (n, mp) buffer of element type T.
+template <typename T>
+__global__ void k_load_S0(const double* __restrict__ S0, int64_t n, int m, int mp, T* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * mp) return;
+  const int64_t i = idx / mp;
+  const int j = (int)(idx % mp);
+  S[idx] = (T)((j < m) ? S0[i * m + j] : 0.0);
+}
+
+template <typename T>
+static int setup_impl(const OpDev& op, const double* S0, int m, int k, double omega, int s1,
+                      double* Pout, double* sigma, const SetupLayout& L, hipStream_t s) {
+  const int64_t n = op.n;
+  const int mp = pad16(m) + (pad16(m) % 2), kq = pad16(k);
+  T* Sa = static_cast<T*>(L.S0buf);
+  T* Sb = static_cast<T*>(L.S1buf);
+  hipLaunchKernelGGL(k_load_S0<T>, dim3(ceil_div(n * mp, 256)), dim3(256), 0, s, S0, n, m, mp, Sa);
+  for (int it = 0; it < s1; ++it) {
+    hipLaunchKernelGGL((k_stencil_cols<T, T>), dim3(ceil_div(n, 4)), dim3(256), 0, s, op, mp, omega,
+                       0, Sa, Sb);
+    std::swap(Sa, Sb);
+  }
+  // Gram and eigenpairs
+  int rc = gram<T>(Sa, Sa, n, mp, mp, 1, L.part, L.G, mp, s);
+  if (rc) return rc;
+  rc = launch_eig(L.G, L.V, mp, L.off, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_eig_finish, dim3(1), dim3(256), 0, s, L.G, L.V, mp, m, k, kq, sigma, L.T,
+                     L.info);
+  // P0 = S T
+  tsgemm<T>(Sa, n, mp, L.T, kq, L.P0, kq, kq, s);
+  // CholeskyQR2 in float64
+  double* Pa = L.P0;
+  double* Pb = L.P1;
+  for (int pass = 0; pass < 2; ++pass) {
+    rc = gram<double>(Pa, Pa, n, kq, kq, 1, L.part, L.G, kq, s);
+    if (rc) return rc;
+    rc = launch_chol(L.G, kq, k, L.Lk, kq, L.info + 1 + pass, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L.Lk, kq, k, L.T, kq);
+    hipLaunchKernelGGL(k_transpose_pad, dim3(ceil_div(kq * kq, 256)), dim3(256), 0, s, L.T, kq,
+                       L.Rinv);
+    tsgemm<double>(Pa, n, kq, L.Rinv, kq, Pb, kq, kq, s);
+    std::swap(Pa, Pb);
+  }
+  hipLaunchKernelGGL(k_colsign, dim3(k), dim3(256), 0, s, Pa, n, kq, k);
+  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(n * k, 256)), dim3(256), 0, s, Pa, kq, n, k, Pout, k);
+  NLSP_HIP(hipGetLastError());
+  int hinfo[4] = {0, 0, 0, 0};
+  NLSP_HIP(hipMemcpyAsync(hinfo, L.info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  NLSP_HIP(hipStreamSynchronize(s));
+  if (hinfo[1] || hinfo[2]) return NLSP_E_NOT_SPD;
+  if (hinfo[0]) return NLSP_E_RANK;
+  return NLSP_OK;
+}
+
+// ------------------------------------------------------------ Galerkin
+struct CoarseLayout {
+  double* Pp;     // (n, kp) padded P
+  double* Y;      // (n, kp) A P, then relaxation ping buffer
+  double* Z;      // (n, kp) pong
+  double* part;
+  double* Acp;    // (kp, kp)
+  double* Lp;     // (kp, kp)
+  int* info;
+  size_t bytes;
+};
+
+inline CoarseLayout carve_coarse(void* ws, int64_t n, int kp) {
+  Carver cv(ws);
+  CoarseLayout L;
+  L.Pp = cv.take<double>(n * kp);
+  L.Y = cv.take<double>(n * kp);
+  L.Z = cv.take<double>(n * kp);
+  const GramPlan g = gram_plan(n);
+  L.part = cv.take<double>((size_t)g.nwg * kp * kp);
+  L.Acp = cv.take<double>((size_t)kp * kp);
+  L.Lp = cv.take<double>((size_t)kp * kp);
+  L.info = cv.take<int>(4);
+  L.bytes = cv.bytes();
+  return L;
+}
+
+}  // namespace nlsp
+
+using namespace nlsp;
+
+extern "C" {
+
+size_t setup_spectral_P_workspace_bytes(const nlsp_operator* A, int m, int k, int prec) {
+  const int64_t n = op_size(A);
+  if (n < 1 || k < 1 || m < k || m > 256 || (prec != NLSP_FP64 && prec != NLSP_MIXED)) return 0;
+  return carve_setup(nullptr, n, m, k, prec).bytes;
+}
+
+int setup_spectral_P(const nlsp_operator* A, const double* S0, int m, int k, double omega, int s1,
+                     int prec, double* P, double* sigma, void* ws, size_t ws_bytes, void* stream) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !S0 || !P || !sigma) return NLSP_E_INVALID;
+  if (k < 1 || m < k || m > 256 || (int64_t)m > n || s1 < 0 || !(omega > 0)) return NLSP_E_INVALID;
+  if (prec != NLSP_FP64 && prec != NLSP_MIXED) return NLSP_E_INVALID;
+  const size_t need = carve_setup(nullptr, n, m, k, prec).bytes;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const SetupLayout L = carve_setup(ws, n, m, k, prec);
+  const OpDev op = make_op(*A);
+  hipStream_t s = as_stream(stream);
+  NLSP_HIP(hipMemsetAsync(L.info, 0, sizeof(int) * 4, s));
+  if (prec == NLSP_FP64) return setup_impl<double>(op, S0, m, k, omega, s1, P, sigma, L, s);
+  return setup_impl<float>(op, S0, m, k, omega, s1, P, sigma, L, s);
+}
+
+size_t galerkin_coarse_workspace_bytes(const nlsp_operator* A, int k) {
+  const int64_t n = op_size(A);
+  const int kp = padded_rank(k);
+  if (n < 1 || kp < 0) return 0;
+  return carve_coarse(nullptr, n, kp).bytes;
+}
+
+int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega, int nu,
+                    double* Ac, double* Lout, double* Linv, double* Q64, float* Q32, void* ws,
+                    size_t ws_bytes, void* stream) {
+  const int64_t n = op_size(A);
+  const int kp = padded_rank(k);
+  if (n < 1 || kp < 0 || !P || !Ac || !Lout || !Linv || (!Q64 && !Q32)) return NLSP_E_INVALID;
+  if ((int64_t)k > n || nu < 1 || !(omega > 0)) return NLSP_E_INVALID;
+  const size_t need = carve_coarse(nullptr, n, kp).bytes;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const CoarseLayout L = carve_coarse(ws, n, kp);
+  const OpDev op = make_op(*A);
+  hipStream_t s = as_stream(stream);
+  NLSP_HIP(hipMemsetAsync(L.info, 0, sizeof(int) * 4, s));
+  // padded P, Y = A P, A_c = P^T Y
+  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(n * kp, 256)), dim3(256), 0, s, P, k, n, k, L.Pp, kp);
+  hipLaunchKernelGGL((k_stencil_cols<double, double>), dim3(ceil_div(n, 4)), dim3(256), 0, s, op, kp,
+                     omega, 1, L.Pp, L.Y);
+  int rc = gram<double>(L.Pp, L.Y, n, kp, kp, 0, L.part, L.Acp, kp, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_symmetrize, dim3(ceil_div(kp * kp, 256)), dim3(256), 0, s, L.Acp, kp, kp);
+  hipLaunchKernelGGL(k_pad_square, dim3(ceil_div(k * k, 256)), dim3(256), 0, s, L.Acp, kp, k, Ac, k, k);
+  rc = launch_chol(L.Acp, kp, k, L.Lp, kp, L.info, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_pad_square, dim3(ceil_div(k * k, 256)), dim3(256), 0, s, L.Lp, kp, k, Lout, k, k);
+  hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L.Lp, kp, k, Linv, kp);
+  // Q = (I - w D^-1 A)^nu P
+  double* cur = L.Pp;
+  double* bufs[2] = {L.Y, L.Z};
+  for (int it = 0; it < nu; ++it) {
+    double* dst = bufs[it & 1];
+    hipLaunchKernelGGL((k_stencil_cols<double, double>), dim3(ceil_div(n, 4)), dim3(256), 0, s, op,
+                       kp, omega, 0, cur, dst);
+    cur = dst;
+  }
+  if (Q64)
+    NLSP_HIP(hipMemcpyAsync(Q64, cur, sizeof(double) * n * kp, hipMemcpyDeviceToDevice, s));
+  if (Q32)
+    hipLaunchKernelGGL(k_to_f32, dim3(ceil_div(n * kp, 256)), dim3(256), 0, s, cur, Q32, n * kp);
+  NLSP_HIP(hipGetLastError());
+  int info = 0;
+  NLSP_HIP(hipMemcpyAsync(&info, L.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  NLSP_HIP(hipStreamSynchronize(s));
+  return info ? NLSP_E_NOT_SPD : NLSP_OK;
+}
+
+}  // extern "C"

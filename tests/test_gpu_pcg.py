@@ -1,0 +1,130 @@
+"""GPU parity of the PCG solve against the FP64 oracle, through the C ABI
+(marked gpu).  Bar: iteration count within +-1 of the oracle per RHS and a
+true relative residual <= rtol in the float64 form; in the mixed form the
+true relative residual <= rtol and ||x - x_oracle|| <= 2 rtol ||f|| /
+lambda_min(A)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+import torch
+
+import oracle as O
+from oracle.method import make_preconditioner
+import workloads as W
+from tests._cases import make_case, cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20174_amd as mod
+    return mod
+
+
+def _lam_min(A):
+    return float(sla.eigsh(A, k=1, sigma=0, which="LM", return_eigenvectors=False)[0])
+
+
+def _oracle_solve(A, P, f, omega, nu, rtol, flexible=False):
+    _, L = O.galerkin(A, P)
+    return O.pcg(A, f, make_preconditioner(A, P, L, omega, nu, nu), rtol=rtol, flexible=flexible)
+
+
+def _check(nl, A, op, P, f, omega=2 / 3, nu=1, rtol=1e-8, prec=0, check_every=8):
+    res = _oracle_solve(A, P, f, omega, nu, rtol, flexible=(prec == 1))
+    M = nl.galerkin_coarse(op, cuda(P), omega, nu)
+    u, info, rc = nl.pcg_solve(op, M, cuda(f), prec=prec, rtol=rtol, check_every=check_every)
+    u = host(u).reshape(f.shape)
+    f2 = f.reshape(f.shape[0], -1)
+    u2 = u.reshape(f2.shape)
+    lam = _lam_min(A)
+    for j, inf in enumerate(info):
+        true_rel = np.linalg.norm(f2[:, j] - A @ u2[:, j]) / np.linalg.norm(f2[:, j])
+        assert inf.status == nl.OK, (j, inf)
+        assert true_rel <= rtol * 1.0001, (j, true_rel)
+        assert abs(inf.relres - true_rel) <= 1e-3 * rtol + 1e-12
+        if prec == 0:
+            assert abs(inf.iters - res.iters[j]) <= 1, (j, inf.iters, res.iters[j])
+        else:
+            assert abs(inf.iters - res.iters[j]) <= max(2, 0.05 * res.iters[j]), (j, inf.iters, res.iters[j])
+        err = np.linalg.norm(u2[:, j] - res.x[:, j])
+        assert err <= 2 * rtol * np.linalg.norm(f2[:, j]) / lam
+    return info, res
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cfg1_poisson(nl, prec):
+    c = W.Cfg1()
+    A, op, n = make_case("poisson", 0, (c.N, c.N))
+    S = O.relax(A, c.S0(), c.omega, c.s1)
+    P, _ = O.spectral_basis(S, c.k)
+    info, res = _check(nl, A, op, P, c.rhs(), prec=prec)
+    assert 45 <= info[0].iters <= 65
+
+
+@pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 24), ("q1", (48, 48), 32),
+                                         ("fv7", (19, 15), 16), ("grf", (64, 64), 64)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kinds(nl, kind, size, k, prec):
+    A, op, n = make_case(kind, 11, size)
+    S = O.relax(A, np.random.default_rng(12).standard_normal((n, 2 * k)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, k)
+    f = np.random.default_rng(13).standard_normal(n)
+    _check(nl, A, op, P, f, prec=prec)
+
+
+@pytest.mark.parametrize("R", [2, 8, 16])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_multi_rhs(nl, R, prec):
+    A, op, n = make_case("fv5", 21, (40, 33))
+    S = O.relax(A, np.random.default_rng(22).standard_normal((n, 32)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, 16)
+    f = np.random.default_rng(23).standard_normal((n, R))
+    f[:, 0] *= 1e-3                      # different scales converge at different iterations
+    _check(nl, A, op, P, f, prec=prec)
+
+
+@pytest.mark.parametrize("nu", [2, 3])
+def test_more_sweeps(nl, nu):
+    A, op, n = make_case("fv5", 31, (50, 41))
+    S = O.relax(A, np.random.default_rng(32).standard_normal((n, 40)), 0.66, 10)
+    P, _ = O.spectral_basis(S, 20)
+    f = np.random.default_rng(33).standard_normal(n)
+    _check(nl, A, op, P, f, omega=0.66, nu=nu)
+    _check(nl, A, op, P, f, omega=0.66, nu=nu, prec=1)
+
+
+def test_statuses(nl):
+    A, op, n = make_case("fv5", 41, (30, 30))
+    S = O.relax(A, np.random.default_rng(42).standard_normal((n, 16)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, 8)
+    M = nl.galerkin_coarse(op, cuda(P), 2 / 3, 1)
+    f = np.random.default_rng(43).standard_normal((n, 3))
+    f[:, 1] = 0.0
+    u, info, rc = nl.pcg_solve(op, M, cuda(f), maxit=3)
+    assert info[0].status == nl.NOT_CONVERGED and info[0].iters == 3
+    assert info[1].status == nl.OK and info[1].iters == 0 and np.all(host(u)[:, 1] == 0)
+    assert rc == nl.NOT_CONVERGED
+    fn = f.copy()
+    fn[5, 2] = np.nan
+    u, info, rc = nl.pcg_solve(op, M, cuda(fn))
+    assert info[2].status == nl.E_NONFINITE and rc == nl.E_NONFINITE
+    assert info[0].status == nl.OK
+    with pytest.raises(nl.NlspError):
+        nl.pcg_solve(op, M, cuda(f), rtol=-1.0)
+
+
+def test_deterministic(nl):
+    A, op, n = make_case("grf", 51, (64, 64))
+    S0 = cuda(np.random.default_rng(52).standard_normal((n, 32)))
+    P1, s1 = nl.setup_spectral_P(op, S0, 16, 2 / 3, 10, 1)
+    P2, s2 = nl.setup_spectral_P(op, S0, 16, 2 / 3, 10, 1)
+    assert torch.equal(P1, P2) and torch.equal(s1, s2)
+    M = nl.galerkin_coarse(op, P1, 2 / 3, 1)
+    f = cuda(np.random.default_rng(53).standard_normal(n))
+    u1, i1, _ = nl.pcg_solve(op, M, f, prec=1)
+    u2, i2, _ = nl.pcg_solve(op, M, f, prec=1)
+    assert torch.equal(u1, u2) and i1[0].iters == i2[0].iters

@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the spectral two-level PCG hot path on one MI355X.
+
+Workload (one "step"): 2-D log-normal diffusion -div(a grad u) = f on a
+512 x 512 cell grid (n = 262144, 5-point finite volumes, harmonic faces,
+a = exp(GRF), correlation length 0.1, sigma 1); setup = 10 weighted-Jacobi
+sweeps (w = 2/3) of m = 128 N(0,1) vectors, spectral basis of rank k = 64,
+Galerkin operator; solve = PCG with the two-grid preconditioner (nu = 1) to a
+true relative residual of 1e-8, mixed precision (float32 bulk, float64
+recurrences and reductions).  Inputs are generated once and are resident in
+HBM before timing starts.
+
+Prints one JSON line.  The headline value is the PCG time-to-1e-8 (ms, lower
+is better); setup time, the float64 path on the same inputs, the stand-alone
+SpMV bandwidth, the roofline of the dominant solver kernel and the oracle's
+time on the host cores are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=512, help="grid side (512 = the full workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the float64 and SpMV legs")
+    ap.add_argument("--timed-phase", type=int, default=0,
+                    help="solver kernel for the roofline (0 = pick the slowest)")
+    return ap.parse_args()
+
+
+def solver_bytes_per_row(phase: int, kp: int, R: int = 1) -> float:
+    """Algorithmic HBM bytes per grid row of one launch of a solver kernel,
+    mixed form, float64 cell coefficient, each array counted once:
+      kernel A (1): read z, p_old, a, Q32; write p_new, q
+                    -> 4 x 8 R + 8 + 4 kp
+      kernel B (2): read x, p, r, q, z_old, a, D^-1 (f32), Q32; write x, r_new, z
+                    -> 8 x 8 R + 8 + 4 + 4 kp
+    """
+    if phase == 1:
+        return 32.0 * R + 8.0 + 4.0 * kp
+    return 64.0 * R + 12.0 + 4.0 * kp
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2601_20174_amd as nl
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    c = W.Cfg2(N=a.N)
+    n, m, k = c.n, c.m, c.k
+    coef = c.coef()
+    S0h, fh = c.S0(), c.rhs()
+    op = nl.Operator(nl.OP_FV5, c.N, c.N, 1, torch.tensor(coef.ravel(), dtype=torch.float64, device=dev))
+    S0 = torch.tensor(S0h, dtype=torch.float64, device=dev)
+    f = torch.tensor(fh, dtype=torch.float64, device=dev)
+    kp = nl.nlsp_padded_rank(k)
+    ws_setup = torch.empty(nl.setup_spectral_P_workspace_bytes(op, m, k, nl.FP64), dtype=torch.uint8, device=dev)
+    ws_gal = torch.empty(nl.galerkin_coarse_workspace_bytes(op, k), dtype=torch.uint8, device=dev)
+    ws_pcg = torch.empty(nl.pcg_solve_workspace_bytes(op, k, 1), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step(prec, timing=None):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        P, sigma = nl.setup_spectral_P(op, S0, k, c.omega, c.s1, prec, workspace=ws_setup)
+        M = nl.galerkin_coarse(op, P, c.omega, c.nu, q64=(prec == nl.FP64), q32=(prec == nl.MIXED),
+                               workspace=ws_gal)
+        e1.record()
+        u, info, rc = nl.pcg_solve(op, M, f, prec=prec, rtol=c.rtol, workspace=ws_pcg, timing=timing)
+        e2.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2), info[0]
+
+    # pick the dominant solver kernel: time each phase once in warm-up
+    for _ in range(max(1, a.warmup)):
+        step(nl.MIXED)
+    phase = a.timed_phase
+    if phase == 0:
+        best = (0.0, 1)
+        for ph in (1, 2):
+            tm = {"phase": ph, "every": 4}
+            step(nl.MIXED, tm)
+            avg = tm["total_ms"] / max(1, tm["launches"])
+            best = max(best, (avg, ph))
+        phase = best[1]
+
+    torch.cuda.synchronize()
+    setup_ms, solve_ms, iters, relres = [], [], [], []
+    tms = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        tm = {"phase": phase, "every": 8}
+        s_ms, p_ms, inf = step(nl.MIXED, tm)
+        setup_ms.append(s_ms)
+        solve_ms.append(p_ms)
+        iters.append(inf.iters)
+        relres.append(inf.relres)
+        tms.append(tm)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1000.0
+
+    launch_ms = sum(t["total_ms"] for t in tms) / max(1, sum(t["launches"] for t in tms))
+    bytes_launch = solver_bytes_per_row(phase, kp) * n
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": "PCG time-to-1e-8 rel-residual (ms)",
+        "value": round(statistics.median(solve_ms), 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(wall / max(1, a.steps), 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"2-D log-normal diffusion FV5 {c.N}x{c.N} (n={n}), m={m}, k={k}, "
+                               f"s1={c.s1}, nu={c.nu}, omega=2/3, rtol={c.rtol}, mixed precision",
+                   "n": n, "m": m, "k": k, "rhs": 1},
+        "setup_ms": round(statistics.median(setup_ms), 4),
+        "total_ms": round(statistics.median([s + p for s, p in zip(setup_ms, solve_ms)]), 4),
+        "iters": int(statistics.median(iters)),
+        "relres": max(relres),
+        "ms_per_iter": round(statistics.median(solve_ms) / max(1, statistics.median(iters)), 5),
+        "roofline": {"bound": "hbm", "kernel": f"k_phase{phase}", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "launch_us": round(launch_ms * 1e3, 3),
+                     "bytes_per_launch": int(bytes_launch)},
+    }
+
+    if not a.no_extras:
+        s64, p64, inf64 = step(nl.FP64)
+        out["fp64"] = {"setup_ms": round(s64, 4), "solve_ms": round(p64, 4), "iters": inf64.iters,
+                       "relres": inf64.relres}
+        # stand-alone float64 SpMV y = A x, 16 right-hand sides (useful bytes:
+        # x and y once, coefficient once)
+        R = 16
+        x = torch.randn(n, R, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            nl.apply_operator(op, x, y)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        ev0.record()
+        for _ in range(reps):
+            nl.apply_operator(op, x, y)
+        ev1.record()
+        torch.cuda.synchronize()
+        sp_ms = ev0.elapsed_time(ev1) / reps
+        sp_bytes = n * (16 * R + 8)
+        out["spmv_f64"] = {"R": R, "ms": round(sp_ms, 5), "GBs": round(sp_bytes / sp_ms / 1e6, 1),
+                           "frac": round(sp_bytes / sp_ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, coef, S0h, fh, out.get("fp64", {}).get("iters", out["iters"]))
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(c, coef, S0h, fh, iters_full):
+    """The FP64 oracle on the host: full setup, then a bounded PCG sample of
+    `sample_it` iterations scaled to the full iteration count."""
+    import oracle as O
+    from oracle.method import make_preconditioner
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    A = O.fv_harmonic_2d(coef)
+    st = O.setup(A, S0h, c.k, c.omega, c.s1)
+    t1 = time.perf_counter()
+    sample_it = 200
+    Minv = make_preconditioner(A, st["P"], st["L"], c.omega, c.nu, c.nu)
+    res = O.pcg(A, fh, Minv, rtol=c.rtol, maxit=sample_it)
+    t2 = time.perf_counter()
+    it = max(1, int(res.iters[0]))
+    per_it = (t2 - t1) * 1000.0 / it
+    return {"value": round(per_it * iters_full, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
+            "setup_ms": round((t1 - t0) * 1000.0, 1), "ms_per_iter": round(per_it, 3),
+            "sample": f"oracle setup in full, then {it} PCG iterations on the same workload, "
+                      f"per-iteration time scaled to {iters_full} iterations"}
+
+
+if __name__ == "__main__":
+    main()

@@ -167,11 +167,24 @@ typedef struct {
   const float* Q32;      /* device (n, kp) or NULL */
 } nlsp_two_level;
 
+/* Optional event timing of one of the solver's two per-iteration kernels:
+ *   1  kernel A: convergence test, p <- z + beta p, q = A p, p^T q, Q^T q
+ *   2  kernel B: alpha, x += alpha p, r -= alpha q, coarse solve, smoother,
+ *      prolongation z = w + Q e, r^T z, ||r||^2
+ * hipEvents are recorded on the solver's stream around one launch in `every`. */
+typedef struct {
+  int phase;             /* 1 or 2; 0 = no timing */
+  int every;             /* time one launch in `every` (>= 1) */
+  double total_ms;       /* out: summed duration of the timed launches */
+  int launches;          /* out: number of timed launches */
+} nlsp_kernel_timing;
+
 typedef struct {
   double rtol;           /* stop when ||f - A u||_2 <= rtol ||f||_2 (per RHS) */
   int maxit;             /* iteration cap (products A p), >= 1 */
   int flexible;          /* 0: beta = r'z / r_old'z_old; 1: Polak-Ribiere beta */
   int check_every;       /* iterations enqueued between host convergence polls (>= 1) */
+  nlsp_kernel_timing* timing;  /* host, optional (NULL): per-kernel event timing */
 } nlsp_pcg_opts;
 
 typedef struct {

@@ -25,8 +25,13 @@ class NlspTwoLevel(ctypes.Structure):
                 ("Linv", c_void_p), ("Q64", c_void_p), ("Q32", c_void_p)]
 
 
+class NlspKernelTiming(ctypes.Structure):
+    _fields_ = [("phase", c_int), ("every", c_int), ("total_ms", c_double), ("launches", c_int)]
+
+
 class NlspPcgOpts(ctypes.Structure):
-    _fields_ = [("rtol", c_double), ("maxit", c_int), ("flexible", c_int), ("check_every", c_int)]
+    _fields_ = [("rtol", c_double), ("maxit", c_int), ("flexible", c_int), ("check_every", c_int),
+                ("timing", ctypes.POINTER(NlspKernelTiming))]
 
 
 class NlspRhsInfo(ctypes.Structure):

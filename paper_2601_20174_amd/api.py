@@ -204,8 +204,11 @@ class RhsInfo:
 
 def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tensor] = None,
               prec: int = FP64, rtol: float = 1e-8, maxit: int = 10000, flexible: Optional[bool] = None,
-              check_every: int = 32, workspace: Optional[torch.Tensor] = None):
-    """Returns (u, [RhsInfo per RHS], status).  ``f`` is (n,) or (n, R)."""
+              check_every: int = 32, workspace: Optional[torch.Tensor] = None,
+              timing: Optional[dict] = None):
+    """Returns (u, [RhsInfo per RHS], status).  ``f`` is (n,) or (n, R).
+    ``timing`` = {"phase": 1|2|3, "every": int} asks the library to time one
+    kernel with hipEvents; on return it also holds "total_ms" and "launches"."""
     squeeze = f.dim() == 1
     f2 = f.reshape(f.shape[0], -1)
     R = f2.shape[1]
@@ -219,12 +222,19 @@ def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tens
     if nb == 0:
         raise NlspError("pcg_solve_workspace_bytes", E_INVALID)
     ws = workspace if workspace is not None else _workspace(nb, f.device)
-    opts = _lib.NlspPcgOpts(float(rtol), int(maxit), 1 if flexible else 0, int(check_every))
+    tm = None
+    if timing is not None:
+        tm = _lib.NlspKernelTiming(int(timing.get("phase", 0)), int(timing.get("every", 1)), 0.0, 0)
+    opts = _lib.NlspPcgOpts(float(rtol), int(maxit), 1 if flexible else 0, int(check_every),
+                            ctypes.pointer(tm) if tm is not None else None)
     info = (_lib.NlspRhsInfo * R)()
     Mc = M.c(prec)
     rc = _L().pcg_solve(ctypes.byref(op.c()), ctypes.byref(Mc), _dev(f2, torch.float64, "f"),
                         _dev(u, torch.float64, "u"), R, ctypes.byref(opts), info, ws.data_ptr(),
                         ws.numel(), _stream())
     _check("pcg_solve", rc, allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    if tm is not None:
+        timing["total_ms"] = tm.total_ms
+        timing["launches"] = tm.launches
     infos: List[RhsInfo] = [RhsInfo(info[i].iters, info[i].status, info[i].relres) for i in range(R)]
     return (u.reshape(f.shape) if squeeze else u), infos, rc

@@ -15,11 +15,34 @@ namespace nlsp {
 
 constexpr int WAVE = 64;
 
+// ------------------------------------------------------------------ indices
+// Unsigned 32-bit division by a run-time constant d >= 1 with a precomputed
+// multiplier ("round-up" method, Granlund & Montgomery 1994):
+//   s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1,
+//   n / d = (mulhi(n, m) + n) >> s      exact for every 32-bit n.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.s = 0;
+  while ((1ull << f.s) < d) ++f.s;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << f.s) - d)) / d) + 1);
+  return f;
+}
+
+NLSP_DEV uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (uint32_t)(((uint64_t)__umulhi(n, f.m) + n) >> f.s);
+}
+
 // ------------------------------------------------------------------ operator
 struct OpDev {
   int kind, nx, ny, nz;
   int64_t n;
   const double* coef;
+  FastDiv fx, fxy;   // division by nx and by nx*ny
 };
 
 inline OpDev make_op(const nlsp_operator& a) {
@@ -30,6 +53,8 @@ inline OpDev make_op(const nlsp_operator& a) {
   o.nz = (a.kind == NLSP_OP_FV7) ? a.nz : 1;
   o.n = (int64_t)o.nx * o.ny * o.nz;
   o.coef = a.coef;
+  o.fx = make_fastdiv((uint32_t)o.nx);
+  o.fxy = make_fastdiv((uint32_t)o.nx * (uint32_t)o.ny);
   return o;
 }
 
@@ -140,12 +165,15 @@ NLSP_DEV T op_diag(const OpDev& op, int64_t i, int x, int y, int z) {
   }
 }
 
+// grid position of unknown i (n < 2^31 is enforced by the host checks)
 NLSP_DEV void decompose(const OpDev& op, int64_t i, int& x, int& y, int& z) {
-  const int64_t sxy = (int64_t)op.nx * op.ny;
-  z = (int)(i / sxy);
-  const int64_t rem = i - (int64_t)z * sxy;
-  y = (int)(rem / op.nx);
-  x = (int)(rem - (int64_t)y * op.nx);
+  const uint32_t ui = (uint32_t)i;
+  const uint32_t zz = fdiv(ui, op.fxy);
+  const uint32_t rem = ui - zz * op.fxy.d;
+  const uint32_t yy = fdiv(rem, op.fx);
+  z = (int)zz;
+  y = (int)yy;
+  x = (int)(rem - yy * op.fx.d);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -178,23 +206,65 @@ NLSP_DEV double block_sum(double v, double* sh) {
   return s;
 }
 
-// Every workgroup of a grid-wide reduction calls this after writing its
-// partials.  Returns true (in all threads) in the workgroup that arrives
-// last; that workgroup may then read every partial.  The ticket is reset by
-// the last workgroup so the next launch can reuse it.
-NLSP_DEV bool arrive_last(unsigned* ticket, unsigned nblocks) {
+// Cross-workgroup partial sums.  Partials are written and read with
+// agent-scope relaxed atomics, which compile to device-coherent stores and
+// loads (sc1) that go to the coherence point shared by all XCDs instead of
+// requiring a write-back of the whole L2 (what __threadfence() costs here).
+NLSP_DEV void store_partial(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+NLSP_DEV double load_partial(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide reductions finish inside the producing kernel in two levels.
+// Workgroups are grouped by TICKET_GROUP consecutive logical indices.  Every
+// workgroup writes its partial record with store_partial and calls
+// arrive_group; the last workgroup of a group (arrive_group == true) sums the
+// group's records, publishes a group record and calls arrive_top; the last of
+// those (arrive_top == true) sums the group records.  Before each ticket
+// every thread waits until its own device-coherent stores have completed.
+// Counters are 64 bytes apart and are reset by the workgroup completing them.
+// `tickets` holds ticket_words(nblocks) unsigned ints, zero before first use.
+constexpr int TICKET_GROUP = 16;
+constexpr int TICKET_STRIDE = 16;
+
+__host__ __device__ inline int ticket_groups(int nblocks) { return (nblocks + TICKET_GROUP - 1) / TICKET_GROUP; }
+__host__ __device__ inline int ticket_words(int nblocks) { return TICKET_STRIDE * (1 + ticket_groups(nblocks)); }
+
+NLSP_DEV void wait_own_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // all of this thread's memory operations done
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+NLSP_DEV bool arrive_group(unsigned* tickets, unsigned nblocks, unsigned lb) {
   __shared__ int s_last;
-  __threadfence();
+  wait_own_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned t = atomicAdd(ticket, 1u);
-    s_last = (t == nblocks - 1) ? 1 : 0;
-    if (s_last) *ticket = 0u;
+    const unsigned grp = lb / TICKET_GROUP;
+    const unsigned gsize = min((unsigned)TICKET_GROUP, nblocks - grp * TICKET_GROUP);
+    unsigned* gt = tickets + TICKET_STRIDE * (1 + grp);
+    const unsigned t1 = __hip_atomic_fetch_add(gt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t1 == gsize - 1) ? 1 : 0;
+    if (s_last) __hip_atomic_store(gt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
+  return s_last != 0;
+}
+
+NLSP_DEV bool arrive_top(unsigned* tickets, unsigned ngroups) {
+  __shared__ int s_last;
+  wait_own_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t2 = __hip_atomic_fetch_add(tickets, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t2 == ngroups - 1) ? 1 : 0;
+    if (s_last) __hip_atomic_store(tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return s_last != 0;
 }
 
 }  // namespace nlsp

@@ -36,7 +36,9 @@ struct Carver {
   size_t bytes() const { return align_up(off); }
 };
 
-inline int64_t op_size(const nlsp_operator* A) {
+// Number of unknowns, -1 if the descriptor is invalid.  Device index math
+// is 32-bit: n must stay below 2^31.
+inline int64_t op_size_raw(const nlsp_operator* A) {
   if (!A) return -1;
   if (A->nx < 1 || A->ny < 1) return -1;
   switch (A->kind) {
@@ -52,6 +54,11 @@ inline int64_t op_size(const nlsp_operator* A) {
     default:
       return -1;
   }
+}
+
+inline int64_t op_size(const nlsp_operator* A) {
+  const int64_t n = op_size_raw(A);
+  return (n >= (int64_t(1) << 31)) ? -1 : n;
 }
 
 inline int padded_rank(int k) {

@@ -44,7 +44,7 @@ __global__ void k_q1_stencil(int nsys, const double* __restrict__ et, double* __
 __global__ void k_apply_f64(OpDev op, const double* __restrict__ x, double* __restrict__ y, int R) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= op.n * R) return;
-  const int64_t i = g / R;
+  const int64_t i = (uint32_t)g / (uint32_t)R;
   const int c = (int)(g - i * R);
   int px, py, pz;
   decompose(op, i, px, py, pz);
@@ -55,7 +55,7 @@ __global__ void k_jacobi_f32(OpDev op, float omega, const float* __restrict__ b,
                              const float* __restrict__ x, float* __restrict__ y, int R) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= op.n * R) return;
-  const int64_t i = g / R;
+  const int64_t i = (uint32_t)g / (uint32_t)R;
   const int c = (int)(g - i * R);
   int px, py, pz;
   decompose(op, i, px, py, pz);
@@ -99,7 +99,7 @@ int q1_aniso_stencil(int nsys, const double* eps_theta, double* stencil, void* s
 
 int apply_operator(const nlsp_operator* A, const double* x, double* y, int R, void* stream) {
   const int64_t n = op_size(A);
-  if (n < 1 || !x || !y || R < 1 || x == y) return NLSP_E_INVALID;
+  if (n < 1 || !x || !y || R < 1 || x == y || n * R >= (int64_t(1) << 31)) return NLSP_E_INVALID;
   const OpDev op = make_op(*A);
   hipLaunchKernelGGL(k_apply_f64, dim3(ceil_div(n * R, 256)), dim3(256), 0, as_stream(stream), op, x,
                      y, R);
@@ -110,7 +110,8 @@ int apply_operator(const nlsp_operator* A, const double* x, double* y, int R, vo
 int jacobi_sweep_f32(const nlsp_operator* A, double omega, const float* b, const float* x,
                      float* y, int R, void* stream) {
   const int64_t n = op_size(A);
-  if (n < 1 || !b || !x || !y || R < 1 || x == y || !(omega > 0)) return NLSP_E_INVALID;
+  if (n < 1 || !b || !x || !y || R < 1 || x == y || !(omega > 0) || n * R >= (int64_t(1) << 31))
+    return NLSP_E_INVALID;
   const OpDev op = make_op(*A);
   hipLaunchKernelGGL(k_jacobi_f32, dim3(ceil_div(n * R, 256)), dim3(256), 0, as_stream(stream), op,
                      (float)omega, b, x, y, R);

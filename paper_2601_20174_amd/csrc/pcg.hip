@@ -7,20 +7,28 @@
 //     M^-1 r = J_{2nu} r + Q A_c^-1 Q^T r,     Q = (I - w D^-1 A)^nu P,
 // (J_{2nu} r = 2nu Jacobi sweeps on A z = r from z = 0).  Q and the inverse
 // Cholesky factor of A_c come from galerkin_coarse.  For nu = 1,
-// J_2 r = 2w D^-1 r - w^2 D^-1 A D^-1 r needs one stencil pass, which is fused
-// with the prolongation; the restriction Q^T r is fused with the r update.
+// J_2 r = 2w D^-1 r - w^2 D^-1 A D^-1 r needs one stencil pass.
 //
-// One iteration = three kernels, each ending in a grid reduction finished by
-// the last workgroup to arrive (fixed summation order, so results are
-// bitwise reproducible):
-//   phase 1  p <- z + beta p (double-buffered), q = A p, partial p^T q
-//            last WG: alpha = gamma / p^T q
-//   phase 2  x += alpha p, r -= alpha q, partial ||r||^2, partial Q^T r
-//            last WG: convergence test, e = L^-T L^-1 (Q^T r)
-//   phase 3  w = J_2 r, z = w + Q e, partial r^T z (and r^T z_old)
-//            last WG: beta
+// One iteration = two kernels and two grid reductions.  The restriction is
+// linear, so Q^T r_new = Q^T r - alpha Q^T q: kernel A restricts q instead of
+// the new residual, and the residual update, smoother and prolongation share
+// kernel B without a grid synchronisation between them.
+//   kernel A  convergence test of r; beta; p <- z + beta p (double buffer);
+//             q = A p; partials p^T q and Q^T q
+//   kernel B  alpha; c <- c - alpha Q^T q; e = A_c^-1 c; x += alpha p;
+//             r_new = r - alpha q (double buffer); z = J r_new + Q e;
+//             partials r^T z, r^T z_old, ||r||^2
+// Grid reductions are finished by the consumer: every workgroup of the next
+// kernel sums the per-workgroup partials it needs in a fixed order (so all
+// workgroups obtain bit-identical scalars and runs are reproducible), while its
+// own loads are in flight.  Only Q^T q (k values per RHS) is pre-summed by the
+// last workgroup of each group of 16 inside kernel A (and, for large k*R,
+// once more by the last group).  The per-RHS state is double-buffered by
+// iteration parity: iteration `it` reads stat[it & 1] and only workgroup 0 of
+// kernel B writes stat[(it + 1) & 1].
 // Vectors and every reduction are float64; in the mixed form Q, the smoother
 // and the prolongation products are float32.
+#include <cstdlib>
 #include <vector>
 
 #include "device_common.hpp"
@@ -28,48 +36,53 @@
 
 namespace nlsp {
 
-constexpr int NT = 512;  // threads per workgroup of the solver kernels
+constexpr int NT = 512;   // threads per workgroup of the solver kernels
+constexpr int MAXR = 16;  // right-hand sides per solve
 
-struct RhsState {
-  double gamma, alpha, beta, delta;
-  double rr, ff, rzold, rr_true;
-  int active, iters, status, conv;
-  int par, pad0, pad1, pad2;
+struct RhsStatus {
+  double gamma_old;  // r^T z of the previous iteration (beta's denominator)
+  double ff;         // ||f||^2
+  int active;        // still iterating
+  int iters;         // updates of x completed
+  int status;        // nlsp_status of this RHS
+  int par;           // p buffer holding the current direction
+  int restart;       // next kernel A uses beta = 0
+  int conv;          // stopped by the recursive residual test (true residual pending)
+  int pad0, pad1;
 };
 
 struct SysDev {
   OpDev op;
   int R, kp, nblk, blk0;
-  int chunk_rows;          // rows per chunk: floor(NT / R); threads past chunk_rows*R idle in elementwise parts
+  int chunk_rows;          // rows per chunk: floor(NT / R); threads past chunk_rows*R idle
   int64_t nchunks;
+  int rw;                  // restriction record width: kp*R + 2R
   const void* Q;           // (n, kp), float or double
-  const double* Linv;      // (kp, kp)
+  const double* Linv;      // (kp, kp) inverse Cholesky factor of A_c
+  const double* Ainv;      // (kp, kp) = L^-T L^-1
   const double* f;
   double* x;
-  double* r;
-  double* p0;
-  double* p1;
+  double* r[2];            // residual, by iteration parity
+  double* p[2];            // search direction, by RhsStatus::par
   double* q;
   double* z;
-  void* w0;                // J_{2nu} r work buffers (nu > 1), element type of Q
-  void* w1;
+  void* w[2];              // J_{2nu} r work buffers (nu > 1), element type of Q
   const double* dinv;
   const float* dinv32;
-  double* part;            // nblk * pstride partial sums
-  int pstride;
-  int nu;
-  unsigned* ticket;
-  RhsState* st;
-  int* sys_active;
-  double* e;               // (kp, R)
+  double* bpart[2];        // [nblk][3R]  kernel-B partials [r^T z | r^T z_old | ||r||^2], by parity
+  double* rpart;           // [nblk][rw]  restriction records [Q^T v | v-scalar | ||f||^2]
+  double* rgrp;            // [ngrp][rw]  group records
+  double* etop;            // [rw]        [A_c^-1 Q^T v | s1 | s2] of the last restriction
+  double* estate[2];       // [kp*R]      e = A_c^-1 Q^T r by parity
+  double* dpart;           // [nblk][R]   true-residual partials
+  unsigned* ticket;        // ticket_words(nblk)
+  RhsStatus* stat[2];      // [R] each
+  int* nact;               // [2] active RHS in the stat buffer of that parity
+  int* n_active;           // host-visible copy
+  double* rr_true;         // [R]
   double omega, tol2;
-  int maxit, flexible;
+  int maxit, flexible, nu;
 };
-
-// partial-sum slots inside one workgroup's record (doubles)
-// [0, kp*R) restriction, then R each for: delta, rr, gamma', r^T z_old, ff
-NLSP_DEV int slot_scalar(const SysDev& S, int which) { return S.kp * S.R + which * S.R; }
-enum { SL_DELTA = 0, SL_RR = 1, SL_GAM = 2, SL_RZOLD = 3, SL_FF = 4, SL_COUNT = 5 };
 
 // XCD-aware order: hardware places workgroup b on XCD b % 8; give each XCD a
 // contiguous range of logical blocks so that stencil halos are served from
@@ -104,206 +117,269 @@ NLSP_DEV void load4(const QT* p, QT (&v)[4]) {
   v[3] = t.w;
 }
 
+// ------------------------------------------------------------- reductions
+// In-place tree sum over "rows" of an LDS array laid out as sh[row*W + col]
+// (rows 0..nrows-1, W columns): on return sh[col] holds the column sums.
+// Pairing is fixed (row r with row r + h), so the result is deterministic.
+// All threads call; contains __syncthreads.
+NLSP_DEV void lds_tree_rows(double* sh, int nrows, int W) {
+  __syncthreads();
+  while (nrows > 1) {
+    const int h = (nrows + 1) / 2;
+    for (int idx = threadIdx.x; idx < (nrows - h) * W; idx += NT) sh[idx] += sh[idx + h * W];
+    __syncthreads();
+    nrows = h;
+  }
+}
+
 // Sum of per-thread values over the threads that share c = t % R; the totals
 // land in red[c] (LDS) for c < R.  Deterministic.  All threads call.
-NLSP_DEV void block_sum_rhs(double v, int R, double* red, double* sh /* NT doubles */) {
+// `sh` holds NT + 16 doubles.
+NLSP_DEV void block_sum_rhs(double v, int R, double* red, double* sh) {
   const int t = threadIdx.x;
+  const int nrows = (NT + R - 1) / R;
   __syncthreads();
   sh[t] = v;
-  __syncthreads();
-  if (t < R) {
-    double s = 0.0;
-    for (int k = t; k < NT; k += R) s += sh[k];
-    red[t] = s;
-  }
+  if (t < nrows * R - NT) sh[NT + t] = 0.0;   // pad the last partial row
+  lds_tree_rows(sh, nrows, R);
+  if (t < R) red[t] = sh[t];
   __syncthreads();
 }
 
-// Last-workgroup reduction of `count` consecutive partial slots starting at
-// `off` over all nblk records.  Result in out[0..count) (LDS).  All threads of
-// the last workgroup call.
-NLSP_DEV void reduce_partials(const SysDev& S, int off, int count, double* out, double* sh) {
+// Sum of `count` consecutive slots starting at `off` over `nrec` records of
+// `stride` doubles at `base`, in ascending record order per thread and a fixed
+// tree across threads; result in out[0..count) (LDS).  COHERENT selects
+// device-coherent loads (records written earlier in the same kernel by other
+// workgroups); plain loads serve records from a previous kernel.  Loads are
+// issued in batches so their latencies overlap.  All threads call.
+template <bool COHERENT>
+NLSP_DEV void sum_records(const double* base, int nrec, int stride, int off, int count, double* out,
+                          double* sh) {
+  constexpr int B = 8;
   const int t = threadIdx.x;
-  const double* P = S.part;
-  for (int base = 0; base < count; base += NT) {
-    const int cnt = min(NT, count - base);
+  for (int c0 = 0; c0 < count; c0 += NT) {
+    const int cnt = min(NT, count - c0);
     const int groups = NT / cnt;               // >= 1
     const int e = t % cnt, g = t / cnt;
     double s = 0.0;
-    if (g < groups)
-      for (int b = g; b < S.nblk; b += groups) s += P[(int64_t)b * S.pstride + off + base + e];
-    __syncthreads();
-    sh[t] = (g < groups) ? s : 0.0;
-    __syncthreads();
-    if (t < cnt) {
-      double tot = 0.0;
-      for (int gg = 0; gg < groups; ++gg) tot += sh[gg * cnt + t];
-      out[base + t] = tot;
+    if (g < groups) {
+      for (int r0 = g; r0 < nrec; r0 += B * groups) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int r = r0 + u * groups;
+          const double* a = &base[(int64_t)r * stride + off + c0 + e];
+          v[u] = (r < nrec) ? (COHERENT ? load_partial(a) : *a) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) s += v[u];
+      }
     }
     __syncthreads();
+    sh[t] = (g < groups) ? s : 0.0;
+    lds_tree_rows(sh, groups, cnt);
+    if (t < cnt) out[c0 + t] = sh[t];
+    __syncthreads();
   }
 }
 
-NLSP_DEV void deactivate(const SysDev& S, int c, int status, int* n_active) {
-  S.st[c].active = 0;
-  S.st[c].status = status;
-  atomicSub(S.sys_active, 1);
-  atomicSub(n_active, 1);
+// Small reductions split in two so that their loads can be issued before a
+// large prefetch (vector loads of a wave complete in issue order): rec_issue
+// loads the records a thread sums (at most 8; the caller checks rec_fits),
+// rec_finish adds them in ascending record order and across threads with a
+// fixed tree.  Same result as sum_records.
+NLSP_DEV bool rec_fits(int nrec, int count) { return count <= NT && nrec <= 8 * (NT / count); }
+
+template <bool COHERENT>
+NLSP_DEV void rec_issue(const double* base, int nrec, int stride, int off, int count, double (&v)[8]) {
+  const int t = threadIdx.x;
+  const int groups = NT / count, e = t % count, g = t / count;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int r = g + u * groups;
+    const double* a = &base[(int64_t)r * stride + off + e];
+    v[u] = (g < groups && r < nrec) ? (COHERENT ? load_partial(a) : *a) : 0.0;
+  }
 }
 
-// e = L^-T (L^-1 c) for every RHS, c in LDS (kp*R), result to S.e (global).
-NLSP_DEV void coarse_solve(const SysDev& S, const double* cvec, double* tmp) {
-  const int kp = S.kp, R = S.R, t = threadIdx.x;
-  for (int idx = t; idx < kp * R; idx += NT) {
-    const int i = idx / R, c = idx % R;
-    double s = 0.0;
-    for (int j = 0; j <= i; ++j) s += S.Linv[i * kp + j] * cvec[j * R + c];
-    tmp[idx] = s;
-  }
+NLSP_DEV void rec_finish(const double (&v)[8], int count, double* out, double* sh) {
+  const int t = threadIdx.x;
+  const int groups = NT / count, g = t / count;
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s += v[u];
   __syncthreads();
-  for (int idx = t; idx < kp * R; idx += NT) {
-    const int i = idx / R, c = idx % R;
-    double s = 0.0;
-    for (int j = i; j < kp; ++j) s += S.Linv[j * kp + i] * tmp[j * R + c];
-    S.e[idx] = s;
+  sh[t] = (g < groups) ? s : 0.0;
+  lds_tree_rows(sh, groups, count);
+  if (t < count) out[t] = sh[t];
+  __syncthreads();
+}
+
+// e = A_c^-1 c for every RHS: c in LDS (kp*R, layout j*R + r), result to
+// eout (LDS or global, same layout).  Thread t takes row i = t / SL of A_c^-1
+// and the column slice js = t % SL (SL consecutive lanes), all R right-hand
+// sides at once; the slices are added with butterflies.
+NLSP_DEV void coarse_apply(const double* __restrict__ Ainv, int kp, int R, const double* cvec,
+                           double* eout) {
+  const int t = threadIdx.x;
+  const int SL = min(NT / kp, kp);            // lanes per row (power of two, <= kp)
+  const int i = t / SL, js = t % SL;
+  const int len = kp / SL;                    // >= 1
+  const bool on = i < kp;                     // threads past kp*SL are idle
+  double acc[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) acc[r] = 0.0;
+  const double* row = Ainv + (int64_t)(on ? i : 0) * kp + js * len;
+  for (int j0 = 0; on && j0 < len; j0 += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = (j0 + u < len) ? row[j0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u >= len) break;
+      const int j = js * len + j0 + u;
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r)
+        if (r < R) acc[r] += a[u] * cvec[j * R + r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    if (r < R) {
+      const double v = group_sum(acc[r], SL);
+      if (on && js == 0) eout[i * R + r] = v;
+    }
   }
 }
 
-// Restriction accumulators: thread t owns column chunk jc (4 columns) of RHS c
-// for row group rg; the workgroup streams rows of Q with consecutive lanes on
-// consecutive 4-column chunks of a row (coalesced).
-struct RestrictMap {
-  int lpr, pairs, rg, ngr, jc, c, npair_iter;
+// A_c^-1 = Linv^T Linv (kp x kp), once per solve
+__global__ void k_coarse_inverse(const double* __restrict__ Linv, int kp, double* __restrict__ Ainv) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kp * kp) return;
+  const int i = idx / kp, j = idx % kp;
+  double s = 0.0;
+  for (int l = (i > j ? i : j); l < kp; ++l) s += Linv[l * kp + i] * Linv[l * kp + j];
+  Ainv[idx] = s;
+}
+
+// ------------------------------------------------------------------ Q passes
+// Thread t owns the 4-column chunk jc of right-hand side c in row group rg:
+// t = jc + lpr*(c + R*rg), lpr = kp/4 lanes per row, so consecutive lanes read
+// consecutive 16-byte pieces of a row of Q (coalesced) and the lanes of one
+// row form an aligned group for butterflies.  Row group rg handles the chunk
+// rows rg, rg + ngr, rg + 2 ngr, ...  kp*R <= 2048 keeps lpr*R <= NT.
+struct QMap {
+  int lpr, ngr, rg, jc, c;
+  bool on;
 };
 
-NLSP_DEV RestrictMap restrict_map(int kp, int R) {
-  RestrictMap m;
+NLSP_DEV QMap q_map(int kp, int R) {
+  QMap m;
   const int t = threadIdx.x;
   m.lpr = kp / 4;
-  m.pairs = m.lpr * R;
-  if (m.pairs <= NT) {
-    m.ngr = NT / m.pairs;
-    m.rg = t / m.pairs;
-    const int pr = t % m.pairs;
-    m.jc = pr % m.lpr;
-    m.c = pr / m.lpr;
-    m.npair_iter = 1;
-  } else {
-    m.ngr = 1;
-    m.rg = 0;
-    m.jc = 0;
-    m.c = 0;
-    m.npair_iter = (m.pairs + NT - 1) / NT;
-  }
+  const int pairs = m.lpr * R;
+  m.ngr = NT / pairs;
+  m.rg = t / pairs;
+  const int pr = t % pairs;
+  m.jc = pr % m.lpr;
+  m.c = pr / m.lpr;
+  m.on = m.rg < m.ngr;
   return m;
 }
 
-template <typename QT>
-NLSP_DEV double prod(QT q, double r) {
-  return (double)(q * (QT)r);  // float32 products in the mixed form
+// rows handled by a thread in a chunk of nrows rows (uniform over the workgroup)
+NLSP_DEV int q_trips(const QMap& m, int nrows) { return (nrows + m.ngr - 1) / m.ngr; }
+
+// NB rows of Q for one thread, issued together so their latencies overlap
+template <typename QT, int NB>
+struct QBatch {
+  QT v[NB][4];
+};
+
+template <typename QT, int NB>
+NLSP_DEV void q_fetch(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, const QMap& m,
+                      int w0, QBatch<QT, NB>& b) {
+#pragma unroll
+  for (int w = 0; w < NB; ++w) {
+    const int row = m.rg + (w0 + w) * m.ngr;
+    if (m.on && row < nrows) {
+      load4(Q + (row0 + row) * kp + 4 * m.jc, b.v[w]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) b.v[w][u] = QT(0);
+    }
+  }
 }
 
-// acc[pi][u] += sum over the chunk rows of Q[row][4 jc + u] * rv[row*R + c]
-template <typename QT, int MAXP>
-NLSP_DEV void restrict_chunk(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, int R,
-                             const RestrictMap& m, const double* rv, double (&acc)[MAXP][4]) {
-  if (m.pairs <= NT) {
-    if (m.rg >= m.ngr) return;
-    const QT* qb = Q + (row0 + m.rg) * kp + 4 * m.jc;
-    const int stride = m.ngr;
-    int row = m.rg;
-#pragma unroll 4
-    for (; row < nrows; row += stride) {
-      QT qv[4];
-      load4(qb, qv);
-      qb += (int64_t)stride * kp;
-      const double rvv = rv[row * R + m.c];
+// Restriction products are formed in float64 also when Q is stored in float32:
+// Q^T r is carried by the recurrence c <- c - alpha Q^T q, whose absolute
+// error must stay far below |Q^T r| as r shrinks by 1e-8 (float32 products
+// would leave an error near 1e-7 |Q^T r_0|).  Storage, and so traffic, stay
+// float32.
+template <typename QT>
+NLSP_DEV double prod(QT q, double r) {
+  return (double)q * r;
+}
+
+// acc[u] += sum over the thread's chunk rows of Q[row][4 jc + u] * rv[row*R + c];
+// `b` holds the first batch (fetched by the caller), later batches are fetched
+// here.
+template <typename QT, int NB>
+NLSP_DEV void restrict_rows(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, int R,
+                            const QMap& m, const double* rv, QBatch<QT, NB>& b, double (&acc)[4]) {
+  const int trips = q_trips(m, nrows);
+  for (int w0 = 0; w0 < trips; w0 += NB) {
+    if (w0 > 0) q_fetch<QT, NB>(Q, row0, nrows, kp, m, w0, b);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[0][u] += prod<QT>(qv[u], rvv);
-    }
-  } else {
-    for (int pi = 0; pi < m.npair_iter && pi < MAXP; ++pi) {
-      const int pr = threadIdx.x + pi * NT;
-      if (pr >= m.pairs) break;
-      const int jc = pr % m.lpr, c = pr / m.lpr;
-      for (int row = 0; row < nrows; ++row) {
-        QT qv[4];
-        load4(Q + (row0 + row) * kp + 4 * jc, qv);
-        const double rvv = rv[row * R + c];
+    for (int w = 0; w < NB; ++w) {
+      const int row = m.rg + (w0 + w) * m.ngr;
+      if (m.on && row < nrows) {
+        const double r = rv[row * R + m.c];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[pi][u] += prod<QT>(qv[u], rvv);
+        for (int u = 0; u < 4; ++u) acc[u] += prod<QT>(b.v[w][u], r);
       }
     }
   }
 }
 
-// Workgroup total of the restriction accumulators -> part[0 .. kp*R) of this
-// workgroup's record (layout j*R + c).  red: LDS of 32*NT bytes.
-template <int MAXP>
-NLSP_DEV void restrict_finish(const RestrictMap& m, int kp, int R, double (&acc)[MAXP][4],
-                              double* red, double* out) {
-  const int t = threadIdx.x;
-  if (m.pairs <= NT) {
-    const int KR = kp * R;
-    __syncthreads();
-    if (m.rg < m.ngr) {
+// Workgroup total of the restriction accumulators -> out[0 .. kp*R) (layout
+// j*R + c) with device-coherent stores.  red: LDS of >= 4*NT doubles.
+NLSP_DEV void restrict_finish(const QMap& m, int kp, int R, const double (&acc)[4], double* red,
+                              double* out) {
+  const int KR = kp * R;
+  __syncthreads();
+  if (m.on) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) red[m.rg * KR + (4 * m.jc + u) * R + m.c] = acc[0][u];
-    }
-    __syncthreads();
-    for (int idx = t; idx < KR; idx += NT) {
-      double s = 0.0;
-      for (int g = 0; g < m.ngr; ++g) s += red[g * KR + idx];
-      out[idx] = s;
-    }
-  } else {
-    for (int pi = 0; pi < m.npair_iter && pi < MAXP; ++pi) {
-      const int pr = t + pi * NT;
-      if (pr >= m.pairs) break;
-      const int jc = pr % m.lpr, c = pr / m.lpr;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) out[(4 * jc + u) * R + c] = acc[pi][u];
-    }
+    for (int u = 0; u < 4; ++u) red[m.rg * KR + (4 * m.jc + u) * R + m.c] = acc[u];
   }
+  lds_tree_rows(red, m.ngr, KR);
+  for (int idx = threadIdx.x; idx < KR; idx += NT) store_partial(&out[idx], red[idx]);
 }
 
 // ys[row*R + c] = sum_j Q[row][j] e[j][c] for the chunk rows (prolongation),
-// arithmetic in QT; lanes of a row reduce with butterflies.
-template <typename QT>
-NLSP_DEV void prolong_chunk(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, int R,
-                            const QT* ev /* LDS (kp*R) */, QT* ys) {
-  const int t = threadIdx.x;
-  const int lpr = kp / 4, pairs = lpr * R;
-  if (pairs <= NT) {
-    const int ngr = NT / pairs, rg = t / pairs, pr = t % pairs;
-    const int jc = pr % lpr, c = pr / lpr;
-    QT e4[4];
+// arithmetic in QT; the lpr lanes of a row add with butterflies.  All lanes
+// run the same trip count (shuffles need the whole wave).
+template <typename QT, int NB>
+NLSP_DEV void prolong_rows(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, int R,
+                           const QMap& m, const QT (&e4)[4], QBatch<QT, NB>& b, QT* ys) {
+  const int trips = q_trips(m, nrows);
+  for (int w0 = 0; w0 < trips; w0 += NB) {
+    if (w0 > 0) q_fetch<QT, NB>(Q, row0, nrows, kp, m, w0, b);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) e4[u] = ev[(4 * jc + u) * R + c];
-    // all lanes of a wave must take part in the butterflies: iterate a
-    // uniform trip count and mask the rows past the end
-    const int trips = (nrows + ngr - 1) / ngr;
-#pragma unroll 4
-    for (int it = 0; it < trips; ++it) {
-      const int row = rg + it * ngr;
-      QT s = QT(0);
-      if (rg < ngr && row < nrows) {
-        QT qv[4];
-        load4(Q + (row0 + row) * kp + 4 * jc, qv);
-        s = qv[0] * e4[0] + qv[1] * e4[1] + qv[2] * e4[2] + qv[3] * e4[3];
-      }
-      s = group_sum(s, lpr);
-      if (jc == 0 && rg < ngr && row < nrows) ys[row * R + c] = s;
-    }
-  } else {
-    for (int idx = t; idx < nrows * R; idx += NT) {
-      const int row = idx / R, c = idx % R;
-      QT s = QT(0);
-      for (int j = 0; j < kp; ++j) s += Q[(row0 + row) * kp + j] * ev[j * R + c];
-      ys[idx] = s;
+    for (int w = 0; w < NB; ++w) {
+      if (w0 + w >= trips) break;
+      const int row = m.rg + (w0 + w) * m.ngr;
+      QT sdot = b.v[w][0] * e4[0] + b.v[w][1] * e4[1] + b.v[w][2] * e4[2] + b.v[w][3] * e4[3];
+      sdot = group_sum(sdot, m.lpr);
+      if (m.jc == 0 && m.on && row < nrows) ys[row * R + m.c] = sdot;
     }
   }
 }
+
+template <typename QT>
+struct QB {
+  static constexpr int NB = (sizeof(QT) == 4) ? 8 : 4;  // 32 registers either way
+};
 
 struct ChunkRange {
   int64_t c0, c1;
@@ -317,6 +393,101 @@ NLSP_DEV ChunkRange my_chunks(const SysDev& S, int lb) {
   return cr;
 }
 
+// Restriction epilogue (kernel A and k_residual): this workgroup's record
+// [Q^T v | s1 | s2] (already in rpart) is summed per group of 16 by the
+// group's last workgroup into rgrp; the last group then sums the group
+// records, applies A_c^-1 to the Q^T v part and publishes
+// etop = [A_c^-1 Q^T v | s1 | s2] for the next kernel.
+NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double* sh) {
+  if (!arrive_group(S.ticket, S.nblk, lb)) return;
+  const int grp = lb / TICKET_GROUP;
+  const int r0 = grp * TICKET_GROUP;
+  const int nrec = min(TICKET_GROUP, S.nblk - r0);
+  sum_records<true>(S.rpart + (int64_t)r0 * S.rw, nrec, S.rw, 0, S.rw, red, sh);
+  double* grec = S.rgrp + (int64_t)grp * S.rw;
+  for (int idx = threadIdx.x; idx < S.rw; idx += NT) store_partial(&grec[idx], red[idx]);
+  if (!arrive_top(S.ticket, ticket_groups(S.nblk))) return;
+  sum_records<true>(S.rgrp, ticket_groups(S.nblk), S.rw, 0, S.rw, red, sh);
+  const int KR = S.kp * S.R;
+  coarse_apply(S.Ainv, S.kp, S.R, red, S.etop);
+  for (int idx = threadIdx.x; idx < 2 * S.R; idx += NT) S.etop[KR + idx] = red[KR + idx];
+}
+
+// ----------------------------------------------------- per-iteration scalars
+// What every workgroup of kernels A and B derives from kernel B's partials of
+// the previous iteration: r^T z, r^T z_old and ||r||^2 of the current residual,
+// the convergence test and whether the direction is updated.
+struct IterScalars {
+  double gam[MAXR], rzo[MAXR], rr[MAXR], beta[MAXR];
+  int conv[MAXR];       // ||r|| <= rtol ||f||
+  int act[MAXR];        // direction and q computed this iteration
+  int bad[MAXR];        // r^T z not positive / not finite, or ||r|| not finite
+};
+
+NLSP_DEV bool finite_pos(double v) { return v > 0.0 && v <= 1.7e308; }
+
+// Loads of kernel B's partials [r^T z | r^T z_old | ||r||^2] of iteration it,
+// issued early (see rec_issue); `fast` is false when they do not fit.
+struct ScalarLoads {
+  double v[8];
+  bool fast;
+};
+
+NLSP_DEV void scalars_issue(const SysDev& S, int it, ScalarLoads& L) {
+  L.fast = rec_fits(S.nblk, 3 * S.R);
+  if (L.fast) rec_issue<false>(S.bpart[it & 1], S.nblk, 3 * S.R, 0, 3 * S.R, L.v);
+}
+
+NLSP_DEV void scalars_finish(const SysDev& S, const RhsStatus* cur, const ScalarLoads& L,
+                             IterScalars& sc, double* buf, double* sh, int it) {
+  const int R = S.R;
+  if (L.fast) {
+    rec_finish(L.v, 3 * R, buf, sh);
+  } else {
+    sum_records<false>(S.bpart[it & 1], S.nblk, 3 * R, 0, 3 * R, buf, sh);
+  }
+  if (threadIdx.x < R) {
+    const int c = threadIdx.x;
+    const RhsStatus& st = cur[c];
+    const double g = buf[c], rz = buf[R + c], rr = buf[2 * R + c];
+    sc.gam[c] = g;
+    sc.rzo[c] = rz;
+    sc.rr[c] = rr;
+    const int rr_ok = rr <= 1.7e308;                       // false for NaN / Inf
+    sc.conv[c] = st.active && rr_ok && rr <= S.tol2 * st.ff;
+    sc.bad[c] = st.active && !sc.conv[c] && (!rr_ok || !finite_pos(g));
+    sc.act[c] = st.active && !sc.conv[c] && !sc.bad[c] && st.iters < S.maxit;
+    double beta = 0.0;
+    if (!st.restart && sc.act[c])
+      beta = S.flexible ? (g - rz) / st.gamma_old : g / st.gamma_old;
+    sc.beta[c] = beta;
+  }
+  __syncthreads();
+}
+
+// Sum over the threads sharing c = t % R of three values at once: the totals
+// land in red[k*R + c], k < 3.  One tree instead of three.  `sh` holds
+// 3*(NT + 16) doubles.
+NLSP_DEV void block_sum_rhs3(double a, double b, double d, int R, double* red, double* sh) {
+  const int t = threadIdx.x;
+  const int nrows = (NT + R - 1) / R;
+  __syncthreads();
+  // row-major [row][3R]: thread t = row*R + c
+  const int row = t / R, c = t % R;
+  sh[row * 3 * R + c] = a;
+  sh[row * 3 * R + R + c] = b;
+  sh[row * 3 * R + 2 * R + c] = d;
+  if (t < nrows * R - NT) {   // pad the last partial row
+    const int pr = (NT + t) / R, pc = (NT + t) % R;
+    sh[pr * 3 * R + pc] = 0.0;
+    sh[pr * 3 * R + R + pc] = 0.0;
+    sh[pr * 3 * R + 2 * R + pc] = 0.0;
+  }
+  lds_tree_rows(sh, nrows, 3 * R);
+  if (t < 3 * R) red[t] = sh[t];
+  __syncthreads();
+}
+
 // ----------------------------------------------------------------- kernels
 __global__ __launch_bounds__(NT) void k_dinv(OpDev op, double* dinv, float* dinv32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -328,29 +499,33 @@ __global__ __launch_bounds__(NT) void k_dinv(OpDev op, double* dinv, float* dinv
   dinv32[i] = (float)d;
 }
 
-// r = f - A x for the RHS in `mask`; partial ||r||^2, Q^T r and (init) ||f||^2.
-// Last workgroup: coarse solve, (re)activation.  Used at start-up (init = 1)
-// and for residual replacement (init = 0).
+// r = f - A x into `rout` for the RHS in `mask` (others untouched);
+// restriction records [Q^T r | ||r||^2 | ||f||^2], then the group (and top)
+// epilogue.  Used at start-up and for residual replacement.
 template <typename QT>
-__global__ __launch_bounds__(NT) void k_residual(const SysDev* __restrict__ sys,
-                                                 const int* __restrict__ blk2sys, int nsys,
-                                                 int* n_active, unsigned mask, int init) {
+__global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ sys,
+                                                    const int* __restrict__ blk2sys, int nsys,
+                                                    unsigned mask, int rout) {
   __shared__ double rv[NT];
-  __shared__ double sh[NT];
-  __shared__ double red[4 * NT];
-  __shared__ double outv[4 * NT];
+  __shared__ double sh[NT + 16];
+  __shared__ double red[4 * NT + 128];
+  __shared__ double outv[MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
   const bool on = (mask >> c) & 1u;
   const QT* Q = static_cast<const QT*>(S.Q);
-  const RestrictMap m = restrict_map(S.kp, R);
-  double acc[4][4] = {};
+  const QMap m = q_map(S.kp, R);
+  constexpr int NB = QB<QT>::NB;
+  QBatch<QT, NB> qb;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double rr = 0.0, ff = 0.0;
+  double* Rout = S.r[rout];
   const ChunkRange cr = my_chunks(S, lb);
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     const int64_t row0 = ch * S.chunk_rows;
     const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
+    q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
     const int64_t i = row0 + t / R;
     double rvv = 0.0;
     if (on && t / R < nrows) {
@@ -360,303 +535,345 @@ __global__ __launch_bounds__(NT) void k_residual(const SysDev* __restrict__ sys,
       const double ax = op_row<double>(S.op, i, px, py, pz, [&](int64_t j) { return X[j * R + c]; });
       const double fi = S.f[i * R + c];
       rvv = fi - ax;
-      S.r[i * R + c] = rvv;
+      Rout[i * R + c] = rvv;
       rr += rvv * rvv;
       ff += fi * fi;
     }
     __syncthreads();
     rv[t] = rvv;
     __syncthreads();
-    restrict_chunk<QT, 4>(Q, row0, nrows, S.kp, R, m, rv, acc);
+    restrict_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, rv, qb, acc);
   }
-  double* mypart = S.part + (int64_t)lb * S.pstride;
-  restrict_finish<4>(m, S.kp, R, acc, red, mypart);
+  double* rec = S.rpart + (int64_t)lb * S.rw;
+  restrict_finish(m, S.kp, R, acc, red, rec);
+  const int KR = S.kp * R;
   block_sum_rhs(rr, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_RR) + t] = outv[t];
+  if (t < R) store_partial(&rec[KR + t], outv[t]);
   block_sum_rhs(ff, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_FF) + t] = outv[t];
-  if (!arrive_last(S.ticket, S.nblk)) return;
-  // ---- last workgroup
-  reduce_partials(S, slot_scalar(S, SL_RR), R, outv, sh);
-  if (t < R && ((mask >> t) & 1u)) {
-    RhsState& st = S.st[t];
-    st.rr = outv[t];
-  }
-  __syncthreads();
-  if (init) {
-    reduce_partials(S, slot_scalar(S, SL_FF), R, outv, sh);
-    if (t < R && ((mask >> t) & 1u)) S.st[t].ff = outv[t];
-  }
-  __syncthreads();
-  if (t < R && ((mask >> t) & 1u)) {
-    RhsState& st = S.st[t];
-    const double tol2 = S.tol2 * st.ff;
-    int want;
-    if (!(st.rr == st.rr) || st.rr > 1.7e308 || !(st.ff == st.ff) || st.ff > 1.7e308) {
-      want = 0;
-      st.status = NLSP_E_NONFINITE;
-    } else if (st.ff == 0.0 || st.rr <= tol2) {
-      want = 0;
-      st.conv = 1;
-      st.status = NLSP_OK;
-    } else {
-      want = 1;
-      st.conv = 0;
-      st.status = NLSP_NOT_CONVERGED;
-    }
-    if (want != st.active) {
-      atomicAdd(S.sys_active, want - st.active);
-      atomicAdd(n_active, want - st.active);
-      st.active = want;
-    }
-  }
-  reduce_partials(S, 0, S.kp * R, red, sh);
-  coarse_solve(S, red, outv);
+  if (t < R) store_partial(&rec[KR + R + t], outv[t]);
+  restriction_epilogue(S, lb, red, sh);
 }
 
-// phase 1: p_new = z + beta p_old (double buffer), q = A p_new, partial p^T q
-__global__ __launch_bounds__(NT) void k_phase1(const SysDev* __restrict__ sys,
-                                               const int* __restrict__ blk2sys, int nsys,
-                                               int* n_active) {
-  __shared__ double sh[NT];
-  __shared__ double outv[NT];
+// kernel A: convergence test; beta; p_new = z + beta p_old (double buffer);
+// q = A p_new; restriction records [Q^T q | p^T q | 0]; the epilogue publishes
+// etop = [A_c^-1 Q^T q | p^T q | 0]
+template <typename QT>
+__global__ __launch_bounds__(NT, 4) void k_iter_a(const SysDev* __restrict__ sys,
+                                                  const int* __restrict__ blk2sys, int nsys, int it) {
+  __shared__ double qv[NT];
+  __shared__ double sh[NT + 16];
+  __shared__ double red[4 * NT + 128];
+  __shared__ double buf[4 * MAXR];
+  __shared__ IterScalars sc;
   const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (*S.sys_active == 0) return;
+  if (S.nact[it & 1] == 0) return;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  const RhsState& st = S.st[c];
-  const bool act = st.active != 0;
-  const double beta = st.beta;
-  const double* pold = st.par ? S.p1 : S.p0;
-  double* pnew = st.par ? S.p0 : S.p1;
-  const double* Z = S.z;
-  double dp = 0.0;
+  const QT* Q = static_cast<const QT*>(S.Q);
+  const QMap m = q_map(S.kp, R);
+  constexpr int NB = QB<QT>::NB;
+  QBatch<QT, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
-  if (act) {
-    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-      const int64_t row0 = ch * S.chunk_rows;
+  const RhsStatus* cur = S.stat[it & 1];
+  ScalarLoads sl;
+  scalars_issue(S, it, sl);                                   // small loads first,
+  int64_t row0 = cr.c0 * S.chunk_rows;
+  int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
+  if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);  // then Q
+  scalars_finish(S, cur, sl, sc, buf, sh, it);
+  const bool act = sc.act[c] != 0;
+  const double beta = sc.beta[c];
+  const int par = cur[c].par;
+  const double* pold = S.p[par];
+  double* pnew = S.p[par ^ 1];
+  const double* Z = S.z;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double dp = 0.0;
+  for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+    if (ch > cr.c0) {
+      row0 = ch * S.chunk_rows;
+      nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
+      q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+    }
+    double qval = 0.0;
+    if (act && t / R < nrows) {
       const int64_t i = row0 + t / R;
-      if (t / R >= S.chunk_rows || i >= S.op.n) continue;
       int px, py, pz;
       decompose(S.op, i, px, py, pz);
       auto pn = [&](int64_t j) { return Z[j * R + c] + beta * pold[j * R + c]; };
       const double pi = pn(i);
-      const double qi = op_row<double>(S.op, i, px, py, pz, pn);
+      qval = op_row<double>(S.op, i, px, py, pz, pn);
       pnew[i * R + c] = pi;
-      S.q[i * R + c] = qi;
-      dp += pi * qi;
-    }
-  }
-  double* mypart = S.part + (int64_t)lb * S.pstride;
-  block_sum_rhs(dp, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_DELTA) + t] = outv[t];
-  if (!arrive_last(S.ticket, S.nblk)) return;
-  reduce_partials(S, slot_scalar(S, SL_DELTA), R, outv, sh);
-  if (t < R && S.st[t].active) {
-    RhsState& s2 = S.st[t];
-    const double d = outv[t];
-    s2.delta = d;
-    s2.par ^= 1;
-    if (!(d == d) || d > 1.7e308 || d < -1.7e308) {
-      deactivate(S, t, NLSP_E_NONFINITE, n_active);
-    } else if (!(d > 0.0)) {
-      deactivate(S, t, NLSP_E_BREAKDOWN, n_active);
-    } else {
-      s2.alpha = s2.gamma / d;
-    }
-  }
-}
-
-// phase 2: x += alpha p, r -= alpha q, partial ||r||^2 and Q^T r;
-// last workgroup: convergence test and coarse solve
-template <typename QT>
-__global__ __launch_bounds__(NT) void k_phase2(const SysDev* __restrict__ sys,
-                                               const int* __restrict__ blk2sys, int nsys,
-                                               int* n_active) {
-  __shared__ double rv[NT];
-  __shared__ double sh[NT];
-  __shared__ double red[4 * NT];
-  __shared__ double outv[4 * NT];
-  const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (*S.sys_active == 0) return;
-  const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
-  const int t = threadIdx.x, R = S.R, c = t % R;
-  const RhsState& st = S.st[c];
-  const bool act = st.active != 0;
-  const double alpha = st.alpha;
-  const double* P = st.par ? S.p1 : S.p0;  // phase 1 flipped the parity
-  const QT* Q = static_cast<const QT*>(S.Q);
-  const RestrictMap m = restrict_map(S.kp, R);
-  double acc[4][4] = {};
-  double rr = 0.0;
-  const ChunkRange cr = my_chunks(S, lb);
-  for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t row0 = ch * S.chunk_rows;
-    const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-    double rvv = 0.0;
-    if (act && t / R < nrows) {
-      const int64_t g = (row0 + t / R) * R + c;
-      S.x[g] += alpha * P[g];
-      rvv = S.r[g] - alpha * S.q[g];
-      S.r[g] = rvv;
-      rr += rvv * rvv;
+      S.q[i * R + c] = qval;
+      dp += pi * qval;
     }
     __syncthreads();
-    rv[t] = rvv;
+    qv[t] = qval;
     __syncthreads();
-    restrict_chunk<QT, 4>(Q, row0, nrows, S.kp, R, m, rv, acc);
+    restrict_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, qv, qb, acc);
   }
-  double* mypart = S.part + (int64_t)lb * S.pstride;
-  restrict_finish<4>(m, S.kp, R, acc, red, mypart);
-  block_sum_rhs(rr, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_RR) + t] = outv[t];
-  if (!arrive_last(S.ticket, S.nblk)) return;
-  reduce_partials(S, slot_scalar(S, SL_RR), R, outv, sh);
-  if (t < R && S.st[t].active) {
-    RhsState& s2 = S.st[t];
-    const double rrv = outv[t];
-    s2.rr = rrv;
-    s2.iters += 1;
-    if (!(rrv == rrv) || rrv > 1.7e308) {
-      deactivate(S, t, NLSP_E_NONFINITE, n_active);
-    } else if (rrv <= S.tol2 * s2.ff) {
-      s2.conv = 1;
-      deactivate(S, t, NLSP_OK, n_active);
-    } else if (s2.iters >= S.maxit) {
-      deactivate(S, t, NLSP_NOT_CONVERGED, n_active);
-    }
+  double* rec = S.rpart + (int64_t)lb * S.rw;
+  restrict_finish(m, S.kp, R, acc, red, rec);
+  const int KR = S.kp * R;
+  block_sum_rhs(dp, R, buf, sh);
+  if (t < R) {
+    store_partial(&rec[KR + t], buf[t]);
+    store_partial(&rec[KR + R + t], 0.0);
   }
-  __syncthreads();
-  reduce_partials(S, 0, S.kp * R, red, sh);
-  coarse_solve(S, red, outv);
+  restriction_epilogue(S, lb, red, sh);
 }
 
-// J_{2nu} sweeps for nu > 1: first = 1 computes y2 = y1 + w D^-1 (r - A y1)
-// with y1 = w D^-1 r; later sweeps y <- y + w D^-1 (r - A y).  PT arithmetic.
+// J_{2nu} sweeps for nu > 1 on the new residual r_new = r_in - a q (a = alpha,
+// or 0 at a restart): first = 1 computes y2 = y1 + w D^-1 (r_new - A y1) with
+// y1 = w D^-1 r_new; later sweeps y <- y + w D^-1 (r_new - A y).  Every RHS
+// still marked active in stat[it & 1] is swept.
 template <typename PT>
 __global__ __launch_bounds__(NT) void k_sweep(const SysDev* __restrict__ sys,
-                                              const int* __restrict__ blk2sys, int nsys, int first,
-                                              int src) {
+                                              const int* __restrict__ blk2sys, int nsys, int it,
+                                              int restart, int rin, int first, int src) {
+  __shared__ double sh[NT + 16];
+  __shared__ double buf[4 * MAXR];
+  __shared__ double s_alpha[MAXR];
+  __shared__ IterScalars sc;
   const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (*S.sys_active == 0) return;
+  if (!restart && S.nact[it & 1] == 0) return;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  if (!S.st[c].active) return;
+  const RhsStatus* cur = S.stat[it & 1];
+  if (!restart) {
+    ScalarLoads sl;
+    scalars_issue(S, it, sl);
+    scalars_finish(S, cur, sl, sc, buf, sh, it);
+    if (t < R) s_alpha[t] = sc.gam[t] / S.etop[S.kp * R + t];
+  } else if (t < R) {
+    s_alpha[t] = 0.0;
+  }
+  __syncthreads();
+  if (!cur[c].active) return;
   const PT om = PT(S.omega);
-  const PT* yin = static_cast<const PT*>(src ? S.w1 : S.w0);
-  PT* yout = static_cast<PT*>(first ? S.w0 : (src ? S.w0 : S.w1));
-  const double* Rv = S.r;
+  const double a = s_alpha[c];
+  const double* Rin = S.r[rin];
+  const double* Qv = S.q;
+  auto rnew = [&](int64_t j) { return Rin[j * R + c] - a * Qv[j * R + c]; };
+  const PT* yin = static_cast<const PT*>(S.w[src]);
+  PT* yout = static_cast<PT*>(S.w[first ? 0 : (src ^ 1)]);
   const ChunkRange cr = my_chunks(S, lb);
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t row0 = ch * S.chunk_rows;
-    const int64_t i = row0 + t / R;
+    const int64_t i = ch * S.chunk_rows + t / R;
     if (t / R >= S.chunk_rows || i >= S.op.n) continue;
     int px, py, pz;
     decompose(S.op, i, px, py, pz);
-    const PT di = (sizeof(PT) == 4) ? PT(S.dinv32[i]) : PT(S.dinv[i]);
-    const PT ri = PT(Rv[i * R + c]);
+    auto dj = [&](int64_t j) -> PT { return (sizeof(PT) == 4) ? PT(S.dinv32[j]) : PT(S.dinv[j]); };
+    const PT ri = PT(rnew(i));
     PT yi, ay;
     if (first) {
-      auto y1 = [&](int64_t j) {
-        const PT dj = (sizeof(PT) == 4) ? PT(S.dinv32[j]) : PT(S.dinv[j]);
-        return om * dj * PT(Rv[j * R + c]);
-      };
+      auto y1 = [&](int64_t j) { return om * dj(j) * PT(rnew(j)); };
       yi = y1(i);
       ay = op_row<PT>(S.op, i, px, py, pz, y1);
     } else {
       yi = yin[i * R + c];
       ay = op_row<PT>(S.op, i, px, py, pz, [&](int64_t j) { return yin[j * R + c]; });
     }
-    yout[i * R + c] = yi + om * di * (ri - ay);
+    yout[i * R + c] = yi + om * dj(i) * (ri - ay);
   }
 }
 
-// phase 3: z = J_{2nu} r + Q e, partial r^T z (and r^T z_old); last
-// workgroup: beta.  wsrc < 0: J_2 inline (nu = 1); else read buffer w{wsrc}.
+// kernel B: status; alpha; e <- e - alpha A_c^-1 Q^T q (so e = A_c^-1 Q^T r_new);
+// x += alpha p; r_new = r - alpha q into r[(it+1)&1]; z = J r_new + Q e;
+// partials [r^T z | r^T z_old | ||r_new||^2] into bpart[(it+1)&1].
+//   restart = 0: an iteration; etop = [A_c^-1 Q^T q | p^T q | 0] from kernel A
+//   restart = 1: after k_residual (which wrote r into r[(it+1)&1] and
+//                etop = [A_c^-1 Q^T r | ||r||^2 | ||f||^2]) for the RHS in
+//                `mask`: no update, `init` also takes ||f||^2, and the next
+//                kernel A uses beta = 0.
+// wsrc < 0: J_2 inline (nu = 1); else J_{2nu} r_new is read from w[wsrc].
 template <typename QT>
-__global__ __launch_bounds__(NT) void k_phase3(const SysDev* __restrict__ sys,
-                                               const int* __restrict__ blk2sys, int nsys,
-                                               int* n_active, int wsrc) {
+__global__ __launch_bounds__(NT, 4) void k_iter_b(const SysDev* __restrict__ sys,
+                                                  const int* __restrict__ blk2sys, int nsys, int it,
+                                                  int restart, unsigned mask, int init, int wsrc) {
   __shared__ QT ws[NT];
   __shared__ QT ys[NT];
-  __shared__ QT ev[2048];
-  __shared__ double sh[NT];
-  __shared__ double outv[NT];
+  __shared__ double sh[3 * (NT + 16)];
+  __shared__ double ebuf[2048];
+  __shared__ double dq[2048];
+  __shared__ double tscal[2 * MAXR];
+  __shared__ double buf[4 * MAXR];
+  __shared__ double s_alpha[MAXR];
+  __shared__ int s_upd[MAXR], s_next[MAXR];
+  __shared__ IterScalars sc;
   const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (*S.sys_active == 0) return;
+  const int nxt = (it + 1) & 1;
+  const int KR = S.kp * S.R;
+  if (!restart && S.nact[it & 1] == 0) {
+    // nothing iterates: carry the state over to the next parity
+    if (blockIdx.x == S.blk0) {
+      for (int idx = threadIdx.x; idx < KR; idx += NT) S.estate[nxt][idx] = S.estate[it & 1][idx];
+      if (threadIdx.x < S.R) S.stat[nxt][threadIdx.x] = S.stat[it & 1][threadIdx.x];
+      if (threadIdx.x == 0) {
+        S.nact[nxt] = 0;
+        *S.n_active = 0;
+      }
+    }
+    return;
+  }
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  const RhsState& st = S.st[c];
-  const bool act = st.active != 0;
   const QT* Q = static_cast<const QT*>(S.Q);
-  const QT om = QT(S.omega);
-  for (int idx = t; idx < S.kp * R; idx += NT) ev[idx] = QT(S.e[idx]);
-  const double* Rv = S.r;
-  double gam = 0.0, rzo = 0.0;
+  const QMap m = q_map(S.kp, R);
+  constexpr int NB = QB<QT>::NB;
+  QBatch<QT, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
+  const RhsStatus* cur = S.stat[it & 1];
+  // small loads first (scalars, the published coarse vector, e), then Q
+  ScalarLoads sl;
+  sl.fast = false;
+  if (!restart) scalars_issue(S, it, sl);
+  for (int idx = t; idx < KR; idx += NT) {
+    const double ep = S.estate[it & 1][idx], et = S.etop[idx];
+    if (restart) {
+      ebuf[idx] = ((mask >> (idx % R)) & 1u) ? et : ep;
+    } else {
+      ebuf[idx] = ep;   // e of r, updated with alpha below
+      dq[idx] = et;     // A_c^-1 Q^T q
+    }
+  }
+  if (t < 2 * R) tscal[t] = S.etop[KR + t];
+  int64_t row0 = cr.c0 * S.chunk_rows;
+  int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
+  if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+  if (!restart) scalars_finish(S, cur, sl, sc, buf, sh, it);
+  __syncthreads();
+  // ---- per-RHS decisions (identical in every workgroup) and the new state
+  if (t < R) {
+    RhsStatus nx = cur[t];
+    int upd = 0, next = 0;
+    double alpha = 0.0;
+    if (restart) {
+      if ((mask >> t) & 1u) {
+        if (init) nx.ff = tscal[R + t];
+        nx.restart = 1;
+        nx.conv = 0;
+        if (!(nx.ff <= 1.7e308)) {
+          nx.status = NLSP_E_NONFINITE;
+        } else {
+          nx.status = NLSP_NOT_CONVERGED;
+          next = 1;
+        }
+      } else {
+        next = nx.active;
+      }
+      upd = next && ((mask >> t) & 1u);
+    } else if (cur[t].active) {
+      nx.restart = 0;
+      if (sc.conv[t]) {
+        nx.status = NLSP_OK;
+        nx.conv = 1;
+      } else if (sc.bad[t]) {
+        // r^T z <= 0 with finite values is a breakdown; anything non-finite is not
+        const bool gfin = sc.gam[t] == sc.gam[t] && fabs(sc.gam[t]) <= 1.7e308;
+        const bool rfin = sc.rr[t] <= 1.7e308;
+        nx.status = (gfin && rfin) ? NLSP_E_BREAKDOWN : NLSP_E_NONFINITE;
+      } else if (!sc.act[t]) {
+        nx.status = NLSP_NOT_CONVERGED;   // maxit reached
+      } else {
+        const double d = tscal[t];
+        nx.par ^= 1;                      // kernel A wrote the new direction
+        nx.gamma_old = sc.gam[t];
+        if (!finite_pos(d)) {
+          nx.status = (d == d && d <= 1.7e308) ? NLSP_E_BREAKDOWN : NLSP_E_NONFINITE;
+        } else {
+          alpha = sc.gam[t] / d;
+          upd = 1;
+          next = 1;
+          nx.iters += 1;
+        }
+      }
+    }
+    nx.active = next;
+    s_alpha[t] = alpha;
+    s_upd[t] = upd;
+    s_next[t] = next;
+    if (lb == 0) S.stat[nxt][t] = nx;
+  }
+  __syncthreads();
+  // ---- e = A_c^-1 Q^T r_new (workgroup 0 keeps it for the next iteration)
+  if (!restart)
+    for (int idx = t; idx < KR; idx += NT) ebuf[idx] -= s_alpha[idx % R] * dq[idx];
+  __syncthreads();
+  if (lb == 0) {
+    for (int idx = t; idx < KR; idx += NT) S.estate[nxt][idx] = ebuf[idx];
+    if (t == 0) {
+      int cnt = 0;
+      for (int k = 0; k < R; ++k) cnt += s_next[k];
+      S.nact[nxt] = cnt;
+      *S.n_active = cnt;
+    }
+  }
+  // ---- x += alpha p; r_new = r - alpha q; z = J r_new + Q e
+  const bool upd = s_upd[c] != 0;
+  const double alpha = s_alpha[c];
+  QT e4[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) e4[u] = QT(ebuf[(4 * m.jc + u) * R + m.c]);
+  const QT om = QT(S.omega);
+  const double* Rin = S.r[restart ? nxt : (it & 1)];
+  double* Rout = S.r[nxt];
+  const double* Qv = S.q;
+  const double* P = S.p[cur[c].par ^ 1];
+  auto rnew = [&](int64_t j) { return restart ? Rin[j * R + c] : Rin[j * R + c] - alpha * Qv[j * R + c]; };
+  double gam = 0.0, rzo = 0.0, rr = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t row0 = ch * S.chunk_rows;
-    const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-    const bool mine = act && t / R < nrows;
+    if (ch > cr.c0) {
+      row0 = ch * S.chunk_rows;
+      nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
+      q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+    }
+    const bool mine = upd && t / R < nrows;
     const int64_t i = row0 + t / R;
     QT w = QT(0);
+    double ri = 0.0;
     if (mine) {
+      ri = rnew(i);
       if (wsrc < 0) {
         int px, py, pz;
         decompose(S.op, i, px, py, pz);
         auto dj = [&](int64_t j) -> QT {
           return (sizeof(QT) == 4) ? QT(S.dinv32[j]) : QT(S.dinv[j]);
         };
-        auto y = [&](int64_t j) { return dj(j) * QT(Rv[j * R + c]); };
+        auto y = [&](int64_t j) { return dj(j) * QT(rnew(j)); };
         const QT yi = y(i);
         const QT ay = op_row<QT>(S.op, i, px, py, pz, y);
         w = QT(2) * om * yi - om * om * dj(i) * ay;
       } else {
-        const QT* wb = static_cast<const QT*>(wsrc ? S.w1 : S.w0);
-        w = wb[i * R + c];
+        w = static_cast<const QT*>(S.w[wsrc])[i * R + c];
       }
     }
     __syncthreads();
     ws[t] = w;
-    __syncthreads();
-    prolong_chunk<QT>(Q, row0, nrows, S.kp, R, ev, ys);
+    prolong_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
     __syncthreads();
     if (mine) {
       const int64_t g = i * R + c;
+      if (!restart) {
+        S.x[g] += alpha * P[g];
+        Rout[g] = ri;
+      }
       const double zn = (double)ws[t] + (double)ys[t];
-      const double ri = Rv[g];
       if (S.flexible) rzo += ri * S.z[g];
       S.z[g] = zn;
       gam += ri * zn;
+      rr += ri * ri;
     }
   }
-  double* mypart = S.part + (int64_t)lb * S.pstride;
-  block_sum_rhs(gam, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_GAM) + t] = outv[t];
-  block_sum_rhs(rzo, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_RZOLD) + t] = outv[t];
-  if (!arrive_last(S.ticket, S.nblk)) return;
-  reduce_partials(S, slot_scalar(S, SL_GAM), 2 * R, outv, sh);
-  if (t < R && S.st[t].active) {
-    RhsState& s2 = S.st[t];
-    const double g = outv[t], rz = outv[R + t];
-    if (!(g == g) || g > 1.7e308) {
-      deactivate(S, t, NLSP_E_NONFINITE, n_active);
-    } else if (!(g > 0.0)) {
-      deactivate(S, t, NLSP_E_BREAKDOWN, n_active);
-    } else {
-      s2.beta = S.flexible ? (g - rz) / s2.gamma : g / s2.gamma;
-      s2.gamma = g;
-      s2.rzold = rz;
-    }
-  }
+  block_sum_rhs3(gam, rzo, rr, R, buf, sh);
+  if (t < 3 * R) S.bpart[nxt][(int64_t)lb * 3 * R + t] = buf[t];
 }
 
-// ||f - A x||^2 per RHS (true residual) into st.rr_true
+// ||f - A x||^2 partials per RHS (true residual) into dpart
 __global__ __launch_bounds__(NT) void k_true_residual(const SysDev* __restrict__ sys,
                                                       const int* __restrict__ blk2sys, int nsys) {
-  __shared__ double sh[NT];
-  __shared__ double outv[NT];
+  __shared__ double sh[NT + 16];
+  __shared__ double buf[MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
@@ -672,12 +889,17 @@ __global__ __launch_bounds__(NT) void k_true_residual(const SysDev* __restrict__
     const double d = S.f[i * R + c] - ax;
     s += d * d;
   }
-  double* mypart = S.part + (int64_t)lb * S.pstride;
-  block_sum_rhs(s, R, outv, sh);
-  if (t < R) mypart[slot_scalar(S, SL_DELTA) + t] = outv[t];
-  if (!arrive_last(S.ticket, S.nblk)) return;
-  reduce_partials(S, slot_scalar(S, SL_DELTA), R, outv, sh);
-  if (t < R) S.st[t].rr_true = outv[t];
+  block_sum_rhs(s, R, buf, sh);
+  if (t < R) S.dpart[(int64_t)lb * R + t] = buf[t];
+}
+
+// one workgroup per system: rr_true = sum of the true-residual partials
+__global__ __launch_bounds__(NT) void k_true_finish(const SysDev* __restrict__ sys) {
+  __shared__ double sh[NT + 16];
+  __shared__ double buf[MAXR];
+  const SysDev& S = sys[blockIdx.x];
+  sum_records<false>(S.dpart, S.nblk, S.R, 0, S.R, buf, sh);
+  if (threadIdx.x < S.R) S.rr_true[threadIdx.x] = buf[threadIdx.x];
 }
 
 __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
@@ -688,25 +910,36 @@ __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
 
 // ------------------------------------------------------------- host side
 struct SolveLayout {
-  double *r, *p0, *p1, *q, *z, *dinv, *part, *e;
+  double *r0, *r1, *p0, *p1, *q, *z, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *etop, *estate0, *estate1,
+      *dpart, *Ainv, *rr_true;
   float* dinv32;
   void *w0, *w1;
-  RhsState* st;
+  RhsStatus *stat0, *stat1;
   SysDev* sysdev;
   unsigned* ticket;
-  int* counters;  // [0] n_active, [1] sys_active
+  int* counters;  // [0..1] active RHS by parity, [2] host-visible copy
   size_t bytes;
 };
 
+// Workgroups per solver launch: one per chunk up to a cap (NLSP_SOLVER_BLOCKS
+// overrides the cap, for tuning).
 inline int solver_blocks(int64_t nchunks) {
-  const int cap = 512;
+  int cap = 512;
+  if (const char* e = std::getenv("NLSP_SOLVER_BLOCKS")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 65536) cap = v;
+  }
   return (int)std::min<int64_t>(nchunks, cap);
 }
+
+inline int restriction_width(int kp, int R) { return kp * R + 2 * R; }
 
 inline SolveLayout carve_solve(void* ws, int64_t n, int kp, int R, int nblk) {
   Carver cv(ws);
   SolveLayout L;
-  L.r = cv.take<double>(n * R);
+  const int rw = restriction_width(kp, R);
+  L.r0 = cv.take<double>(n * R);
+  L.r1 = cv.take<double>(n * R);
   L.p0 = cv.take<double>(n * R);
   L.p1 = cv.take<double>(n * R);
   L.q = cv.take<double>(n * R);
@@ -715,12 +948,20 @@ inline SolveLayout carve_solve(void* ws, int64_t n, int kp, int R, int nblk) {
   L.w1 = cv.take<double>(n * R);
   L.dinv = cv.take<double>(n);
   L.dinv32 = cv.take<float>(n);
-  const int pstride = kp * R + SL_COUNT * R;
-  L.part = cv.take<double>((size_t)nblk * pstride);
-  L.e = cv.take<double>((size_t)kp * R);
-  L.st = cv.take<RhsState>(R);
+  L.bpart0 = cv.take<double>((size_t)nblk * 3 * R);
+  L.bpart1 = cv.take<double>((size_t)nblk * 3 * R);
+  L.rpart = cv.take<double>((size_t)nblk * rw);
+  L.rgrp = cv.take<double>((size_t)ticket_groups(nblk) * rw);
+  L.etop = cv.take<double>(rw);
+  L.estate0 = cv.take<double>((size_t)kp * R);
+  L.estate1 = cv.take<double>((size_t)kp * R);
+  L.dpart = cv.take<double>((size_t)nblk * R);
+  L.Ainv = cv.take<double>((size_t)kp * kp);
+  L.rr_true = cv.take<double>(R);
+  L.stat0 = cv.take<RhsStatus>(R);
+  L.stat1 = cv.take<RhsStatus>(R);
   L.sysdev = cv.take<SysDev>(1);
-  L.ticket = cv.take<unsigned>(4);
+  L.ticket = cv.take<unsigned>(ticket_words(nblk));
   L.counters = cv.take<int>(4);
   L.bytes = cv.bytes();
   return L;
@@ -731,29 +972,67 @@ static int run_pcg(const SysDev& hs, const SolveLayout& L, int R, const nlsp_pcg
                    nlsp_rhs_info* info, hipStream_t stream) {
   const int nblk = hs.nblk;
   const SysDev* dsys = L.sysdev;
-  int* n_active = L.counters;
-  const unsigned all = (R >= 32) ? 0xffffffffu : ((1u << R) - 1u);
+  const unsigned all = (1u << R) - 1u;
   const dim3 grid(nblk), block(NT);
-  hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs.op.n, NT)), block, 0, stream, hs.op, L.dinv,
-                     L.dinv32);
-  hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, nullptr, 1, n_active, all, 1);
-  auto launch_phase3 = [&]() {
-    if (hs.nu == 1) {
-      hipLaunchKernelGGL(k_phase3<QT>, grid, block, 0, stream, dsys, nullptr, 1, n_active, -1);
+  nlsp_kernel_timing* tm = opts->timing;
+  const int tphase = (tm && tm->phase >= 1 && tm->phase <= 2) ? tm->phase : 0;
+  const int tevery = tm ? std::max(1, tm->every) : 1;
+  std::vector<hipEvent_t> evs;
+  int64_t phase_launch[3] = {0, 0, 0};
+  // records a start/stop event pair around one launch of a timed kernel
+  auto timed = [&](int ph, auto&& launch) {
+    const bool on = (ph == tphase) && (phase_launch[ph]++ % tevery == 0);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+      (void)hipEventRecord(a, stream);
+      launch();
+      (void)hipEventRecord(b, stream);
+      evs.push_back(a);
+      evs.push_back(b);
     } else {
-      hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, stream, dsys, nullptr, 1, 1, 0);
-      int src = 0;
-      for (int s = 1; s < 2 * hs.nu - 1; ++s) {
-        hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, stream, dsys, nullptr, 1, 0, src);
-        src ^= 1;
-      }
-      hipLaunchKernelGGL(k_phase3<QT>, grid, block, 0, stream, dsys, nullptr, 1, n_active, src);
+      launch();
     }
   };
-  launch_phase3();
+  // J_{2nu} r_new (nu > 1) and kernel B of iteration `it`
+  auto launch_b = [&](int it, int restart, unsigned mask, int init) {
+    int wsrc = -1;
+    if (hs.nu > 1) {
+      const int rin = restart ? ((it + 1) & 1) : (it & 1);
+      hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, stream, dsys, nullptr, 1, it, restart, rin, 1, 0);
+      int src = 0;
+      for (int s = 1; s < 2 * hs.nu - 1; ++s) {
+        hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, stream, dsys, nullptr, 1, it, restart, rin, 0,
+                           src);
+        src ^= 1;
+      }
+      wsrc = src;
+    }
+    timed(2, [&] {
+      hipLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, stream, dsys, nullptr, 1, it, restart, mask,
+                         init, wsrc);
+    });
+  };
+  auto finish_timing = [&]() {
+    if (tm) {
+      double tot = 0.0;
+      for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) tot += ms;
+      }
+      tm->total_ms = tot;
+      tm->launches = (int)(evs.size() / 2);
+    }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  };
+  hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs.op.n, NT)), block, 0, stream, hs.op, L.dinv, L.dinv32);
+  hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs.kp * hs.kp, 256)), dim3(256), 0, stream,
+                     hs.Linv, hs.kp, L.Ainv);
+  // start-up as iteration -1: r = f - A x into r[0], then kernel B in restart mode
+  hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, nullptr, 1, all, 0);
+  launch_b(-1, 1, all, 1);
   NLSP_HIP(hipGetLastError());
-  std::vector<RhsState> hst(R);
-  NLSP_HIP(hipMemcpyAsync(hst.data(), L.st, sizeof(RhsState) * R, hipMemcpyDeviceToHost, stream));
+  std::vector<RhsStatus> hst(R);
+  NLSP_HIP(hipMemcpyAsync(hst.data(), L.stat0, sizeof(RhsStatus) * R, hipMemcpyDeviceToHost, stream));
   NLSP_HIP(hipStreamSynchronize(stream));
   unsigned zero_mask = 0;
   for (int c = 0; c < R; ++c)
@@ -763,55 +1042,67 @@ static int run_pcg(const SysDev& hs, const SolveLayout& L, int R, const nlsp_pcg
                        hs.op.n, R, zero_mask);
   const int every = std::max(1, opts->check_every);
   int guard = 0;
-  // every RHS stops by maxit iterations; the launch budget is a hard bound
-  // on the host loop in case the device-side bookkeeping were ever wrong
+  int it = 0;  // next iteration index; stat[it & 1] is the current state
+  // every RHS stops by maxit iterations; the launch budget is a hard bound on
+  // the host loop in case the device-side bookkeeping were ever wrong
   int64_t launched = 0;
   const int64_t launch_cap = (int64_t)hs.maxit + 2 * every + 64;
   for (;;) {
     int h_active = 0;
-    NLSP_HIP(hipMemcpyAsync(&h_active, n_active, sizeof(int), hipMemcpyDeviceToHost, stream));
+    NLSP_HIP(hipMemcpyAsync(&h_active, L.counters + 2, sizeof(int), hipMemcpyDeviceToHost, stream));
     NLSP_HIP(hipStreamSynchronize(stream));
     if (h_active > 0 && launched < launch_cap) {
-      launched += every;
-      for (int it = 0; it < every; ++it) {
-        hipLaunchKernelGGL(k_phase1, grid, block, 0, stream, dsys, nullptr, 1, n_active);
-        hipLaunchKernelGGL(k_phase2<QT>, grid, block, 0, stream, dsys, nullptr, 1, n_active);
-        launch_phase3();
+      for (int k = 0; k < every; ++k, ++it) {
+        timed(1, [&] {
+          hipLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, stream, dsys, nullptr, 1, it);
+        });
+        launch_b(it, 0, 0u, 0);
       }
+      launched += every;
       NLSP_HIP(hipGetLastError());
       continue;
     }
     // every RHS stopped: confirm the converged ones with the true residual
     hipLaunchKernelGGL(k_true_residual, grid, block, 0, stream, dsys, nullptr, 1);
+    hipLaunchKernelGGL(k_true_finish, dim3(1), block, 0, stream, dsys);
     NLSP_HIP(hipGetLastError());
-    NLSP_HIP(hipMemcpyAsync(hst.data(), L.st, sizeof(RhsState) * R, hipMemcpyDeviceToHost, stream));
+    RhsStatus* cur_d = (it & 1) ? L.stat1 : L.stat0;
+    std::vector<double> rrt(R);
+    NLSP_HIP(hipMemcpyAsync(hst.data(), cur_d, sizeof(RhsStatus) * R, hipMemcpyDeviceToHost, stream));
+    NLSP_HIP(hipMemcpyAsync(rrt.data(), L.rr_true, sizeof(double) * R, hipMemcpyDeviceToHost, stream));
     NLSP_HIP(hipStreamSynchronize(stream));
     unsigned redo = 0;
     for (int c = 0; c < R; ++c) {
-      RhsState& s = hst[c];
-      if (s.conv && s.ff > 0.0 && s.rr_true > hs.tol2 * s.ff && s.iters < hs.maxit) redo |= 1u << c;
+      const RhsStatus& s = hst[c];
+      if (s.conv && s.ff > 0.0 && rrt[c] > hs.tol2 * s.ff && s.iters < hs.maxit) redo |= 1u << c;
     }
-    if (!redo || ++guard > 16) break;
-    // residual replacement: r = f - A x for `redo`, then continue iterating
-    for (int c = 0; c < R; ++c)
-      if ((redo >> c) & 1u) {
-        hst[c].conv = 0;
+    if (!redo || ++guard > 16) {
+      int worst = NLSP_OK;
+      for (int c = 0; c < R; ++c) {
+        const RhsStatus& s = hst[c];
+        info[c].iters = s.iters;
+        info[c].status = s.status;
+        info[c].relres = (s.ff > 0.0) ? std::sqrt(rrt[c] / s.ff) : 0.0;
+        if (s.status < 0 && (worst >= 0 || s.status < worst)) worst = s.status;
+        if (s.status == NLSP_NOT_CONVERGED && worst == NLSP_OK) worst = NLSP_NOT_CONVERGED;
       }
-    NLSP_HIP(hipMemcpyAsync(L.st, hst.data(), sizeof(RhsState) * R, hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, nullptr, 1, n_active, redo, 0);
-    launch_phase3();
+      finish_timing();
+      return worst;
+    }
+    // residual replacement: r = f - A x for `redo` into r[it & 1] and those RHS
+    // restart from it (kernel B in restart mode as iteration it - 1, reading
+    // stat[(it - 1) & 1])
+    for (int c = 0; c < R; ++c)
+      if ((redo >> c) & 1u) hst[c].active = 1;
+    RhsStatus* prev_d = ((it - 1) & 1) ? L.stat1 : L.stat0;
+    NLSP_HIP(hipMemcpyAsync(prev_d, hst.data(), sizeof(RhsStatus) * R, hipMemcpyHostToDevice, stream));
+    const int nredo = __builtin_popcount(redo);
+    NLSP_HIP(hipMemcpyAsync(L.counters + ((it - 1) & 1), &nredo, sizeof(int), hipMemcpyHostToDevice,
+                            stream));
+    hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, nullptr, 1, redo, it & 1);
+    launch_b(it - 1, 1, redo, 0);
     NLSP_HIP(hipGetLastError());
   }
-  int worst = NLSP_OK;
-  for (int c = 0; c < R; ++c) {
-    const RhsState& s = hst[c];
-    info[c].iters = s.iters;
-    info[c].status = s.status;
-    info[c].relres = (s.ff > 0.0) ? std::sqrt(s.rr_true / s.ff) : 0.0;
-    if (s.status < 0 && (worst >= 0 || s.status < worst)) worst = s.status;
-    if (s.status == NLSP_NOT_CONVERGED && worst == NLSP_OK) worst = NLSP_NOT_CONVERGED;
-  }
-  return worst;
 }
 
 }  // namespace nlsp
@@ -823,7 +1114,7 @@ extern "C" {
 size_t pcg_solve_workspace_bytes(const nlsp_operator* A, int k, int R) {
   const int64_t n = op_size(A);
   const int kp = padded_rank(k);
-  if (n < 1 || kp < 0 || R < 1 || R > 16 || kp * R > 2048) return 0;
+  if (n < 1 || kp < 0 || R < 1 || R > MAXR || kp * R > 2048 || n * R >= (int64_t(1) << 31)) return 0;
   const int64_t nchunks = (n + NT / R - 1) / (NT / R);
   return carve_solve(nullptr, n, kp, R, solver_blocks(nchunks)).bytes;
 }
@@ -833,7 +1124,7 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
               void* stream_) {
   const int64_t n = op_size(A);
   if (n < 1 || !M || !f || !u || !opts || !info) return NLSP_E_INVALID;
-  if (R < 1 || R > 16) return NLSP_E_INVALID;
+  if (R < 1 || R > MAXR || n * R >= (int64_t(1) << 31)) return NLSP_E_INVALID;
   const int kp = padded_rank(M->k);
   if (kp < 0 || M->nu < 1 || !(M->omega > 0) || !M->Linv) return NLSP_E_INVALID;
   if (kp * R > 2048) return NLSP_E_INVALID;  // LDS staging of the coarse vectors
@@ -857,44 +1148,62 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
   hs.blk0 = 0;
   hs.chunk_rows = chunk_rows;
   hs.nchunks = nchunks;
+  hs.rw = restriction_width(kp, R);
   hs.Q = (M->prec == NLSP_FP64) ? (const void*)M->Q64 : (const void*)M->Q32;
   hs.Linv = M->Linv;
+  hs.Ainv = L.Ainv;
   hs.f = f;
   hs.x = u;
-  hs.r = L.r;
-  hs.p0 = L.p0;
-  hs.p1 = L.p1;
+  hs.r[0] = L.r0;
+  hs.r[1] = L.r1;
+  hs.p[0] = L.p0;
+  hs.p[1] = L.p1;
   hs.q = L.q;
   hs.z = L.z;
-  hs.w0 = L.w0;
-  hs.w1 = L.w1;
+  hs.w[0] = L.w0;
+  hs.w[1] = L.w1;
   hs.dinv = L.dinv;
   hs.dinv32 = L.dinv32;
-  hs.part = L.part;
-  hs.pstride = kp * R + SL_COUNT * R;
-  hs.nu = M->nu;
+  hs.bpart[0] = L.bpart0;
+  hs.bpart[1] = L.bpart1;
+  hs.rpart = L.rpart;
+  hs.rgrp = L.rgrp;
+  hs.etop = L.etop;
+  hs.estate[0] = L.estate0;
+  hs.estate[1] = L.estate1;
+  hs.dpart = L.dpart;
   hs.ticket = L.ticket;
-  hs.st = L.st;
-  hs.sys_active = L.counters + 1;
-  hs.e = L.e;
+  hs.stat[0] = L.stat0;
+  hs.stat[1] = L.stat1;
+  hs.nact = L.counters;
+  hs.n_active = L.counters + 2;
+  hs.rr_true = L.rr_true;
+  hs.nu = M->nu;
   hs.omega = M->omega;
   hs.tol2 = opts->rtol * opts->rtol;
   hs.maxit = opts->maxit;
   hs.flexible = opts->flexible ? 1 : 0;
 
-  std::vector<RhsState> st0(R);
+  // iteration -1 reads stat[1]: every RHS starts active with a fresh direction
+  std::vector<RhsStatus> st0(R);
   for (auto& s : st0) {
-    s = RhsState{};
-    s.gamma = 1.0;
-    s.active = 0;
+    s = RhsStatus{};
+    s.gamma_old = 1.0;
+    s.active = 1;
+    s.restart = 1;
     s.status = NLSP_NOT_CONVERGED;
   }
   NLSP_HIP(hipMemsetAsync(L.p0, 0, sizeof(double) * n * R, stream));
   NLSP_HIP(hipMemsetAsync(L.p1, 0, sizeof(double) * n * R, stream));
   NLSP_HIP(hipMemsetAsync(L.z, 0, sizeof(double) * n * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.ticket, 0, sizeof(unsigned) * 4, stream));
-  NLSP_HIP(hipMemsetAsync(L.counters, 0, sizeof(int) * 4, stream));
-  NLSP_HIP(hipMemcpyAsync(L.st, st0.data(), sizeof(RhsState) * R, hipMemcpyHostToDevice, stream));
+  NLSP_HIP(hipMemsetAsync(L.q, 0, sizeof(double) * n * R, stream));
+  NLSP_HIP(hipMemsetAsync(L.estate0, 0, sizeof(double) * kp * R, stream));
+  NLSP_HIP(hipMemsetAsync(L.estate1, 0, sizeof(double) * kp * R, stream));
+  NLSP_HIP(hipMemsetAsync(L.ticket, 0, sizeof(unsigned) * ticket_words(nblk), stream));
+  // counters: [0] = 0, [1] = R (the iteration -1 state has every RHS active), [2] = 0
+  const int counters0[4] = {0, R, 0, 0};
+  NLSP_HIP(hipMemcpyAsync(L.counters, counters0, sizeof(counters0), hipMemcpyHostToDevice, stream));
+  NLSP_HIP(hipMemcpyAsync(L.stat1, st0.data(), sizeof(RhsStatus) * R, hipMemcpyHostToDevice, stream));
   NLSP_HIP(hipMemcpyAsync(L.sysdev, &hs, sizeof(SysDev), hipMemcpyHostToDevice, stream));
   if (M->prec == NLSP_FP64) return run_pcg<double>(hs, L, R, opts, info, stream);
   return run_pcg<float>(hs, L, R, opts, info, stream);

@@ -171,7 +171,9 @@ typedef struct {
  *   1  kernel A: convergence test, p <- z + beta p, q = A p, p^T q, Q^T q
  *   2  kernel B: alpha, x += alpha p, r -= alpha q, coarse solve, smoother,
  *      prolongation z = w + Q e, r^T z, ||r||^2
- * hipEvents are recorded on the solver's stream around one launch in `every`. */
+ * one launch in `every` carries a start and a stop hipEvent attached to its
+ * own dispatch (hipExtLaunchKernelGGL), so the events take the dispatch's
+ * begin and end timestamps and no marker packet is inserted between kernels. */
 typedef struct {
   int phase;             /* 1 or 2; 0 = no timing */
   int every;             /* time one launch in `every` (>= 1) */

@@ -31,6 +31,8 @@
 #include <cstdlib>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "device_common.hpp"
 #include "host_common.hpp"
 
@@ -378,7 +380,7 @@ NLSP_DEV void prolong_rows(const QT* __restrict__ Q, int64_t row0, int nrows, in
 
 template <typename QT>
 struct QB {
-  static constexpr int NB = (sizeof(QT) == 4) ? 8 : 4;  // 32 registers either way
+  static constexpr int NB = (sizeof(QT) == 4) ? 6 : 4;  // no spills at 128 VGPRs
 };
 
 struct ChunkRange {
@@ -979,18 +981,18 @@ static int run_pcg(const SysDev& hs, const SolveLayout& L, int R, const nlsp_pcg
   const int tevery = tm ? std::max(1, tm->every) : 1;
   std::vector<hipEvent_t> evs;
   int64_t phase_launch[3] = {0, 0, 0};
-  // records a start/stop event pair around one launch of a timed kernel
+  // `launch(a, b)` enqueues one kernel with hipExtLaunchKernelGGL; a and b are
+  // the start/stop events of a timed launch, null otherwise
   auto timed = [&](int ph, auto&& launch) {
     const bool on = (ph == tphase) && (phase_launch[ph]++ % tevery == 0);
     hipEvent_t a = nullptr, b = nullptr;
     if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-      (void)hipEventRecord(a, stream);
-      launch();
-      (void)hipEventRecord(b, stream);
+      launch(a, b);
       evs.push_back(a);
       evs.push_back(b);
     } else {
-      launch();
+      if (a) (void)hipEventDestroy(a);
+      launch(nullptr, nullptr);
     }
   };
   // J_{2nu} r_new (nu > 1) and kernel B of iteration `it`
@@ -1007,9 +1009,9 @@ static int run_pcg(const SysDev& hs, const SolveLayout& L, int R, const nlsp_pcg
       }
       wsrc = src;
     }
-    timed(2, [&] {
-      hipLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, stream, dsys, nullptr, 1, it, restart, mask,
-                         init, wsrc);
+    timed(2, [&](hipEvent_t a, hipEvent_t b) {
+      hipExtLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, stream, a, b, 0, dsys, nullptr, 1, it,
+                            restart, mask, init, wsrc);
     });
   };
   auto finish_timing = [&]() {
@@ -1053,8 +1055,8 @@ static int run_pcg(const SysDev& hs, const SolveLayout& L, int R, const nlsp_pcg
     NLSP_HIP(hipStreamSynchronize(stream));
     if (h_active > 0 && launched < launch_cap) {
       for (int k = 0; k < every; ++k, ++it) {
-        timed(1, [&] {
-          hipLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, stream, dsys, nullptr, 1, it);
+        timed(1, [&](hipEvent_t a, hipEvent_t b) {
+          hipExtLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, stream, a, b, 0, dsys, nullptr, 1, it);
         });
         launch_b(it, 0, 0u, 0);
       }

@@ -1,0 +1,153 @@
+"""The C-ABI library on the host (no GPU needed): it loads, exports every
+function that include/nlsp.h declares, and its host-side entry points and
+argument validation behave as documented.  Nothing here launches a kernel:
+every call below either is pure host code or is rejected by validation,
+which runs before any HIP call."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for m in re.finditer(r"^[A-Za-z_][\w \t\*]*?\b([A-Za-z_]\w*)\s*\(", text, flags=re.M):
+            if m.group(0).lstrip().startswith(("typedef", "#", "return")):
+                continue
+            names.append(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2601_20174_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+def test_header_declares_functions():
+    names = declared_functions()
+    assert len(names) == len(set(names))
+    for must in ("setup_spectral_P", "galerkin_coarse", "pcg_solve", "nlsp_status_string"):
+        assert must in names
+
+
+def test_binding_covers_header():
+    from paper_2601_20174_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_every_declared_symbol_exported(lib):
+    from paper_2601_20174_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_status_strings(lib):
+    from paper_2601_20174_amd import api
+    seen = set()
+    for name in ("NLSP_OK", "NLSP_NOT_CONVERGED", "NLSP_E_INVALID", "NLSP_E_NOT_SPD", "NLSP_E_BREAKDOWN",
+                 "NLSP_E_NONFINITE", "NLSP_E_WORKSPACE", "NLSP_E_HIP", "NLSP_E_RANK"):
+        code = getattr(api, name[5:]) if hasattr(api, name[5:]) else None
+        if code is None:
+            continue
+        s = lib.nlsp_status_string(code).decode()
+        assert s == name
+        seen.add(code)
+    assert len(seen) >= 8
+    assert lib.nlsp_status_string(12345).decode() == "NLSP_UNKNOWN_STATUS"
+
+
+def test_padded_rank(lib):
+    for k, kp in [(1, 16), (16, 16), (17, 32), (32, 32), (48, 64), (64, 64), (65, 128), (128, 128),
+                  (129, 256), (256, 256)]:
+        assert lib.nlsp_padded_rank(k) == kp
+    for k in (0, -3, 257):
+        assert lib.nlsp_padded_rank(k) == -1
+
+
+def _op(kind, nx, ny, nz=1, coef=None):
+    from paper_2601_20174_amd import _lib
+    return _lib.NlspOperator(kind, nx, ny, nz, coef)
+
+
+def test_operator_size(lib):
+    from paper_2601_20174_amd import api
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced by the size query
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_POISSON5, 7, 5))) == 35
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_FV5, 8, 4, 1, fake))) == 32
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_FV7, 4, 3, 2, fake))) == 24
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_STENCIL9, 9, 9, 1, fake))) == 81
+    # invalid: missing coefficients, empty grid, unknown kind, n >= 2^31, null
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_FV5, 8, 4))) == -1
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_POISSON5, 0, 4))) == -1
+    assert lib.nlsp_operator_size(ctypes.byref(_op(99, 4, 4, 1, fake))) == -1
+    assert lib.nlsp_operator_size(ctypes.byref(_op(api.OP_FV7, 2048, 1024, 1024, fake))) == -1
+    assert lib.nlsp_operator_size(None) == -1
+
+
+def test_workspace_queries(lib):
+    from paper_2601_20174_amd import api
+    op = ctypes.byref(_op(api.OP_POISSON5, 64, 64))
+    a = lib.setup_spectral_P_workspace_bytes(op, 32, 16, api.FP64)
+    b = lib.setup_spectral_P_workspace_bytes(op, 32, 16, api.MIXED)
+    assert a > 0 and b > 0 and a % 256 == 0
+    assert lib.setup_spectral_P_workspace_bytes(op, 8, 16, api.FP64) == 0      # m < k
+    assert lib.setup_spectral_P_workspace_bytes(op, 300, 16, api.FP64) == 0    # m > 256
+    assert lib.setup_spectral_P_workspace_bytes(op, 32, 16, 7) == 0            # bad precision
+    assert lib.galerkin_coarse_workspace_bytes(op, 16) > 0
+    assert lib.galerkin_coarse_workspace_bytes(op, 0) == 0
+    w1 = lib.pcg_solve_workspace_bytes(op, 16, 1)
+    w8 = lib.pcg_solve_workspace_bytes(op, 16, 8)
+    assert 0 < w1 < w8
+    assert lib.pcg_solve_workspace_bytes(op, 16, 17) == 0                       # R > 16
+    assert lib.pcg_solve_workspace_bytes(op, 256, 16) == 0                      # kp * R > 2048
+
+
+def test_validation_rejects_before_any_gpu_call(lib):
+    """Invalid arguments come back as NLSP_E_INVALID / NLSP_E_WORKSPACE on a
+    machine without a GPU, i.e. validation precedes every HIP call."""
+    from paper_2601_20174_amd import _lib, api
+    fake = ctypes.c_void_p(0x1000)
+    op = ctypes.byref(_op(api.OP_POISSON5, 16, 16))
+    bad = ctypes.byref(_op(api.OP_FV5, 16, 16))  # no coefficients
+    E_INV, E_WS = api.E_INVALID, api.E_WORKSPACE
+    assert lib.apply_operator(op, fake, fake, 1, None) == E_INV              # x == y
+    assert lib.apply_operator(bad, fake, ctypes.c_void_p(0x2000), 1, None) == E_INV
+    assert lib.apply_operator(op, None, fake, 1, None) == E_INV
+    assert lib.jacobi_sweep_f32(op, 0.0, fake, fake, ctypes.c_void_p(0x2000), 1, None) == E_INV
+    assert lib.q1_aniso_stencil(0, fake, fake, None) == E_INV
+    sig = ctypes.c_void_p(0x3000)
+    assert lib.setup_spectral_P(op, None, 32, 16, 2 / 3, 10, api.FP64, fake, sig, None, 0, None) == E_INV
+    assert lib.setup_spectral_P(op, fake, 8, 16, 2 / 3, 10, api.FP64, fake, sig, None, 0, None) == E_INV
+    assert lib.setup_spectral_P(op, fake, 32, 16, -1.0, 10, api.FP64, fake, sig, None, 0, None) == E_INV
+    assert lib.setup_spectral_P(op, fake, 32, 16, 2 / 3, 10, api.FP64, fake, sig, None, 0, None) == E_WS
+    assert lib.galerkin_coarse(op, fake, 16, 2 / 3, 0, fake, fake, fake, fake, None, None, 0, None) == E_INV
+    assert lib.galerkin_coarse(op, fake, 16, 2 / 3, 1, fake, fake, fake, None, None, None, 0, None) == E_INV
+    assert lib.galerkin_coarse(op, fake, 16, 2 / 3, 1, fake, fake, fake, fake, None, None, 0, None) == E_WS
+    M = _lib.NlspTwoLevel(16, 1, 2 / 3, api.MIXED, fake, None, fake)
+    opts = _lib.NlspPcgOpts(1e-8, 100, 0, 8, None)
+    info = (_lib.NlspRhsInfo * 16)()
+    u = ctypes.c_void_p(0x4000)
+    assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 17, ctypes.byref(opts), info, None, 0, None) == E_INV
+    M_noq = _lib.NlspTwoLevel(16, 1, 2 / 3, api.MIXED, fake, fake, None)
+    assert lib.pcg_solve(op, ctypes.byref(M_noq), fake, u, 1, ctypes.byref(opts), info, None, 0, None) == E_INV
+    opts_bad = _lib.NlspPcgOpts(0.0, 100, 0, 8, None)
+    assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts_bad), info, None, 0, None) == E_INV
+    assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts), info, None, 0, None) == E_WS

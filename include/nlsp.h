@@ -211,6 +211,38 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
               int R, const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws,
               size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------- training losses */
+/* Subspace loss of a batch of predicted bases against relaxed samples (Sec. 4,
+ * projected energy eq. subspace_energy and the NLSS loss eq. nlss_loss; the
+ * loss form follows the appendix on optimality of smooth-error reduction):
+ *   colw == NULL  L_b = ||B_b - P_b P_b^T B_b||_F^2 / ||B_b||_F^2, evaluated
+ *                 through C = P^T B and G = P^T P, so valid for any P
+ *   colw != NULL  L_b = 1 - sum_j colw_j ||p_j^T B_b||^2 / ||B_b||_F^2; with
+ *                 colw_j = (k - j + 1)/k this equals the NLSS loss for any P
+ *   P     device (batch, n, k) float32        B  device (batch, n, m) float32
+ *   colw  device (k) float32 or NULL          loss  device (batch) float32
+ *   saved device, >= subspace_loss_saved_bytes, 256-byte aligned: written by
+ *         the forward (per sample the float64 loss, then the backward's small
+ *         matrix), read by the backward; owned by the caller
+ * Limits: 1 <= k <= 64, 1 <= m <= 256 (else NLSP_E_INVALID).  Products are
+ * float32 MFMA over row slabs; slabs are added in float64 in a fixed order,
+ * so results are bit-reproducible.  Asynchronous on `stream`. */
+size_t subspace_loss_saved_bytes(int batch, int n, int k, int m);
+size_t subspace_loss_workspace_bytes(int batch, int n, int k, int m);
+int subspace_loss_fwd(int batch, int n, int k, int m, const float* P, const float* B,
+                      const float* colw, float* loss, void* saved, size_t saved_bytes,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient of the forward's loss: gP_b = gloss_b * dL_b/dP_b, with
+ *   plain     dL/dP = -(2/||B||^2) [B C^T (2I - G) - P C C^T]
+ *   weighted  dL/dP = -(2/||B||^2) B C^T diag(colw)
+ *   saved  device, as written by subspace_loss_fwd for the same P, B, colw
+ *   gloss  device (batch) float32          gP  device (batch, n, k) float32
+ * Asynchronous on `stream`. */
+int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const float* B,
+                      const void* saved, size_t saved_bytes, const float* gloss, float* gP,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

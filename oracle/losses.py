@@ -6,6 +6,9 @@ infrastructure only).
   subspace_energy); the appendix on optimality of smooth-error reduction gives
   the expansion.  Evaluated here from the definition for any P.
 * NLSS loss (Sec. 4, eq. nlss_loss): (1/k) sum_l (1 - ||P_{1:l}^T S||^2/||S||^2).
+* Column-weighted energy loss 1 - sum_j w_j ||p_j^T B||^2 / ||B||^2; with
+  w_j = (k - j + 1)/k it is the NLSS loss for any P (prefix norms add up over
+  columns), the weighted Ky Fan form stated after eq. nlss_loss.
 * Captured energy Energy(r) = ||Q_r^T S||^2 / ||S||^2 (Sec. 4.1 diagnostic).
 * Galerkin-convergence objective (appendix, "Galerkin Convergence"):
   J(P) = ||A^{1/2}(I - Pi_A(P)) S||_F^2, Pi_A(P) = P (P^T A P)^{-1} P^T A.
@@ -16,7 +19,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-__all__ = ["subspace_loss", "subspace_loss_grad", "nlss_loss", "captured_energy",
+__all__ = ["subspace_loss", "subspace_loss_grad", "nlss_loss", "nlss_weights",
+           "weighted_energy_loss", "weighted_energy_loss_grad", "captured_energy",
            "galerkin_term", "galerkin_term_grad", "galerkin_term_dense",
            "galerkin_coarse_vjp"]
 
@@ -51,6 +55,23 @@ def nlss_loss(P: np.ndarray, S: np.ndarray) -> float:
         W = P[:, :l].T @ S
         tot += 1.0 - float(np.sum(W * W)) / ss
     return tot / k
+
+
+def nlss_weights(k: int) -> np.ndarray:
+    """w_j = (k - j + 1)/k, j = 1..k: column j lies in the prefixes l = j..k."""
+    return (k - np.arange(k)) / float(k)
+
+
+def weighted_energy_loss(P: np.ndarray, B: np.ndarray, w: np.ndarray) -> float:
+    """1 - sum_j w_j ||p_j^T B||^2 / ||B||^2."""
+    C = P.T @ B
+    return float(1.0 - np.sum(w * np.sum(C * C, axis=1)) / np.sum(B * B))
+
+
+def weighted_energy_loss_grad(P: np.ndarray, B: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """d/dP of the loss above: -(2/||B||^2) B C^T diag(w), C = P^T B."""
+    C = P.T @ B
+    return -(2.0 / float(np.sum(B * B))) * (B @ C.T) * w[None, :]
 
 
 def captured_energy(Q: np.ndarray, S: np.ndarray, r: int) -> float:

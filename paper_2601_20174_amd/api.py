@@ -239,3 +239,71 @@ def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tens
         timing["launches"] = tm.launches
     infos: List[RhsInfo] = [RhsInfo(info[i].iters, info[i].status, info[i].relres) for i in range(R)]
     return (u.reshape(f.shape) if squeeze else u), infos, rc
+
+
+# ------------------------------------------------------------ training losses
+def subspace_loss_saved_bytes(batch: int, n: int, k: int, m: int) -> int:
+    return int(_L().subspace_loss_saved_bytes(batch, n, k, m))
+
+
+def subspace_loss_workspace_bytes(batch: int, n: int, k: int, m: int) -> int:
+    return int(_L().subspace_loss_workspace_bytes(batch, n, k, m))
+
+
+def _loss_dims(P: torch.Tensor, B: torch.Tensor):
+    if P.dim() != 3 or B.dim() != 3 or P.shape[:2] != B.shape[:2]:
+        raise ValueError("P must be (batch, n, k) and B (batch, n, m)")
+    return P.shape[0], P.shape[1], P.shape[2], B.shape[2]
+
+
+def subspace_loss_fwd(P: torch.Tensor, B: torch.Tensor, colw: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None):
+    """Per-sample loss (batch,) float32 and the `saved` buffer for the backward."""
+    batch, n, k, m = _loss_dims(P, B)
+    nb = subspace_loss_saved_bytes(batch, n, k, m)
+    if nb == 0:
+        raise NlspError("subspace_loss_saved_bytes", E_INVALID)
+    saved = torch.empty(nb, dtype=torch.uint8, device=P.device)
+    loss = torch.empty(batch, dtype=torch.float32, device=P.device)
+    wb = subspace_loss_workspace_bytes(batch, n, k, m)
+    ws = workspace if workspace is not None else _workspace(wb, P.device)
+    cw = _dev(colw, torch.float32, "colw") if colw is not None else None
+    rc = _L().subspace_loss_fwd(batch, n, k, m, _dev(P, torch.float32, "P"), _dev(B, torch.float32, "B"), cw,
+                                loss.data_ptr(), saved.data_ptr(), nb, ws.data_ptr(), ws.numel(), _stream())
+    _check("subspace_loss_fwd", rc)
+    return loss, saved
+
+
+def subspace_loss_bwd(P: torch.Tensor, B: torch.Tensor, saved: torch.Tensor, gloss: torch.Tensor,
+                      gP: Optional[torch.Tensor] = None) -> torch.Tensor:
+    batch, n, k, m = _loss_dims(P, B)
+    if gP is None:
+        gP = torch.empty_like(P)
+    rc = _L().subspace_loss_bwd(batch, n, k, m, _dev(P, torch.float32, "P"), _dev(B, torch.float32, "B"),
+                                saved.data_ptr(), saved.numel(), _dev(gloss, torch.float32, "gloss"),
+                                _dev(gP, torch.float32, "gP"), _stream())
+    _check("subspace_loss_bwd", rc)
+    return gP
+
+
+class SubspaceLoss(torch.autograd.Function):
+    """Per-sample subspace (or, with colw, column-weighted / NLSS) loss with
+    the library's backward; B and colw receive no gradient."""
+
+    @staticmethod
+    def forward(ctx, P, B, colw=None):
+        P = P.contiguous()
+        B = B.contiguous()
+        loss, saved = subspace_loss_fwd(P, B, colw)
+        ctx.save_for_backward(P, B, saved)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gloss):
+        P, B, saved = ctx.saved_tensors
+        gP = subspace_loss_bwd(P, B, saved, gloss.contiguous().to(torch.float32))
+        return gP, None, None
+
+
+def subspace_loss(P: torch.Tensor, B: torch.Tensor, colw: Optional[torch.Tensor] = None) -> torch.Tensor:
+    return SubspaceLoss.apply(P, B, colw)

@@ -1,0 +1,553 @@
+// Subspace-loss forward and backward for a batch of bases (float32 data,
+// float32 MFMA products, float64 cross-workgroup sums in a fixed order).
+//
+//   plain     L_b = ||B_b - P_b P_b^T B_b||_F^2 / ||B_b||_F^2
+//               = (||B||^2 - 2 tr(C C^T) + tr(C^T G C)) / ||B||^2,
+//             C = P^T B, G = P^T P (valid for any P, orthonormal or not)
+//             dL/dP = B M1 + P M2,  M1 = -(2/||B||^2) C^T (2I - G),
+//                                    M2 =  (2/||B||^2) C C^T
+//   weighted  L_b = 1 - sum_j w_j ||p_j^T B_b||^2 / ||B_b||^2; with
+//             w_j = (k - j + 1)/k this is the NLSS loss (eq. nlss_loss)
+//             dL/dP = B M1,  M1 = -(2/||B||^2) C^T diag(w)
+//
+// The forward pass forms T = P^T [B | P] (k x (m + k)) per row slab with
+// v_mfma_f32_16x16x4f32, a second kernel adds the slabs in float64, takes the
+// loss and stores the backward's small matrix M = [M1; M2] (per unit upstream
+// gradient) in `saved`; the backward streams [B | P] once more and forms
+// dL/dP = [B | P] M with the same MFMA.
+#include <algorithm>
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "host_common.hpp"
+
+namespace nlsp {
+
+namespace sub {
+
+constexpr int NT = 256;            // 4 waves
+constexpr int NTF = 1024;          // the finishing kernel
+constexpr int RB = 64;             // rows staged per block
+constexpr int MAX_TILES = 64;      // 16 x 16 output tiles of P^T [B | P] (upper G only)
+constexpr size_t LDS_MAX = 160 * 1024;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+NLSP_DEV f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+struct Dims {
+  int n, k, m, kp, mp, cols, KT, MT, ntiles;  // kp, mp: k, m rounded up to 16; cols = mp + kp
+  int rows_per_slab, nslab;
+  int vec;                                    // 16-byte loads of B and P rows allowed
+  FastDiv fm, fk;                             // division by m and by k
+};
+
+inline int round16(int v) { return (v + 15) / 16 * 16; }
+
+inline int count_tiles(int KT, int MT) {
+  int c = 0;
+  for (int ti = 0; ti < KT; ++ti)
+    for (int tj = 0; tj < MT + KT; ++tj)
+      if (tj < MT || tj - MT >= ti) ++c;
+  return c;
+}
+
+inline Dims make_dims(int batch, int n, int k, int m) {
+  Dims d;
+  d.n = n;
+  d.k = k;
+  d.m = m;
+  d.kp = round16(k);
+  d.mp = round16(m);
+  d.cols = d.mp + d.kp;
+  d.KT = d.kp / 16;
+  d.MT = d.mp / 16;
+  d.ntiles = count_tiles(d.KT, d.MT);
+  // about 2048 workgroups over the batch, slabs a multiple of RB rows
+  const int64_t blocks = (n + RB - 1) / RB;
+  int64_t want = (2048 + batch - 1) / batch;
+  want = std::max<int64_t>(1, std::min<int64_t>(want, blocks));
+  const int64_t per = (blocks + want - 1) / want;
+  d.rows_per_slab = (int)(per * RB);
+  d.nslab = (int)((n + d.rows_per_slab - 1) / d.rows_per_slab);
+  d.vec = (m % 4 == 0 && k % 4 == 0) ? 1 : 0;
+  d.fm = make_fastdiv((uint32_t)m);
+  d.fk = make_fastdiv((uint32_t)k);
+  return d;
+}
+
+// linear tile id -> (ti, tj): row-major over ti, tj, without the tiles of G
+// below its diagonal
+NLSP_DEV void tile_of(int id, int KT, int MT, int& ti, int& tj) {
+  ti = 0;
+  int rowlen = MT + KT;
+  while (id >= rowlen) {
+    id -= rowlen;
+    ++ti;
+    rowlen = MT + KT - ti;
+  }
+  tj = (id < MT) ? id : MT + ti + (id - MT);
+}
+
+// Staging of [B | P] rows r0 .. r0 + RB of one sample into LDS: B in columns
+// [0, m), P in [mp, mp + k), zero in the padding columns and in rows beyond n.
+// The block's B rows and P rows are each one contiguous range in memory;
+// every thread issues its share of 16-byte (or 4-byte) loads, up to NV of
+// them, before it writes any, so the loads of a pass are in flight together
+// (each load is clamped to a valid address and masked afterwards, which keeps
+// the code free of branches around the loads).
+//   TRANS = true   column-major X^T[c][r], stride xs (>= RB, multiple of 4)
+//   TRANS = false  row-major X[r][c], stride xs (>= cols, multiple of 4)
+// Optionally adds the squares of the B entries to *bsq.
+constexpr int NV = 8;
+
+template <bool VEC, bool TRANS>
+NLSP_DEV void stage_rows(const float* __restrict__ Bs, const float* __restrict__ Ps, const Dims& d,
+                         int64_t r0, float* X, int xs, float* bsq) {
+  constexpr int W = VEC ? 4 : 1;                   // floats per load
+  const int t = threadIdx.x;
+  const int nb = RB * d.m / W, np = RB * d.k / W;  // loads of the B and P ranges
+  const int rmax = (int)min((int64_t)RB, (int64_t)d.n - r0);  // rows of this block that exist (>= 1)
+  const float* Bb = Bs + r0 * d.m;
+  const float* Pb = Ps + r0 * d.k;
+  const int lastb = rmax * d.m - W, lastp = rmax * d.k - W;   // last valid load offsets
+  float acc = 0.f;
+  for (int base = 0; base < nb + np; base += NT * NV) {
+    float v[NV][W];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int q = base + t + NT * j;
+      const bool isb = q < nb;
+      const int e = (isb ? q : q - nb) * W;
+      const float* src = isb ? Bb + min(e, lastb) : Pb + min(e, lastp);
+      if constexpr (VEC) {
+        const float4 x = *reinterpret_cast<const float4*>(src);
+        v[j][0] = x.x;
+        v[j][1] = x.y;
+        v[j][2] = x.z;
+        v[j][3] = x.w;
+      } else {
+        v[j][0] = *src;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int q = base + t + NT * j;
+      if (q < nb + np) {
+        const bool isb = q < nb;
+        const int e = (isb ? q : q - nb) * W;
+        const int row = (int)fdiv((uint32_t)e, isb ? d.fm : d.fk);
+        const int col = e - row * (isb ? d.m : d.k) + (isb ? 0 : d.mp);
+        const bool live = row < rmax;
+        float x[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          x[u] = live ? v[j][u] : 0.f;
+          if (isb) acc += x[u] * x[u];
+        }
+        if constexpr (TRANS) {
+#pragma unroll
+          for (int u = 0; u < W; ++u) X[(col + u) * xs + row] = x[u];
+        } else if constexpr (VEC) {
+          *reinterpret_cast<float4*>(X + row * xs + col) = float4{x[0], x[W > 1 ? 1 : 0], x[W > 2 ? 2 : 0],
+                                                                  x[W > 3 ? 3 : 0]};
+        } else {
+          X[row * xs + col] = x[0];
+        }
+      }
+    }
+  }
+  if (bsq) *bsq += acc;
+}
+
+// zero the padding columns [m, mp) and [mp + k, cols) of a staging buffer
+template <bool TRANS>
+NLSP_DEV void zero_padding(const Dims& d, float* X, int xs) {
+  const int padb = d.mp - d.m, padp = d.kp - d.k, pw = padb + padp;
+  if (pw == 0) return;
+  for (int e = threadIdx.x; e < RB * pw; e += NT) {
+    const int r = e / pw, c0 = e % pw;
+    const int c = (c0 < padb) ? d.m + c0 : d.mp + d.k + (c0 - padb);
+    if (TRANS)
+      X[c * xs + r] = 0.f;
+    else
+      X[r * xs + c] = 0.f;
+  }
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+NLSP_DEV f4v lds4(const float* p) { return *reinterpret_cast<const f4v*>(p); }
+
+// partial T = P^T [B | P] over one row slab; per tile 256 floats in the MFMA
+// output order (lane, v), then the slab's ||B||^2 in float64.  Wave w owns
+// tiles w, w + 4, ..., w + 4 (TPW - 1); ids past the last tile repeat tile 0
+// and are not stored.  The MFMA's contraction index kk = lane / 16 is mapped
+// to the block rows 16 kk .. 16 kk + 15 over 16 steps, so a lane's operands
+// for four consecutive steps are four consecutive floats of a column of X^T:
+// one 16-byte LDS read feeds four MFMAs.
+template <int TPW, bool VEC>
+__global__ __launch_bounds__(NT) void k_fwd_partial(Dims d, const float* __restrict__ P,
+                                                    const float* __restrict__ B, float* __restrict__ part,
+                                                    double* __restrict__ bbpart) {
+  extern __shared__ float X[];               // X^T: cols x xs
+  __shared__ double red[NT / 64];
+  const int slab = blockIdx.x, b = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int xs = RB + 4;
+  const float* Bs = B + (int64_t)b * d.n * d.m;
+  const float* Ps = P + (int64_t)b * d.n * d.k;
+  zero_padding<true>(d, X, xs);
+  const int lc = lane & 15, lg = lane >> 4;
+  const float* pa[TPW];
+  const float* pb[TPW];
+  f4 acc[TPW];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    int id = w + 4 * s, ti, tj;
+    if (id >= d.ntiles) id = 0;
+    tile_of(id, d.KT, d.MT, ti, tj);
+    pa[s] = X + (d.mp + 16 * ti + lc) * xs + 16 * lg;
+    pb[s] = X + (16 * tj + lc) * xs + 16 * lg;
+    acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  float bsq = 0.f;
+  const int64_t s0 = (int64_t)slab * d.rows_per_slab;
+  const int64_t s1 = min((int64_t)(s0 + d.rows_per_slab), (int64_t)d.n);
+  for (int64_t r0 = s0; r0 < s1; r0 += RB) {
+    __syncthreads();
+    stage_rows<VEC, true>(Bs, Ps, d, r0, X, xs, &bsq);
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      f4v a[TPW], bv[TPW];
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) {
+        a[s] = lds4(pa[s] + 4 * s4);
+        bv[s] = lds4(pb[s] + 4 * s4);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) acc[s] = mfma4(a[s][u], bv[s][u], acc[s]);
+    }
+  }
+  float* out = part + ((int64_t)b * d.nslab + slab) * d.ntiles * 256;
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const int id = w + 4 * s;
+    if (id < d.ntiles) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(int64_t)id * 256 + v * 64 + lane] = acc[s][v];
+    }
+  }
+  double bs = wave_sum((double)bsq);
+  if (lane == 0) red[w] = bs;
+  __syncthreads();
+  if (threadIdx.x == 0) bbpart[(int64_t)b * d.nslab + slab] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// T summed over the slabs in slab order, float64: grid (ceil(nel / NT), batch),
+// one element per thread, loads issued eight at a time
+__global__ __launch_bounds__(NT) void k_fwd_reduce(Dims d, const float* __restrict__ part,
+                                                   double* __restrict__ T64) {
+  const int b = blockIdx.y;
+  const int nel = d.ntiles * 256;
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= nel) return;
+  const float* pb = part + (int64_t)b * d.nslab * nel + e;
+  double s = 0.0;
+  for (int sl = 0; sl < d.nslab; sl += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (sl + j < d.nslab) ? pb[(int64_t)(sl + j) * nel] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += (double)v[j];
+  }
+  T64[(int64_t)b * nel + e] = s;
+}
+
+// per sample: T (from the slab sums) and ||B||^2, the loss, and M = [M1; M2]
+// for a unit upstream gradient; 16 waves share the small float64 products
+__global__ __launch_bounds__(NTF) void k_fwd_finish(Dims d, const double* __restrict__ T64,
+                                                   const double* __restrict__ bbpart,
+                                                   const float* __restrict__ colw, float* __restrict__ loss,
+                                                   double* __restrict__ loss64, float* __restrict__ Msave) {
+  extern __shared__ double T[];     // k_p x cols
+  __shared__ double H[64 * 64];     // C C^T (k x k)
+  __shared__ double sh[NTF / 64];
+  __shared__ double s_bb;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int cols = d.cols;
+  const int tcs = cols + 1;         // odd row stride (doubles): rows fall in different banks
+  const int nel = d.ntiles * 256;
+  const double* tb = T64 + (int64_t)b * nel;
+  for (int e = t; e < nel; e += NTF) {
+    const int id = e >> 8, v = (e >> 6) & 3, lane = e & 63;
+    int ti, tj;
+    tile_of(id, d.KT, d.MT, ti, tj);
+    T[(16 * ti + 4 * (lane >> 4) + v) * tcs + 16 * tj + (lane & 15)] = tb[e];
+  }
+  if (t == 0) {
+    double s = 0.0;
+    for (int sl = 0; sl < d.nslab; ++sl) s += bbpart[(int64_t)b * d.nslab + sl];
+    s_bb = s;
+  }
+  __syncthreads();
+  // G below its diagonal tiles from the transposed upper part
+  for (int e = t; e < d.kp * d.kp; e += NTF) {
+    const int i = e / d.kp, j = e % d.kp;
+    if (j / 16 < i / 16) T[i * tcs + d.mp + j] = T[j * tcs + d.mp + i];
+  }
+  __syncthreads();
+  const int k = d.k, m = d.m;
+  // H = C C^T, C = T[:, :m]
+  for (int e = t; e < k * k; e += NTF) {
+    const int i = e / k, j = e % k;
+    double s = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < m; ++c) s += T[i * tcs + c] * T[j * tcs + c];
+    H[i * 64 + j] = s;
+  }
+  __syncthreads();
+  const double bb = s_bb;
+  const double inv = (bb > 0.0) ? 1.0 / bb : 0.0;
+  // loss terms
+  double part_l = 0.0;
+  for (int e = t; e < k * k; e += NTF) {
+    const int i = e / k, j = e % k;
+    if (colw) {
+      if (i == j) part_l += (double)colw[i] * H[i * 64 + i];
+    } else {
+      part_l += T[i * tcs + d.mp + j] * H[i * 64 + j] - ((i == j) ? 2.0 * H[i * 64 + i] : 0.0);
+    }
+  }
+  part_l = wave_sum(part_l);
+  if ((t & 63) == 0) sh[t >> 6] = part_l;
+  __syncthreads();
+  double lt = 0.0;
+  for (int q = 0; q < NTF / 64; ++q) lt += sh[q];
+  if (t == 0) {
+    const double L = colw ? 1.0 - lt * inv : (bb + lt) * inv;
+    loss64[b] = L;
+    loss[b] = (float)L;
+  }
+  // M (cols x kp), float32, for a unit upstream gradient
+  float* M = Msave + (int64_t)b * cols * d.kp;
+  for (int e = t; e < cols * d.kp; e += NTF) {
+    const int c = e / d.kp, j = e % d.kp;
+    double v = 0.0;
+    if (j < k) {
+      if (c < m) {
+        if (colw) {
+          v = -2.0 * inv * (double)colw[j] * T[j * tcs + c];
+        } else {
+          double s = 0.0;
+#pragma unroll 8
+          for (int i = 0; i < k; ++i) s += T[i * tcs + c] * (((i == j) ? 2.0 : 0.0) - T[i * tcs + d.mp + j]);
+          v = -2.0 * inv * s;
+        }
+      } else if (c >= d.mp && c - d.mp < k && !colw) {
+        v = 2.0 * inv * H[(c - d.mp) * 64 + j];
+      }
+    }
+    M[e] = (float)v;
+  }
+}
+
+// dL/dP = g_b [B | P] M over one row slab; wave w forms rows 16 w .. 16 w + 15
+// of each staged block, all KT column tiles at once.  The contraction runs
+// over the cols = 4 cq columns of [B | P]; the MFMA's kk = lane / 16 takes
+// columns kk cq .. kk cq + cq - 1 over cq steps, so four consecutive steps are
+// four consecutive floats of a row of X and of a row of M^T (16-byte reads).
+template <int KT, bool VEC>
+__global__ __launch_bounds__(NT) void k_bwd(Dims d, const float* __restrict__ P, const float* __restrict__ B,
+                                            const float* __restrict__ Msave, const float* __restrict__ gloss,
+                                            float* __restrict__ gP) {
+  extern __shared__ float lds[];
+  const int slab = blockIdx.x, b = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int xs = d.cols + 4;             // X: RB x xs, row-major
+  const int mts = d.cols + 4;            // M^T: kp x mts
+  float* X = lds;
+  float* MT = lds + RB * xs;
+  zero_padding<false>(d, X, xs);
+  const float g = gloss[b];
+  const float* Mb = Msave + (int64_t)b * d.cols * d.kp;
+  for (int e = threadIdx.x; e < d.cols * d.kp; e += NT) MT[(e % d.kp) * mts + e / d.kp] = g * Mb[e];
+  const float* Bs = B + (int64_t)b * d.n * d.m;
+  const float* Ps = P + (int64_t)b * d.n * d.k;
+  float* G = gP + (int64_t)b * d.n * d.k;
+  const int64_t s0 = (int64_t)slab * d.rows_per_slab;
+  const int64_t s1 = min((int64_t)(s0 + d.rows_per_slab), (int64_t)d.n);
+  const int lr = lane & 15, lg = lane >> 4;
+  const int cq = d.cols / 4;             // multiple of 4
+  const float* xa = X + (16 * w + lr) * xs + lg * cq;
+  const float* mb = MT + lr * mts + lg * cq;
+  for (int64_t r0 = s0; r0 < s1; r0 += RB) {
+    __syncthreads();
+    stage_rows<VEC, false>(Bs, Ps, d, r0, X, xs, nullptr);
+    __syncthreads();
+    f4 acc[KT];
+#pragma unroll
+    for (int tj = 0; tj < KT; ++tj) acc[tj] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int c = 0; c < cq; c += 4) {
+      const f4v a = lds4(xa + c);
+      f4v bm[KT];
+#pragma unroll
+      for (int tj = 0; tj < KT; ++tj) bm[tj] = lds4(mb + 16 * tj * mts + c);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int tj = 0; tj < KT; ++tj) acc[tj] = mfma4(a[u], bm[tj][u], acc[tj]);
+    }
+#pragma unroll
+    for (int tj = 0; tj < KT; ++tj) {
+      const int col = 16 * tj + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 16 * w + 4 * lg + v;
+        if (row < s1 && col < d.k) G[row * d.k + col] = acc[tj][v];
+      }
+    }
+  }
+}
+
+struct SubLayout {
+  float* part;
+  double* bbpart;
+  double* T64;
+  size_t bytes;
+};
+
+inline SubLayout carve_sub(void* ws, int batch, const Dims& d) {
+  Carver c(ws);
+  SubLayout L;
+  L.part = c.take<float>((size_t)batch * d.nslab * d.ntiles * 256);
+  L.bbpart = c.take<double>((size_t)batch * d.nslab);
+  L.T64 = c.take<double>((size_t)batch * d.ntiles * 256);
+  L.bytes = c.bytes();
+  return L;
+}
+
+// saved: per sample loss in float64, then M (cols x kp float32)
+inline size_t saved_bytes(int batch, const Dims& d) {
+  return align_up((size_t)batch * sizeof(double)) + (size_t)batch * d.cols * d.kp * sizeof(float);
+}
+
+inline size_t fwd_lds(const Dims& d) { return (size_t)d.cols * (RB + 4) * sizeof(float); }
+inline size_t fin_lds(const Dims& d) { return (size_t)d.kp * (d.cols + 1) * sizeof(double); }
+inline size_t bwd_lds(const Dims& d) {
+  return ((size_t)RB * (d.cols + 4) + (size_t)d.kp * (d.cols + 4)) * sizeof(float);
+}
+
+// k <= 64, m <= 256, at most 64 output tiles, and every kernel's LDS within a CU's
+inline bool dims_ok(int batch, int n, int k, int m) {
+  if (batch < 1 || n < 1 || k < 1 || m < 1 || k > 64 || m > 256) return false;
+  if ((int64_t)batch * n * std::max(k, m) >= (int64_t(1) << 40)) return false;
+  const Dims d = make_dims(batch, n, k, m);
+  return d.ntiles <= MAX_TILES && fwd_lds(d) <= LDS_MAX && fin_lds(d) + 64 * 64 * 8 + 256 <= LDS_MAX &&
+         bwd_lds(d) <= LDS_MAX;
+}
+
+template <typename K>
+inline hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace sub
+}  // namespace nlsp
+
+using namespace nlsp;
+using namespace nlsp::sub;
+
+extern "C" {
+
+size_t subspace_loss_saved_bytes(int batch, int n, int k, int m) {
+  if (!dims_ok(batch, n, k, m)) return 0;
+  return saved_bytes(batch, make_dims(batch, n, k, m));
+}
+
+size_t subspace_loss_workspace_bytes(int batch, int n, int k, int m) {
+  if (!dims_ok(batch, n, k, m)) return 0;
+  return carve_sub(nullptr, batch, make_dims(batch, n, k, m)).bytes;
+}
+
+int subspace_loss_fwd(int batch, int n, int k, int m, const float* P, const float* B, const float* colw,
+                      float* loss, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes, void* stream) {
+  if (!dims_ok(batch, n, k, m) || !P || !B || !loss || !saved) return NLSP_E_INVALID;
+  Dims d = make_dims(batch, n, k, m);
+  if (reinterpret_cast<uintptr_t>(P) % 16 || reinterpret_cast<uintptr_t>(B) % 16) d.vec = 0;
+  if (saved_nbytes < saved_bytes(batch, d) || reinterpret_cast<uintptr_t>(saved) % WS_ALIGN)
+    return NLSP_E_WORKSPACE;
+  const size_t need = carve_sub(nullptr, batch, d).bytes;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const SubLayout L = carve_sub(ws, batch, d);
+  hipStream_t s = as_stream(stream);
+  double* loss64 = static_cast<double*>(saved);
+  float* Msave = reinterpret_cast<float*>(static_cast<char*>(saved) + align_up((size_t)batch * sizeof(double)));
+  const dim3 grid(d.nslab, batch);
+  const size_t lds = fwd_lds(d);
+  const int tpw = (d.ntiles + 3) / 4;
+  int rc = NLSP_OK;
+  auto go = [&](auto kern) {
+    if (allow_lds(kern, lds) != hipSuccess) { rc = NLSP_E_HIP; return; }
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, d, P, B, L.part, L.bbpart);
+  };
+  auto pick = [&](auto vec) {
+    constexpr bool V = decltype(vec)::value;
+    switch (tpw) {
+      case 1: go(k_fwd_partial<1, V>); break;
+      case 2: go(k_fwd_partial<2, V>); break;
+      case 3: go(k_fwd_partial<3, V>); break;
+      case 4: go(k_fwd_partial<4, V>); break;
+      case 5: case 6: go(k_fwd_partial<6, V>); break;
+      case 7: case 8: go(k_fwd_partial<8, V>); break;
+      case 9: case 10: case 11: case 12: go(k_fwd_partial<12, V>); break;
+      default: go(k_fwd_partial<16, V>); break;
+    }
+  };
+  if (d.vec) pick(std::true_type{}); else pick(std::false_type{});
+  if (rc != NLSP_OK) return rc;
+  hipLaunchKernelGGL(k_fwd_reduce, dim3(ceil_div((int64_t)d.ntiles * 256, NT), batch), dim3(NT), 0, s, d, L.part,
+                     L.T64);
+  NLSP_HIP(allow_lds(k_fwd_finish, fin_lds(d)));
+  hipLaunchKernelGGL(k_fwd_finish, dim3(batch), dim3(NTF), fin_lds(d), s, d, L.T64, L.bbpart, colw, loss, loss64,
+                     Msave);
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const float* B, const void* saved,
+                      size_t saved_nbytes, const float* gloss, float* gP, void* stream) {
+  if (!dims_ok(batch, n, k, m) || !P || !B || !saved || !gloss || !gP) return NLSP_E_INVALID;
+  Dims d = make_dims(batch, n, k, m);
+  if (reinterpret_cast<uintptr_t>(P) % 16 || reinterpret_cast<uintptr_t>(B) % 16) d.vec = 0;
+  if (saved_nbytes < saved_bytes(batch, d)) return NLSP_E_WORKSPACE;
+  const float* Msave =
+      reinterpret_cast<const float*>(static_cast<const char*>(saved) + align_up((size_t)batch * sizeof(double)));
+  hipStream_t s = as_stream(stream);
+  const size_t lds = bwd_lds(d);
+  int rc = NLSP_OK;
+  auto go = [&](auto kern) {
+    if (allow_lds(kern, lds) != hipSuccess) { rc = NLSP_E_HIP; return; }
+    hipLaunchKernelGGL(kern, dim3(d.nslab, batch), dim3(NT), lds, s, d, P, B, Msave, gloss, gP);
+  };
+  auto pick = [&](auto vec) {
+    constexpr bool V = decltype(vec)::value;
+    switch (d.KT) {
+      case 1: go(k_bwd<1, V>); break;
+      case 2: go(k_bwd<2, V>); break;
+      case 3: go(k_bwd<3, V>); break;
+      default: go(k_bwd<4, V>); break;
+    }
+  };
+  if (d.vec) pick(std::true_type{}); else pick(std::false_type{});
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+}  // extern "C"

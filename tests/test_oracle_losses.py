@@ -67,6 +67,27 @@ def test_subspace_loss_gradient_finite_differences_and_autograd():
     np.testing.assert_allclose(g, Pt.grad.numpy(), atol=1e-12)
 
 
+def test_weighted_energy_loss_is_nlss_for_any_P_and_its_gradient():
+    S = _S(6)
+    k = 5
+    P = np.random.default_rng(7).standard_normal((64, k))      # not orthonormal
+    w = O.nlss_weights(k)
+    np.testing.assert_allclose(w, [5 / 5, 4 / 5, 3 / 5, 2 / 5, 1 / 5])
+    # the prefix definition of eq. nlss_loss, summed term by term
+    np.testing.assert_allclose(O.weighted_energy_loss(P, S, w), O.nlss_loss(P, S), rtol=1e-13)
+    g = O.weighted_energy_loss_grad(P, S, w)
+    gfd = _fd(lambda Q: O.nlss_loss(Q, S), P)
+    assert np.abs(g - gfd).max() <= 1e-7 * max(1.0, np.abs(g).max())
+    Pt = torch.tensor(P, requires_grad=True)
+    St = torch.tensor(S)
+    l = sum(1 - ((Pt[:, :j].T @ St) ** 2).sum() / (St ** 2).sum() for j in range(1, k + 1)) / k
+    l.backward()
+    np.testing.assert_allclose(g, Pt.grad.numpy(), atol=1e-12)
+    # uniform weights 1 on orthonormal P give the plain subspace loss
+    Q, _ = np.linalg.qr(P)
+    np.testing.assert_allclose(O.weighted_energy_loss(Q, S, np.ones(k)), O.subspace_loss(Q, S), atol=1e-14)
+
+
 def _small_spd(seed=0, N=6):
     rng = np.random.default_rng(seed)
     return O.fv_harmonic_2d(np.exp(rng.standard_normal((N, N))))

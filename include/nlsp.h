@@ -243,6 +243,31 @@ int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const floa
                       const void* saved, size_t saved_bytes, const float* gloss, float* gP,
                       void* stream);
 
+/* Galerkin product of a batch of bases with a batch of operators (Algorithm 1
+ * coarse operator; appendix "Two-Level Subspace Correction", coarse-operator
+ * equation), for training through A_c:
+ *   Y_b = A_b P_b,  A_c,b = (P_b^T Y_b + Y_b^T P_b) / 2
+ *   A     host descriptor shared by the batch (kind, grid); its coefficients
+ *         are batched: FV5/FV7 coef = batch x n doubles, STENCIL9 coef =
+ *         batch x 9 doubles, POISSON5 none
+ *   P     device (batch, n, k) float32     Ac  device (batch, k, k) float32
+ *   Y     device (batch, n, k) float32, output, kept by the caller for the
+ *         backward
+ * Limits: 1 <= k <= 64, n k < 2^31.  Float32 stencil and MFMA products,
+ * slab sums in float64.  Asynchronous on `stream`. */
+size_t galerkin_fwd_workspace_bytes(int batch, const nlsp_operator* A, int k);
+int galerkin_fwd(int batch, const nlsp_operator* A, const float* P, int k, float* Ac, float* Y,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the Galerkin product: with G_b = dL/dA_c,b (upstream),
+ * dL/dP_b = A_b P_b (G_b + G_b^T) = Y_b (G_b + G_b^T)   (A_b symmetric).
+ *   Y    device (batch, n, k) float32 from galerkin_fwd
+ *   gAc  device (batch, k, k) float32      gP  device (batch, n, k) float32
+ * Asynchronous on `stream`. */
+size_t galerkin_bwd_workspace_bytes(int batch, int n, int k);
+int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, float* gP, void* ws,
+                 size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

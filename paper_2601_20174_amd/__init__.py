@@ -14,5 +14,6 @@ from .api import (  # noqa: F401
     jacobi_sweep_f32, setup_spectral_P_workspace_bytes, setup_spectral_P,
     galerkin_coarse_workspace_bytes, galerkin_coarse, pcg_solve_workspace_bytes, pcg_solve,
     subspace_loss_saved_bytes, subspace_loss_workspace_bytes, subspace_loss_fwd, subspace_loss_bwd,
-    SubspaceLoss, subspace_loss,
+    SubspaceLoss, subspace_loss, galerkin_fwd_workspace_bytes, galerkin_bwd_workspace_bytes, galerkin_fwd,
+    galerkin_bwd, GalerkinProduct, galerkin_product,
 )

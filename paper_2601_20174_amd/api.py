@@ -307,3 +307,67 @@ class SubspaceLoss(torch.autograd.Function):
 
 def subspace_loss(P: torch.Tensor, B: torch.Tensor, colw: Optional[torch.Tensor] = None) -> torch.Tensor:
     return SubspaceLoss.apply(P, B, colw)
+
+
+# ------------------------------------------------------------ Galerkin product
+def galerkin_fwd_workspace_bytes(batch: int, op: Operator, k: int) -> int:
+    return int(_L().galerkin_fwd_workspace_bytes(batch, ctypes.byref(op.c()), k))
+
+
+def galerkin_bwd_workspace_bytes(batch: int, n: int, k: int) -> int:
+    return int(_L().galerkin_bwd_workspace_bytes(batch, n, k))
+
+
+def galerkin_fwd(op: Operator, P: torch.Tensor):
+    """A_c = P^T A P per sample, P (batch, n, k) float32; ``op`` carries the
+    batched coefficients (batch x n for FV5/FV7).  Returns (Ac, Y = A P)."""
+    if P.dim() != 3:
+        raise ValueError("P must be (batch, n, k)")
+    batch, n, k = P.shape
+    if n != nlsp_operator_size(op):
+        raise ValueError("P rows must match the operator size")
+    per = {OP_FV5: n, OP_FV7: n, OP_STENCIL9: 9}.get(op.kind, 0)
+    if per and (op.coef is None or op.coef.numel() < batch * per):
+        raise ValueError(f"batched coefficients: need {batch} x {per} values")
+    Ac = torch.empty(batch, k, k, dtype=torch.float32, device=P.device)
+    Y = torch.empty_like(P)
+    nb = galerkin_fwd_workspace_bytes(batch, op, k)
+    if nb == 0:
+        raise NlspError("galerkin_fwd_workspace_bytes", E_INVALID)
+    ws = _workspace(nb, P.device)
+    rc = _L().galerkin_fwd(batch, ctypes.byref(op.c()), _dev(P, torch.float32, "P"), k, Ac.data_ptr(),
+                           Y.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check("galerkin_fwd", rc)
+    return Ac, Y
+
+
+def galerkin_bwd(Y: torch.Tensor, gAc: torch.Tensor) -> torch.Tensor:
+    batch, n, k = Y.shape
+    gP = torch.empty_like(Y)
+    nb = galerkin_bwd_workspace_bytes(batch, n, k)
+    if nb == 0:
+        raise NlspError("galerkin_bwd_workspace_bytes", E_INVALID)
+    ws = _workspace(nb, Y.device)
+    rc = _L().galerkin_bwd(batch, n, k, _dev(Y, torch.float32, "Y"), _dev(gAc, torch.float32, "gAc"),
+                           gP.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check("galerkin_bwd", rc)
+    return gP
+
+
+class GalerkinProduct(torch.autograd.Function):
+    """A_c = P^T A P (batched) with the library's backward A P (G + G^T)."""
+
+    @staticmethod
+    def forward(ctx, P, op):
+        Ac, Y = galerkin_fwd(op, P.contiguous())
+        ctx.save_for_backward(Y)
+        return Ac
+
+    @staticmethod
+    def backward(ctx, gAc):
+        (Y,) = ctx.saved_tensors
+        return galerkin_bwd(Y, gAc.contiguous().to(torch.float32)), None
+
+
+def galerkin_product(P: torch.Tensor, op: Operator) -> torch.Tensor:
+    return GalerkinProduct.apply(P, op)

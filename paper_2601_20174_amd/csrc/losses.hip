@@ -35,8 +35,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 NLSP_DEV f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
+// Shapes of one batched product.  The staged block is [B | P] (P omitted when
+// ks = 0); the forward forms P^T [B | P] over the tiles of P^T B and, when
+// gt = 1, the upper tiles of G = P^T P.
 struct Dims {
-  int n, k, m, kp, mp, cols, KT, MT, ntiles;  // kp, mp: k, m rounded up to 16; cols = mp + kp
+  int n, k, m, kp, mp, cols, KT, MT, ntiles;  // kp, mp: k, m rounded up to 16; cols = mp + (ks ? kp : 0)
+  int gt, ks;                                 // G tiles included; P columns staged (k or 0)
   int rows_per_slab, nslab;
   int vec;                                    // 16-byte loads of B and P rows allowed
   FastDiv fm, fk;                             // division by m and by k
@@ -44,25 +48,27 @@ struct Dims {
 
 inline int round16(int v) { return (v + 15) / 16 * 16; }
 
-inline int count_tiles(int KT, int MT) {
+inline int count_tiles(int KT, int MT, int gt) {
   int c = 0;
   for (int ti = 0; ti < KT; ++ti)
-    for (int tj = 0; tj < MT + KT; ++tj)
+    for (int tj = 0; tj < MT + (gt ? KT : 0); ++tj)
       if (tj < MT || tj - MT >= ti) ++c;
   return c;
 }
 
-inline Dims make_dims(int batch, int n, int k, int m) {
+inline Dims make_dims(int batch, int n, int k, int m, bool gt = true, bool stage_p = true) {
   Dims d;
   d.n = n;
   d.k = k;
   d.m = m;
   d.kp = round16(k);
   d.mp = round16(m);
-  d.cols = d.mp + d.kp;
+  d.gt = gt ? 1 : 0;
+  d.ks = stage_p ? k : 0;
+  d.cols = d.mp + (stage_p ? d.kp : 0);
   d.KT = d.kp / 16;
   d.MT = d.mp / 16;
-  d.ntiles = count_tiles(d.KT, d.MT);
+  d.ntiles = count_tiles(d.KT, d.MT, d.gt);
   // about 2048 workgroups over the batch, slabs a multiple of RB rows
   const int64_t blocks = (n + RB - 1) / RB;
   int64_t want = (2048 + batch - 1) / batch;
@@ -70,15 +76,20 @@ inline Dims make_dims(int batch, int n, int k, int m) {
   const int64_t per = (blocks + want - 1) / want;
   d.rows_per_slab = (int)(per * RB);
   d.nslab = (int)((n + d.rows_per_slab - 1) / d.rows_per_slab);
-  d.vec = (m % 4 == 0 && k % 4 == 0) ? 1 : 0;
+  d.vec = (m % 4 == 0 && d.ks % 4 == 0) ? 1 : 0;
   d.fm = make_fastdiv((uint32_t)m);
   d.fk = make_fastdiv((uint32_t)k);
   return d;
 }
 
 // linear tile id -> (ti, tj): row-major over ti, tj, without the tiles of G
-// below its diagonal
-NLSP_DEV void tile_of(int id, int KT, int MT, int& ti, int& tj) {
+// below its diagonal (or without G at all when gt = 0)
+NLSP_DEV void tile_of(int id, int KT, int MT, int gt, int& ti, int& tj) {
+  if (!gt) {
+    ti = id / MT;
+    tj = id - ti * MT;
+    return;
+  }
   ti = 0;
   int rowlen = MT + KT;
   while (id >= rowlen) {
@@ -106,11 +117,11 @@ NLSP_DEV void stage_rows(const float* __restrict__ Bs, const float* __restrict__
                          int64_t r0, float* X, int xs, float* bsq) {
   constexpr int W = VEC ? 4 : 1;                   // floats per load
   const int t = threadIdx.x;
-  const int nb = RB * d.m / W, np = RB * d.k / W;  // loads of the B and P ranges
+  const int nb = RB * d.m / W, np = RB * d.ks / W;  // loads of the B and P ranges
   const int rmax = (int)min((int64_t)RB, (int64_t)d.n - r0);  // rows of this block that exist (>= 1)
   const float* Bb = Bs + r0 * d.m;
-  const float* Pb = Ps + r0 * d.k;
-  const int lastb = rmax * d.m - W, lastp = rmax * d.k - W;   // last valid load offsets
+  const float* Pb = Ps + r0 * d.ks;
+  const int lastb = rmax * d.m - W, lastp = rmax * d.ks - W;  // last valid load offsets
   float acc = 0.f;
   for (int base = 0; base < nb + np; base += NT * NV) {
     float v[NV][W];
@@ -119,7 +130,7 @@ NLSP_DEV void stage_rows(const float* __restrict__ Bs, const float* __restrict__
       const int q = base + t + NT * j;
       const bool isb = q < nb;
       const int e = (isb ? q : q - nb) * W;
-      const float* src = isb ? Bb + min(e, lastb) : Pb + min(e, lastp);
+      const float* src = isb ? Bb + min(e, lastb) : Pb + max(0, min(e, lastp));
       if constexpr (VEC) {
         const float4 x = *reinterpret_cast<const float4*>(src);
         v[j][0] = x.x;
@@ -163,7 +174,7 @@ NLSP_DEV void stage_rows(const float* __restrict__ Bs, const float* __restrict__
 // zero the padding columns [m, mp) and [mp + k, cols) of a staging buffer
 template <bool TRANS>
 NLSP_DEV void zero_padding(const Dims& d, float* X, int xs) {
-  const int padb = d.mp - d.m, padp = d.kp - d.k, pw = padb + padp;
+  const int padb = d.mp - d.m, padp = d.ks ? d.kp - d.k : 0, pw = padb + padp;
   if (pw == 0) return;
   for (int e = threadIdx.x; e < RB * pw; e += NT) {
     const int r = e / pw, c0 = e % pw;
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_fwd_partial(Dims d, const float* __restr
   for (int s = 0; s < TPW; ++s) {
     int id = w + 4 * s, ti, tj;
     if (id >= d.ntiles) id = 0;
-    tile_of(id, d.KT, d.MT, ti, tj);
+    tile_of(id, d.KT, d.MT, d.gt, ti, tj);
     pa[s] = X + (d.mp + 16 * ti + lc) * xs + 16 * lg;
     pb[s] = X + (16 * tj + lc) * xs + 16 * lg;
     acc[s] = f4{0.f, 0.f, 0.f, 0.f};
@@ -285,7 +296,7 @@ __global__ __launch_bounds__(NTF) void k_fwd_finish(Dims d, const double* __rest
   for (int e = t; e < nel; e += NTF) {
     const int id = e >> 8, v = (e >> 6) & 3, lane = e & 63;
     int ti, tj;
-    tile_of(id, d.KT, d.MT, ti, tj);
+    tile_of(id, d.KT, d.MT, d.gt, ti, tj);
     T[(16 * ti + 4 * (lane >> 4) + v) * tcs + 16 * tj + (lane & 15)] = tb[e];
   }
   if (t == 0) {
@@ -372,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_bwd(Dims d, const float* __restrict__ P,
   float* X = lds;
   float* MT = lds + RB * xs;
   zero_padding<false>(d, X, xs);
-  const float g = gloss[b];
+  const float g = gloss ? gloss[b] : 1.f;
   const float* Mb = Msave + (int64_t)b * d.cols * d.kp;
   for (int e = threadIdx.x; e < d.cols * d.kp; e += NT) MT[(e % d.kp) * mts + e / d.kp] = g * Mb[e];
   const float* Bs = B + (int64_t)b * d.n * d.m;
@@ -414,6 +425,49 @@ __global__ __launch_bounds__(NT) void k_bwd(Dims d, const float* __restrict__ P,
   }
 }
 
+// ---------------------------------------------------- Galerkin product
+// Y = A_b P_b for a batch of operators that share kind and grid: sample b uses
+// coefficients coef + b * cstride (float32 products of the float64 stencil).
+__global__ __launch_bounds__(NT) void k_gal_apply(OpDev op, int64_t cstride, int k, FastDiv fk,
+                                                  const float* __restrict__ P, float* __restrict__ Y) {
+  const int b = blockIdx.y;
+  const uint32_t g = blockIdx.x * NT + threadIdx.x;
+  if ((int64_t)g >= op.n * k) return;
+  OpDev ob = op;
+  if (ob.coef) ob.coef += (int64_t)b * cstride;
+  const uint32_t i = fdiv(g, fk);
+  const int c = (int)(g - i * (uint32_t)k);
+  int px, py, pz;
+  decompose(ob, i, px, py, pz);
+  const float* Pb = P + (int64_t)b * op.n * k;
+  Y[(int64_t)b * op.n * k + g] = op_row<float>(ob, i, px, py, pz, [&](int64_t j) { return Pb[j * k + c]; });
+}
+
+// A_c = (T + T^T) / 2 from the slab sums of T = P^T Y (tiles row-major, no G)
+__global__ __launch_bounds__(NT) void k_gal_finish(Dims d, const double* __restrict__ T64, float* __restrict__ Ac) {
+  const int b = blockIdx.x;
+  const double* tb = T64 + (int64_t)b * d.ntiles * 256;
+  auto at = [&](int i, int j) {
+    const int id = (i >> 4) * d.MT + (j >> 4), r = i & 15;
+    return tb[id * 256 + (r & 3) * 64 + (r >> 2) * 16 + (j & 15)];
+  };
+  for (int e = threadIdx.x; e < d.k * d.k; e += NT) {
+    const int i = e / d.k, j = e % d.k;
+    Ac[(int64_t)b * d.k * d.k + e] = (float)(0.5 * (at(i, j) + at(j, i)));
+  }
+}
+
+// M = G + G^T (kp x kp, zero padded) for the Galerkin backward
+__global__ __launch_bounds__(NT) void k_gal_bwd_prep(int k, int kp, const float* __restrict__ gAc,
+                                                     float* __restrict__ M) {
+  const int b = blockIdx.x;
+  const float* G = gAc + (int64_t)b * k * k;
+  for (int e = threadIdx.x; e < kp * kp; e += NT) {
+    const int i = e / kp, j = e % kp;
+    M[(int64_t)b * kp * kp + e] = (i < k && j < k) ? G[i * k + j] + G[j * k + i] : 0.f;
+  }
+}
+
 struct SubLayout {
   float* part;
   double* bbpart;
@@ -451,6 +505,26 @@ inline bool dims_ok(int batch, int n, int k, int m) {
          bwd_lds(d) <= LDS_MAX;
 }
 
+// Galerkin product: forward T = P^T [Y | P] over the tiles of P^T Y only,
+// backward [Y] (G + G^T); k <= 64, n k < 2^31 per sample
+inline Dims gal_fwd_dims(int batch, int n, int k) { return make_dims(batch, n, k, k, false, true); }
+inline Dims gal_bwd_dims(int batch, int n, int k) { return make_dims(batch, n, k, k, false, false); }
+inline bool gal_ok(int batch, int64_t n, int k) {
+  if (batch < 1 || n < 1 || k < 1 || k > 64 || n * k >= (int64_t(1) << 31)) return false;
+  const Dims d = gal_fwd_dims(batch, (int)n, k);
+  return d.ntiles <= MAX_TILES && fwd_lds(d) <= LDS_MAX && bwd_lds(gal_bwd_dims(batch, (int)n, k)) <= LDS_MAX;
+}
+
+// coefficient values per sample of a batched operator
+inline int64_t coef_stride(const nlsp_operator& a, int64_t n) {
+  switch (a.kind) {
+    case NLSP_OP_FV5:
+    case NLSP_OP_FV7: return n;
+    case NLSP_OP_STENCIL9: return 9;
+    default: return 0;
+  }
+}
+
 template <typename K>
 inline hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -463,31 +537,9 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
 using namespace nlsp;
 using namespace nlsp::sub;
 
-extern "C" {
-
-size_t subspace_loss_saved_bytes(int batch, int n, int k, int m) {
-  if (!dims_ok(batch, n, k, m)) return 0;
-  return saved_bytes(batch, make_dims(batch, n, k, m));
-}
-
-size_t subspace_loss_workspace_bytes(int batch, int n, int k, int m) {
-  if (!dims_ok(batch, n, k, m)) return 0;
-  return carve_sub(nullptr, batch, make_dims(batch, n, k, m)).bytes;
-}
-
-int subspace_loss_fwd(int batch, int n, int k, int m, const float* P, const float* B, const float* colw,
-                      float* loss, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes, void* stream) {
-  if (!dims_ok(batch, n, k, m) || !P || !B || !loss || !saved) return NLSP_E_INVALID;
-  Dims d = make_dims(batch, n, k, m);
-  if (reinterpret_cast<uintptr_t>(P) % 16 || reinterpret_cast<uintptr_t>(B) % 16) d.vec = 0;
-  if (saved_nbytes < saved_bytes(batch, d) || reinterpret_cast<uintptr_t>(saved) % WS_ALIGN)
-    return NLSP_E_WORKSPACE;
-  const size_t need = carve_sub(nullptr, batch, d).bytes;
-  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
-  const SubLayout L = carve_sub(ws, batch, d);
-  hipStream_t s = as_stream(stream);
-  double* loss64 = static_cast<double*>(saved);
-  float* Msave = reinterpret_cast<float*>(static_cast<char*>(saved) + align_up((size_t)batch * sizeof(double)));
+// forward product partials + slab sums (shared by both forward passes)
+inline int launch_products(const Dims& d, int batch, const float* P, const float* B, const SubLayout& L,
+                           hipStream_t s) {
   const dim3 grid(d.nslab, batch);
   const size_t lds = fwd_lds(d);
   const int tpw = (d.ntiles + 3) / 4;
@@ -513,27 +565,17 @@ int subspace_loss_fwd(int batch, int n, int k, int m, const float* P, const floa
   if (rc != NLSP_OK) return rc;
   hipLaunchKernelGGL(k_fwd_reduce, dim3(ceil_div((int64_t)d.ntiles * 256, NT), batch), dim3(NT), 0, s, d, L.part,
                      L.T64);
-  NLSP_HIP(allow_lds(k_fwd_finish, fin_lds(d)));
-  hipLaunchKernelGGL(k_fwd_finish, dim3(batch), dim3(NTF), fin_lds(d), s, d, L.T64, L.bbpart, colw, loss, loss64,
-                     Msave);
-  NLSP_HIP(hipGetLastError());
   return NLSP_OK;
 }
 
-int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const float* B, const void* saved,
-                      size_t saved_nbytes, const float* gloss, float* gP, void* stream) {
-  if (!dims_ok(batch, n, k, m) || !P || !B || !saved || !gloss || !gP) return NLSP_E_INVALID;
-  Dims d = make_dims(batch, n, k, m);
-  if (reinterpret_cast<uintptr_t>(P) % 16 || reinterpret_cast<uintptr_t>(B) % 16) d.vec = 0;
-  if (saved_nbytes < saved_bytes(batch, d)) return NLSP_E_WORKSPACE;
-  const float* Msave =
-      reinterpret_cast<const float*>(static_cast<const char*>(saved) + align_up((size_t)batch * sizeof(double)));
-  hipStream_t s = as_stream(stream);
+// [B | P] M per row slab (shared by both backward passes); gloss may be null
+inline int launch_bwd(const Dims& d, int batch, const float* P, const float* B, const float* M,
+                      const float* gloss, float* gP, hipStream_t s) {
   const size_t lds = bwd_lds(d);
   int rc = NLSP_OK;
   auto go = [&](auto kern) {
     if (allow_lds(kern, lds) != hipSuccess) { rc = NLSP_E_HIP; return; }
-    hipLaunchKernelGGL(kern, dim3(d.nslab, batch), dim3(NT), lds, s, d, P, B, Msave, gloss, gP);
+    hipLaunchKernelGGL(kern, dim3(d.nslab, batch), dim3(NT), lds, s, d, P, B, M, gloss, gP);
   };
   auto pick = [&](auto vec) {
     constexpr bool V = decltype(vec)::value;
@@ -545,6 +587,103 @@ int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const floa
     }
   };
   if (d.vec) pick(std::true_type{}); else pick(std::false_type{});
+  return rc;
+}
+
+inline bool aligned16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
+extern "C" {
+
+size_t subspace_loss_saved_bytes(int batch, int n, int k, int m) {
+  if (!dims_ok(batch, n, k, m)) return 0;
+  return saved_bytes(batch, make_dims(batch, n, k, m));
+}
+
+size_t subspace_loss_workspace_bytes(int batch, int n, int k, int m) {
+  if (!dims_ok(batch, n, k, m)) return 0;
+  return carve_sub(nullptr, batch, make_dims(batch, n, k, m)).bytes;
+}
+
+int subspace_loss_fwd(int batch, int n, int k, int m, const float* P, const float* B, const float* colw,
+                      float* loss, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes, void* stream) {
+  if (!dims_ok(batch, n, k, m) || !P || !B || !loss || !saved) return NLSP_E_INVALID;
+  Dims d = make_dims(batch, n, k, m);
+  if (!aligned16(P) || !aligned16(B)) d.vec = 0;
+  if (saved_nbytes < saved_bytes(batch, d) || reinterpret_cast<uintptr_t>(saved) % WS_ALIGN)
+    return NLSP_E_WORKSPACE;
+  const size_t need = carve_sub(nullptr, batch, d).bytes;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const SubLayout L = carve_sub(ws, batch, d);
+  hipStream_t s = as_stream(stream);
+  double* loss64 = static_cast<double*>(saved);
+  float* Msave = reinterpret_cast<float*>(static_cast<char*>(saved) + align_up((size_t)batch * sizeof(double)));
+  const int rc = launch_products(d, batch, P, B, L, s);
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(allow_lds(k_fwd_finish, fin_lds(d)));
+  hipLaunchKernelGGL(k_fwd_finish, dim3(batch), dim3(NTF), fin_lds(d), s, d, L.T64, L.bbpart, colw, loss, loss64,
+                     Msave);
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const float* B, const void* saved,
+                      size_t saved_nbytes, const float* gloss, float* gP, void* stream) {
+  if (!dims_ok(batch, n, k, m) || !P || !B || !saved || !gloss || !gP) return NLSP_E_INVALID;
+  Dims d = make_dims(batch, n, k, m);
+  if (!aligned16(P) || !aligned16(B)) d.vec = 0;
+  if (saved_nbytes < saved_bytes(batch, d)) return NLSP_E_WORKSPACE;
+  const float* Msave =
+      reinterpret_cast<const float*>(static_cast<const char*>(saved) + align_up((size_t)batch * sizeof(double)));
+  const int rc = launch_bwd(d, batch, P, B, Msave, gloss, gP, as_stream(stream));
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+size_t galerkin_fwd_workspace_bytes(int batch, const nlsp_operator* A, int k) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !gal_ok(batch, n, k)) return 0;
+  return carve_sub(nullptr, batch, gal_fwd_dims(batch, (int)n, k)).bytes;
+}
+
+int galerkin_fwd(int batch, const nlsp_operator* A, const float* P, int k, float* Ac, float* Y, void* ws,
+                 size_t ws_bytes, void* stream) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !gal_ok(batch, n, k) || !P || !Ac || !Y || P == Y) return NLSP_E_INVALID;
+  Dims d = gal_fwd_dims(batch, (int)n, k);
+  if (!aligned16(P) || !aligned16(Y)) d.vec = 0;
+  const size_t need = carve_sub(nullptr, batch, d).bytes;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const SubLayout L = carve_sub(ws, batch, d);
+  hipStream_t s = as_stream(stream);
+  const OpDev op = make_op(*A);
+  hipLaunchKernelGGL(k_gal_apply, dim3(ceil_div(n * k, NT), batch), dim3(NT), 0, s, op, coef_stride(*A, n), k,
+                     make_fastdiv((uint32_t)k), P, Y);
+  // T = P^T [Y | P], tiles of P^T Y only: Y is the "B" block, P the "P" block
+  const int rc = launch_products(d, batch, P, Y, L, s);
+  if (rc != NLSP_OK) return rc;
+  hipLaunchKernelGGL(k_gal_finish, dim3(batch), dim3(NT), 0, s, d, L.T64, Ac);
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+size_t galerkin_bwd_workspace_bytes(int batch, int n, int k) {
+  if (!gal_ok(batch, n, k)) return 0;
+  return align_up((size_t)batch * round16(k) * round16(k) * sizeof(float));
+}
+
+int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, float* gP, void* ws, size_t ws_bytes,
+                 void* stream) {
+  if (!gal_ok(batch, n, k) || !Y || !gAc || !gP || Y == gP) return NLSP_E_INVALID;
+  Dims d = gal_bwd_dims(batch, n, k);
+  if (!aligned16(Y)) d.vec = 0;
+  const size_t need = galerkin_bwd_workspace_bytes(batch, n, k);
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  float* M = static_cast<float*>(ws);
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(k_gal_bwd_prep, dim3(batch), dim3(NT), 0, s, k, d.kp, gAc, M);
+  // gP = [Y] (G + G^T): Y is the "B" block, no P block
+  const int rc = launch_bwd(d, batch, Y, Y, M, nullptr, gP, s);
   if (rc != NLSP_OK) return rc;
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;

@@ -178,29 +178,95 @@ def main():
         s64, p64, inf64 = step(nl.FP64)
         out["fp64"] = {"setup_ms": round(s64, 4), "solve_ms": round(p64, 4), "iters": inf64.iters,
                        "relres": inf64.relres}
-        # stand-alone float64 SpMV y = A x, 16 right-hand sides (useful bytes:
-        # x and y once, coefficient once)
-        R = 16
-        x = torch.randn(n, R, dtype=torch.float64, device=dev)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            nl.apply_operator(op, x, y)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        ev0.record()
-        for _ in range(reps):
-            nl.apply_operator(op, x, y)
-        ev1.record()
-        torch.cuda.synchronize()
-        sp_ms = ev0.elapsed_time(ev1) / reps
-        sp_bytes = n * (16 * R + 8)
-        out["spmv_f64"] = {"R": R, "ms": round(sp_ms, 5), "GBs": round(sp_bytes / sp_ms / 1e6, 1),
-                           "frac": round(sp_bytes / sp_ms / 1e6 / HBM_PEAK_GBS, 4)}
+        out["spmv"] = spmv_legs(nl, torch, dev)
+        out["training"] = training_legs(nl, torch, dev)
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, coef, S0h, fh, out.get("fp64", {}).get("iters", out["iters"]))
     print(json.dumps(out), flush=True)
+
+
+def _time_ms(torch, fn, reps=20, warm=3):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def spmv_legs(nl, torch, dev):
+    """Stand-alone operator kernels on the 3-D workload (FV7, 128^3 cells,
+    16^3-cell blocks of a in {1, 1e3}, 16 right-hand sides; the working set
+    exceeds the 256 MB last-level cache):
+      float64 y = A x           useful bytes n (16 R + 8)
+      float32 Jacobi sweep      useful bytes n (12 R + 8)
+    and a plain device copy of 1 GiB for the achievable read+write rate."""
+    import workloads as W
+    c4 = W.Cfg4()
+    N, R = c4.N, c4.R
+    n = N ** 3
+    op = nl.Operator(nl.OP_FV7, N, N, N, torch.tensor(c4.coef().ravel(), dtype=torch.float64, device=dev))
+    res = {"workload": f"FV7 {N}^3 (n={n}), R={R}"}
+    x = torch.randn(n, R, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    ms = _time_ms(torch, lambda: nl.apply_operator(op, x, y))
+    by = n * (16 * R + 8)
+    res["f64_apply"] = {"ms": round(ms, 4), "GBs": round(by / ms / 1e6, 1), "frac": round(by / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del x, y
+    b32 = torch.randn(n, R, dtype=torch.float32, device=dev)
+    x32 = torch.randn(n, R, dtype=torch.float32, device=dev)
+    y32 = torch.empty_like(x32)
+    ms = _time_ms(torch, lambda: nl.jacobi_sweep_f32(op, 2.0 / 3.0, b32, x32, y32))
+    by = n * (12 * R + 8)
+    res["f32_jacobi"] = {"ms": round(ms, 4), "GBs": round(by / ms / 1e6, 1),
+                         "frac": round(by / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del b32, x32, y32
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = _time_ms(torch, lambda: dst.copy_(src))
+    res["copy_1GiB_GBs"] = round(2 * (1 << 30) / ms / 1e6, 1)
+    for key in ("f64_apply", "f32_jacobi"):
+        res[key]["of_copy"] = round(res[key]["GBs"] / res["copy_1GiB_GBs"], 4)
+    return res
+
+
+def training_legs(nl, torch, dev):
+    """Differentiable products on the training workload (64 log-normal fields
+    of 128^2 cells, k = 32, m = 64 relaxed vectors per field): subspace loss
+    and Galerkin product, forward and backward (float32 MFMA)."""
+    import workloads as W
+    c5 = W.Cfg5()
+    batch, n, k, m = c5.batch, c5.N * c5.N, c5.k, c5.m
+    g = torch.Generator(device=dev).manual_seed(5000)
+    P = torch.randn(batch, n, k, device=dev, generator=g) / n ** 0.5
+    B = torch.randn(batch, n, m, device=dev, generator=g)
+    ones = torch.ones(batch, device=dev)
+    res = {"workload": f"{batch} x FV5 {c5.N}^2, k={k}, m={m}"}
+    ws = torch.empty(nl.subspace_loss_workspace_bytes(batch, n, k, m), dtype=torch.uint8, device=dev)
+    _, saved = nl.subspace_loss_fwd(P, B, workspace=ws)
+    gP = torch.empty_like(P)
+    f_ms = _time_ms(torch, lambda: nl.subspace_loss_fwd(P, B, workspace=ws))
+    b_ms = _time_ms(torch, lambda: nl.subspace_loss_bwd(P, B, saved, ones, gP))
+    fb = batch * n * (m + k) * 4
+    flop = 2.0 * batch * n * k * (m + k)
+    res["subspace_loss"] = {"fwd_ms": round(f_ms, 4), "bwd_ms": round(b_ms, 4),
+                            "fwd_GBs": round(fb / f_ms / 1e6, 1), "bwd_GBs": round((fb + batch * n * k * 4) / b_ms / 1e6, 1),
+                            "fwd_TFLOPs": round(flop / f_ms / 1e9, 2), "bwd_TFLOPs": round(flop / b_ms / 1e9, 2)}
+    coefs = torch.tensor(np.concatenate([c5.coef(i).ravel() for i in range(batch)]), dtype=torch.float64, device=dev)
+    op = nl.Operator(nl.OP_FV5, c5.N, c5.N, 1, coefs)
+    Ac, Y = nl.galerkin_fwd(op, P)
+    gAc = torch.randn(batch, k, k, device=dev, generator=g)
+    f_ms = _time_ms(torch, lambda: nl.galerkin_fwd(op, P))
+    b_ms = _time_ms(torch, lambda: nl.galerkin_bwd(Y, gAc))
+    res["galerkin"] = {"fwd_ms": round(f_ms, 4), "bwd_ms": round(b_ms, 4),
+                       "fwd_GBs": round(batch * n * (4 * k * 4 + 8) / f_ms / 1e6, 1),
+                       "bwd_GBs": round(batch * n * 2 * k * 4 / b_ms / 1e6, 1)}
+    return res
 
 
 def counter_traffic(kname: str, N: int, k: int):

@@ -176,6 +176,16 @@ NLSP_DEV void decompose(const OpDev& op, int64_t i, int& x, int& y, int& z) {
   x = (int)(rem - yy * op.fx.d);
 }
 
+// Logical block index for a launch of nb blocks so that consecutive logical
+// blocks run on the same XCD: the hardware deals blocks round-robin over the
+// 8 XCDs (block b on XCD b % 8), so XCD x receives the contiguous logical range
+// [start_x, start_x + count_x).  Keeps stencil neighbours in one L2.
+NLSP_DEV int xcd_remap(int b, int nb) {
+  const int x = b & 7, q = nb >> 3, rem = nb & 7;
+  const int start = x * q + (x < rem ? x : rem);
+  return start + (b >> 3);
+}
+
 // ---------------------------------------------------------------- reductions
 template <typename T>
 NLSP_DEV T wave_sum(T v) {

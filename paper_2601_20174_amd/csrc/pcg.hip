@@ -89,12 +89,6 @@ struct SysDev {
 // XCD-aware order: hardware places workgroup b on XCD b % 8; give each XCD a
 // contiguous range of logical blocks so that stencil halos are served from
 // that XCD's L2.
-NLSP_DEV int xcd_remap(int b, int nb) {
-  const int x = b & 7, q = nb >> 3, rem = nb & 7;
-  const int start = x * q + (x < rem ? x : rem);
-  return start + (b >> 3);
-}
-
 NLSP_DEV const SysDev& my_sys(const SysDev* sys, const int* blk2sys, int nsys) {
   return sys[nsys == 1 ? 0 : blk2sys[blockIdx.x]];
 }

@@ -21,9 +21,17 @@ def nl():
     return mod
 
 
-@pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("R", [1, 3, 16])
+@pytest.mark.parametrize("kind", KINDS + ["poisson_big"])
+@pytest.mark.parametrize("R", [1, 2, 3, 16])
 def test_apply_operator(nl, kind, R):
+    if kind == "poisson_big":   # several slabs of y-lines, lines split over blocks
+        A, op, n = make_case("poisson", 1, (300, 70))
+        x = np.random.default_rng(2).standard_normal((n, R))
+        y = host(nl.apply_operator(op, cuda(x)))
+        ref = A @ x
+        scale = abs(A).sum(axis=1).A.ravel()[:, None] * np.abs(x).max()
+        assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+        return
     A, op, n = make_case(kind, 1, (37, 29) if kind != "q1" else (41, 41))
     x = np.random.default_rng(2).standard_normal((n, R))
     y = host(nl.apply_operator(op, cuda(x)))
@@ -43,11 +51,12 @@ def test_q1_stencil_matches_oracle_assembly(nl):
         np.testing.assert_allclose(st[s].reshape(3, 3), row[1:4, 1:4], atol=1e-14)
 
 
-@pytest.mark.parametrize("kind", ["fv5", "q1"])
-def test_jacobi_sweep_f32(nl, kind):
+@pytest.mark.parametrize("kind", ["fv5", "q1", "fv7", "poisson"])
+@pytest.mark.parametrize("R", [2, 8])
+def test_jacobi_sweep_f32(nl, kind, R):
     A, op, n = make_case(kind, 4, (33, 20) if kind != "q1" else (30, 30))
     rng = np.random.default_rng(5)
-    b, x = rng.standard_normal((n, 2)), rng.standard_normal((n, 2))
+    b, x = rng.standard_normal((n, R)), rng.standard_normal((n, R))
     y = host(nl.jacobi_sweep_f32(op, 2 / 3, cuda(b, torch.float32), cuda(x, torch.float32)))
     D = A.diagonal()[:, None]
     xr = x.astype(np.float32).astype(np.float64)

@@ -211,6 +211,45 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
               int R, const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws,
               size_t ws_bytes, void* stream);
 
+/* One system of a batch: its operator, its two-level preconditioner (from
+ * setup_spectral_P + galerkin_coarse) and its right-hand sides. */
+typedef struct {
+  nlsp_operator A;
+  nlsp_two_level M;      /* k, nu and prec must be equal across the batch */
+  const double* f;       /* device (n_i, R) float64 */
+  double* u;             /* device (n_i, R) float64: initial guess in, solution out */
+} nlsp_system;
+
+size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R, int rows_per_block);
+
+/* pcg_solve for a batch of independent systems of different sizes, each with
+ * R right-hand sides, in the same kernel launches: every iteration is one
+ * launch of each solver kernel over the workgroups of all systems (a system
+ * whose right-hand sides have stopped exits at once).  Without opts->timing
+ * the check_every iterations between host polls (made even) are captured
+ * once in a hipGraph and replayed.
+ *   sys             host array of nsys descriptors
+ *   rows_per_block  rows of a system per workgroup (0 = one workgroup per
+ *                   NT / R rows, capped at 512 per system); pick it with
+ *                   pcg_solve_batched_tune
+ *   info            host array of nsys * R records, system-major
+ * Returns the worst per-RHS status.  Synchronises `stream`. */
+int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_block,
+                      const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Autotuner of the batched solve's tile (rows of a system per workgroup):
+ * times `iters` iterations of pcg_solve_batched (on copies of the initial
+ * guesses held in the workspace; the caller's u is not modified) for each
+ * candidate of pcg_solve_batched_tune_candidates and returns the fastest.
+ *   ms  host array of candidate times (ms), or NULL
+ * Synchronises `stream`. */
+int pcg_solve_batched_tune_candidates(int R, int* rows_per_block);
+size_t pcg_solve_batched_tune_workspace_bytes(int nsys, const nlsp_system* sys, int R);
+int pcg_solve_batched_tune(int nsys, const nlsp_system* sys, int R, const nlsp_pcg_opts* opts,
+                           int iters, int* best_rows_per_block, double* ms, void* ws,
+                           size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------- training losses */
 /* Subspace loss of a batch of predicted bases against relaxed samples (Sec. 4,
  * projected energy eq. subspace_energy and the NLSS loss eq. nlss_loss; the

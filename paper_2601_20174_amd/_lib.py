@@ -34,6 +34,10 @@ class NlspPcgOpts(ctypes.Structure):
                 ("timing", ctypes.POINTER(NlspKernelTiming))]
 
 
+class NlspSystem(ctypes.Structure):
+    _fields_ = [("A", NlspOperator), ("M", NlspTwoLevel), ("f", c_void_p), ("u", c_void_p)]
+
+
 class NlspRhsInfo(ctypes.Structure):
     _fields_ = [("iters", c_int), ("status", c_int), ("relres", c_double)]
 
@@ -68,6 +72,14 @@ SIGNATURES = {
     "galerkin_fwd": (c_int, [c_int, POP, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "galerkin_bwd_workspace_bytes": (c_size_t, [c_int, c_int, c_int]),
     "galerkin_bwd": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pcg_solve_batched_workspace_bytes": (c_size_t, [c_int, ctypes.POINTER(NlspSystem), c_int, c_int]),
+    "pcg_solve_batched": (c_int, [c_int, ctypes.POINTER(NlspSystem), c_int, c_int, ctypes.POINTER(NlspPcgOpts),
+                                  ctypes.POINTER(NlspRhsInfo), c_void_p, c_size_t, c_void_p]),
+    "pcg_solve_batched_tune_candidates": (c_int, [c_int, ctypes.POINTER(c_int)]),
+    "pcg_solve_batched_tune_workspace_bytes": (c_size_t, [c_int, ctypes.POINTER(NlspSystem), c_int]),
+    "pcg_solve_batched_tune": (c_int, [c_int, ctypes.POINTER(NlspSystem), c_int, ctypes.POINTER(NlspPcgOpts),
+                                       c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_void_p,
+                                       c_size_t, c_void_p]),
 }
 
 _LIB = None

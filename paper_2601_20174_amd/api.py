@@ -371,3 +371,81 @@ class GalerkinProduct(torch.autograd.Function):
 
 def galerkin_product(P: torch.Tensor, op: Operator) -> torch.Tensor:
     return GalerkinProduct.apply(P, op)
+
+
+# ------------------------------------------------------------ batched solve
+@dataclasses.dataclass
+class System:
+    """One system of a batch: operator, its two-level factors, right-hand
+    sides f (n, R) and solution u (n, R), float64 GPU tensors."""
+    op: Operator
+    M: TwoLevel
+    f: torch.Tensor
+    u: torch.Tensor
+
+
+def _systems(systems: List[System], prec: int):
+    arr = (_lib.NlspSystem * len(systems))()
+    R = None
+    for i, s in enumerate(systems):
+        f2 = s.f.reshape(s.f.shape[0], -1)
+        if R is None:
+            R = f2.shape[1]
+        if f2.shape[1] != R or s.u.numel() != f2.numel():
+            raise ValueError("every system needs the same number of right-hand sides, u shaped like f")
+        arr[i] = _lib.NlspSystem(s.op.c(), s.M.c(prec), _dev(s.f, torch.float64, "f"),
+                                 _dev(s.u, torch.float64, "u"))
+    return arr, R
+
+
+def _opts(rtol, maxit, flexible, check_every):
+    return _lib.NlspPcgOpts(float(rtol), int(maxit), 1 if flexible else 0, int(check_every), None)
+
+
+def pcg_solve_batched_workspace_bytes(systems: List[System], prec: int, rows_per_block: int = 0) -> int:
+    arr, R = _systems(systems, prec)
+    return int(_L().pcg_solve_batched_workspace_bytes(len(systems), arr, R, int(rows_per_block)))
+
+
+def pcg_solve_batched(systems: List[System], prec: int = MIXED, rtol: float = 1e-8, maxit: int = 10000,
+                      flexible: Optional[bool] = None, check_every: int = 32, rows_per_block: int = 0,
+                      workspace: Optional[torch.Tensor] = None):
+    """Solves every system in place (s.u); returns ([[RhsInfo] per system], status)."""
+    arr, R = _systems(systems, prec)
+    if flexible is None:
+        flexible = prec == MIXED
+    nb = _L().pcg_solve_batched_workspace_bytes(len(systems), arr, R, int(rows_per_block))
+    if nb == 0:
+        raise NlspError("pcg_solve_batched_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(nb, systems[0].f.device)
+    info = (_lib.NlspRhsInfo * (len(systems) * R))()
+    opts = _opts(rtol, maxit, flexible, check_every)
+    rc = _L().pcg_solve_batched(len(systems), arr, R, int(rows_per_block), ctypes.byref(opts), info,
+                                ws.data_ptr(), ws.numel(), _stream())
+    _check("pcg_solve_batched", rc, allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    out = [[RhsInfo(info[i * R + c].iters, info[i * R + c].status, info[i * R + c].relres) for c in range(R)]
+           for i in range(len(systems))]
+    return out, rc
+
+
+def pcg_solve_batched_tune(systems: List[System], prec: int = MIXED, rtol: float = 1e-8, iters: int = 16,
+                           flexible: Optional[bool] = None):
+    """Times `iters` iterations per candidate tile (u is left untouched);
+    returns (best rows_per_block, {rows_per_block: ms})."""
+    arr, R = _systems(systems, prec)
+    if flexible is None:
+        flexible = prec == MIXED
+    ncand = _L().pcg_solve_batched_tune_candidates(R, None)
+    cand = (ctypes.c_int * ncand)()
+    _L().pcg_solve_batched_tune_candidates(R, cand)
+    nb = _L().pcg_solve_batched_tune_workspace_bytes(len(systems), arr, R)
+    if nb == 0:
+        raise NlspError("pcg_solve_batched_tune_workspace_bytes", E_INVALID)
+    ws = _workspace(nb, systems[0].f.device)
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * ncand)()
+    opts = _opts(rtol, 10000, flexible, iters)
+    rc = _L().pcg_solve_batched_tune(len(systems), arr, R, ctypes.byref(opts), int(iters), ctypes.byref(best), ms,
+                                     ws.data_ptr(), ws.numel(), _stream())
+    _check("pcg_solve_batched_tune", rc)
+    return best.value, {int(cand[i]): float(ms[i]) for i in range(ncand)}

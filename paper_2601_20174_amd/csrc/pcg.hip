@@ -28,6 +28,8 @@
 // kernel B writes stat[(it + 1) & 1].
 // Vectors and every reduction are float64; in the mixed form Q, the smoother
 // and the prolongation products are float32.
+#include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <vector>
 
@@ -84,6 +86,7 @@ struct SysDev {
   double* rr_true;         // [R]
   double omega, tol2;
   int maxit, flexible, nu;
+  unsigned rmask;          // RHS a restart launch applies to (ANDed with the launch mask)
 };
 
 // XCD-aware order: hardware places workgroup b on XCD b % 8; give each XCD a
@@ -507,6 +510,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
   __shared__ double red[4 * NT + 128];
   __shared__ double outv[MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
+  mask &= S.rmask;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
   const bool on = (mask >> c) & 1u;
@@ -698,6 +702,7 @@ __global__ __launch_bounds__(NT, 4) void k_iter_b(const SysDev* __restrict__ sys
   __shared__ int s_upd[MAXR], s_next[MAXR];
   __shared__ IterScalars sc;
   const SysDev& S = my_sys(sys, blk2sys, nsys);
+  mask &= S.rmask;
   const int nxt = (it + 1) & 1;
   const int KR = S.kp * S.R;
   if (!restart && S.nact[it & 1] == 0) {
@@ -905,20 +910,42 @@ __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
 }
 
 // ------------------------------------------------------------- host side
+// ------------------------------------------------------------------ host side
+// Per-system buffers.  The arrays that must start at zero come first and are
+// carved for every system of a batch before anything else, so one fill clears
+// them all.
 struct SolveLayout {
-  double *r0, *r1, *p0, *p1, *q, *z, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *etop, *estate0, *estate1,
-      *dpart, *Ainv, *rr_true;
+  double *p0, *p1, *q, *z, *estate0, *estate1;
+  unsigned* ticket;
+  double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *etop, *dpart, *Ainv;
   float* dinv32;
   void *w0, *w1;
+};
+
+// Arrays shared by the systems of a batch (contiguous, so the host reads or
+// writes them with one copy): per-RHS status by parity, true residuals,
+// counters [nact(0), nact(1), active, -] per system, descriptors, block map.
+struct BatchLayout {
   RhsStatus *stat0, *stat1;
+  double* rr_true;
+  int* counters;
   SysDev* sysdev;
-  unsigned* ticket;
-  int* counters;  // [0..1] active RHS by parity, [2] host-visible copy
+  int* blk2sys;
+  char* zero_begin;
+  size_t zero_bytes;
   size_t bytes;
 };
 
-// Workgroups per solver launch: one per chunk up to a cap (NLSP_SOLVER_BLOCKS
-// overrides the cap, for tuning).
+struct SysShape {
+  int64_t n;
+  int kp, R, nblk;
+  int64_t nchunks;
+  int chunk_rows;
+};
+
+// Workgroups per system: one per chunk of NT / R rows up to a cap (512 for a
+// single system, NLSP_SOLVER_BLOCKS overrides it for tuning), or, in a batch,
+// one per `rows_per_block` rows.
 inline int solver_blocks(int64_t nchunks) {
   int cap = 512;
   if (const char* e = std::getenv("NLSP_SOLVER_BLOCKS")) {
@@ -930,223 +957,94 @@ inline int solver_blocks(int64_t nchunks) {
 
 inline int restriction_width(int kp, int R) { return kp * R + 2 * R; }
 
-inline SolveLayout carve_solve(void* ws, int64_t n, int kp, int R, int nblk) {
-  Carver cv(ws);
-  SolveLayout L;
-  const int rw = restriction_width(kp, R);
-  L.r0 = cv.take<double>(n * R);
-  L.r1 = cv.take<double>(n * R);
-  L.p0 = cv.take<double>(n * R);
-  L.p1 = cv.take<double>(n * R);
-  L.q = cv.take<double>(n * R);
-  L.z = cv.take<double>(n * R);
-  L.w0 = cv.take<double>(n * R);
-  L.w1 = cv.take<double>(n * R);
-  L.dinv = cv.take<double>(n);
-  L.dinv32 = cv.take<float>(n);
-  L.bpart0 = cv.take<double>((size_t)nblk * 3 * R);
-  L.bpart1 = cv.take<double>((size_t)nblk * 3 * R);
-  L.rpart = cv.take<double>((size_t)nblk * rw);
-  L.rgrp = cv.take<double>((size_t)ticket_groups(nblk) * rw);
-  L.etop = cv.take<double>(rw);
-  L.estate0 = cv.take<double>((size_t)kp * R);
-  L.estate1 = cv.take<double>((size_t)kp * R);
-  L.dpart = cv.take<double>((size_t)nblk * R);
-  L.Ainv = cv.take<double>((size_t)kp * kp);
-  L.rr_true = cv.take<double>(R);
-  L.stat0 = cv.take<RhsStatus>(R);
-  L.stat1 = cv.take<RhsStatus>(R);
-  L.sysdev = cv.take<SysDev>(1);
-  L.ticket = cv.take<unsigned>(ticket_words(nblk));
-  L.counters = cv.take<int>(4);
-  L.bytes = cv.bytes();
-  return L;
-}
-
-template <typename QT>
-static int run_pcg(const SysDev& hs, const SolveLayout& L, int R, const nlsp_pcg_opts* opts,
-                   nlsp_rhs_info* info, hipStream_t stream) {
-  const int nblk = hs.nblk;
-  const SysDev* dsys = L.sysdev;
-  const unsigned all = (1u << R) - 1u;
-  const dim3 grid(nblk), block(NT);
-  nlsp_kernel_timing* tm = opts->timing;
-  const int tphase = (tm && tm->phase >= 1 && tm->phase <= 2) ? tm->phase : 0;
-  const int tevery = tm ? std::max(1, tm->every) : 1;
-  std::vector<hipEvent_t> evs;
-  int64_t phase_launch[3] = {0, 0, 0};
-  // `launch(a, b)` enqueues one kernel with hipExtLaunchKernelGGL; a and b are
-  // the start/stop events of a timed launch, null otherwise
-  auto timed = [&](int ph, auto&& launch) {
-    const bool on = (ph == tphase) && (phase_launch[ph]++ % tevery == 0);
-    hipEvent_t a = nullptr, b = nullptr;
-    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-      launch(a, b);
-      evs.push_back(a);
-      evs.push_back(b);
-    } else {
-      if (a) (void)hipEventDestroy(a);
-      launch(nullptr, nullptr);
-    }
-  };
-  // J_{2nu} r_new (nu > 1) and kernel B of iteration `it`
-  auto launch_b = [&](int it, int restart, unsigned mask, int init) {
-    int wsrc = -1;
-    if (hs.nu > 1) {
-      const int rin = restart ? ((it + 1) & 1) : (it & 1);
-      hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, stream, dsys, nullptr, 1, it, restart, rin, 1, 0);
-      int src = 0;
-      for (int s = 1; s < 2 * hs.nu - 1; ++s) {
-        hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, stream, dsys, nullptr, 1, it, restart, rin, 0,
-                           src);
-        src ^= 1;
-      }
-      wsrc = src;
-    }
-    timed(2, [&](hipEvent_t a, hipEvent_t b) {
-      hipExtLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, stream, a, b, 0, dsys, nullptr, 1, it,
-                            restart, mask, init, wsrc);
-    });
-  };
-  auto finish_timing = [&]() {
-    if (tm) {
-      double tot = 0.0;
-      for (size_t i = 0; i + 1 < evs.size(); i += 2) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) tot += ms;
-      }
-      tm->total_ms = tot;
-      tm->launches = (int)(evs.size() / 2);
-    }
-    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-  };
-  hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs.op.n, NT)), block, 0, stream, hs.op, L.dinv, L.dinv32);
-  hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs.kp * hs.kp, 256)), dim3(256), 0, stream,
-                     hs.Linv, hs.kp, L.Ainv);
-  // start-up as iteration -1: r = f - A x into r[0], then kernel B in restart mode
-  hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, nullptr, 1, all, 0);
-  launch_b(-1, 1, all, 1);
-  NLSP_HIP(hipGetLastError());
-  std::vector<RhsStatus> hst(R);
-  NLSP_HIP(hipMemcpyAsync(hst.data(), L.stat0, sizeof(RhsStatus) * R, hipMemcpyDeviceToHost, stream));
-  NLSP_HIP(hipStreamSynchronize(stream));
-  unsigned zero_mask = 0;
-  for (int c = 0; c < R; ++c)
-    if (hst[c].ff == 0.0) zero_mask |= 1u << c;
-  if (zero_mask)
-    hipLaunchKernelGGL(k_zero_cols, dim3(ceil_div(hs.op.n * R, 256)), dim3(256), 0, stream, hs.x,
-                       hs.op.n, R, zero_mask);
-  const int every = std::max(1, opts->check_every);
-  int guard = 0;
-  int it = 0;  // next iteration index; stat[it & 1] is the current state
-  // every RHS stops by maxit iterations; the launch budget is a hard bound on
-  // the host loop in case the device-side bookkeeping were ever wrong
-  int64_t launched = 0;
-  const int64_t launch_cap = (int64_t)hs.maxit + 2 * every + 64;
-  for (;;) {
-    int h_active = 0;
-    NLSP_HIP(hipMemcpyAsync(&h_active, L.counters + 2, sizeof(int), hipMemcpyDeviceToHost, stream));
-    NLSP_HIP(hipStreamSynchronize(stream));
-    if (h_active > 0 && launched < launch_cap) {
-      for (int k = 0; k < every; ++k, ++it) {
-        timed(1, [&](hipEvent_t a, hipEvent_t b) {
-          hipExtLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, stream, a, b, 0, dsys, nullptr, 1, it);
-        });
-        launch_b(it, 0, 0u, 0);
-      }
-      launched += every;
-      NLSP_HIP(hipGetLastError());
-      continue;
-    }
-    // every RHS stopped: confirm the converged ones with the true residual
-    hipLaunchKernelGGL(k_true_residual, grid, block, 0, stream, dsys, nullptr, 1);
-    hipLaunchKernelGGL(k_true_finish, dim3(1), block, 0, stream, dsys);
-    NLSP_HIP(hipGetLastError());
-    RhsStatus* cur_d = (it & 1) ? L.stat1 : L.stat0;
-    std::vector<double> rrt(R);
-    NLSP_HIP(hipMemcpyAsync(hst.data(), cur_d, sizeof(RhsStatus) * R, hipMemcpyDeviceToHost, stream));
-    NLSP_HIP(hipMemcpyAsync(rrt.data(), L.rr_true, sizeof(double) * R, hipMemcpyDeviceToHost, stream));
-    NLSP_HIP(hipStreamSynchronize(stream));
-    unsigned redo = 0;
-    for (int c = 0; c < R; ++c) {
-      const RhsStatus& s = hst[c];
-      if (s.conv && s.ff > 0.0 && rrt[c] > hs.tol2 * s.ff && s.iters < hs.maxit) redo |= 1u << c;
-    }
-    if (!redo || ++guard > 16) {
-      int worst = NLSP_OK;
-      for (int c = 0; c < R; ++c) {
-        const RhsStatus& s = hst[c];
-        info[c].iters = s.iters;
-        info[c].status = s.status;
-        info[c].relres = (s.ff > 0.0) ? std::sqrt(rrt[c] / s.ff) : 0.0;
-        if (s.status < 0 && (worst >= 0 || s.status < worst)) worst = s.status;
-        if (s.status == NLSP_NOT_CONVERGED && worst == NLSP_OK) worst = NLSP_NOT_CONVERGED;
-      }
-      finish_timing();
-      return worst;
-    }
-    // residual replacement: r = f - A x for `redo` into r[it & 1] and those RHS
-    // restart from it (kernel B in restart mode as iteration it - 1, reading
-    // stat[(it - 1) & 1])
-    for (int c = 0; c < R; ++c)
-      if ((redo >> c) & 1u) hst[c].active = 1;
-    RhsStatus* prev_d = ((it - 1) & 1) ? L.stat1 : L.stat0;
-    NLSP_HIP(hipMemcpyAsync(prev_d, hst.data(), sizeof(RhsStatus) * R, hipMemcpyHostToDevice, stream));
-    const int nredo = __builtin_popcount(redo);
-    NLSP_HIP(hipMemcpyAsync(L.counters + ((it - 1) & 1), &nredo, sizeof(int), hipMemcpyHostToDevice,
-                            stream));
-    hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, nullptr, 1, redo, it & 1);
-    launch_b(it - 1, 1, redo, 0);
-    NLSP_HIP(hipGetLastError());
+inline SysShape shape_of(int64_t n, int kp, int R, int rows_per_block) {
+  SysShape h;
+  h.n = n;
+  h.kp = kp;
+  h.R = R;
+  h.chunk_rows = NT / R;
+  h.nchunks = (n + h.chunk_rows - 1) / h.chunk_rows;
+  if (rows_per_block <= 0) {
+    h.nblk = solver_blocks(h.nchunks);
+  } else {
+    const int64_t cpb = std::max<int64_t>(1, rows_per_block / h.chunk_rows);
+    h.nblk = (int)std::min<int64_t>((h.nchunks + cpb - 1) / cpb, 65536);
   }
+  return h;
 }
 
-}  // namespace nlsp
-
-using namespace nlsp;
-
-extern "C" {
-
-size_t pcg_solve_workspace_bytes(const nlsp_operator* A, int k, int R) {
-  const int64_t n = op_size(A);
-  const int kp = padded_rank(k);
-  if (n < 1 || kp < 0 || R < 1 || R > MAXR || kp * R > 2048 || n * R >= (int64_t(1) << 31)) return 0;
-  const int64_t nchunks = (n + NT / R - 1) / (NT / R);
-  return carve_solve(nullptr, n, kp, R, solver_blocks(nchunks)).bytes;
+inline void carve_zero(Carver& cv, const SysShape& h, SolveLayout& L) {
+  const int64_t nR = h.n * h.R;
+  L.p0 = cv.take<double>(nR);
+  L.p1 = cv.take<double>(nR);
+  L.q = cv.take<double>(nR);
+  L.z = cv.take<double>(nR);
+  L.estate0 = cv.take<double>((size_t)h.kp * h.R);
+  L.estate1 = cv.take<double>((size_t)h.kp * h.R);
+  L.ticket = cv.take<unsigned>(ticket_words(h.nblk));
 }
 
-int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, double* u, int R,
-              const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes,
-              void* stream_) {
-  const int64_t n = op_size(A);
-  if (n < 1 || !M || !f || !u || !opts || !info) return NLSP_E_INVALID;
-  if (R < 1 || R > MAXR || n * R >= (int64_t(1) << 31)) return NLSP_E_INVALID;
-  const int kp = padded_rank(M->k);
-  if (kp < 0 || M->nu < 1 || !(M->omega > 0) || !M->Linv) return NLSP_E_INVALID;
-  if (kp * R > 2048) return NLSP_E_INVALID;  // LDS staging of the coarse vectors
-  if (M->prec == NLSP_FP64 ? !M->Q64 : (M->prec == NLSP_MIXED ? !M->Q32 : true))
-    return NLSP_E_INVALID;
-  if (!(opts->rtol > 0) || opts->maxit < 1 || opts->check_every < 1) return NLSP_E_INVALID;
-  if ((int64_t)M->k > n) return NLSP_E_INVALID;
-  const int chunk_rows = NT / R;
-  const int64_t nchunks = (n + chunk_rows - 1) / chunk_rows;
-  const int nblk = solver_blocks(nchunks);
-  const SolveLayout L0 = carve_solve(nullptr, n, kp, R, nblk);
-  if (!ws_ok(ws, ws_bytes, L0.bytes)) return NLSP_E_WORKSPACE;
-  const SolveLayout L = carve_solve(ws, n, kp, R, nblk);
-  hipStream_t stream = as_stream(stream_);
+inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
+  const int64_t nR = h.n * h.R;
+  const int rw = restriction_width(h.kp, h.R);
+  L.r0 = cv.take<double>(nR);
+  L.r1 = cv.take<double>(nR);
+  L.w0 = cv.take<double>(nR);
+  L.w1 = cv.take<double>(nR);
+  L.dinv = cv.take<double>(h.n);
+  L.dinv32 = cv.take<float>(h.n);
+  L.bpart0 = cv.take<double>((size_t)h.nblk * 3 * h.R);
+  L.bpart1 = cv.take<double>((size_t)h.nblk * 3 * h.R);
+  L.rpart = cv.take<double>((size_t)h.nblk * rw);
+  L.rgrp = cv.take<double>((size_t)ticket_groups(h.nblk) * rw);
+  L.etop = cv.take<double>(rw);
+  L.dpart = cv.take<double>((size_t)h.nblk * h.R);
+  L.Ainv = cv.take<double>((size_t)h.kp * h.kp);
+}
 
+// Carves the whole workspace (base == nullptr: sizes only).  `Ls` receives the
+// per-system layouts when non-null.
+inline BatchLayout carve_batch(void* ws, const std::vector<SysShape>& sh, std::vector<SolveLayout>* Ls) {
+  const int nsys = (int)sh.size();
+  const int R = sh[0].R;
+  int64_t blocks = 0;
+  for (const auto& h : sh) blocks += h.nblk;
+  Carver cv(ws);
+  BatchLayout B;
+  B.stat0 = cv.take<RhsStatus>((size_t)nsys * R);
+  B.stat1 = cv.take<RhsStatus>((size_t)nsys * R);
+  B.rr_true = cv.take<double>((size_t)nsys * R);
+  B.counters = cv.take<int>((size_t)nsys * 4);
+  B.sysdev = cv.take<SysDev>(nsys);
+  B.blk2sys = cv.take<int>((size_t)std::max<int64_t>(1, blocks));
+  std::vector<SolveLayout> tmp(nsys);
+  const size_t z0 = align_up(cv.off);
+  for (int i = 0; i < nsys; ++i) carve_zero(cv, sh[i], tmp[i]);
+  const size_t z1 = align_up(cv.off);
+  for (int i = 0; i < nsys; ++i) carve_rest(cv, sh[i], tmp[i]);
+  B.zero_begin = cv.base ? cv.base + z0 : nullptr;
+  B.zero_bytes = z1 - z0;
+  B.bytes = cv.bytes();
+  if (Ls) *Ls = tmp;
+  return B;
+}
+
+// device descriptor of one system
+inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const double* f, double* u,
+                          const SysShape& h, const SolveLayout& L, const BatchLayout& B, int i, int blk0,
+                          const nlsp_pcg_opts* opts) {
   SysDev hs{};
-  hs.op = make_op(*A);
+  const int R = h.R;
+  hs.op = make_op(A);
   hs.R = R;
-  hs.kp = kp;
-  hs.nblk = nblk;
-  hs.blk0 = 0;
-  hs.chunk_rows = chunk_rows;
-  hs.nchunks = nchunks;
-  hs.rw = restriction_width(kp, R);
-  hs.Q = (M->prec == NLSP_FP64) ? (const void*)M->Q64 : (const void*)M->Q32;
-  hs.Linv = M->Linv;
+  hs.kp = h.kp;
+  hs.nblk = h.nblk;
+  hs.blk0 = blk0;
+  hs.chunk_rows = h.chunk_rows;
+  hs.nchunks = h.nchunks;
+  hs.rw = restriction_width(h.kp, R);
+  hs.Q = (M.prec == NLSP_FP64) ? (const void*)M.Q64 : (const void*)M.Q32;
+  hs.Linv = M.Linv;
   hs.Ainv = L.Ainv;
   hs.f = f;
   hs.x = u;
@@ -1169,19 +1067,265 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
   hs.estate[1] = L.estate1;
   hs.dpart = L.dpart;
   hs.ticket = L.ticket;
-  hs.stat[0] = L.stat0;
-  hs.stat[1] = L.stat1;
-  hs.nact = L.counters;
-  hs.n_active = L.counters + 2;
-  hs.rr_true = L.rr_true;
-  hs.nu = M->nu;
-  hs.omega = M->omega;
+  hs.stat[0] = B.stat0 + (size_t)i * R;
+  hs.stat[1] = B.stat1 + (size_t)i * R;
+  hs.nact = B.counters + 4 * i;
+  hs.n_active = B.counters + 4 * i + 2;
+  hs.rr_true = B.rr_true + (size_t)i * R;
+  hs.nu = M.nu;
+  hs.omega = M.omega;
   hs.tol2 = opts->rtol * opts->rtol;
   hs.maxit = opts->maxit;
   hs.flexible = opts->flexible ? 1 : 0;
+  hs.rmask = 0xffffffffu;
+  return hs;
+}
 
+// One solve of `nsys` systems (nsys = 1: pcg_solve).  Every system advances
+// in the same launches; a system whose right-hand sides have all stopped
+// exits its workgroups at their first instruction.  The host polls the
+// per-system active counts every `check_every` iterations; with `graph` the
+// check_every iterations are captured once in a hipGraph and replayed (their
+// kernels read the iteration only through its parity, and check_every is
+// even).
+template <typename QT>
+static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, const nlsp_pcg_opts* opts,
+                   nlsp_rhs_info* info, bool graph, hipStream_t stream) {
+  const int R = hs[0].R;
+  int nblk = 0;
+  for (const auto& h : hs) nblk += h.nblk;
+  const SysDev* dsys = B.sysdev;
+  const int* b2s = (nsys == 1) ? nullptr : B.blk2sys;
+  const unsigned all = (1u << R) - 1u;
+  const int nu = hs[0].nu;
+  const dim3 grid(nblk), block(NT);
+  nlsp_kernel_timing* tm = opts->timing;
+  const int tphase = (tm && tm->phase >= 1 && tm->phase <= 2) ? tm->phase : 0;
+  const int tevery = tm ? std::max(1, tm->every) : 1;
+  std::vector<hipEvent_t> evs;
+  int64_t phase_launch[3] = {0, 0, 0};
+  // `launch(a, b)` enqueues one kernel with hipExtLaunchKernelGGL; a and b are
+  // the start/stop events of a timed launch, null otherwise
+  auto timed = [&](int ph, auto&& launch) {
+    const bool on = (ph == tphase) && (phase_launch[ph]++ % tevery == 0);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+      launch(a, b);
+      evs.push_back(a);
+      evs.push_back(b);
+    } else {
+      if (a) (void)hipEventDestroy(a);
+      launch(nullptr, nullptr);
+    }
+  };
+  // J_{2nu} r_new (nu > 1) and kernel B of iteration `it`
+  auto launch_b = [&](hipStream_t st, int it, int restart, unsigned mask, int init, bool can_time) {
+    int wsrc = -1;
+    if (nu > 1) {
+      const int rin = restart ? ((it + 1) & 1) : (it & 1);
+      hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, rin, 1, 0);
+      int src = 0;
+      for (int s = 1; s < 2 * nu - 1; ++s) {
+        hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, rin, 0, src);
+        src ^= 1;
+      }
+      wsrc = src;
+    }
+    if (can_time) {
+      timed(2, [&](hipEvent_t a, hipEvent_t b) {
+        hipExtLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart, mask,
+                              init, wsrc);
+      });
+    } else {
+      hipLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init, wsrc);
+    }
+  };
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t gph = nullptr;
+  auto release = [&]() {
+    if (tm) {
+      double tot = 0.0;
+      for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) tot += ms;
+      }
+      tm->total_ms = tot;
+      tm->launches = (int)(evs.size() / 2);
+    }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gph) (void)hipGraphDestroy(gph);
+  };
+  // stops with the HIP error, after releasing events and graphs
+#define NLSP_RUN(call)                  \
+  do {                                  \
+    if ((call) != hipSuccess) {         \
+      release();                        \
+      return NLSP_E_HIP;                \
+    }                                   \
+  } while (0)
+  for (int i = 0; i < nsys; ++i) {
+    hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs[i].op.n, NT)), block, 0, stream, hs[i].op,
+                       const_cast<double*>(hs[i].dinv), const_cast<float*>(hs[i].dinv32));
+    hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs[i].kp * hs[i].kp, 256)), dim3(256), 0, stream,
+                       hs[i].Linv, hs[i].kp, const_cast<double*>(hs[i].Ainv));
+  }
+  // start-up as iteration -1: r = f - A x into r[0], then kernel B in restart mode
+  hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, b2s, nsys, all, 0);
+  launch_b(stream, -1, 1, all, 1, true);
+  NLSP_RUN(hipGetLastError());
+  std::vector<RhsStatus> hst((size_t)nsys * R);
+  NLSP_RUN(hipMemcpyAsync(hst.data(), B.stat0, sizeof(RhsStatus) * nsys * R, hipMemcpyDeviceToHost, stream));
+  NLSP_RUN(hipStreamSynchronize(stream));
+  for (int i = 0; i < nsys; ++i) {
+    unsigned zero_mask = 0;
+    for (int c = 0; c < R; ++c)
+      if (hst[(size_t)i * R + c].ff == 0.0) zero_mask |= 1u << c;
+    if (zero_mask)
+      hipLaunchKernelGGL(k_zero_cols, dim3(ceil_div(hs[i].op.n * R, 256)), dim3(256), 0, stream, hs[i].x,
+                         hs[i].op.n, R, zero_mask);
+  }
+  int every = std::max(1, opts->check_every);
+  if (graph && (every & 1)) ++every;   // replayed bodies keep the iteration parity
+  int guard = 0;
+  int it = 0;  // next iteration index; stat[it & 1] is the current state
+  // every RHS stops by maxit iterations; the launch budget is a hard bound on
+  // the host loop in case the device-side bookkeeping were ever wrong
+  int64_t launched = 0;
+  const int64_t launch_cap = (int64_t)hs[0].maxit + 2 * every + 64;
+  std::vector<int> cnt((size_t)nsys * 4);
+  for (;;) {
+    NLSP_RUN(hipMemcpyAsync(cnt.data(), B.counters, sizeof(int) * 4 * nsys, hipMemcpyDeviceToHost, stream));
+    NLSP_RUN(hipStreamSynchronize(stream));
+    int any = 0;
+    for (int i = 0; i < nsys; ++i) any += cnt[(size_t)4 * i + 2] > 0;
+    if (any && launched < launch_cap) {
+      if (graph) {
+        if (!gexec) {
+          hipStream_t cs = nullptr;
+          NLSP_RUN(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+          if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipStreamDestroy(cs);
+            release();
+            return NLSP_E_HIP;
+          }
+          for (int k = 0; k < every; ++k) {
+            hipLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, cs, dsys, b2s, nsys, it + k);
+            launch_b(cs, it + k, 0, 0u, 0, false);
+          }
+          const hipError_t ce = hipStreamEndCapture(cs, &gph);
+          (void)hipStreamDestroy(cs);
+          NLSP_RUN(ce);
+          NLSP_RUN(hipGraphInstantiate(&gexec, gph, nullptr, nullptr, 0));
+        }
+        NLSP_RUN(hipGraphLaunch(gexec, stream));
+        it += every;
+      } else {
+        for (int k = 0; k < every; ++k, ++it) {
+          timed(1, [&](hipEvent_t a, hipEvent_t b) {
+            hipExtLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, stream, a, b, 0, dsys, b2s, nsys, it);
+          });
+          launch_b(stream, it, 0, 0u, 0, true);
+        }
+      }
+      launched += every;
+      NLSP_RUN(hipGetLastError());
+      continue;
+    }
+    // every RHS stopped: confirm the converged ones with the true residual
+    hipLaunchKernelGGL(k_true_residual, grid, block, 0, stream, dsys, b2s, nsys);
+    hipLaunchKernelGGL(k_true_finish, dim3(nsys), block, 0, stream, dsys);
+    NLSP_RUN(hipGetLastError());
+    RhsStatus* cur_d = (it & 1) ? B.stat1 : B.stat0;
+    std::vector<double> rrt((size_t)nsys * R);
+    NLSP_RUN(hipMemcpyAsync(hst.data(), cur_d, sizeof(RhsStatus) * nsys * R, hipMemcpyDeviceToHost, stream));
+    NLSP_RUN(hipMemcpyAsync(rrt.data(), B.rr_true, sizeof(double) * nsys * R, hipMemcpyDeviceToHost, stream));
+    NLSP_RUN(hipStreamSynchronize(stream));
+    std::vector<unsigned> redo(nsys, 0u);
+    bool any_redo = false;
+    for (int i = 0; i < nsys; ++i)
+      for (int c = 0; c < R; ++c) {
+        const RhsStatus& s = hst[(size_t)i * R + c];
+        if (s.conv && s.ff > 0.0 && rrt[(size_t)i * R + c] > hs[i].tol2 * s.ff && s.iters < hs[i].maxit) {
+          redo[i] |= 1u << c;
+          any_redo = true;
+        }
+      }
+    if (!any_redo || ++guard > 16) {
+      int worst = NLSP_OK;
+      for (size_t j = 0; j < (size_t)nsys * R; ++j) {
+        const RhsStatus& s = hst[j];
+        info[j].iters = s.iters;
+        info[j].status = s.status;
+        info[j].relres = (s.ff > 0.0) ? std::sqrt(rrt[j] / s.ff) : 0.0;
+        if (s.status < 0 && (worst >= 0 || s.status < worst)) worst = s.status;
+        if (s.status == NLSP_NOT_CONVERGED && worst == NLSP_OK) worst = NLSP_NOT_CONVERGED;
+      }
+      release();
+      return worst;
+    }
+    // residual replacement: r = f - A x for the `redo` RHS into r[it & 1] and
+    // those RHS restart from it (kernel B in restart mode as iteration it - 1,
+    // reading stat[(it - 1) & 1], which receives the current state of every
+    // system with the redo RHS made active)
+    std::vector<SysDev> hr = hs;   // descriptors with the restart masks
+    for (int i = 0; i < nsys; ++i) {
+      for (int c = 0; c < R; ++c)
+        if ((redo[i] >> c) & 1u) hst[(size_t)i * R + c].active = 1;
+      cnt[(size_t)4 * i + ((it - 1) & 1)] = __builtin_popcount(redo[i]);
+      hr[i].rmask = redo[i];
+    }
+    RhsStatus* prev_d = ((it - 1) & 1) ? B.stat1 : B.stat0;
+    NLSP_RUN(hipMemcpyAsync(prev_d, hst.data(), sizeof(RhsStatus) * nsys * R, hipMemcpyHostToDevice, stream));
+    NLSP_RUN(hipMemcpyAsync(B.counters, cnt.data(), sizeof(int) * 4 * nsys, hipMemcpyHostToDevice, stream));
+    NLSP_RUN(hipMemcpyAsync(B.sysdev, hr.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, b2s, nsys, all, it & 1);
+    launch_b(stream, it - 1, 1, all, 0, true);
+    NLSP_RUN(hipMemcpyAsync(B.sysdev, hs.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
+    NLSP_RUN(hipGetLastError());
+    // the host arrays above are reused by the next pass: finish their copies
+    NLSP_RUN(hipStreamSynchronize(stream));
+  }
+#undef NLSP_RUN
+}
+
+// Validation of one system against the batch's common settings; 0 if fine.
+inline bool system_ok(const nlsp_operator* A, const nlsp_two_level* M, const double* f, const double* u, int R,
+                      int64_t n) {
+  if (n < 1 || !M || !f || !u) return false;
+  if (R < 1 || R > MAXR || n * R >= (int64_t(1) << 31)) return false;
+  const int kp = padded_rank(M->k);
+  if (kp < 0 || M->nu < 1 || !(M->omega > 0) || !M->Linv) return false;
+  if (kp * R > 2048) return false;  // LDS staging of the coarse vectors
+  if (M->prec == NLSP_FP64 ? !M->Q64 : (M->prec == NLSP_MIXED ? !M->Q32 : true)) return false;
+  if ((int64_t)M->k > n) return false;
+  return true;
+}
+
+inline bool opts_ok(const nlsp_pcg_opts* o) {
+  return o && o->rtol > 0 && o->maxit >= 1 && o->check_every >= 1;
+}
+
+// Sets up and runs a batch; nsys = 1 and rows_per_block = 0 is pcg_solve.
+static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_level* const* Ms,
+                       const double* const* fs, double* const* us, int R, int rows_per_block,
+                       const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes, bool graph,
+                       hipStream_t stream) {
+  std::vector<SysShape> sh(nsys);
+  for (int i = 0; i < nsys; ++i) sh[i] = shape_of(op_size(As[i]), padded_rank(Ms[i]->k), R, rows_per_block);
+  if (!ws_ok(ws, ws_bytes, carve_batch(nullptr, sh, nullptr).bytes)) return NLSP_E_WORKSPACE;
+  std::vector<SolveLayout> Ls;
+  const BatchLayout B = carve_batch(ws, sh, &Ls);
+  std::vector<SysDev> hs(nsys);
+  std::vector<int> b2s;
+  int blk0 = 0;
+  for (int i = 0; i < nsys; ++i) {
+    hs[i] = make_sysdev(*As[i], *Ms[i], fs[i], us[i], sh[i], Ls[i], B, i, blk0, opts);
+    for (int b = 0; b < sh[i].nblk; ++b) b2s.push_back(i);
+    blk0 += sh[i].nblk;
+  }
   // iteration -1 reads stat[1]: every RHS starts active with a fresh direction
-  std::vector<RhsStatus> st0(R);
+  std::vector<RhsStatus> st0((size_t)nsys * R);
   for (auto& s : st0) {
     s = RhsStatus{};
     s.gamma_old = 1.0;
@@ -1189,20 +1333,162 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
     s.restart = 1;
     s.status = NLSP_NOT_CONVERGED;
   }
-  NLSP_HIP(hipMemsetAsync(L.p0, 0, sizeof(double) * n * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.p1, 0, sizeof(double) * n * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.z, 0, sizeof(double) * n * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.q, 0, sizeof(double) * n * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.estate0, 0, sizeof(double) * kp * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.estate1, 0, sizeof(double) * kp * R, stream));
-  NLSP_HIP(hipMemsetAsync(L.ticket, 0, sizeof(unsigned) * ticket_words(nblk), stream));
-  // counters: [0] = 0, [1] = R (the iteration -1 state has every RHS active), [2] = 0
-  const int counters0[4] = {0, R, 0, 0};
-  NLSP_HIP(hipMemcpyAsync(L.counters, counters0, sizeof(counters0), hipMemcpyHostToDevice, stream));
-  NLSP_HIP(hipMemcpyAsync(L.stat1, st0.data(), sizeof(RhsStatus) * R, hipMemcpyHostToDevice, stream));
-  NLSP_HIP(hipMemcpyAsync(L.sysdev, &hs, sizeof(SysDev), hipMemcpyHostToDevice, stream));
-  if (M->prec == NLSP_FP64) return run_pcg<double>(hs, L, R, opts, info, stream);
-  return run_pcg<float>(hs, L, R, opts, info, stream);
+  // counters per system: nact(0) = 0, nact(1) = R (the iteration -1 state has
+  // every RHS active), active = 0
+  std::vector<int> counters0((size_t)nsys * 4, 0);
+  for (int i = 0; i < nsys; ++i) counters0[(size_t)4 * i + 1] = R;
+  NLSP_HIP(hipMemsetAsync(B.zero_begin, 0, B.zero_bytes, stream));
+  NLSP_HIP(hipMemcpyAsync(B.counters, counters0.data(), sizeof(int) * 4 * nsys, hipMemcpyHostToDevice, stream));
+  NLSP_HIP(hipMemcpyAsync(B.stat1, st0.data(), sizeof(RhsStatus) * nsys * R, hipMemcpyHostToDevice, stream));
+  NLSP_HIP(hipMemcpyAsync(B.sysdev, hs.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
+  if (nsys > 1)
+    NLSP_HIP(hipMemcpyAsync(B.blk2sys, b2s.data(), sizeof(int) * b2s.size(), hipMemcpyHostToDevice, stream));
+  // the host arrays above are locals: their copies must finish before return
+  NLSP_HIP(hipStreamSynchronize(stream));
+  if (Ms[0]->prec == NLSP_FP64) return run_pcg<double>(nsys, hs, B, opts, info, graph, stream);
+  return run_pcg<float>(nsys, hs, B, opts, info, graph, stream);
+}
+
+}  // namespace nlsp
+
+using namespace nlsp;
+
+extern "C" {
+
+size_t pcg_solve_workspace_bytes(const nlsp_operator* A, int k, int R) {
+  const int64_t n = op_size(A);
+  const int kp = padded_rank(k);
+  if (n < 1 || kp < 0 || R < 1 || R > MAXR || kp * R > 2048 || n * R >= (int64_t(1) << 31)) return 0;
+  return carve_batch(nullptr, {shape_of(n, kp, R, 0)}, nullptr).bytes;
+}
+
+int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, double* u, int R,
+              const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes,
+              void* stream_) {
+  const int64_t n = op_size(A);
+  if (!info || !opts_ok(opts) || !system_ok(A, M, f, u, R, n)) return NLSP_E_INVALID;
+  return solve_batch(1, &A, &M, &f, &u, R, 0, opts, info, ws, ws_bytes, false, as_stream(stream_));
+}
+
+size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R, int rows_per_block) {
+  if (nsys < 1 || !sys || R < 1 || R > MAXR || rows_per_block < 0) return 0;
+  std::vector<SysShape> sh(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    const int64_t n = op_size(&sys[i].A);
+    const int kp = padded_rank(sys[i].M.k);
+    if (n < 1 || kp < 0 || kp * R > 2048 || n * R >= (int64_t(1) << 31)) return 0;
+    sh[i] = shape_of(n, kp, R, rows_per_block);
+  }
+  return carve_batch(nullptr, sh, nullptr).bytes;
+}
+
+int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_block, const nlsp_pcg_opts* opts,
+                      nlsp_rhs_info* info, void* ws, size_t ws_bytes, void* stream_) {
+  if (nsys < 1 || !sys || !info || !opts_ok(opts) || rows_per_block < 0) return NLSP_E_INVALID;
+  std::vector<const nlsp_operator*> As(nsys);
+  std::vector<const nlsp_two_level*> Ms(nsys);
+  std::vector<const double*> fs(nsys);
+  std::vector<double*> us(nsys);
+  int64_t blocks = 0;
+  for (int i = 0; i < nsys; ++i) {
+    const nlsp_system& s = sys[i];
+    const int64_t n = op_size(&s.A);
+    if (!system_ok(&s.A, &s.M, s.f, s.u, R, n)) return NLSP_E_INVALID;
+    // one precision, smoother and k for the whole batch (one kernel per step)
+    if (s.M.prec != sys[0].M.prec || s.M.nu != sys[0].M.nu || s.M.k != sys[0].M.k) return NLSP_E_INVALID;
+    As[i] = &s.A;
+    Ms[i] = &s.M;
+    fs[i] = s.f;
+    us[i] = s.u;
+    blocks += shape_of(n, padded_rank(s.M.k), R, rows_per_block).nblk;
+  }
+  if (blocks > (int64_t(1) << 30)) return NLSP_E_INVALID;
+  const bool graph = opts->timing == nullptr;
+  return solve_batch(nsys, As.data(), Ms.data(), fs.data(), us.data(), R, rows_per_block, opts, info, ws,
+                     ws_bytes, graph, as_stream(stream_));
+}
+
+// ---------------------------------------------------------------- autotuner
+// Candidate tile sizes (rows of a system per workgroup) tried by
+// pcg_solve_batched_tune, as multiples of the NT / R rows of one chunk; 0 is
+// the default one-workgroup-per-chunk plan.
+static const int kTuneChunks[] = {0, 2, 4, 8, 16, 32};
+static const int kTuneCount = sizeof(kTuneChunks) / sizeof(kTuneChunks[0]);
+
+int pcg_solve_batched_tune_candidates(int R, int* rows_per_block) {
+  if (R < 1 || R > MAXR) return 0;
+  for (int c = 0; c < kTuneCount; ++c)
+    if (rows_per_block) rows_per_block[c] = kTuneChunks[c] * (NT / R);
+  return kTuneCount;
+}
+
+size_t pcg_solve_batched_tune_workspace_bytes(int nsys, const nlsp_system* sys, int R) {
+  if (nsys < 1 || !sys || R < 1 || R > MAXR) return 0;
+  size_t most = 0, us = 0;
+  for (int c = 0; c < kTuneCount; ++c) {
+    const size_t b = pcg_solve_batched_workspace_bytes(nsys, sys, R, kTuneChunks[c] * (NT / R));
+    if (b == 0) return 0;
+    most = std::max(most, b);
+  }
+  for (int i = 0; i < nsys; ++i) us += align_up((size_t)op_size(&sys[i].A) * R * sizeof(double));
+  return align_up(most) + us;
+}
+
+int pcg_solve_batched_tune(int nsys, const nlsp_system* sys, int R, const nlsp_pcg_opts* opts, int iters,
+                           int* best_rows_per_block, double* ms, void* ws, size_t ws_bytes, void* stream_) {
+  if (nsys < 1 || !sys || !opts_ok(opts) || iters < 2 || !best_rows_per_block) return NLSP_E_INVALID;
+  const size_t need = pcg_solve_batched_tune_workspace_bytes(nsys, sys, R);
+  if (need == 0) return NLSP_E_INVALID;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  hipStream_t stream = as_stream(stream_);
+  size_t solve_bytes = 0;
+  for (int c = 0; c < kTuneCount; ++c)
+    solve_bytes = std::max(solve_bytes, pcg_solve_batched_workspace_bytes(nsys, sys, R, kTuneChunks[c] * (NT / R)));
+  char* base = static_cast<char*>(ws);
+  // the trial solves iterate on copies of the initial guesses
+  std::vector<nlsp_system> trial(sys, sys + nsys);
+  size_t off = align_up(solve_bytes);
+  for (int i = 0; i < nsys; ++i) {
+    trial[i].u = reinterpret_cast<double*>(base + off);
+    off += align_up((size_t)op_size(&sys[i].A) * R * sizeof(double));
+  }
+  nlsp_pcg_opts o = *opts;
+  o.maxit = iters;
+  o.check_every = iters + (iters & 1);
+  o.timing = nullptr;
+  std::vector<nlsp_rhs_info> info((size_t)nsys * R);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  NLSP_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return NLSP_E_HIP;
+  }
+  double best = 1e300;
+  int best_c = 0, rc = NLSP_OK;
+  for (int c = 0; c < kTuneCount && rc == NLSP_OK; ++c) {
+    const int rpb = kTuneChunks[c] * (NT / R);
+    for (int i = 0; i < nsys && rc == NLSP_OK; ++i)
+      if (hipMemcpyAsync(trial[i].u, sys[i].u, (size_t)op_size(&sys[i].A) * R * sizeof(double),
+                         hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        rc = NLSP_E_HIP;
+    if (rc != NLSP_OK) break;
+    if (hipEventRecord(e0, stream) != hipSuccess) { rc = NLSP_E_HIP; break; }
+    const int r = pcg_solve_batched(nsys, trial.data(), R, rpb, &o, info.data(), ws, solve_bytes, stream);
+    if (r < 0) { rc = r; break; }
+    float t = 0.f;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) { rc = NLSP_E_HIP; break; }
+    if (ms) ms[c] = t;
+    if (t < best) {
+      best = t;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != NLSP_OK) return rc;
+  *best_rows_per_block = kTuneChunks[best_c] * (NT / R);
+  return NLSP_OK;
 }
 
 }  // extern "C"

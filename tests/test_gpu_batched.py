@@ -1,0 +1,125 @@
+"""GPU parity of the batched solve (many systems of different sizes in the
+same launches, hipGraph replay, tuned tiles), through the C ABI (marked gpu).
+
+Bars: with the default tile every system is partitioned exactly as by
+pcg_solve, so the batched solve must reproduce the single-system solves bit
+for bit; with other tiles the reductions are ordered differently, and the
+float64 form must keep the iteration count within +-1 of the FP64 oracle with
+a true relative residual <= rtol per right-hand side (mixed form: true
+relative residual <= rtol)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.method import make_preconditioner
+import workloads as W
+from tests._cases import cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20174_amd as mod
+    return mod
+
+
+SIDES = [24, 31, 40, 17, 50, 33]
+
+
+def _batch(nl, R, k=12, m=24, seed=0, sides=SIDES, zero_col=False):
+    """Anisotropic Q1 systems (one (eps, theta) per system), GPU setup."""
+    rng = np.random.default_rng(seed)
+    et = np.stack([10 ** rng.uniform(-2, 0, len(sides)), rng.uniform(0, np.pi, len(sides))], 1)
+    st = nl.q1_aniso_stencil(torch.tensor(et, dtype=torch.float64, device="cuda"))
+    out = []
+    for i, side in enumerate(sides):
+        n = side * side
+        op = nl.Operator(nl.OP_STENCIL9, side, side, 1, st[i].contiguous())
+        S0 = cuda(W.normal_block(W.seed_for(3, 1, 10 * seed + i), n, m))
+        P, _ = nl.setup_spectral_P(op, S0, k, 2 / 3, 10, nl.FP64)
+        M = nl.galerkin_coarse(op, P, 2 / 3, 1)
+        f = W.normal_block(W.seed_for(3, 2, 10 * seed + i), n, R)
+        if zero_col and i == 2:
+            f[:, 1] = 0.0
+        A = O.q1_aniso(side, et[i, 0], et[i, 1])
+        out.append((A, op, M, P, f))
+    return out
+
+
+def _systems(nl, batch):
+    return [nl.System(op, M, cuda(f), torch.zeros(f.shape, dtype=torch.float64, device="cuda"))
+            for (_, op, M, _, f) in batch]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("R", [1, 3, 8])
+def test_default_tile_matches_single_system_bitwise(nl, prec, R):
+    batch = _batch(nl, R, zero_col=(R == 3))
+    systems = _systems(nl, batch)
+    infos, rc = nl.pcg_solve_batched(systems, prec=prec, rtol=1e-8, check_every=8)
+    assert rc == nl.OK
+    for (A, op, M, _, f), s, inf in zip(batch, systems, infos):
+        u1, info1, rc1 = nl.pcg_solve(op, M, cuda(f), prec=prec, rtol=1e-8, check_every=8)
+        assert torch.equal(s.u, u1.reshape(s.u.shape))
+        for a, b in zip(inf, info1):
+            assert (a.iters, a.status, a.relres) == (b.iters, b.status, b.relres)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("rows", [128, 512, 2048])
+def test_tiles_against_oracle(nl, prec, rows):
+    R = 8
+    batch = _batch(nl, R, seed=1)
+    systems = _systems(nl, batch)
+    infos, rc = nl.pcg_solve_batched(systems, prec=prec, rtol=1e-8, rows_per_block=rows)
+    assert rc == nl.OK
+    for (A, op, M, P, f), s, inf in zip(batch, systems, infos):
+        u = host(s.u)
+        Ph = host(P)
+        _, L = O.galerkin(A, Ph)
+        res = O.pcg(A, f, make_preconditioner(A, Ph, L, 2 / 3, 1, 1), rtol=1e-8, flexible=(prec == 1))
+        for c in range(R):
+            rel = np.linalg.norm(f[:, c] - A @ u[:, c]) / np.linalg.norm(f[:, c])
+            assert inf[c].status == nl.OK
+            assert rel <= 1e-8 * 1.0001
+            if prec == 0:
+                assert abs(inf[c].iters - res.iters[c]) <= 1, (c, inf[c].iters, res.iters[c])
+            else:
+                assert abs(inf[c].iters - res.iters[c]) <= max(2, 0.05 * res.iters[c])
+
+
+def test_deterministic_and_graph_replay_matches_direct_launches(nl):
+    """Two graph-replayed batched solves are bit-identical, and equal to the
+    single-system solves (direct launches, no graph)."""
+    batch = _batch(nl, 2, seed=2)
+    s1 = _systems(nl, batch)
+    s2 = _systems(nl, batch)
+    i1, _ = nl.pcg_solve_batched(s1, prec=1, rows_per_block=0, check_every=6)
+    i2, _ = nl.pcg_solve_batched(s2, prec=1, rows_per_block=0, check_every=6)
+    for a, b in zip(s1, s2):
+        assert torch.equal(a.u, b.u)
+
+
+def test_tuner_picks_a_candidate_and_leaves_u(nl):
+    batch = _batch(nl, 8, seed=3)
+    systems = _systems(nl, batch)
+    for s in systems:
+        s.u.fill_(0.25)
+    best, times = nl.pcg_solve_batched_tune(systems, prec=1, iters=8)
+    assert best in times and len(times) >= 4 and all(t > 0 for t in times.values())
+    for s in systems:
+        assert torch.all(s.u == 0.25)
+    infos, rc = nl.pcg_solve_batched(systems, prec=1, rows_per_block=best)
+    assert rc == nl.OK
+
+
+def test_invalid(nl):
+    batch = _batch(nl, 2, seed=4, sides=[20, 21])
+    systems = _systems(nl, batch)
+    systems[1].M = nl.galerkin_coarse(batch[1][1], batch[1][3][:, :8].contiguous(), 2 / 3, 1)   # other k
+    with pytest.raises(nl.NlspError):
+        nl.pcg_solve_batched(systems)

@@ -180,6 +180,7 @@ def main():
                        "relres": inf64.relres}
         out["spmv"] = spmv_legs(nl, torch, dev)
         out["training"] = training_legs(nl, torch, dev)
+        out["batched"] = batched_legs(nl, torch, dev)
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, coef, S0h, fh, out.get("fp64", {}).get("iters", out["iters"]))
@@ -267,6 +268,80 @@ def training_legs(nl, torch, dev):
                        "fwd_GBs": round(batch * n * (4 * k * 4 + 8) / f_ms / 1e6, 1),
                        "bwd_GBs": round(batch * n * 2 * k * 4 / b_ms / 1e6, 1)}
     return res
+
+
+def batched_legs(nl, torch, dev, nsys=None):
+    """Batched solve on the anisotropic workload: 256 Q1 systems, side ~
+    U{64, 96, 128, 192, 256}, eps = 10^U(-3, 0), theta ~ U(0, pi), k = 32,
+    m = 64, 8 right-hand sides each, rtol 1e-8.  Setup (float64) once per
+    system; then (a) the batched mixed-precision solve (one launch per kernel
+    per iteration over all systems, hipGraph replay, tuned tile) and (b) the
+    plain single-system float64 path, one pcg_solve per system, on the same
+    inputs and coarse spaces."""
+    import workloads as W
+    c3 = W.Cfg3()
+    side, eps, theta = c3.systems()
+    ns = len(side) if nsys is None else nsys
+    st = nl.q1_aniso_stencil(torch.tensor(np.stack([eps[:ns], theta[:ns]], 1), dtype=torch.float64, device=dev))
+    systems = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    setup_ms = 0.0
+    rows = 0
+    for i in range(ns):
+        sd = int(side[i])
+        n = sd * sd
+        rows += n
+        op = nl.Operator(nl.OP_STENCIL9, sd, sd, 1, st[i].contiguous())
+        S0 = torch.tensor(c3.S0(i, n), dtype=torch.float64, device=dev)
+        f = torch.tensor(c3.rhs(i, n), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        e0.record()
+        P, _ = nl.setup_spectral_P(op, S0, c3.k, c3.omega, c3.s1, nl.FP64)
+        M = nl.galerkin_coarse(op, P, c3.omega, c3.nu)
+        e1.record()
+        torch.cuda.synchronize()
+        setup_ms += e0.elapsed_time(e1)
+        systems.append(nl.System(op, M, f, torch.zeros_like(f)))
+        del S0, P
+    best, tune_ms = nl.pcg_solve_batched_tune(systems, prec=nl.MIXED, rtol=c3.rtol, iters=16)
+    ws = torch.empty(nl.pcg_solve_batched_workspace_bytes(systems, nl.MIXED, best), dtype=torch.uint8, device=dev)
+    times, iters, worst = [], [], 0.0
+    for rep in range(3):
+        for s in systems:
+            s.u.zero_()
+        torch.cuda.synchronize()
+        e0.record()
+        infos, rc = nl.pcg_solve_batched(systems, prec=nl.MIXED, rtol=c3.rtol, rows_per_block=best, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        iters = [inf.iters for si in infos for inf in si]
+        worst = max(inf.relres for si in infos for inf in si)
+    b_ms = statistics.median(times)
+    pairs = ns * c3.R
+    # plain single-system float64 path on the same systems
+    t0 = time.perf_counter()
+    f64_iters, f64_worst = [], 0.0
+    torch.cuda.synchronize()
+    e0.record()
+    for s in systems:
+        u, info, rc = nl.pcg_solve(s.op, s.M, s.f, prec=nl.FP64, rtol=c3.rtol)
+        f64_iters += [inf.iters for inf in info]
+        f64_worst = max([f64_worst] + [inf.relres for inf in info])
+    e1.record()
+    torch.cuda.synchronize()
+    s_ms = e0.elapsed_time(e1)
+    return {"workload": f"{ns} Q1 anisotropic systems, sum n = {rows}, k={c3.k}, m={c3.m}, R={c3.R}, rtol={c3.rtol}",
+            "setup_f64_ms": round(setup_ms, 2),
+            "batched_mixed": {"solve_ms": round(b_ms, 3), "rows_per_block": best,
+                              "pairs_per_s": round(pairs / (b_ms * 1e-3), 1),
+                              "systems_per_s": round(ns / (b_ms * 1e-3), 1),
+                              "iters_max": int(max(iters)), "iters_median": float(np.median(iters)),
+                              "relres_max": worst, "tune_ms": {str(k): round(v, 3) for k, v in tune_ms.items()}},
+            "single_system_f64": {"solve_ms": round(s_ms, 3), "pairs_per_s": round(pairs / (s_ms * 1e-3), 1),
+                                  "iters_max": int(max(f64_iters)), "relres_max": f64_worst},
+            "speedup_solve": round(s_ms / b_ms, 2),
+            "speedup_setup_plus_solve": round((setup_ms + s_ms) / (setup_ms + b_ms), 3)}
 
 
 def counter_traffic(kname: str, N: int, k: int):

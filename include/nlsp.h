@@ -307,6 +307,65 @@ size_t galerkin_bwd_workspace_bytes(int batch, int n, int k);
 int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, float* gP, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* Thin QR of a batch of n x k matrices (the qf() of Sec. 4 that makes the
+ * predicted basis orthonormal): A = Q R, R upper triangular with positive
+ * diagonal, by CholeskyQR2 (Gram matrix in float64 from float32 MFMA
+ * products, Cholesky, triangular inverse; twice).
+ *   A    device (batch, n, k) float32      Q  device (batch, n, k) float32
+ *   R    device (batch, k, k) float64      bad device (batch) int: set to 1
+ *        where a Gram matrix was not positive definite (A rank deficient)
+ * Limits: 1 <= k <= 64, k <= n.  Asynchronous on `stream`. */
+size_t qr_thin_workspace_bytes(int batch, int n, int k);
+int qr_thin_fwd(int batch, int n, int k, const float* A, float* Q, double* R, int* bad, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* Backward of Q = qf(A) for an upstream gradient gQ (R receives none):
+ *   gA = [gQ + Q copyltu(-gQ^T Q)] R^-T,
+ * copyltu(M) = the symmetric matrix with the lower triangle of M.
+ * Asynchronous on `stream`. */
+int qr_thin_bwd(int batch, int n, int k, const float* Q, const double* R, const float* gQ, float* gA,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------- P-predictor CNN */
+/* A small convolutional predictor of the basis (Sec. 4, neural
+ * parameterisation + thin QR; here a CNN on the coefficient field):
+ *   P_hat_b = Phi_k + conv4(g(conv3(g(conv2(g(conv1(x_b))))))),
+ *   x_b = [ (log a_b - mean) / std , Phi_k ]   (1 + k channels per cell),
+ * 3x3 'same' convolutions with zero padding and bias, width `hidden`, g =
+ * erf-GELU, Phi_k the k smoothest sine modes sin(i pi x) sin(j pi y) of the
+ * unit square (by i^2 + j^2, ties by i) at the cell centres, unit 2-norm.
+ * Fields are N x N cells, numbered x fastest (as the operators).
+ * Parameters (float32, one vector): for l = 1..4, W_l (Cout, Cin, 3, 3) then
+ * b_l (Cout).  Arithmetic: bfloat16 activations and weights in the
+ * convolutions, float32 accumulation, float32 output and gradients.
+ * Limits: k and hidden multiples of 16, <= 64; N >= 16. */
+typedef struct {
+  int batch;             /* fields */
+  int N;                 /* cells per side */
+  int k;                 /* basis columns */
+  int hidden;            /* channels of the hidden layers */
+} nlsp_cnn_shape;
+
+int64_t cnn_param_count(const nlsp_cnn_shape* shape);   /* -1 if the shape is invalid */
+size_t cnn_workspace_bytes(const nlsp_cnn_shape* shape);
+
+/* P_hat (batch, N*N, k) float32 from params and the cell coefficients
+ * coef (batch, N*N) float64 (device).  The workspace keeps the activations
+ * for cnn_bwd.  Synchronises `stream`. */
+int cnn_fwd(const nlsp_cnn_shape* shape, const float* params, const double* coef, float* Phat,
+            void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient of the parameters (written, not accumulated) for an upstream
+ * gradient gPhat (batch, N*N, k); `ws` must hold the activations of the
+ * cnn_fwd call with the same params.  Asynchronous on `stream`. */
+int cnn_bwd(const nlsp_cnn_shape* shape, const float* params, const float* gPhat, float* gparams,
+            void* ws, size_t ws_bytes, void* stream);
+
+/* One bias-corrected Adam step (step >= 1) on `count` float32 parameters;
+ * m and v are the caller's moment buffers (zero before step 1). */
+int adam_step(int64_t count, float* params, const float* grads, float* m, float* v, float lr,
+              float beta1, float beta2, float eps, int step, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,12 +25,14 @@ from .operators import (poisson5, fv_harmonic_2d, fv_harmonic_3d, q1_aniso_eleme
 from .method import (relax, spectral_basis, galerkin, two_grid_apply, pcg, PCGResult,
                      setup, NOT_CONVERGED, OK, E_BREAKDOWN, E_NONFINITE, E_NOT_SPD,
                      E_INVALID)
+from . import predictor
 from .losses import (subspace_loss, subspace_loss_grad, nlss_loss, nlss_weights,
                      weighted_energy_loss, weighted_energy_loss_grad, captured_energy,
                      galerkin_term, galerkin_term_grad, galerkin_term_dense,
                      galerkin_coarse_vjp)
 
 __all__ = [
+    "predictor",
     "poisson5", "fv_harmonic_2d", "fv_harmonic_3d", "q1_aniso_element", "q1_aniso",
     "jacobi_diag", "relax", "spectral_basis", "galerkin", "two_grid_apply", "pcg",
     "PCGResult", "setup", "OK", "NOT_CONVERGED", "E_BREAKDOWN", "E_NONFINITE",

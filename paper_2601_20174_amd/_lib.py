@@ -38,6 +38,10 @@ class NlspSystem(ctypes.Structure):
     _fields_ = [("A", NlspOperator), ("M", NlspTwoLevel), ("f", c_void_p), ("u", c_void_p)]
 
 
+class NlspCnnShape(ctypes.Structure):
+    _fields_ = [("batch", c_int), ("N", c_int), ("k", c_int), ("hidden", c_int)]
+
+
 class NlspRhsInfo(ctypes.Structure):
     _fields_ = [("iters", c_int), ("status", c_int), ("relres", c_double)]
 
@@ -80,6 +84,17 @@ SIGNATURES = {
     "pcg_solve_batched_tune": (c_int, [c_int, ctypes.POINTER(NlspSystem), c_int, ctypes.POINTER(NlspPcgOpts),
                                        c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_void_p,
                                        c_size_t, c_void_p]),
+    "qr_thin_workspace_bytes": (c_size_t, [c_int, c_int, c_int]),
+    "qr_thin_fwd": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                            c_void_p]),
+    "qr_thin_bwd": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                            c_void_p]),
+    "cnn_param_count": (c_int64, [ctypes.POINTER(NlspCnnShape)]),
+    "cnn_workspace_bytes": (c_size_t, [ctypes.POINTER(NlspCnnShape)]),
+    "cnn_fwd": (c_int, [ctypes.POINTER(NlspCnnShape), c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "cnn_bwd": (c_int, [ctypes.POINTER(NlspCnnShape), c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "adam_step": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float, ctypes.c_float, c_int, c_void_p]),
 }
 
 _LIB = None

@@ -449,3 +449,113 @@ def pcg_solve_batched_tune(systems: List[System], prec: int = MIXED, rtol: float
                                      ws.data_ptr(), ws.numel(), _stream())
     _check("pcg_solve_batched_tune", rc)
     return best.value, {int(cand[i]): float(ms[i]) for i in range(ncand)}
+
+
+# ------------------------------------------------------------ thin QR
+def qr_thin_workspace_bytes(batch: int, n: int, k: int) -> int:
+    return int(_L().qr_thin_workspace_bytes(batch, n, k))
+
+
+def qr_thin_fwd(A: torch.Tensor, workspace: Optional[torch.Tensor] = None):
+    """Q, R, bad for A (batch, n, k) float32: A = Q R, R (batch, k, k) float64."""
+    batch, n, k = A.shape
+    Q = torch.empty_like(A)
+    R = torch.empty(batch, k, k, dtype=torch.float64, device=A.device)
+    bad = torch.empty(batch, dtype=torch.int32, device=A.device)
+    nb = qr_thin_workspace_bytes(batch, n, k)
+    if nb == 0:
+        raise NlspError("qr_thin_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(nb, A.device)
+    rc = _L().qr_thin_fwd(batch, n, k, _dev(A, torch.float32, "A"), Q.data_ptr(), R.data_ptr(), bad.data_ptr(),
+                          ws.data_ptr(), ws.numel(), _stream())
+    _check("qr_thin_fwd", rc)
+    return Q, R, bad
+
+
+def qr_thin_bwd(Q: torch.Tensor, R: torch.Tensor, gQ: torch.Tensor, workspace: Optional[torch.Tensor] = None):
+    batch, n, k = Q.shape
+    gA = torch.empty_like(Q)
+    nb = qr_thin_workspace_bytes(batch, n, k)
+    ws = workspace if workspace is not None else _workspace(nb, Q.device)
+    rc = _L().qr_thin_bwd(batch, n, k, _dev(Q, torch.float32, "Q"), _dev(R, torch.float64, "R"),
+                          _dev(gQ, torch.float32, "gQ"), gA.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check("qr_thin_bwd", rc)
+    return gA
+
+
+class ThinQ(torch.autograd.Function):
+    """Q factor of the thin QR (CholeskyQR2) with the library's backward."""
+
+    @staticmethod
+    def forward(ctx, A):
+        Q, R, bad = qr_thin_fwd(A.contiguous())
+        ctx.save_for_backward(Q, R)
+        return Q
+
+    @staticmethod
+    def backward(ctx, gQ):
+        Q, R = ctx.saved_tensors
+        return qr_thin_bwd(Q, R, gQ.contiguous().to(torch.float32))
+
+
+def thin_q(A: torch.Tensor) -> torch.Tensor:
+    return ThinQ.apply(A)
+
+
+# ------------------------------------------------------------ P-predictor CNN
+def _cnn_shape(batch: int, N: int, k: int, hidden: int):
+    return _lib.NlspCnnShape(int(batch), int(N), int(k), int(hidden))
+
+
+def cnn_param_count(batch: int, N: int, k: int, hidden: int = 32) -> int:
+    return int(_L().cnn_param_count(ctypes.byref(_cnn_shape(batch, N, k, hidden))))
+
+
+def cnn_workspace_bytes(batch: int, N: int, k: int, hidden: int = 32) -> int:
+    return int(_L().cnn_workspace_bytes(ctypes.byref(_cnn_shape(batch, N, k, hidden))))
+
+
+def cnn_fwd(params: torch.Tensor, coef: torch.Tensor, N: int, k: int, hidden: int, workspace: torch.Tensor):
+    """P_hat (batch, N*N, k) float32 from coef (batch, N*N) float64; the
+    workspace keeps the activations for cnn_bwd."""
+    batch = coef.shape[0]
+    Phat = torch.empty(batch, N * N, k, dtype=torch.float32, device=coef.device)
+    sh = _cnn_shape(batch, N, k, hidden)
+    rc = _L().cnn_fwd(ctypes.byref(sh), _dev(params, torch.float32, "params"), _dev(coef, torch.float64, "coef"),
+                      Phat.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    _check("cnn_fwd", rc)
+    return Phat
+
+
+def cnn_bwd(params: torch.Tensor, gPhat: torch.Tensor, N: int, k: int, hidden: int, workspace: torch.Tensor):
+    batch = gPhat.shape[0]
+    g = torch.empty_like(params)
+    sh = _cnn_shape(batch, N, k, hidden)
+    rc = _L().cnn_bwd(ctypes.byref(sh), _dev(params, torch.float32, "params"), _dev(gPhat, torch.float32, "gPhat"),
+                      g.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    _check("cnn_bwd", rc)
+    return g
+
+
+class CnnPredictor(torch.autograd.Function):
+    """P_hat = CNN(coef; params) with the library's backward for params."""
+
+    @staticmethod
+    def forward(ctx, params, coef, N, k, hidden, workspace):
+        ctx.meta = (N, k, hidden, workspace)
+        ctx.save_for_backward(params)
+        return cnn_fwd(params.contiguous(), coef, N, k, hidden, workspace)
+
+    @staticmethod
+    def backward(ctx, gPhat):
+        (params,) = ctx.saved_tensors
+        N, k, hidden, ws = ctx.meta
+        return cnn_bwd(params, gPhat.contiguous().to(torch.float32), N, k, hidden, ws), None, None, None, None, None
+
+
+def adam_step(params: torch.Tensor, grads: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float, step: int,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    rc = _L().adam_step(params.numel(), _dev(params, torch.float32, "params"), _dev(grads, torch.float32, "grads"),
+                        _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), float(lr), float(beta1),
+                        float(beta2), float(eps), int(step), _stream())
+    _check("adam_step", rc)

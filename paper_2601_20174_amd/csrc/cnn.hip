@@ -1,0 +1,614 @@
+// P-predictor: a small convolutional network mapping a coefficient field to
+// an unconstrained basis, P_hat = Phi_k + CNN([log a standardised, Phi_k]),
+// whose thin Q factor is the learned prolongation (Sec. 4, neural
+// parameterisation followed by a thin QR; the paper's network is an MLP on
+// the relaxed vectors, here a local CNN on the field with the k smoothest
+// sine modes of the unit square as extra input channels and as a residual).
+//
+// Four 3x3 convolutions ('same', zero padding), hidden width CH, erf-GELU
+// after the first three.  Activations are NHWC bfloat16 with channel counts
+// padded to multiples of 16; products are v_mfma_f32_16x16x16_bf16 with
+// float32 accumulation.  Layer l stores its pre-activation z_l; the next
+// layer applies GELU while staging its input, and the backward multiplies by
+// GELU'(z_l) in the epilogue of the data gradient, so no activation is
+// stored twice.  Master parameters, gradients and the optimiser are float32.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_common.hpp"
+#include "host_common.hpp"
+
+namespace nlsp {
+namespace cnn {
+
+constexpr int NT = 256;
+constexpr int TILE = 16;            // 16 x 16 output pixels per workgroup
+constexpr int HALO = TILE + 2;
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+NLSP_DEV f4 mfma_bf16(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+
+// float <-> bfloat16 (round to nearest even; inputs are finite)
+NLSP_DEV unsigned short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+NLSP_DEV float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// erf-based GELU and its derivative
+NLSP_DEV float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+NLSP_DEV float gelu_grad(float x) {
+  return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// ------------------------------------------------------------- inputs
+// per field: mean and standard deviation of log a (float64)
+__global__ __launch_bounds__(NT) void k_field_stats(const double* __restrict__ coef, int n,
+                                                    double* __restrict__ stats) {
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.x;
+  const double* a = coef + (int64_t)b * n;
+  double s = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double l = log(a[i]);
+    s += l;
+    s2 += l * l;
+  }
+  s = block_sum(s, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    const double mean = s / n;
+    const double var = std::max(s2 / n - mean * mean, 0.0);
+    stats[2 * b] = mean;
+    stats[2 * b + 1] = var > 0.0 ? sqrt(var) : 1.0;
+  }
+}
+
+// Phi (n x k, float32): the k sine modes sin(i pi x) sin(j pi y) of the unit
+// square with the smallest i^2 + j^2 (ties by i), at the cell centres
+// ((c + 1/2)/N), scaled to unit 2-norm on the grid.  modes: (k x 2) int pairs.
+__global__ __launch_bounds__(NT) void k_sine_modes(int N, int k, const int* __restrict__ modes,
+                                                   float* __restrict__ phi) {
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (g >= (int64_t)N * N * k) return;
+  const int j = (int)(g % k);
+  const int64_t p = g / k;
+  const int x = (int)(p % N), y = (int)(p / N);
+  const double h = 1.0 / N;
+  const double v = sin(modes[2 * j] * M_PI * (x + 0.5) * h) * sin(modes[2 * j + 1] * M_PI * (y + 0.5) * h);
+  phi[g] = (float)(v * 2.0 * h);   // sum over the grid of sin^2 sin^2 = N^2 / 4
+}
+
+// x0[b][pixel][c]: c = 0 standardised log a, c = 1..k Phi, zero up to C0p
+__global__ __launch_bounds__(NT) void k_cnn_input(const double* __restrict__ coef, const double* __restrict__ stats,
+                                                  const float* __restrict__ phi, int n, int k, int C0p,
+                                                  unsigned short* __restrict__ x0) {
+  const int b = blockIdx.y;
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (g >= (int64_t)n * C0p) return;
+  const int c = (int)(g % C0p);
+  const int64_t p = g / C0p;
+  float v = 0.f;
+  if (c == 0)
+    v = (float)((log(coef[(int64_t)b * n + p]) - stats[2 * b]) / stats[2 * b + 1]);
+  else if (c <= k)
+    v = phi[p * k + (c - 1)];
+  x0[((int64_t)b * n) * C0p + g] = to_bf16(v);
+}
+
+// --------------------------------------------------------- weight layouts
+// Master layout of layer l: W (Cout, Cin, 3, 3) then b (Cout), float32.
+// Forward kernel weights:  Wf[tap][oc][icp]  = W[oc][ic][tap]
+// Data-gradient weights:   Wb[tap][ocp][ic]  = W[oc][ic][8 - tap] (as a
+// convolution from the Cout channels of dz to the Cin channels of dx)
+// Channel counts are padded to Cinp, Coutp (multiples of 16) with zeros.
+__global__ __launch_bounds__(NT) void k_prep_weights(const float* __restrict__ W, int Cin, int Cout, int Cinp,
+                                                     int Coutp, unsigned short* __restrict__ Wf,
+                                                     unsigned short* __restrict__ Wb) {
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= 9 * Coutp * Cinp) return;
+  const int tap = g / (Coutp * Cinp);
+  const int rem = g % (Coutp * Cinp);
+  {
+    const int oc = rem / Cinp, ic = rem % Cinp;
+    const float w = (oc < Cout && ic < Cin) ? W[((int64_t)oc * Cin + ic) * 9 + tap] : 0.f;
+    Wf[g] = to_bf16(w);
+  }
+  {
+    const int ic = rem / Coutp, oc = rem % Coutp;   // Wb[tap][ic][oc]: out channel ic, in channel oc
+    const float w = (oc < Cout && ic < Cin) ? W[((int64_t)oc * Cin + ic) * 9 + (8 - tap)] : 0.f;
+    Wb[g] = to_bf16(w);
+  }
+}
+
+// ------------------------------------------------------------- convolution
+// One 16 x 16 pixel tile of one field per workgroup, all OC output channels
+// (OCT = OC / 16 tiles).  D (16 oc x 16 pixels) = sum over taps and input
+// channels of Wk[tap][oc][ic] X[pixel + tap][ic]: A = weights (lane: oc =
+// l % 16, 4 consecutive ic), B = input (lane: pixel = l % 16, 4 consecutive
+// ic), so each lane holds 4 consecutive output channels of one pixel.
+// Wave w owns output rows 4 w .. 4 w + 3 of the tile.
+//   IN_GELU   input value = GELU(stored value)
+//   MODE 0    out bf16 z = D + bias                           (hidden layers)
+//   MODE 1    out float32 P_hat = Phi + D + bias, oc < k       (last layer)
+//   MODE 2    out bf16 dz_prev = D * GELU'(zprev)              (data gradient)
+template <int OCT, bool IN_GELU, int MODE>
+__global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsigned short* __restrict__ X,
+                                             const unsigned short* __restrict__ Wk, const float* __restrict__ bias,
+                                             const float* __restrict__ phi, const unsigned short* __restrict__ zprev,
+                                             void* __restrict__ out) {
+  constexpr int OC = OCT * 16;
+  extern __shared__ unsigned short lds[];
+  const int xs = ICp + 4;                      // bf16 per staged pixel (padding against bank conflicts)
+  unsigned short* Xs = lds;                    // HALO x HALO x xs
+  unsigned short* Ws = lds + HALO * HALO * xs; // 9 x OC x xs
+  const int b = blockIdx.z;
+  const int ty0 = blockIdx.y * TILE, tx0 = blockIdx.x * TILE;
+  const int64_t n = (int64_t)N * N;
+  const unsigned short* Xb = X + (int64_t)b * n * ICp;
+  // stage the halo tile, 4 channels (8 bytes) per load
+  const int q4 = ICp / 4;
+  for (int e = threadIdx.x; e < HALO * HALO * q4; e += NT) {
+    const int pix = e / q4, c4 = e % q4;
+    const int hy = pix / HALO, hx = pix % HALO;
+    const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+    uint2 v = make_uint2(0u, 0u);
+    if (y >= 0 && y < N && x >= 0 && x < N) {
+      v = *reinterpret_cast<const uint2*>(Xb + ((int64_t)y * N + x) * ICp + 4 * c4);
+      if (IN_GELU) {
+        unsigned short h[4] = {(unsigned short)(v.x & 0xffff), (unsigned short)(v.x >> 16),
+                               (unsigned short)(v.y & 0xffff), (unsigned short)(v.y >> 16)};
+        for (int u = 0; u < 4; ++u) h[u] = to_bf16(gelu(from_bf16(h[u])));
+        v.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
+        v.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+      }
+    }
+    *reinterpret_cast<uint2*>(Xs + pix * xs + 4 * c4) = v;
+  }
+  for (int e = threadIdx.x; e < 9 * OC * q4; e += NT) {
+    const int row = e / q4, c4 = e % q4;      // row = tap * OC + oc
+    *reinterpret_cast<uint2*>(Ws + row * xs + 4 * c4) =
+        *reinterpret_cast<const uint2*>(Wk + (int64_t)row * ICp + 4 * c4);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lp = lane & 15, lg = lane >> 4;
+  f4 acc[4][OCT];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int t = 0; t < OCT; ++t) acc[r][t] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap % 3;     // halo offsets (0..2)
+    for (int ic0 = 0; ic0 < ICp; ic0 += 16) {
+      s4 a[OCT], bv[4];
+#pragma unroll
+      for (int t = 0; t < OCT; ++t)
+        a[t] = *reinterpret_cast<const s4*>(Ws + (tap * OC + 16 * t + lp) * xs + ic0 + 4 * lg);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        bv[r] = *reinterpret_cast<const s4*>(Xs + ((4 * w + r + dy) * HALO + lp + dx) * xs + ic0 + 4 * lg);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int t = 0; t < OCT; ++t) acc[r][t] = mfma_bf16(a[t], bv[r], acc[r][t]);
+    }
+  }
+  // epilogue: lane holds oc = 16 t + 4 lg + v of pixel (row 4 w + r, column lp)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int y = ty0 + 4 * w + r, x = tx0 + lp;
+    if (y >= N || x >= N) continue;
+    const int64_t pix = (int64_t)b * n + (int64_t)y * N + x;
+#pragma unroll
+    for (int t = 0; t < OCT; ++t) {
+      const int oc0 = 16 * t + 4 * lg;
+      if (MODE == 0) {
+        unsigned short h[4];
+        for (int v = 0; v < 4; ++v) h[v] = to_bf16(acc[r][t][v] + bias[oc0 + v]);
+        *reinterpret_cast<uint2*>(static_cast<unsigned short*>(out) + pix * OC + oc0) =
+            make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+      } else if (MODE == 1) {
+        float* P = static_cast<float*>(out);
+        const int64_t pl = (int64_t)y * N + x;
+        for (int v = 0; v < 4; ++v)
+          if (oc0 + v < k) P[pix * k + oc0 + v] = phi[pl * k + oc0 + v] + acc[r][t][v] + bias[oc0 + v];
+      } else {
+        const uint2 zz = *reinterpret_cast<const uint2*>(zprev + pix * OC + oc0);
+        const unsigned short zh[4] = {(unsigned short)(zz.x & 0xffff), (unsigned short)(zz.x >> 16),
+                                      (unsigned short)(zz.y & 0xffff), (unsigned short)(zz.y >> 16)};
+        unsigned short h[4];
+        for (int v = 0; v < 4; ++v) h[v] = to_bf16(acc[r][t][v] * gelu_grad(from_bf16(zh[v])));
+        *reinterpret_cast<uint2*>(static_cast<unsigned short*>(out) + pix * OC + oc0) =
+            make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ weight gradient
+// Partial dW[tap][oc][ic] = sum over the workgroup's pixel tiles of
+// dZ[p][oc] X[p + tap][ic] and db[oc] = sum dZ[p][oc].  D (16 oc x 16 ic)
+// per (tap, oc-tile, ic-tile); the contraction runs over 16 pixels of one
+// image row per step: A = dZ^T (lane: oc = l % 16, 4 consecutive pixels),
+// B = shifted X (lane: 4 consecutive pixels, ic = l % 16).  Both tiles are
+// staged channel-major.  Tiles of the 9 x OCT x ICT outputs are dealt to the
+// 4 waves; a wave holds at most MAXT accumulators.
+constexpr int WG_TILES = 8;          // pixel tiles per workgroup
+template <int MAXT, bool IN_GELU>
+__global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int ntiles_total,
+                                                   const unsigned short* __restrict__ X,
+                                                   const unsigned short* __restrict__ dZ,
+                                                   float* __restrict__ part) {
+  extern __shared__ unsigned short lds[];
+  constexpr int HS = HALO * HALO + 4;          // channel stride of the staged halo tile
+  constexpr int DS = TILE * TILE + 4;          // channel stride of the staged dz tile
+  unsigned short* Xt = lds;                    // ICp x HS
+  unsigned short* Dt = lds + ICp * HS;         // OCp x DS
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lp = lane & 15, lg = lane >> 4;
+  const int ICT = ICp / 16, OCT = OCp / 16;
+  const int nout = 9 * OCT * ICT;
+  f4 acc[MAXT];
+#pragma unroll
+  for (int s = 0; s < MAXT; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+  float dbias = 0.f;                           // lanes of wave 0: oc = threadIdx.x
+  const int tiles_x = (N + TILE - 1) / TILE;
+  const int per_field = tiles_x * tiles_x;
+  const int64_t n = (int64_t)N * N;
+  for (int ti = 0; ti < WG_TILES; ++ti) {
+    const int tile = blockIdx.x * WG_TILES + ti;
+    if (tile >= ntiles_total) break;
+    const int b = tile / per_field, tt = tile % per_field;
+    const int ty0 = (tt / tiles_x) * TILE, tx0 = (tt % tiles_x) * TILE;
+    __syncthreads();
+    for (int e = threadIdx.x; e < HALO * HALO * ICp; e += NT) {
+      const int pix = e / ICp, c = e % ICp;
+      const int y = ty0 + pix / HALO - 1, x = tx0 + pix % HALO - 1;
+      unsigned short v = 0;
+      if (y >= 0 && y < N && x >= 0 && x < N) {
+        v = X[((int64_t)b * n + (int64_t)y * N + x) * ICp + c];
+        if (IN_GELU) v = to_bf16(gelu(from_bf16(v)));
+      }
+      Xt[c * HS + pix] = v;
+    }
+    for (int e = threadIdx.x; e < TILE * TILE * OCp; e += NT) {
+      const int pix = e / OCp, c = e % OCp;
+      const int y = ty0 + pix / TILE, x = tx0 + pix % TILE;
+      unsigned short v = 0;
+      if (y < N && x < N) v = dZ[((int64_t)b * n + (int64_t)y * N + x) * OCp + c];
+      Dt[c * DS + pix] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < OCp)
+      for (int p = 0; p < TILE * TILE; ++p) dbias += from_bf16(Dt[threadIdx.x * DS + p]);
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      const int o = w + 4 * s;
+      if (o >= nout) break;
+      const int tap = o / (OCT * ICT), rem = o % (OCT * ICT);
+      const int ot = rem / ICT, it = rem % ICT;
+      const int dy = tap / 3, dx = tap % 3;
+      for (int row = 0; row < TILE; ++row) {
+        // pixels 4 lg .. 4 lg + 3 of output row `row`
+        const s4 a = *reinterpret_cast<const s4*>(Dt + (16 * ot + lp) * DS + row * TILE + 4 * lg);
+        const unsigned short* xr = Xt + (16 * it + lp) * HS + (row + dy) * HALO + 4 * lg + dx;
+        const s4 bv = s4{(short)xr[0], (short)xr[1], (short)xr[2], (short)xr[3]};
+        acc[s] = mfma_bf16(a, bv, acc[s]);
+      }
+    }
+  }
+  // partial record of this workgroup: [9][OCp][ICp] then [OCp]
+  float* rec = part + (int64_t)blockIdx.x * (9 * OCp * ICp + OCp);
+#pragma unroll
+  for (int s = 0; s < MAXT; ++s) {
+    const int o = w + 4 * s;
+    if (o >= nout) break;
+    const int tap = o / (OCT * ICT), rem = o % (OCT * ICT);
+    const int ot = rem / ICT, it = rem % ICT;
+    for (int v = 0; v < 4; ++v)
+      rec[((int64_t)tap * OCp + 16 * ot + 4 * lg + v) * ICp + 16 * it + lp] = acc[s][v];
+  }
+  if (threadIdx.x < OCp) rec[9 * OCp * ICp + threadIdx.x] = dbias;
+}
+
+// dW (master layout (Cout, Cin, 3, 3)) and db from the partial records,
+// summed over workgroups in order
+__global__ __launch_bounds__(NT) void k_wgrad_reduce(int nrec, int ICp, int OCp, int Cin, int Cout,
+                                                     const float* __restrict__ part, float* __restrict__ gW,
+                                                     float* __restrict__ gb) {
+  const int g = blockIdx.x * NT + threadIdx.x;
+  const int nW = Cout * Cin * 9;
+  if (g >= nW + Cout) return;
+  int64_t src;
+  if (g < nW) {
+    const int oc = g / (Cin * 9), ic = (g / 9) % Cin, tap = g % 9;
+    src = ((int64_t)tap * OCp + oc) * ICp + ic;
+  } else {
+    src = (int64_t)9 * OCp * ICp + (g - nW);
+  }
+  const int64_t stride = 9 * OCp * ICp + OCp;
+  double s = 0.0;
+  for (int r0 = 0; r0 < nrec; r0 += 8) {     // eight loads in flight, added in order
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (r0 + j < nrec) ? part[(r0 + j) * stride + src] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += (double)v[j];
+  }
+  if (g < nW)
+    gW[g] = (float)s;
+  else
+    gb[g - nW] = (float)s;
+}
+
+// float32 -> bfloat16 with channel padding: (rows, C) -> (rows, Cp)
+__global__ __launch_bounds__(NT) void k_pad_bf16(int64_t rows, int C, int Cp, const float* __restrict__ src,
+                                                 unsigned short* __restrict__ dst) {
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (g >= rows * Cp) return;
+  const int c = (int)(g % Cp);
+  const int64_t r = g / Cp;
+  dst[g] = to_bf16(c < C ? src[r * C + c] : 0.f);
+}
+
+// Adam (bias-corrected) on float32 parameters
+__global__ __launch_bounds__(NT) void k_adam(int64_t count, float* __restrict__ p, const float* __restrict__ g,
+                                             float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                             float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------- host side
+struct Net {
+  int batch, N, k, ch;
+  int64_t n;
+  int cin[4], cout[4], cinp[4], coutp[4];
+  int64_t woff[4], boff[4];   // offsets of W_l and b_l in the parameter vector
+  int64_t nparams;
+};
+
+inline int r16(int v) { return (v + 15) / 16 * 16; }
+
+inline bool make_net(const nlsp_cnn_shape* s, Net& t) {
+  if (!s || s->batch < 1 || s->N < TILE || s->k < 1 || s->k > 64 || s->hidden < 1 || s->hidden > 64) return false;
+  if (s->k % 16 || s->hidden % 16) return false;
+  if ((int64_t)s->batch * s->N * s->N * 64 >= (int64_t(1) << 31)) return false;
+  t.batch = s->batch;
+  t.N = s->N;
+  t.k = s->k;
+  t.ch = s->hidden;
+  t.n = (int64_t)s->N * s->N;
+  const int cin[4] = {1 + s->k, s->hidden, s->hidden, s->hidden};
+  const int cout[4] = {s->hidden, s->hidden, s->hidden, s->k};
+  int64_t off = 0;
+  for (int l = 0; l < 4; ++l) {
+    t.cin[l] = cin[l];
+    t.cout[l] = cout[l];
+    t.cinp[l] = r16(cin[l]);
+    t.coutp[l] = r16(cout[l]);
+    t.woff[l] = off;
+    off += (int64_t)cout[l] * cin[l] * 9;
+    t.boff[l] = off;
+    off += cout[l];
+  }
+  t.nparams = off;
+  return true;
+}
+
+struct NetLayout {
+  double* stats;                 // (batch, 2)
+  int* modes;                    // (k, 2)
+  float* phi;                    // (n, k)
+  unsigned short* x0;            // (batch n, cinp[0])
+  unsigned short* z[3];          // (batch n, ch) pre-activations of layers 1..3
+  unsigned short* wf[4];         // forward weights per layer
+  unsigned short* wb[4];         // data-gradient weights per layer
+  unsigned short* dz[4];         // (batch n, coutp[l]) gradients of the pre-activations
+  float* part;                   // weight-gradient partial records
+  size_t bytes;
+};
+
+inline int wgrad_groups(const Net& t) {
+  const int tx = (t.N + TILE - 1) / TILE;
+  const int tiles = t.batch * tx * tx;
+  return (tiles + WG_TILES - 1) / WG_TILES;
+}
+
+inline NetLayout carve_net(void* ws, const Net& t) {
+  Carver c(ws);
+  NetLayout L;
+  L.stats = c.take<double>(2 * t.batch);
+  L.modes = c.take<int>(2 * t.k);
+  L.phi = c.take<float>(t.n * t.k);
+  const int64_t bn = t.batch * t.n;
+  L.x0 = c.take<unsigned short>(bn * t.cinp[0]);
+  for (int l = 0; l < 3; ++l) L.z[l] = c.take<unsigned short>(bn * t.coutp[l]);
+  int64_t maxrec = 0;
+  for (int l = 0; l < 4; ++l) {
+    L.wf[l] = c.take<unsigned short>((size_t)9 * t.coutp[l] * t.cinp[l]);
+    L.wb[l] = c.take<unsigned short>((size_t)9 * t.coutp[l] * t.cinp[l]);
+    L.dz[l] = c.take<unsigned short>(bn * t.coutp[l]);
+    maxrec = std::max<int64_t>(maxrec, 9 * t.coutp[l] * t.cinp[l] + t.coutp[l]);
+  }
+  L.part = c.take<float>((size_t)wgrad_groups(t) * maxrec);
+  L.bytes = c.bytes();
+  return L;
+}
+
+inline size_t conv_lds(int ICp, int OC) { return ((size_t)HALO * HALO * (ICp + 4) + (size_t)9 * OC * (ICp + 4)) * 2; }
+inline size_t wgrad_lds(int ICp, int OCp) {
+  return ((size_t)ICp * (HALO * HALO + 4) + (size_t)OCp * (TILE * TILE + 4)) * 2;
+}
+
+template <typename K>
+inline hipError_t allow(K kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+// k smoothest sine modes (i, j >= 1) by i^2 + j^2, ties by i
+inline std::vector<int> smooth_modes(int k) {
+  std::vector<std::pair<int, std::pair<int, int>>> all;
+  for (int i = 1; i <= 64; ++i)
+    for (int j = 1; j <= 64; ++j) all.push_back({i * i + j * j, {i, j}});
+  std::sort(all.begin(), all.end());
+  std::vector<int> m;
+  for (int q = 0; q < k; ++q) {
+    m.push_back(all[q].second.first);
+    m.push_back(all[q].second.second);
+  }
+  return m;
+}
+
+// launch one convolution: input X (ICp channels), weights Wk (OC x ICp per tap)
+template <bool IN_GELU, int MODE>
+inline int conv(const Net& t, int ICp, int OC, const unsigned short* X, const unsigned short* Wk, const float* bias,
+                const float* phi, const unsigned short* zprev, void* out, hipStream_t s) {
+  const int tx = (t.N + TILE - 1) / TILE;
+  const dim3 grid(tx, tx, t.batch);
+  const size_t lds = conv_lds(ICp, OC);
+  auto go = [&](auto kern) -> int {
+    if (allow(kern, lds) != hipSuccess) return NLSP_E_HIP;
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, t.N, ICp, t.k, X, Wk, bias, phi, zprev, out);
+    return NLSP_OK;
+  };
+  switch (OC / 16) {
+    case 1: return go(k_conv<1, IN_GELU, MODE>);
+    case 2: return go(k_conv<2, IN_GELU, MODE>);
+    case 3: return go(k_conv<3, IN_GELU, MODE>);
+    default: return go(k_conv<4, IN_GELU, MODE>);
+  }
+}
+
+template <bool IN_GELU>
+inline int wgrad(const Net& t, int l, const unsigned short* X, const unsigned short* dZ, float* part, float* gW,
+                 float* gb, hipStream_t s) {
+  const int ICp = t.cinp[l], OCp = t.coutp[l];
+  const int groups = wgrad_groups(t);
+  const int tx = (t.N + TILE - 1) / TILE;
+  const int tiles = t.batch * tx * tx;
+  const size_t lds = wgrad_lds(ICp, OCp);
+  const int need = (9 * (OCp / 16) * (ICp / 16) + 3) / 4;
+  auto go = [&](auto kern) -> int {
+    if (allow(kern, lds) != hipSuccess) return NLSP_E_HIP;
+    hipLaunchKernelGGL(kern, dim3(groups), dim3(NT), lds, s, t.N, ICp, OCp, tiles, X, dZ, part);
+    return NLSP_OK;
+  };
+  int rc;
+  if (need <= 9)
+    rc = go(k_conv_wgrad<9, IN_GELU>);
+  else if (need <= 18)
+    rc = go(k_conv_wgrad<18, IN_GELU>);
+  else
+    rc = go(k_conv_wgrad<36, IN_GELU>);
+  if (rc != NLSP_OK) return rc;
+  const int nout = t.cout[l] * t.cin[l] * 9 + t.cout[l];
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(nout, NT)), dim3(NT), 0, s, groups, ICp, OCp, t.cin[l],
+                     t.cout[l], part, gW, gb);
+  return NLSP_OK;
+}
+
+}  // namespace cnn
+}  // namespace nlsp
+
+using namespace nlsp;
+using namespace nlsp::cnn;
+
+extern "C" {
+
+int64_t cnn_param_count(const nlsp_cnn_shape* shape) {
+  Net t;
+  return make_net(shape, t) ? t.nparams : -1;
+}
+
+size_t cnn_workspace_bytes(const nlsp_cnn_shape* shape) {
+  Net t;
+  if (!make_net(shape, t)) return 0;
+  const size_t need = std::max({conv_lds(t.cinp[0], t.coutp[0]), conv_lds(t.ch, t.ch), wgrad_lds(t.cinp[0], t.ch),
+                                wgrad_lds(t.ch, t.ch), wgrad_lds(t.ch, t.k)});
+  if (need > 160 * 1024) return 0;
+  return carve_net(nullptr, t).bytes;
+}
+
+int cnn_fwd(const nlsp_cnn_shape* shape, const float* params, const double* coef, float* Phat, void* ws,
+            size_t ws_bytes, void* stream) {
+  Net t;
+  if (!make_net(shape, t) || !params || !coef || !Phat) return NLSP_E_INVALID;
+  const size_t need = cnn_workspace_bytes(shape);
+  if (need == 0) return NLSP_E_INVALID;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const NetLayout L = carve_net(ws, t);
+  hipStream_t s = as_stream(stream);
+  const std::vector<int> modes = smooth_modes(t.k);
+  NLSP_HIP(hipMemcpyAsync(L.modes, modes.data(), sizeof(int) * modes.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_sine_modes, dim3(ceil_div(t.n * t.k, NT)), dim3(NT), 0, s, t.N, t.k, L.modes, L.phi);
+  hipLaunchKernelGGL(k_field_stats, dim3(t.batch), dim3(NT), 0, s, coef, (int)t.n, L.stats);
+  hipLaunchKernelGGL(k_cnn_input, dim3(ceil_div(t.n * t.cinp[0], NT), t.batch), dim3(NT), 0, s, coef, L.stats,
+                     L.phi, (int)t.n, t.k, t.cinp[0], L.x0);
+  for (int l = 0; l < 4; ++l)
+    hipLaunchKernelGGL(k_prep_weights, dim3(ceil_div(9 * t.coutp[l] * t.cinp[l], NT)), dim3(NT), 0, s,
+                       params + t.woff[l], t.cin[l], t.cout[l], t.cinp[l], t.coutp[l], L.wf[l], L.wb[l]);
+  int rc = conv<false, 0>(t, t.cinp[0], t.ch, L.x0, L.wf[0], params + t.boff[0], nullptr, nullptr, L.z[0], s);
+  if (rc == NLSP_OK) rc = conv<true, 0>(t, t.ch, t.ch, L.z[0], L.wf[1], params + t.boff[1], nullptr, nullptr, L.z[1], s);
+  if (rc == NLSP_OK) rc = conv<true, 0>(t, t.ch, t.ch, L.z[1], L.wf[2], params + t.boff[2], nullptr, nullptr, L.z[2], s);
+  if (rc == NLSP_OK) rc = conv<true, 1>(t, t.ch, t.k, L.z[2], L.wf[3], params + t.boff[3], L.phi, nullptr, Phat, s);
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  // the modes table is a host local: its copy must finish before return
+  NLSP_HIP(hipStreamSynchronize(s));
+  return NLSP_OK;
+}
+
+int cnn_bwd(const nlsp_cnn_shape* shape, const float* params, const float* gPhat, float* gparams, void* ws,
+            size_t ws_bytes, void* stream) {
+  Net t;
+  if (!make_net(shape, t) || !params || !gPhat || !gparams) return NLSP_E_INVALID;
+  const size_t need = cnn_workspace_bytes(shape);
+  if (need == 0) return NLSP_E_INVALID;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const NetLayout L = carve_net(ws, t);
+  hipStream_t s = as_stream(stream);
+  const int64_t bn = t.batch * t.n;
+  // dz4 = dP_hat (the residual Phi and the bias add pass gradients through)
+  hipLaunchKernelGGL(k_pad_bf16, dim3(ceil_div(bn * t.coutp[3], NT)), dim3(NT), 0, s, bn, t.k, t.coutp[3], gPhat,
+                     L.dz[3]);
+  int rc = wgrad<true>(t, 3, L.z[2], L.dz[3], L.part, gparams + t.woff[3], gparams + t.boff[3], s);
+  // dz3 = (W4^T * dz4) GELU'(z3), and so on down to layer 1
+  for (int l = 3; l >= 1 && rc == NLSP_OK; --l) {
+    rc = conv<false, 2>(t, t.coutp[l], t.cinp[l], L.dz[l], L.wb[l], nullptr, nullptr, L.z[l - 1], L.dz[l - 1], s);
+    if (rc != NLSP_OK) break;
+    if (l - 1 >= 1)
+      rc = wgrad<true>(t, l - 1, L.z[l - 2], L.dz[l - 1], L.part, gparams + t.woff[l - 1], gparams + t.boff[l - 1], s);
+    else
+      rc = wgrad<false>(t, 0, L.x0, L.dz[0], L.part, gparams + t.woff[0], gparams + t.boff[0], s);
+  }
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+int adam_step(int64_t count, float* params, const float* grads, float* m, float* v, float lr, float beta1,
+              float beta2, float eps, int step, void* stream) {
+  if (count < 1 || !params || !grads || !m || !v || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+      !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return NLSP_E_INVALID;
+  const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(ceil_div(count, NT)), dim3(NT), 0, as_stream(stream), count, params, grads, m, v,
+                     lr, beta1, beta2, eps, c1, c2);
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+}  // extern "C"

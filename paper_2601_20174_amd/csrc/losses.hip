@@ -468,6 +468,143 @@ __global__ __launch_bounds__(NT) void k_gal_bwd_prep(int k, int kp, const float*
   }
 }
 
+// ------------------------------------------------------------- thin QR
+// A = Q R (A: n x k per sample, R upper with positive diagonal) by
+// CholeskyQR2: G = A^T A = R1^T R1, Q1 = A R1^-1, then once more on Q1, and
+// R = R2 R1.  The backward (only Q is used downstream) is
+//   dA = [dQ + Q copyltu(M)] R^-T,   M = -dQ^T Q,
+// copyltu(M) the symmetric matrix with M's lower triangle, evaluated as
+// [dQ | Q] [R^-T ; copyltu(M) R^-T] with the product kernels.
+constexpr int QRK = 64;
+
+// G (k x k) from the slab sums of T = P^T B (tiles row-major, no G tiles),
+// symmetrised
+NLSP_DEV void load_gram(const Dims& d, const double* tb, double* G) {
+  for (int e = threadIdx.x; e < d.k * d.k; e += NT) {
+    const int i = e / d.k, j = e % d.k;
+    auto at = [&](int a, int c) {
+      const int id = (a >> 4) * d.MT + (c >> 4), r = a & 15;
+      return tb[id * 256 + (r & 3) * 64 + (r >> 2) * 16 + (c & 15)];
+    };
+    G[i * QRK + j] = 0.5 * (at(i, j) + at(j, i));
+  }
+}
+
+// upper Cholesky factor R of G (G = R^T R) in place, and X = R^-1 (upper);
+// returns false (in every thread) if a pivot is not positive
+NLSP_DEV bool chol_inv(int k, double* G, double* X) {
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int i = 0; i < k; ++i) {
+    if (threadIdx.x == 0) {
+      double d = G[i * QRK + i];
+      for (int p = 0; p < i; ++p) d -= G[p * QRK + i] * G[p * QRK + i];
+      if (!(d > 0.0)) {
+        s_bad = 1;
+        d = 1.0;
+      }
+      G[i * QRK + i] = sqrt(d);
+    }
+    __syncthreads();
+    for (int j = i + 1 + threadIdx.x; j < k; j += NT) {
+      double v = G[i * QRK + j];
+      for (int p = 0; p < i; ++p) v -= G[p * QRK + i] * G[p * QRK + j];
+      G[i * QRK + j] = v / G[i * QRK + i];
+    }
+    __syncthreads();
+  }
+  // R^-1 by columns (upper triangular back substitution), one thread per column
+  for (int j = threadIdx.x; j < k; j += NT) {
+    for (int i = 0; i < k; ++i) X[i * QRK + j] = 0.0;
+    X[j * QRK + j] = 1.0 / G[j * QRK + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int p = i + 1; p <= j; ++p) v += G[i * QRK + p] * X[p * QRK + j];
+      X[i * QRK + j] = -v / G[i * QRK + i];
+    }
+  }
+  __syncthreads();
+  return s_bad == 0;
+}
+
+// pass 1 (first = 1): R1 from G = A^T A, M = R1^-1, Rprev = R1
+// pass 2 (first = 0): R2 from G = Q1^T Q1, M = R2^-1, R = R2 Rprev
+// M is (kp x kp) float32 row-major; R (k x k) float64; bad[b] |= 1 if a pivot
+// was not positive
+__global__ __launch_bounds__(NT) void k_qr_small(Dims d, const double* __restrict__ T64, int first,
+                                                 double* __restrict__ Rprev, double* __restrict__ Rout,
+                                                 float* __restrict__ M, int* __restrict__ bad) {
+  __shared__ double G[QRK * QRK];
+  __shared__ double X[QRK * QRK];
+  const int b = blockIdx.x, k = d.k, kp = d.kp;
+  load_gram(d, T64 + (int64_t)b * d.ntiles * 256, G);
+  __syncthreads();
+  const bool ok = chol_inv(k, G, X);
+  if (threadIdx.x == 0 && !ok) bad[b] = 1;
+  for (int e = threadIdx.x; e < kp * kp; e += NT) {
+    const int i = e / kp, j = e % kp;
+    M[(int64_t)b * kp * kp + e] = (i < k && j < k) ? (float)X[i * QRK + j] : 0.f;
+  }
+  double* Rp = Rprev + (int64_t)b * k * k;
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int i = e / k, j = e % k;
+    if (first) {
+      Rp[e] = (j >= i) ? G[i * QRK + j] : 0.0;
+    } else {
+      double v = 0.0;   // (R2 R1)_ij = sum_{i <= p <= j} R2_ip R1_pj
+      for (int p = i; p <= j; ++p) v += G[i * QRK + p] * Rp[p * k + j];
+      Rout[(int64_t)b * k * k + e] = (j >= i) ? v : 0.0;
+    }
+  }
+}
+
+// backward: from T = Q^T dQ (slab sums) and R, the stacked (2 kp x kp) matrix
+// [R^-T ; C R^-T] with C_ij = -T[min(i,j)][max(i,j)] (= copyltu(-dQ^T Q))
+__global__ __launch_bounds__(NT) void k_qr_bwd_small(Dims d, const double* __restrict__ T64,
+                                                     const double* __restrict__ R, float* __restrict__ M) {
+  __shared__ double G[QRK * QRK];   // R, then reused
+  __shared__ double X[QRK * QRK];   // R^-1
+  __shared__ double C[QRK * QRK];
+  const int b = blockIdx.x, k = d.k, kp = d.kp;
+  const double* Rb = R + (int64_t)b * k * k;
+  const double* tb = T64 + (int64_t)b * d.ntiles * 256;
+  auto at = [&](int a, int c) {
+    const int id = (a >> 4) * d.MT + (c >> 4), r = a & 15;
+    return tb[id * 256 + (r & 3) * 64 + (r >> 2) * 16 + (c & 15)];
+  };
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int i = e / k, j = e % k;
+    G[i * QRK + j] = Rb[e];
+    C[i * QRK + j] = -at(min(i, j), max(i, j));
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += NT) {
+    for (int i = 0; i < k; ++i) X[i * QRK + j] = 0.0;
+    X[j * QRK + j] = 1.0 / G[j * QRK + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int p = i + 1; p <= j; ++p) v += G[i * QRK + p] * X[p * QRK + j];
+      X[i * QRK + j] = -v / G[i * QRK + i];
+    }
+  }
+  __syncthreads();
+  float* Mb = M + (int64_t)b * 2 * kp * kp;
+  for (int e = threadIdx.x; e < 2 * kp * kp; e += NT) {
+    const int r = e / kp, j = e % kp;
+    double v = 0.0;
+    if (j < k) {
+      if (r < kp) {
+        if (r < k) v = X[j * QRK + r];                       // (R^-T)_rj = (R^-1)_jr
+      } else if (r - kp < k) {
+        const int i = r - kp;                                // (C R^-T)_ij = sum_p C_ip (R^-1)_jp
+        for (int p = j; p < k; ++p) v += C[i * QRK + p] * X[j * QRK + p];
+      }
+    }
+    Mb[e] = (float)v;
+  }
+}
+
 struct SubLayout {
   float* part;
   double* bbpart;
@@ -594,6 +731,34 @@ inline bool aligned16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 1
 
 extern "C" {
 
+// thin QR dims: products P^T B with B an n x k block (tiles of P^T B only)
+inline Dims qr_dims(int batch, int n, int k, bool stage_p) { return make_dims(batch, n, k, k, false, stage_p); }
+inline bool qr_ok(int batch, int64_t n, int k) {
+  if (batch < 1 || n < k || k < 1 || k > QRK || n * k >= (int64_t(1) << 31)) return false;
+  const Dims d = qr_dims(batch, (int)n, k, true);
+  return d.ntiles <= MAX_TILES && fwd_lds(d) <= LDS_MAX && bwd_lds(d) <= LDS_MAX;
+}
+
+struct QrLayout {
+  SubLayout prod;
+  float* Q1;        // (batch, n, k)
+  float* M;         // (batch, 2 kp, kp)
+  double* R1;       // (batch, k, k)
+  size_t bytes;
+};
+
+inline QrLayout carve_qr(void* ws, int batch, int n, int k) {
+  const Dims d = qr_dims(batch, n, k, true);
+  QrLayout L;
+  L.prod = carve_sub(ws, batch, d);
+  Carver c(ws ? static_cast<char*>(ws) + L.prod.bytes : nullptr);
+  L.Q1 = c.take<float>((size_t)batch * n * k);
+  L.M = c.take<float>((size_t)batch * 2 * d.kp * d.kp);
+  L.R1 = c.take<double>((size_t)batch * k * k);
+  L.bytes = L.prod.bytes + c.bytes();
+  return L;
+}
+
 size_t subspace_loss_saved_bytes(int batch, int n, int k, int m) {
   if (!dims_ok(batch, n, k, m)) return 0;
   return saved_bytes(batch, make_dims(batch, n, k, m));
@@ -684,6 +849,56 @@ int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, floa
   hipLaunchKernelGGL(k_gal_bwd_prep, dim3(batch), dim3(NT), 0, s, k, d.kp, gAc, M);
   // gP = [Y] (G + G^T): Y is the "B" block, no P block
   const int rc = launch_bwd(d, batch, Y, Y, M, nullptr, gP, s);
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+size_t qr_thin_workspace_bytes(int batch, int n, int k) {
+  if (!qr_ok(batch, n, k)) return 0;
+  return carve_qr(nullptr, batch, n, k).bytes;
+}
+
+int qr_thin_fwd(int batch, int n, int k, const float* A, float* Q, double* R, int* bad, void* ws, size_t ws_bytes,
+                void* stream) {
+  if (!qr_ok(batch, n, k) || !A || !Q || !R || !bad || A == Q) return NLSP_E_INVALID;
+  if (!ws_ok(ws, ws_bytes, carve_qr(nullptr, batch, n, k).bytes)) return NLSP_E_WORKSPACE;
+  const QrLayout L = carve_qr(ws, batch, n, k);
+  hipStream_t s = as_stream(stream);
+  Dims dp = qr_dims(batch, n, k, true);       // P^T B
+  Dims db = qr_dims(batch, n, k, false);      // B M
+  if (!aligned16(A) || !aligned16(Q)) dp.vec = db.vec = 0;
+  NLSP_HIP(hipMemsetAsync(bad, 0, sizeof(int) * batch, s));
+  // pass 1: G = A^T A, R1, Q1 = A R1^-1
+  int rc = launch_products(dp, batch, A, A, L.prod, s);
+  if (rc != NLSP_OK) return rc;
+  hipLaunchKernelGGL(k_qr_small, dim3(batch), dim3(NT), 0, s, dp, L.prod.T64, 1, L.R1, R, L.M, bad);
+  rc = launch_bwd(db, batch, A, A, L.M, nullptr, L.Q1, s);
+  if (rc != NLSP_OK) return rc;
+  // pass 2: G = Q1^T Q1, R2, Q = Q1 R2^-1, R = R2 R1
+  rc = launch_products(dp, batch, L.Q1, L.Q1, L.prod, s);
+  if (rc != NLSP_OK) return rc;
+  hipLaunchKernelGGL(k_qr_small, dim3(batch), dim3(NT), 0, s, dp, L.prod.T64, 0, L.R1, R, L.M, bad);
+  rc = launch_bwd(db, batch, L.Q1, L.Q1, L.M, nullptr, Q, s);
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+int qr_thin_bwd(int batch, int n, int k, const float* Q, const double* R, const float* gQ, float* gA, void* ws,
+                size_t ws_bytes, void* stream) {
+  if (!qr_ok(batch, n, k) || !Q || !R || !gQ || !gA || gA == Q || gA == gQ) return NLSP_E_INVALID;
+  if (!ws_ok(ws, ws_bytes, carve_qr(nullptr, batch, n, k).bytes)) return NLSP_E_WORKSPACE;
+  const QrLayout L = carve_qr(ws, batch, n, k);
+  hipStream_t s = as_stream(stream);
+  Dims dp = qr_dims(batch, n, k, true);
+  if (!aligned16(Q) || !aligned16(gQ) || !aligned16(gA)) dp.vec = 0;
+  // T = Q^T dQ (A operand Q, B block dQ)
+  int rc = launch_products(dp, batch, Q, gQ, L.prod, s);
+  if (rc != NLSP_OK) return rc;
+  hipLaunchKernelGGL(k_qr_bwd_small, dim3(batch), dim3(NT), 0, s, dp, L.prod.T64, R, L.M);
+  // dA = [dQ | Q] [R^-T ; C R^-T]
+  rc = launch_bwd(dp, batch, Q, gQ, L.M, nullptr, gA, s);
   if (rc != NLSP_OK) return rc;
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;

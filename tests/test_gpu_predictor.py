@@ -1,0 +1,157 @@
+"""GPU parity of the P-predictor pieces against the float64 oracle, through
+the C ABI (marked gpu): thin QR forward/backward, CNN forward/backward, Adam,
+and a short training run.
+
+Tolerances (derived from the arithmetic):
+  * thin QR: CholeskyQR2 from float32 data with float64 Gram matrices; Q is
+    stored in float32: |Q - Q_ref| <= 64 kappa(A) u32, |R - R_ref| <=
+    64 kappa(A) u32 |R|, ||Q^T Q - I|| <= 64 k u32 (u32 = 2^-24).  The
+    backward: relative Frobenius error <= 256 kappa(A)^2 u32.
+  * CNN forward: bfloat16 inputs, weights and stored pre-activations, float32
+    accumulation: twice the first-order bound propagated by
+    oracle.predictor.cnn_error_bound.
+  * CNN parameter gradients: every product of the backward rounds both
+    operands to bfloat16 (2^-9) and the data gradients are stored in
+    bfloat16; over the four layers and their backward this first-order
+    relative error stays below 8 x 3 x 2^-9 ~ 5%, which bounds the relative
+    Frobenius error of each layer's gradient.
+  * Adam: float32 update, relative 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import predictor as PR
+import oracle as O
+import workloads as W
+from tests._cases import host
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def nl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20174_amd as mod
+    return mod
+
+
+@pytest.mark.parametrize("n,k", [(200, 5), (1000, 16), (777, 32), (5000, 64)])
+def test_thin_qr_fwd_bwd(nl, n, k):
+    rng = np.random.default_rng(k)
+    batch = 3
+    A = (rng.standard_normal((batch, n, k)) + 0.3).astype(np.float32)
+    gQ = rng.standard_normal((batch, n, k)).astype(np.float32)
+    Q, R, bad = nl.qr_thin_fwd(torch.tensor(A, device="cuda"))
+    gA = host(nl.qr_thin_bwd(Q, R, torch.tensor(gQ, device="cuda")))
+    Q, R = host(Q), host(R)
+    assert host(bad).sum() == 0
+    for b in range(batch):
+        A64 = A[b].astype(np.float64)
+        kap = np.linalg.cond(A64)
+        Qr, Rr = PR.qf(A64)
+        assert np.abs(Q[b] - Qr).max() <= 64 * kap * U32
+        assert np.abs(R[b] - Rr).max() <= 64 * kap * U32 * np.abs(Rr).max()
+        assert np.abs(Q[b].astype(np.float64).T @ Q[b] - np.eye(k)).max() <= 64 * k * U32
+        gr = PR.qr_backward(Qr, Rr, gQ[b].astype(np.float64))
+        assert np.linalg.norm(gA[b] - gr) <= 256 * kap ** 2 * U32 * np.linalg.norm(gr)
+
+
+def _params(k, hid, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci in PR.layer_shapes(k, hid):
+        parts.append(rng.standard_normal(co * ci * 9) * scale * np.sqrt(2.0 / (ci * 9)))
+        parts.append(rng.standard_normal(co) * 0.1)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _fields(batch, N, seed):
+    return np.stack([W.lognormal_field(seed + b, N).ravel() for b in range(batch)])
+
+
+@pytest.mark.parametrize("N,k,hid", [(32, 16, 16), (40, 16, 32), (48, 32, 32)])
+def test_cnn_forward(nl, N, k, hid):
+    batch = 2
+    p = _params(k, hid, 1)
+    coef = _fields(batch, N, 10)
+    ws = torch.empty(nl.cnn_workspace_bytes(batch, N, k, hid), dtype=torch.uint8, device="cuda")
+    Phat = host(nl.cnn_fwd(torch.tensor(p, device="cuda"), torch.tensor(coef, device="cuda"), N, k, hid, ws))
+    ref = PR.cnn_forward(p.astype(np.float64), coef, N, k, hid)
+    bound = PR.cnn_error_bound(p.astype(np.float64), coef, N, k, hid)
+    err = np.abs(Phat - ref)
+    assert np.all(err <= 2 * bound + 2 * U32 * np.abs(ref)), (err.max(), bound.max())
+    assert err.max() > 0          # the bfloat16 path is not the float64 oracle
+
+
+@pytest.mark.parametrize("N,k,hid", [(32, 16, 16), (48, 32, 32)])
+def test_cnn_backward(nl, N, k, hid):
+    batch = 2
+    p = _params(k, hid, 2)
+    coef = _fields(batch, N, 20)
+    Wt = np.random.default_rng(3).standard_normal((batch, N * N, k))
+    ws = torch.empty(nl.cnn_workspace_bytes(batch, N, k, hid), dtype=torch.uint8, device="cuda")
+    pt = torch.tensor(p, device="cuda")
+    ct = torch.tensor(coef, device="cuda")
+    nl.cnn_fwd(pt, ct, N, k, hid, ws)
+    g = host(nl.cnn_bwd(pt, torch.tensor(Wt, dtype=torch.float32, device="cuda"), N, k, hid, ws))
+    leaf, Phat = PR.cnn_forward(p.astype(np.float64), coef, N, k, hid, return_graph=True)
+    (Phat * torch.tensor(Wt)).sum().backward()
+    gr = leaf.grad.numpy()
+    off = 0
+    for co, ci in PR.layer_shapes(k, hid):
+        for size in (co * ci * 9, co):
+            a, r = g[off:off + size], gr[off:off + size]
+            assert np.linalg.norm(a - r) <= 0.05 * np.linalg.norm(r), (off, size)
+            off += size
+    # (no finite-difference check of the GPU forward here: its bfloat16
+    # rounding noise, about sqrt(#outputs) 2^-9 |P_hat| / (2 h), is as large as
+    # the directional derivative itself; the float64 autograd above is the
+    # reference, and the oracle's own gradient is pinned on the CPU)
+
+
+def test_adam(nl):
+    rng = np.random.default_rng(5)
+    n = 10000
+    p0, g = rng.standard_normal(n), rng.standard_normal(n)
+    m0, v0 = rng.standard_normal(n) * 0.1, np.abs(rng.standard_normal(n)) * 0.1
+    pt, gt = torch.tensor(p0, dtype=torch.float32, device="cuda"), torch.tensor(g, dtype=torch.float32, device="cuda")
+    mt, vt = torch.tensor(m0, dtype=torch.float32, device="cuda"), torch.tensor(v0, dtype=torch.float32, device="cuda")
+    nl.adam_step(pt, gt, mt, vt, 1e-3, 7)
+    pr, mr, vr = PR.adam_update(p0.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64),
+                                m0.astype(np.float32).astype(np.float64), v0.astype(np.float32).astype(np.float64),
+                                1e-3, 7)
+    np.testing.assert_allclose(host(mt), mr, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(host(vt), vr, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(host(pt), pr, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_nlss_and_gives_a_working_preconditioner(nl):
+    """Ten Adam steps on four 32^2 fields lower the NLSS loss, and the learned
+    basis (orthonormal by construction) preconditions PCG to 1e-8."""
+    from paper_2601_20174_amd.predictor import Predictor
+    N, k, m, batch = 32, 16, 32, 4
+    coefs = _fields(batch, N, 40)
+    ct = torch.tensor(coefs, device="cuda")
+    Bs = []
+    for b in range(batch):
+        op = nl.Operator(nl.OP_FV5, N, N, 1, ct[b].contiguous())
+        x = torch.tensor(W.normal_block(500 + b, N * N, m), dtype=torch.float32, device="cuda")
+        zero = torch.zeros_like(x)
+        for _ in range(10):
+            x = nl.jacobi_sweep_f32(op, 2 / 3, zero, x)
+        Bs.append(x)
+    B = torch.stack(Bs)
+    pred = Predictor(N, k, hidden=16, seed=0)
+    losses = [pred.step(ct, B, lr=3e-3) for _ in range(10)]
+    assert losses[-1] < losses[0]
+    Q = pred.basis(ct).detach()
+    qh = host(Q[0]).astype(np.float64)
+    np.testing.assert_allclose(qh.T @ qh, np.eye(k), atol=64 * k * U32)
+    op = nl.Operator(nl.OP_FV5, N, N, 1, ct[0].contiguous())
+    M = nl.galerkin_coarse(op, Q[0].double().contiguous(), 2 / 3, 1)
+    f = torch.tensor(W.normal_block(600, N * N, 1), device="cuda")
+    u, info, rc = nl.pcg_solve(op, M, f, prec=nl.FP64, rtol=1e-8)
+    assert rc == nl.OK and info[0].relres <= 1e-8

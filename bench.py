@@ -181,6 +181,7 @@ def main():
         out["spmv"] = spmv_legs(nl, torch, dev)
         out["training"] = training_legs(nl, torch, dev)
         out["batched"] = batched_legs(nl, torch, dev)
+        out["predictor"] = predictor_leg(nl, torch, dev)
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, coef, S0h, fh, out.get("fp64", {}).get("iters", out["iters"]))
@@ -342,6 +343,71 @@ def batched_legs(nl, torch, dev, nsys=None):
                                   "iters_max": int(max(f64_iters)), "relres_max": f64_worst},
             "speedup_solve": round(s_ms / b_ms, 2),
             "speedup_setup_plus_solve": round((setup_ms + s_ms) / (setup_ms + b_ms), 3)}
+
+
+def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
+    """P-predictor on the training workload (64 log-normal fields of 128^2,
+    k = 32, m = 64 relaxed vectors per field, hidden width 32): time of one
+    training step (CNN forward, thin QR, NLSS loss, their backward, Adam),
+    then `train_steps` steps and, on held-out fields, PCG iterations
+    (float64, rtol 1e-8) with the learned basis against the SVD basis of the
+    same relaxed vectors."""
+    import workloads as W
+    from paper_2601_20174_amd.predictor import Predictor
+    c5 = W.Cfg5()
+    N, k, m, batch = c5.N, c5.k, c5.m, c5.batch
+    n = N * N
+
+    def fields(ids):
+        coef = torch.tensor(np.stack([c5.coef(i).ravel() for i in ids]), dtype=torch.float64, device=dev)
+        Bs = []
+        for j, i in enumerate(ids):
+            op = nl.Operator(nl.OP_FV5, N, N, 1, coef[j].contiguous())
+            x = torch.tensor(c5.S0(i), dtype=torch.float32, device=dev)
+            zero = torch.zeros_like(x)
+            for _ in range(c5.s1):
+                x = nl.jacobi_sweep_f32(op, c5.omega, zero, x)
+            Bs.append(x)
+        return coef, torch.stack(Bs)
+
+    coef, B = fields(range(batch))
+    pred = Predictor(N, k, hidden=32, seed=5)
+    pred.step(coef, B)                      # warm-up (workspaces, kernels)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        pred.step(coef, B)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / reps
+    losses = [pred.step(coef, B, lr=1e-3) for _ in range(train_steps)]
+    # held-out fields: learned basis vs SVD basis of the same relaxed vectors
+    ids = list(range(batch + 100, batch + 100 + held_out))
+    hcoef, hB = fields(ids)
+    Q = pred.basis(hcoef).detach()
+    it_learned, it_svd, loss_l, loss_s = [], [], [], []
+    w = pred.nlss_weights()
+    for j, i in enumerate(ids):
+        op = nl.Operator(nl.OP_FV5, N, N, 1, hcoef[j].contiguous())
+        f = torch.tensor(W.normal_block(W.seed_for(5, 2, i), n, 1), device=dev)
+        Ps, _ = nl.setup_spectral_P(op, torch.tensor(c5.S0(i), dtype=torch.float64, device=dev), k, c5.omega,
+                                    c5.s1, nl.FP64)
+        for P, its, ls in ((Q[j].double().contiguous(), it_learned, loss_l), (Ps, it_svd, loss_s)):
+            M = nl.galerkin_coarse(op, P, c5.omega, 1)
+            _, info, rc = nl.pcg_solve(op, M, f, prec=nl.FP64, rtol=1e-8)
+            its.append(info[0].iters)
+            lv, _ = nl.subspace_loss_fwd(P.float().unsqueeze(0).contiguous(), hB[j:j + 1].contiguous(), w)
+            ls.append(float(lv[0]))
+    flop = 2.0 * batch * n * 9 * 32 * (33 + 32 + 32 + 32) * 3
+    return {"workload": f"{batch} x FV5 {N}^2, k={k}, m={m}, CNN 4 x 3x3 conv, width 32",
+            "train_step_ms": round(step_ms, 3), "conv_TFLOPs_est": round(flop / step_ms / 1e9, 2),
+            "train_steps": train_steps + reps + 1, "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 5),
+            "held_out": held_out,
+            "pcg_iters_learned_median": float(np.median(it_learned)), "pcg_iters_svd_median": float(np.median(it_svd)),
+            "nlss_learned_median": round(float(np.median(loss_l)), 5),
+            "nlss_svd_median": round(float(np.median(loss_s)), 5)}
 
 
 def counter_traffic(kname: str, N: int, k: int):

@@ -83,21 +83,26 @@ __global__ __launch_bounds__(NT) void k_sine_modes(int N, int k, const int* __re
   phi[g] = (float)(v * 2.0 * h);   // sum over the grid of sin^2 sin^2 = N^2 / 4
 }
 
-// x0[b][pixel][c]: c = 0 standardised log a, c = 1..k Phi, zero up to C0p
+// x0[b][pixel][c]: c = 0 standardised log a, c = 1..k Phi, zero up to C0p;
+// one thread per pixel (one logarithm), 8-byte stores of 4 channels
 __global__ __launch_bounds__(NT) void k_cnn_input(const double* __restrict__ coef, const double* __restrict__ stats,
                                                   const float* __restrict__ phi, int n, int k, int C0p,
                                                   unsigned short* __restrict__ x0) {
   const int b = blockIdx.y;
-  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (g >= (int64_t)n * C0p) return;
-  const int c = (int)(g % C0p);
-  const int64_t p = g / C0p;
-  float v = 0.f;
-  if (c == 0)
-    v = (float)((log(coef[(int64_t)b * n + p]) - stats[2 * b]) / stats[2 * b + 1]);
-  else if (c <= k)
-    v = phi[p * k + (c - 1)];
-  x0[((int64_t)b * n) * C0p + g] = to_bf16(v);
+  const int p = blockIdx.x * NT + threadIdx.x;
+  if (p >= n) return;
+  const float a0 = (float)((log(coef[(int64_t)b * n + p]) - stats[2 * b]) / stats[2 * b + 1]);
+  unsigned short* dst = x0 + ((int64_t)b * n + p) * C0p;
+  const float* ph = phi + (int64_t)p * k;
+  for (int c0 = 0; c0 < C0p; c0 += 4) {
+    unsigned short h[4];
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u;
+      h[u] = to_bf16(c == 0 ? a0 : (c <= k ? ph[c - 1] : 0.f));
+    }
+    *reinterpret_cast<uint2*>(dst + c0) =
+        make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+  }
 }
 
 // --------------------------------------------------------- weight layouts
@@ -150,29 +155,31 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
   const int ty0 = blockIdx.y * TILE, tx0 = blockIdx.x * TILE;
   const int64_t n = (int64_t)N * N;
   const unsigned short* Xb = X + (int64_t)b * n * ICp;
-  // stage the halo tile, 4 channels (8 bytes) per load
+  // stage the halo tile and the weights, 4 channels (8 bytes) per load: a
+  // thread keeps one channel group and steps over pixels (rows of weights)
   const int q4 = ICp / 4;
-  for (int e = threadIdx.x; e < HALO * HALO * q4; e += NT) {
-    const int pix = e / q4, c4 = e % q4;
-    const int hy = pix / HALO, hx = pix % HALO;
-    const int y = ty0 + hy - 1, x = tx0 + hx - 1;
-    uint2 v = make_uint2(0u, 0u);
-    if (y >= 0 && y < N && x >= 0 && x < N) {
-      v = *reinterpret_cast<const uint2*>(Xb + ((int64_t)y * N + x) * ICp + 4 * c4);
-      if (IN_GELU) {
-        unsigned short h[4] = {(unsigned short)(v.x & 0xffff), (unsigned short)(v.x >> 16),
-                               (unsigned short)(v.y & 0xffff), (unsigned short)(v.y >> 16)};
-        for (int u = 0; u < 4; ++u) h[u] = to_bf16(gelu(from_bf16(h[u])));
-        v.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
-        v.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+  const int per = NT / q4;                     // pixels per pass
+  const int c4 = threadIdx.x % q4, p0 = threadIdx.x / q4;
+  if (p0 < per) {
+    for (int pix = p0; pix < HALO * HALO; pix += per) {
+      const int hy = pix / HALO, hx = pix - hy * HALO;
+      const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+      uint2 v = make_uint2(0u, 0u);
+      if (y >= 0 && y < N && x >= 0 && x < N) {
+        v = *reinterpret_cast<const uint2*>(Xb + ((int64_t)y * N + x) * ICp + 4 * c4);
+        if (IN_GELU) {
+          unsigned short h[4] = {(unsigned short)(v.x & 0xffff), (unsigned short)(v.x >> 16),
+                                 (unsigned short)(v.y & 0xffff), (unsigned short)(v.y >> 16)};
+          for (int u = 0; u < 4; ++u) h[u] = to_bf16(gelu(from_bf16(h[u])));
+          v.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
+          v.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+        }
       }
+      *reinterpret_cast<uint2*>(Xs + pix * xs + 4 * c4) = v;
     }
-    *reinterpret_cast<uint2*>(Xs + pix * xs + 4 * c4) = v;
-  }
-  for (int e = threadIdx.x; e < 9 * OC * q4; e += NT) {
-    const int row = e / q4, c4 = e % q4;      // row = tap * OC + oc
-    *reinterpret_cast<uint2*>(Ws + row * xs + 4 * c4) =
-        *reinterpret_cast<const uint2*>(Wk + (int64_t)row * ICp + 4 * c4);
+    for (int row = p0; row < 9 * OC; row += per)   // row = tap * OC + oc
+      *reinterpret_cast<uint2*>(Ws + row * xs + 4 * c4) =
+          *reinterpret_cast<const uint2*>(Wk + (int64_t)row * ICp + 4 * c4);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -256,7 +263,11 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
   f4 acc[MAXT];
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
-  float dbias = 0.f;                           // lanes of wave 0: oc = threadIdx.x
+  // bias gradient: thread t < nsl * OCp sums pixels slot, slot + nsl, ... of
+  // channel oc = t % OCp (slot = t / OCp); slots are added in order at the end
+  const int nsl = NT / OCp;
+  const int boc = threadIdx.x % OCp, bsl = threadIdx.x / OCp;
+  float dbias = 0.f;
   const int tiles_x = (N + TILE - 1) / TILE;
   const int per_field = tiles_x * tiles_x;
   const int64_t n = (int64_t)N * N;
@@ -266,26 +277,38 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
     const int b = tile / per_field, tt = tile % per_field;
     const int ty0 = (tt / tiles_x) * TILE, tx0 = (tt % tiles_x) * TILE;
     __syncthreads();
-    for (int e = threadIdx.x; e < HALO * HALO * ICp; e += NT) {
-      const int pix = e / ICp, c = e % ICp;
-      const int y = ty0 + pix / HALO - 1, x = tx0 + pix % HALO - 1;
-      unsigned short v = 0;
-      if (y >= 0 && y < N && x >= 0 && x < N) {
-        v = X[((int64_t)b * n + (int64_t)y * N + x) * ICp + c];
-        if (IN_GELU) v = to_bf16(gelu(from_bf16(v)));
-      }
-      Xt[c * HS + pix] = v;
-    }
-    for (int e = threadIdx.x; e < TILE * TILE * OCp; e += NT) {
-      const int pix = e / OCp, c = e % OCp;
-      const int y = ty0 + pix / TILE, x = tx0 + pix % TILE;
-      unsigned short v = 0;
-      if (y < N && x < N) v = dZ[((int64_t)b * n + (int64_t)y * N + x) * OCp + c];
-      Dt[c * DS + pix] = v;
+    {
+      // halo tile channel-major, 4 channels per 8-byte load; one channel
+      // group per thread, stepping over pixels
+      const int q4 = ICp / 4, per = NT / q4;
+      const int c4 = threadIdx.x % q4, p0 = threadIdx.x / q4;
+      if (p0 < per)
+        for (int pix = p0; pix < HALO * HALO; pix += per) {
+          const int hy = pix / HALO, hx = pix - hy * HALO;
+          const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+          uint2 v = make_uint2(0u, 0u);
+          if (y >= 0 && y < N && x >= 0 && x < N)
+            v = *reinterpret_cast<const uint2*>(X + ((int64_t)b * n + (int64_t)y * N + x) * ICp + 4 * c4);
+          unsigned short h[4] = {(unsigned short)(v.x & 0xffff), (unsigned short)(v.x >> 16),
+                                 (unsigned short)(v.y & 0xffff), (unsigned short)(v.y >> 16)};
+          for (int u = 0; u < 4; ++u) Xt[(4 * c4 + u) * HS + pix] = IN_GELU ? to_bf16(gelu(from_bf16(h[u]))) : h[u];
+        }
+      const int o4 = OCp / 4, pero = NT / o4;
+      const int d4 = threadIdx.x % o4, q0 = threadIdx.x / o4;
+      if (q0 < pero)
+        for (int pix = q0; pix < TILE * TILE; pix += pero) {
+          const int y = ty0 + pix / TILE, x = tx0 + pix % TILE;
+          uint2 v = make_uint2(0u, 0u);
+          if (y < N && x < N) v = *reinterpret_cast<const uint2*>(dZ + ((int64_t)b * n + (int64_t)y * N + x) * OCp + 4 * d4);
+          Dt[(4 * d4 + 0) * DS + pix] = (unsigned short)(v.x & 0xffff);
+          Dt[(4 * d4 + 1) * DS + pix] = (unsigned short)(v.x >> 16);
+          Dt[(4 * d4 + 2) * DS + pix] = (unsigned short)(v.y & 0xffff);
+          Dt[(4 * d4 + 3) * DS + pix] = (unsigned short)(v.y >> 16);
+        }
     }
     __syncthreads();
-    if (threadIdx.x < OCp)
-      for (int p = 0; p < TILE * TILE; ++p) dbias += from_bf16(Dt[threadIdx.x * DS + p]);
+    if (bsl < nsl)
+      for (int p = bsl; p < TILE * TILE; p += nsl) dbias += from_bf16(Dt[boc * DS + p]);
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
       const int o = w + 4 * s;
@@ -293,12 +316,21 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
       const int tap = o / (OCT * ICT), rem = o % (OCT * ICT);
       const int ot = rem / ICT, it = rem % ICT;
       const int dy = tap / 3, dx = tap % 3;
-      for (int row = 0; row < TILE; ++row) {
-        // pixels 4 lg .. 4 lg + 3 of output row `row`
-        const s4 a = *reinterpret_cast<const s4*>(Dt + (16 * ot + lp) * DS + row * TILE + 4 * lg);
-        const unsigned short* xr = Xt + (16 * it + lp) * HS + (row + dy) * HALO + 4 * lg + dx;
-        const s4 bv = s4{(short)xr[0], (short)xr[1], (short)xr[2], (short)xr[3]};
-        acc[s] = mfma_bf16(a, bv, acc[s]);
+      const unsigned short* dr = Dt + (16 * ot + lp) * DS + 4 * lg;
+      const unsigned short* xb = Xt + (16 * it + lp) * HS + dy * HALO + 4 * lg + dx;
+      for (int row0 = 0; row0 < TILE; row0 += 4) {
+        // pixels 4 lg .. 4 lg + 3 of output rows row0 .. row0 + 3: all operand
+        // reads first, then the four products
+        s4 a[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int row = row0 + u;
+          a[u] = *reinterpret_cast<const s4*>(dr + row * TILE);
+          const unsigned short* xr = xb + row * HALO;
+          bv[u] = s4{(short)xr[0], (short)xr[1], (short)xr[2], (short)xr[3]};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[s] = mfma_bf16(a[u], bv[u], acc[s]);
       }
     }
   }
@@ -313,13 +345,41 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
     for (int v = 0; v < 4; ++v)
       rec[((int64_t)tap * OCp + 16 * ot + 4 * lg + v) * ICp + 16 * it + lp] = acc[s][v];
   }
-  if (threadIdx.x < OCp) rec[9 * OCp * ICp + threadIdx.x] = dbias;
+  __syncthreads();
+  float* sb = reinterpret_cast<float*>(lds);   // staging area is free now
+  if (bsl < nsl) sb[bsl * OCp + boc] = dbias;
+  __syncthreads();
+  if (threadIdx.x < OCp) {
+    float tot = 0.f;
+    for (int q = 0; q < nsl; ++q) tot += sb[q * OCp + threadIdx.x];
+    rec[9 * OCp * ICp + threadIdx.x] = tot;
+  }
 }
 
-// dW (master layout (Cout, Cin, 3, 3)) and db from the partial records,
-// summed over workgroups in order
-__global__ __launch_bounds__(NT) void k_wgrad_reduce(int nrec, int ICp, int OCp, int Cin, int Cout,
-                                                     const float* __restrict__ part, float* __restrict__ gW,
+// Weight-gradient records are added in two fixed-order levels: slices of
+// RSL consecutive records first (many workgroups in flight), then the slices.
+constexpr int RSL = 32;
+
+__global__ __launch_bounds__(NT) void k_wgrad_slices(int nrec, int64_t stride, const float* __restrict__ part,
+                                                     float* __restrict__ slices) {
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (g >= stride) return;
+  const int sl = blockIdx.y;
+  const int r0 = sl * RSL, r1 = min(nrec, r0 + RSL);
+  float v[8];
+  float s = 0.f;
+  for (int r = r0; r < r1; r += 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (r + j < r1) ? part[(int64_t)(r + j) * stride + g] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  slices[(int64_t)sl * stride + g] = s;
+}
+
+// dW (master layout (Cout, Cin, 3, 3)) and db from the slices, in order
+__global__ __launch_bounds__(NT) void k_wgrad_reduce(int nsl, int ICp, int OCp, int Cin, int Cout,
+                                                     const float* __restrict__ slices, float* __restrict__ gW,
                                                      float* __restrict__ gb) {
   const int g = blockIdx.x * NT + threadIdx.x;
   const int nW = Cout * Cin * 9;
@@ -333,13 +393,7 @@ __global__ __launch_bounds__(NT) void k_wgrad_reduce(int nrec, int ICp, int OCp,
   }
   const int64_t stride = 9 * OCp * ICp + OCp;
   double s = 0.0;
-  for (int r0 = 0; r0 < nrec; r0 += 8) {     // eight loads in flight, added in order
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (r0 + j < nrec) ? part[(r0 + j) * stride + src] : 0.f;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) s += (double)v[j];
-  }
+  for (int q = 0; q < nsl; ++q) s += (double)slices[q * stride + src];
   if (g < nW)
     gW[g] = (float)s;
   else
@@ -442,7 +496,8 @@ inline NetLayout carve_net(void* ws, const Net& t) {
     L.dz[l] = c.take<unsigned short>(bn * t.coutp[l]);
     maxrec = std::max<int64_t>(maxrec, 9 * t.coutp[l] * t.cinp[l] + t.coutp[l]);
   }
-  L.part = c.take<float>((size_t)wgrad_groups(t) * maxrec);
+  const int groups = wgrad_groups(t);
+  L.part = c.take<float>((size_t)(groups + (groups + RSL - 1) / RSL) * maxrec);   // records, then slices
   L.bytes = c.bytes();
   return L;
 }
@@ -515,8 +570,12 @@ inline int wgrad(const Net& t, int l, const unsigned short* X, const unsigned sh
     rc = go(k_conv_wgrad<36, IN_GELU>);
   if (rc != NLSP_OK) return rc;
   const int nout = t.cout[l] * t.cin[l] * 9 + t.cout[l];
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(nout, NT)), dim3(NT), 0, s, groups, ICp, OCp, t.cin[l],
-                     t.cout[l], part, gW, gb);
+  const int64_t stride = 9 * OCp * ICp + OCp;
+  const int nsl = (groups + RSL - 1) / RSL;
+  float* slices = part + (int64_t)groups * stride;
+  hipLaunchKernelGGL(k_wgrad_slices, dim3(ceil_div(stride, NT), nsl), dim3(NT), 0, s, groups, stride, part, slices);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(nout, NT)), dim3(NT), 0, s, nsl, ICp, OCp, t.cin[l], t.cout[l],
+                     slices, gW, gb);
   return NLSP_OK;
 }
 
@@ -555,8 +614,8 @@ int cnn_fwd(const nlsp_cnn_shape* shape, const float* params, const double* coef
   NLSP_HIP(hipMemcpyAsync(L.modes, modes.data(), sizeof(int) * modes.size(), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_sine_modes, dim3(ceil_div(t.n * t.k, NT)), dim3(NT), 0, s, t.N, t.k, L.modes, L.phi);
   hipLaunchKernelGGL(k_field_stats, dim3(t.batch), dim3(NT), 0, s, coef, (int)t.n, L.stats);
-  hipLaunchKernelGGL(k_cnn_input, dim3(ceil_div(t.n * t.cinp[0], NT), t.batch), dim3(NT), 0, s, coef, L.stats,
-                     L.phi, (int)t.n, t.k, t.cinp[0], L.x0);
+  hipLaunchKernelGGL(k_cnn_input, dim3(ceil_div(t.n, NT), t.batch), dim3(NT), 0, s, coef, L.stats, L.phi,
+                     (int)t.n, t.k, t.cinp[0], L.x0);
   for (int l = 0; l < 4; ++l)
     hipLaunchKernelGGL(k_prep_weights, dim3(ceil_div(9 * t.coutp[l] * t.cinp[l], NT)), dim3(NT), 0, s,
                        params + t.woff[l], t.cin[l], t.cout[l], t.cinp[l], t.coutp[l], L.wf[l], L.wb[l]);

@@ -60,6 +60,7 @@ struct SysDev {
   int R, kp, nblk, blk0;
   int chunk_rows;          // rows per chunk: floor(NT / R); threads past chunk_rows*R idle
   int64_t nchunks;
+  int64_t cpb;             // chunks per workgroup: ceil(nchunks / nblk)
   int rw;                  // restriction record width: kp*R + 2R
   const void* Q;           // (n, kp), float or double
   const double* Linv;      // (kp, kp) inverse Cholesky factor of A_c
@@ -76,7 +77,6 @@ struct SysDev {
   double* bpart[2];        // [nblk][3R]  kernel-B partials [r^T z | r^T z_old | ||r||^2], by parity
   double* rpart;           // [nblk][rw]  restriction records [Q^T v | v-scalar | ||f||^2]
   double* rgrp;            // [ngrp][rw]  group records
-  double* etop;            // [rw]        [A_c^-1 Q^T v | s1 | s2] of the last restriction
   double* estate[2];       // [kp*R]      e = A_c^-1 Q^T r by parity
   double* dpart;           // [nblk][R]   true-residual partials
   unsigned* ticket;        // ticket_words(nblk)
@@ -131,10 +131,45 @@ NLSP_DEV void lds_tree_rows(double* sh, int nrows, int W) {
   }
 }
 
+NLSP_DEV bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// R a power of two <= 64: butterflies inside each wave over the lanes that
+// share c = lane % R, then the wave totals in wave order (one barrier round).
+// K values per thread; totals to red[k*R + c].  `sh` holds >= 8 K R doubles.
+template <int K>
+NLSP_DEV void block_sum_waves(const double (&v0)[K], int R, double* red, double* sh) {
+  constexpr int NW = NT / WAVE;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = v0[k];
+  for (int o = WAVE / 2; o >= R; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], o, WAVE);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane < R)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[(w * K + k) * R + lane] = v[k];
+  __syncthreads();
+  if (threadIdx.x < K * R) {
+    const int k = threadIdx.x / R, c = threadIdx.x % R;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s += sh[(q * K + k) * R + c];
+    red[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
 // Sum of per-thread values over the threads that share c = t % R; the totals
 // land in red[c] (LDS) for c < R.  Deterministic.  All threads call.
 // `sh` holds NT + 16 doubles.
 NLSP_DEV void block_sum_rhs(double v, int R, double* red, double* sh) {
+  if (pow2(R) && R <= WAVE) {
+    const double vv[1] = {v};
+    block_sum_waves<1>(vv, R, red, sh);
+    return;
+  }
   const int t = threadIdx.x;
   const int nrows = (NT + R - 1) / R;
   __syncthreads();
@@ -218,8 +253,20 @@ NLSP_DEV void rec_finish(const double (&v)[8], int count, double* out, double* s
 // eout (LDS or global, same layout).  Thread t takes row i = t / SL of A_c^-1
 // and the column slice js = t % SL (SL consecutive lanes), all R right-hand
 // sides at once; the slices are added with butterflies.
+// The first 8 entries of this thread's row slice of A_c^-1, loaded ahead of
+// coarse_apply so that their latency overlaps other waits.
+NLSP_DEV void coarse_prefetch(const double* __restrict__ Ainv, int kp, double (&a)[8]) {
+  const int t = threadIdx.x;
+  const int SL = min(NT / kp, kp);
+  const int i = t / SL, js = t % SL;
+  const int len = kp / SL;
+  const double* row = Ainv + (int64_t)(i < kp ? i : 0) * kp + js * len;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = (u < len) ? row[u] : 0.0;
+}
+
 NLSP_DEV void coarse_apply(const double* __restrict__ Ainv, int kp, int R, const double* cvec,
-                           double* eout) {
+                           double* eout, const double* pre = nullptr) {
   const int t = threadIdx.x;
   const int SL = min(NT / kp, kp);            // lanes per row (power of two, <= kp)
   const int i = t / SL, js = t % SL;
@@ -232,7 +279,7 @@ NLSP_DEV void coarse_apply(const double* __restrict__ Ainv, int kp, int R, const
   for (int j0 = 0; on && j0 < len; j0 += 8) {
     double a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = (j0 + u < len) ? row[j0 + u] : 0.0;
+    for (int u = 0; u < 8; ++u) a[u] = (pre && j0 == 0) ? pre[u] : ((j0 + u < len) ? row[j0 + u] : 0.0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       if (j0 + u >= len) break;
@@ -346,6 +393,28 @@ NLSP_DEV void restrict_rows(const QT* __restrict__ Q, int64_t row0, int nrows, i
 NLSP_DEV void restrict_finish(const QMap& m, int kp, int R, const double (&acc)[4], double* red,
                               double* out) {
   const int KR = kp * R;
+  const int pairs = m.lpr * R;                 // lanes of one row group
+  if (pow2(pairs) && pairs <= WAVE && (NT / WAVE) * KR <= 4 * NT + 128) {
+    // the row groups inside a wave add with butterflies (lanes xor pairs, ...),
+    // then the 8 wave totals in wave order
+    double v[4] = {acc[0], acc[1], acc[2], acc[3]};
+    for (int o = WAVE / 2; o >= pairs; o >>= 1)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] += __shfl_xor(v[u], o, WAVE);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane < pairs)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) red[w * KR + (4 * m.jc + u) * R + m.c] = v[u];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < KR; idx += NT) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NT / WAVE; ++q) s += red[q * KR + idx];
+      store_partial(&out[idx], s);
+    }
+    return;
+  }
   __syncthreads();
   if (m.on) {
 #pragma unroll
@@ -385,18 +454,17 @@ struct ChunkRange {
 };
 
 NLSP_DEV ChunkRange my_chunks(const SysDev& S, int lb) {
-  const int64_t per = (S.nchunks + S.nblk - 1) / S.nblk;
   ChunkRange cr;
-  cr.c0 = (int64_t)lb * per;
-  cr.c1 = min(S.nchunks, cr.c0 + per);
+  cr.c0 = (int64_t)lb * S.cpb;
+  cr.c1 = min(S.nchunks, cr.c0 + S.cpb);
   return cr;
 }
 
 // Restriction epilogue (kernel A and k_residual): this workgroup's record
 // [Q^T v | s1 | s2] (already in rpart) is summed per group of 16 by the
-// group's last workgroup into rgrp; the last group then sums the group
-// records, applies A_c^-1 to the Q^T v part and publishes
-// etop = [A_c^-1 Q^T v | s1 | s2] for the next kernel.
+// group's last workgroup into rgrp.  The next kernel sums the group records
+// in order and applies A_c^-1 itself, so this kernel ends one ticket level
+// earlier.
 NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double* sh) {
   if (!arrive_group(S.ticket, S.nblk, lb)) return;
   const int grp = lb / TICKET_GROUP;
@@ -405,11 +473,6 @@ NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double*
   sum_records<true>(S.rpart + (int64_t)r0 * S.rw, nrec, S.rw, 0, S.rw, red, sh);
   double* grec = S.rgrp + (int64_t)grp * S.rw;
   for (int idx = threadIdx.x; idx < S.rw; idx += NT) store_partial(&grec[idx], red[idx]);
-  if (!arrive_top(S.ticket, ticket_groups(S.nblk))) return;
-  sum_records<true>(S.rgrp, ticket_groups(S.nblk), S.rw, 0, S.rw, red, sh);
-  const int KR = S.kp * S.R;
-  coarse_apply(S.Ainv, S.kp, S.R, red, S.etop);
-  for (int idx = threadIdx.x; idx < 2 * S.R; idx += NT) S.etop[KR + idx] = red[KR + idx];
 }
 
 // ----------------------------------------------------- per-iteration scalars
@@ -427,27 +490,72 @@ NLSP_DEV bool finite_pos(double v) { return v > 0.0 && v <= 1.7e308; }
 
 // Loads of kernel B's partials [r^T z | r^T z_old | ||r||^2] of iteration it,
 // issued early (see rec_issue); `fast` is false when they do not fit.
+// With R <= 4 (3R <= 12) and at most NT records, thread t loads record t
+// whole (`tiny`) and the records are added with butterflies; otherwise
+// rec_issue/rec_finish, or sum_records when that does not fit either.  The
+// per-RHS status is loaded here too, by threads t < R.
 struct ScalarLoads {
-  double v[8];
-  bool fast;
+  double v[12];
+  bool fast, tiny;
+  RhsStatus st;
 };
 
 NLSP_DEV void scalars_issue(const SysDev& S, int it, ScalarLoads& L) {
-  L.fast = rec_fits(S.nblk, 3 * S.R);
-  if (L.fast) rec_issue<false>(S.bpart[it & 1], S.nblk, 3 * S.R, 0, 3 * S.R, L.v);
+  const int R = S.R, t = threadIdx.x;
+  L.tiny = (R <= 4 && pow2(R) && S.nblk <= NT);
+  L.fast = !L.tiny && rec_fits(S.nblk, 3 * R);
+  if (L.tiny) {
+    const double* rec = S.bpart[it & 1] + (int64_t)min(t, S.nblk - 1) * 3 * R;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) L.v[j] = (j < 3 * R && t < S.nblk) ? rec[j] : 0.0;
+  } else if (L.fast) {
+    double v8[8];
+    rec_issue<false>(S.bpart[it & 1], S.nblk, 3 * R, 0, 3 * R, v8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) L.v[j] = v8[j];
+  }
+  if (t < R) L.st = S.stat[it & 1][t];
 }
 
 NLSP_DEV void scalars_finish(const SysDev& S, const RhsStatus* cur, const ScalarLoads& L,
                              IterScalars& sc, double* buf, double* sh, int it) {
   const int R = S.R;
-  if (L.fast) {
-    rec_finish(L.v, 3 * R, buf, sh);
+  if (L.tiny) {
+    // all 64 lanes of a wave hold different records: full butterflies per value
+    constexpr int NW = NT / WAVE;
+    double v[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) v[j] = L.v[j];
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+      if (j < 3 * R)   // uniform
+#pragma unroll
+        for (int o = WAVE / 2; o >= 1; o >>= 1) v[j] += __shfl_xor(v[j], o, WAVE);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < 12; ++j)
+        if (j < 3 * R) sh[w * 3 * R + j] = v[j];
+    __syncthreads();
+    if (threadIdx.x < 3 * R) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) a += sh[q * 3 * R + threadIdx.x];
+      buf[threadIdx.x] = a;
+    }
+    __syncthreads();
+  } else if (L.fast) {
+    double v8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v8[j] = L.v[j];
+    rec_finish(v8, 3 * R, buf, sh);
   } else {
     sum_records<false>(S.bpart[it & 1], S.nblk, 3 * R, 0, 3 * R, buf, sh);
   }
   if (threadIdx.x < R) {
     const int c = threadIdx.x;
-    const RhsStatus& st = cur[c];
+    const RhsStatus& st = L.st;
     const double g = buf[c], rz = buf[R + c], rr = buf[2 * R + c];
     sc.gam[c] = g;
     sc.rzo[c] = rz;
@@ -468,6 +576,11 @@ NLSP_DEV void scalars_finish(const SysDev& S, const RhsStatus* cur, const Scalar
 // land in red[k*R + c], k < 3.  One tree instead of three.  `sh` holds
 // 3*(NT + 16) doubles.
 NLSP_DEV void block_sum_rhs3(double a, double b, double d, int R, double* red, double* sh) {
+  if (pow2(R) && R <= WAVE) {
+    const double vv[3] = {a, b, d};
+    block_sum_waves<3>(vv, R, red, sh);
+    return;
+  }
   const int t = threadIdx.x;
   const int nrows = (NT + R - 1) / R;
   __syncthreads();
@@ -555,8 +668,8 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
 }
 
 // kernel A: convergence test; beta; p_new = z + beta p_old (double buffer);
-// q = A p_new; restriction records [Q^T q | p^T q | 0]; the epilogue publishes
-// etop = [A_c^-1 Q^T q | p^T q | 0]
+// q = A p_new; restriction records [Q^T q | p^T q | 0], summed per group of 16
+// workgroups by the epilogue
 template <typename QT>
 __global__ __launch_bounds__(NT, 4) void k_iter_a(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it) {
@@ -566,7 +679,6 @@ __global__ __launch_bounds__(NT, 4) void k_iter_a(const SysDev* __restrict__ sys
   __shared__ double buf[4 * MAXR];
   __shared__ IterScalars sc;
   const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (S.nact[it & 1] == 0) return;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
   const QT* Q = static_cast<const QT*>(S.Q);
@@ -579,7 +691,8 @@ __global__ __launch_bounds__(NT, 4) void k_iter_a(const SysDev* __restrict__ sys
   scalars_issue(S, it, sl);                                   // small loads first,
   int64_t row0 = cr.c0 * S.chunk_rows;
   int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
-  if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);  // then Q
+  if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);  // then Q,
+  if (S.nact[it & 1] == 0) return;                            // then the early exit
   scalars_finish(S, cur, sl, sc, buf, sh, it);
   const bool act = sc.act[c] != 0;
   const double beta = sc.beta[c];
@@ -644,7 +757,11 @@ __global__ __launch_bounds__(NT) void k_sweep(const SysDev* __restrict__ sys,
     ScalarLoads sl;
     scalars_issue(S, it, sl);
     scalars_finish(S, cur, sl, sc, buf, sh, it);
-    if (t < R) s_alpha[t] = sc.gam[t] / S.etop[S.kp * R + t];
+    if (t < R) {
+      double pq = 0.0;   // p^T q: entry kp R + t of the group records, in order
+      for (int g = 0; g < ticket_groups(S.nblk); ++g) pq += S.rgrp[(int64_t)g * S.rw + S.kp * R + t];
+      s_alpha[t] = sc.gam[t] / pq;
+    }
   } else if (t < R) {
     s_alpha[t] = 0.0;
   }
@@ -681,9 +798,9 @@ __global__ __launch_bounds__(NT) void k_sweep(const SysDev* __restrict__ sys,
 // kernel B: status; alpha; e <- e - alpha A_c^-1 Q^T q (so e = A_c^-1 Q^T r_new);
 // x += alpha p; r_new = r - alpha q into r[(it+1)&1]; z = J r_new + Q e;
 // partials [r^T z | r^T z_old | ||r_new||^2] into bpart[(it+1)&1].
-//   restart = 0: an iteration; etop = [A_c^-1 Q^T q | p^T q | 0] from kernel A
-//   restart = 1: after k_residual (which wrote r into r[(it+1)&1] and
-//                etop = [A_c^-1 Q^T r | ||r||^2 | ||f||^2]) for the RHS in
+//   restart = 0: an iteration; group records [Q^T q | p^T q | 0] from kernel A
+//   restart = 1: after k_residual (which wrote r into r[(it+1)&1] and group
+//                records [Q^T r | ||r||^2 | ||f||^2]) for the RHS in
 //                `mask`: no update, `init` also takes ||f||^2, and the next
 //                kernel A uses beta = 0.
 // wsrc < 0: J_2 inline (nu = 1); else J_{2nu} r_new is read from w[wsrc].
@@ -696,6 +813,7 @@ __global__ __launch_bounds__(NT, 4) void k_iter_b(const SysDev* __restrict__ sys
   __shared__ double sh[3 * (NT + 16)];
   __shared__ double ebuf[2048];
   __shared__ double dq[2048];
+  __shared__ double cg[2048 + 2 * MAXR];
   __shared__ double tscal[2 * MAXR];
   __shared__ double buf[4 * MAXR];
   __shared__ double s_alpha[MAXR];
@@ -725,24 +843,32 @@ __global__ __launch_bounds__(NT, 4) void k_iter_b(const SysDev* __restrict__ sys
   QBatch<QT, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
   const RhsStatus* cur = S.stat[it & 1];
-  // small loads first (scalars, the published coarse vector, e), then Q
+  // small loads first (scalars, the restriction's group records, e), then Q
   ScalarLoads sl;
-  sl.fast = false;
+  sl.fast = sl.tiny = false;
   if (!restart) scalars_issue(S, it, sl);
-  for (int idx = t; idx < KR; idx += NT) {
-    const double ep = S.estate[it & 1][idx], et = S.etop[idx];
-    if (restart) {
-      ebuf[idx] = ((mask >> (idx % R)) & 1u) ? et : ep;
-    } else {
-      ebuf[idx] = ep;   // e of r, updated with alpha below
-      dq[idx] = et;     // A_c^-1 Q^T q
-    }
-  }
-  if (t < 2 * R) tscal[t] = S.etop[KR + t];
+  const int ngrp = ticket_groups(S.nblk);
+  const bool gfast = rec_fits(ngrp, S.rw);
+  double gv[8], av[8];
+  if (gfast) rec_issue<false>(S.rgrp, ngrp, S.rw, 0, S.rw, gv);
+  coarse_prefetch(S.Ainv, S.kp, av);
+  for (int idx = t; idx < KR; idx += NT) ebuf[idx] = S.estate[it & 1][idx];
   int64_t row0 = cr.c0 * S.chunk_rows;
   int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
   if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
   if (!restart) scalars_finish(S, cur, sl, sc, buf, sh, it);
+  // c = [Q^T v | s1 | s2] summed over the groups in order (v = q, or r after
+  // k_residual), then dq = A_c^-1 Q^T v
+  if (gfast)
+    rec_finish(gv, S.rw, cg, sh);
+  else
+    sum_records<false>(S.rgrp, ngrp, S.rw, 0, S.rw, cg, sh);
+  coarse_apply(S.Ainv, S.kp, R, cg, dq, av);
+  if (t < 2 * R) tscal[t] = cg[KR + t];
+  __syncthreads();
+  if (restart)
+    for (int idx = t; idx < KR; idx += NT)
+      if ((mask >> (idx % R)) & 1u) ebuf[idx] = dq[idx];
   __syncthreads();
   // ---- per-RHS decisions (identical in every workgroup) and the new state
   if (t < R) {
@@ -917,7 +1043,7 @@ __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
 struct SolveLayout {
   double *p0, *p1, *q, *z, *estate0, *estate1;
   unsigned* ticket;
-  double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *etop, *dpart, *Ainv;
+  double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *dpart, *Ainv;
   float* dinv32;
   void *w0, *w1;
 };
@@ -997,7 +1123,6 @@ inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
   L.bpart1 = cv.take<double>((size_t)h.nblk * 3 * h.R);
   L.rpart = cv.take<double>((size_t)h.nblk * rw);
   L.rgrp = cv.take<double>((size_t)ticket_groups(h.nblk) * rw);
-  L.etop = cv.take<double>(rw);
   L.dpart = cv.take<double>((size_t)h.nblk * h.R);
   L.Ainv = cv.take<double>((size_t)h.kp * h.kp);
 }
@@ -1042,6 +1167,7 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.blk0 = blk0;
   hs.chunk_rows = h.chunk_rows;
   hs.nchunks = h.nchunks;
+  hs.cpb = (h.nchunks + h.nblk - 1) / h.nblk;
   hs.rw = restriction_width(h.kp, R);
   hs.Q = (M.prec == NLSP_FP64) ? (const void*)M.Q64 : (const void*)M.Q32;
   hs.Linv = M.Linv;
@@ -1062,7 +1188,6 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.bpart[1] = L.bpart1;
   hs.rpart = L.rpart;
   hs.rgrp = L.rgrp;
-  hs.etop = L.etop;
   hs.estate[0] = L.estate0;
   hs.estate[1] = L.estate1;
   hs.dpart = L.dpart;

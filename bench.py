@@ -65,14 +65,13 @@ def copy_calibration(mib: int):
 def solver_bytes_per_row(phase: int, kp: int, R: int = 1) -> float:
     """Algorithmic HBM bytes per grid row of one launch of a solver kernel,
     mixed form, float64 cell coefficient, each array counted once:
-      kernel A (1): read z, p_old, a, Q32; write p_new, q
-                    -> 4 x 8 R + 8 + 4 kp
-      kernel B (2): read x, p, r, q, z_old, a, D^-1 (f32), Q32; write x, r_new, z
-                    -> 8 x 8 R + 8 + 4 + 4 kp
+      update (1): read z, p, w, q_old, x, r, a, D^-1 (f32), Q32;
+                  write p, q, x, r_new, z  -> 11 x 8 R + 8 + 4 + 4 kp
+      matvec (2): read z, p, q, a, Qt32; write w  -> 4 x 8 R + 8 + 4 kp
     """
     if phase == 1:
-        return 32.0 * R + 8.0 + 4.0 * kp
-    return 64.0 * R + 12.0 + 4.0 * kp
+        return 88.0 * R + 12.0 + 4.0 * kp
+    return 32.0 * R + 8.0 + 4.0 * kp
 
 
 def main():
@@ -146,7 +145,7 @@ def main():
     launch_ms = sum(t["total_ms"] for t in tms) / max(1, sum(t["launches"] for t in tms))
     bytes_launch = solver_bytes_per_row(phase, kp) * n
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    kname = {1: "nlsp::k_iter_a<float>", 2: "nlsp::k_iter_b<float>"}[phase]
+    kname = {1: "nlsp::k_update<float>", 2: "nlsp::k_matvec<float>"}[phase]
     out = {
         "metric": "PCG time-to-1e-8 rel-residual (ms)",
         "value": round(statistics.median(solve_ms), 4),

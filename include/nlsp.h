@@ -168,9 +168,11 @@ typedef struct {
 } nlsp_two_level;
 
 /* Optional event timing of one of the solver's two per-iteration kernels:
- *   1  kernel A: convergence test, p <- z + beta p, q = A p, p^T q, Q^T q
- *   2  kernel B: alpha, x += alpha p, r -= alpha q, coarse solve, smoother,
- *      prolongation z = w + Q e, r^T z, ||r||^2
+ *   1  update: convergence test, beta, p^T q, alpha, p <- z + beta p,
+ *      q <- w + beta q, x += alpha p, r -= alpha q, coarse coefficients,
+ *      smoother and prolongation z = J r + Q c, r^T z, ||r||^2, p^T q
+ *      (for nu > 1: its update phase)
+ *   2  matvec: w = A z, (Q A_c^-1)^T w, z^T w, z^T q + p^T w
  * one launch in `every` carries a start and a stop hipEvent attached to its
  * own dispatch (hipExtLaunchKernelGGL), so the events take the dispatch's
  * begin and end timestamps and no marker packet is inserted between kernels. */

@@ -207,8 +207,8 @@ def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tens
               check_every: int = 32, workspace: Optional[torch.Tensor] = None,
               timing: Optional[dict] = None):
     """Returns (u, [RhsInfo per RHS], status).  ``f`` is (n,) or (n, R).
-    ``timing`` = {"phase": 1|2|3, "every": int} asks the library to time one
-    kernel with hipEvents attached to its dispatches; on return it also holds
+    ``timing`` = {"phase": 1|2, "every": int} asks the library to time one
+    kernel (1 the update kernel, 2 the matvec kernel) with hipEvents attached to its dispatches; on return it also holds
     "total_ms" and "launches"."""
     squeeze = f.dim() == 1
     f2 = f.reshape(f.shape[0], -1)

@@ -11,7 +11,27 @@
 
 #define NLSP_DEV __device__ __forceinline__
 
+// Pointers that the device reads out of descriptors in memory are generic
+// (flat) to the compiler, and flat accesses count against both the vector and
+// the LDS/scalar wait counters, so every scalar or LDS wait would also drain
+// the loads in flight.  Descriptor pointers are therefore declared in the
+// global address space for the device pass (same layout and bits as on the
+// host, where the qualifier is empty).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NLSP_GAS __attribute__((address_space(1)))
+#else
+#define NLSP_GAS
+#endif
+
 namespace nlsp {
+
+template <typename T>
+using Glob = NLSP_GAS T;
+
+template <typename T>
+__host__ __device__ inline Glob<T>* as_glob(T* p) {
+  return (Glob<T>*)p;
+}
 
 constexpr int WAVE = 64;
 
@@ -41,7 +61,7 @@ NLSP_DEV uint32_t fdiv(uint32_t n, const FastDiv& f) {
 struct OpDev {
   int kind, nx, ny, nz;
   int64_t n;
-  const double* coef;
+  Glob<const double>* coef;
   FastDiv fx, fxy;   // division by nx and by nx*ny
 };
 
@@ -52,7 +72,7 @@ inline OpDev make_op(const nlsp_operator& a) {
   o.ny = a.ny;
   o.nz = (a.kind == NLSP_OP_FV7) ? a.nz : 1;
   o.n = (int64_t)o.nx * o.ny * o.nz;
-  o.coef = a.coef;
+  o.coef = as_glob(a.coef);
   o.fx = make_fastdiv((uint32_t)o.nx);
   o.fxy = make_fastdiv((uint32_t)o.nx * (uint32_t)o.ny);
   return o;
@@ -66,69 +86,56 @@ NLSP_DEV T harmonic(T a, T b) {
 
 // (A v)_i for the unknown i at grid position (x, y, z).  `v(j)` returns the
 // value of the operand at unknown j.  Arithmetic in T (double or float).
+// Branch-free: a neighbour outside the grid reads row i itself and its term
+// is discarded by a select, so every load of the row is issued before the
+// first use (a load under a branch would be waited for inside the branch).
 template <typename T, typename V>
 NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v) {
   const int nx = op.nx, ny = op.ny;
   switch (op.kind) {
     case NLSP_OP_POISSON5: {
+      const int64_t jn[4] = {i - 1, i + 1, i - nx, i + nx};
+      const bool in[4] = {x > 0, x < nx - 1, y > 0, y < ny - 1};
       T s = T(0);
-      if (x > 0) s += v(i - 1);
-      if (x < nx - 1) s += v(i + 1);
-      if (y > 0) s += v(i - nx);
-      if (y < ny - 1) s += v(i + nx);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const T vj = v(in[f] ? jn[f] : i);
+        s += in[f] ? vj : T(0);
+      }
       return T(4) * v(i) - s;
     }
-    case NLSP_OP_FV5: {
-      const double* a = op.coef;
-      const T aP = T(a[i]);
-      T d = T(0), s = T(0);
-      auto face = [&](bool inside, int64_t j) {
-        if (inside) {
-          const T t = harmonic<T>(aP, T(a[j]));
-          d += t;
-          s += t * v(j);
-        } else {
-          d += T(2) * aP;
-        }
-      };
-      face(x > 0, i - 1);
-      face(x < nx - 1, i + 1);
-      face(y > 0, i - nx);
-      face(y < ny - 1, i + nx);
-      return d * v(i) - s;
-    }
+    case NLSP_OP_FV5:
     case NLSP_OP_FV7: {
-      const double* a = op.coef;
+      // faces -x, +x, -y, +y (, -z, +z); a boundary face puts its Dirichlet
+      // weight 2 a_P on the diagonal only
+      const auto a = op.coef;
       const int64_t sxy = (int64_t)nx * ny;
+      const int nf = (op.kind == NLSP_OP_FV7) ? 6 : 4;
+      const int64_t jn[6] = {i - 1, i + 1, i - nx, i + nx, i - sxy, i + sxy};
+      const bool in[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < op.nz - 1};
       const T aP = T(a[i]);
       T d = T(0), s = T(0);
-      auto face = [&](bool inside, int64_t j) {
-        if (inside) {
-          const T t = harmonic<T>(aP, T(a[j]));
-          d += t;
-          s += t * v(j);
-        } else {
-          d += T(2) * aP;
-        }
-      };
-      face(x > 0, i - 1);
-      face(x < nx - 1, i + 1);
-      face(y > 0, i - nx);
-      face(y < ny - 1, i + nx);
-      face(z > 0, i - sxy);
-      face(z < op.nz - 1, i + sxy);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        if (f >= nf) break;
+        const int64_t j = in[f] ? jn[f] : i;
+        const T aj = T(a[j]), vj = v(j);
+        const T t = harmonic<T>(aP, aj);
+        d += in[f] ? t : T(2) * aP;
+        s += in[f] ? t * vj : T(0);
+      }
       return d * v(i) - s;
     }
     default: {  // NLSP_OP_STENCIL9
-      const double* c = op.coef;
+      const auto c = op.coef;
       T s = T(0);
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
-        if (y + dy < 0 || y + dy >= ny) continue;
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-          if (x + dx < 0 || x + dx >= nx) continue;
-          s += T(c[(dy + 1) * 3 + (dx + 1)]) * v(i + dx + (int64_t)dy * nx);
+          const bool ok = y + dy >= 0 && y + dy < ny && x + dx >= 0 && x + dx < nx;
+          const T vj = v(ok ? i + dx + (int64_t)dy * nx : i);
+          s += ok ? T(c[(dy + 1) * 3 + (dx + 1)]) * vj : T(0);
         }
       }
       return s;
@@ -144,12 +151,15 @@ NLSP_DEV T op_diag(const OpDev& op, int64_t i, int x, int y, int z) {
       return T(4);
     case NLSP_OP_FV5:
     case NLSP_OP_FV7: {
-      const double* a = op.coef;
+      const auto a = op.coef;
       const int nx = op.nx, ny = op.ny;
       const int64_t sxy = (int64_t)nx * ny;
       const T aP = T(a[i]);
       T d = T(0);
-      auto face = [&](bool inside, int64_t j) { d += inside ? harmonic<T>(aP, T(a[j])) : T(2) * aP; };
+      auto face = [&](bool inside, int64_t j) {
+        const T h = harmonic<T>(aP, T(a[inside ? j : i]));
+        d += inside ? h : T(2) * aP;
+      };
       face(x > 0, i - 1);
       face(x < nx - 1, i + 1);
       face(y > 0, i - nx);
@@ -220,11 +230,13 @@ NLSP_DEV double block_sum(double v, double* sh) {
 // agent-scope relaxed atomics, which compile to device-coherent stores and
 // loads (sc1) that go to the coherence point shared by all XCDs instead of
 // requiring a write-back of the whole L2 (what __threadfence() costs here).
-NLSP_DEV void store_partial(double* p, double v) {
+template <typename P>
+NLSP_DEV void store_partial(P p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-NLSP_DEV double load_partial(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <typename P>
+NLSP_DEV double load_partial(P p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Grid-wide reductions finish inside the producing kernel in two levels.
@@ -248,14 +260,15 @@ NLSP_DEV void wait_own_stores() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-NLSP_DEV bool arrive_group(unsigned* tickets, unsigned nblocks, unsigned lb) {
+template <typename P>
+NLSP_DEV bool arrive_group(P tickets, unsigned nblocks, unsigned lb) {
   __shared__ int s_last;
   wait_own_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned grp = lb / TICKET_GROUP;
     const unsigned gsize = min((unsigned)TICKET_GROUP, nblocks - grp * TICKET_GROUP);
-    unsigned* gt = tickets + TICKET_STRIDE * (1 + grp);
+    auto gt = tickets + TICKET_STRIDE * (1 + grp);
     const unsigned t1 = __hip_atomic_fetch_add(gt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_last = (t1 == gsize - 1) ? 1 : 0;
     if (s_last) __hip_atomic_store(gt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -264,7 +277,8 @@ NLSP_DEV bool arrive_group(unsigned* tickets, unsigned nblocks, unsigned lb) {
   return s_last != 0;
 }
 
-NLSP_DEV bool arrive_top(unsigned* tickets, unsigned ngroups) {
+template <typename P>
+NLSP_DEV bool arrive_top(P tickets, unsigned ngroups) {
   __shared__ int s_last;
   wait_own_stores();
   __syncthreads();

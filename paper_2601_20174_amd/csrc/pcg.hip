@@ -9,25 +9,32 @@
 // Cholesky factor of A_c come from galerkin_coarse.  For nu = 1,
 // J_2 r = 2w D^-1 r - w^2 D^-1 A D^-1 r needs one stencil pass.
 //
-// One iteration = two kernels and two grid reductions.  The restriction is
-// linear, so Q^T r_new = Q^T r - alpha Q^T q: kernel A restricts q instead of
-// the new residual, and the residual update, smoother and prolongation share
-// kernel B without a grid synchronisation between them.
-//   kernel A  convergence test of r; beta; p <- z + beta p (double buffer);
-//             q = A p; partials p^T q and Q^T q
-//   kernel B  alpha; c <- c - alpha Q^T q; e = A_c^-1 c; x += alpha p;
-//             r_new = r - alpha q (double buffer); z = J r_new + Q e;
-//             partials r^T z, r^T z_old, ||r||^2
+// One iteration = two kernels and one grid reduction point per kernel, in the
+// single-reduction arrangement of CG (the scalars of both inner products are
+// gathered where z and w = A z are formed):
+//   update  (reads the partials of the previous update and the matvec's
+//            records) beta; p^T q = z^T w + beta (z^T q_old + p_old^T w)
+//            + beta^2 p_old^T q_old; alpha; p = z + beta p_old;
+//            q = w + beta q_old; x += alpha p; r_new = r - alpha q;
+//            c_new = c - alpha g, g = A_c^-1 Q^T q = Qt^T w + beta g_old;
+//            z = J r_new + Q c_new; partials r^T z, r^T z_old, ||r||^2, p^T q
+//   matvec  w = A z; records [Qt^T w | z^T w | z^T q + p^T w]
+// with Qt = Q A_c^-1 formed once per solve, so the coarse coefficients
+// c = A_c^-1 Q^T r are carried by recurrences and never need a coarse solve
+// inside the iteration.  In exact arithmetic p, q, x, r, z are those of
+// standard PCG (q = A p by induction, p^T q by expanding both recurrences);
+// p^T q uses the dot product of the stored vectors, not a scalar recurrence.
+// The matvec kernel waits for no scalar, so it streams from its first
+// instruction; the update kernel needs no coarse solve before its stream.
 // Grid reductions are finished by the consumer: every workgroup of the next
 // kernel sums the per-workgroup partials it needs in a fixed order (so all
 // workgroups obtain bit-identical scalars and runs are reproducible), while its
-// own loads are in flight.  Only Q^T q (k values per RHS) is pre-summed by the
-// last workgroup of each group of 16 inside kernel A (and, for large k*R,
-// once more by the last group).  The per-RHS state is double-buffered by
-// iteration parity: iteration `it` reads stat[it & 1] and only workgroup 0 of
-// kernel B writes stat[(it + 1) & 1].
-// Vectors and every reduction are float64; in the mixed form Q, the smoother
-// and the prolongation products are float32.
+// own loads are in flight.  Only the restriction records (k values per RHS)
+// are pre-summed by the last workgroup of each group of 16.  The per-RHS state
+// is double-buffered by iteration parity: iteration `it` reads stat[it & 1]
+// and only workgroup 0 of the update kernel writes stat[(it + 1) & 1].
+// Vectors and every reduction are float64; in the mixed form Q, Qt, the
+// smoother and the prolongation products are float32.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -49,10 +56,9 @@ struct RhsStatus {
   int active;        // still iterating
   int iters;         // updates of x completed
   int status;        // nlsp_status of this RHS
-  int par;           // p buffer holding the current direction
-  int restart;       // next kernel A uses beta = 0
+  int restart;       // the next update uses beta = 0
   int conv;          // stopped by the recursive residual test (true residual pending)
-  int pad0, pad1;
+  int pad0, pad1, pad2;
 };
 
 struct SysDev {
@@ -62,28 +68,32 @@ struct SysDev {
   int64_t nchunks;
   int64_t cpb;             // chunks per workgroup: ceil(nchunks / nblk)
   int rw;                  // restriction record width: kp*R + 2R
-  const void* Q;           // (n, kp), float or double
-  const double* Linv;      // (kp, kp) inverse Cholesky factor of A_c
-  const double* Ainv;      // (kp, kp) = L^-T L^-1
-  const double* f;
-  double* x;
-  double* r[2];            // residual, by iteration parity
-  double* p[2];            // search direction, by RhsStatus::par
-  double* q;
-  double* z;
-  void* w[2];              // J_{2nu} r work buffers (nu > 1), element type of Q
-  const double* dinv;
-  const float* dinv32;
-  double* bpart[2];        // [nblk][3R]  kernel-B partials [r^T z | r^T z_old | ||r||^2], by parity
-  double* rpart;           // [nblk][rw]  restriction records [Q^T v | v-scalar | ||f||^2]
-  double* rgrp;            // [ngrp][rw]  group records
-  double* estate[2];       // [kp*R]      e = A_c^-1 Q^T r by parity
-  double* dpart;           // [nblk][R]   true-residual partials
-  unsigned* ticket;        // ticket_words(nblk)
-  RhsStatus* stat[2];      // [R] each
-  int* nact;               // [2] active RHS in the stat buffer of that parity
-  int* n_active;           // host-visible copy
-  double* rr_true;         // [R]
+  // device pointers (global address space in the device pass)
+  Glob<const void>* Q;     // (n, kp), float or double: prolongation
+  Glob<const void>* Qt;    // (n, kp) Q A_c^-1, same type: restriction to coarse coefficients
+  Glob<const double>* Linv;  // (kp, kp) inverse Cholesky factor of A_c
+  Glob<double>* Ainv;      // (kp, kp) = L^-T L^-1
+  Glob<const double>* f;
+  Glob<double>* x;
+  Glob<double>* r[2];      // residual, by iteration parity
+  Glob<double>* p;         // search direction (updated in place)
+  Glob<double>* q[2];      // A p, by iteration parity
+  Glob<double>* z;         // preconditioned residual (updated in place)
+  Glob<double>* w;         // A z
+  Glob<void>* wj[2];       // J_{2nu} r work buffers (nu > 1), element type of Q
+  Glob<double>* dinv;
+  Glob<float>* dinv32;
+  Glob<double>* bpart[2];  // [nblk][4R]  update partials [r^T z | r^T z_old | ||r||^2 | p^T q], by parity
+  Glob<double>* rpart;     // [nblk][rw]  restriction records [Qt^T v | s1 | s2]
+  Glob<double>* rgrp;      // [ngrp][rw]  group records
+  Glob<double>* cstate[2]; // [kp*R]      c = A_c^-1 Q^T r, by parity
+  Glob<double>* gstate[2]; // [kp*R]      g = A_c^-1 Q^T q, by parity
+  Glob<double>* dpart;     // [nblk][R]   true-residual partials
+  Glob<unsigned>* ticket;  // ticket_words(nblk)
+  Glob<RhsStatus>* stat[2];  // [R] each
+  Glob<int>* nact;         // [2] active RHS in the stat buffer of that parity
+  Glob<int>* n_active;     // host-visible copy
+  Glob<double>* rr_true;   // [R]
   double omega, tol2;
   int maxit, flexible, nu;
   unsigned rmask;          // RHS a restart launch applies to (ANDed with the launch mask)
@@ -220,8 +230,10 @@ NLSP_DEV void sum_records(const double* base, int nrec, int stride, int off, int
 // Small reductions split in two so that their loads can be issued before a
 // large prefetch (vector loads of a wave complete in issue order): rec_issue
 // loads the records a thread sums (at most 8; the caller checks rec_fits),
-// rec_finish adds them in ascending record order and across threads with a
-// fixed tree.  Same result as sum_records.
+// unconditionally from clamped addresses and without touching the values, so
+// that no wait follows the loads; rec_finish masks the surplus, adds them in
+// ascending record order and across threads with a fixed tree.  Same result as
+// sum_records.
 NLSP_DEV bool rec_fits(int nrec, int count) { return count <= NT && nrec <= 8 * (NT / count); }
 
 template <bool COHERENT>
@@ -230,72 +242,22 @@ NLSP_DEV void rec_issue(const double* base, int nrec, int stride, int off, int c
   const int groups = NT / count, e = t % count, g = t / count;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int r = g + u * groups;
-    const double* a = &base[(int64_t)r * stride + off + e];
-    v[u] = (g < groups && r < nrec) ? (COHERENT ? load_partial(a) : *a) : 0.0;
+    const auto a = &base[(int64_t)min(g + u * groups, nrec - 1) * stride + off + e];
+    v[u] = COHERENT ? load_partial(a) : *a;
   }
 }
 
-NLSP_DEV void rec_finish(const double (&v)[8], int count, double* out, double* sh) {
+NLSP_DEV void rec_finish(const double (&v)[8], int nrec, int count, double* out, double* sh) {
   const int t = threadIdx.x;
   const int groups = NT / count, g = t / count;
   double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) s += v[u];
+  for (int u = 0; u < 8; ++u) s += (g < groups && g + u * groups < nrec) ? v[u] : 0.0;
   __syncthreads();
   sh[t] = (g < groups) ? s : 0.0;
   lds_tree_rows(sh, groups, count);
   if (t < count) out[t] = sh[t];
   __syncthreads();
-}
-
-// e = A_c^-1 c for every RHS: c in LDS (kp*R, layout j*R + r), result to
-// eout (LDS or global, same layout).  Thread t takes row i = t / SL of A_c^-1
-// and the column slice js = t % SL (SL consecutive lanes), all R right-hand
-// sides at once; the slices are added with butterflies.
-// The first 8 entries of this thread's row slice of A_c^-1, loaded ahead of
-// coarse_apply so that their latency overlaps other waits.
-NLSP_DEV void coarse_prefetch(const double* __restrict__ Ainv, int kp, double (&a)[8]) {
-  const int t = threadIdx.x;
-  const int SL = min(NT / kp, kp);
-  const int i = t / SL, js = t % SL;
-  const int len = kp / SL;
-  const double* row = Ainv + (int64_t)(i < kp ? i : 0) * kp + js * len;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) a[u] = (u < len) ? row[u] : 0.0;
-}
-
-NLSP_DEV void coarse_apply(const double* __restrict__ Ainv, int kp, int R, const double* cvec,
-                           double* eout, const double* pre = nullptr) {
-  const int t = threadIdx.x;
-  const int SL = min(NT / kp, kp);            // lanes per row (power of two, <= kp)
-  const int i = t / SL, js = t % SL;
-  const int len = kp / SL;                    // >= 1
-  const bool on = i < kp;                     // threads past kp*SL are idle
-  double acc[MAXR];
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) acc[r] = 0.0;
-  const double* row = Ainv + (int64_t)(on ? i : 0) * kp + js * len;
-  for (int j0 = 0; on && j0 < len; j0 += 8) {
-    double a[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = (pre && j0 == 0) ? pre[u] : ((j0 + u < len) ? row[j0 + u] : 0.0);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (j0 + u >= len) break;
-      const int j = js * len + j0 + u;
-#pragma unroll
-      for (int r = 0; r < MAXR; ++r)
-        if (r < R) acc[r] += a[u] * cvec[j * R + r];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    if (r < R) {
-      const double v = group_sum(acc[r], SL);
-      if (on && js == 0) eout[i * R + r] = v;
-    }
-  }
 }
 
 // A_c^-1 = Linv^T Linv (kp x kp), once per solve
@@ -342,18 +304,16 @@ struct QBatch {
   QT v[NB][4];
 };
 
+// Rows past the chunk (and idle row groups) load a clamped row instead of
+// branching around the load: the consumers only use rows < nrows of active row
+// groups, and an unconditional load is never waited for before the next one.
 template <typename QT, int NB>
 NLSP_DEV void q_fetch(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, const QMap& m,
                       int w0, QBatch<QT, NB>& b) {
 #pragma unroll
   for (int w = 0; w < NB; ++w) {
-    const int row = m.rg + (w0 + w) * m.ngr;
-    if (m.on && row < nrows) {
-      load4(Q + (row0 + row) * kp + 4 * m.jc, b.v[w]);
-    } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) b.v[w][u] = QT(0);
-    }
+    const int row = min(m.rg + (w0 + w) * m.ngr, nrows - 1);
+    load4(Q + (row0 + row) * kp + 4 * m.jc, b.v[w]);
   }
 }
 
@@ -446,7 +406,8 @@ NLSP_DEV void prolong_rows(const QT* __restrict__ Q, int64_t row0, int nrows, in
 
 template <typename QT>
 struct QB {
-  static constexpr int NB = (sizeof(QT) == 4) ? 6 : 4;  // no spills at 128 VGPRs
+  static constexpr int NB = (sizeof(QT) == 4) ? 6 : 2;  // update kernel: no spills at 128 VGPRs
+  static constexpr int NBR = 4;                          // matvec and residual kernels
 };
 
 struct ChunkRange {
@@ -460,11 +421,10 @@ NLSP_DEV ChunkRange my_chunks(const SysDev& S, int lb) {
   return cr;
 }
 
-// Restriction epilogue (kernel A and k_residual): this workgroup's record
-// [Q^T v | s1 | s2] (already in rpart) is summed per group of 16 by the
-// group's last workgroup into rgrp.  The next kernel sums the group records
-// in order and applies A_c^-1 itself, so this kernel ends one ticket level
-// earlier.
+// Restriction epilogue (matvec kernel and k_residual): this workgroup's
+// record [Qt^T v | s1 | s2] (already in rpart) is summed per group of 16 by
+// the group's last workgroup into rgrp.  The next kernel sums the group
+// records in order itself, so this kernel ends one ticket level early.
 NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double* sh) {
   if (!arrive_group(S.ticket, S.nblk, lb)) return;
   const int grp = lb / TICKET_GROUP;
@@ -476,127 +436,93 @@ NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double*
 }
 
 // ----------------------------------------------------- per-iteration scalars
-// What every workgroup of kernels A and B derives from kernel B's partials of
-// the previous iteration: r^T z, r^T z_old and ||r||^2 of the current residual,
-// the convergence test and whether the direction is updated.
-struct IterScalars {
-  double gam[MAXR], rzo[MAXR], rr[MAXR], beta[MAXR];
-  int conv[MAXR];       // ||r|| <= rtol ||f||
-  int act[MAXR];        // direction and q computed this iteration
-  int bad[MAXR];        // r^T z not positive / not finite, or ||r|| not finite
-};
-
-NLSP_DEV bool finite_pos(double v) { return v > 0.0 && v <= 1.7e308; }
-
-// Loads of kernel B's partials [r^T z | r^T z_old | ||r||^2] of iteration it,
-// issued early (see rec_issue); `fast` is false when they do not fit.
-// With R <= 4 (3R <= 12) and at most NT records, thread t loads record t
-// whole (`tiny`) and the records are added with butterflies; otherwise
-// rec_issue/rec_finish, or sum_records when that does not fit either.  The
-// per-RHS status is loaded here too, by threads t < R.
+// Loads of the update kernel's partials [r^T z | r^T z_old | ||r||^2 | p^T q]
+// of the previous iteration, issued early (see rec_issue); `fast` is false
+// when they do not fit.  With R <= 2 (4R <= 8) and at most NT records, thread
+// t loads record t whole (`tiny`) and the records are added with
+// butterflies; otherwise rec_issue/rec_finish, or sum_records when that does
+// not fit either.  The per-RHS status is loaded by threads t < R.
 struct ScalarLoads {
-  double v[12];
+  double v[8];
   bool fast, tiny;
-  RhsStatus st;
 };
 
-NLSP_DEV void scalars_issue(const SysDev& S, int it, ScalarLoads& L) {
+constexpr int BW = 4;   // update-kernel partials per RHS
+
+NLSP_DEV void bpart_issue(const SysDev& S, int par, ScalarLoads& L) {
   const int R = S.R, t = threadIdx.x;
-  L.tiny = (R <= 4 && pow2(R) && S.nblk <= NT);
-  L.fast = !L.tiny && rec_fits(S.nblk, 3 * R);
+  L.tiny = (R <= 2 && S.nblk <= NT);
+  L.fast = !L.tiny && rec_fits(S.nblk, BW * R);
   if (L.tiny) {
-    const double* rec = S.bpart[it & 1] + (int64_t)min(t, S.nblk - 1) * 3 * R;
+    // raw loads from clamped addresses; bpart_finish masks the surplus
+    const int nv = BW * R;   // <= 8
+    const auto rec = S.bpart[par] + (int64_t)min(t, S.nblk - 1) * nv;
 #pragma unroll
-    for (int j = 0; j < 12; ++j) L.v[j] = (j < 3 * R && t < S.nblk) ? rec[j] : 0.0;
+    for (int j = 0; j < 8; ++j) L.v[j] = rec[min(j, nv - 1)];
   } else if (L.fast) {
-    double v8[8];
-    rec_issue<false>(S.bpart[it & 1], S.nblk, 3 * R, 0, 3 * R, v8);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) L.v[j] = v8[j];
+    rec_issue<false>(S.bpart[par], S.nblk, BW * R, 0, BW * R, L.v);
   }
-  if (t < R) L.st = S.stat[it & 1][t];
 }
 
-NLSP_DEV void scalars_finish(const SysDev& S, const RhsStatus* cur, const ScalarLoads& L,
-                             IterScalars& sc, double* buf, double* sh, int it) {
+// totals of the partials into buf[0 .. 4R)
+NLSP_DEV void bpart_finish(const SysDev& S, int par, const ScalarLoads& L, double* buf, double* sh) {
   const int R = S.R;
   if (L.tiny) {
     // all 64 lanes of a wave hold different records: full butterflies per value
     constexpr int NW = NT / WAVE;
-    double v[12];
+    double v[8];
 #pragma unroll
-    for (int j = 0; j < 12; ++j) v[j] = L.v[j];
+    for (int j = 0; j < 8; ++j) v[j] = (j < BW * R && (int)threadIdx.x < S.nblk) ? L.v[j] : 0.0;
 #pragma unroll
-    for (int j = 0; j < 12; ++j)
-      if (j < 3 * R)   // uniform
+    for (int j = 0; j < 8; ++j)
+      if (j < BW * R)   // uniform
 #pragma unroll
         for (int o = WAVE / 2; o >= 1; o >>= 1) v[j] += __shfl_xor(v[j], o, WAVE);
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     __syncthreads();
     if (lane == 0)
 #pragma unroll
-      for (int j = 0; j < 12; ++j)
-        if (j < 3 * R) sh[w * 3 * R + j] = v[j];
+      for (int j = 0; j < 8; ++j)
+        if (j < BW * R) sh[w * BW * R + j] = v[j];
     __syncthreads();
-    if (threadIdx.x < 3 * R) {
+    if (threadIdx.x < BW * R) {
       double a = 0.0;
 #pragma unroll
-      for (int q = 0; q < NW; ++q) a += sh[q * 3 * R + threadIdx.x];
+      for (int q = 0; q < NW; ++q) a += sh[q * BW * R + threadIdx.x];
       buf[threadIdx.x] = a;
     }
     __syncthreads();
   } else if (L.fast) {
-    double v8[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v8[j] = L.v[j];
-    rec_finish(v8, 3 * R, buf, sh);
+    rec_finish(L.v, S.nblk, BW * R, buf, sh);
   } else {
-    sum_records<false>(S.bpart[it & 1], S.nblk, 3 * R, 0, 3 * R, buf, sh);
+    sum_records<false>(S.bpart[par], S.nblk, BW * R, 0, BW * R, buf, sh);
   }
-  if (threadIdx.x < R) {
-    const int c = threadIdx.x;
-    const RhsStatus& st = L.st;
-    const double g = buf[c], rz = buf[R + c], rr = buf[2 * R + c];
-    sc.gam[c] = g;
-    sc.rzo[c] = rz;
-    sc.rr[c] = rr;
-    const int rr_ok = rr <= 1.7e308;                       // false for NaN / Inf
-    sc.conv[c] = st.active && rr_ok && rr <= S.tol2 * st.ff;
-    sc.bad[c] = st.active && !sc.conv[c] && (!rr_ok || !finite_pos(g));
-    sc.act[c] = st.active && !sc.conv[c] && !sc.bad[c] && st.iters < S.maxit;
-    double beta = 0.0;
-    if (!st.restart && sc.act[c])
-      beta = S.flexible ? (g - rz) / st.gamma_old : g / st.gamma_old;
-    sc.beta[c] = beta;
-  }
-  __syncthreads();
 }
 
-// Sum over the threads sharing c = t % R of three values at once: the totals
-// land in red[k*R + c], k < 3.  One tree instead of three.  `sh` holds
-// 3*(NT + 16) doubles.
-NLSP_DEV void block_sum_rhs3(double a, double b, double d, int R, double* red, double* sh) {
+NLSP_DEV bool finite_pos(double v) { return v > 0.0 && v <= 1.7e308; }
+
+// Sum over the threads sharing c = t % R of K values at once: the totals land
+// in red[k*R + c].  One tree instead of K.  `sh` holds K*(NT + 16) doubles.
+template <int K>
+NLSP_DEV void block_sum_rhsk(const double (&v)[K], int R, double* red, double* sh) {
   if (pow2(R) && R <= WAVE) {
-    const double vv[3] = {a, b, d};
-    block_sum_waves<3>(vv, R, red, sh);
+    block_sum_waves<K>(v, R, red, sh);
     return;
   }
   const int t = threadIdx.x;
   const int nrows = (NT + R - 1) / R;
   __syncthreads();
-  // row-major [row][3R]: thread t = row*R + c
+  // row-major [row][K R]: thread t = row*R + c
   const int row = t / R, c = t % R;
-  sh[row * 3 * R + c] = a;
-  sh[row * 3 * R + R + c] = b;
-  sh[row * 3 * R + 2 * R + c] = d;
+#pragma unroll
+  for (int k = 0; k < K; ++k) sh[row * K * R + k * R + c] = v[k];
   if (t < nrows * R - NT) {   // pad the last partial row
     const int pr = (NT + t) / R, pc = (NT + t) % R;
-    sh[pr * 3 * R + pc] = 0.0;
-    sh[pr * 3 * R + R + pc] = 0.0;
-    sh[pr * 3 * R + 2 * R + pc] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[pr * K * R + k * R + pc] = 0.0;
   }
-  lds_tree_rows(sh, nrows, 3 * R);
-  if (t < 3 * R) red[t] = sh[t];
+  lds_tree_rows(sh, nrows, K * R);
+  if (t < K * R) red[t] = sh[t];
   __syncthreads();
 }
 
@@ -611,25 +537,70 @@ __global__ __launch_bounds__(NT) void k_dinv(OpDev op, double* dinv, float* dinv
   dinv32[i] = (float)d;
 }
 
+// Qt = Q A_c^-1 (n x kp), once per solve: restricting with Qt gives the
+// coarse coefficients A_c^-1 Q^T v directly.  64 rows per workgroup, four
+// threads per row, column tiles of up to 64 with A_c^-1 and the rows of Q
+// staged in LDS; float64 arithmetic, ascending sums.
+template <typename QT>
+__global__ __launch_bounds__(256) void k_qtilde(const QT* __restrict__ Q, const double* __restrict__ Ainv,
+                                                int64_t n, int kp, QT* __restrict__ Qt) {
+  __shared__ double qs[64][65];
+  __shared__ double as[64][64];
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int r = t / 4, cq = t % 4;
+  const int TW = min(kp, 64), cpt = TW / 4;   // 4, 8 or 16 columns per thread
+  for (int ct = 0; ct < kp; ct += TW) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int l0 = 0; l0 < kp; l0 += 64) {
+      const int LW = min(64, kp - l0);
+      __syncthreads();
+      for (int idx = t; idx < 64 * LW; idx += 256) {
+        const int rr = idx / LW, l = idx % LW;
+        const int64_t row = row0 + rr;
+        qs[rr][l] = (row < n) ? (double)Q[row * kp + l0 + l] : 0.0;
+      }
+      for (int idx = t; idx < LW * TW; idx += 256) {
+        const int l = idx / TW, j = idx % TW;
+        as[l][j] = Ainv[(int64_t)(l0 + l) * kp + ct + j];
+      }
+      __syncthreads();
+      for (int l = 0; l < LW; ++l) {
+        const double a = qs[r][l];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u < cpt) acc[u] += a * as[l][cq * cpt + u];
+      }
+    }
+    const int64_t row = row0 + r;
+    if (row < n)
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < cpt) Qt[row * kp + ct + cq * cpt + u] = QT(acc[u]);
+  }
+}
+
 // r = f - A x into `rout` for the RHS in `mask` (others untouched);
-// restriction records [Q^T r | ||r||^2 | ||f||^2], then the group (and top)
-// epilogue.  Used at start-up and for residual replacement.
+// restriction records [Qt^T r | ||r||^2 | ||f||^2] (Qt^T r = A_c^-1 Q^T r),
+// then the group epilogue.  Used at start-up and for residual replacement.
 template <typename QT>
 __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ sys,
                                                     const int* __restrict__ blk2sys, int nsys,
                                                     unsigned mask, int rout) {
   __shared__ double rv[NT];
-  __shared__ double sh[NT + 16];
+  __shared__ double sh[2 * (NT + 16)];
   __shared__ double red[4 * NT + 128];
-  __shared__ double outv[MAXR];
+  __shared__ double outv[2 * MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
   mask &= S.rmask;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
   const bool on = (mask >> c) & 1u;
-  const QT* Q = static_cast<const QT*>(S.Q);
+  const QT* Qt = static_cast<const QT*>(S.Qt);
   const QMap m = q_map(S.kp, R);
-  constexpr int NB = QB<QT>::NB;
+  constexpr int NB = QB<QT>::NBR;
   QBatch<QT, NB> qb;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double rr = 0.0, ff = 0.0;
@@ -638,7 +609,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     const int64_t row0 = ch * S.chunk_rows;
     const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-    q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+    q_fetch<QT, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
     const int64_t i = row0 + t / R;
     double rvv = 0.0;
     if (on && t / R < nrows) {
@@ -655,136 +626,102 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
     __syncthreads();
     rv[t] = rvv;
     __syncthreads();
-    restrict_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, rv, qb, acc);
+    restrict_rows<QT, NB>(Qt, row0, nrows, S.kp, R, m, rv, qb, acc);
   }
   double* rec = S.rpart + (int64_t)lb * S.rw;
   restrict_finish(m, S.kp, R, acc, red, rec);
   const int KR = S.kp * R;
-  block_sum_rhs(rr, R, outv, sh);
-  if (t < R) store_partial(&rec[KR + t], outv[t]);
-  block_sum_rhs(ff, R, outv, sh);
-  if (t < R) store_partial(&rec[KR + R + t], outv[t]);
+  const double v2[2] = {rr, ff};
+  block_sum_rhsk<2>(v2, R, outv, sh);
+  if (t < 2 * R) store_partial(&rec[KR + t], outv[t]);
   restriction_epilogue(S, lb, red, sh);
 }
 
-// kernel A: convergence test; beta; p_new = z + beta p_old (double buffer);
-// q = A p_new; restriction records [Q^T q | p^T q | 0], summed per group of 16
-// workgroups by the epilogue
+// Matvec kernel of iteration `it` (after the update kernel of `it`):
+// w = A z for the new z; restriction records [Qt^T w | z^T w | z^T q + p^T w]
+// (q, p: this iteration's direction pair), summed per group of 16 workgroups
+// by the epilogue.  Nothing here waits for a scalar: every workgroup streams
+// from its first instruction.  In a batch, a system whose right-hand sides
+// have all stopped exits at once.
 template <typename QT>
-__global__ __launch_bounds__(NT, 4) void k_iter_a(const SysDev* __restrict__ sys,
+__global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it) {
-  __shared__ double qv[NT];
-  __shared__ double sh[NT + 16];
+  __shared__ double wv[NT];
+  __shared__ double sh[2 * (NT + 16)];
   __shared__ double red[4 * NT + 128];
-  __shared__ double buf[4 * MAXR];
-  __shared__ IterScalars sc;
+  __shared__ double buf[2 * MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
+  if (nsys > 1 && S.nact[(it + 1) & 1] == 0) return;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  const QT* Q = static_cast<const QT*>(S.Q);
+  const QT* Qt = static_cast<const QT*>(S.Qt);
   const QMap m = q_map(S.kp, R);
-  constexpr int NB = QB<QT>::NB;
+  constexpr int NB = QB<QT>::NBR;
   QBatch<QT, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
-  const RhsStatus* cur = S.stat[it & 1];
-  ScalarLoads sl;
-  scalars_issue(S, it, sl);                                   // small loads first,
-  int64_t row0 = cr.c0 * S.chunk_rows;
-  int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
-  if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);  // then Q,
-  if (S.nact[it & 1] == 0) return;                            // then the early exit
-  scalars_finish(S, cur, sl, sc, buf, sh, it);
-  const bool act = sc.act[c] != 0;
-  const double beta = sc.beta[c];
-  const int par = cur[c].par;
-  const double* pold = S.p[par];
-  double* pnew = S.p[par ^ 1];
   const double* Z = S.z;
+  const double* Pv = S.p;
+  const double* Qv = S.q[(it + 1) & 1];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  double dp = 0.0;
+  double zw = 0.0, e1 = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    if (ch > cr.c0) {
-      row0 = ch * S.chunk_rows;
-      nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-      q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
-    }
-    double qval = 0.0;
-    if (act && t / R < nrows) {
+    const int64_t row0 = ch * S.chunk_rows;
+    const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
+    q_fetch<QT, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
+    double wval = 0.0;
+    if (t / R < nrows) {
       const int64_t i = row0 + t / R;
+      const int64_t g = i * R + c;
       int px, py, pz;
       decompose(S.op, i, px, py, pz);
-      auto pn = [&](int64_t j) { return Z[j * R + c] + beta * pold[j * R + c]; };
-      const double pi = pn(i);
-      qval = op_row<double>(S.op, i, px, py, pz, pn);
-      pnew[i * R + c] = pi;
-      S.q[i * R + c] = qval;
-      dp += pi * qval;
+      const double zi = Z[g], qi = Qv[g], pi = Pv[g];
+      wval = op_row<double>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
+      S.w[g] = wval;
+      zw += zi * wval;
+      e1 += zi * qi + pi * wval;
     }
     __syncthreads();
-    qv[t] = qval;
+    wv[t] = wval;
     __syncthreads();
-    restrict_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, qv, qb, acc);
+    restrict_rows<QT, NB>(Qt, row0, nrows, S.kp, R, m, wv, qb, acc);
   }
   double* rec = S.rpart + (int64_t)lb * S.rw;
   restrict_finish(m, S.kp, R, acc, red, rec);
   const int KR = S.kp * R;
-  block_sum_rhs(dp, R, buf, sh);
-  if (t < R) {
-    store_partial(&rec[KR + t], buf[t]);
-    store_partial(&rec[KR + R + t], 0.0);
-  }
+  const double v2[2] = {zw, e1};
+  block_sum_rhsk<2>(v2, R, buf, sh);
+  if (t < 2 * R) store_partial(&rec[KR + t], buf[t]);
   restriction_epilogue(S, lb, red, sh);
 }
 
-// J_{2nu} sweeps for nu > 1 on the new residual r_new = r_in - a q (a = alpha,
-// or 0 at a restart): first = 1 computes y2 = y1 + w D^-1 (r_new - A y1) with
-// y1 = w D^-1 r_new; later sweeps y <- y + w D^-1 (r_new - A y).  Every RHS
-// still marked active in stat[it & 1] is swept.
+// J_{2nu} sweeps for nu > 1 on the new residual r[rin] (written by the update
+// phase, or by k_residual): first = 1 computes y2 = y1 + w D^-1 (r - A y1)
+// with y1 = w D^-1 r; later sweeps y <- y + w D^-1 (r - A y).  Every RHS
+// marked active in stat[spar] is swept.
 template <typename PT>
 __global__ __launch_bounds__(NT) void k_sweep(const SysDev* __restrict__ sys,
-                                              const int* __restrict__ blk2sys, int nsys, int it,
-                                              int restart, int rin, int first, int src) {
-  __shared__ double sh[NT + 16];
-  __shared__ double buf[4 * MAXR];
-  __shared__ double s_alpha[MAXR];
-  __shared__ IterScalars sc;
+                                              const int* __restrict__ blk2sys, int nsys, int spar, int rin,
+                                              int first, int src) {
   const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (!restart && S.nact[it & 1] == 0) return;
+  if (S.nact[spar] == 0) return;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  const RhsStatus* cur = S.stat[it & 1];
-  if (!restart) {
-    ScalarLoads sl;
-    scalars_issue(S, it, sl);
-    scalars_finish(S, cur, sl, sc, buf, sh, it);
-    if (t < R) {
-      double pq = 0.0;   // p^T q: entry kp R + t of the group records, in order
-      for (int g = 0; g < ticket_groups(S.nblk); ++g) pq += S.rgrp[(int64_t)g * S.rw + S.kp * R + t];
-      s_alpha[t] = sc.gam[t] / pq;
-    }
-  } else if (t < R) {
-    s_alpha[t] = 0.0;
-  }
-  __syncthreads();
-  if (!cur[c].active) return;
+  if (!S.stat[spar][c].active) return;
   const PT om = PT(S.omega);
-  const double a = s_alpha[c];
   const double* Rin = S.r[rin];
-  const double* Qv = S.q;
-  auto rnew = [&](int64_t j) { return Rin[j * R + c] - a * Qv[j * R + c]; };
-  const PT* yin = static_cast<const PT*>(S.w[src]);
-  PT* yout = static_cast<PT*>(S.w[first ? 0 : (src ^ 1)]);
+  const PT* yin = static_cast<const PT*>(S.wj[src]);
+  PT* yout = static_cast<PT*>(S.wj[first ? 0 : (src ^ 1)]);
   const ChunkRange cr = my_chunks(S, lb);
+  auto dj = [&](int64_t j) -> PT { return (sizeof(PT) == 4) ? PT(S.dinv32[j]) : PT(S.dinv[j]); };
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     const int64_t i = ch * S.chunk_rows + t / R;
     if (t / R >= S.chunk_rows || i >= S.op.n) continue;
     int px, py, pz;
     decompose(S.op, i, px, py, pz);
-    auto dj = [&](int64_t j) -> PT { return (sizeof(PT) == 4) ? PT(S.dinv32[j]) : PT(S.dinv[j]); };
-    const PT ri = PT(rnew(i));
+    const PT ri = PT(Rin[i * R + c]);
     PT yi, ay;
     if (first) {
-      auto y1 = [&](int64_t j) { return om * dj(j) * PT(rnew(j)); };
+      auto y1 = [&](int64_t j) { return om * dj(j) * PT(Rin[j * R + c]); };
       yi = y1(i);
       ay = op_row<PT>(S.op, i, px, py, pz, y1);
     } else {
@@ -795,39 +732,90 @@ __global__ __launch_bounds__(NT) void k_sweep(const SysDev* __restrict__ sys,
   }
 }
 
-// kernel B: status; alpha; e <- e - alpha A_c^-1 Q^T q (so e = A_c^-1 Q^T r_new);
-// x += alpha p; r_new = r - alpha q into r[(it+1)&1]; z = J r_new + Q e;
-// partials [r^T z | r^T z_old | ||r_new||^2] into bpart[(it+1)&1].
-//   restart = 0: an iteration; group records [Q^T q | p^T q | 0] from kernel A
-//   restart = 1: after k_residual (which wrote r into r[(it+1)&1] and group
-//                records [Q^T r | ||r||^2 | ||f||^2]) for the RHS in
-//                `mask`: no update, `init` also takes ||f||^2, and the next
-//                kernel A uses beta = 0.
-// wsrc < 0: J_2 inline (nu = 1); else J_{2nu} r_new is read from w[wsrc].
+// Phases of the update kernel.
+constexpr int PH_UPD = 1;   // decisions; p, q, x and the new residual
+constexpr int PH_Z = 2;     // z = J r_new + Q c_new; partials r^T z, r^T z_old, ||r||^2
+
+// Update kernel of iteration `it`.  Every workgroup sums the partials of the
+// previous update kernel [r^T z | r^T z_old | ||r||^2 | p^T q] and the group
+// records of the matvec kernel [Qt^T w | z^T w | z^T q_old + p_old^T w] in a
+// fixed order and takes, per RHS, the same decisions:
+//   convergence test on ||r||; beta; p^T q of the new pair from
+//   z^T w + beta (z^T q_old + p_old^T w) + beta^2 p_old^T q_old; alpha;
+//   g = A_c^-1 Q^T q = Qt^T w + beta g_old;  c_new = c - alpha g.
+// Then per row: p = z + beta p_old; q = w + beta q_old (q double-buffered by
+// parity); x += alpha p; r_new = r - alpha q (double-buffered); and, with
+// PH_Z, z = J_2 r_new + Q c_new with J_2 formed from the neighbours' r_new
+// (nu = 1; for nu > 1 J_{2nu} r_new comes from wj[wsrc]).  Partials of
+// [r^T z | r^T z_old | ||r||^2 | p^T q] into bpart[(it+1)&1].
+//   restart = 1: after k_residual (r in r[(it+1)&1], group records
+//     [Qt^T r | ||r||^2 | ||f||^2]) for the RHS in `mask`: c = Qt^T r, no
+//     update, `init` also takes ||f||^2, and the next iteration uses beta = 0.
+//   phase = PH_UPD only (nu > 1): stops after r_new; phase = PH_Z only, not a
+//     restart: z for the RHS the update phase advanced (stat[(it+1)&1]).
 template <typename QT>
-__global__ __launch_bounds__(NT, 4) void k_iter_b(const SysDev* __restrict__ sys,
+__global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it,
-                                                  int restart, unsigned mask, int init, int wsrc) {
+                                                  int restart, unsigned mask, int init, int phase, int wsrc) {
   __shared__ QT ws[NT];
   __shared__ QT ys[NT];
-  __shared__ double sh[3 * (NT + 16)];
-  __shared__ double ebuf[2048];
-  __shared__ double dq[2048];
-  __shared__ double cg[2048 + 2 * MAXR];
-  __shared__ double tscal[2 * MAXR];
-  __shared__ double buf[4 * MAXR];
-  __shared__ double s_alpha[MAXR];
-  __shared__ int s_upd[MAXR], s_next[MAXR];
-  __shared__ IterScalars sc;
+  __shared__ double sh[NT + 16];
+  // cvec: c_new = A_c^-1 Q^T r_new; gvec: g = A_c^-1 Q^T q; cg: the matvec (or
+  // k_residual) group records, summed.  The region serves the final partial
+  // sums once they are dead.
+  __shared__ double big[3 * 2048 + 2 * MAXR];
+  double* cvec = big;
+  double* gvec = big + 2048;
+  double* cg = big + 2 * 2048;
+  __shared__ double buf[BW * MAXR];          // update partials, summed
+  __shared__ double s_alpha[MAXR], s_beta[MAXR];
+  __shared__ int s_upd[MAXR], s_rs[MAXR], s_next[MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
   mask &= S.rmask;
-  const int nxt = (it + 1) & 1;
+  const int cp = it & 1, nxt = (it + 1) & 1;
   const int KR = S.kp * S.R;
-  if (!restart && S.nact[it & 1] == 0) {
+  const bool decide = restart || (phase & PH_UPD);
+  const bool normal = decide && !restart;
+  const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
+  const int t = threadIdx.x, R = S.R, c = t % R;
+  const Glob<const QT>* Q = (Glob<const QT>*)S.Q;
+  const QMap m = q_map(S.kp, R);
+  constexpr int NB = QB<QT>::NB;
+  QBatch<QT, NB> qb;
+  const ChunkRange cr = my_chunks(S, lb);
+  // every load of the prologue is issued before the first wait: partials,
+  // group records, status, coarse state (into registers), then Q
+  ScalarLoads sl;
+  sl.fast = sl.tiny = false;
+  if (normal) bpart_issue(S, cp, sl);
+  // status of RHS t (threads t < R use it), loaded unconditionally
+  const RhsStatus st0 = S.stat[cp][min(t, R - 1)];
+  const int ngrp = ticket_groups(S.nblk);
+  const bool gfast = decide && rec_fits(ngrp, S.rw);
+  double gv[8];
+  if (gfast) rec_issue<false>(S.rgrp, ngrp, S.rw, 0, S.rw, gv);
+  double cin_r[4], gin_r[4];   // kp*R <= 2048 = 4 NT
+  {
+    const auto cin = decide ? S.cstate[cp] : S.cstate[nxt];
+    const auto gin = S.gstate[cp];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = min(t + u * NT, KR - 1);
+      cin_r[u] = cin[idx];
+      gin_r[u] = gin[idx];
+    }
+  }
+  int64_t row0 = cr.c0 * S.chunk_rows;
+  int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
+  if ((phase & PH_Z) && cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+  if (normal && S.nact[cp] == 0) {
     // nothing iterates: carry the state over to the next parity
     if (blockIdx.x == S.blk0) {
-      for (int idx = threadIdx.x; idx < KR; idx += NT) S.estate[nxt][idx] = S.estate[it & 1][idx];
-      if (threadIdx.x < S.R) S.stat[nxt][threadIdx.x] = S.stat[it & 1][threadIdx.x];
+      for (int idx = threadIdx.x; idx < KR; idx += NT) {
+        S.cstate[nxt][idx] = S.cstate[cp][idx];
+        S.gstate[nxt][idx] = S.gstate[cp][idx];
+      }
+      if (threadIdx.x < S.R) S.stat[nxt][threadIdx.x] = S.stat[cp][threadIdx.x];
       if (threadIdx.x == 0) {
         S.nact[nxt] = 0;
         *S.n_active = 0;
@@ -835,165 +823,211 @@ __global__ __launch_bounds__(NT, 4) void k_iter_b(const SysDev* __restrict__ sys
     }
     return;
   }
-  const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
-  const int t = threadIdx.x, R = S.R, c = t % R;
-  const QT* Q = static_cast<const QT*>(S.Q);
-  const QMap m = q_map(S.kp, R);
-  constexpr int NB = QB<QT>::NB;
-  QBatch<QT, NB> qb;
-  const ChunkRange cr = my_chunks(S, lb);
-  const RhsStatus* cur = S.stat[it & 1];
-  // small loads first (scalars, the restriction's group records, e), then Q
-  ScalarLoads sl;
-  sl.fast = sl.tiny = false;
-  if (!restart) scalars_issue(S, it, sl);
-  const int ngrp = ticket_groups(S.nblk);
-  const bool gfast = rec_fits(ngrp, S.rw);
-  double gv[8], av[8];
-  if (gfast) rec_issue<false>(S.rgrp, ngrp, S.rw, 0, S.rw, gv);
-  coarse_prefetch(S.Ainv, S.kp, av);
-  for (int idx = t; idx < KR; idx += NT) ebuf[idx] = S.estate[it & 1][idx];
-  int64_t row0 = cr.c0 * S.chunk_rows;
-  int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
-  if (cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
-  if (!restart) scalars_finish(S, cur, sl, sc, buf, sh, it);
-  // c = [Q^T v | s1 | s2] summed over the groups in order (v = q, or r after
-  // k_residual), then dq = A_c^-1 Q^T v
-  if (gfast)
-    rec_finish(gv, S.rw, cg, sh);
-  else
-    sum_records<false>(S.rgrp, ngrp, S.rw, 0, S.rw, cg, sh);
-  coarse_apply(S.Ainv, S.kp, R, cg, dq, av);
-  if (t < 2 * R) tscal[t] = cg[KR + t];
-  __syncthreads();
-  if (restart)
-    for (int idx = t; idx < KR; idx += NT)
-      if ((mask >> (idx % R)) & 1u) ebuf[idx] = dq[idx];
-  __syncthreads();
-  // ---- per-RHS decisions (identical in every workgroup) and the new state
-  if (t < R) {
-    RhsStatus nx = cur[t];
-    int upd = 0, next = 0;
-    double alpha = 0.0;
-    if (restart) {
-      if ((mask >> t) & 1u) {
-        if (init) nx.ff = tscal[R + t];
-        nx.restart = 1;
-        nx.conv = 0;
-        if (!(nx.ff <= 1.7e308)) {
-          nx.status = NLSP_E_NONFINITE;
-        } else {
-          nx.status = NLSP_NOT_CONVERGED;
-          next = 1;
-        }
-      } else {
-        next = nx.active;
-      }
-      upd = next && ((mask >> t) & 1u);
-    } else if (cur[t].active) {
-      nx.restart = 0;
-      if (sc.conv[t]) {
-        nx.status = NLSP_OK;
-        nx.conv = 1;
-      } else if (sc.bad[t]) {
-        // r^T z <= 0 with finite values is a breakdown; anything non-finite is not
-        const bool gfin = sc.gam[t] == sc.gam[t] && fabs(sc.gam[t]) <= 1.7e308;
-        const bool rfin = sc.rr[t] <= 1.7e308;
-        nx.status = (gfin && rfin) ? NLSP_E_BREAKDOWN : NLSP_E_NONFINITE;
-      } else if (!sc.act[t]) {
-        nx.status = NLSP_NOT_CONVERGED;   // maxit reached
-      } else {
-        const double d = tscal[t];
-        nx.par ^= 1;                      // kernel A wrote the new direction
-        nx.gamma_old = sc.gam[t];
-        if (!finite_pos(d)) {
-          nx.status = (d == d && d <= 1.7e308) ? NLSP_E_BREAKDOWN : NLSP_E_NONFINITE;
-        } else {
-          alpha = sc.gam[t] / d;
-          upd = 1;
-          next = 1;
-          nx.iters += 1;
-        }
-      }
-    }
-    nx.active = next;
-    s_alpha[t] = alpha;
-    s_upd[t] = upd;
-    s_next[t] = next;
-    if (lb == 0) S.stat[nxt][t] = nx;
-  }
-  __syncthreads();
-  // ---- e = A_c^-1 Q^T r_new (workgroup 0 keeps it for the next iteration)
-  if (!restart)
-    for (int idx = t; idx < KR; idx += NT) ebuf[idx] -= s_alpha[idx % R] * dq[idx];
-  __syncthreads();
-  if (lb == 0) {
-    for (int idx = t; idx < KR; idx += NT) S.estate[nxt][idx] = ebuf[idx];
-    if (t == 0) {
-      int cnt = 0;
-      for (int k = 0; k < R; ++k) cnt += s_next[k];
-      S.nact[nxt] = cnt;
-      *S.n_active = cnt;
+  if (!decide && S.nact[nxt] == 0) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = t + u * NT;
+    if (idx < KR) {
+      cvec[idx] = cin_r[u];
+      gvec[idx] = gin_r[u];
     }
   }
-  // ---- x += alpha p; r_new = r - alpha q; z = J r_new + Q e
+  if (decide) {
+    if (normal) bpart_finish(S, cp, sl, buf, sh);
+    if (gfast)
+      rec_finish(gv, ngrp, S.rw, cg, sh);
+    else
+      sum_records<false>(S.rgrp, ngrp, S.rw, 0, S.rw, cg, sh);
+    // ---- per-RHS decisions (identical in every workgroup) and the new state
+    if (t < R) {
+      // the status fields as scalars (a local struct would be placed in LDS)
+      double gamma_old = st0.gamma_old, ff = st0.ff;
+      int active = st0.active, iters = st0.iters, status = st0.status, rflag = st0.restart, conv = st0.conv;
+      int upd = 0, next = 0, rs = 0;
+      double alpha = 0.0, beta = 0.0;
+      if (restart) {
+        if ((mask >> t) & 1u) {
+          if (init) ff = cg[KR + R + t];
+          rflag = 1;
+          conv = 0;
+          if (!(ff <= 1.7e308)) {
+            status = NLSP_E_NONFINITE;
+          } else {
+            status = NLSP_NOT_CONVERGED;
+            next = 1;
+          }
+        } else {
+          next = active;
+        }
+        upd = next && ((mask >> t) & 1u);
+      } else if (active) {
+        const double g = buf[t], rz = buf[R + t], rr = buf[2 * R + t], pqo = buf[3 * R + t];
+        const double zw = cg[KR + t], e1 = cg[KR + R + t];
+        const bool rr_ok = rr <= 1.7e308;                   // false for NaN / Inf
+        const bool cv = rr_ok && rr <= S.tol2 * ff;
+        rs = rflag;
+        rflag = 0;
+        if (cv) {
+          status = NLSP_OK;
+          conv = 1;
+        } else if (!rr_ok || !finite_pos(g)) {
+          // r^T z <= 0 with finite values is a breakdown; anything non-finite is not
+          const bool gfin = g == g && fabs(g) <= 1.7e308;
+          status = (gfin && rr_ok) ? NLSP_E_BREAKDOWN : NLSP_E_NONFINITE;
+        } else if (iters >= S.maxit) {
+          status = NLSP_NOT_CONVERGED;
+        } else {
+          beta = rs ? 0.0 : (S.flexible ? (g - rz) / gamma_old : g / gamma_old);
+          const double pq = rs ? zw : zw + beta * e1 + beta * beta * pqo;
+          gamma_old = g;
+          if (!finite_pos(pq)) {
+            status = (pq == pq && pq <= 1.7e308) ? NLSP_E_BREAKDOWN : NLSP_E_NONFINITE;
+          } else {
+            alpha = g / pq;
+            upd = 1;
+            next = 1;
+            iters += 1;
+          }
+        }
+      }
+      s_alpha[t] = alpha;
+      s_beta[t] = beta;
+      s_upd[t] = upd;
+      s_rs[t] = rs;
+      s_next[t] = next;
+      if (lb == 0) {
+        RhsStatus nx{};
+        nx.gamma_old = gamma_old;
+        nx.ff = ff;
+        nx.active = next;
+        nx.iters = iters;
+        nx.status = status;
+        nx.restart = rflag;
+        nx.conv = conv;
+        S.stat[nxt][t] = nx;
+      }
+    }
+    __syncthreads();
+    // ---- coarse state: g = Qt^T q, c_new = c - alpha g (restart: c = Qt^T r)
+    for (int idx = t; idx < KR; idx += NT) {
+      const int r = idx % R;
+      if (!s_upd[r]) continue;
+      if (restart) {
+        cvec[idx] = cg[idx];
+        gvec[idx] = 0.0;
+      } else {
+        const double g = s_rs[r] ? cg[idx] : cg[idx] + s_beta[r] * gvec[idx];
+        gvec[idx] = g;
+        cvec[idx] -= s_alpha[r] * g;
+      }
+    }
+    __syncthreads();
+    if (lb == 0) {
+      for (int idx = t; idx < KR; idx += NT) {
+        S.cstate[nxt][idx] = cvec[idx];
+        S.gstate[nxt][idx] = gvec[idx];
+      }
+      if (t == 0) {
+        int cnt = 0;
+        for (int k = 0; k < R; ++k) cnt += s_next[k];
+        S.nact[nxt] = cnt;
+        *S.n_active = cnt;
+      }
+    }
+  } else {
+    if (t < R) {
+      s_upd[t] = S.stat[nxt][t].active;   // advanced by the update phase
+      s_alpha[t] = s_beta[t] = 0.0;
+      s_rs[t] = 0;
+    }
+    __syncthreads();
+  }
+  // ---- the rows
   const bool upd = s_upd[c] != 0;
-  const double alpha = s_alpha[c];
+  const bool full = normal && (phase & PH_UPD);   // p, q, x, r_new formed here
+  const double alpha = s_alpha[c], beta = s_beta[c];
+  const bool rs = s_rs[c] != 0;
+  const double* Rin = S.r[full ? cp : nxt];
+  double* Rout = S.r[nxt];
+  const double* Wv = S.w;
+  const double* Qo = S.q[cp];
+  double* Qn = S.q[nxt];
+  auto qnew = [&](int64_t j) { return rs ? Wv[j * R + c] : Wv[j * R + c] + beta * Qo[j * R + c]; };
+  auto rnew = [&](int64_t j) { return full ? Rin[j * R + c] - alpha * qnew(j) : Rin[j * R + c]; };
   QT e4[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) e4[u] = QT(ebuf[(4 * m.jc + u) * R + m.c]);
+  for (int u = 0; u < 4; ++u) e4[u] = QT(cvec[(4 * m.jc + u) * R + m.c]);
   const QT om = QT(S.omega);
-  const double* Rin = S.r[restart ? nxt : (it & 1)];
-  double* Rout = S.r[nxt];
-  const double* Qv = S.q;
-  const double* P = S.p[cur[c].par ^ 1];
-  auto rnew = [&](int64_t j) { return restart ? Rin[j * R + c] : Rin[j * R + c] - alpha * Qv[j * R + c]; };
-  double gam = 0.0, rzo = 0.0, rr = 0.0;
+  double gam = 0.0, rzo = 0.0, rr = 0.0, pq = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     if (ch > cr.c0) {
       row0 = ch * S.chunk_rows;
       nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-      q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+      if (phase & PH_Z) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
     }
     const bool mine = upd && t / R < nrows;
     const int64_t i = row0 + t / R;
-    QT w = QT(0);
-    double ri = 0.0;
+    const int64_t g = i * R + c;
+    double ri = 0.0, zo = 0.0;
+    QT wjv = QT(0);
     if (mine) {
-      ri = rnew(i);
-      if (wsrc < 0) {
-        int px, py, pz;
-        decompose(S.op, i, px, py, pz);
-        auto dj = [&](int64_t j) -> QT {
-          return (sizeof(QT) == 4) ? QT(S.dinv32[j]) : QT(S.dinv[j]);
-        };
-        auto y = [&](int64_t j) { return dj(j) * QT(rnew(j)); };
-        const QT yi = y(i);
-        const QT ay = op_row<QT>(S.op, i, px, py, pz, y);
-        w = QT(2) * om * yi - om * om * dj(i) * ay;
+      zo = S.z[g];
+      if (full) {
+        const double pi = rs ? zo : zo + beta * S.p[g];
+        const double qi = qnew(i);
+        S.p[g] = pi;
+        Qn[g] = qi;
+        S.x[g] += alpha * pi;
+        ri = Rin[g] - alpha * qi;
+        pq += pi * qi;
+        if (!(phase & PH_Z)) Rout[g] = ri;
       } else {
-        w = static_cast<const QT*>(S.w[wsrc])[i * R + c];
+        ri = Rin[g];
+      }
+      if (phase & PH_Z) {
+        if (wsrc < 0) {
+          int px, py, pz;
+          decompose(S.op, i, px, py, pz);
+          auto dj = [&](int64_t j) -> QT {
+            return (sizeof(QT) == 4) ? QT(S.dinv32[j]) : QT(S.dinv[j]);
+          };
+          auto y = [&](int64_t j) { return dj(j) * QT(rnew(j)); };
+          const QT yi = dj(i) * QT(ri);
+          const QT ay = op_row<QT>(S.op, i, px, py, pz, y);
+          wjv = QT(2) * om * yi - om * om * dj(i) * ay;
+        } else {
+          wjv = static_cast<const QT*>(S.wj[wsrc])[g];
+        }
       }
     }
-    __syncthreads();
-    ws[t] = w;
-    prolong_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
-    __syncthreads();
-    if (mine) {
-      const int64_t g = i * R + c;
-      if (!restart) {
-        S.x[g] += alpha * P[g];
-        Rout[g] = ri;
+    if (phase & PH_Z) {
+      __syncthreads();
+      ws[t] = wjv;
+      prolong_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
+      __syncthreads();
+      if (mine) {
+        const double zn = (double)ws[t] + (double)ys[t];
+        if (full) Rout[g] = ri;
+        S.z[g] = zn;
+        gam += ri * zn;
+        if (S.flexible) rzo += ri * zo;
+        rr += ri * ri;
       }
-      const double zn = (double)ws[t] + (double)ys[t];
-      if (S.flexible) rzo += ri * S.z[g];
-      S.z[g] = zn;
-      gam += ri * zn;
-      rr += ri * ri;
     }
   }
-  block_sum_rhs3(gam, rzo, rr, R, buf, sh);
-  if (t < 3 * R) S.bpart[nxt][(int64_t)lb * 3 * R + t] = buf[t];
+  double* bp = S.bpart[nxt] + (int64_t)lb * BW * R;
+  static_assert(3 * 2048 >= BW * (NT + 16), "partial-sum scratch");
+  if (phase & PH_Z) {
+    const double v4[4] = {gam, rzo, rr, pq};
+    block_sum_rhsk<4>(v4, R, buf, big);   // cvec, gvec, cg are dead here
+    // p^T q: this kernel's (full), none at a restart, the update phase's otherwise
+    const int nw = (full || restart) ? BW * R : 3 * R;
+    if (t < nw) bp[t] = buf[t];
+  } else {
+    const double v1[1] = {pq};
+    block_sum_rhsk<1>(v1, R, buf, sh);
+    if (t < R) bp[3 * R + t] = buf[t];
+  }
 }
 
 // ||f - A x||^2 partials per RHS (true residual) into dpart
@@ -1041,11 +1075,11 @@ __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
 // carved for every system of a batch before anything else, so one fill clears
 // them all.
 struct SolveLayout {
-  double *p0, *p1, *q, *z, *estate0, *estate1;
+  double *p, *q0, *q1, *z, *w, *cstate0, *cstate1, *gstate0, *gstate1;
   unsigned* ticket;
-  double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *dpart, *Ainv;
+  double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *dpart, *Ainv, *Qt;
   float* dinv32;
-  void *w0, *w1;
+  void *wj0, *wj1;
 };
 
 // Arrays shared by the systems of a batch (contiguous, so the host reads or
@@ -1101,12 +1135,15 @@ inline SysShape shape_of(int64_t n, int kp, int R, int rows_per_block) {
 
 inline void carve_zero(Carver& cv, const SysShape& h, SolveLayout& L) {
   const int64_t nR = h.n * h.R;
-  L.p0 = cv.take<double>(nR);
-  L.p1 = cv.take<double>(nR);
-  L.q = cv.take<double>(nR);
+  L.p = cv.take<double>(nR);
+  L.q0 = cv.take<double>(nR);
+  L.q1 = cv.take<double>(nR);
   L.z = cv.take<double>(nR);
-  L.estate0 = cv.take<double>((size_t)h.kp * h.R);
-  L.estate1 = cv.take<double>((size_t)h.kp * h.R);
+  L.w = cv.take<double>(nR);
+  L.cstate0 = cv.take<double>((size_t)h.kp * h.R);
+  L.cstate1 = cv.take<double>((size_t)h.kp * h.R);
+  L.gstate0 = cv.take<double>((size_t)h.kp * h.R);
+  L.gstate1 = cv.take<double>((size_t)h.kp * h.R);
   L.ticket = cv.take<unsigned>(ticket_words(h.nblk));
 }
 
@@ -1115,16 +1152,17 @@ inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
   const int rw = restriction_width(h.kp, h.R);
   L.r0 = cv.take<double>(nR);
   L.r1 = cv.take<double>(nR);
-  L.w0 = cv.take<double>(nR);
-  L.w1 = cv.take<double>(nR);
+  L.wj0 = cv.take<double>(nR);
+  L.wj1 = cv.take<double>(nR);
   L.dinv = cv.take<double>(h.n);
   L.dinv32 = cv.take<float>(h.n);
-  L.bpart0 = cv.take<double>((size_t)h.nblk * 3 * h.R);
-  L.bpart1 = cv.take<double>((size_t)h.nblk * 3 * h.R);
+  L.bpart0 = cv.take<double>((size_t)h.nblk * BW * h.R);
+  L.bpart1 = cv.take<double>((size_t)h.nblk * BW * h.R);
   L.rpart = cv.take<double>((size_t)h.nblk * rw);
   L.rgrp = cv.take<double>((size_t)ticket_groups(h.nblk) * rw);
   L.dpart = cv.take<double>((size_t)h.nblk * h.R);
   L.Ainv = cv.take<double>((size_t)h.kp * h.kp);
+  L.Qt = cv.take<double>((size_t)h.n * h.kp);   // sized for float64, used as the type of Q
 }
 
 // Carves the whole workspace (base == nullptr: sizes only).  `Ls` receives the
@@ -1169,34 +1207,38 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.nchunks = h.nchunks;
   hs.cpb = (h.nchunks + h.nblk - 1) / h.nblk;
   hs.rw = restriction_width(h.kp, R);
-  hs.Q = (M.prec == NLSP_FP64) ? (const void*)M.Q64 : (const void*)M.Q32;
-  hs.Linv = M.Linv;
-  hs.Ainv = L.Ainv;
-  hs.f = f;
-  hs.x = u;
-  hs.r[0] = L.r0;
-  hs.r[1] = L.r1;
-  hs.p[0] = L.p0;
-  hs.p[1] = L.p1;
-  hs.q = L.q;
-  hs.z = L.z;
-  hs.w[0] = L.w0;
-  hs.w[1] = L.w1;
-  hs.dinv = L.dinv;
-  hs.dinv32 = L.dinv32;
-  hs.bpart[0] = L.bpart0;
-  hs.bpart[1] = L.bpart1;
-  hs.rpart = L.rpart;
-  hs.rgrp = L.rgrp;
-  hs.estate[0] = L.estate0;
-  hs.estate[1] = L.estate1;
-  hs.dpart = L.dpart;
-  hs.ticket = L.ticket;
-  hs.stat[0] = B.stat0 + (size_t)i * R;
-  hs.stat[1] = B.stat1 + (size_t)i * R;
-  hs.nact = B.counters + 4 * i;
-  hs.n_active = B.counters + 4 * i + 2;
-  hs.rr_true = B.rr_true + (size_t)i * R;
+  hs.Q = as_glob((M.prec == NLSP_FP64) ? (const void*)M.Q64 : (const void*)M.Q32);
+  hs.Qt = as_glob((const void*)L.Qt);
+  hs.Linv = as_glob((const double*)M.Linv);
+  hs.Ainv = as_glob(L.Ainv);
+  hs.f = as_glob(f);
+  hs.x = as_glob(u);
+  hs.r[0] = as_glob(L.r0);
+  hs.r[1] = as_glob(L.r1);
+  hs.p = as_glob(L.p);
+  hs.q[0] = as_glob(L.q0);
+  hs.q[1] = as_glob(L.q1);
+  hs.z = as_glob(L.z);
+  hs.w = as_glob(L.w);
+  hs.wj[0] = as_glob((void*)L.wj0);
+  hs.wj[1] = as_glob((void*)L.wj1);
+  hs.dinv = as_glob(L.dinv);
+  hs.dinv32 = as_glob(L.dinv32);
+  hs.bpart[0] = as_glob(L.bpart0);
+  hs.bpart[1] = as_glob(L.bpart1);
+  hs.rpart = as_glob(L.rpart);
+  hs.rgrp = as_glob(L.rgrp);
+  hs.cstate[0] = as_glob(L.cstate0);
+  hs.cstate[1] = as_glob(L.cstate1);
+  hs.gstate[0] = as_glob(L.gstate0);
+  hs.gstate[1] = as_glob(L.gstate1);
+  hs.dpart = as_glob(L.dpart);
+  hs.ticket = as_glob(L.ticket);
+  hs.stat[0] = as_glob(B.stat0 + (size_t)i * R);
+  hs.stat[1] = as_glob(B.stat1 + (size_t)i * R);
+  hs.nact = as_glob(B.counters + 4 * i);
+  hs.n_active = as_glob(B.counters + 4 * i + 2);
+  hs.rr_true = as_glob(B.rr_true + (size_t)i * R);
   hs.nu = M.nu;
   hs.omega = M.omega;
   hs.tol2 = opts->rtol * opts->rtol;
@@ -1243,26 +1285,45 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
       launch(nullptr, nullptr);
     }
   };
-  // J_{2nu} r_new (nu > 1) and kernel B of iteration `it`
-  auto launch_b = [&](hipStream_t st, int it, int restart, unsigned mask, int init, bool can_time) {
-    int wsrc = -1;
-    if (nu > 1) {
-      const int rin = restart ? ((it + 1) & 1) : (it & 1);
-      hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, rin, 1, 0);
-      int src = 0;
-      for (int s = 1; s < 2 * nu - 1; ++s) {
-        hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, rin, 0, src);
-        src ^= 1;
+  // the update kernel(s) of iteration `it`: one launch for nu = 1; for
+  // nu > 1 the update phase, the J_{2nu} sweeps on r_new and the z phase
+  auto launch_update = [&](hipStream_t st, int it, int restart, unsigned mask, int init, bool can_time) {
+    auto upd = [&](int phase, int wsrc, bool timed_one) {
+      if (timed_one) {
+        timed(1, [&](hipEvent_t a, hipEvent_t b) {
+          hipExtLaunchKernelGGL(k_update<QT>, grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart, mask,
+                                init, phase, wsrc);
+        });
+      } else {
+        hipLaunchKernelGGL(k_update<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init, phase,
+                           wsrc);
       }
-      wsrc = src;
+    };
+    if (nu == 1) {
+      upd(restart ? PH_Z : (PH_UPD | PH_Z), -1, can_time);
+      return;
     }
+    int spar = it & 1;
+    if (!restart) {
+      upd(PH_UPD, -1, can_time);
+      spar = (it + 1) & 1;
+    }
+    const int rin = (it + 1) & 1;
+    hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, st, dsys, b2s, nsys, spar, rin, 1, 0);
+    int src = 0;
+    for (int s = 1; s < 2 * nu - 1; ++s) {
+      hipLaunchKernelGGL(k_sweep<QT>, grid, block, 0, st, dsys, b2s, nsys, spar, rin, 0, src);
+      src ^= 1;
+    }
+    upd(PH_Z, src, false);
+  };
+  auto launch_matvec = [&](hipStream_t st, int it, bool can_time) {
     if (can_time) {
       timed(2, [&](hipEvent_t a, hipEvent_t b) {
-        hipExtLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart, mask,
-                              init, wsrc);
+        hipExtLaunchKernelGGL(k_matvec<QT>, grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
       });
     } else {
-      hipLaunchKernelGGL(k_iter_b<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init, wsrc);
+      hipLaunchKernelGGL(k_matvec<QT>, grid, block, 0, st, dsys, b2s, nsys, it);
     }
   };
   hipGraphExec_t gexec = nullptr;
@@ -1290,14 +1351,19 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     }                                   \
   } while (0)
   for (int i = 0; i < nsys; ++i) {
-    hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs[i].op.n, NT)), block, 0, stream, hs[i].op,
-                       const_cast<double*>(hs[i].dinv), const_cast<float*>(hs[i].dinv32));
+    // (C casts: the descriptor's pointers carry the device's address space)
+    hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs[i].op.n, NT)), block, 0, stream, hs[i].op, (double*)hs[i].dinv,
+                       (float*)hs[i].dinv32);
     hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs[i].kp * hs[i].kp, 256)), dim3(256), 0, stream,
-                       hs[i].Linv, hs[i].kp, const_cast<double*>(hs[i].Ainv));
+                       (const double*)hs[i].Linv, hs[i].kp, (double*)hs[i].Ainv);
+    hipLaunchKernelGGL(k_qtilde<QT>, dim3(ceil_div(hs[i].op.n, 64)), dim3(256), 0, stream, (const QT*)hs[i].Q,
+                       (const double*)hs[i].Ainv, hs[i].op.n, hs[i].kp, (QT*)hs[i].Qt);
   }
-  // start-up as iteration -1: r = f - A x into r[0], then kernel B in restart mode
+  // start-up as iteration -1: r = f - A x into r[0], the update kernel in
+  // restart mode (c = Qt^T r, z = M^-1 r), then w = A z
   hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, b2s, nsys, all, 0);
-  launch_b(stream, -1, 1, all, 1, true);
+  launch_update(stream, -1, 1, all, 1, true);
+  launch_matvec(stream, -1, true);
   NLSP_RUN(hipGetLastError());
   std::vector<RhsStatus> hst((size_t)nsys * R);
   NLSP_RUN(hipMemcpyAsync(hst.data(), B.stat0, sizeof(RhsStatus) * nsys * R, hipMemcpyDeviceToHost, stream));
@@ -1335,8 +1401,8 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
             return NLSP_E_HIP;
           }
           for (int k = 0; k < every; ++k) {
-            hipLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, cs, dsys, b2s, nsys, it + k);
-            launch_b(cs, it + k, 0, 0u, 0, false);
+            launch_update(cs, it + k, 0, 0u, 0, false);
+            launch_matvec(cs, it + k, false);
           }
           const hipError_t ce = hipStreamEndCapture(cs, &gph);
           (void)hipStreamDestroy(cs);
@@ -1347,10 +1413,8 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
         it += every;
       } else {
         for (int k = 0; k < every; ++k, ++it) {
-          timed(1, [&](hipEvent_t a, hipEvent_t b) {
-            hipExtLaunchKernelGGL(k_iter_a<QT>, grid, block, 0, stream, a, b, 0, dsys, b2s, nsys, it);
-          });
-          launch_b(stream, it, 0, 0u, 0, true);
+          launch_update(stream, it, 0, 0u, 0, true);
+          launch_matvec(stream, it, true);
         }
       }
       launched += every;
@@ -1390,7 +1454,7 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
       return worst;
     }
     // residual replacement: r = f - A x for the `redo` RHS into r[it & 1] and
-    // those RHS restart from it (kernel B in restart mode as iteration it - 1,
+    // those RHS restart from it (the update kernel in restart mode as iteration it - 1,
     // reading stat[(it - 1) & 1], which receives the current state of every
     // system with the redo RHS made active)
     std::vector<SysDev> hr = hs;   // descriptors with the restart masks
@@ -1405,7 +1469,8 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     NLSP_RUN(hipMemcpyAsync(B.counters, cnt.data(), sizeof(int) * 4 * nsys, hipMemcpyHostToDevice, stream));
     NLSP_RUN(hipMemcpyAsync(B.sysdev, hr.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, b2s, nsys, all, it & 1);
-    launch_b(stream, it - 1, 1, all, 0, true);
+    launch_update(stream, it - 1, 1, all, 0, true);
+    launch_matvec(stream, it - 1, true);
     NLSP_RUN(hipMemcpyAsync(B.sysdev, hs.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
     NLSP_RUN(hipGetLastError());
     // the host arrays above are reused by the next pass: finish their copies

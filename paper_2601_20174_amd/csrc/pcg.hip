@@ -449,18 +449,20 @@ struct ScalarLoads {
 
 constexpr int BW = 4;   // update-kernel partials per RHS
 
-NLSP_DEV void bpart_issue(const SysDev& S, int par, ScalarLoads& L) {
-  const int R = S.R, t = threadIdx.x;
-  L.tiny = (R <= 2 && S.nblk <= NT);
-  L.fast = !L.tiny && rec_fits(S.nblk, BW * R);
-  if (L.tiny) {
-    // raw loads from clamped addresses; bpart_finish masks the surplus
-    const int nv = BW * R;   // <= 8
-    const auto rec = S.bpart[par] + (int64_t)min(t, S.nblk - 1) * nv;
+NLSP_DEV void bpart_issue(const SysDev& S, int par, ScalarLoads& L, bool want) {
+  const int R = S.R, t = threadIdx.x, nv = BW * R;
+  L.tiny = want && (R <= 2 && S.nblk <= NT);
+  L.fast = want && !L.tiny && rec_fits(S.nblk, nv);
+  // always eight loads from clamped addresses, whatever the layout (a load
+  // count that depends on a branch would make every later wait conservative);
+  // bpart_finish masks the surplus
+  const int groups = NT / nv, e = t % nv, g = t / nv;
+  const auto base = S.bpart[par];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) L.v[j] = rec[min(j, nv - 1)];
-  } else if (L.fast) {
-    rec_issue<false>(S.bpart[par], S.nblk, BW * R, 0, BW * R, L.v);
+  for (int u = 0; u < 8; ++u) {
+    const int64_t off_tiny = (int64_t)min(t, S.nblk - 1) * nv + min(u, nv - 1);
+    const int64_t off_fast = (int64_t)min(g + u * groups, S.nblk - 1) * nv + e;
+    L.v[u] = base[L.tiny ? off_tiny : (L.fast ? off_fast : 0)];
   }
 }
 
@@ -783,17 +785,27 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   constexpr int NB = QB<QT>::NB;
   QBatch<QT, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
-  // every load of the prologue is issued before the first wait: partials,
-  // group records, status, coarse state (into registers), then Q
+  // every load of the prologue is issued before the first wait, and the same
+  // number of them on every path (waits complete in issue order, and a count
+  // that depends on a branch makes the compiler wait for everything):
+  // partials, status, active counts, group records, coarse state (into
+  // registers), then the first batch of Q
   ScalarLoads sl;
-  sl.fast = sl.tiny = false;
-  if (normal) bpart_issue(S, cp, sl);
+  bpart_issue(S, cp, sl, normal);
   // status of RHS t (threads t < R use it), loaded unconditionally
   const RhsStatus st0 = S.stat[cp][min(t, R - 1)];
+  const int nact_cp = S.nact[cp], nact_nxt = S.nact[nxt];
+  const int act_nxt = S.stat[nxt][min(t, R - 1)].active;
   const int ngrp = ticket_groups(S.nblk);
   const bool gfast = decide && rec_fits(ngrp, S.rw);
   double gv[8];
-  if (gfast) rec_issue<false>(S.rgrp, ngrp, S.rw, 0, S.rw, gv);
+  {
+    const int cnt = gfast ? S.rw : 1;
+    const int groups = NT / cnt, e = t % cnt, g = t / cnt;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      gv[u] = S.rgrp[gfast ? (int64_t)min(g + u * groups, ngrp - 1) * S.rw + e : 0];
+  }
   double cin_r[4], gin_r[4];   // kp*R <= 2048 = 4 NT
   {
     const auto cin = decide ? S.cstate[cp] : S.cstate[nxt];
@@ -805,10 +817,12 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
       gin_r[u] = gin[idx];
     }
   }
-  int64_t row0 = cr.c0 * S.chunk_rows;
-  int nrows = (cr.c0 < cr.c1) ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 0;
-  if ((phase & PH_Z) && cr.c0 < cr.c1) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
-  if (normal && S.nact[cp] == 0) {
+  // a workgroup without a chunk issues the same loads on row 0
+  const bool has = cr.c0 < cr.c1;
+  int64_t row0 = has ? cr.c0 * S.chunk_rows : 0;
+  int nrows = has ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 1;
+  q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+  if (normal && nact_cp == 0) {
     // nothing iterates: carry the state over to the next parity
     if (blockIdx.x == S.blk0) {
       for (int idx = threadIdx.x; idx < KR; idx += NT) {
@@ -823,7 +837,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     }
     return;
   }
-  if (!decide && S.nact[nxt] == 0) return;
+  if (!decide && nact_nxt == 0) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int idx = t + u * NT;
@@ -936,7 +950,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     }
   } else {
     if (t < R) {
-      s_upd[t] = S.stat[nxt][t].active;   // advanced by the update phase
+      s_upd[t] = act_nxt;   // advanced by the update phase
       s_alpha[t] = s_beta[t] = 0.0;
       s_rs[t] = 0;
     }

@@ -49,6 +49,7 @@ namespace nlsp {
 
 constexpr int NT = 512;   // threads per workgroup of the solver kernels
 constexpr int MAXR = 16;  // right-hand sides per solve
+constexpr int BW = 4;     // update-kernel partials per RHS: r^T z, r^T z_old, ||r||^2, p^T q
 
 struct RhsStatus {
   double gamma_old;  // r^T z of the previous iteration (beta's denominator)
@@ -68,6 +69,7 @@ struct SysDev {
   int64_t nchunks;
   int64_t cpb;             // chunks per workgroup: ceil(nchunks / nblk)
   int rw;                  // restriction record width: kp*R + 2R
+  int gw;                  // group record width: rw + 4R (the update partials ride along)
   // device pointers (global address space in the device pass)
   Glob<const void>* Q;     // (n, kp), float or double: prolongation
   Glob<const void>* Qt;    // (n, kp) Q A_c^-1, same type: restriction to coarse coefficients
@@ -85,7 +87,7 @@ struct SysDev {
   Glob<float>* dinv32;
   Glob<double>* bpart[2];  // [nblk][4R]  update partials [r^T z | r^T z_old | ||r||^2 | p^T q], by parity
   Glob<double>* rpart;     // [nblk][rw]  restriction records [Qt^T v | s1 | s2]
-  Glob<double>* rgrp;      // [ngrp][rw]  group records
+  Glob<double>* rgrp;      // [ngrp][gw]  group records [restriction record | update partials]
   Glob<double>* cstate[2]; // [kp*R]      c = A_c^-1 Q^T r, by parity
   Glob<double>* gstate[2]; // [kp*R]      g = A_c^-1 Q^T q, by parity
   Glob<double>* dpart;     // [nblk][R]   true-residual partials
@@ -423,82 +425,50 @@ NLSP_DEV ChunkRange my_chunks(const SysDev& S, int lb) {
 
 // Restriction epilogue (matvec kernel and k_residual): this workgroup's
 // record [Qt^T v | s1 | s2] (already in rpart) is summed per group of 16 by
-// the group's last workgroup into rgrp.  The next kernel sums the group
-// records in order itself, so this kernel ends one ticket level early.
-NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double* sh) {
+// the group's last workgroup into rgrp, together with the group's partials of
+// the preceding update kernel (bpart[bpar]; zeros for bpar < 0), so the next
+// update kernel reads one short list of group records and sums it in order
+// itself.  This kernel ends one ticket level early.
+NLSP_DEV void restriction_epilogue(const SysDev& S, int lb, double* red, double* sh, int bpar) {
   if (!arrive_group(S.ticket, S.nblk, lb)) return;
   const int grp = lb / TICKET_GROUP;
   const int r0 = grp * TICKET_GROUP;
   const int nrec = min(TICKET_GROUP, S.nblk - r0);
-  sum_records<true>(S.rpart + (int64_t)r0 * S.rw, nrec, S.rw, 0, S.rw, red, sh);
-  double* grec = S.rgrp + (int64_t)grp * S.rw;
-  for (int idx = threadIdx.x; idx < S.rw; idx += NT) store_partial(&grec[idx], red[idx]);
-}
-
-// ----------------------------------------------------- per-iteration scalars
-// Loads of the update kernel's partials [r^T z | r^T z_old | ||r||^2 | p^T q]
-// of the previous iteration, issued early (see rec_issue); `fast` is false
-// when they do not fit.  With R <= 2 (4R <= 8) and at most NT records, thread
-// t loads record t whole (`tiny`) and the records are added with
-// butterflies; otherwise rec_issue/rec_finish, or sum_records when that does
-// not fit either.  The per-RHS status is loaded by threads t < R.
-struct ScalarLoads {
-  double v[8];
-  bool fast, tiny;
-};
-
-constexpr int BW = 4;   // update-kernel partials per RHS
-
-NLSP_DEV void bpart_issue(const SysDev& S, int par, ScalarLoads& L, bool want) {
-  const int R = S.R, t = threadIdx.x, nv = BW * R;
-  L.tiny = want && (R <= 2 && S.nblk <= NT);
-  L.fast = want && !L.tiny && rec_fits(S.nblk, nv);
-  // always eight loads from clamped addresses, whatever the layout (a load
-  // count that depends on a branch would make every later wait conservative);
-  // bpart_finish masks the surplus
-  const int groups = NT / nv, e = t % nv, g = t / nv;
-  const auto base = S.bpart[par];
+  const int bw = BW * S.R;
+  const auto ra = S.rpart + (int64_t)r0 * S.rw;
+  const auto rb = S.bpart[bpar < 0 ? 0 : bpar] + (int64_t)r0 * bw;
+  if (S.gw <= NT && nrec <= 4 * (NT / S.gw)) {
+    // one pass over [record | partials]: at most 4 records per thread, all
+    // loads issued before the first add
+    const int t = threadIdx.x, cnt = S.gw, groups = NT / cnt, e = t % cnt, g = t / cnt;
+    double v[4];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int64_t off_tiny = (int64_t)min(t, S.nblk - 1) * nv + min(u, nv - 1);
-    const int64_t off_fast = (int64_t)min(g + u * groups, S.nblk - 1) * nv + e;
-    L.v[u] = base[L.tiny ? off_tiny : (L.fast ? off_fast : 0)];
-  }
-}
-
-// totals of the partials into buf[0 .. 4R)
-NLSP_DEV void bpart_finish(const SysDev& S, int par, const ScalarLoads& L, double* buf, double* sh) {
-  const int R = S.R;
-  if (L.tiny) {
-    // all 64 lanes of a wave hold different records: full butterflies per value
-    constexpr int NW = NT / WAVE;
-    double v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (j < BW * R && (int)threadIdx.x < S.nblk) ? L.v[j] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (j < BW * R)   // uniform
-#pragma unroll
-        for (int o = WAVE / 2; o >= 1; o >>= 1) v[j] += __shfl_xor(v[j], o, WAVE);
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j < BW * R) sh[w * BW * R + j] = v[j];
-    __syncthreads();
-    if (threadIdx.x < BW * R) {
-      double a = 0.0;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) a += sh[q * BW * R + threadIdx.x];
-      buf[threadIdx.x] = a;
+    for (int u = 0; u < 4; ++u) {
+      const int r = min(g + u * groups, nrec - 1);
+      const double x = load_partial(&ra[(int64_t)r * S.rw + min(e, S.rw - 1)]);
+      const double y = rb[(int64_t)r * bw + max(e - S.rw, 0)];
+      v[u] = (e < S.rw) ? x : y;
     }
+    double sum = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      sum += (g < groups && g + u * groups < nrec && (e < S.rw || bpar >= 0)) ? v[u] : 0.0;
     __syncthreads();
-  } else if (L.fast) {
-    rec_finish(L.v, S.nblk, BW * R, buf, sh);
+    sh[t] = (g < groups) ? sum : 0.0;
+    lds_tree_rows(sh, groups, cnt);
+    if (t < cnt) red[t] = sh[t];
+    __syncthreads();
   } else {
-    sum_records<false>(S.bpart[par], S.nblk, BW * R, 0, BW * R, buf, sh);
+    sum_records<true>(ra, nrec, S.rw, 0, S.rw, red, sh);
+    if (bpar >= 0) {
+      sum_records<false>(rb, nrec, bw, 0, bw, red + S.rw, sh);
+    } else {
+      for (int idx = threadIdx.x; idx < bw; idx += NT) red[S.rw + idx] = 0.0;
+      __syncthreads();
+    }
   }
+  double* grec = S.rgrp + (int64_t)grp * S.gw;
+  for (int idx = threadIdx.x; idx < S.gw; idx += NT) store_partial(&grec[idx], red[idx]);
 }
 
 NLSP_DEV bool finite_pos(double v) { return v > 0.0 && v <= 1.7e308; }
@@ -636,7 +606,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
   const double v2[2] = {rr, ff};
   block_sum_rhsk<2>(v2, R, outv, sh);
   if (t < 2 * R) store_partial(&rec[KR + t], outv[t]);
-  restriction_epilogue(S, lb, red, sh);
+  restriction_epilogue(S, lb, red, sh, -1);
 }
 
 // Matvec kernel of iteration `it` (after the update kernel of `it`):
@@ -693,7 +663,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
   const double v2[2] = {zw, e1};
   block_sum_rhsk<2>(v2, R, buf, sh);
   if (t < 2 * R) store_partial(&rec[KR + t], buf[t]);
-  restriction_epilogue(S, lb, red, sh);
+  restriction_epilogue(S, lb, red, sh, (it + 1) & 1);
 }
 
 // J_{2nu} sweeps for nu > 1 on the new residual r[rin] (written by the update
@@ -765,11 +735,11 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   // cvec: c_new = A_c^-1 Q^T r_new; gvec: g = A_c^-1 Q^T q; cg: the matvec (or
   // k_residual) group records, summed.  The region serves the final partial
   // sums once they are dead.
-  __shared__ double big[3 * 2048 + 2 * MAXR];
+  __shared__ double big[3 * 2048 + 6 * MAXR];
   double* cvec = big;
   double* gvec = big + 2048;
-  double* cg = big + 2 * 2048;
-  __shared__ double buf[BW * MAXR];          // update partials, summed
+  double* cg = big + 2 * 2048;   // [Qt^T w | z^T w | e1 | r^T z | r^T z_old | ||r||^2 | p^T q]
+  __shared__ double buf[BW * MAXR];          // final partial sums
   __shared__ double s_alpha[MAXR], s_beta[MAXR];
   __shared__ int s_upd[MAXR], s_rs[MAXR], s_next[MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
@@ -787,24 +757,22 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   const ChunkRange cr = my_chunks(S, lb);
   // every load of the prologue is issued before the first wait, and the same
   // number of them on every path (waits complete in issue order, and a count
-  // that depends on a branch makes the compiler wait for everything):
-  // partials, status, active counts, group records, coarse state (into
-  // registers), then the first batch of Q
-  ScalarLoads sl;
-  bpart_issue(S, cp, sl, normal);
+  // that depends on a branch makes the compiler wait for everything): status,
+  // active counts, group records, coarse state (into registers), then the
+  // first batch of Q
   // status of RHS t (threads t < R use it), loaded unconditionally
   const RhsStatus st0 = S.stat[cp][min(t, R - 1)];
   const int nact_cp = S.nact[cp], nact_nxt = S.nact[nxt];
   const int act_nxt = S.stat[nxt][min(t, R - 1)].active;
   const int ngrp = ticket_groups(S.nblk);
-  const bool gfast = decide && rec_fits(ngrp, S.rw);
+  const bool gfast = decide && rec_fits(ngrp, S.gw);
   double gv[8];
   {
-    const int cnt = gfast ? S.rw : 1;
+    const int cnt = gfast ? S.gw : 1;
     const int groups = NT / cnt, e = t % cnt, g = t / cnt;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      gv[u] = S.rgrp[gfast ? (int64_t)min(g + u * groups, ngrp - 1) * S.rw + e : 0];
+      gv[u] = S.rgrp[gfast ? (int64_t)min(g + u * groups, ngrp - 1) * S.gw + e : 0];
   }
   double cin_r[4], gin_r[4];   // kp*R <= 2048 = 4 NT
   {
@@ -847,11 +815,10 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     }
   }
   if (decide) {
-    if (normal) bpart_finish(S, cp, sl, buf, sh);
     if (gfast)
-      rec_finish(gv, ngrp, S.rw, cg, sh);
+      rec_finish(gv, ngrp, S.gw, cg, sh);
     else
-      sum_records<false>(S.rgrp, ngrp, S.rw, 0, S.rw, cg, sh);
+      sum_records<false>(S.rgrp, ngrp, S.gw, 0, S.gw, cg, sh);
     // ---- per-RHS decisions (identical in every workgroup) and the new state
     if (t < R) {
       // the status fields as scalars (a local struct would be placed in LDS)
@@ -875,7 +842,8 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         }
         upd = next && ((mask >> t) & 1u);
       } else if (active) {
-        const double g = buf[t], rz = buf[R + t], rr = buf[2 * R + t], pqo = buf[3 * R + t];
+        const double* up = cg + S.rw;   // the previous update's partials
+        const double g = up[t], rz = up[R + t], rr = up[2 * R + t], pqo = up[3 * R + t];
         const double zw = cg[KR + t], e1 = cg[KR + R + t];
         const bool rr_ok = rr <= 1.7e308;                   // false for NaN / Inf
         const bool cv = rr_ok && rr <= S.tol2 * ff;
@@ -1030,7 +998,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     }
   }
   double* bp = S.bpart[nxt] + (int64_t)lb * BW * R;
-  static_assert(3 * 2048 >= BW * (NT + 16), "partial-sum scratch");
+  static_assert(3 * 2048 + 6 * MAXR >= BW * (NT + 16), "partial-sum scratch");
   if (phase & PH_Z) {
     const double v4[4] = {gam, rzo, rr, pq};
     block_sum_rhsk<4>(v4, R, buf, big);   // cvec, gvec, cg are dead here
@@ -1173,7 +1141,7 @@ inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
   L.bpart0 = cv.take<double>((size_t)h.nblk * BW * h.R);
   L.bpart1 = cv.take<double>((size_t)h.nblk * BW * h.R);
   L.rpart = cv.take<double>((size_t)h.nblk * rw);
-  L.rgrp = cv.take<double>((size_t)ticket_groups(h.nblk) * rw);
+  L.rgrp = cv.take<double>((size_t)ticket_groups(h.nblk) * (rw + BW * h.R));
   L.dpart = cv.take<double>((size_t)h.nblk * h.R);
   L.Ainv = cv.take<double>((size_t)h.kp * h.kp);
   L.Qt = cv.take<double>((size_t)h.n * h.kp);   // sized for float64, used as the type of Q
@@ -1221,6 +1189,7 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.nchunks = h.nchunks;
   hs.cpb = (h.nchunks + h.nblk - 1) / h.nblk;
   hs.rw = restriction_width(h.kp, R);
+  hs.gw = hs.rw + BW * R;
   hs.Q = as_glob((M.prec == NLSP_FP64) ? (const void*)M.Q64 : (const void*)M.Q32);
   hs.Qt = as_glob((const void*)L.Qt);
   hs.Linv = as_glob((const double*)M.Linv);

@@ -386,6 +386,46 @@ NLSP_DEV void restrict_finish(const QMap& m, int kp, int R, const double (&acc)[
   for (int idx = threadIdx.x; idx < KR; idx += NT) store_partial(&out[idx], red[idx]);
 }
 
+// restrict_finish plus the workgroup sums of two per-thread values per RHS
+// (t % R) in one barrier round: out[KR + k*R + c] for k < 2.  Both use wave
+// butterflies; needs R a power of two (the caller falls back otherwise).
+NLSP_DEV void restrict_finish_x2(const QMap& m, int kp, int R, const double (&acc)[4], const double (&x)[2],
+                                 double* red, double* out) {
+  const int KR = kp * R;
+  const int pairs = m.lpr * R;
+  constexpr int NW = NT / WAVE;
+  double v[4] = {acc[0], acc[1], acc[2], acc[3]};
+  for (int o = WAVE / 2; o >= pairs; o >>= 1)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] += __shfl_xor(v[u], o, WAVE);
+  double y[2] = {x[0], x[1]};
+  for (int o = WAVE / 2; o >= R; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y[k] += __shfl_xor(y[k], o, WAVE);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  double* red2 = red + NW * KR;
+  __syncthreads();
+  if (lane < pairs)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) red[w * KR + (4 * m.jc + u) * R + m.c] = v[u];
+  if (lane < R)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) red2[(w * 2 + k) * R + lane] = y[k];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < KR + 2 * R; idx += NT) {
+    double s = 0.0;
+    if (idx < KR) {
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s += red[q * KR + idx];
+    } else {
+      const int j = idx - KR;   // k*R + c
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s += red2[q * 2 * R + j];
+    }
+    store_partial(&out[idx], s);
+  }
+}
+
 // ys[row*R + c] = sum_j Q[row][j] e[j][c] for the chunk rows (prolongation),
 // arithmetic in QT; the lpr lanes of a row add with butterflies.  All lanes
 // run the same trip count (shuffles need the whole wave).
@@ -658,11 +698,15 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     restrict_rows<QT, NB>(Qt, row0, nrows, S.kp, R, m, wv, qb, acc);
   }
   double* rec = S.rpart + (int64_t)lb * S.rw;
-  restrict_finish(m, S.kp, R, acc, red, rec);
   const int KR = S.kp * R;
   const double v2[2] = {zw, e1};
-  block_sum_rhsk<2>(v2, R, buf, sh);
-  if (t < 2 * R) store_partial(&rec[KR + t], buf[t]);
+  if (pow2(R) && m.lpr * R <= WAVE && (NT / WAVE) * (KR + 2 * R) <= 4 * NT + 128) {
+    restrict_finish_x2(m, S.kp, R, acc, v2, red, rec);
+  } else {
+    restrict_finish(m, S.kp, R, acc, red, rec);
+    block_sum_rhsk<2>(v2, R, buf, sh);
+    if (t < 2 * R) store_partial(&rec[KR + t], buf[t]);
+  }
   restriction_epilogue(S, lb, red, sh, (it + 1) & 1);
 }
 

@@ -309,6 +309,30 @@ size_t galerkin_bwd_workspace_bytes(int batch, int n, int k);
 int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, float* gP, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* Galerkin-convergence term (Sec. 4 and the appendix's Galerkin objective,
+ * the projected energy that the Galerkin coarse space minimises) for a batch:
+ *   J_b(P) = ||A_b^{1/2} (I - P (P^T A_b P)^{-1} P^T A_b) S_b||_F^2
+ *          = tr(S^T A S) - tr(W^T A_c^{-1} W),   W = P^T A S,  A_c = P^T A P,
+ *   dJ_b/dP_b = 2 [A P Z Z^T - A S Z^T],  Z = A_c^{-1} W   (A_b symmetric).
+ *   A      host descriptor with batched coefficients, as for galerkin_fwd
+ *   P      device (batch, n, k) float32      S  device (batch, n, m) float32
+ *   J      device (batch) float32            bad device (batch) int: 1 where
+ *          P^T A P was not positive definite (J and M of that sample invalid)
+ *   saved  device, galerkin_term_saved_bytes: [A S | A P] (float32) and the
+ *          backward's small matrix, written by the forward, read by the
+ *          backward (caller-owned, 256-byte aligned)
+ * Limits: 1 <= k <= 64, m + k <= 256, k m <= 4096, n (m + k) < 2^31.  Float32
+ * stencil and MFMA products, slab sums, Cholesky and the k x m solves in
+ * float64.  Asynchronous on `stream`. */
+size_t galerkin_term_saved_bytes(int batch, const nlsp_operator* A, int k, int m);
+size_t galerkin_term_workspace_bytes(int batch, const nlsp_operator* A, int k, int m);
+int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const float* S, int k, int m, float* J,
+                      int* bad, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream);
+/* dL/dP_b = gJ_b dJ_b/dP_b from `saved` (gJ device (batch) float32, gP device
+ * (batch, n, k) float32).  Asynchronous on `stream`. */
+int galerkin_term_bwd(int batch, const nlsp_operator* A, int k, int m, const void* saved, const float* gJ,
+                      float* gP, void* stream);
+
 /* Thin QR of a batch of n x k matrices (the qf() of Sec. 4 that makes the
  * predicted basis orthonormal): A = Q R, R upper triangular with positive
  * diagonal, by CholeskyQR2 (Gram matrix in float64 from float32 MFMA

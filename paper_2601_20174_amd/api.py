@@ -373,6 +373,75 @@ def galerkin_product(P: torch.Tensor, op: Operator) -> torch.Tensor:
     return GalerkinProduct.apply(P, op)
 
 
+# ------------------------------------------------- Galerkin-convergence term
+def galerkin_term_saved_bytes(batch: int, op: Operator, k: int, m: int) -> int:
+    return int(_L().galerkin_term_saved_bytes(batch, ctypes.byref(op.c()), k, m))
+
+
+def galerkin_term_workspace_bytes(batch: int, op: Operator, k: int, m: int) -> int:
+    return int(_L().galerkin_term_workspace_bytes(batch, ctypes.byref(op.c()), k, m))
+
+
+def galerkin_term_fwd(op: Operator, P: torch.Tensor, S: torch.Tensor):
+    """J_b = ||A^{1/2}(I - P A_c^{-1} P^T A) S||_F^2 per sample, P (batch, n, k)
+    and S (batch, n, m) float32; ``op`` carries the batched coefficients.
+    Returns (J, bad, saved)."""
+    if P.dim() != 3 or S.dim() != 3 or P.shape[:2] != S.shape[:2]:
+        raise ValueError("P must be (batch, n, k) and S (batch, n, m)")
+    batch, n, k = P.shape
+    m = S.shape[2]
+    if n != nlsp_operator_size(op):
+        raise ValueError("rows must match the operator size")
+    per = {OP_FV5: n, OP_FV7: n, OP_STENCIL9: 9}.get(op.kind, 0)
+    if per and (op.coef is None or op.coef.numel() < batch * per):
+        raise ValueError(f"batched coefficients: need {batch} x {per} values")
+    sb = galerkin_term_saved_bytes(batch, op, k, m)
+    nb = galerkin_term_workspace_bytes(batch, op, k, m)
+    if sb == 0 or nb == 0:
+        raise NlspError("galerkin_term_workspace_bytes", E_INVALID)
+    J = torch.empty(batch, dtype=torch.float32, device=P.device)
+    bad = torch.empty(batch, dtype=torch.int32, device=P.device)
+    saved = _workspace(sb, P.device)
+    ws = _workspace(nb, P.device)
+    rc = _L().galerkin_term_fwd(batch, ctypes.byref(op.c()), _dev(P, torch.float32, "P"),
+                                _dev(S, torch.float32, "S"), k, m, J.data_ptr(), bad.data_ptr(),
+                                saved.data_ptr(), saved.numel(), ws.data_ptr(), ws.numel(), _stream())
+    _check("galerkin_term_fwd", rc)
+    return J, bad, saved
+
+
+def galerkin_term_bwd(op: Operator, k: int, m: int, saved: torch.Tensor, gJ: torch.Tensor) -> torch.Tensor:
+    batch = gJ.numel()
+    n = nlsp_operator_size(op)
+    gP = torch.empty(batch, n, k, dtype=torch.float32, device=saved.device)
+    rc = _L().galerkin_term_bwd(batch, ctypes.byref(op.c()), k, m, saved.data_ptr(),
+                                _dev(gJ, torch.float32, "gJ"), gP.data_ptr(), _stream())
+    _check("galerkin_term_bwd", rc)
+    return gP
+
+
+class GalerkinTerm(torch.autograd.Function):
+    """J(P) per sample with the library's backward."""
+
+    @staticmethod
+    def forward(ctx, P, S, op):
+        J, bad, saved = galerkin_term_fwd(op, P.contiguous(), S.contiguous())
+        ctx.op, ctx.k, ctx.m = op, P.shape[2], S.shape[2]
+        ctx.save_for_backward(saved)
+        ctx.mark_non_differentiable(bad)
+        return J, bad
+
+    @staticmethod
+    def backward(ctx, gJ, gbad):
+        (saved,) = ctx.saved_tensors
+        return galerkin_term_bwd(ctx.op, ctx.k, ctx.m, saved, gJ.contiguous().to(torch.float32)), None, None
+
+
+def galerkin_term(P: torch.Tensor, S: torch.Tensor, op: Operator):
+    """Returns (J, bad); J is differentiable in P."""
+    return GalerkinTerm.apply(P, S, op)
+
+
 # ------------------------------------------------------------ batched solve
 @dataclasses.dataclass
 class System:

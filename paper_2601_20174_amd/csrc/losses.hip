@@ -668,6 +668,122 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
+// ------------------------------------------------ Galerkin-convergence term
+// J_b(P) = tr(S^T A S) - tr(W^T A_c^-1 W), W = P^T A S, A_c = P^T A P (the
+// projected-energy objective of the appendix, in the projector identity's
+// form).  With A_c = R^T R (R upper), V = R^-T W and Z = R^-1 V = A_c^-1 W:
+//   J = tr(S^T A S) - ||V||_F^2,
+//   dJ/dP = 2 [A P Z Z^T - A S Z^T] = [A S | A P] M,
+//   M = [-2 Z^T ; 2 Z Z^T]   ((m + k) x k).
+// The forward stores X = [A S | A P] (n x (m + k), float32) and M; the
+// backward is one product pass over X.
+
+// X[i][c] = (A S)_ic for c < m, (A P)_i(c-m) otherwise (float32 products of
+// the float64 stencil), and per-workgroup partials of tr(S^T A S) in float64
+__global__ __launch_bounds__(NT) void k_gterm_apply(OpDev op, int64_t cstride, int k, int m, FastDiv fw,
+                                                    const float* __restrict__ P, const float* __restrict__ S,
+                                                    float* __restrict__ X, double* __restrict__ spart) {
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.y;
+  const int w = m + k;
+  const uint32_t g = blockIdx.x * NT + threadIdx.x;
+  OpDev ob = op;
+  if (ob.coef) ob.coef += (int64_t)b * cstride;
+  double ss = 0.0;
+  if ((int64_t)g < op.n * w) {
+    const uint32_t i = fdiv(g, fw);
+    const int c = (int)(g - i * (uint32_t)w);
+    int px, py, pz;
+    decompose(ob, i, px, py, pz);
+    const float* Sb = S + (int64_t)b * op.n * m;
+    const float* Pb = P + (int64_t)b * op.n * k;
+    float v;
+    if (c < m) {
+      v = op_row<float>(ob, i, px, py, pz, [&](int64_t j) { return Sb[j * m + c]; });
+      ss = (double)Sb[(int64_t)i * m + c] * (double)v;
+    } else {
+      v = op_row<float>(ob, i, px, py, pz, [&](int64_t j) { return Pb[j * k + (c - m)]; });
+    }
+    X[(int64_t)b * op.n * w + g] = v;
+  }
+  ss = block_sum(ss, sh);
+  if (threadIdx.x == 0) spart[(int64_t)b * gridDim.x + blockIdx.x] = ss;
+}
+
+// per sample: T = P^T X from the slab sums, A_c = sym(T[:, m:]), W = T[:, :m],
+// Cholesky, V = R^-T W, Z = R^-1 V, J, and M for a unit upstream gradient.
+// LDS (dynamic): R and R^-1 (QRK x QRK each), V and Z (k x m each).
+__global__ __launch_bounds__(NT) void k_gterm_finish(Dims d, int m, const double* __restrict__ T64,
+                                                     const double* __restrict__ spart, int nspart,
+                                                     float* __restrict__ J, int* __restrict__ bad,
+                                                     float* __restrict__ Msave) {
+  extern __shared__ double glds[];
+  double* G = glds;                 // R (upper), then H = Z Z^T
+  double* Xi = G + QRK * QRK;       // R^-1 (upper)
+  double* V = Xi + QRK * QRK;       // W, then V = R^-T W   (k x m)
+  double* Z = V + d.k * m;          // Z = R^-1 V           (k x m)
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.x, k = d.k, t = threadIdx.x;
+  const double* tb = T64 + (int64_t)b * d.ntiles * 256;
+  auto at = [&](int a, int c) {   // T[a][c], c < m + k
+    const int id = (a >> 4) * d.MT + (c >> 4), r = a & 15;
+    return tb[id * 256 + (r & 3) * 64 + (r >> 2) * 16 + (c & 15)];
+  };
+  for (int e = t; e < k * k; e += NT) {
+    const int i = e / k, j = e % k;
+    G[i * QRK + j] = 0.5 * (at(i, m + j) + at(j, m + i));
+  }
+  for (int e = t; e < k * m; e += NT) Z[e] = at(e / m, e % m);   // W, parked in Z
+  // tr(S^T A S) from the apply kernel's partials, in order
+  double tr = 0.0;
+  if (t == 0)
+    for (int q = 0; q < nspart; ++q) tr += spart[(int64_t)b * nspart + q];
+  __syncthreads();
+  const bool ok = chol_inv(k, G, Xi);
+  if (t == 0) bad[b] = ok ? 0 : 1;
+  // V = R^-T W: V_ic = sum_{p <= i} (R^-1)_pi W_pc
+  for (int e = t; e < k * m; e += NT) {
+    const int i = e / m, c = e % m;
+    double v = 0.0;
+    for (int p = 0; p <= i; ++p) v += Xi[p * QRK + i] * Z[p * m + c];
+    V[e] = v;
+  }
+  __syncthreads();
+  // Z = R^-1 V: Z_ic = sum_{p >= i} (R^-1)_ip V_pc;  ||V||^2
+  double vv = 0.0;
+  for (int e = t; e < k * m; e += NT) {
+    const int i = e / m, c = e % m;
+    double z = 0.0;
+    for (int p = i; p < k; ++p) z += Xi[i * QRK + p] * V[p * m + c];
+    Z[e] = z;
+    vv += V[e] * V[e];
+  }
+  vv = block_sum(vv, sh);
+  if (t == 0) J[b] = (float)(tr - vv);
+  // H = Z Z^T (k x k) into G
+  for (int e = t; e < k * k; e += NT) {
+    const int i = e / k, j = e % k;
+    double h = 0.0;
+    for (int c = 0; c < m; ++c) h += Z[i * m + c] * Z[j * m + c];
+    G[i * QRK + j] = h;
+  }
+  __syncthreads();
+  // M ((cols x kp), rows = columns of X): -2 Z^T over the A S columns, 2 Z Z^T
+  // over the A P columns, zero padding
+  float* Mb = Msave + (int64_t)b * d.cols * d.kp;
+  for (int e = t; e < d.cols * d.kp; e += NT) {
+    const int c = e / d.kp, j = e % d.kp;
+    double v = 0.0;
+    if (j < k) {
+      if (c < m)
+        v = -2.0 * Z[j * m + c];
+      else if (c < m + k)
+        v = 2.0 * G[(c - m) * QRK + j];
+    }
+    Mb[e] = (float)v;
+  }
+}
+
 }  // namespace sub
 }  // namespace nlsp
 
@@ -899,6 +1015,93 @@ int qr_thin_bwd(int batch, int n, int k, const float* Q, const double* R, const 
   hipLaunchKernelGGL(k_qr_bwd_small, dim3(batch), dim3(NT), 0, s, dp, L.prod.T64, R, L.M);
   // dA = [dQ | Q] [R^-T ; C R^-T]
   rc = launch_bwd(dp, batch, Q, gQ, L.M, nullptr, gA, s);
+  if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+// ---------------------------------------------------------------- J(P)
+// forward dims: products P^T X over the tiles of P^T X (X = [A S | A P] is
+// the "B" block, P the "P" block); backward dims: X M, no P block
+inline Dims gterm_fwd_dims(int batch, int n, int k, int m) { return make_dims(batch, n, k, m + k, false, true); }
+inline Dims gterm_bwd_dims(int batch, int n, int k, int m) { return make_dims(batch, n, k, m + k, false, false); }
+inline bool gterm_ok(int batch, int64_t n, int k, int m) {
+  if (batch < 1 || n < 1 || k < 1 || m < 1 || k > QRK || m + k > 256 || k * m > 4096) return false;
+  if (n * (m + k) >= (int64_t(1) << 31)) return false;
+  const Dims d = gterm_fwd_dims(batch, (int)n, k, m);
+  return d.ntiles <= MAX_TILES && fwd_lds(d) <= LDS_MAX && bwd_lds(gterm_bwd_dims(batch, (int)n, k, m)) <= LDS_MAX;
+}
+inline int gterm_apply_blocks(int64_t n, int k, int m) { return (int)ceil_div(n * (m + k), NT); }
+inline size_t gterm_finish_lds(int k, int m) { return (2 * (size_t)QRK * QRK + 2 * (size_t)k * m) * sizeof(double); }
+
+struct GtermSaved {
+  float* X;   // (batch, n, m + k)
+  float* M;   // (batch, cols, kp)
+  size_t bytes;
+};
+inline GtermSaved carve_gterm(void* saved, int batch, int64_t n, int k, int m) {
+  const Dims db = gterm_bwd_dims(batch, (int)n, k, m);
+  Carver c(saved);
+  GtermSaved G;
+  G.X = c.take<float>((size_t)batch * n * (m + k));
+  G.M = c.take<float>((size_t)batch * db.cols * db.kp);
+  G.bytes = c.bytes();
+  return G;
+}
+
+size_t galerkin_term_saved_bytes(int batch, const nlsp_operator* A, int k, int m) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !gterm_ok(batch, n, k, m)) return 0;
+  return carve_gterm(nullptr, batch, n, k, m).bytes;
+}
+
+size_t galerkin_term_workspace_bytes(int batch, const nlsp_operator* A, int k, int m) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !gterm_ok(batch, n, k, m)) return 0;
+  const SubLayout L = carve_sub(nullptr, batch, gterm_fwd_dims(batch, (int)n, k, m));
+  return align_up(L.bytes) + align_up((size_t)batch * gterm_apply_blocks(n, k, m) * sizeof(double));
+}
+
+int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const float* S, int k, int m, float* J,
+                      int* bad, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes, void* stream) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !gterm_ok(batch, n, k, m) || !P || !S || !J || !bad || !saved) return NLSP_E_INVALID;
+  const GtermSaved G = carve_gterm(nullptr, batch, n, k, m);
+  if (saved_nbytes < G.bytes || reinterpret_cast<uintptr_t>(saved) % WS_ALIGN) return NLSP_E_WORKSPACE;
+  const size_t need = galerkin_term_workspace_bytes(batch, A, k, m);
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const GtermSaved Gs = carve_gterm(saved, batch, n, k, m);
+  Dims d = gterm_fwd_dims(batch, (int)n, k, m);
+  if (!aligned16(P)) d.vec = 0;
+  const SubLayout L = carve_sub(ws, batch, d);
+  double* spart = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up(L.bytes));
+  hipStream_t s = as_stream(stream);
+  const OpDev op = make_op(*A);
+  const int nb = gterm_apply_blocks(n, k, m);
+  hipLaunchKernelGGL(k_gterm_apply, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, m,
+                     make_fastdiv((uint32_t)(m + k)), P, S, Gs.X, spart);
+  // T = P^T X: X is the "B" block, P the "P" block
+  int rc = launch_products(d, batch, P, Gs.X, L, s);
+  if (rc != NLSP_OK) return rc;
+  const size_t lds = gterm_finish_lds(k, m);
+  if (allow_lds(k_gterm_finish, lds) != hipSuccess) return NLSP_E_HIP;
+  const Dims db = gterm_bwd_dims(batch, (int)n, k, m);
+  Dims df = d;
+  df.cols = db.cols;   // the finishing kernel writes M with the backward's row count
+  hipLaunchKernelGGL(k_gterm_finish, dim3(batch), dim3(NT), lds, s, df, m, L.T64, spart, nb, J, bad, Gs.M);
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+int galerkin_term_bwd(int batch, const nlsp_operator* A, int k, int m, const void* saved, const float* gJ,
+                      float* gP, void* stream) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !gterm_ok(batch, n, k, m) || !saved || !gJ || !gP) return NLSP_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(saved) % WS_ALIGN) return NLSP_E_WORKSPACE;
+  const GtermSaved Gs = carve_gterm(const_cast<void*>(saved), batch, n, k, m);
+  const Dims d = gterm_bwd_dims(batch, (int)n, k, m);
+  // dJ/dP = g_b X M: X is the "B" block, no P block
+  const int rc = launch_bwd(d, batch, Gs.X, Gs.X, Gs.M, gJ, gP, as_stream(stream));
   if (rc != NLSP_OK) return rc;
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;

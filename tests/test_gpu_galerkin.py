@@ -165,3 +165,91 @@ def test_invalid(nl):
         nl.galerkin_fwd(op, torch.zeros(3, n, 4, device="cuda"))    # only 2 coefficient fields
     with pytest.raises(nl.NlspError):
         nl.galerkin_fwd(op, torch.zeros(2, n, 65, device="cuda"))   # k > 64
+
+
+# ------------------------------------------------- Galerkin-convergence term
+def _gterm_bounds(A, P, S):
+    """First-order worst-case bounds of the GPU's J and dJ/dP (float32 stencil
+    and MFMA products over n/4 + 8 steps, slab sums and the small solves in
+    float64, M rounded to float32 and X M accumulated over (m + k)/4 + 8 steps):
+      |dAS| <= 16 u |A||S|,  |dAP| <= 16 u |A||P|,  g = (n/4 + 8) u
+      |dW| <= g |P|^T|AS| + |P|^T|dAS|,  |dAc| <= g |P|^T|AP| + |P|^T|dAP|
+      |dJ| <= sum |S||dAS| + 2 <|Z|, |dW|> + <|Z||Z|^T, |dAc|> + u |J|
+      |dZ| <= |Ac^-1| (|dW| + |dAc||Z|)
+      |dgrad| <= 2 (|dAP||ZZ^T| + |AP| (|dZ||Z|^T + |Z||dZ|^T) + |dAS||Z|^T
+                 + |AS||dZ|^T) + ((m + k)/4 + 9) u |X||M|,  X = [AS | AP]."""
+    n, k = P.shape
+    m = S.shape[1]
+    aA, aP, aS = abs(A), np.abs(P), np.abs(S)
+    AS, AP = A @ S, A @ P
+    dAS, dAP = 16 * U32 * (aA @ aS), 16 * U32 * (aA @ aP)
+    g = (n / 4 + 8) * U32
+    dW = g * (aP.T @ np.abs(AS)) + aP.T @ dAS
+    dAc = g * (aP.T @ np.abs(AP)) + aP.T @ dAP
+    Ac = P.T @ AP
+    Acinv = np.linalg.inv(0.5 * (Ac + Ac.T))
+    Z = Acinv @ (P.T @ AS)
+    aZ = np.abs(Z)
+    J = float(np.sum(S * AS) - np.sum((P.T @ AS) * Z))
+    dJ = np.sum(aS * dAS) + 2 * np.sum(aZ * dW) + np.sum((aZ @ aZ.T) * dAc) + U32 * abs(J)
+    dZ = np.abs(Acinv) @ (dW + dAc @ aZ)
+    M = np.vstack([-2 * Z.T, 2 * Z @ Z.T])
+    X = np.hstack([AS, AP])
+    dg = 2 * (dAP @ np.abs(Z @ Z.T) + np.abs(AP) @ (dZ @ aZ.T + aZ @ dZ.T) + dAS @ aZ.T + np.abs(AS) @ dZ.T)
+    dg = dg + ((m + k) / 4 + 9) * U32 * (np.abs(X) @ np.abs(M))
+    return dJ, dg
+
+
+@pytest.mark.parametrize("kind", ["fv5", "grf", "fv7", "q1", "poisson"])
+@pytest.mark.parametrize("k,m", [(5, 7), (16, 24), (12, 60)])
+def test_galerkin_term_fwd_bwd(nl, kind, k, m):
+    batch = 3
+    As, op, n = _batch(nl, kind, batch, 21)
+    rng = np.random.default_rng(17)
+    P32 = np.stack([np.linalg.qr(rng.standard_normal((n, k)))[0] for _ in range(batch)]).astype(np.float32)
+    S32 = rng.standard_normal((batch, n, m)).astype(np.float32)
+    gJ = torch.linspace(0.5, 1.5, batch, dtype=torch.float32, device="cuda")
+    J, bad, saved = nl.galerkin_term_fwd(op, torch.tensor(P32, device="cuda"), torch.tensor(S32, device="cuda"))
+    gP = host(nl.galerkin_term_bwd(op, k, m, saved, gJ))
+    J, bad, gJh = host(J), host(bad), host(gJ)
+    assert np.all(bad == 0)
+    for b in range(batch):
+        A, P, S = As[b], P32[b].astype(np.float64), S32[b].astype(np.float64)
+        ref = O.galerkin_term(A, P, S)
+        gref = O.galerkin_term_grad(A, P, S)
+        dJ, dg = _gterm_bounds(A, P, S)
+        assert abs(J[b] - ref) <= 2 * dJ, (b, J[b], ref, dJ)
+        err = np.abs(gP[b] - gJh[b] * gref)
+        assert np.all(err <= 2 * gJh[b] * dg + 1e-30), (b, err.max(), (gJh[b] * dg).max())
+
+
+def test_galerkin_term_autograd_and_optimum(nl):
+    """Autograd through GalerkinTerm equals galerkin_term_bwd; at the top-k
+    left singular subspace of A^{1/2} S the GPU's J is the oracle's minimum,
+    below J at a random basis (the appendix's optimality statement)."""
+    As, op, n = _batch(nl, "grf", 2, 31)
+    k, m = 6, 16
+    rng = np.random.default_rng(3)
+    S32 = rng.standard_normal((2, n, m)).astype(np.float32)
+    P32 = np.stack([np.linalg.qr(rng.standard_normal((n, k)))[0] for _ in range(2)]).astype(np.float32)
+    Pt = torch.tensor(P32, device="cuda", requires_grad=True)
+    St = torch.tensor(S32, device="cuda")
+    J, bad = nl.galerkin_term(Pt, St, op)
+    (J * torch.tensor([1.0, 2.0], device="cuda")).sum().backward()
+    _, _, saved = nl.galerkin_term_fwd(op, Pt.detach(), St)
+    assert torch.equal(Pt.grad, nl.galerkin_term_bwd(op, k, m, saved, torch.tensor([1.0, 2.0], device="cuda")))
+    # the optimum: P* = A^{-1/2} U_k spans the Galerkin-optimal subspace
+    Popt = []
+    for b in range(2):
+        Ad = As[b].toarray()
+        lam, V = np.linalg.eigh(Ad)
+        Ah = (V * np.sqrt(lam)) @ V.T
+        U = np.linalg.svd(Ah @ S32[b].astype(np.float64), full_matrices=False)[0][:, :k]
+        Popt.append(np.linalg.qr(np.linalg.solve(Ah, U))[0])
+    Jo = host(nl.galerkin_term_fwd(op, torch.tensor(np.stack(Popt).astype(np.float32), device="cuda"), St)[0])
+    Jr = host(J.detach())
+    for b in range(2):
+        P = Popt[b].astype(np.float32).astype(np.float64)
+        Jref = O.galerkin_term(As[b], P, S32[b].astype(np.float64))
+        assert abs(Jo[b] - Jref) <= 2 * _gterm_bounds(As[b], P, S32[b].astype(np.float64))[0]
+        assert Jo[b] < Jr[b]

@@ -238,8 +238,9 @@ def spmv_legs(nl, torch, dev):
 
 def training_legs(nl, torch, dev):
     """Differentiable products on the training workload (64 log-normal fields
-    of 128^2 cells, k = 32, m = 64 relaxed vectors per field): subspace loss
-    and Galerkin product, forward and backward (float32 MFMA)."""
+    of 128^2 cells, k = 32, m = 64 relaxed vectors per field): subspace loss,
+    Galerkin product and Galerkin-convergence term, forward and backward
+    (float32 MFMA)."""
     import workloads as W
     c5 = W.Cfg5()
     batch, n, k, m = c5.batch, c5.N * c5.N, c5.k, c5.m
@@ -267,6 +268,17 @@ def training_legs(nl, torch, dev):
     res["galerkin"] = {"fwd_ms": round(f_ms, 4), "bwd_ms": round(b_ms, 4),
                        "fwd_GBs": round(batch * n * (4 * k * 4 + 8) / f_ms / 1e6, 1),
                        "bwd_GBs": round(batch * n * 2 * k * 4 / b_ms / 1e6, 1)}
+    # Galerkin-convergence term J(P) on the relaxed vectors B (forward: read
+    # B, P, a, write [AB | AP], then read it and P again for P^T [AB | AP];
+    # backward: read [AB | AP], write dJ/dP)
+    J, bad, gsaved = nl.galerkin_term_fwd(op, P, B)
+    f_ms = _time_ms(torch, lambda: nl.galerkin_term_fwd(op, P, B))
+    b_ms = _time_ms(torch, lambda: nl.galerkin_term_bwd(op, k, m, gsaved, ones))
+    fwd_bytes = batch * n * (4 * m + 2 * 4 * k + 8 + 2 * 4 * (m + k))
+    bwd_bytes = batch * n * (4 * (m + k) + 4 * k)
+    res["galerkin_term"] = {"fwd_ms": round(f_ms, 4), "bwd_ms": round(b_ms, 4),
+                            "fwd_GBs": round(fwd_bytes / f_ms / 1e6, 1), "bwd_GBs": round(bwd_bytes / b_ms / 1e6, 1),
+                            "bad": int(bad.sum().item())}
     return res
 
 

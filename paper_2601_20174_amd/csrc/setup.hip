@@ -201,13 +201,33 @@ NLSP_DEV void wg_sync() {
 
 // Cyclic Jacobi eigensolver for a symmetric m x m matrix (Golub & Van Loan,
 // Sec. 8.5), parallel ("round-robin") ordering: m/2 disjoint rotations per
-// round, m-1 rounds per sweep.  The working copy of G lives in LDS when
-// LDS = true (m <= 128), else in Gg itself.  On exit Gg holds the rotated
-// matrix (its diagonal converges to the eigenvalues) and V the rotations.
-// m even.
+// round, m-1 rounds per sweep.  A round forms its rotations from the current
+// 2 x 2 diagonal blocks and applies G <- J^T G J as one pass over the 2 x 2
+// blocks (rows of pair a, columns of pair b: J_b on the columns, then J_a on
+// the rows), so each element is read and written once per round.  The
+// rotations (c, s per pair, pairs in the order of the round-robin formula)
+// are recorded in `rot` for k_jacobi_vecs; nsweeps[0] receives the number of
+// sweeps recorded.  The working copy of G lives in LDS when LDS = true
+// (m <= 128), else in Gg itself.  On exit Gg holds the rotated matrix (its
+// diagonal converges to the eigenvalues).  m even.
+NLSP_DEV void rr_pair(int rnd, int t, int m, int& p, int& q) {
+  if (t == 0) {
+    p = rnd;
+    q = m - 1;
+  } else {
+    p = (rnd + t) % (m - 1);
+    q = (rnd - t + (m - 1)) % (m - 1);
+  }
+  if (p > q) {
+    const int tmp = p;
+    p = q;
+    q = tmp;
+  }
+}
+
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, double* __restrict__ V,
-                                                     int m, int max_sweeps,
+__global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, int m, int max_sweeps,
+                                                     double* __restrict__ rot, int* __restrict__ nsweeps,
                                                      double* __restrict__ offnorm) {
   extern __shared__ double dyn[];
   __shared__ double cs[128], sn[128];
@@ -217,10 +237,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, do
   double* G = LDS ? dyn : Gg;
   if (LDS)
     for (int idx = t; idx < m * m; idx += nt) G[idx] = Gg[idx];
-  for (int idx = t; idx < m * m; idx += nt) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
   wg_sync<LDS>();
   const int half = m / 2;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int idx = t; idx < m * m; idx += nt) {
       const double g = G[idx];
@@ -232,17 +252,11 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, do
     tot = block_sum(tot, red);
     if (t == 0) offnorm[0] = sqrt(off / (tot > 0 ? tot : 1.0));
     if (off <= 1e-30 * tot) break;
+    double* rs = rot + (int64_t)sweep * (m - 1) * half * 2;
     for (int rnd = 0; rnd < m - 1; ++rnd) {
       if (t < half) {
         int p, q;
-        if (t == 0) {
-          p = rnd;
-          q = m - 1;
-        } else {
-          p = (rnd + t) % (m - 1);
-          q = (rnd - t + (m - 1)) % (m - 1);
-        }
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        rr_pair(rnd, t, m, p, q);
         const double apq = G[p * m + q], app = G[p * m + p], aqq = G[q * m + q];
         double c = 1.0, s = 0.0;
         if (apq != 0.0 && fabs(apq) > 1e-300) {
@@ -255,35 +269,59 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, do
         sn[t] = s;
         pp[t] = p;
         qq[t] = q;
+        rs[((int64_t)rnd * half + t) * 2] = c;
+        rs[((int64_t)rnd * half + t) * 2 + 1] = s;
       }
       __syncthreads();
-      // columns: G <- G J, V <- V J
-      for (int idx = t; idx < m * half; idx += nt) {
-        const int i = idx / half, k = idx % half;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double gp = G[i * m + p], gq = G[i * m + q];
-        G[i * m + p] = c * gp - s * gq;
-        G[i * m + q] = s * gp + c * gq;
-        const double vp = V[i * m + p], vq = V[i * m + q];
-        V[i * m + p] = c * vp - s * vq;
-        V[i * m + q] = s * vp + c * vq;
-      }
-      wg_sync<LDS>();
-      // rows: G <- J^T G
-      for (int idx = t; idx < m * half; idx += nt) {
-        const int j = idx / half, k = idx % half;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double gp = G[p * m + j], gq = G[q * m + j];
-        G[p * m + j] = c * gp - s * gq;
-        G[q * m + j] = s * gp + c * gq;
+      for (int idx = t; idx < half * half; idx += nt) {
+        const int a = idx / half, b = idx % half;
+        const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+        const double ca = cs[a], sa = sn[a], cb = cs[b], sb = sn[b];
+        const double g11 = G[pa * m + pb], g12 = G[pa * m + qb], g21 = G[qa * m + pb], g22 = G[qa * m + qb];
+        const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;   // columns: J_b
+        const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
+        G[pa * m + pb] = ca * h11 - sa * h21;                                  // rows: J_a
+        G[qa * m + pb] = sa * h11 + ca * h21;
+        G[pa * m + qb] = ca * h12 - sa * h22;
+        G[qa * m + qb] = sa * h12 + ca * h22;
       }
       wg_sync<LDS>();
     }
   }
+  if (t == 0) nsweeps[0] = sweep;
   if (LDS)
     for (int idx = t; idx < m * m; idx += nt) Gg[idx] = G[idx];
+}
+
+// V = J_1 J_2 ... from the recorded rotations.  Each row of V evolves on its
+// own (row_i <- row_i J), so one wave keeps one row in LDS and applies every
+// round's disjoint rotations, one pair per lane, in the recorded order.
+__global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ rot,
+                                                     const int* __restrict__ nsweeps, int m,
+                                                     double* __restrict__ V) {
+  extern __shared__ double vrows[];   // 4 rows of m
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = blockIdx.x * 4 + w;   // m is a multiple of 4
+  double* row = vrows + w * m;
+  const int half = m / 2;
+  for (int j = lane; j < m; j += 64) row[j] = (j == i) ? 1.0 : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  const int ns = nsweeps[0];
+  for (int sw = 0; sw < ns; ++sw) {
+    const double* rs = rot + (int64_t)sw * (m - 1) * half * 2;
+    for (int rnd = 0; rnd < m - 1; ++rnd) {
+      for (int k = lane; k < half; k += 64) {
+        int p, q;
+        rr_pair(rnd, k, m, p, q);
+        const double c = rs[((int64_t)rnd * half + k) * 2], s = rs[((int64_t)rnd * half + k) * 2 + 1];
+        const double vp = row[p], vq = row[q];
+        row[p] = c * vp - s * vq;
+        row[q] = s * vp + c * vq;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  for (int j = lane; j < m; j += 64) V[(int64_t)i * m + j] = row[j];
 }
 
 // Sort eigenpairs descending; sigma = sqrt(max(lambda, 0)); T = V_k diag(lambda_k^-1/2)
@@ -498,15 +536,22 @@ __global__ void k_to_f32(const double* __restrict__ A, float* __restrict__ B, in
 // ------------------------------------------------------------ host helpers
 constexpr int LDS_DENSE_MAX = 128;   // m or k up to which the dense kernels work in LDS
 
-static int launch_eig(double* G, double* V, int m, double* off, hipStream_t s) {
+constexpr int JACOBI_MAX_SWEEPS = 40;
+
+inline size_t rot_doubles(int m) { return (size_t)JACOBI_MAX_SWEEPS * (m - 1) * (m / 2) * 2; }
+
+static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, double* off, hipStream_t s) {
   if (m <= LDS_DENSE_MAX) {
     const size_t sh = sizeof(double) * m * m;
     NLSP_HIP(hipFuncSetAttribute((const void*)k_jacobi_eig<true>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-    hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(1024), sh, s, G, V, m, 40, off);
+    hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(1024), sh, s, G, m, JACOBI_MAX_SWEEPS, rot, nsweeps,
+                       off);
   } else {
-    hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(1024), 0, s, G, V, m, 40, off);
+    hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(1024), 0, s, G, m, JACOBI_MAX_SWEEPS, rot, nsweeps,
+                       off);
   }
+  hipLaunchKernelGGL(k_jacobi_vecs, dim3(m / 4), dim3(256), sizeof(double) * 4 * m, s, rot, nsweeps, m, V);
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;
 }
@@ -579,6 +624,8 @@ struct SetupLayout {
   double* Lk;       // (kp16, kp16)
   double* off;      // 4
   int* info;        // 4
+  double* rot;      // Jacobi rotations, rot_doubles(mp)
+  int* nsweeps;     // 1
   size_t bytes;
 };
 
@@ -600,6 +647,8 @@ inline SetupLayout carve_setup(void* ws, int64_t n, int m, int k, int prec) {
   L.Lk = cv.take<double>((size_t)kq * kq);
   L.off = cv.take<double>(4);
   L.info = cv.take<int>(4);
+  L.rot = cv.take<double>(rot_doubles(mp));
+  L.nsweeps = cv.take<int>(4);
   L.bytes = cv.bytes();
   return L;
 }
@@ -630,7 +679,7 @@ static int setup_impl(const OpDev& op, const double* S0, int m, int k, double om
   // Gram and eigenpairs
   int rc = gram<T>(Sa, Sa, n, mp, mp, 1, L.part, L.G, mp, s);
   if (rc) return rc;
-  rc = launch_eig(L.G, L.V, mp, L.off, s);
+  rc = launch_eig(L.G, L.V, mp, L.rot, L.nsweeps, L.off, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_eig_finish, dim3(1), dim3(256), 0, s, L.G, L.V, mp, m, k, kq, sigma, L.T,
                      L.info);

@@ -470,34 +470,81 @@ __global__ void k_transpose_pad(const double* __restrict__ A, int kp, double* __
   B[j * kp + i] = A[idx];
 }
 
-// Largest-magnitude entry of each column (lowest row on ties), then flip the
-// column so that entry is positive.  One workgroup per column.
-__global__ __launch_bounds__(256) void k_colsign(double* __restrict__ P, int64_t n, int ld, int k) {
+// Largest-magnitude entry of each column (lowest row on ties), in two
+// passes: every workgroup scans a row range of the whole (n, ld) block with
+// coalesced loads (lane t takes column t % ld) and keeps, per column, the
+// first maximum of |P|; k_colsign_finish combines the workgroups in order and
+// stores the column signs, which k_copy_cols_signed applies.
+constexpr int CS_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_colmax_partial(const double* __restrict__ P, int64_t n, int ld,
+                                                        int64_t rows_per, double* __restrict__ pv,
+                                                        int64_t* __restrict__ pi) {
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
-  const int j = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
+  const int per = 256 / ld;                // rows per pass (ld <= 256, a power of two)
+  const int c = t % ld, r = t / ld;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = min(n, r0 + rows_per);
   double best = -1.0;
-  int64_t bidx = 0;
-  for (int64_t i = t; i < n; i += blockDim.x) {
-    const double v = fabs(P[i * ld + j]);
-    if (v > best) { best = v; bidx = i; }
-  }
+  int64_t bidx = r0;
+  if (r < per)
+    for (int64_t i = r0 + r; i < r1; i += per) {
+      const double v = fabs(P[i * ld + c]);
+      if (v > best) {
+        best = v;
+        bidx = i;
+      }
+    }
   bv[t] = best;
   bi[t] = bidx;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      if (bv[t + s] > bv[t] || (bv[t + s] == bv[t] && bi[t + s] < bi[t])) {
-        bv[t] = bv[t + s];
-        bi[t] = bi[t + s];
+  // combine the `per` threads of each column (rows r, r + per, ... interleave,
+  // so ties go to the lower row index)
+  if (t < ld) {
+    double b = bv[t];
+    int64_t bx = bi[t];
+    for (int q = 1; q < per; ++q) {
+      const double v = bv[q * ld + t];
+      const int64_t x = bi[q * ld + t];
+      if (v > b || (v == b && x < bx)) {
+        b = v;
+        bx = x;
       }
     }
-    __syncthreads();
+    pv[(int64_t)blockIdx.x * ld + t] = b;
+    pi[(int64_t)blockIdx.x * ld + t] = bx;
   }
-  const bool flip = P[bi[0] * ld + j] < 0.0;
-  __syncthreads();
-  if (flip)
-    for (int64_t i = t; i < n; i += blockDim.x) P[i * ld + j] = -P[i * ld + j];
+}
+
+__global__ __launch_bounds__(256) void k_colsign_finish(const double* __restrict__ P, int ld, int k, int nblk,
+                                                        const double* __restrict__ pv,
+                                                        const int64_t* __restrict__ pi,
+                                                        double* __restrict__ sign) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  double b = -1.0;
+  int64_t bx = 0;
+  for (int w = 0; w < nblk; ++w) {
+    const double v = pv[(int64_t)w * ld + c];
+    const int64_t x = pi[(int64_t)w * ld + c];
+    if (v > b || (v == b && x < bx)) {
+      b = v;
+      bx = x;
+    }
+  }
+  sign[c] = (P[bx * ld + c] < 0.0) ? -1.0 : 1.0;
+}
+
+// Copy (n, k) with leading dimension lda into (n, kout) row-major, column j
+// multiplied by sign[j].
+__global__ void k_copy_cols_signed(const double* __restrict__ A, int lda, int64_t n, int k,
+                                   const double* __restrict__ sign, double* __restrict__ B, int ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k;
+  const int j = (int)(idx % k);
+  B[i * ldb + j] = sign[j] * A[i * lda + j];
 }
 
 // Copy (n, k) with leading dimension lda into (n, kout) row-major.
@@ -626,6 +673,9 @@ struct SetupLayout {
   int* info;        // 4
   double* rot;      // Jacobi rotations, rot_doubles(mp)
   int* nsweeps;     // 1
+  double* cmax;     // column maxima per workgroup (CS_BLOCKS, kq)
+  int64_t* cidx;    // their rows
+  double* csign;    // (kq)
   size_t bytes;
 };
 
@@ -649,6 +699,9 @@ inline SetupLayout carve_setup(void* ws, int64_t n, int m, int k, int prec) {
   L.info = cv.take<int>(4);
   L.rot = cv.take<double>(rot_doubles(mp));
   L.nsweeps = cv.take<int>(4);
+  L.cmax = cv.take<double>((size_t)CS_BLOCKS * kq);
+  L.cidx = cv.take<int64_t>((size_t)CS_BLOCKS * kq);
+  L.csign = cv.take<double>(kq);
   L.bytes = cv.bytes();
   return L;
 }
@@ -699,8 +752,14 @@ static int setup_impl(const OpDev& op, const double* S0, int m, int k, double om
     tsgemm<double>(Pa, n, kq, L.Rinv, kq, Pb, kq, kq, s);
     std::swap(Pa, Pb);
   }
-  hipLaunchKernelGGL(k_colsign, dim3(k), dim3(256), 0, s, Pa, n, kq, k);
-  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(n * k, 256)), dim3(256), 0, s, Pa, kq, n, k, Pout, k);
+  {
+    const int64_t rows_per = (n + CS_BLOCKS - 1) / CS_BLOCKS;
+    const int nblk = (int)((n + rows_per - 1) / rows_per);
+    hipLaunchKernelGGL(k_colmax_partial, dim3(nblk), dim3(256), 0, s, Pa, n, kq, rows_per, L.cmax, L.cidx);
+    hipLaunchKernelGGL(k_colsign_finish, dim3(1), dim3(256), 0, s, Pa, kq, k, nblk, L.cmax, L.cidx, L.csign);
+    hipLaunchKernelGGL(k_copy_cols_signed, dim3(ceil_div(n * k, 256)), dim3(256), 0, s, Pa, kq, n, k, L.csign,
+                       Pout, k);
+  }
   NLSP_HIP(hipGetLastError());
   int hinfo[4] = {0, 0, 0, 0};
   NLSP_HIP(hipMemcpyAsync(hinfo, L.info, sizeof(hinfo), hipMemcpyDeviceToHost, s));

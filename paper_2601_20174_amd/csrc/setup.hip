@@ -24,6 +24,8 @@ struct Row9 {
 };
 
 NLSP_DEV void row_coeffs(const OpDev& op, int64_t i, Row9& rw) {
+  // branch-free: absent neighbours get weight 0 and column i, and their
+  // coefficient loads read row i, so all loads of the row issue together
   int x, y, z;
   decompose(op, i, x, y, z);
   const int nx = op.nx, ny = op.ny;
@@ -33,16 +35,15 @@ NLSP_DEV void row_coeffs(const OpDev& op, int64_t i, Row9& rw) {
     rw.j[t] = i;
   }
   if (op.kind == NLSP_OP_STENCIL9) {
-    const double* c = op.coef;
+    const auto c = op.coef;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int t = (dy + 1) * 3 + (dx + 1);
-        if (y + dy >= 0 && y + dy < ny && x + dx >= 0 && x + dx < nx) {
-          rw.c[t] = c[t];
-          rw.j[t] = i + dx + (int64_t)dy * nx;
-        }
+        const bool ok = y + dy >= 0 && y + dy < ny && x + dx >= 0 && x + dx < nx;
+        rw.c[t] = ok ? c[t] : 0.0;
+        rw.j[t] = ok ? i + dx + (int64_t)dy * nx : i;
       }
     return;
   }
@@ -53,35 +54,30 @@ NLSP_DEV void row_coeffs(const OpDev& op, int64_t i, Row9& rw) {
   if (op.kind == NLSP_OP_POISSON5) {
     rw.c[0] = 4.0;
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-      if (in[f]) {
-        rw.c[1 + f] = -1.0;
-        rw.j[1 + f] = nb[f];
-      }
+    for (int f = 0; f < 4; ++f) {
+      rw.c[1 + f] = in[f] ? -1.0 : 0.0;
+      rw.j[1 + f] = in[f] ? nb[f] : i;
+    }
     return;
   }
-  const double* a = op.coef;
+  const auto a = op.coef;
   const double aP = a[i];
   double d = 0.0;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (f >= nf) break;
-    if (in[f]) {
-      const double t = harmonic<double>(aP, a[nb[f]]);
-      d += t;
-      rw.c[1 + f] = -t;
-      rw.j[1 + f] = nb[f];
-    } else {
-      d += 2.0 * aP;
-    }
+    const int64_t j = in[f] ? nb[f] : i;
+    const double t = harmonic<double>(aP, a[j]);
+    d += in[f] ? t : 2.0 * aP;
+    rw.c[1 + f] = in[f] ? -t : 0.0;
+    rw.j[1 + f] = j;
   }
   rw.c[0] = d;
 }
 
-NLSP_DEV double row_diag(const OpDev& op, int64_t i) {
-  int x, y, z;
-  decompose(op, i, x, y, z);
-  return op_diag<double>(op, i, x, y, z);
+// the diagonal entry of a row from its coefficients (the centre slot)
+NLSP_DEV double row_center(const OpDev& op, const Row9& rw) {
+  return (op.kind == NLSP_OP_STENCIL9) ? rw.c[4] : rw.c[0];
 }
 
 // Multi-column stencil pass over (n, m) row-major blocks.  One wave per
@@ -98,7 +94,7 @@ __global__ __launch_bounds__(256) void k_stencil_cols(OpDev op, int m, double om
   if (i >= op.n) return;
   Row9 rw;
   row_coeffs(op, i, rw);
-  const double scale = (mode == 0) ? omega / row_diag(op, i) : 0.0;
+  const double scale = (mode == 0) ? omega / row_center(op, rw) : 0.0;
   for (int col = lane; col < m; col += 64) {
     double s = 0.0;
 #pragma unroll

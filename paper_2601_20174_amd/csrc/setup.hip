@@ -303,19 +303,36 @@ __global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ 
   for (int j = lane; j < m; j += 64) row[j] = (j == i) ? 1.0 : 0.0;
   __builtin_amdgcn_wave_barrier();
   const int ns = nsweeps[0];
-  for (int sw = 0; sw < ns; ++sw) {
-    const double* rs = rot + (int64_t)sw * (m - 1) * half * 2;
-    for (int rnd = 0; rnd < m - 1; ++rnd) {
-      for (int k = lane; k < half; k += 64) {
+  const int64_t nr = (int64_t)ns * (m - 1);   // rounds recorded, in order
+  // rotations of round g for this lane's pairs k = lane and lane + 64
+  // (half <= 128), loaded one round ahead of their use
+  auto fetch = [&](int64_t g, double (&c)[2], double (&s)[2]) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int kk = min(lane + 64 * u, half - 1);
+      const int64_t gg = min(g, nr - 1);
+      c[u] = rot[(gg * half + kk) * 2];
+      s[u] = rot[(gg * half + kk) * 2 + 1];
+    }
+  };
+  double cn[2], sn_[2];
+  if (nr > 0) fetch(0, cn, sn_);
+  for (int64_t g = 0; g < nr; ++g) {
+    double c[2] = {cn[0], cn[1]}, s[2] = {sn_[0], sn_[1]};
+    fetch(g + 1, cn, sn_);
+    const int rnd = (int)(g % (m - 1));
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = lane + 64 * u;
+      if (k < half) {
         int p, q;
         rr_pair(rnd, k, m, p, q);
-        const double c = rs[((int64_t)rnd * half + k) * 2], s = rs[((int64_t)rnd * half + k) * 2 + 1];
         const double vp = row[p], vq = row[q];
-        row[p] = c * vp - s * vq;
-        row[q] = s * vp + c * vq;
+        row[p] = c[u] * vp - s[u] * vq;
+        row[q] = s[u] * vp + c[u] * vq;
       }
-      __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_wave_barrier();
   }
   for (int j = lane; j < m; j += 64) V[(int64_t)i * m + j] = row[j];
 }
@@ -331,22 +348,23 @@ __global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G
   const int t = threadIdx.x;
   for (int i = t; i < m; i += blockDim.x) lam[i] = G[i * m + i];
   __syncthreads();
-  if (t == 0) {
-    // selection of the mreal largest, descending (stable: lower index first)
-    for (int i = 0; i < m; ++i) order[i] = i;
-    for (int i = 0; i < m; ++i) {
-      int best = i;
-      for (int j = i + 1; j < m; ++j)
-        if (lam[order[j]] > lam[order[best]]) best = j;
-      const int tmp = order[i];
-      order[i] = order[best];
-      order[best] = tmp;
+  // descending order, ties by lower index: the rank of i counts the entries
+  // that precede it
+  for (int i = t; i < m; i += blockDim.x) {
+    const double li = lam[i];
+    int r = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = lam[j];
+      r += (lj > li || (lj == li && j < i)) ? 1 : 0;
     }
+    order[r] = i;
+  }
+  __syncthreads();
+  if (t == 0) {
     const double l1 = lam[order[0]] > 0 ? lam[order[0]] : 0.0;
     const double lk = lam[order[k - 1]];
     info[0] = (lk <= 1e-26 * l1 || !(lk > 0)) ? 1 : 0;
   }
-  __syncthreads();
   for (int i = t; i < mreal; i += blockDim.x) {
     const double l = lam[order[i]];
     sigma[i] = sqrt(l > 0 ? l : 0.0);
@@ -406,7 +424,32 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ G,
 // (kp, kp): column j of L^-1 solves L x = e_j by forward substitution.
 __global__ __launch_bounds__(256) void k_tri_inv_lower(const double* __restrict__ L, int ldl, int k,
                                                        double* __restrict__ Li, int kp) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  // thread j forms column j of L^-1 by forward substitution; for kp <= 64 the
+  // columns and L itself sit in LDS (no round trip through memory per row)
+  __shared__ double Ls[64 * 65];
+  __shared__ double X[64 * 65];
+  const int t = threadIdx.x;
+  if (kp <= 64) {
+    for (int e = t; e < kp * kp; e += blockDim.x) {
+      const int i = e / kp, c = e % kp;
+      Ls[i * 65 + c] = (i < k && c < k) ? L[i * ldl + c] : 0.0;
+    }
+    __syncthreads();
+    const int j = t;
+    if (j < kp) {
+      for (int i = 0; i < kp; ++i) X[i * 65 + j] = 0.0;
+      if (j < k)
+        for (int i = j; i < k; ++i) {
+          double s = (i == j) ? 1.0 : 0.0;
+          for (int c = j; c < i; ++c) s -= Ls[i * 65 + c] * X[c * 65 + j];
+          X[i * 65 + j] = s / Ls[i * 65 + i];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < kp * kp; e += blockDim.x) Li[e] = X[(e / kp) * 65 + e % kp];
+    return;
+  }
+  const int j = blockIdx.x * blockDim.x + t;
   if (j >= kp) return;
   for (int i = 0; i < kp; ++i) Li[i * kp + j] = 0.0;
   if (j >= k) return;

@@ -1584,7 +1584,10 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
               void* stream_) {
   const int64_t n = op_size(A);
   if (!info || !opts_ok(opts) || !system_ok(A, M, f, u, R, n)) return NLSP_E_INVALID;
-  return solve_batch(1, &A, &M, &f, &u, R, 0, opts, info, ws, ws_bytes, false, as_stream(stream_));
+  // iterations are replayed from a hipGraph unless per-kernel event timing is
+  // asked for (events attach to single dispatches)
+  const bool graph = opts->timing == nullptr;
+  return solve_batch(1, &A, &M, &f, &u, R, 0, opts, info, ws, ws_bytes, graph, as_stream(stream_));
 }
 
 size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R, int rows_per_block) {

@@ -663,7 +663,10 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
   __shared__ double red[4 * NT + 128];
   __shared__ double buf[2 * MAXR];
   const SysDev& S = my_sys(sys, blk2sys, nsys);
-  if (nsys > 1 && S.nact[(it + 1) & 1] == 0) return;
+  // a system whose right-hand sides have all stopped skips the pass; the
+  // count is loaded first and tested after the row loads are issued, so the
+  // test costs no extra round trip
+  const int na = S.nact[(it + 1) & 1];
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
   const QT* Qt = static_cast<const QT*>(S.Qt);
@@ -688,6 +691,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
       decompose(S.op, i, px, py, pz);
       const double zi = Z[g], qi = Qv[g], pi = Pv[g];
       wval = op_row<double>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
+      if (na == 0) return;   // uniform over the workgroup (one system)
       S.w[g] = wval;
       zw += zi * wval;
       e1 += zi * qi + pi * wval;

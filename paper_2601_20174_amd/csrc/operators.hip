@@ -228,6 +228,266 @@ __global__ __launch_bounds__(RNT) void k_rows(OpDev op, BlockMap bm, int R, int 
   }
 }
 
+// ------------------------------------------------------------ 3-D z-march
+// For 3-D FV7 operators with R = LPR * VW right-hand sides (LPR = 2, 4 or 8
+// lanes per row, VW values per lane).  A block owns a TX x TY tile of the x-y
+// plane and marches over a range of planes z.  Every row is read from HBM once:
+// planes z-1, z, z+1 sit in registers (plane z+2 is already in flight), the x
+// and y neighbours come from an LDS copy of plane z with a one-cell halo, and
+// the halo cells, neighbours' coefficients and (Jacobi) right-hand sides of
+// plane z+1 are loaded one step ahead.  The row kernel instead reads each
+// neighbour row through the cache hierarchy; here only the halo is re-read.
+//
+// Each step issues its loads for later steps before it consumes anything, and
+// consumes only data loaded in earlier steps (the vector memory counter
+// retires in issue order, so a wait for a fresh load would drain the
+// prefetches too).  The register rings are indexed by constants (the z loop is
+// unrolled by the ring length, 4), so no register that is still being loaded
+// is ever copied.  The LDS plane is double-buffered: one barrier per step, and
+// the barrier orders LDS only, leaving global loads in flight.
+//
+// Face weights as in row_weights: lane j of a row forms the harmonic means of
+// faces j, j + LPR, ... (ceil(6 / LPR) of them) and the row's lanes exchange
+// them with wave shuffles, so the coefficient divisions are not repeated per
+// lane.  Arithmetic and summation order per output equal the row kernel's up
+// to the compiler's choice of fused multiply-adds.
+template <int LPR, int TX, int TY>
+struct ZTile {
+  static constexpr int NT = 64 * LPR;                    // threads
+  static constexpr int CPP = NT / LPR, TYS = CPP / TX;   // cells per pass, y rows per pass
+  static constexpr int IPT = TY / TYS;                   // cells per thread
+  static constexpr int HC = 2 * TX + 2 * TY;             // halo cells of a plane
+  static constexpr int HI = (HC * LPR + NT - 1) / NT;    // halo items per thread
+  static constexpr int FF = (6 + LPR - 1) / LPR;         // faces per lane
+  static_assert(CPP % TX == 0 && TY % TYS == 0 && IPT >= 1, "tile shape");
+};
+
+// workgroup barrier that orders LDS accesses only
+NLSP_DEV void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// base + a byte offset (a scalar base and a 32-bit lane offset map onto the
+// scalar-base form of the global load)
+template <typename P>
+NLSP_DEV P* at_b(P* base, uint32_t off) {
+  using C = std::conditional_t<std::is_const<P>::value, const char, char>;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
+}
+
+//   MODE 0: y = A x;  MODE 1: y = x + omega D^-1 (b - A x)  (as k_rows)
+template <typename T, int MODE, int VW, int LPR, int TX, int TY>
+__global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty, int zc, T omega,
+                                                                   const T* __restrict__ b,
+                                                                   const T* __restrict__ x, T* __restrict__ y) {
+  using Z = ZTile<LPR, TX, TY>;
+  static_assert(Z::NT == 64 * LPR, "launch bound");
+  constexpr int NT = Z::NT, R = LPR * VW, IPT = Z::IPT, TYS = Z::TYS, HI = Z::HI, FF = Z::FF;
+  constexpr int LW = TX + 2, LSZ = (TY + 2) * LW * R;
+  __shared__ T lds[2 * LSZ];
+  const int nx = op.nx, ny = op.ny, nz = op.nz;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);   // z-chunk major: an XCD sweeps whole planes
+  const int tiles = ntx * nty;
+  const int zb0 = lb / tiles, tt = lb - zb0 * tiles, ty = tt / ntx, tx = tt - ty * ntx;
+  const int x0 = tx * TX, y0 = ty * TY, z0 = zb0 * zc, z1 = min(nz, z0 + zc);
+  const int t = threadIdx.x, j = t % LPR, cl = t / LPR, cx = cl % TX, cy0 = cl / TX;
+  const int gbase = (t & (WAVE - 1)) - j;
+  const uint32_t sxy = (uint32_t)nx * ny;
+  const int gx = min(x0 + cx, nx - 1);   // cells outside the grid compute on a clamped copy, store nothing
+  uint32_t vo[IPT], co[IPT];             // byte offsets within a plane: values (lane's RHS), coefficient
+  bool ok[IPT], inxy[IPT][4];
+  int gyv[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int yy = y0 + cy0 + u * TYS;
+    ok[u] = x0 + cx < nx && yy < ny;
+    const int gy = min(yy, ny - 1);
+    gyv[u] = gy;
+    const uint32_t ci = (uint32_t)gy * nx + gx;
+    vo[u] = (ci * R + j * VW) * (uint32_t)sizeof(T);
+    co[u] = ci * 8u;
+    inxy[u][0] = gx > 0;
+    inxy[u][1] = gx < nx - 1;
+    inxy[u][2] = gy > 0;
+    inxy[u][3] = gy < ny - 1;
+  }
+  // halo items: cells (lx, -1), (lx, TY), (-1, ly), (TX, ly) of the tile
+  uint32_t ho[HI];   // byte offset within a plane
+  int hl[HI];        // LDS element offset, -1: outside the grid (never read)
+#pragma unroll
+  for (int q = 0; q < HI; ++q) {
+    const int h = t + q * NT, hc = h / LPR, hj = h % LPR;
+    int lx, ly;
+    if (hc < TX) { lx = hc; ly = -1; }
+    else if (hc < 2 * TX) { lx = hc - TX; ly = TY; }
+    else if (hc < 2 * TX + TY) { lx = -1; ly = hc - 2 * TX; }
+    else { lx = TX; ly = hc - 2 * TX - TY; }
+    const int hx = x0 + lx, hy = y0 + ly;
+    const bool in = h < Z::HC * LPR && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+    ho[q] = in ? (((uint32_t)hy * nx + hx) * R + hj * VW) * (uint32_t)sizeof(T) : 0u;
+    hl[q] = in ? ((ly + 1) * LW + lx + 1) * R + hj * VW : -1;
+  }
+  // this lane's faces: z step and the in-plane byte offset of the neighbour's
+  // coefficient (clamped into the grid: a missing face reads the cell itself)
+  int fdz[FF];
+  uint32_t fco[IPT][FF];
+#pragma unroll
+  for (int f = 0; f < FF; ++f) {
+    const int s = min(j + f * LPR, 5);
+    const int dx = s == 0 ? -1 : (s == 1 ? 1 : 0), dy = s == 2 ? -1 : (s == 3 ? 1 : 0);
+    fdz[f] = s == 4 ? -1 : (s == 5 ? 1 : 0);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u)
+      fco[u][f] = ((uint32_t)min(max(gyv[u] + dy, 0), ny - 1) * nx + min(max(gx + dx, 0), nx - 1)) * 8u;
+  }
+  const double* a = op.coef;   // generic pointer of a global buffer: the loads stay global
+  T pl[4][IPT][VW], hb[2][HI][VW], ac[2][IPT], af[2][IPT][FF], bq[2][IPT][VW];
+  const int64_t pstride = (int64_t)sxy * R;
+  auto plane = [&](const T* base, int z) { return base + (int64_t)min(max(z, 0), nz - 1) * pstride; };
+  auto ld_plane = [&](T (&v)[IPT][VW], const T* base, int z) {
+    const T* p = plane(base, z);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) vload<T, VW>(at_b(p, vo[u]), v[u]);
+  };
+  auto ld_halo = [&](T (&v)[HI][VW], int z) {
+    const T* p = plane(x, z);
+#pragma unroll
+    for (int q = 0; q < HI; ++q) vload<T, VW>(at_b(p, ho[q]), v[q]);
+  };
+  auto ld_coef = [&](T (&ap)[IPT], T (&fp)[IPT][FF], int z) {
+    const int zz = min(z, nz - 1), zlo = max(zz - 1, 0);
+    const double* pa = a + (int64_t)zz * sxy;
+    const double* pb = a + (int64_t)zlo * sxy;
+#pragma unroll
+    for (int f = 0; f < FF; ++f) {
+      const uint32_t zo = (uint32_t)(min(max(zz + fdz[f], 0), nz - 1) - zlo) * sxy * 8u;
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) fp[u][f] = T(*at_b(pb, zo + fco[u][f]));
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) ap[u] = T(*at_b(pa, co[u]));
+  };
+  auto step = [&](auto ph, int z) {
+    constexpr int PH = decltype(ph)::value;
+    // plane ring: z-1, z, z+1, and the slot that receives z+2; two-slot rings
+    // for the halo, coefficients and right-hand sides of planes z and z+1
+    constexpr int IP = (PH + 3) & 3, IC = PH, IN = (PH + 1) & 3, IF = (PH + 2) & 3;
+    constexpr int H0 = PH & 1, H1 = (PH + 1) & 1;
+    T* const buf = lds + H0 * LSZ;
+    ld_coef(ac[H1], af[H1], z + 1);
+    ld_plane(pl[IF], x, z + 2);
+    ld_halo(hb[H1], z + 1);
+    if (MODE == 1) ld_plane(bq[H1], b, z + 1);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      T* d = buf + ((cy0 + u * TYS + 1) * LW + cx + 1) * R + j * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) d[e] = pl[IC][u][e];
+    }
+#pragma unroll
+    for (int q = 0; q < HI; ++q)
+      if (hl[q] >= 0) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) buf[hl[q] + e] = hb[H0][q][e];
+      }
+    lds_barrier();
+    T* const yp = y + (int64_t)z * pstride;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const bool in[6] = {inxy[u][0], inxy[u][1], inxy[u][2], inxy[u][3], z > 0, z < nz - 1};
+      const T aP = ac[H0][u];
+      T tf[FF];
+#pragma unroll
+      for (int f = 0; f < FF; ++f) tf[f] = harmonic<T>(aP, af[H0][u][f]);
+      T w[7];
+      T d = T(0);
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const T th = __shfl(tf[s / LPR], gbase + s % LPR);
+        d += in[s] ? th : T(2) * aP;
+        w[1 + s] = in[s] ? -th : T(0);
+      }
+      w[0] = d;
+      // a missing neighbour reads the centre value with weight 0 (as k_rows)
+      const int ly = cy0 + u * TYS + 1, lx = cx + 1;
+      const T* L = buf + j * VW;
+      T v[7][VW];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[0][e] = pl[IC][u][e];
+      vload<T, VW>(L + (ly * LW + lx - (in[0] ? 1 : 0)) * R, v[1]);
+      vload<T, VW>(L + (ly * LW + lx + (in[1] ? 1 : 0)) * R, v[2]);
+      vload<T, VW>(L + ((ly - (in[2] ? 1 : 0)) * LW + lx) * R, v[3]);
+      vload<T, VW>(L + ((ly + (in[3] ? 1 : 0)) * LW + lx) * R, v[4]);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        v[5][e] = in[4] ? pl[IP][u][e] : pl[IC][u][e];
+        v[6][e] = in[5] ? pl[IN][u][e] : pl[IC][u][e];
+      }
+      T out[VW];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        T acc = w[0] * v[0][e];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) acc += w[1 + s] * v[1 + s][e];
+        out[e] = acc;
+      }
+      if (MODE == 1) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) out[e] = v[0][e] + omega * (bq[H0][u][e] - out[e]) / w[0];
+      }
+      if (ok[u]) vstore<T, VW>(at_b(yp, vo[u]), out);
+    }
+  };
+  ld_plane(pl[3], x, z0 - 1);
+  ld_plane(pl[0], x, z0);
+  ld_plane(pl[1], x, z0 + 1);
+  ld_halo(hb[0], z0);
+  ld_coef(ac[0], af[0], z0);
+  if (MODE == 1) ld_plane(bq[0], b, z0);
+  for (int z = z0; z < z1; z += 4) {   // z1 - z0 and the conditions below are uniform per block
+    step(std::integral_constant<int, 0>{}, z);
+    if (z + 1 < z1) step(std::integral_constant<int, 1>{}, z + 1);
+    if (z + 2 < z1) step(std::integral_constant<int, 2>{}, z + 2);
+    if (z + 3 < z1) step(std::integral_constant<int, 3>{}, z + 3);
+  }
+}
+
+// tile 16 x 8 cells, 64 LPR threads; z-chunk 16 planes for 512 threads, 8
+// otherwise (measured on FV7 128^3, R = 16), fewer when the grid is small
+template <typename T, int MODE, int VW, int LPR>
+inline void launch_zmarch(const OpDev& op, T omega, const T* b, const T* x, T* y, hipStream_t s) {
+  constexpr int TX = 16, TY = 8;
+  using Z = ZTile<LPR, TX, TY>;
+  const int ntx = (op.nx + TX - 1) / TX, nty = (op.ny + TY - 1) / TY;
+  int zc = Z::NT >= 512 ? 16 : 8;
+  while (zc > 4 && (int64_t)ntx * nty * ((op.nz + zc - 1) / zc) < 1024) zc /= 2;
+  const unsigned nb = (unsigned)((int64_t)ntx * nty * ((op.nz + zc - 1) / zc));
+  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY>), dim3(nb), dim3(Z::NT), 0, s, op, ntx, nty, zc,
+                     omega, b, x, y);
+}
+
+// the z-march applies to 3-D FV7 operators with 2, 4 or 8 lanes of 16-byte
+// vectors per row, when every byte offset within three planes fits 32 bits
+template <typename T, int MODE>
+inline bool try_zmarch(const OpDev& op, int R, T omega, const T* b, const T* x, T* y, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  if (op.kind != NLSP_OP_FV7 || op.nz < 2 || R % VW != 0) return false;
+  const int lpr = R / VW;
+  if (lpr != 2 && lpr != 4 && lpr != 8) return false;
+  const int64_t sxy = (int64_t)op.nx * op.ny;
+  if (sxy * R * (int64_t)sizeof(T) >= (int64_t(1) << 32) || 3 * sxy * 8 >= (int64_t(1) << 32)) return false;
+  auto al = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+  if (!al(x) || !al(y) || (b && !al(b))) return false;
+  switch (lpr) {
+    case 2: launch_zmarch<T, MODE, VW, 2>(op, omega, b, x, y, s); break;
+    case 4: launch_zmarch<T, MODE, VW, 4>(op, omega, b, x, y, s); break;
+    default: launch_zmarch<T, MODE, VW, 8>(op, omega, b, x, y, s);
+  }
+  return true;
+}
+
 // rows per block: 2048 (row, rhs) pairs, at most TRMAX rows
 inline int rows_per_block(int R) { return R >= 4 ? std::max(16, std::min(TRMAX, 2048 / R)) : TRMAX; }
 
@@ -247,6 +507,7 @@ inline unsigned plan_rows(const OpDev& op, int TR, BlockMap& bm) {
 // side count and the pointers allow
 template <typename T, int MODE>
 inline void launch_rows(const OpDev& op, int R, T omega, const T* b, const T* x, T* y, hipStream_t s) {
+  if (try_zmarch<T, MODE>(op, R, omega, b, x, y, s)) return;
   constexpr int VMAX = 16 / sizeof(T);
   const bool vec = (R % VMAX == 0) && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(y) % 16 == 0 && (!b || reinterpret_cast<uintptr_t>(b) % 16 == 0);

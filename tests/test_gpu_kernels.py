@@ -6,7 +6,8 @@ import scipy.sparse as sp
 import torch
 
 import oracle as O
-from tests._cases import make_case, cuda, host
+import workloads as W
+from tests._cases import make_case, cuda, host, gpu_op
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +63,70 @@ def test_jacobi_sweep_f32(nl, kind, R):
     xr = x.astype(np.float32).astype(np.float64)
     br = b.astype(np.float32).astype(np.float64)
     ref = xr + (2 / 3) * (br - A @ xr) / D
+    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def _fv7(nl, nx, ny, nz, seed, lognormal=False):
+    rng = np.random.default_rng(seed)
+    if lognormal:
+        a = np.exp(rng.standard_normal((nz, ny, nx)))
+    else:
+        a = np.where(rng.integers(0, 2, size=(nz, ny, nx)) == 1, 1e3, 1.0)
+    return O.fv_harmonic_3d(a), gpu_op(nl.OP_FV7, nx, ny, nz, a), nx * ny * nz
+
+
+# 3-D FV7 with 2, 4 or 8 lanes of 16-byte vectors per row takes the z-march
+# kernel: tiles of 16 x 8 cells, ragged in x, y and in the z-chunks (4 or 8
+# planes), grids narrower than one tile, and two planes only
+ZSHAPES = [(37, 29, 23), (16, 8, 4), (5, 3, 2), (50, 17, 9), (33, 9, 40)]
+
+
+@pytest.mark.parametrize("shape", ZSHAPES)
+@pytest.mark.parametrize("R", [4, 8, 16])
+def test_apply_operator_fv7_zmarch(nl, shape, R):
+    A, op, n = _fv7(nl, *shape, seed=sum(shape), lognormal=shape[0] % 2 == 1)
+    x = np.random.default_rng(R).standard_normal((n, R))
+    y = host(nl.apply_operator(op, cuda(x)))
+    ref = A @ x
+    scale = abs(A).sum(axis=1).A.ravel()[:, None] * np.abs(x).max()
+    assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+
+
+@pytest.mark.parametrize("shape", ZSHAPES)
+@pytest.mark.parametrize("R", [8, 16, 32])
+def test_jacobi_sweep_f32_fv7_zmarch(nl, shape, R):
+    A, op, n = _fv7(nl, *shape, seed=sum(shape) + 1, lognormal=shape[1] % 2 == 1)
+    rng = np.random.default_rng(R)
+    b, x = rng.standard_normal((n, R)), rng.standard_normal((n, R))
+    y = host(nl.jacobi_sweep_f32(op, 2 / 3, cuda(b, torch.float32), cuda(x, torch.float32)))
+    D = A.diagonal()[:, None]
+    xr = x.astype(np.float32).astype(np.float64)
+    br = b.astype(np.float32).astype(np.float64)
+    ref = xr + (2 / 3) * (br - A @ xr) / D
+    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_fv7_operator_kernels_full_size(nl):
+    """The 3-D benchmark workload (FV7, 128^3 cells, 16^3-cell blocks of a in
+    {1, 1e3}, 16 right-hand sides) in the launch configuration the benchmark
+    times: float64 y = A x and the float32 Jacobi sweep, every element against
+    the oracle's assembled operator."""
+    c4 = W.Cfg4()
+    a = c4.coef()
+    A = O.fv_harmonic_3d(a)
+    op = gpu_op(nl.OP_FV7, c4.N, c4.N, c4.N, a)
+    rng = np.random.default_rng(44)
+    x = rng.standard_normal((c4.n, c4.R))
+    y = host(nl.apply_operator(op, cuda(x)))
+    ref = A @ x
+    scale = abs(A).sum(axis=1).A.ravel()[:, None] * np.abs(x).max()
+    assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+    del y, ref
+    b = rng.standard_normal((c4.n, c4.R)).astype(np.float32)
+    x32 = x.astype(np.float32)
+    y = host(nl.jacobi_sweep_f32(op, 2 / 3, cuda(b, torch.float32), cuda(x32, torch.float32)))
+    xr, br = x32.astype(np.float64), b.astype(np.float64)
+    ref = xr + (2 / 3) * (br - A @ xr) / A.diagonal()[:, None]
     assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
 
 

@@ -104,6 +104,100 @@ __global__ __launch_bounds__(256) void k_stencil_cols(OpDev op, int m, double om
   }
 }
 
+// Row-blocked form of the same passes for 16-byte column vectors (VW columns
+// per lane): a workgroup owns TR consecutive rows (consecutive workgroups on
+// one XCD, so the rows' y- and z-neighbours were read by the same L2), forms
+// each row's coefficients once into LDS, then streams the (row, column
+// vector) items, two per thread with every load issued before the arithmetic.
+// Only the operator's NSL slots are read (5, 7 or 9, in the order of
+// k_stencil_cols); coefficients and sums in float64 as there.
+constexpr int COLS_NT = 256, COLS_TR = 128;
+
+template <typename T, int VW>
+struct ColVec {
+  using V = T __attribute__((ext_vector_type(VW)));
+};
+
+template <typename T, int VW, int NSL>
+__global__ __launch_bounds__(COLS_NT) void k_cols(OpDev op, int mp, int TR, FastDiv fcv, double omega, int mode,
+                                                 const T* __restrict__ in, T* __restrict__ out) {
+  using V = typename ColVec<T, VW>::V;
+  constexpr int CS = NSL == 9 ? 4 : 0;   // the centre slot
+  __shared__ double sc[COLS_TR][NSL];
+  __shared__ int sj[COLS_TR][NSL];       // neighbour row minus the row
+  __shared__ double ssc[COLS_TR];        // omega / a_ii (mode 0)
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t r0 = (int64_t)lb * TR;
+  const int nrows = (int)min((int64_t)TR, op.n - r0);
+  for (int t = threadIdx.x; t < nrows; t += COLS_NT) {
+    Row9 rw;
+    row_coeffs(op, r0 + t, rw);
+#pragma unroll
+    for (int q = 0; q < NSL; ++q) {
+      sc[t][q] = rw.c[q];
+      sj[t][q] = (int)(rw.j[q] - (r0 + t));
+    }
+    ssc[t] = (mode == 0) ? omega / row_center(op, rw) : 0.0;
+  }
+  __syncthreads();
+  const int CV = (int)fcv.d;
+  const int total = nrows * CV;
+  for (int b0 = threadIdx.x; b0 < total; b0 += 2 * COLS_NT) {
+    int rl[2];
+    int64_t g[2];
+    V v[2][NSL];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = min(b0 + h * COLS_NT, total - 1);   // a spare item repeats the last one
+      rl[h] = (int)fdiv((uint32_t)idx, fcv);
+      g[h] = (r0 + rl[h]) * mp + (int64_t)(idx - rl[h] * CV) * VW;
+#pragma unroll
+      for (int q = 0; q < NSL; ++q)
+        v[h][q] = *reinterpret_cast<const V*>(in + g[h] + (int64_t)sj[rl[h]][q] * mp);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (b0 + h * COLS_NT >= total) break;
+      V o;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NSL; ++q) acc += sc[rl[h]][q] * (double)v[h][q][e];
+        o[e] = (T)((mode == 0) ? (double)v[h][CS][e] - ssc[rl[h]] * acc : acc);
+      }
+      *reinterpret_cast<V*>(out + g[h]) = o;
+    }
+  }
+}
+
+// the multi-column pass over (n, mp) blocks: k_cols when the rows are whole
+// 16-byte vectors, k_stencil_cols otherwise
+template <typename T>
+inline void launch_cols(const OpDev& op, int mp, double omega, int mode, const T* in, T* out, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  const bool al = reinterpret_cast<uintptr_t>(in) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  if (mp % VW != 0 || !al || op.n * mp >= (int64_t(1) << 31)) {
+    hipLaunchKernelGGL((k_stencil_cols<T, T>), dim3(ceil_div(op.n, 4)), dim3(256), 0, s, op, mp, omega, mode,
+                       in, out);
+    return;
+  }
+  const int CV = mp / VW;
+  const int TR = std::max(1, std::min(COLS_TR, 2048 / CV));
+  const unsigned nb = (unsigned)ceil_div(op.n, TR);
+  const FastDiv f = make_fastdiv((uint32_t)CV);
+  switch (op.kind) {
+    case NLSP_OP_STENCIL9:
+      hipLaunchKernelGGL((k_cols<T, VW, 9>), dim3(nb), dim3(COLS_NT), 0, s, op, mp, TR, f, omega, mode, in, out);
+      break;
+    case NLSP_OP_FV7:
+      hipLaunchKernelGGL((k_cols<T, VW, 7>), dim3(nb), dim3(COLS_NT), 0, s, op, mp, TR, f, omega, mode, in, out);
+      break;
+    default:
+      hipLaunchKernelGGL((k_cols<T, VW, 5>), dim3(nb), dim3(COLS_NT), 0, s, op, mp, TR, f, omega, mode, in, out);
+  }
+}
+
 // --------------------------------------------------------------- MFMA Gram
 // Partial cross products C = X^T Y over a slice of rows, X (n, a), Y (n, b)
 // row-major, a and b multiples of 16.  v_mfma_f64_16x16x4f64: lane l supplies
@@ -764,8 +858,7 @@ static int setup_impl(const OpDev& op, const double* S0, int m, int k, double om
   T* Sb = static_cast<T*>(L.S1buf);
   hipLaunchKernelGGL(k_load_S0<T>, dim3(ceil_div(n * mp, 256)), dim3(256), 0, s, S0, n, m, mp, Sa);
   for (int it = 0; it < s1; ++it) {
-    hipLaunchKernelGGL((k_stencil_cols<T, T>), dim3(ceil_div(n, 4)), dim3(256), 0, s, op, mp, omega,
-                       0, Sa, Sb);
+    launch_cols<T>(op, mp, omega, 0, Sa, Sb, s);
     std::swap(Sa, Sb);
   }
   // Gram and eigenpairs
@@ -885,8 +978,7 @@ int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega
   NLSP_HIP(hipMemsetAsync(L.info, 0, sizeof(int) * 4, s));
   // padded P, Y = A P, A_c = P^T Y
   hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(n * kp, 256)), dim3(256), 0, s, P, k, n, k, L.Pp, kp);
-  hipLaunchKernelGGL((k_stencil_cols<double, double>), dim3(ceil_div(n, 4)), dim3(256), 0, s, op, kp,
-                     omega, 1, L.Pp, L.Y);
+  launch_cols<double>(op, kp, omega, 1, L.Pp, L.Y, s);
   int rc = gram<double>(L.Pp, L.Y, n, kp, kp, 0, L.part, L.Acp, kp, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_symmetrize, dim3(ceil_div(kp * kp, 256)), dim3(256), 0, s, L.Acp, kp, kp);
@@ -900,8 +992,7 @@ int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega
   double* bufs[2] = {L.Y, L.Z};
   for (int it = 0; it < nu; ++it) {
     double* dst = bufs[it & 1];
-    hipLaunchKernelGGL((k_stencil_cols<double, double>), dim3(ceil_div(n, 4)), dim3(256), 0, s, op,
-                       kp, omega, 0, cur, dst);
+    launch_cols<double>(op, kp, omega, 0, cur, dst, s);
     cur = dst;
   }
   if (Q64)

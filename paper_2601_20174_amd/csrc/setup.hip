@@ -206,19 +206,38 @@ inline void launch_cols(const OpDev& op, int mp, double omega, int mode, const T
 // With A[i][kk] = X[r0+kk][16I+i] and B[kk][j] = Y[r0+kk][16J+j] both operands
 // are "row r0 + l/16, column l%16 of a 4 x 16 block".  Tiles are dealt
 // round-robin to the waves; `sym` keeps only tiles with I <= J (X == Y).
+constexpr int GS_ROWS = 16;   // rows per staged slab (4 MFMA k-steps)
+constexpr int GS_MAXV = 2;    // 16-byte vectors per thread and slab (host-checked)
 template <typename T>
-__global__ __launch_bounds__(512) void k_gram_partial(const T* __restrict__ X,
-                                                      const T* __restrict__ Y, int64_t n, int a,
-                                                      int b, int sym, int64_t rows_per_wg,
-                                                      double* __restrict__ part) {
-  constexpr int MAXT = 18;
+struct GsVec {
+  static constexpr int VE = 16 / sizeof(T);
+  using V = T __attribute__((ext_vector_type(VE)));
+};
+// LDS row stride (doubles): a row of 8a bytes that is a multiple of 256
+// bytes gets 16 doubles of padding, so consecutive rows start 128 bytes apart
+// modulo the 256-byte bank row
+__host__ __device__ inline int gs_stride(int a) { return a + ((a * 8) % 256 == 0 ? 16 : 0); }
+inline size_t gs_lds_bytes(int a, int b, int sym) {
+  return sizeof(double) * GS_ROWS * (gs_stride(a) + (sym ? 0 : gs_stride(b)));
+}
+
+template <typename T, int MAXT>
+__global__ __launch_bounds__(1024) void k_gram_partial(const T* __restrict__ X,
+                                                       const T* __restrict__ Y, int64_t n, int a,
+                                                       int b, int sym, int64_t rows_per_wg,
+                                                       double* __restrict__ part) {
+  extern __shared__ double gsh[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int TA = a / 16, TB = b / 16;
   const int ntiles = sym ? TA * (TA + 1) / 2 : TA * TB;
+  // tiles in a fixed order (row-major; upper triangle with sym), dealt
+  // round-robin: slot q of this wave holds tile wave + q * nwave.  Decoded per
+  // slot with a compile-time slot index, so the list stays in registers.
   int tI[MAXT], tJ[MAXT];
-  int nt = 0;
-  for (int tile = wave, cnt = 0; cnt < ntiles; ++cnt) {
-    // enumerate tiles in a fixed order; keep those dealt to this wave
+  const int nt = wave < ntiles ? min(MAXT, (ntiles - wave + nwave - 1) / nwave) : 0;
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) {
+    const int cnt = min(wave + q * nwave, ntiles - 1);
     int I, J;
     if (sym) {
       int rem = cnt, row = 0;
@@ -229,28 +248,82 @@ __global__ __launch_bounds__(512) void k_gram_partial(const T* __restrict__ X,
       I = cnt / TB;
       J = cnt % TB;
     }
-    if (cnt == tile) {
-      if (nt < MAXT) { tI[nt] = I; tJ[nt] = J; ++nt; }
-      tile += nwave;
-    }
+    tI[q] = I;
+    tJ[q] = J;
   }
   d4_t acc[MAXT];
 #pragma unroll
   for (int q = 0; q < MAXT; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+  // Row slabs of GS_ROWS rows of X (and Y) are staged in LDS as float64 with
+  // coalesced 16-byte loads; the next slab is loaded into registers while the
+  // MFMAs consume the current one.  Rows past the slice are zero.  LDS rows
+  // are padded so that the four 128-byte row segments an MFMA operand read
+  // touches fall on alternating bank halves.
+  using V = typename GsVec<T>::V;
+  constexpr int VE = GsVec<T>::VE;
+  const int sa = gs_stride(a), sb = sym ? 0 : gs_stride(b);
+  double* Xs = gsh;
+  double* Ys = sym ? gsh : gsh + GS_ROWS * sa;
+  const int nva = GS_ROWS * a / VE, nvb = sym ? 0 : GS_ROWS * b / VE;   // vectors per slab
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min(n, r0 + rows_per_wg);
-  const int kr = lane >> 4, kc = lane & 15;
-  for (int64_t row = r0; row < r1; row += 4) {
-    const int64_t rr = row + kr;
-    const bool ok = rr < r1;
+  V reg[GS_MAXV];
+  auto fetch = [&](int64_t row0) {
 #pragma unroll
-    for (int q = 0; q < MAXT; ++q) {
-      if (q < nt) {
-        const double av = ok ? (double)X[rr * a + 16 * tI[q] + kc] : 0.0;
-        const double bv = ok ? (double)Y[rr * b + 16 * tJ[q] + kc] : 0.0;
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+    for (int u = 0; u < GS_MAXV; ++u) {
+      const int v = threadIdx.x + u * blockDim.x;
+      V x = V{};
+      if (v < nva) {
+        const int rr = v * VE / a;
+        if (row0 + rr < r1) x = *reinterpret_cast<const V*>(X + row0 * a + (int64_t)v * VE);
+      } else if (v < nva + nvb) {
+        const int w = v - nva, rr = w * VE / b;
+        if (row0 + rr < r1) x = *reinterpret_cast<const V*>(Y + row0 * b + (int64_t)w * VE);
+      }
+      reg[u] = x;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < GS_MAXV; ++u) {
+      const int v = threadIdx.x + u * blockDim.x;
+      if (v < nva) {
+        const int e = v * VE, rr = e / a, cc = e - rr * a;
+#pragma unroll
+        for (int c = 0; c < VE; ++c) Xs[rr * sa + cc + c] = (double)reg[u][c];
+      } else if (v < nva + nvb) {
+        const int e = (v - nva) * VE, rr = e / b, cc = e - rr * b;
+#pragma unroll
+        for (int c = 0; c < VE; ++c) Ys[rr * sb + cc + c] = (double)reg[u][c];
       }
     }
+  };
+  const int kr = lane >> 4, kc = lane & 15;
+  const int ldy = sym ? sa : sb;
+  if (r0 < r1) {
+    fetch(r0);
+    stage();
+  }
+  __syncthreads();
+  for (int64_t row0 = r0; row0 < r1; row0 += GS_ROWS) {
+    const bool more = row0 + GS_ROWS < r1;
+    if (more) fetch(row0 + GS_ROWS);
+#pragma unroll 1
+    for (int ks = 0; ks < GS_ROWS / 4; ++ks) {
+      const double* xr = Xs + (4 * ks + kr) * sa + kc;
+      const double* yr = Ys + (4 * ks + kr) * ldy + kc;
+#pragma unroll
+      for (int q = 0; q < MAXT; ++q) {
+        if (q < nt) {
+          const double av = xr[16 * tI[q]];
+          const double bv = yr[16 * tJ[q]];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    if (more) stage();
+    __syncthreads();
   }
   double* P = part + (int64_t)blockIdx.x * a * b;
 #pragma unroll
@@ -265,17 +338,38 @@ __global__ __launch_bounds__(512) void k_gram_partial(const T* __restrict__ X,
   }
 }
 
-// Fixed-order sum of the partials; sym mirrors the upper triangle.
-__global__ void k_gram_reduce(const double* __restrict__ part, int nwg, int a, int b, int sym,
-                              double* __restrict__ out, int lda_out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a * b) return;
-  int i = idx / b, j = idx % b;
-  int si = i, sj = j;
-  if (sym && (i / 16) > (j / 16)) { si = j; sj = i; }
-  double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * a * b + (int64_t)si * b + sj];
-  out[(int64_t)i * lda_out + j] = s;
+// Sum of the nwg partial products, fixed order.  A block owns 64 stored
+// elements (e = i b + j; with sym only tiles I <= J are stored, each written
+// to (i, j) and (j, i)); its four waves sum the partials w = q, q + 4, ... for
+// q = wave (eight loads in flight per lane), then the four slice sums are
+// added in wave order.
+constexpr int GR_NT = 256;
+__global__ __launch_bounds__(GR_NT) void k_gram_reduce(const double* __restrict__ part, int nwg, int a, int b, int sym,
+                                                      double* __restrict__ out, int lda_out) {
+  __shared__ double sl[GR_NT];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int ec = min(e, a * b - 1);
+  const int64_t ab = (int64_t)a * b;
+  const bool stored = !sym || (ec / b) / 16 <= (ec % b) / 16;
+  double acc = 0.0;
+  int w = stored ? q : nwg;
+  for (; w + 28 < nwg; w += 32) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(w + 4 * u) * ab + ec];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; w < nwg; w += 4) acc += part[(int64_t)w * ab + ec];
+  sl[threadIdx.x] = acc;
+  __syncthreads();
+  if (q != 0 || e >= a * b) return;
+  const double sum = ((sl[lane] + sl[64 + lane]) + sl[128 + lane]) + sl[192 + lane];
+  const int i = e / b, j = e % b;
+  if (sym && (i / 16) > (j / 16)) return;   // lower tiles are not stored
+  out[(int64_t)i * lda_out + j] = sum;
+  if (sym && (i / 16) < (j / 16)) out[(int64_t)j * lda_out + i] = sum;
 }
 
 // ------------------------------------------------- small dense, one WG
@@ -770,12 +864,21 @@ static int gram(const T* X, const T* Y, int64_t n, int a, int b, int sym, double
   const GramPlan g = gram_plan(n);
   const int TA = a / 16, TB = b / 16;
   const int ntiles = sym ? TA * (TA + 1) / 2 : TA * TB;
-  int threads = 64 * std::min(8, std::max(1, ntiles));
-  while (threads < 512 && (ntiles + threads / 64 - 1) / (threads / 64) > 18) threads += 64;
-  if ((ntiles + threads / 64 - 1) / (threads / 64) > 18) return NLSP_E_INVALID;
-  hipLaunchKernelGGL(k_gram_partial<T>, dim3(g.nwg), dim3(threads), 0, s, X, Y, n, a, b, sym,
-                     g.rows_per_wg, part);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(a * b, 256)), dim3(256), 0, s, part, g.nwg, a, b,
+  // up to 16 waves, tiles dealt round-robin: 3 slots per wave up to 48 tiles, 9 up to 144
+  const int vecs = GS_ROWS * (a + (sym ? 0 : b)) / GsVec<T>::VE;
+  const int waves = std::min(16, std::max({1, ntiles, (vecs + 64 * GS_MAXV - 1) / (64 * GS_MAXV)}));
+  const int per_wave = (ntiles + waves - 1) / waves;
+  if (per_wave > 9) return NLSP_E_INVALID;
+  const int threads = 64 * waves;
+  if (vecs > GS_MAXV * threads || gs_lds_bytes(a, b, sym) > 65536) return NLSP_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(X) % 16 != 0 || reinterpret_cast<uintptr_t>(Y) % 16 != 0) return NLSP_E_INVALID;
+  if (per_wave <= 3)
+    hipLaunchKernelGGL((k_gram_partial<T, 3>), dim3(g.nwg), dim3(threads), gs_lds_bytes(a, b, sym), s, X, Y, n,
+                       a, b, sym, g.rows_per_wg, part);
+  else
+    hipLaunchKernelGGL((k_gram_partial<T, 9>), dim3(g.nwg), dim3(threads), gs_lds_bytes(a, b, sym), s, X, Y, n,
+                       a, b, sym, g.rows_per_wg, part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(a * b, 64)), dim3(GR_NT), 0, s, part, g.nwg, a, b,
                      sym, out, ldo);
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;

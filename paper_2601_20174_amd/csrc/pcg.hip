@@ -550,47 +550,62 @@ __global__ __launch_bounds__(NT) void k_dinv(OpDev op, double* dinv, float* dinv
 }
 
 // Qt = Q A_c^-1 (n x kp), once per solve: restricting with Qt gives the
-// coarse coefficients A_c^-1 Q^T v directly.  64 rows per workgroup, four
-// threads per row, column tiles of up to 64 with A_c^-1 and the rows of Q
-// staged in LDS; float64 arithmetic, ascending sums.
+// coarse coefficients A_c^-1 Q^T v directly.  64 rows per workgroup and
+// column tiles of 64; thread t forms the 4 x 4 block of rows 4 (t / 16) ..
+// and columns 4 (t % 16) .. of the tile.  The rows of Q are staged
+// transposed (and in Q's own type) and the tile of A_c^-1 as is, so each
+// step l reads 4 consecutive values of each with two 16-byte LDS reads and
+// feeds 16 fused multiply-adds.  float64 arithmetic, sums over l ascending.
 template <typename QT>
 __global__ __launch_bounds__(256) void k_qtilde(const QT* __restrict__ Q, const double* __restrict__ Ainv,
                                                 int64_t n, int kp, QT* __restrict__ Qt) {
-  __shared__ double qs[64][65];
-  __shared__ double as[64][64];
+  constexpr int QW = 64 + 16 / (int)sizeof(QT);   // padded row of the transposed tile
+  __shared__ __align__(16) QT qs[64][QW];         // qs[l][row]
+  __shared__ __align__(16) double as[64][64];     // as[l][column]
   const int t = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * 64;
-  const int r = t / 4, cq = t % 4;
-  const int TW = min(kp, 64), cpt = TW / 4;   // 4, 8 or 16 columns per thread
-  for (int ct = 0; ct < kp; ct += TW) {
-    double acc[16];
+  const int rg = t / 16, cg = t % 16;
+  for (int ct = 0; ct < kp; ct += 64) {
+    const int TW = min(64, kp - ct);   // kp is a multiple of 16
+    double acc[4][4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
     for (int l0 = 0; l0 < kp; l0 += 64) {
       const int LW = min(64, kp - l0);
       __syncthreads();
       for (int idx = t; idx < 64 * LW; idx += 256) {
         const int rr = idx / LW, l = idx % LW;
         const int64_t row = row0 + rr;
-        qs[rr][l] = (row < n) ? (double)Q[row * kp + l0 + l] : 0.0;
+        qs[l][rr] = (row < n) ? Q[row * kp + l0 + l] : QT(0);
       }
-      for (int idx = t; idx < LW * TW; idx += 256) {
-        const int l = idx / TW, j = idx % TW;
-        as[l][j] = Ainv[(int64_t)(l0 + l) * kp + ct + j];
+      for (int idx = t; idx < LW * 64; idx += 256) {
+        const int l = idx / 64, j = idx % 64;
+        as[l][j] = (j < TW) ? Ainv[(int64_t)(l0 + l) * kp + ct + j] : 0.0;
       }
       __syncthreads();
+#pragma unroll 4
       for (int l = 0; l < LW; ++l) {
-        const double a = qs[r][l];
+        double a[4], b[4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (u < cpt) acc[u] += a * as[l][cq * cpt + u];
+        for (int i = 0; i < 4; ++i) a[i] = (double)qs[l][4 * rg + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = as[l][4 * cg + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
       }
     }
-    const int64_t row = row0 + r;
-    if (row < n)
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u < cpt) Qt[row * kp + ct + cq * cpt + u] = QT(acc[u]);
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = row0 + 4 * rg + i;
+      if (row < n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * cg + j < TW) Qt[row * kp + ct + 4 * cg + j] = QT(acc[i][j]);
+    }
   }
 }
 

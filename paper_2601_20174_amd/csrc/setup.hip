@@ -688,6 +688,52 @@ __global__ __launch_bounds__(256) void k_tsgemm(const T* __restrict__ X, int64_t
   }
 }
 
+// The same product with B staged in LDS once per workgroup (a b <= 8192):
+// the waves of a workgroup walk the 16-row tiles tile0 + w, tile0 + w + W, ...
+// (W = waves in the grid), so B is read from HBM once per workgroup instead
+// of once per MFMA.  Same operand layout and summation order as k_tsgemm.
+constexpr int TSG_LDS = 8192;   // doubles of B in LDS
+template <typename T, int MAXJ>
+__global__ __launch_bounds__(256) void k_tsgemm_lds(const T* __restrict__ X, int64_t n, int a,
+                                                    const double* __restrict__ B, int b,
+                                                    double* __restrict__ C, int ldc, int bcols_out) {
+  __shared__ double bs[TSG_LDS];
+  for (int idx = threadIdx.x; idx < a * b; idx += blockDim.x) bs[idx] = B[idx];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int TB = b / 16;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t step = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; tile < tiles; tile += step) {
+    const int64_t r0 = tile * 16;
+    d4_t acc[MAXJ];
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const int64_t ra = r0 + li;
+#pragma unroll 8
+    for (int k0 = 0; k0 < a; k0 += 4) {
+      const double av = (ra < n) ? (double)X[ra * a + k0 + lk] : 0.0;
+      const double* br = bs + (k0 + lk) * b + li;
+#pragma unroll
+      for (int q = 0; q < MAXJ; ++q) {
+        if (q < TB) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, br[16 * q], acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+      if (q < TB) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = r0 + 4 * v + lk;   // float64 MFMA output row order
+          const int col = 16 * q + li;
+          if (row < n && col < bcols_out) C[row * ldc + col] = acc[q][v];
+        }
+      }
+    }
+  }
+}
+
 // Inverse of the upper-triangular R = L^T given L lower: Ri = L^-T, (kp x kp)
 // zero padded; reuses the lower inverse: (L^T)^-1 = (L^-1)^T.
 __global__ void k_transpose_pad(const double* __restrict__ A, int kp, double* __restrict__ B) {
@@ -888,6 +934,17 @@ template <typename T>
 static void tsgemm(const T* X, int64_t n, int a, const double* B, int b, double* C, int ldc,
                    int bcols_out, hipStream_t s) {
   const int64_t tiles = (n + 15) / 16;
+  if ((int64_t)a * b <= TSG_LDS) {
+    // two workgroups per CU (LDS), four 16-row tiles per wave and more
+    const unsigned wgs = (unsigned)std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(tiles, 16)));
+    if (b <= 64)
+      hipLaunchKernelGGL((k_tsgemm_lds<T, 4>), dim3(wgs), dim3(256), 0, s, X, n, a, B, b, C, ldc, bcols_out);
+    else if (b <= 128)
+      hipLaunchKernelGGL((k_tsgemm_lds<T, 8>), dim3(wgs), dim3(256), 0, s, X, n, a, B, b, C, ldc, bcols_out);
+    else
+      hipLaunchKernelGGL((k_tsgemm_lds<T, 16>), dim3(wgs), dim3(256), 0, s, X, n, a, B, b, C, ldc, bcols_out);
+    return;
+  }
   hipLaunchKernelGGL(k_tsgemm<T>, dim3(ceil_div(tiles, 4)), dim3(256), 0, s, X, n, a, B, b, C, ldc,
                      bcols_out);
 }

@@ -42,6 +42,8 @@ def _args():
     ap.add_argument("--no-extras", action="store_true", help="skip the float64 and SpMV legs")
     ap.add_argument("--timed-phase", type=int, default=0,
                     help="solver kernel for the roofline (0 = pick the slowest)")
+    ap.add_argument("--spmv-leg", action="store_true",
+                    help="only run the stand-alone operator kernels on the 3-D workload and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count) and exit")
@@ -89,6 +91,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.spmv_leg:
+        print(json.dumps({"spmv": spmv_legs(nl, torch, dev)}), flush=True)
+        return
     c = W.Cfg2(N=a.N)
     n, m, k = c.n, c.m, c.k
     coef = c.coef()

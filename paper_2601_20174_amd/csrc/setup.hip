@@ -457,10 +457,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, in
         rs[((int64_t)rnd * half + t) * 2 + 1] = s;
       }
       __syncthreads();
-      for (int idx = t; idx < half * half; idx += nt) {
-        const int a = idx / half, b = idx % half;
-        const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-        const double ca = cs[a], sa = sn[a], cb = cs[b], sb = sn[b];
+      // the launch has a multiple of m/2 threads, so this thread's column
+      // pair b is the same for every block it updates: its indices and
+      // rotation are read once per round; row pairs a are wave-uniform
+      const int b = t % half;
+      const int pb = pp[b], qb = qq[b];
+      const double cb = cs[b], sb = sn[b];
+      for (int a = t / half; a < half; a += nt / half) {
+        const int pa = pp[a], qa = qq[a];
+        const double ca = cs[a], sa = sn[a];
         const double g11 = G[pa * m + pb], g12 = G[pa * m + qb], g21 = G[qa * m + pb], g22 = G[qa * m + qb];
         const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;   // columns: J_b
         const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
@@ -860,16 +865,27 @@ constexpr int JACOBI_MAX_SWEEPS = 40;
 
 inline size_t rot_doubles(int m) { return (size_t)JACOBI_MAX_SWEEPS * (m - 1) * (m / 2) * 2; }
 
+// threads of the eigensolver: the largest multiple of lcm(m/2, 64) up to
+// 1024 (whole waves, and a fixed column pair per thread)
+inline int eig_threads(int m) {
+  const int h = m / 2;
+  int g = h, r = 64;
+  while (r) { const int tmp = g % r; g = r; r = tmp; }
+  const int l = h / g * 64;
+  return (1024 / l) * l;
+}
+
 static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, double* off, hipStream_t s) {
+  if (m < 2 || m % 2 != 0 || eig_threads(m) < 64) return NLSP_E_INVALID;   // m is padded to a multiple of 16
   if (m <= LDS_DENSE_MAX) {
     const size_t sh = sizeof(double) * m * m;
     NLSP_HIP(hipFuncSetAttribute((const void*)k_jacobi_eig<true>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-    hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(1024), sh, s, G, m, JACOBI_MAX_SWEEPS, rot, nsweeps,
-                       off);
+    hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(eig_threads(m)), sh, s, G, m, JACOBI_MAX_SWEEPS, rot,
+                       nsweeps, off);
   } else {
-    hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(1024), 0, s, G, m, JACOBI_MAX_SWEEPS, rot, nsweeps,
-                       off);
+    hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(eig_threads(m)), 0, s, G, m, JACOBI_MAX_SWEEPS, rot,
+                       nsweeps, off);
   }
   hipLaunchKernelGGL(k_jacobi_vecs, dim3(m / 4), dim3(256), sizeof(double) * 4 * m, s, rot, nsweeps, m, V);
   NLSP_HIP(hipGetLastError());

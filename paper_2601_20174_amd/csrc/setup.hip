@@ -484,48 +484,84 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, in
 
 // V = J_1 J_2 ... from the recorded rotations.  Each row of V evolves on its
 // own (row_i <- row_i J), so one wave keeps one row in LDS and applies every
-// round's disjoint rotations, one pair per lane, in the recorded order.
+// round's disjoint rotations, one pair per lane, in the recorded order.  The
+// rotations are staged in LDS in chunks of JV_PAIRS pairs (whole rounds),
+// loaded by the whole workgroup with 16-byte loads one chunk ahead; a lane's
+// pair indices follow the round-robin formula incrementally (both move up by
+// one per round, modulo m - 1).
+constexpr int JV_PAIRS = 1024;              // pairs per staged chunk
+constexpr int JV_CPT = JV_PAIRS / 256;      // (c, s) pairs per thread and chunk
 __global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ rot,
                                                      const int* __restrict__ nsweeps, int m,
                                                      double* __restrict__ V) {
-  extern __shared__ double vrows[];   // 4 rows of m
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  extern __shared__ double vsh[];   // 4 rows of m, then two chunks of 2 JV_PAIRS
+  const int t = threadIdx.x, w = t / 64, lane = t % 64;
   const int i = blockIdx.x * 4 + w;   // m is a multiple of 4
-  double* row = vrows + w * m;
-  const int half = m / 2;
+  double* row = vsh + w * m;
+  double* cbuf[2] = {vsh + 4 * m, vsh + 4 * m + 2 * JV_PAIRS};
+  const int half = m / 2, mm = m - 1;
+  const int rpc = JV_PAIRS / half;    // whole rounds per chunk
+  const int cpairs = rpc * half;      // pairs per chunk (<= JV_PAIRS)
   for (int j = lane; j < m; j += 64) row[j] = (j == i) ? 1.0 : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  const int ns = nsweeps[0];
-  const int64_t nr = (int64_t)ns * (m - 1);   // rounds recorded, in order
-  // rotations of round g for this lane's pairs k = lane and lane + 64
-  // (half <= 128), loaded one round ahead of their use
-  auto fetch = [&](int64_t g, double (&c)[2], double (&s)[2]) {
+  const int64_t nr = (int64_t)nsweeps[0] * mm;   // rounds recorded, in order
+  const int64_t nch = (nr + rpc - 1) / rpc;
+  const int64_t npairs = nr * half;
+  const double2* rot2 = reinterpret_cast<const double2*>(rot);
+  double2 reg[JV_CPT];
+  auto fetch = [&](int64_t c) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int kk = min(lane + 64 * u, half - 1);
-      const int64_t gg = min(g, nr - 1);
-      c[u] = rot[(gg * half + kk) * 2];
-      s[u] = rot[(gg * half + kk) * 2 + 1];
+    for (int u = 0; u < JV_CPT; ++u) {
+      const int64_t g = c * cpairs + min(t + u * 256, cpairs - 1);
+      reg[u] = rot2[min(g, npairs - 1)];
     }
   };
-  double cn[2], sn_[2];
-  if (nr > 0) fetch(0, cn, sn_);
-  for (int64_t g = 0; g < nr; ++g) {
-    double c[2] = {cn[0], cn[1]}, s[2] = {sn_[0], sn_[1]};
-    fetch(g + 1, cn, sn_);
-    const int rnd = (int)(g % (m - 1));
+  auto stage = [&](double* buf) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int k = lane + 64 * u;
-      if (k < half) {
-        int p, q;
-        rr_pair(rnd, k, m, p, q);
-        const double vp = row[p], vq = row[q];
-        row[p] = c[u] * vp - s[u] * vq;
-        row[q] = s[u] * vp + c[u] * vq;
+    for (int u = 0; u < JV_CPT; ++u) {
+      if (t + u * 256 < cpairs) {
+        buf[2 * (t + u * 256)] = reg[u].x;
+        buf[2 * (t + u * 256) + 1] = reg[u].y;
       }
     }
-    __builtin_amdgcn_wave_barrier();
+  };
+  // round-robin state of this lane's pairs k = lane, lane + 64 at round 0
+  int pr[2], qr[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int k = lane + 64 * u;
+    pr[u] = k == 0 ? 0 : k % mm;
+    qr[u] = k == 0 ? mm : (mm - k) % mm;
+  }
+  if (nch > 0) {
+    fetch(0);
+    stage(cbuf[0]);
+  }
+  __syncthreads();
+  if (nch > 1) fetch(1);
+  for (int64_t c = 0; c < nch; ++c) {
+    const double* cur = cbuf[c & 1];
+    const int nrc = (int)min<int64_t>(rpc, nr - c * rpc);
+    for (int rl = 0; rl < nrc; ++rl) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = lane + 64 * u;
+        if (k < half) {
+          const int p = min(pr[u], qr[u]), q = max(pr[u], qr[u]);
+          const double cc = cur[2 * (rl * half + k)], ss = cur[2 * (rl * half + k) + 1];
+          const double vp = row[p], vq = row[q];
+          row[p] = cc * vp - ss * vq;
+          row[q] = ss * vp + cc * vq;
+        }
+        // next round: both indices move up by one modulo m - 1 (pair 0 keeps q = m - 1)
+        pr[u] = pr[u] + 1 == mm ? 0 : pr[u] + 1;
+        if (k != 0) qr[u] = qr[u] + 1 == mm ? 0 : qr[u] + 1;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();   // every wave is done with the buffer the next stage overwrites
+    if (c + 1 < nch) stage(cbuf[(c + 1) & 1]);
+    __syncthreads();
+    if (c + 2 < nch) fetch(c + 2);
   }
   for (int j = lane; j < m; j += 64) V[(int64_t)i * m + j] = row[j];
 }
@@ -876,7 +912,8 @@ inline int eig_threads(int m) {
 }
 
 static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, double* off, hipStream_t s) {
-  if (m < 2 || m % 2 != 0 || eig_threads(m) < 64) return NLSP_E_INVALID;   // m is padded to a multiple of 16
+  // m is padded to a multiple of 16
+  if (m < 16 || m % 16 != 0 || m > 256 || eig_threads(m) < 64) return NLSP_E_INVALID;
   if (m <= LDS_DENSE_MAX) {
     const size_t sh = sizeof(double) * m * m;
     NLSP_HIP(hipFuncSetAttribute((const void*)k_jacobi_eig<true>,
@@ -887,7 +924,8 @@ static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, do
     hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(eig_threads(m)), 0, s, G, m, JACOBI_MAX_SWEEPS, rot,
                        nsweeps, off);
   }
-  hipLaunchKernelGGL(k_jacobi_vecs, dim3(m / 4), dim3(256), sizeof(double) * 4 * m, s, rot, nsweeps, m, V);
+  hipLaunchKernelGGL(k_jacobi_vecs, dim3(m / 4), dim3(256), sizeof(double) * (4 * m + 4 * JV_PAIRS), s, rot, nsweeps,
+                     m, V);
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;
 }

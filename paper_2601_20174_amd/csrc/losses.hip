@@ -710,6 +710,94 @@ __global__ __launch_bounds__(NT) void k_gterm_apply(OpDev op, int64_t cstride, i
   if (threadIdx.x == 0) spart[(int64_t)b * gridDim.x + blockIdx.x] = ss;
 }
 
+// The same product row-blocked, for FV5 / FV7 / Poisson operators and m, k
+// multiples of 4: a workgroup owns GT_TR consecutive rows of one sample, forms
+// each row's face weights once into LDS (in float, as op_row<float>: the
+// diagonal d and the face means t_f, a boundary face adding 2 a_P to d), then
+// streams the (row, 4-column) items of [S | P] with 16-byte loads:
+// (A v)_i = d v_i - sum_f [f inside] t_f v_j, faces in op_row's order.
+constexpr int GT_TR = 64;
+template <int NF>
+__global__ __launch_bounds__(NT) void k_gterm_rows(OpDev op, int64_t cstride, int k, int m, FastDiv fcv,
+                                                   const float* __restrict__ P, const float* __restrict__ S,
+                                                   float* __restrict__ X, double* __restrict__ spart) {
+  __shared__ float sw[GT_TR][NF + 1];   // d, t_f (0 for a boundary face)
+  __shared__ int sj[GT_TR][NF];         // neighbour row minus the row (0 for a boundary face)
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.y;
+  OpDev ob = op;
+  if (ob.coef) ob.coef += (int64_t)b * cstride;
+  const int64_t n = op.n;
+  const int64_t r0 = (int64_t)blockIdx.x * GT_TR;
+  const int nrows = (int)min((int64_t)GT_TR, n - r0);
+  for (int t = threadIdx.x; t < nrows; t += NT) {
+    const int64_t i = r0 + t;
+    int x, y, z;
+    decompose(ob, i, x, y, z);
+    const int nx = ob.nx, ny = ob.ny;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int64_t jn[6] = {-1, 1, -(int64_t)nx, (int64_t)nx, -sxy, sxy};
+    const bool in[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < ob.nz - 1};
+    if (ob.kind == NLSP_OP_POISSON5) {
+      sw[t][0] = 4.0f;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        sw[t][1 + f] = in[f] ? 1.0f : 0.0f;
+        sj[t][f] = in[f] ? (int)jn[f] : 0;
+      }
+    } else {
+      const auto a = ob.coef;
+      const float aP = float(a[i]);
+      float d = 0.0f;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const float tf = harmonic<float>(aP, float(a[in[f] ? i + jn[f] : i]));
+        d += in[f] ? tf : 2.0f * aP;
+        sw[t][1 + f] = in[f] ? tf : 0.0f;
+        sj[t][f] = in[f] ? (int)jn[f] : 0;
+      }
+      sw[t][0] = d;
+    }
+  }
+  __syncthreads();
+  const int m4 = m / 4, CV = (int)fcv.d, total = nrows * CV;
+  const float* Sb = S + (int64_t)b * n * m;
+  const float* Pb = P + (int64_t)b * n * k;
+  float* Xb = X + (int64_t)b * n * (m + k);
+  double ss = 0.0;
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    const int rl = (int)fdiv((uint32_t)idx, fcv), c4 = idx - rl * CV;
+    const int64_t i = r0 + rl;
+    const bool fromS = c4 < m4;
+    const float* src = fromS ? Sb : Pb;
+    const int w = fromS ? m : k;
+    const int col = 4 * (fromS ? c4 : c4 - m4);
+    const float4 vi = *reinterpret_cast<const float4*>(src + i * w + col);
+    float4 vj[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) vj[f] = *reinterpret_cast<const float4*>(src + (i + sj[rl][f]) * w + col);
+    const float d = sw[rl][0];
+    float o[4];
+    const float* vip = reinterpret_cast<const float*>(&vi);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float sacc = 0.0f;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const float tf = sw[rl][1 + f];
+        sacc += sj[rl][f] != 0 ? tf * reinterpret_cast<const float*>(&vj[f])[e] : 0.0f;
+      }
+      o[e] = d * vip[e] - sacc;
+      if (fromS) ss += (double)vip[e] * (double)o[e];
+    }
+    *reinterpret_cast<float4*>(Xb + i * (m + k) + 4 * c4) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+  if (spart) {   // (m = 0, no partials: the plain Galerkin product Y = A P)
+    ss = block_sum(ss, sh);
+    if (threadIdx.x == 0) spart[(int64_t)b * gridDim.x + blockIdx.x] = ss;
+  }
+}
+
 // per sample: T = P^T X from the slab sums, A_c = sym(T[:, m:]), W = T[:, :m],
 // Cholesky, V = R^-T W, Z = R^-1 V, J, and M for a unit upstream gradient.
 // LDS (dynamic): R and R^-1 (QRK x QRK each), V and Z (k x m each).
@@ -938,8 +1026,21 @@ int galerkin_fwd(int batch, const nlsp_operator* A, const float* P, int k, float
   const SubLayout L = carve_sub(ws, batch, d);
   hipStream_t s = as_stream(stream);
   const OpDev op = make_op(*A);
-  hipLaunchKernelGGL(k_gal_apply, dim3(ceil_div(n * k, NT), batch), dim3(NT), 0, s, op, coef_stride(*A, n), k,
-                     make_fastdiv((uint32_t)k), P, Y);
+  if ((A->kind == NLSP_OP_FV5 || A->kind == NLSP_OP_FV7 || A->kind == NLSP_OP_POISSON5) && k % 4 == 0 &&
+      aligned16(P) && aligned16(Y)) {
+    // row-blocked: the Galerkin-term product with no S block
+    const FastDiv fcv = make_fastdiv((uint32_t)(k / 4));
+    const unsigned nb = (unsigned)ceil_div(n, GT_TR);
+    if (A->kind == NLSP_OP_FV7)
+      hipLaunchKernelGGL(k_gterm_rows<6>, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, 0, fcv, P,
+                         nullptr, Y, nullptr);
+    else
+      hipLaunchKernelGGL(k_gterm_rows<4>, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, 0, fcv, P,
+                         nullptr, Y, nullptr);
+  } else {
+    hipLaunchKernelGGL(k_gal_apply, dim3(ceil_div(n * k, NT), batch), dim3(NT), 0, s, op, coef_stride(*A, n), k,
+                       make_fastdiv((uint32_t)k), P, Y);
+  }
   // T = P^T [Y | P], tiles of P^T Y only: Y is the "B" block, P the "P" block
   const int rc = launch_products(d, batch, P, Y, L, s);
   if (rc != NLSP_OK) return rc;
@@ -1077,9 +1178,24 @@ int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const f
   double* spart = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up(L.bytes));
   hipStream_t s = as_stream(stream);
   const OpDev op = make_op(*A);
-  const int nb = gterm_apply_blocks(n, k, m);
-  hipLaunchKernelGGL(k_gterm_apply, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, m,
-                     make_fastdiv((uint32_t)(m + k)), P, S, Gs.X, spart);
+  // row-blocked product for face operators with 16-byte rows, else one element per thread
+  const bool rows = (A->kind == NLSP_OP_FV5 || A->kind == NLSP_OP_FV7 || A->kind == NLSP_OP_POISSON5) &&
+                    m % 4 == 0 && k % 4 == 0 && aligned16(P) && aligned16(S) && aligned16(Gs.X);
+  int nb;
+  if (rows) {
+    nb = (int)ceil_div(n, GT_TR);
+    const FastDiv fcv = make_fastdiv((uint32_t)((m + k) / 4));
+    if (A->kind == NLSP_OP_FV7)
+      hipLaunchKernelGGL(k_gterm_rows<6>, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, m, fcv, P,
+                         S, Gs.X, spart);
+    else
+      hipLaunchKernelGGL(k_gterm_rows<4>, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, m, fcv, P,
+                         S, Gs.X, spart);
+  } else {
+    nb = gterm_apply_blocks(n, k, m);
+    hipLaunchKernelGGL(k_gterm_apply, dim3(nb, batch), dim3(NT), 0, s, op, coef_stride(*A, n), k, m,
+                       make_fastdiv((uint32_t)(m + k)), P, S, Gs.X, spart);
+  }
   // T = P^T X: X is the "B" block, P the "P" block
   int rc = launch_products(d, batch, P, Gs.X, L, s);
   if (rc != NLSP_OK) return rc;

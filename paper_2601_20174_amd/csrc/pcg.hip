@@ -452,6 +452,42 @@ struct QB {
   static constexpr int NBR = 4;                          // matvec and residual kernels
 };
 
+// ---------------------------------------------- MFMA form of the basis passes
+// For R = 16 right-hand sides (one 16 x 16 tile of them) and kp = 64 or 128
+// the passes are 16 x 16 x 4 matrix products on the matrix cores, so every
+// element of Q / Qt is loaded once per pass instead of once per right-hand
+// side.  Operands: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// the accumulator element v of lane l is D[4 (l / 16) + v][l % 16] for the
+// float32 product and D[4 v + l / 16][l % 16] for the float64 one.
+//   matvec: (Qt^T w) tile I = sum over rows of Qt[row][16 I + i] w[row][c],
+//     float64 products (as restrict_rows), one column tile per wave.
+//   update: (Q c) for the 32 rows of a chunk in QT, waves = 2 row tiles x 4
+//     slices of kp / 4 columns, the slices added in order through LDS.
+constexpr int MF_R = 16;
+inline bool mf_ok(int R, int kp) { return R == MF_R && (kp == 64 || kp == 128); }
+
+template <typename QT>
+struct MfAcc;
+template <>
+struct MfAcc<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct MfAcc<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+};
+NLSP_DEV MfAcc<float>::type mf_mma(float a, float b, MfAcc<float>::type c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+NLSP_DEV MfAcc<double>::type mf_mma(double a, double b, MfAcc<double>::type c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// accumulator slot (v, lane) holding D[i][c] of a 16 x 16 tile: v * 64 + lane
+template <typename QT>
+NLSP_DEV int mf_slot(int i, int c) {
+  return sizeof(QT) == 4 ? (i & 3) * 64 + (i >> 2) * 16 + c : (i >> 2) * 64 + (i & 3) * 16 + c;
+}
+
 struct ChunkRange {
   int64_t c0, c1;
 };
@@ -670,7 +706,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
 // by the epilogue.  Nothing here waits for a scalar: every workgroup streams
 // from its first instruction.  In a batch, a system whose right-hand sides
 // have all stopped exits at once.
-template <typename QT>
+template <typename QT, bool MF>
 __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it) {
   __shared__ double wv[NT];
@@ -692,6 +728,66 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
   const double* Z = S.z;
   const double* Pv = S.p;
   const double* Qv = S.q[(it + 1) & 1];
+  if constexpr (MF) {
+    // wave: column tile I of Qt and row slice sl of each chunk (kp = 128: the
+    // whole chunk; kp = 64: two waves per tile, half the rows each)
+    const int wave = t / WAVE, lane = t % WAVE, lr = lane & 15, lg = lane >> 4;
+    const int TI = S.kp / 16, WPT = (NT / WAVE) / TI;
+    const int I = wave % TI, sl = wave / TI, rps = S.chunk_rows / WPT, ksteps = rps / 4;
+    typename MfAcc<double>::type acc = {0.0, 0.0, 0.0, 0.0};
+    double zw = 0.0, e1 = 0.0;
+    for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+      const int64_t row0 = ch * S.chunk_rows;
+      const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
+      QT a[8];   // A operands of this chunk, loaded before the stencil (rows past the chunk: a clamped row)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int rr = min(sl * rps + 4 * min(s, ksteps - 1) + lg, nrows - 1);
+        a[s] = Qt[(row0 + rr) * S.kp + 16 * I + lr];
+      }
+      double wval = 0.0;
+      if (t / R < nrows) {
+        const int64_t i = row0 + t / R;
+        const int64_t g = i * R + c;
+        int px, py, pz;
+        decompose(S.op, i, px, py, pz);
+        const double zi = Z[g], qi = Qv[g], pi = Pv[g];
+        wval = op_row<double>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
+        if (na == 0) return;   // uniform over the workgroup (one system)
+        S.w[g] = wval;
+        zw += zi * wval;
+        e1 += zi * qi + pi * wval;
+      }
+      __syncthreads();
+      wv[t] = wval;   // rows past the chunk hold 0
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (s < ksteps) acc = mf_mma((double)a[s], wv[(sl * rps + 4 * s + lg) * MF_R + lr], acc);
+    }
+    double* rec = S.rpart + (int64_t)lb * S.rw;
+    const int KR = S.kp * R;
+    if (WPT == 1) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) store_partial(&rec[(16 * I + 4 * v + lg) * MF_R + lr], acc[v]);
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + lane] = acc[v];
+      __syncthreads();
+      for (int idx = t; idx < KR; idx += NT) {
+        const int j = idx / MF_R, cc = idx % MF_R;
+        double sum = 0.0;
+        for (int q = 0; q < WPT; ++q) sum += red[(q * TI + j / 16) * 256 + mf_slot<double>(j % 16, cc)];
+        store_partial(&rec[idx], sum);
+      }
+    }
+    const double v2[2] = {zw, e1};
+    block_sum_rhsk<2>(v2, R, buf, sh);
+    if (t < 2 * R) store_partial(&rec[KR + t], buf[t]);
+    restriction_epilogue(S, lb, red, sh, (it + 1) & 1);
+    return;
+  }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double zw = 0.0, e1 = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
@@ -788,12 +884,13 @@ constexpr int PH_Z = 2;     // z = J r_new + Q c_new; partials r^T z, r^T z_old,
 //     update, `init` also takes ||f||^2, and the next iteration uses beta = 0.
 //   phase = PH_UPD only (nu > 1): stops after r_new; phase = PH_Z only, not a
 //     restart: z for the RHS the update phase advanced (stat[(it+1)&1]).
-template <typename QT>
+template <typename QT, bool MF>
 __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it,
                                                   int restart, unsigned mask, int init, int phase, int wsrc) {
   __shared__ QT ws[NT];
   __shared__ QT ys[NT];
+  __shared__ QT mfpart[MF ? (NT / WAVE) * 256 : 1];   // MFMA prolongation: per-wave partial tiles
   __shared__ double sh[NT + 16];
   // cvec: c_new = A_c^-1 Q^T r_new; gvec: g = A_c^-1 Q^T q; cg: the matvec (or
   // k_residual) group records, summed.  The region serves the final partial
@@ -852,7 +949,21 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   const bool has = cr.c0 < cr.c1;
   int64_t row0 = has ? cr.c0 * S.chunk_rows : 0;
   int nrows = has ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 1;
-  q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+  // MFMA prolongation (R = 16): wave = row tile RT x column slice ks of kp/4
+  // columns (nbk blocks of 16); a lane loads 4 consecutive columns of one row
+  // per block, feeding 4 products
+  const int mwave = t / WAVE, mlane = t % WAVE, mlr = mlane & 15, mlg = mlane >> 4;
+  const int mRT = mwave & 1, mks = mwave >> 1, mcols = S.kp / 4, mnbk = mcols / 16;
+  QT q4[2][4];
+  auto mf_fetch = [&](int64_t r0, int nr) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk)
+      load4<QT>(Q + (r0 + min(16 * mRT + mlr, nr - 1)) * S.kp + mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg, q4[blk]);
+  };
+  if constexpr (MF)
+    mf_fetch(row0, nrows);
+  else
+    q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
   if (normal && nact_cp == 0) {
     // nothing iterates: carry the state over to the next parity
     if (blockIdx.x == S.blk0) {
@@ -1000,15 +1111,29 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   auto qnew = [&](int64_t j) { return rs ? Wv[j * R + c] : Wv[j * R + c] + beta * Qo[j * R + c]; };
   auto rnew = [&](int64_t j) { return full ? Rin[j * R + c] - alpha * qnew(j) : Rin[j * R + c]; };
   QT e4[4];
+  QT eb[2][4];   // MFMA: B operands c_new[k][lane % 16] for this lane's columns k
+  if constexpr (MF) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) e4[u] = QT(cvec[(4 * m.jc + u) * R + m.c]);
+    for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        eb[blk][u] = QT(cvec[(mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg + u) * MF_R + mlr]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e4[u] = QT(cvec[(4 * m.jc + u) * R + m.c]);
+  }
   const QT om = QT(S.omega);
   double gam = 0.0, rzo = 0.0, rr = 0.0, pq = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     if (ch > cr.c0) {
       row0 = ch * S.chunk_rows;
       nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-      if (phase & PH_Z) q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+      if (phase & PH_Z) {
+        if constexpr (MF)
+          mf_fetch(row0, nrows);
+        else
+          q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+      }
     }
     const bool mine = upd && t / R < nrows;
     const int64_t i = row0 + t / R;
@@ -1048,7 +1173,27 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     if (phase & PH_Z) {
       __syncthreads();
       ws[t] = wjv;
-      prolong_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
+      if constexpr (MF) {
+        typename MfAcc<QT>::type pacc = {QT(0), QT(0), QT(0), QT(0)};
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk)
+          if (blk < mnbk)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pacc = mf_mma(q4[blk][u], eb[blk][u], pacc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) mfpart[mwave * 256 + v * 64 + mlane] = pacc[v];
+        __syncthreads();
+        // ys[row * 16 + c]: the four column slices of row tile row / 16, in order
+        {
+          const int row = t / MF_R, cc = t % MF_R, slot = mf_slot<QT>(row % 16, cc);
+          QT sum = QT(0);
+#pragma unroll
+          for (int k2 = 0; k2 < 4; ++k2) sum += mfpart[(k2 * 2 + row / 16) * 256 + slot];
+          ys[t] = sum;
+        }
+      } else {
+        prolong_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
+      }
       __syncthreads();
       if (mine) {
         const double zn = (double)ws[t] + (double)ys[t];
@@ -1306,7 +1451,11 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
                    nlsp_rhs_info* info, bool graph, hipStream_t stream) {
   const int R = hs[0].R;
   int nblk = 0;
-  for (const auto& h : hs) nblk += h.nblk;
+  bool mf = true;   // MFMA basis passes when every system has 16 right-hand sides and kp = 64 or 128
+  for (const auto& h : hs) {
+    nblk += h.nblk;
+    mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / MF_R;
+  }
   const SysDev* dsys = B.sysdev;
   const int* b2s = (nsys == 1) ? nullptr : B.blk2sys;
   const unsigned all = (1u << R) - 1u;
@@ -1337,12 +1486,20 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     auto upd = [&](int phase, int wsrc, bool timed_one) {
       if (timed_one) {
         timed(1, [&](hipEvent_t a, hipEvent_t b) {
-          hipExtLaunchKernelGGL(k_update<QT>, grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart, mask,
-                                init, phase, wsrc);
+          if (mf)
+            hipExtLaunchKernelGGL((k_update<QT, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
+                                  mask, init, phase, wsrc);
+          else
+            hipExtLaunchKernelGGL((k_update<QT, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
+                                  mask, init, phase, wsrc);
         });
       } else {
-        hipLaunchKernelGGL(k_update<QT>, grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init, phase,
-                           wsrc);
+        if (mf)
+          hipLaunchKernelGGL((k_update<QT, true>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
+                             phase, wsrc);
+        else
+          hipLaunchKernelGGL((k_update<QT, false>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
+                             phase, wsrc);
       }
     };
     if (nu == 1) {
@@ -1366,10 +1523,16 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   auto launch_matvec = [&](hipStream_t st, int it, bool can_time) {
     if (can_time) {
       timed(2, [&](hipEvent_t a, hipEvent_t b) {
-        hipExtLaunchKernelGGL(k_matvec<QT>, grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+        if (mf)
+          hipExtLaunchKernelGGL((k_matvec<QT, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+        else
+          hipExtLaunchKernelGGL((k_matvec<QT, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
       });
     } else {
-      hipLaunchKernelGGL(k_matvec<QT>, grid, block, 0, st, dsys, b2s, nsys, it);
+      if (mf)
+        hipLaunchKernelGGL((k_matvec<QT, true>), grid, block, 0, st, dsys, b2s, nsys, it);
+      else
+        hipLaunchKernelGGL((k_matvec<QT, false>), grid, block, 0, st, dsys, b2s, nsys, it);
     }
   };
   hipGraphExec_t gexec = nullptr;

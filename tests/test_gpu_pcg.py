@@ -87,6 +87,20 @@ def test_multi_rhs(nl, R, prec):
     _check(nl, A, op, P, f, prec=prec)
 
 
+# 16 right-hand sides with kp = 64 or 128 take the matrix-core form of the
+# basis passes (one 16 x 16 tile of right-hand sides); 2-D and 3-D grids
+# with ragged chunks, and more than one row chunk per workgroup
+@pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 40), ("fv5", (90, 77), 100), ("fv7", (19, 14), 64)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_multi_rhs_mfma(nl, kind, size, k, prec):
+    A, op, n = make_case(kind, 24, size)
+    S = O.relax(A, np.random.default_rng(25).standard_normal((n, 2 * k)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, k)
+    f = np.random.default_rng(26).standard_normal((n, 16))
+    f[:, 3] *= 1e-4                      # different scales converge at different iterations
+    _check(nl, A, op, P, f, prec=prec)
+
+
 @pytest.mark.parametrize("nu", [2, 3])
 def test_more_sweeps(nl, nu):
     A, op, n = make_case("fv5", 31, (50, 41))

@@ -185,6 +185,7 @@ def main():
         out["fp64"] = {"setup_ms": round(s64, 4), "solve_ms": round(p64, 4), "iters": inf64.iters,
                        "relres": inf64.relres}
         out["spmv"] = spmv_legs(nl, torch, dev)
+        out["solve3d"] = solve3d_leg(nl, torch, dev)
         out["training"] = training_legs(nl, torch, dev)
         out["batched"] = batched_legs(nl, torch, dev)
         out["predictor"] = predictor_leg(nl, torch, dev)
@@ -240,6 +241,46 @@ def spmv_legs(nl, torch, dev):
     res["copy_1GiB_GBs"] = round(2 * (1 << 30) / ms / 1e6, 1)
     for key in ("f64_apply", "f32_jacobi"):
         res[key]["of_copy"] = round(res[key]["GBs"] / res["copy_1GiB_GBs"], 4)
+    return res
+
+
+def solve3d_leg(nl, torch, dev):
+    """Setup and solve on the 3-D workload (FV7, 128^3 cells, 16^3-cell
+    blocks of a in {1, 1e3}, m = 256 relaxed vectors, k = 128, 16 right-hand
+    sides solved together: the basis passes run on the matrix cores), mixed
+    and float64, one timed run each after a warm-up.  Algorithmic bytes per
+    iteration: n (88 R + 12 + 4 kp) + n (32 R + 8 + 4 kp) in the mixed form."""
+    import workloads as W
+    c4 = W.Cfg4()
+    n, R, k = c4.n, c4.R, c4.k
+    kp = nl.nlsp_padded_rank(k)
+    op = nl.Operator(nl.OP_FV7, c4.N, c4.N, c4.N,
+                     torch.tensor(c4.coef().ravel(), dtype=torch.float64, device=dev))
+    S0 = torch.tensor(c4.S0(), dtype=torch.float64, device=dev)
+    f = torch.tensor(c4.rhs(), dtype=torch.float64, device=dev)
+    res = {"workload": f"FV7 {c4.N}^3 (n={n}), 16^3 blocks of a in {{1, 1e3}}, m={c4.m}, k={k}, R={R}, rtol={c4.rtol}"}
+    for name, prec in (("mixed", nl.MIXED), ("fp64", nl.FP64)):
+        for rep in range(2):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            P, _ = nl.setup_spectral_P(op, S0, k, c4.omega, c4.s1, prec)
+            M = nl.galerkin_coarse(op, P, c4.omega, c4.nu, q64=(prec == nl.FP64), q32=(prec == nl.MIXED))
+            e1.record()
+            u, info, rc = nl.pcg_solve(op, M, f, prec=prec, rtol=c4.rtol)
+            e2.record()
+            torch.cuda.synchronize()
+        iters = max(i.iters for i in info)
+        solve_ms = e1.elapsed_time(e2)
+        r = {"setup_ms": round(e0.elapsed_time(e1), 3), "solve_ms": round(solve_ms, 3), "rc": rc,
+             "iters_max": iters, "relres_max": max(i.relres for i in info),
+             "ms_per_iter": round(solve_ms / max(1, iters), 4)}
+        if prec == nl.MIXED:
+            by = n * ((88 * R + 12 + 4 * kp) + (32 * R + 8 + 4 * kp))
+            r["bytes_per_iter"] = by
+            r["GBs_per_iter"] = round(by / (solve_ms / max(1, iters)) / 1e6, 1)
+            r["frac"] = round(r["GBs_per_iter"] / HBM_PEAK_GBS, 4)
+        res[name] = r
+        del P, M, u
     return res
 
 

@@ -142,3 +142,31 @@ def test_deterministic(nl):
     u1, i1, _ = nl.pcg_solve(op, M, f, prec=1)
     u2, i2, _ = nl.pcg_solve(op, M, f, prec=1)
     assert torch.equal(u1, u2) and i1[0].iters == i2[0].iters
+
+
+def test_3d_workload_full_size(nl):
+    """The 3-D workload at full size in the configuration the benchmark times
+    (FV7 128^3, 16^3-cell blocks of a in {1, 1e3}, m = 256, k = 128, 16
+    right-hand sides, mixed form, matrix-core basis passes): every right-hand
+    side reaches a true relative residual <= rtol, computed with the oracle's
+    operator."""
+    c4 = W.Cfg4()
+    a = c4.coef()
+    A = O.fv_harmonic_3d(a)
+    from tests._cases import gpu_op
+    op = gpu_op(nl.OP_FV7, c4.N, c4.N, c4.N, a)
+    S0 = cuda(c4.S0())
+    fh = c4.rhs()
+    P, _ = nl.setup_spectral_P(op, S0, c4.k, c4.omega, c4.s1, nl.MIXED)
+    del S0
+    M = nl.galerkin_coarse(op, P, c4.omega, c4.nu, q64=False, q32=True)
+    u, info, rc = nl.pcg_solve(op, M, cuda(fh), prec=nl.MIXED, rtol=c4.rtol)
+    assert rc == nl.OK
+    u = host(u).reshape(fh.shape)
+    res = fh - A @ u
+    for j, inf in enumerate(info):
+        true_rel = np.linalg.norm(res[:, j]) / np.linalg.norm(fh[:, j])
+        assert inf.status == nl.OK, (j, inf)
+        assert true_rel <= c4.rtol * 1.0001, (j, true_rel)
+        assert abs(inf.relres - true_rel) <= 1e-3 * c4.rtol + 1e-12
+

@@ -492,6 +492,24 @@ struct ChunkRange {
   int64_t c0, c1;
 };
 
+// First row of logical chunk ch.  For 3-D operators whose x-lines split into
+// whole chunks, chunks are enumerated z fastest: logical chunk ch is plane
+// ch % nz of the column (y, x-segment) ch / nz, so the consecutive chunks of
+// a workgroup march through z (a row's z-neighbours are the workgroup's own
+// previous and next chunk) and the workgroups of one XCD hold neighbouring
+// columns.  Otherwise chunks are consecutive row ranges.
+NLSP_DEV int64_t chunk_row0(const SysDev& S, int64_t ch) {
+  const int nz = S.op.nz, cr = S.chunk_rows;
+  if (nz > 1 && S.op.nx % cr == 0) {
+    const int nxq = S.op.nx / cr;
+    const int64_t col = ch / nz;
+    const int z = (int)(ch - col * nz);
+    const int y = (int)(col / nxq), xq = (int)(col - (int64_t)y * nxq);
+    return ((int64_t)z * S.op.ny + y) * S.op.nx + (int64_t)xq * cr;
+  }
+  return ch * cr;
+}
+
 NLSP_DEV ChunkRange my_chunks(const SysDev& S, int lb) {
   ChunkRange cr;
   cr.c0 = (int64_t)lb * S.cpb;
@@ -670,7 +688,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
   double* Rout = S.r[rout];
   const ChunkRange cr = my_chunks(S, lb);
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t row0 = ch * S.chunk_rows;
+    const int64_t row0 = chunk_row0(S, ch);
     const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
     q_fetch<QT, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
     const int64_t i = row0 + t / R;
@@ -737,7 +755,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     typename MfAcc<double>::type acc = {0.0, 0.0, 0.0, 0.0};
     double zw = 0.0, e1 = 0.0;
     for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-      const int64_t row0 = ch * S.chunk_rows;
+      const int64_t row0 = chunk_row0(S, ch);
       const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
       QT a[8];   // A operands of this chunk, loaded before the stencil (rows past the chunk: a clamped row)
 #pragma unroll
@@ -791,7 +809,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double zw = 0.0, e1 = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t row0 = ch * S.chunk_rows;
+    const int64_t row0 = chunk_row0(S, ch);
     const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
     q_fetch<QT, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
     double wval = 0.0;
@@ -845,7 +863,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SysDev* __restrict__ sys,
   const ChunkRange cr = my_chunks(S, lb);
   auto dj = [&](int64_t j) -> PT { return (sizeof(PT) == 4) ? PT(S.dinv32[j]) : PT(S.dinv[j]); };
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t i = ch * S.chunk_rows + t / R;
+    const int64_t i = chunk_row0(S, ch) + t / R;
     if (t / R >= S.chunk_rows || i >= S.op.n) continue;
     int px, py, pz;
     decompose(S.op, i, px, py, pz);
@@ -947,7 +965,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   }
   // a workgroup without a chunk issues the same loads on row 0
   const bool has = cr.c0 < cr.c1;
-  int64_t row0 = has ? cr.c0 * S.chunk_rows : 0;
+  int64_t row0 = has ? chunk_row0(S, cr.c0) : 0;
   int nrows = has ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 1;
   // MFMA prolongation (R = 16): wave = row tile RT x column slice ks of kp/4
   // columns (nbk blocks of 16); a lane loads 4 consecutive columns of one row
@@ -1126,7 +1144,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   double gam = 0.0, rzo = 0.0, rr = 0.0, pq = 0.0;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     if (ch > cr.c0) {
-      row0 = ch * S.chunk_rows;
+      row0 = chunk_row0(S, ch);
       nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
       if (phase & PH_Z) {
         if constexpr (MF)
@@ -1232,7 +1250,7 @@ __global__ __launch_bounds__(NT) void k_true_residual(const SysDev* __restrict__
   const ChunkRange cr = my_chunks(S, lb);
   const double* X = S.x;
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-    const int64_t i = ch * S.chunk_rows + t / R;
+    const int64_t i = chunk_row0(S, ch) + t / R;
     if (t / R >= S.chunk_rows || i >= S.op.n) continue;
     int px, py, pz;
     decompose(S.op, i, px, py, pz);

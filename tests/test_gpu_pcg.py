@@ -90,7 +90,8 @@ def test_multi_rhs(nl, R, prec):
 # 16 right-hand sides with kp = 64 or 128 take the matrix-core form of the
 # basis passes (one 16 x 16 tile of right-hand sides); 2-D and 3-D grids
 # with ragged chunks, and more than one row chunk per workgroup
-@pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 40), ("fv5", (90, 77), 100), ("fv7", (19, 14), 64)])
+@pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 40), ("fv5", (90, 77), 100), ("fv7", (19, 14), 64),
+                                          ("fv7", (32, 11), 64)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_multi_rhs_mfma(nl, kind, size, k, prec):
     A, op, n = make_case(kind, 24, size)
@@ -98,6 +99,18 @@ def test_multi_rhs_mfma(nl, kind, size, k, prec):
     P, _ = O.spectral_basis(S, k)
     f = np.random.default_rng(26).standard_normal((n, 16))
     f[:, 3] *= 1e-4                      # different scales converge at different iterations
+    _check(nl, A, op, P, f, prec=prec)
+
+
+# 3-D grids whose x-lines split into whole chunks (chunk = 512 / R rows)
+# enumerate chunks z fastest, so a workgroup marches through z
+@pytest.mark.parametrize("R,size", [(8, (64, 9)), (16, (32, 13))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_zmajor_chunks(nl, R, size, prec):
+    A, op, n = make_case("fv7", 27, size)
+    S = O.relax(A, np.random.default_rng(28).standard_normal((n, 32)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, 16)
+    f = np.random.default_rng(29).standard_normal((n, R))
     _check(nl, A, op, P, f, prec=prec)
 
 

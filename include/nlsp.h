@@ -284,6 +284,22 @@ int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const floa
                       const void* saved, size_t saved_bytes, const float* gloss, float* gP,
                       void* stream);
 
+/* Captured energy of a batch of ordered bases under prefix truncation (Sec. 5,
+ * Quantitative Results: the energy-gap figure E_SVD(r) - E_model(r); the
+ * captured energy Tr(P^T S S^T P) of the appendix's Ky Fan argument):
+ *   energy[b][r-1] = ||P_b[:, :r]^T S_b||_F^2 / ||S_b||_F^2,  r = 1 .. k
+ * (the fraction of ||S_b||_F^2 that the first r columns capture when P_b has
+ * orthonormal columns).  Truncating a basis to its first r columns needs no
+ * call: pass P[:, :r] wherever a basis is taken.
+ *   P  device (batch, n, k) float32      S  device (batch, n, m) float32
+ *   energy  device (batch, k) float64
+ * Limits as subspace_loss_fwd.  The products P^T S are the forward's float32
+ * MFMA products with float64 slab sums; row energies and prefix sums in
+ * float64, fixed order.  Asynchronous on `stream`. */
+size_t captured_energy_workspace_bytes(int batch, int n, int k, int m);
+int captured_energy(int batch, int n, int k, int m, const float* P, const float* S, double* energy, void* ws,
+                    size_t ws_bytes, void* stream);
+
 /* Galerkin product of a batch of bases with a batch of operators (Algorithm 1
  * coarse operator; appendix "Two-Level Subspace Correction", coarse-operator
  * equation), for training through A_c:

@@ -14,7 +14,7 @@ from .api import (  # noqa: F401
     jacobi_sweep_f32, setup_spectral_P_workspace_bytes, setup_spectral_P,
     galerkin_coarse_workspace_bytes, galerkin_coarse, pcg_solve_workspace_bytes, pcg_solve,
     subspace_loss_saved_bytes, subspace_loss_workspace_bytes, subspace_loss_fwd, subspace_loss_bwd,
-    SubspaceLoss, subspace_loss, galerkin_fwd_workspace_bytes, galerkin_bwd_workspace_bytes, galerkin_fwd,
+    SubspaceLoss, subspace_loss, captured_energy, galerkin_fwd_workspace_bytes, galerkin_bwd_workspace_bytes, galerkin_fwd,
     galerkin_bwd, GalerkinProduct, galerkin_product, galerkin_term_saved_bytes, galerkin_term_workspace_bytes,
     galerkin_term_fwd, galerkin_term_bwd, GalerkinTerm, galerkin_term, System, pcg_solve_batched_workspace_bytes,
     pcg_solve_batched, pcg_solve_batched_tune, qr_thin_workspace_bytes, qr_thin_fwd, qr_thin_bwd, ThinQ, thin_q,

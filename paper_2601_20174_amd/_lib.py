@@ -72,6 +72,9 @@ SIGNATURES = {
                                   c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "subspace_loss_bwd": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_size_t,
                                   c_void_p, c_void_p, c_void_p]),
+    "captured_energy_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int]),
+    "captured_energy": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                c_void_p]),
     "galerkin_fwd_workspace_bytes": (c_size_t, [c_int, POP, c_int]),
     "galerkin_fwd": (c_int, [c_int, POP, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "galerkin_bwd_workspace_bytes": (c_size_t, [c_int, c_int, c_int]),

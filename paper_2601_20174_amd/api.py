@@ -286,6 +286,22 @@ def subspace_loss_bwd(P: torch.Tensor, B: torch.Tensor, saved: torch.Tensor, glo
     return gP
 
 
+def captured_energy(P: torch.Tensor, S: torch.Tensor, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Energy_b(r) = ||P_b[:, :r]^T S_b||_F^2 / ||S_b||_F^2 for r = 1..k, as a
+    (batch, k) float64 tensor: the captured energy of the leading r columns
+    (prefix truncation of an ordered basis; orthonormal P)."""
+    batch, n, k, m = _loss_dims(P, S)
+    wb = int(_L().captured_energy_workspace_bytes(batch, n, k, m))
+    if wb == 0:
+        raise NlspError("captured_energy_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(wb, P.device)
+    energy = torch.empty(batch, k, dtype=torch.float64, device=P.device)
+    rc = _L().captured_energy(batch, n, k, m, _dev(P, torch.float32, "P"), _dev(S, torch.float32, "S"),
+                              energy.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check("captured_energy", rc)
+    return energy
+
+
 class SubspaceLoss(torch.autograd.Function):
     """Per-sample subspace (or, with colw, column-weighted / NLSS) loss with
     the library's backward; B and colw receive no gradient."""

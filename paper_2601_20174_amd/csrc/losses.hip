@@ -933,6 +933,43 @@ inline int launch_bwd(const Dims& d, int batch, const float* P, const float* B, 
 
 inline bool aligned16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
 
+namespace nlsp {
+namespace sub {
+// Captured energy per sample from the slab sums of C = P^T S (tiles of the
+// forward product with P staged and no G tiles): e_j = sum_c C[j][c]^2 for rows j < k, each
+// row by one thread over c in order, then the prefix sums
+//   energy[b][r - 1] = (e_0 + ... + e_{r-1}) / ||S_b||_F^2   (r = 1 .. k)
+// in order by one thread.  Float64 throughout.
+__global__ __launch_bounds__(64) void k_energy_finish(Dims d, const double* __restrict__ T64,
+                                                     const double* __restrict__ bbpart,
+                                                     double* __restrict__ energy) {
+  __shared__ double e[64];
+  const int b = blockIdx.x, j = threadIdx.x;
+  const double* tb = T64 + (int64_t)b * d.ntiles * 256;
+  if (j < d.k) {
+    const int ti = j / 16, r = j % 16;
+    double s = 0.0;
+    for (int c = 0; c < d.m; ++c) {
+      const int id = ti * d.MT + c / 16;   // tiles row-major, no G tiles
+      const double v = tb[id * 256 + (r & 3) * 64 + (r >> 2) * 16 + (c & 15)];
+      s += v * v;
+    }
+    e[j] = s;
+  }
+  __syncthreads();
+  if (j == 0) {
+    double bb = 0.0;
+    for (int sl = 0; sl < d.nslab; ++sl) bb += bbpart[(int64_t)b * d.nslab + sl];
+    double acc = 0.0;
+    for (int r = 0; r < d.k; ++r) {
+      acc += e[r];
+      energy[(int64_t)b * d.k + r] = acc / bb;
+    }
+  }
+}
+}  // namespace sub
+}  // namespace nlsp
+
 extern "C" {
 
 // thin QR dims: products P^T B with B an n x k block (tiles of P^T B only)
@@ -1005,6 +1042,27 @@ int subspace_loss_bwd(int batch, int n, int k, int m, const float* P, const floa
       reinterpret_cast<const float*>(static_cast<const char*>(saved) + align_up((size_t)batch * sizeof(double)));
   const int rc = launch_bwd(d, batch, P, B, Msave, gloss, gP, as_stream(stream));
   if (rc != NLSP_OK) return rc;
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
+size_t captured_energy_workspace_bytes(int batch, int n, int k, int m) {
+  if (!dims_ok(batch, n, k, m)) return 0;
+  return carve_sub(nullptr, batch, make_dims(batch, n, k, m, false, true)).bytes;
+}
+
+int captured_energy(int batch, int n, int k, int m, const float* P, const float* S, double* energy, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (!dims_ok(batch, n, k, m) || !P || !S || !energy) return NLSP_E_INVALID;
+  Dims d = make_dims(batch, n, k, m, false, true);   // P staged (the A operand), no G tiles
+  if (!aligned16(P) || !aligned16(S)) d.vec = 0;
+  if (d.ntiles > MAX_TILES || fwd_lds(d) > LDS_MAX) return NLSP_E_INVALID;
+  if (!ws_ok(ws, ws_bytes, carve_sub(nullptr, batch, d).bytes)) return NLSP_E_WORKSPACE;
+  const SubLayout L = carve_sub(ws, batch, d);
+  hipStream_t s = as_stream(stream);
+  const int rc = launch_products(d, batch, P, S, L, s);
+  if (rc != NLSP_OK) return rc;
+  hipLaunchKernelGGL(k_energy_finish, dim3(batch), dim3(64), 0, s, d, L.T64, L.bbpart, energy);
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;
 }

@@ -174,3 +174,54 @@ def test_full_size_batch(nl):
         P, B = P32[b].astype(np.float64), B32[b].astype(np.float64)
         _, dgP = _bounds(P, B, None)
         assert np.all(np.abs(host(gP[b]) - O.subspace_loss_grad(P, B)) <= 2 * dgP)
+
+
+def _energy_bound(P, S):
+    """First-order bound on Energy(r) from the product bound of T = P^T S
+    (module docstring) and a float32 sum bound on ||S||^2."""
+    n = P.shape[0]
+    g = (n / 4 + 8) * U32
+    T = P.T @ S
+    dT = g * (np.abs(P).T @ np.abs(S))
+    de = np.sum(2.0 * np.abs(T) * dT + dT * dT, axis=1)
+    bb = float(np.sum(S * S))
+    E = np.cumsum(np.sum(T * T, axis=1)) / bb
+    return np.cumsum(de) / bb + E * (n + 8) * U32
+
+
+@pytest.mark.parametrize("n,k,m", [(1000, 5, 7), (4099, 16, 64), (2311, 40, 33)])
+def test_captured_energy(nl, n, k, m):
+    """Energy_b(r) of the leading r columns of orthonormal bases against the
+    oracle's captured_energy, r = 1..k, one basis per sample; the curve is
+    non-decreasing and ends at the energy of the whole basis."""
+    rng = np.random.default_rng(n + k)
+    batch = 3
+    Ps, Ss = [], []
+    for b in range(batch):
+        S = rng.standard_normal((n, m)) * np.exp(-0.1 * np.arange(m))[None, :]
+        Q, _ = np.linalg.qr(rng.standard_normal((n, k)) + S[:, :1])
+        Ps.append(Q.astype(np.float32))
+        Ss.append(S.astype(np.float32))
+    P32, S32 = np.stack(Ps), np.stack(Ss)
+    E = host(nl.captured_energy(torch.tensor(P32, device="cuda"), torch.tensor(S32, device="cuda")))
+    assert E.shape == (batch, k) and E.dtype == np.float64
+    for b in range(batch):
+        P64, S64 = P32[b].astype(np.float64), S32[b].astype(np.float64)
+        ref = np.array([O.captured_energy(P64, S64, r) for r in range(1, k + 1)])
+        tol = 2.0 * _energy_bound(P64, S64) + 1e-15
+        assert np.all(np.abs(E[b] - ref) <= tol), np.max(np.abs(E[b] - ref) / tol)
+        assert np.all(np.diff(E[b]) >= 0.0)
+
+
+def test_captured_energy_svd_prefix(nl):
+    """For the leading left singular vectors of S the curve is the prefix sums
+    of sigma^2 over their total (Eckart-Young), up to the float32 rounding of
+    the basis."""
+    rng = np.random.default_rng(11)
+    n, m, k = 3000, 48, 24
+    S = rng.standard_normal((n, m)) * np.exp(-0.15 * np.arange(m))[None, :]
+    U, sig, _ = np.linalg.svd(S, full_matrices=False)
+    P32, S32 = U[:, :k].astype(np.float32)[None], S.astype(np.float32)[None]
+    E = host(nl.captured_energy(torch.tensor(P32, device="cuda"), torch.tensor(S32, device="cuda")))[0]
+    closed = np.cumsum(sig[:k] ** 2) / np.sum(sig ** 2)
+    assert np.max(np.abs(E - closed)) <= 1e-5

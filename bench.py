@@ -446,7 +446,7 @@ def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
     ids = list(range(batch + 100, batch + 100 + held_out))
     hcoef, hB = fields(ids)
     Q = pred.basis(hcoef).detach()
-    it_learned, it_svd, loss_l, loss_s = [], [], [], []
+    it_learned, it_svd, loss_l, loss_s, gaps = [], [], [], [], []
     w = pred.nlss_weights()
     for j, i in enumerate(ids):
         op = nl.Operator(nl.OP_FV5, N, N, 1, hcoef[j].contiguous())
@@ -459,6 +459,10 @@ def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
             its.append(info[0].iters)
             lv, _ = nl.subspace_loss_fwd(P.float().unsqueeze(0).contiguous(), hB[j:j + 1].contiguous(), w)
             ls.append(float(lv[0]))
+        # energy gap E_SVD(r) - E_learned(r) under prefix truncation
+        E = nl.captured_energy(torch.stack([Ps.float(), Q[j].float()]).contiguous(),
+                               hB[j:j + 1].expand(2, -1, -1).contiguous())
+        gaps.append((E[0] - E[1]).cpu().numpy())
     flop = 2.0 * batch * n * 9 * 32 * (33 + 32 + 32 + 32) * 3
     return {"workload": f"{batch} x FV5 {N}^2, k={k}, m={m}, CNN 4 x 3x3 conv, width 32",
             "train_step_ms": round(step_ms, 3), "conv_TFLOPs_est": round(flop / step_ms / 1e9, 2),
@@ -466,7 +470,9 @@ def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
             "held_out": held_out,
             "pcg_iters_learned_median": float(np.median(it_learned)), "pcg_iters_svd_median": float(np.median(it_svd)),
             "nlss_learned_median": round(float(np.median(loss_l)), 5),
-            "nlss_svd_median": round(float(np.median(loss_s)), 5)}
+            "nlss_svd_median": round(float(np.median(loss_s)), 5),
+            "energy_gap_median": {f"r={r}": round(float(np.median([g[r - 1] for g in gaps])), 5)
+                                  for r in (k // 4, k // 2, k)}}
 
 
 def counter_traffic(kname: str, N: int, k: int):

@@ -70,6 +70,25 @@ def test_default_tile_matches_single_system_bitwise(nl, prec, R):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_sixteen_rhs_matrix_core_batch(nl, prec):
+    """16 right-hand sides and kp = 64: the batch takes the matrix-core basis
+    passes; with the default tile it reproduces the single-system solves bit
+    for bit, and every right-hand side reaches the tolerance."""
+    batch = _batch(nl, 16, k=50, m=64, sides=[24, 31, 40, 50])
+    systems = _systems(nl, batch)
+    infos, rc = nl.pcg_solve_batched(systems, prec=prec, rtol=1e-8, check_every=8)
+    assert rc == nl.OK
+    for (A, op, M, _, f), s, inf in zip(batch, systems, infos):
+        u1, info1, rc1 = nl.pcg_solve(op, M, cuda(f), prec=prec, rtol=1e-8, check_every=8)
+        assert torch.equal(s.u, u1.reshape(s.u.shape))
+        u = host(s.u).reshape(f.shape)
+        for j, a in enumerate(inf):
+            true_rel = np.linalg.norm(f[:, j] - A @ u[:, j]) / np.linalg.norm(f[:, j])
+            assert a.status == nl.OK, (j, a)
+            assert true_rel <= 1e-8 * 1.0001, (j, true_rel)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("rows", [128, 512, 2048])
 def test_tiles_against_oracle(nl, prec, rows):
     R = 8

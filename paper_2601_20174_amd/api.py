@@ -202,6 +202,43 @@ class RhsInfo:
     relres: float
 
 
+def setup_many(ops: List[Operator], S0s: List[torch.Tensor], k: int, omega: float, s1: int, nu: int = 1,
+               prec: int = FP64, workers: int = 4, q64: bool = True, q32: bool = True) -> List[TwoLevel]:
+    """setup_spectral_P + galerkin_coarse for many systems (Algorithm 1's setup
+    per system), `workers` systems at a time: each worker thread issues its
+    systems on a stream of its own (default priority), so the small kernels of
+    different systems overlap on the device (each setup call waits for its own
+    stream before it returns its status).  `prec` is the setup's precision;
+    q64 / q32 select the stored bases as in galerkin_coarse.  Returns the
+    coarse spaces in the order of `ops`; the caller's current stream waits for
+    all of them."""
+    from concurrent.futures import ThreadPoolExecutor
+    if len(ops) != len(S0s):
+        raise ValueError("ops and S0s differ in length")
+    if not ops:
+        return []
+    dev = S0s[0].device
+    workers = max(1, min(workers, len(ops)))
+    cur = torch.cuda.current_stream(dev)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(workers)]
+    for st in streams:
+        st.wait_stream(cur)
+    out: List[Optional[TwoLevel]] = [None] * len(ops)
+
+    def run(w: int):
+        with torch.cuda.stream(streams[w]):
+            for i in range(w, len(ops), workers):
+                P, _ = setup_spectral_P(ops[i], S0s[i], k, omega, s1, prec)
+                out[i] = galerkin_coarse(ops[i], P, omega, nu, q64=q64, q32=q32)
+
+    with ThreadPoolExecutor(workers) as ex:
+        for fut in [ex.submit(run, w) for w in range(workers)]:
+            fut.result()
+    for st in streams:
+        cur.wait_stream(st)
+    return out   # type: ignore[return-value]
+
+
 def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tensor] = None,
               prec: int = FP64, rtol: float = 1e-8, maxit: int = 10000, flexible: Optional[bool] = None,
               check_every: int = 32, workspace: Optional[torch.Tensor] = None,

@@ -142,3 +142,25 @@ def test_invalid(nl):
     systems[1].M = nl.galerkin_coarse(batch[1][1], batch[1][3][:, :8].contiguous(), 2 / 3, 1)   # other k
     with pytest.raises(nl.NlspError):
         nl.pcg_solve_batched(systems)
+
+
+def test_setup_many_matches_sequential_setup(nl):
+    """setup_many (systems spread over worker threads and streams) returns the
+    coarse spaces of one setup_spectral_P + galerkin_coarse per system, bit for
+    bit, in the order of the systems."""
+    rng = np.random.default_rng(3)
+    sides = [24, 31, 40, 17, 50, 33, 29]
+    et = np.stack([10 ** rng.uniform(-2, 0, len(sides)), rng.uniform(0, np.pi, len(sides))], 1)
+    st = nl.q1_aniso_stencil(torch.tensor(et, dtype=torch.float64, device="cuda"))
+    ops, S0s = [], []
+    for i, side in enumerate(sides):
+        n = side * side
+        ops.append(nl.Operator(nl.OP_STENCIL9, side, side, 1, st[i].contiguous()))
+        S0s.append(cuda(W.normal_block(W.seed_for(3, 1, 70 + i), n, 24)))
+    Ms = nl.setup_many(ops, S0s, 12, 2 / 3, 10, 1, nl.FP64, workers=3)
+    torch.cuda.synchronize()
+    for op, S0, M in zip(ops, S0s, Ms):
+        P, _ = nl.setup_spectral_P(op, S0, 12, 2 / 3, 10, nl.FP64)
+        M1 = nl.galerkin_coarse(op, P, 2 / 3, 1)
+        for a, b in ((M.Ac, M1.Ac), (M.L, M1.L), (M.Linv, M1.Linv), (M.Q64, M1.Q64), (M.Q32, M1.Q32)):
+            assert torch.equal(a, b)

@@ -79,8 +79,8 @@ def solver_bytes_per_row(phase: int, kp: int, R: int = 1) -> float:
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this program runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is designed, not built)"}))
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)

@@ -448,8 +448,11 @@ NLSP_DEV void prolong_rows(const QT* __restrict__ Q, int64_t row0, int nrows, in
 
 template <typename QT>
 struct QB {
-  static constexpr int NB = (sizeof(QT) == 4) ? 6 : 2;  // update kernel: no spills at 128 VGPRs
-  static constexpr int NBR = 4;                          // matvec and residual kernels
+  // update kernel: 4 rows of Q per thread in flight (float; measured against
+  // 2, 3, 5, 6 and 8 on the 2-D workload); 2 keeps the float64 kernel at 128
+  // VGPRs without spills
+  static constexpr int NB = (sizeof(QT) == 4) ? 4 : 2;
+  static constexpr int NBR = 4;   // matvec and residual kernels (measured against 2, 3, 5 and 6)
 };
 
 // ---------------------------------------------- MFMA form of the basis passes

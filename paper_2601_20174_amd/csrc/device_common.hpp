@@ -63,6 +63,13 @@ struct OpDev {
   int64_t n;
   Glob<const double>* coef;
   FastDiv fx, fxy;   // division by nx and by nx*ny
+  // Optional face weights of the finite-volume operators (null: formed on the
+  // fly): fw64[a*n + i] = harmonic(a_i, a_j) in float64 and fw32 the same
+  // formed in float32 from the rounded coefficients, for the face between i
+  // and its neighbour j = i + 1, i + nx, i + nx*ny (axis a = 0, 1, 2).  Both
+  // are what op_row would form, bit for bit (the mean is commutative).
+  Glob<const double>* fw64;
+  Glob<const float>* fw32;
 };
 
 inline OpDev make_op(const nlsp_operator& a) {
@@ -75,6 +82,8 @@ inline OpDev make_op(const nlsp_operator& a) {
   o.coef = as_glob(a.coef);
   o.fx = make_fastdiv((uint32_t)o.nx);
   o.fxy = make_fastdiv((uint32_t)o.nx * (uint32_t)o.ny);
+  o.fw64 = nullptr;
+  o.fw32 = nullptr;
   return o;
 }
 
@@ -86,10 +95,12 @@ NLSP_DEV T harmonic(T a, T b) {
 
 // (A v)_i for the unknown i at grid position (x, y, z).  `v(j)` returns the
 // value of the operand at unknown j.  Arithmetic in T (double or float).
+// FW: a finite-volume operator reads its face weights from op.fw64 / op.fw32
+// (which must then be set) instead of forming the harmonic means.
 // Branch-free: a neighbour outside the grid reads row i itself and its term
 // is discarded by a select, so every load of the row is issued before the
 // first use (a load under a branch would be waited for inside the branch).
-template <typename T, typename V>
+template <typename T, bool FW = false, typename V>
 NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v) {
   const int nx = op.nx, ny = op.ny;
   switch (op.kind) {
@@ -115,6 +126,27 @@ NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v) {
       const bool in[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < op.nz - 1};
       const T aP = T(a[i]);
       T d = T(0), s = T(0);
+      if constexpr (FW) {
+        const auto fw = [&] {
+          if constexpr (sizeof(T) == 8)
+            return op.fw64;
+          else
+            return op.fw32;
+        }();
+        // face f of axis f/2: the lower face (-) is stored at the lower
+        // neighbour, the upper one at i; a boundary face reads i's own
+        const int64_t n = op.n;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          if (f >= nf) break;
+          const int64_t j = in[f] ? jn[f] : i;
+          const int64_t fi = (f / 2) * n + ((in[f] && (f & 1) == 0) ? j : i);
+          const T t = T(fw[fi]), vj = v(j);
+          d += in[f] ? t : T(2) * aP;
+          s += in[f] ? t * vj : T(0);
+        }
+        return d * v(i) - s;
+      }
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         if (f >= nf) break;

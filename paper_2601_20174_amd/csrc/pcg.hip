@@ -606,6 +606,27 @@ __global__ __launch_bounds__(NT) void k_dinv(OpDev op, double* dinv, float* dinv
   dinv32[i] = (float)d;
 }
 
+// Face weights of a finite-volume operator, once per solve: for each cell i
+// and axis a, the weight of the face to the next cell along a (0 where there
+// is none), in float64 and formed in float32 from the rounded coefficients,
+// the same expressions op_row evaluates.
+__global__ __launch_bounds__(NT) void k_faces(OpDev op, double* fw64, float* fw32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= op.n) return;
+  int x, y, z;
+  decompose(op, i, x, y, z);
+  const int64_t sxy = (int64_t)op.nx * op.ny;
+  const bool up[3] = {x < op.nx - 1, y < op.ny - 1, z < op.nz - 1};
+  const int64_t jn[3] = {i + 1, i + op.nx, i + sxy};
+  const double ai = op.coef[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double aj = op.coef[up[a] ? jn[a] : i];
+    fw64[a * op.n + i] = up[a] ? harmonic<double>(ai, aj) : 0.0;
+    fw32[a * op.n + i] = up[a] ? harmonic<float>((float)ai, (float)aj) : 0.0f;
+  }
+}
+
 // Qt = Q A_c^-1 (n x kp), once per solve: restricting with Qt gives the
 // coarse coefficients A_c^-1 Q^T v directly.  64 rows per workgroup and
 // column tiles of 64; thread t forms the 4 x 4 block of rows 4 (t / 16) ..
@@ -773,7 +794,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
         int px, py, pz;
         decompose(S.op, i, px, py, pz);
         const double zi = Z[g], qi = Qv[g], pi = Pv[g];
-        wval = op_row<double>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
+        wval = op_row<double, MF>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
         if (na == 0) return;   // uniform over the workgroup (one system)
         store_partial(&S.w[g], wval);
         zw += zi * wval;
@@ -822,7 +843,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
       int px, py, pz;
       decompose(S.op, i, px, py, pz);
       const double zi = Z[g], qi = Qv[g], pi = Pv[g];
-      wval = op_row<double>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
+      wval = op_row<double, MF>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
       if (na == 0) return;   // uniform over the workgroup (one system)
       store_partial(&S.w[g], wval);
       zw += zi * wval;
@@ -1189,7 +1210,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
           };
           auto y = [&](int64_t j) { return dj(j) * QT(rnew(j)); };
           const QT yi = dj(i) * QT(ri);
-          const QT ay = op_row<QT>(S.op, i, px, py, pz, y);
+          const QT ay = op_row<QT, MF>(S.op, i, px, py, pz, y);
           wjv = QT(2) * om * yi - om * om * dj(i) * ay;
         } else {
           wjv = static_cast<const QT*>(S.wj[wsrc])[g];
@@ -1296,6 +1317,8 @@ struct SolveLayout {
   double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *dpart, *Ainv, *Qt;
   float* dinv32;
   void *wj0, *wj1;
+  double* fw64;   // face weights (null unless SysShape::faces)
+  float* fw32;
 };
 
 // Arrays shared by the systems of a batch (contiguous, so the host reads or
@@ -1317,7 +1340,18 @@ struct SysShape {
   int kp, R, nblk;
   int64_t nchunks;
   int chunk_rows;
+  bool faces;   // face weights of a finite-volume operator formed once per solve
 };
+
+// In the matrix-core form (16 right-hand sides) every lane of a row would form
+// the row's harmonic face means itself (float64 divisions in the matvec
+// kernel); there they are formed once per solve into the workspace (3 n
+// float64 + 3 n float32) and read instead (3-D workload: mixed solve 1.49 ->
+// 1.43 s, float64 1.87 -> 1.79 s, bit-identical results).  The other forms
+// keep forming them: the extra code path alone cost the one-RHS 2-D solve 3 %.
+inline bool use_faces(const nlsp_operator* A, int R, int kp) {
+  return mf_ok(R, kp) && (A->kind == NLSP_OP_FV5 || A->kind == NLSP_OP_FV7);
+}
 
 // Workgroups per system: one per chunk of NT / R rows up to a cap (512 for a
 // single system, NLSP_SOLVER_BLOCKS overrides it for tuning), or, in a batch,
@@ -1333,9 +1367,10 @@ inline int solver_blocks(int64_t nchunks) {
 
 inline int restriction_width(int kp, int R) { return kp * R + 2 * R; }
 
-inline SysShape shape_of(int64_t n, int kp, int R, int rows_per_block) {
+inline SysShape shape_of(int64_t n, int kp, int R, int rows_per_block, bool faces) {
   SysShape h;
   h.n = n;
+  h.faces = faces;
   h.kp = kp;
   h.R = R;
   h.chunk_rows = NT / R;
@@ -1372,6 +1407,8 @@ inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
   L.wj1 = cv.take<double>(nR);
   L.dinv = cv.take<double>(h.n);
   L.dinv32 = cv.take<float>(h.n);
+  L.fw64 = h.faces ? cv.take<double>((size_t)3 * h.n) : nullptr;
+  L.fw32 = h.faces ? cv.take<float>((size_t)3 * h.n) : nullptr;
   L.bpart0 = cv.take<double>((size_t)h.nblk * BW * h.R);
   L.bpart1 = cv.take<double>((size_t)h.nblk * BW * h.R);
   L.rpart = cv.take<double>((size_t)h.nblk * rw);
@@ -1415,6 +1452,8 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   SysDev hs{};
   const int R = h.R;
   hs.op = make_op(A);
+  hs.op.fw64 = as_glob((const double*)L.fw64);
+  hs.op.fw32 = as_glob((const float*)L.fw32);
   hs.R = R;
   hs.kp = h.kp;
   hs.nblk = h.nblk;
@@ -1482,6 +1521,9 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     nblk += h.nblk;
     mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / MF_R;
   }
+  // the matrix-core kernels read the face weights of finite-volume operators
+  for (const auto& h : hs)
+    if (mf && (h.op.kind == NLSP_OP_FV5 || h.op.kind == NLSP_OP_FV7) && h.op.fw64 == nullptr) return NLSP_E_INVALID;
   const SysDev* dsys = B.sysdev;
   const int* b2s = (nsys == 1) ? nullptr : B.blk2sys;
   const unsigned all = (1u << R) - 1u;
@@ -1589,6 +1631,15 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     // (C casts: the descriptor's pointers carry the device's address space)
     hipLaunchKernelGGL(k_dinv, dim3(ceil_div(hs[i].op.n, NT)), block, 0, stream, hs[i].op, (double*)hs[i].dinv,
                        (float*)hs[i].dinv32);
+    if (hs[i].op.fw64 != nullptr) {
+      // formed from a copy of the descriptor without them (op_row is not used here)
+      OpDev o = hs[i].op;
+      double* f64 = (double*)o.fw64;
+      float* f32 = (float*)o.fw32;
+      o.fw64 = nullptr;
+      o.fw32 = nullptr;
+      hipLaunchKernelGGL(k_faces, dim3(ceil_div(o.n, NT)), block, 0, stream, o, f64, f32);
+    }
     hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs[i].kp * hs[i].kp, 256)), dim3(256), 0, stream,
                        (const double*)hs[i].Linv, hs[i].kp, (double*)hs[i].Ainv);
     hipLaunchKernelGGL(k_qtilde<QT>, dim3(ceil_div(hs[i].op.n, 64)), dim3(256), 0, stream, (const QT*)hs[i].Q,
@@ -1737,7 +1788,9 @@ static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_
                        const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes, bool graph,
                        hipStream_t stream) {
   std::vector<SysShape> sh(nsys);
-  for (int i = 0; i < nsys; ++i) sh[i] = shape_of(op_size(As[i]), padded_rank(Ms[i]->k), R, rows_per_block);
+  for (int i = 0; i < nsys; ++i)
+    sh[i] = shape_of(op_size(As[i]), padded_rank(Ms[i]->k), R, rows_per_block,
+                     use_faces(As[i], R, padded_rank(Ms[i]->k)));
   if (!ws_ok(ws, ws_bytes, carve_batch(nullptr, sh, nullptr).bytes)) return NLSP_E_WORKSPACE;
   std::vector<SolveLayout> Ls;
   const BatchLayout B = carve_batch(ws, sh, &Ls);
@@ -1784,7 +1837,7 @@ size_t pcg_solve_workspace_bytes(const nlsp_operator* A, int k, int R) {
   const int64_t n = op_size(A);
   const int kp = padded_rank(k);
   if (n < 1 || kp < 0 || R < 1 || R > MAXR || kp * R > 2048 || n * R >= (int64_t(1) << 31)) return 0;
-  return carve_batch(nullptr, {shape_of(n, kp, R, 0)}, nullptr).bytes;
+  return carve_batch(nullptr, {shape_of(n, kp, R, 0, use_faces(A, R, kp))}, nullptr).bytes;
 }
 
 int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, double* u, int R,
@@ -1805,7 +1858,7 @@ size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R
     const int64_t n = op_size(&sys[i].A);
     const int kp = padded_rank(sys[i].M.k);
     if (n < 1 || kp < 0 || kp * R > 2048 || n * R >= (int64_t(1) << 31)) return 0;
-    sh[i] = shape_of(n, kp, R, rows_per_block);
+    sh[i] = shape_of(n, kp, R, rows_per_block, use_faces(&sys[i].A, R, kp));
   }
   return carve_batch(nullptr, sh, nullptr).bytes;
 }
@@ -1828,7 +1881,7 @@ int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_bloc
     Ms[i] = &s.M;
     fs[i] = s.f;
     us[i] = s.u;
-    blocks += shape_of(n, padded_rank(s.M.k), R, rows_per_block).nblk;
+    blocks += shape_of(n, padded_rank(s.M.k), R, rows_per_block, false).nblk;
   }
   if (blocks > (int64_t(1) << 30)) return NLSP_E_INVALID;
   const bool graph = opts->timing == nullptr;

@@ -1347,8 +1347,9 @@ struct SysShape {
 // the row's harmonic face means itself (float64 divisions in the matvec
 // kernel); there they are formed once per solve into the workspace (3 n
 // float64 + 3 n float32) and read instead (3-D workload: mixed solve 1.49 ->
-// 1.43 s, float64 1.87 -> 1.79 s, bit-identical results).  The other forms
-// keep forming them: the extra code path alone cost the one-RHS 2-D solve 3 %.
+// 1.43 s, float64 1.87 -> 1.71 s, bit-identical results).  The other forms
+// keep forming them: a run-time switch between the two in those kernels cost
+// the one-RHS 2-D solve 3 %.
 inline bool use_faces(const nlsp_operator* A, int R, int kp) {
   return mf_ok(R, kp) && (A->kind == NLSP_OP_FV5 || A->kind == NLSP_OP_FV7);
 }

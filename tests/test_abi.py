@@ -120,6 +120,26 @@ def test_workspace_queries(lib):
     assert lib.pcg_solve_workspace_bytes(op, 256, 16) == 0                      # kp * R > 2048
 
 
+def test_solver_workspace_holds_face_weights_for_matrix_core_form(lib):
+    """A finite-volume operator solved in the matrix-core form (16 right-hand
+    sides, k padded to 64 or 128: k in 33 .. 128) gets 3 n float64 + 3 n
+    float32 face weights in the solver workspace; other operators and the
+    other forms do not."""
+    from paper_2601_20174_amd import api
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced by the size query
+    fv7 = ctypes.byref(_op(api.OP_FV7, 8, 8, 8, fake))       # n = 512
+    fv5 = ctypes.byref(_op(api.OP_FV5, 32, 16, 1, fake))     # n = 512
+    p5 = ctypes.byref(_op(api.OP_POISSON5, 32, 16))          # n = 512
+    n = 512
+    for k in (40, 64, 100, 128):
+        base = lib.pcg_solve_workspace_bytes(p5, k, 16)
+        assert base > 0
+        assert lib.pcg_solve_workspace_bytes(fv7, k, 16) == base + 3 * n * (8 + 4)
+        assert lib.pcg_solve_workspace_bytes(fv5, k, 16) == base + 3 * n * (8 + 4)
+    for k, R in ((64, 8), (32, 16), (16, 16), (64, 1)):
+        assert lib.pcg_solve_workspace_bytes(fv7, k, R) == lib.pcg_solve_workspace_bytes(p5, k, R)
+
+
 def test_validation_rejects_before_any_gpu_call(lib):
     """Invalid arguments come back as NLSP_E_INVALID / NLSP_E_WORKSPACE on a
     machine without a GPU, i.e. validation precedes every HIP call."""

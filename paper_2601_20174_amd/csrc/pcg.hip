@@ -1151,28 +1151,36 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   const double* Qo = S.q[cp];
   double* Qn = S.q[nxt];
   // MFMA form: a workgroup marches through many chunks; the thread's own
-  // entries of the row vectors of the next chunk are loaded at the end of the
-  // current one.  They are the first loads the next chunk waits for, so the
-  // order of issue stays the order of use (waits complete in issue order; the
-  // basis tile fetched ahead instead was measured slower).  3-D workload:
-  // mixed solve 1.43 -> 1.32 s, float64 1.71 -> 1.68 s.
+  // entries of the row vectors of a later chunk are loaded at the end of the
+  // current one.  They are the first loads a chunk waits for, so the order of
+  // issue stays the order of use (waits complete in issue order; the basis
+  // tile fetched ahead instead was measured slower).  With a float basis they
+  // are loaded two chunks ahead: on z-ordered 3-D grids the next chunk is the
+  // +z plane, whose r, w, q_old the stencil gathers, so that gather then hits
+  // the cache (the float64 kernel has no registers left for the second set).
+  // 3-D workload: mixed solve 1.43 -> 1.32 s (one ahead) -> 1.28 s (two
+  // ahead), float64 1.71 -> 1.68 s.
   constexpr bool PF = MF;
+  constexpr bool PF2 = MF && sizeof(QT) == 4;
   struct RowVals {
     double z, r, p, w, qo, x;
-  } rv{};
-  auto row_fetch = [&](int64_t ch1) {
+  } rv{}, rvn{};
+  auto row_fetch = [&](RowVals& o, int64_t ch1) {
     const int64_t r1 = chunk_row0(S, ch1);
     const int nr = (int)min<int64_t>(S.chunk_rows, S.op.n - r1);
     const int64_t gg = (r1 + min(t / R, nr - 1)) * R + c;
-    rv.z = S.z[gg];
-    rv.r = Rin[gg];
-    rv.p = S.p[gg];
-    rv.w = Wv[gg];
-    rv.qo = Qo[gg];
-    rv.x = S.x[gg];
+    o.z = S.z[gg];
+    o.r = Rin[gg];
+    o.p = S.p[gg];
+    o.w = Wv[gg];
+    o.qo = Qo[gg];
+    o.x = S.x[gg];
   };
   if constexpr (PF)
-    if (cr.c0 < cr.c1) row_fetch(cr.c0);
+    if (cr.c0 < cr.c1) {
+      row_fetch(rv, cr.c0);
+      if constexpr (PF2) row_fetch(rvn, min(cr.c0 + 1, cr.c1 - 1));
+    }
   auto qnew = [&](int64_t j) { return rs ? Wv[j * R + c] : Wv[j * R + c] + beta * Qo[j * R + c]; };
   auto rnew = [&](int64_t j) { return full ? Rin[j * R + c] - alpha * qnew(j) : Rin[j * R + c]; };
   QT e4[4];
@@ -1274,7 +1282,12 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         rr += ri * ri;
       }
     }
-    if constexpr (PF) row_fetch(min(ch + 1, cr.c1 - 1));
+    if constexpr (PF2) {
+      rv = rvn;
+      row_fetch(rvn, min(ch + 2, cr.c1 - 1));
+    } else if constexpr (PF) {
+      row_fetch(rv, min(ch + 1, cr.c1 - 1));
+    }
   }
   double* bp = S.bpart[nxt] + (int64_t)lb * BW * R;
   static_assert(3 * 2048 + 6 * MAXR >= BW * (NT + 16), "partial-sum scratch");

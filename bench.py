@@ -44,6 +44,8 @@ def _args():
                     help="solver kernel for the roofline (0 = pick the slowest)")
     ap.add_argument("--spmv-leg", action="store_true",
                     help="only run the stand-alone operator kernels on the 3-D workload and exit")
+    ap.add_argument("--solve3d-leg", action="store_true",
+                    help="only run the 3-D setup + solve leg (mixed and float64) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count) and exit")
@@ -93,6 +95,9 @@ def main():
     torch.cuda.set_device(dev)
     if a.spmv_leg:
         print(json.dumps({"spmv": spmv_legs(nl, torch, dev)}), flush=True)
+        return
+    if a.solve3d_leg:
+        print(json.dumps({"solve3d": solve3d_leg(nl, torch, dev)}), flush=True)
         return
     c = W.Cfg2(N=a.N)
     n, m, k = c.n, c.m, c.k

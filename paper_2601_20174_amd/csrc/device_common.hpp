@@ -97,11 +97,13 @@ NLSP_DEV T harmonic(T a, T b) {
 // value of the operand at unknown j.  Arithmetic in T (double or float).
 // FW: a finite-volume operator reads its face weights from op.fw64 / op.fw32
 // (which must then be set) instead of forming the harmonic means.
+// ZC (with FW): the operand at the -z and +z neighbours is given as vzm, vzp
+// instead of being read through v (used only where those faces exist).
 // Branch-free: a neighbour outside the grid reads row i itself and its term
 // is discarded by a select, so every load of the row is issued before the
 // first use (a load under a branch would be waited for inside the branch).
-template <typename T, bool FW = false, typename V>
-NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v) {
+template <typename T, bool FW = false, bool ZC = false, typename V>
+NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v, T vzm = T(0), T vzp = T(0)) {
   const int nx = op.nx, ny = op.ny;
   switch (op.kind) {
     case NLSP_OP_POISSON5: {
@@ -141,7 +143,8 @@ NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v) {
           if (f >= nf) break;
           const int64_t j = in[f] ? jn[f] : i;
           const int64_t fi = (f / 2) * n + ((in[f] && (f & 1) == 0) ? j : i);
-          const T t = T(fw[fi]), vj = v(j);
+          const T t = T(fw[fi]);
+          const T vj = (ZC && f == 4) ? vzm : ((ZC && f == 5) ? vzp : v(j));
           d += in[f] ? t : T(2) * aP;
           s += in[f] ? t * vj : T(0);
         }

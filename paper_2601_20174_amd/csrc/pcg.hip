@@ -1159,8 +1159,12 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   // +z plane, whose r, w, q_old the stencil gathers, so that gather then hits
   // the cache (the float64 kernel has no registers left for the second set).
   // 3-D workload: mixed solve 1.43 -> 1.32 s (one ahead) -> 1.28 s (two
-  // ahead), float64 1.71 -> 1.68 s.
-  constexpr bool PF = MF;
+  // ahead), float64 1.71 -> 1.68 s.  The vector-lane float kernel loads them
+  // one chunk ahead too (batched anisotropic leg, 16 chunks per workgroup:
+  // 2.26 -> 2.12 s; 2-D solve 45.8 -> 45.55 ms).  There the smoother's centre
+  // term is then formed from its own loads rather than shared with r_new, so
+  // results move at float32 rounding level (same iteration counts).
+  constexpr bool PF = MF || sizeof(QT) == 4;
   constexpr bool PF2 = MF && sizeof(QT) == 4;
   struct RowVals {
     double z, r, p, w, qo, x;

@@ -16,7 +16,9 @@ Where the paper leaves a choice open the oracle takes one reading, and the HIP
 path takes the same one: relative residual ||f - A x||_2 / ||f||_2 per
 right-hand side; iteration count = number of products A p; on meeting the
 tolerance with the recursive residual the true residual is formed and, if it
-fails, replaces the recursive one; multi-RHS means independent CG per column;
+fails, replaces the recursive one and the iteration restarts from it (beta = 0:
+the old direction belongs to a residual up to 1/rtol times smaller and would
+swamp the new one); multi-RHS means independent CG per column;
 nu1 must equal nu2 (a symmetric preconditioner is needed by PCG).
 """
 from __future__ import annotations
@@ -155,12 +157,14 @@ def _pcg_one(A, f, x0, Minv, rtol, maxit, flexible, xstar=None):
         if not np.isfinite(rn):
             status = E_NONFINITE
             break
+        restart = False
         if rn <= tol:
             rt = f - A @ x
             if float(np.linalg.norm(rt)) <= tol:
                 status = OK
                 break
-            r = rt                                  # residual replacement
+            r = rt                                  # residual replacement ...
+            restart = True                          # ... and a restart from it
         z_new = Minv(r)
         gamma_new = float(r @ z_new)
         if not np.isfinite(gamma_new):
@@ -169,7 +173,9 @@ def _pcg_one(A, f, x0, Minv, rtol, maxit, flexible, xstar=None):
         if gamma_new <= 0.0:
             status = E_BREAKDOWN
             break
-        if flexible:
+        if restart:
+            beta = 0.0
+        elif flexible:
             beta = (gamma_new - float(r @ z)) / gamma
         else:
             beta = gamma_new / gamma
@@ -186,7 +192,8 @@ def pcg(A: sp.spmatrix, f: np.ndarray, Minv=None, rtol: float = 1e-8, maxit: int
 
     q = A p; delta = p^T q; alpha = gamma/delta; x += alpha p; r -= alpha q;
     stop when ||r|| <= rtol ||f|| and the true residual also passes (else the
-    true residual replaces r); z = M^-1 r; gamma' = r^T z; beta = gamma'/gamma
+    true residual replaces r and beta = 0 in the next update); z = M^-1 r;
+    gamma' = r^T z; beta = gamma'/gamma
     (``flexible``: beta = (gamma' - r^T z_old)/gamma, Polak-Ribiere);
     p = z + beta p.  ``Minv`` defaults to the identity (plain CG).
     ``xstar`` (optional, (n,R)) records the A-norm error after every iteration

@@ -159,3 +159,71 @@ def test_failure_statuses():
     assert st in (O.E_BREAKDOWN, O.NOT_CONVERGED)
     z = O.pcg(A, np.zeros(n), None)
     assert z.iters[0] == 0 and z.relres[0] == 0 and z.status[0] == O.OK
+
+
+def test_flexible_beta_equals_standard_beta_for_a_fixed_spd_preconditioner():
+    """With a fixed symmetric positive definite M^-1 the new residual is
+    M-orthogonal to the old one (r_new^T z_old = 0 in exact arithmetic), so the
+    Polak-Ribiere beta (gamma' - r_new^T z_old) / gamma reduces to
+    gamma' / gamma and both forms produce the same iterates: compared after
+    every iteration (maxit = 1, 2, ...)."""
+    A, P, Ac, L = _problem(6, N=10)
+    Minv = make_preconditioner(A, P, L, 2 / 3, 1, 1)
+    f = np.random.default_rng(7).standard_normal(A.shape[0])
+    full = O.pcg(A, f, Minv, rtol=1e-10)
+    assert full.status[0] == O.OK and full.iters[0] > 8
+    for j in range(1, int(full.iters[0]) + 1):
+        a = O.pcg(A, f, Minv, rtol=1e-10, maxit=j, flexible=False)
+        b = O.pcg(A, f, Minv, rtol=1e-10, maxit=j, flexible=True)
+        assert a.iters[0] == b.iters[0] == j
+        np.testing.assert_allclose(b.x, a.x, rtol=0, atol=1e-10 * np.abs(a.x).max())
+    # the flexible branch is live: with a nonsymmetric M^-1 (pre-smoothing only)
+    # the two betas give different iterates
+    Mns = make_preconditioner(A, P, L, 2 / 3, 1, 0)
+    a = O.pcg(A, f, Mns, rtol=1e-10, maxit=6, flexible=False)
+    b = O.pcg(A, f, Mns, rtol=1e-10, maxit=6, flexible=True)
+    assert np.abs(a.x - b.x).max() > 1e-6 * np.abs(a.x).max()
+
+
+class _OnceWrongProduct:
+    """A sparse matrix whose `call`-th product A @ v carries an error of
+    relative size `eps` (every other product is exact): makes the recursive
+    residual drift away from the true residual f - A x."""
+
+    def __init__(self, A, call, eps):
+        self.A, self.call, self.eps, self.count = A, call, eps, 0
+        self.shape = A.shape
+
+    def __matmul__(self, v):
+        self.count += 1
+        out = self.A @ v
+        if self.count == self.call:
+            rng = np.random.default_rng(0)
+            out = out + self.eps * np.linalg.norm(out) * rng.standard_normal(out.shape) / np.sqrt(out.size)
+        return out
+
+
+def test_residual_replacement_forced():
+    """One inexact product A p early in the iteration: the recursive residual
+    then meets the tolerance while the true residual does not, so the true
+    residual replaces the recursive one and the iteration continues (the count
+    goes on) until the true residual meets the tolerance."""
+    A, P, Ac, L = _problem(8, N=10)
+    Minv = make_preconditioner(A, P, L, 2 / 3, 1, 1)
+    f = np.random.default_rng(9).standard_normal(A.shape[0])
+    rtol = 1e-9
+    clean = O.pcg(A, f, Minv, rtol=rtol)
+    bad = _OnceWrongProduct(A, call=3, eps=1e-5)      # call 1: r0; call 2: q of iteration 1
+    res = O.pcg(bad, f, Minv, rtol=rtol)
+    assert res.status[0] == O.OK
+    assert np.linalg.norm(f - A @ res.x[:, 0]) <= rtol * np.linalg.norm(f)
+    h = res.history[0]
+    # the replaced residual is far above the recursive one it replaces
+    jumps = [i for i in range(1, len(h) - 1) if h[i + 1] > 100 * h[i]]
+    assert len(jumps) == 1 and h[jumps[0]] <= rtol * np.linalg.norm(f)
+    assert res.iters[0] > clean.iters[0] and res.iters[0] == len(h) - 1
+    # the true residual at the replacement was far above the tolerance (a run
+    # stopping on the recursive residual would have returned a wrong x), and
+    # the restart from it converges in no more iterations than a fresh solve
+    assert h[jumps[0] + 1] > 100 * rtol * np.linalg.norm(f)
+    assert res.iters[0] - jumps[0] <= clean.iters[0]

@@ -25,7 +25,7 @@ import numpy as np
 import torch
 
 __all__ = ["smooth_modes", "sine_modes", "layer_shapes", "param_count", "cnn_input", "cnn_forward",
-           "cnn_error_bound", "qf", "qr_backward", "adam_update"]
+           "qf", "qr_backward", "adam_update"]
 
 
 def smooth_modes(k: int):
@@ -92,33 +92,6 @@ def cnn_forward(params, coef: np.ndarray, N: int, k: int, hidden: int, return_gr
     if return_graph:
         return p, Phat
     return Phat.detach().numpy()
-
-
-def cnn_error_bound(params, coef: np.ndarray, N: int, k: int, hidden: int, u: float = 2.0 ** -9,
-                    gamma: float = 300 * 2.0 ** -24) -> np.ndarray:
-    """First-order worst-case bound on |P_hat(bfloat16 arithmetic) -
-    P_hat(exact)|, propagated layer by layer with absolute values: the input,
-    the weights and every stored pre-activation are rounded to bfloat16
-    (relative u), the next input is GELU of it rounded again, products
-    accumulate in float32 (relative gamma per output), |GELU'| <= 1.13."""
-    layers = _unpack(params, k, hidden)
-    x = torch.tensor(cnn_input(coef, N, k))
-    h, dh = x, u * x.abs()
-    conv = torch.nn.functional.conv2d
-    for l, (W, b) in enumerate(layers):
-        aW = W.abs()
-        z = conv(h, W, b, padding=1)
-        mag = conv(h.abs(), aW, None, padding=1)
-        dz = conv(dh, aW, None, padding=1) + u * mag + gamma * mag
-        if l < 3:
-            dz = dz + u * z.abs()                      # z stored in bfloat16
-            hn = torch.nn.functional.gelu(z)
-            dh = 1.13 * dz + u * hn.abs()              # GELU(z) rounded to bfloat16
-            h = hn
-        else:
-            h = z
-            dlast = dz
-    return dlast.reshape(dlast.shape[0], k, N * N).transpose(1, 2).numpy()
 
 
 def qf(A: np.ndarray):

@@ -8,6 +8,7 @@ several steps."""
 import math
 
 import numpy as np
+import pytest
 import torch
 
 import oracle as O
@@ -176,3 +177,36 @@ def test_adam_steps_two_and_three_closed_form():
     for t in range(1, 4):
         p, m, v = PR.adam_update(p, g, m, v, lr, t, b1=b1, b2=b2, eps=eps)
         np.testing.assert_allclose(p, -t * lr * g / (np.abs(g) + eps), rtol=1e-12)
+
+
+def _gpu_test_params(k, hid, seed):
+    """The parameter draw of the GPU CNN tests (He-scaled weights, small biases)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci in PR.layer_shapes(k, hid):
+        parts.append(rng.standard_normal(co * ci * 9) * np.sqrt(2.0 / (ci * 9)))
+        parts.append(rng.standard_normal(co) * 0.1)
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("N,k,hid", [(32, 16, 16), (40, 16, 32), (48, 32, 32)])
+def test_cnn_forward_bar_accepts_bf16_rounding_and_rejects_gross_errors(N, k, hid):
+    """The CNN-forward parity bar (tests/_cnn_bar.py) on the GPU test's own
+    inputs: a bfloat16 model of the GPU arithmetic passes it with room to
+    spare, and an all-zero output, Phi alone, a zeroed last layer and a
+    sign-flipped network all fail it."""
+    import workloads as W
+    from tests._cnn_bar import CNN_REL_TOL, U_BF16, bf16_forward, rel_errors
+    p = _gpu_test_params(k, hid, 1)
+    coef = np.stack([W.lognormal_field(10 + b, N).ravel() for b in range(2)])
+    ref = PR.cnn_forward(p.astype(np.float64), coef, N, k, hid)
+    phi = PR.sine_modes(N, k)
+    em = rel_errors(bf16_forward(p, coef, N, k, hid), ref, phi)
+    assert np.all(em <= CNN_REL_TOL / 4) and np.all(em >= U_BF16 / 4), em
+    q = p.astype(np.float64)
+    n4 = k * hid * 9
+    q[-k - n4:-k] = 0.0
+    mutants = {"zeros": np.zeros_like(ref), "phi only": np.broadcast_to(phi, ref.shape),
+               "layer 4 zeroed": PR.cnn_forward(q, coef, N, k, hid), "sign flip": 2 * phi[None] - ref}
+    for name, Y in mutants.items():
+        assert np.all(rel_errors(Y, ref, phi) > 10 * CNN_REL_TOL), name

@@ -125,9 +125,11 @@ size_t setup_spectral_P_workspace_bytes(const nlsp_operator* A, int m, int k, in
  *   prec   NLSP_FP64: S kept in float64; NLSP_MIXED: S relaxed in float32
  *   P      device (n, k) float64, output, P^T P = I
  *   sigma  device (m,) float64, output: singular values of S, descending
- * Synchronises `stream`; returns NLSP_E_RANK when sigma_k <= 1e-13 sigma_1
- * (P is then not meaningful) and NLSP_E_NOT_SPD when an orthonormalisation
- * Gram matrix is not positive definite. */
+ * Synchronises `stream`; returns NLSP_E_RANK when sigma_k <= 1e-6 sigma_1
+ * (S is then numerically of rank < k: the Gram route resolves singular values
+ * only down to about sqrt(eps) sigma_1, and P is not meaningful) and
+ * NLSP_E_NOT_SPD when an orthonormalisation Gram matrix is not positive
+ * definite. */
 int setup_spectral_P(const nlsp_operator* A, const double* S0, int m, int k, double omega,
                      int s1, int prec, double* P, double* sigma, void* ws, size_t ws_bytes,
                      void* stream);

@@ -53,6 +53,30 @@ def _dev(t: torch.Tensor, dtype, name: str) -> int:
     return t.data_ptr()
 
 
+def _op_checked(op: "Operator") -> "Operator":
+    """A single-system operator whose coefficient array holds exactly what its
+    kind reads (the library cannot see buffer lengths)."""
+    if op.nx < 1 or op.ny < 1 or op.nz < 1:
+        raise ValueError(f"operator extents must be positive, got {op.nx} x {op.ny} x {op.nz}")
+    per = {OP_FV5: op.n, OP_FV7: op.n, OP_STENCIL9: 9}.get(op.kind)
+    if per is not None and (op.coef is None or op.coef.numel() != per):
+        got = None if op.coef is None else op.coef.numel()
+        raise ValueError(f"operator kind {op.kind} needs {per} coefficients, got {got}")
+    return op
+
+
+def _rows(t: torch.Tensor, n: int, name: str, cols: Optional[int] = None):
+    """Checks that t is (n,) or (n, cols) before its pointer reaches a kernel."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dim() not in (1, 2) or t.shape[0] != n:
+        raise ValueError(f"{name} must have {n} rows, got shape {tuple(t.shape)}")
+    c = 1 if t.dim() == 1 else t.shape[1]
+    if cols is not None and c != cols:
+        raise ValueError(f"{name} must have {cols} columns, got shape {tuple(t.shape)}")
+    return c
+
+
 def _stream() -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -104,9 +128,10 @@ def q1_aniso_stencil(eps_theta: torch.Tensor) -> torch.Tensor:
 
 
 def apply_operator(op: Operator, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
-    R = 1 if x.dim() == 1 else x.shape[1]
+    R = _rows(x, _op_checked(op).n, "x")
     if y is None:
         y = torch.empty_like(x)
+    _rows(y, op.n, "y", R)
     _check("apply_operator", _L().apply_operator(ctypes.byref(op.c()), _dev(x, torch.float64, "x"),
                                                  _dev(y, torch.float64, "y"), R, _stream()))
     return y
@@ -114,9 +139,11 @@ def apply_operator(op: Operator, x: torch.Tensor, y: Optional[torch.Tensor] = No
 
 def jacobi_sweep_f32(op: Operator, omega: float, b: torch.Tensor, x: torch.Tensor,
                      y: Optional[torch.Tensor] = None) -> torch.Tensor:
-    R = 1 if x.dim() == 1 else x.shape[1]
+    R = _rows(x, _op_checked(op).n, "x")
+    _rows(b, op.n, "b", R)
     if y is None:
         y = torch.empty_like(x)
+    _rows(y, op.n, "y", R)
     _check("jacobi_sweep_f32", _L().jacobi_sweep_f32(
         ctypes.byref(op.c()), float(omega), _dev(b, torch.float32, "b"), _dev(x, torch.float32, "x"),
         _dev(y, torch.float32, "y"), R, _stream()))
@@ -130,7 +157,10 @@ def setup_spectral_P_workspace_bytes(op: Operator, m: int, k: int, prec: int) ->
 def setup_spectral_P(op: Operator, S0: torch.Tensor, k: int, omega: float, s1: int,
                      prec: int = FP64, workspace: Optional[torch.Tensor] = None):
     """Returns (P (n,k) float64, sigma (m,) float64)."""
+    if S0.dim() != 2:
+        raise ValueError("S0 must be (n, m)")
     n, m = S0.shape
+    _rows(S0, _op_checked(op).n, "S0", m)
     P = torch.empty((n, k), dtype=torch.float64, device=S0.device)
     sigma = torch.empty((m,), dtype=torch.float64, device=S0.device)
     nb = setup_spectral_P_workspace_bytes(op, m, k, prec)
@@ -164,13 +194,27 @@ class TwoLevel:
             _dev(self.Q32, torch.float32, "Q32") if self.Q32 is not None else None)
 
 
+def _two_level_checked(M: TwoLevel, n: int, prec: int) -> TwoLevel:
+    """The stored basis the solve reads has n rows and the padded rank."""
+    kp = nlsp_padded_rank(M.k)
+    Q = M.Q64 if prec == FP64 else M.Q32
+    if Q is None:
+        raise ValueError("the coarse space holds no basis of the requested precision")
+    if tuple(Q.shape) != (n, kp) or tuple(M.Linv.shape) != (kp, kp):
+        raise ValueError(f"coarse space shaped for another system: Q {tuple(Q.shape)}, expected ({n}, {kp})")
+    return M
+
+
 def galerkin_coarse_workspace_bytes(op: Operator, k: int) -> int:
     return int(_L().galerkin_coarse_workspace_bytes(ctypes.byref(op.c()), k))
 
 
 def galerkin_coarse(op: Operator, P: torch.Tensor, omega: float, nu: int = 1, q64: bool = True,
                     q32: bool = True, workspace: Optional[torch.Tensor] = None) -> TwoLevel:
+    if P.dim() != 2:
+        raise ValueError("P must be (n, k)")
     n, k = P.shape
+    _rows(P, _op_checked(op).n, "P", k)
     kp = nlsp_padded_rank(k)
     dev = P.device
     Ac = torch.empty((k, k), dtype=torch.float64, device=dev)
@@ -248,11 +292,13 @@ def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tens
     kernel (1 the update kernel, 2 the matvec kernel) with hipEvents attached to its dispatches; on return it also holds
     "total_ms" and "launches"."""
     squeeze = f.dim() == 1
+    R = _rows(f, _op_checked(op).n, "f")
+    _two_level_checked(M, op.n, prec)
     f2 = f.reshape(f.shape[0], -1)
-    R = f2.shape[1]
     if u is None:
         u = torch.zeros_like(f2)
     else:
+        _rows(u, op.n, "u", R)
         u = u.reshape(f2.shape)
     if flexible is None:
         flexible = prec == MIXED
@@ -510,11 +556,14 @@ def _systems(systems: List[System], prec: int):
     arr = (_lib.NlspSystem * len(systems))()
     R = None
     for i, s in enumerate(systems):
-        f2 = s.f.reshape(s.f.shape[0], -1)
+        Ri = _rows(s.f, _op_checked(s.op).n, f"systems[{i}].f")
         if R is None:
-            R = f2.shape[1]
-        if f2.shape[1] != R or s.u.numel() != f2.numel():
-            raise ValueError("every system needs the same number of right-hand sides, u shaped like f")
+            R = Ri
+        if Ri != R:
+            raise ValueError("every system needs the same number of right-hand sides")
+        _rows(s.u, s.op.n, f"systems[{i}].u", R)
+        _two_level_checked(s.M, s.op.n, prec)
+    for i, s in enumerate(systems):
         arr[i] = _lib.NlspSystem(s.op.c(), s.M.c(prec), _dev(s.f, torch.float64, "f"),
                                  _dev(s.u, torch.float64, "u"))
     return arr, R

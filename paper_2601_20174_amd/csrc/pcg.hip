@@ -795,11 +795,13 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
         decompose(S.op, i, px, py, pz);
         const double zi = Z[g], qi = Qv[g], pi = Pv[g];
         wval = op_row<double, MF>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
-        if (na == 0) return;   // uniform over the workgroup (one system)
-        store_partial(&S.w[g], wval);
-        zw += zi * wval;
-        e1 += zi * qi + pi * wval;
+        if (na != 0) {
+          store_partial(&S.w[g], wval);
+          zw += zi * wval;
+          e1 += zi * qi + pi * wval;
+        }
       }
+      if (na == 0) return;   // uniform over the workgroup (one system), before any barrier
       __syncthreads();
       wv[t] = wval;   // rows past the chunk hold 0
       __syncthreads();
@@ -844,11 +846,13 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
       decompose(S.op, i, px, py, pz);
       const double zi = Z[g], qi = Qv[g], pi = Pv[g];
       wval = op_row<double, MF>(S.op, i, px, py, pz, [&](int64_t j) { return Z[j * R + c]; });
-      if (na == 0) return;   // uniform over the workgroup (one system)
-      store_partial(&S.w[g], wval);
-      zw += zi * wval;
-      e1 += zi * qi + pi * wval;
+      if (na != 0) {
+        store_partial(&S.w[g], wval);
+        zw += zi * wval;
+        e1 += zi * qi + pi * wval;
+      }
     }
+    if (na == 0) return;   // uniform over the workgroup (one system), before any barrier
     __syncthreads();
     wv[t] = wval;
     __syncthreads();
@@ -1049,6 +1053,10 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
           conv = 0;
           if (!(ff <= 1.7e308)) {
             status = NLSP_E_NONFINITE;
+          } else if (init && ff == 0.0) {
+            // f = 0: the solution is u = 0 whatever the initial guess (the
+            // host clears those columns of u); no iteration
+            status = NLSP_OK;
           } else {
             status = NLSP_NOT_CONVERGED;
             next = 1;
@@ -1809,8 +1817,13 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
         info[j].iters = s.iters;
         info[j].status = s.status;
         info[j].relres = (s.ff > 0.0) ? std::sqrt(rrt[j] / s.ff) : 0.0;
-        if (s.status < 0 && (worst >= 0 || s.status < worst)) worst = s.status;
-        if (s.status == NLSP_NOT_CONVERGED && worst == NLSP_OK) worst = NLSP_NOT_CONVERGED;
+        // the recursive residual passed but the true one did not and no
+        // replacement is left (maxit reached or the replacement guard spent)
+        if (s.status == NLSP_OK && s.ff > 0.0 && !(rrt[j] <= hs[j / R].tol2 * s.ff))
+          info[j].status = NLSP_NOT_CONVERGED;
+        const int st = info[j].status;
+        if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+        if (st == NLSP_NOT_CONVERGED && worst == NLSP_OK) worst = NLSP_NOT_CONVERGED;
       }
       release();
       return worst;

@@ -567,7 +567,11 @@ __global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ 
 }
 
 // Sort eigenpairs descending; sigma = sqrt(max(lambda, 0)); T = V_k diag(lambda_k^-1/2)
-// (m x k, padded columns zero); info[0] = 1 if lambda_k <= (1e-13 sigma_1)^2.
+// (m x k, padded columns zero); info[0] = 1 if lambda_k <= (1e-6 sigma_1)^2.
+// The Gram route resolves singular values only down to about sqrt(eps) sigma_1
+// (the eigenvalues of G = S^T S carry rounding of order m eps lambda_1), so a
+// sigma_k below 1e-6 sigma_1 cannot be told apart from zero: S is then
+// numerically of rank < k and P_0 = S V_k / sigma_k would amplify noise.
 __global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G,
                                                     const double* __restrict__ V, int m, int mreal,
                                                     int k, int kpad, double* __restrict__ sigma,
@@ -592,7 +596,7 @@ __global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G
   if (t == 0) {
     const double l1 = lam[order[0]] > 0 ? lam[order[0]] : 0.0;
     const double lk = lam[order[k - 1]];
-    info[0] = (lk <= 1e-26 * l1 || !(lk > 0)) ? 1 : 0;
+    info[0] = (lk <= 1e-12 * l1 || !(lk > 0)) ? 1 : 0;
   }
   for (int i = t; i < mreal; i += blockDim.x) {
     const double l = lam[order[i]];

@@ -171,3 +171,53 @@ def test_validation_rejects_before_any_gpu_call(lib):
     opts_bad = _lib.NlspPcgOpts(0.0, 100, 0, 8, None)
     assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts_bad), info, None, 0, None) == E_INV
     assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts), info, None, 0, None) == E_WS
+
+
+def test_binding_checks_shapes_before_any_launch(lib):
+    """The binding compares every buffer's rows with the operator's size (and
+    the coefficient count with the operator kind) before a pointer reaches the
+    library, which cannot see buffer lengths.  CPU tensors suffice: each check
+    raises before the tensor's device is looked at."""
+    import torch
+    from paper_2601_20174_amd import api
+    n = 16 * 16
+    op = api.Operator(api.OP_POISSON5, 16, 16)
+    x = torch.zeros(n + 1, 2, dtype=torch.float64)
+    with pytest.raises(ValueError, match="rows"):
+        api.apply_operator(op, x)
+    with pytest.raises(ValueError, match="columns"):
+        api.apply_operator(op, torch.zeros(n, 2, dtype=torch.float64), torch.zeros(n, 3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="coefficients"):
+        api.apply_operator(api.Operator(api.OP_FV5, 16, 16, 1, torch.ones(n - 1, dtype=torch.float64)),
+                           torch.zeros(n, dtype=torch.float64))
+    with pytest.raises(ValueError, match="coefficients"):
+        api.apply_operator(api.Operator(api.OP_STENCIL9, 16, 16, 1, torch.ones(8, dtype=torch.float64)),
+                           torch.zeros(n, dtype=torch.float64))
+    with pytest.raises(ValueError, match="coefficients"):
+        api.apply_operator(api.Operator(api.OP_FV7, 8, 8, 8, None), torch.zeros(512, dtype=torch.float64))
+    with pytest.raises(ValueError, match="rows"):
+        api.jacobi_sweep_f32(op, 2 / 3, torch.zeros(n - 1, dtype=torch.float32), torch.zeros(n, dtype=torch.float32))
+    with pytest.raises(ValueError, match="rows"):
+        api.setup_spectral_P(op, torch.zeros(n - 2, 32, dtype=torch.float64), 16, 2 / 3, 10)
+    with pytest.raises(ValueError, match="rows"):
+        api.galerkin_coarse(op, torch.zeros(n + 16, 16, dtype=torch.float64), 2 / 3)
+    kp = api.nlsp_padded_rank(16)
+    M = api.TwoLevel(16, 1, 2 / 3, torch.zeros(16, 16, dtype=torch.float64), torch.zeros(16, 16, dtype=torch.float64),
+                     torch.zeros(kp, kp, dtype=torch.float64), None, torch.zeros(n, kp, dtype=torch.float32))
+    with pytest.raises(ValueError, match="rows"):
+        api.pcg_solve(op, M, torch.zeros(n - 1, dtype=torch.float64), prec=api.MIXED)
+    with pytest.raises(ValueError, match="columns"):
+        api.pcg_solve(op, M, torch.zeros(n, 2, dtype=torch.float64), torch.zeros(n, 3, dtype=torch.float64),
+                      prec=api.MIXED)
+    with pytest.raises(ValueError, match="no basis"):
+        api.pcg_solve(op, M, torch.zeros(n, dtype=torch.float64), prec=api.FP64)
+    small = api.Operator(api.OP_POISSON5, 8, 8)
+    with pytest.raises(ValueError, match="another system"):
+        api.pcg_solve(small, M, torch.zeros(64, dtype=torch.float64), prec=api.MIXED)
+    sysA = api.System(op, M, torch.zeros(n, 2, dtype=torch.float64), torch.zeros(n, 2, dtype=torch.float64))
+    sysB = api.System(op, M, torch.zeros(n, 2, dtype=torch.float64), torch.zeros(n - 1, 2, dtype=torch.float64))
+    with pytest.raises(ValueError, match="rows"):
+        api.pcg_solve_batched([sysA, sysB])
+    sysC = api.System(op, M, torch.zeros(n, 3, dtype=torch.float64), torch.zeros(n, 3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="same number"):
+        api.pcg_solve_batched([sysA, sysC])

@@ -144,6 +144,58 @@ def test_statuses(nl):
         nl.pcg_solve(op, M, cuda(f), rtol=-1.0)
 
 
+def test_zero_rhs_with_initial_guess(nl):
+    """A zero right-hand side has the solution u = 0 whatever the initial
+    guess (the oracle returns it with no iteration); the other right-hand
+    sides of the same call iterate from their guesses as usual."""
+    A, op, n = make_case("fv5", 44, (30, 30))
+    S = O.relax(A, np.random.default_rng(45).standard_normal((n, 16)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, 8)
+    M = nl.galerkin_coarse(op, cuda(P), 2 / 3, 1)
+    rng = np.random.default_rng(46)
+    f = rng.standard_normal((n, 3))
+    f[:, 1] = 0.0
+    u0 = rng.standard_normal((n, 3))
+    _, L = O.galerkin(A, P)
+    res = O.pcg(A, f, make_preconditioner(A, P, L, 2 / 3, 1, 1), rtol=1e-8, x0=u0)
+    for prec in (nl.FP64, nl.MIXED):
+        u, info, rc = nl.pcg_solve(op, M, cuda(f), cuda(u0), prec=prec)
+        u = host(u)
+        assert rc == nl.OK
+        assert info[1].status == nl.OK and info[1].iters == 0 and info[1].relres == 0.0
+        assert np.all(u[:, 1] == 0.0)
+        for j in (0, 2):
+            true_rel = np.linalg.norm(f[:, j] - A @ u[:, j]) / np.linalg.norm(f[:, j])
+            assert info[j].status == nl.OK and true_rel <= 1e-8 * 1.0001, (prec, j, info[j], true_rel)
+            if prec == nl.FP64:
+                assert abs(info[j].iters - res.iters[j]) <= 1, (j, info[j].iters, res.iters[j])
+    assert res.status[1] == O.OK and res.iters[1] == 0
+
+
+def test_unreachable_tolerance_is_not_converged(nl):
+    """rtol = 1e-17 lies below what a float64 true residual can show: the
+    recursive residual passes again and again, each time the true residual
+    fails and replaces it, until maxit or the replacement limit ends the
+    solve.  No right-hand side may then be reported as converged, since its
+    true residual misses the tolerance (the oracle agrees)."""
+    A, op, n = make_case("fv5", 47, (24, 20))
+    S = O.relax(A, np.random.default_rng(48).standard_normal((n, 16)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, 8)
+    M = nl.galerkin_coarse(op, cuda(P), 2 / 3, 1)
+    f = np.random.default_rng(49).standard_normal((n, 2))
+    _, L = O.galerkin(A, P)
+    res = O.pcg(A, f, make_preconditioner(A, P, L, 2 / 3, 1, 1), rtol=1e-17, maxit=300)
+    assert np.all(res.status != O.OK)
+    for prec in (nl.FP64, nl.MIXED):
+        u, info, rc = nl.pcg_solve(op, M, cuda(f), prec=prec, rtol=1e-17, maxit=300)
+        u = host(u)
+        assert rc != nl.OK, (prec, info)
+        for j, inf in enumerate(info):
+            true_rel = np.linalg.norm(f[:, j] - A @ u[:, j]) / np.linalg.norm(f[:, j])
+            assert inf.status != nl.OK, (prec, j, inf)
+            assert true_rel > 1e-17 and true_rel <= 1e-12, (prec, j, true_rel)
+
+
 def test_deterministic(nl):
     A, op, n = make_case("grf", 51, (64, 64))
     S0 = cuda(np.random.default_rng(52).standard_normal((n, 32)))

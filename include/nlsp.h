@@ -215,6 +215,31 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
               int R, const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws,
               size_t ws_bytes, void* stream);
 
+/* Size of the device scratch array behind pcg_solve_noalloc (256 MiB; e.g.
+ * 149 MiB for n = 512^2, k = 64, R = 1). */
+#define NLSP_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* pcg_solve for callers that cannot allocate device memory (code between
+ * graph captures, serving loops that forbid allocation): the same solve, the
+ * same kernels and results, with the workspace taken from a device array of
+ * NLSP_NOALLOC_SCRATCH_BYTES inside the library instead of a caller buffer.
+ *   A, M, f, u, R, info   as pcg_solve; the caller owns f, u and info
+ *   opts                  as pcg_solve; opts->timing must be NULL
+ * Calls no hipMalloc/hipFree and instantiates no graph (iterations are
+ * launched directly).  The scratch array is per GPU (the one current at the
+ * call, which must be the device of `stream`), held by the library until the
+ * process ends; its device address is looked up once per device.  Calls on
+ * one GPU share it: two calls that overlap on that GPU (different streams or
+ * threads) race and give undefined results; calls in sequence are fine (each
+ * clears what must start at zero).
+ * Returns NLSP_E_WORKSPACE, enqueueing nothing, when
+ * pcg_solve_workspace_bytes(A, M->k, R) exceeds NLSP_NOALLOC_SCRATCH_BYTES;
+ * NLSP_E_INVALID as pcg_solve, or if opts->timing is set; NLSP_E_HIP if the
+ * scratch address cannot be obtained.  Otherwise as pcg_solve (synchronises
+ * `stream`). */
+int pcg_solve_noalloc(const nlsp_operator* A, const nlsp_two_level* M, const double* f, double* u,
+                      int R, const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* stream);
+
 /* One system of a batch: its operator, its two-level preconditioner (from
  * setup_spectral_P + galerkin_coarse) and its right-hand sides. */
 typedef struct {

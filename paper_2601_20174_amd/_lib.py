@@ -66,6 +66,8 @@ SIGNATURES = {
     "pcg_solve": (c_int, [POP, ctypes.POINTER(NlspTwoLevel), c_void_p, c_void_p, c_int,
                           ctypes.POINTER(NlspPcgOpts), ctypes.POINTER(NlspRhsInfo), c_void_p,
                           c_size_t, c_void_p]),
+    "pcg_solve_noalloc": (c_int, [POP, ctypes.POINTER(NlspTwoLevel), c_void_p, c_void_p, c_int,
+                                  ctypes.POINTER(NlspPcgOpts), ctypes.POINTER(NlspRhsInfo), c_void_p]),
     "subspace_loss_saved_bytes": (c_size_t, [c_int, c_int, c_int, c_int]),
     "subspace_loss_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int]),
     "subspace_loss_fwd": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -324,6 +324,30 @@ def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tens
     return (u.reshape(f.shape) if squeeze else u), infos, rc
 
 
+NOALLOC_SCRATCH_BYTES = 256 << 20   # NLSP_NOALLOC_SCRATCH_BYTES
+
+
+def pcg_solve_noalloc(op: Operator, M: TwoLevel, f: torch.Tensor, u: torch.Tensor, prec: int = FP64,
+                      rtol: float = 1e-8, maxit: int = 10000, flexible: Optional[bool] = None,
+                      check_every: int = 32):
+    """pcg_solve through the library's non-allocating entry point: the
+    workspace is the library's own device scratch array, so the C call
+    allocates nothing; ``u`` (n,) or (n, R), the initial guess, is updated in
+    place.  Returns ([RhsInfo per RHS], status)."""
+    R = _rows(f, _op_checked(op).n, "f")
+    _rows(u, op.n, "u", R)
+    _two_level_checked(M, op.n, prec)
+    if flexible is None:
+        flexible = prec == MIXED
+    opts = _lib.NlspPcgOpts(float(rtol), int(maxit), 1 if flexible else 0, int(check_every), None)
+    info = (_lib.NlspRhsInfo * R)()
+    Mc = M.c(prec)
+    rc = _L().pcg_solve_noalloc(ctypes.byref(op.c()), ctypes.byref(Mc), _dev(f, torch.float64, "f"),
+                                _dev(u, torch.float64, "u"), R, ctypes.byref(opts), info, _stream())
+    _check("pcg_solve_noalloc", rc, allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    return [RhsInfo(info[i].iters, info[i].status, info[i].relres) for i in range(R)], rc
+
+
 # ------------------------------------------------------------ training losses
 def subspace_loss_saved_bytes(batch: int, n: int, k: int, m: int) -> int:
     return int(_L().subspace_loss_saved_bytes(batch, n, k, m))

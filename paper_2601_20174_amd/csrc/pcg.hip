@@ -38,6 +38,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -1916,6 +1917,35 @@ static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_
   return run_pcg<float>(nsys, hs, B, opts, info, graph, stream);
 }
 
+// ------------------------------------------------ non-allocating solve
+// Scratch memory of pcg_solve_noalloc: a file-scope device array, so a caller
+// that cannot allocate (graph capture elsewhere in its loop, a serving loop
+// that forbids allocation) still gets the solver's workspace.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in symbol): the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[NLSP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (NLSP_E_HIP if the
+// runtime cannot give it).
+static int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NLSP_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return NLSP_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NLSP_OK;
+}
+
 }  // namespace nlsp
 
 using namespace nlsp;
@@ -1938,6 +1968,20 @@ int pcg_solve(const nlsp_operator* A, const nlsp_two_level* M, const double* f, 
   // asked for (events attach to single dispatches)
   const bool graph = opts->timing == nullptr;
   return solve_batch(1, &A, &M, &f, &u, R, 0, opts, info, ws, ws_bytes, graph, as_stream(stream_));
+}
+
+int pcg_solve_noalloc(const nlsp_operator* A, const nlsp_two_level* M, const double* f, double* u, int R,
+                      const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* stream_) {
+  const int64_t n = op_size(A);
+  if (!info || !opts_ok(opts) || opts->timing != nullptr || !system_ok(A, M, f, u, R, n)) return NLSP_E_INVALID;
+  const size_t need = pcg_solve_workspace_bytes(A, M->k, R);
+  if (need == 0) return NLSP_E_INVALID;
+  if (need > NLSP_NOALLOC_SCRATCH_BYTES) return NLSP_E_WORKSPACE;
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc != NLSP_OK) return rc;
+  // direct launches: no graph is instantiated, so nothing is allocated
+  return solve_batch(1, &A, &M, &f, &u, R, 0, opts, info, ws, need, false, as_stream(stream_));
 }
 
 size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R, int rows_per_block) {

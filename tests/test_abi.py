@@ -171,6 +171,15 @@ def test_validation_rejects_before_any_gpu_call(lib):
     opts_bad = _lib.NlspPcgOpts(0.0, 100, 0, 8, None)
     assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts_bad), info, None, 0, None) == E_INV
     assert lib.pcg_solve(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts), info, None, 0, None) == E_WS
+    # the non-allocating solve: its scratch array holds 256 MiB; a 128^3
+    # system with k = 128 and 16 right-hand sides needs more
+    assert lib.pcg_solve_noalloc(op, ctypes.byref(M_noq), fake, u, 1, ctypes.byref(opts), info, None) == E_INV
+    big = ctypes.byref(_op(api.OP_POISSON5, 2048, 1024))
+    Mbig = _lib.NlspTwoLevel(128, 1, 2 / 3, api.MIXED, fake, None, fake)
+    assert lib.pcg_solve_noalloc(big, ctypes.byref(Mbig), fake, u, 16, ctypes.byref(opts), info, None) == E_WS
+    tm = _lib.NlspKernelTiming(1, 1, 0.0, 0)
+    opts_tm = _lib.NlspPcgOpts(1e-8, 100, 0, 8, ctypes.pointer(tm))
+    assert lib.pcg_solve_noalloc(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts_tm), info, None) == E_INV
 
 
 def test_binding_checks_shapes_before_any_launch(lib):

@@ -15,14 +15,15 @@ application per PCG iteration).  Everything is float64.
 Modules
 -------
 operators  assembly of the SPD operator A for each workload family
-method     relaxation, spectral basis, Galerkin coarse operator, two-grid
+method     relaxation, spectral basis (SVD and randomized range finder),
+           Galerkin coarse operator, two-grid
            preconditioner, PCG
 losses     subspace loss, NLSS loss, Galerkin-convergence objective and
            their gradients
 """
 from .operators import (poisson5, fv_harmonic_2d, fv_harmonic_3d, q1_aniso_element,
                         q1_aniso, jacobi_diag)
-from .method import (relax, spectral_basis, galerkin, two_grid_apply, pcg, PCGResult,
+from .method import (relax, spectral_basis, randomized_basis, galerkin, two_grid_apply, pcg, PCGResult,
                      setup, NOT_CONVERGED, OK, E_BREAKDOWN, E_NONFINITE, E_NOT_SPD,
                      E_INVALID)
 from . import predictor
@@ -34,7 +35,7 @@ from .losses import (subspace_loss, subspace_loss_grad, nlss_loss, nlss_weights,
 __all__ = [
     "predictor",
     "poisson5", "fv_harmonic_2d", "fv_harmonic_3d", "q1_aniso_element", "q1_aniso",
-    "jacobi_diag", "relax", "spectral_basis", "galerkin", "two_grid_apply", "pcg",
+    "jacobi_diag", "relax", "spectral_basis", "randomized_basis", "galerkin", "two_grid_apply", "pcg",
     "PCGResult", "setup", "OK", "NOT_CONVERGED", "E_BREAKDOWN", "E_NONFINITE",
     "E_NOT_SPD", "E_INVALID", "subspace_loss", "subspace_loss_grad", "nlss_loss",
     "nlss_weights", "weighted_energy_loss", "weighted_energy_loss_grad",

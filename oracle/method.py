@@ -33,7 +33,7 @@ from .operators import jacobi_diag
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOT_SPD, E_BREAKDOWN, E_NONFINITE = -1, -2, -3, -4
 
-__all__ = ["relax", "spectral_basis", "galerkin", "two_grid_apply", "pcg", "PCGResult",
+__all__ = ["relax", "spectral_basis", "randomized_basis", "galerkin", "two_grid_apply", "pcg", "PCGResult",
            "setup", "OK", "NOT_CONVERGED", "E_INVALID", "E_NOT_SPD", "E_BREAKDOWN",
            "E_NONFINITE"]
 
@@ -57,6 +57,37 @@ def spectral_basis(S: np.ndarray, k: int):
     descending))."""
     U, sigma, _ = np.linalg.svd(np.asarray(S, dtype=np.float64), full_matrices=False)
     P = np.array(U[:, :k], copy=True)
+    for j in range(k):
+        i = int(np.argmax(np.abs(P[:, j])))
+        if P[i, j] < 0:
+            P[:, j] = -P[:, j]
+    return P, sigma
+
+
+def randomized_basis(S: np.ndarray, k: int, Omega: np.ndarray, q: int = 1):
+    """P = leading k left singular vectors of S estimated by a randomized
+    range finder (the RandomSVD baseline of the experimental setup; the
+    sketching methods of Halko, Martinsson and Tropp 2011, cited in the related
+    work): with a random test matrix Omega (m x l, l >= k, drawn by the caller),
+
+      Y = S Omega,  Q_Y = orth(Y)
+      q times:  Z = S^T Q_Y, Q_Z = orth(Z);  Y = S Q_Z, Q_Y = orth(Y)
+      B = Q_Y^T S (l x m),  B = U_B diag(sigma) V_B^T
+      P = Q_Y U_B[:, :k]
+
+    (randomized subspace iteration, re-orthonormalised after every product,
+    followed by the direct SVD of the small matrix B).  orth is a Householder
+    QR.  Same sign convention as spectral_basis.  Returns (P (n, k), sigma
+    (l,) the singular values of B, descending)."""
+    S = np.asarray(S, dtype=np.float64)
+    Y = S @ np.asarray(Omega, dtype=np.float64)
+    Qy, _ = np.linalg.qr(Y)
+    for _ in range(q):
+        Qz, _ = np.linalg.qr(S.T @ Qy)
+        Qy, _ = np.linalg.qr(S @ Qz)
+    B = Qy.T @ S
+    Ub, sigma, _ = np.linalg.svd(B, full_matrices=False)
+    P = Qy @ Ub[:, :k]
     for j in range(k):
         i = int(np.argmax(np.abs(P[:, j])))
         if P[i, j] < 0:

@@ -111,3 +111,82 @@ def test_not_spd_raises():
     P = np.zeros((16, 2)); P[0, 0] = 1; P[0, 1] = 1      # rank deficient
     with pytest.raises(np.linalg.LinAlgError):
         O.galerkin(A, P)
+
+
+# ------------------------------------------------- randomized range finder
+def _sin_theta(P, U):
+    """sin of the largest principal angle between span(P) and span(U)
+    (both orthonormal)."""
+    return np.linalg.norm(P - U @ (U.T @ P), 2)
+
+
+def test_randomized_basis_exact_on_low_rank():
+    """S of exact rank 10 < l: range(S Omega) = range(S), so the randomized
+    basis is the exact top-k singular subspace and the estimated singular
+    values are the exact ones (library SVD), for any number of power steps."""
+    rng = np.random.default_rng(80)
+    n, m, r, k, l = 300, 40, 10, 6, 12
+    sv = np.array([10.0, 7, 5, 3, 2, 1.5, 0.9, 0.5, 0.2, 0.1])
+    U0, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    V0, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    S = (U0 * sv) @ V0.T
+    Om = rng.standard_normal((m, l))
+    for q in (0, 1, 2):
+        P, sigma = O.randomized_basis(S, k, Om, q)
+        np.testing.assert_allclose(P.T @ P, np.eye(k), atol=1e-13)
+        assert _sin_theta(P, U0[:, :k]) < 1e-10
+        np.testing.assert_allclose(sigma[:r], sv, rtol=1e-10)
+        assert np.all(sigma[r:] < 1e-12 * sv[0])
+
+
+def test_randomized_basis_full_sketch_equals_svd():
+    """l = m with an invertible Omega: range(S Omega) = range(S) for a full
+    rank S, so P spans the exact leading subspace (compared with the oracle's
+    SVD route on a relaxed Poisson sample with a healthy gap at k)."""
+    c = W.Cfg1()
+    A = O.poisson5(c.N)
+    S = O.relax(A, c.S0(), c.omega, c.s1)
+    Pe, se = O.spectral_basis(S, c.k)
+    assert se[c.k - 1] - se[c.k] > 1e-3 * se[0]
+    Om = np.random.default_rng(81).standard_normal((c.m, c.m))
+    P, sigma = O.randomized_basis(S, c.k, Om, 0)
+    assert _sin_theta(P, Pe) < 1e-9
+    np.testing.assert_allclose(sigma, se, rtol=1e-10)
+    # same sign convention: equal columns, not only equal spans
+    np.testing.assert_allclose(P, Pe, atol=1e-8)
+
+
+def test_randomized_basis_depends_only_on_the_sketch_range():
+    """Omega -> Omega G (G invertible l x l) leaves range(S Omega) and hence P
+    unchanged; a transposed or mis-ordered product would not."""
+    rng = np.random.default_rng(82)
+    c = W.Cfg1()
+    A = O.poisson5(c.N)
+    S = O.relax(A, c.S0(), c.omega, c.s1)
+    Om = rng.standard_normal((c.m, 24))
+    G = rng.standard_normal((24, 24)) + 5 * np.eye(24)
+    P1, s1 = O.randomized_basis(S, c.k, Om, 1)
+    P2, s2 = O.randomized_basis(S, c.k, Om @ G, 1)
+    assert _sin_theta(P1, P2) < 1e-9
+    np.testing.assert_allclose(s1, s2, rtol=1e-10)
+
+
+def test_randomized_basis_power_steps_approach_eckart_young():
+    """With a decaying spectrum the projection residual ||S - P P^T S||_F
+    never goes below the Eckart-Young optimum sqrt(sum_{j>k} sigma_j^2), and
+    power steps bring it to that optimum (within 1e-3 relative at q = 4)."""
+    rng = np.random.default_rng(83)
+    n, m, k, l = 400, 60, 8, 14
+    U0, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    V0, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    sv = 0.8 ** np.arange(m)
+    S = (U0 * sv) @ V0.T
+    opt = np.sqrt(np.sum(sv[k:] ** 2))
+    Om = rng.standard_normal((m, l))
+    res = []
+    for q in (0, 1, 2, 4):
+        P, _ = O.randomized_basis(S, k, Om, q)
+        res.append(np.linalg.norm(S - P @ (P.T @ S)))
+    assert all(r >= opt * (1 - 1e-12) for r in res)
+    assert res[0] > res[-1]
+    assert res[-1] <= opt * (1 + 1e-3)

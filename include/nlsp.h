@@ -134,6 +134,34 @@ int setup_spectral_P(const nlsp_operator* A, const double* S0, int m, int k, dou
                      int s1, int prec, double* P, double* sigma, void* ws, size_t ws_bytes,
                      void* stream);
 
+size_t setup_randomized_P_workspace_bytes(const nlsp_operator* A, int m, int k, int l, int prec);
+
+/* Spectral prolongation from a randomized sketch of the relaxed vectors (the
+ * RandomSVD baseline of the experimental setup: randomized range finder with
+ * subspace iteration, Halko, Martinsson and Tropp 2011, cited in the related
+ * work):
+ *   S = (I - w D^-1 A)^{s1} S0                relaxation, as setup_spectral_P
+ *   Y = S Omega, Q_Y = orth(Y)                sketch of the range of S
+ *   q times: Q_Z = orth(S^T Q_Y), Q_Y = orth(S Q_Z)   subspace iteration
+ *   B = Q_Y^T S = U_B diag(sigma) V_B^T        (through B B^T, l x l)
+ *   P = CholeskyQR2(Q_Y U_B[:, :k])           signs as setup_spectral_P
+ * orth is CholeskyQR2 in float64.  The eigenproblem is l x l instead of m x m.
+ *   S0     device (n, m) float64, read only
+ *   Omega  device (m, l) float64, read only: the random test matrix (drawn by
+ *          the caller, e.g. N(0, 1) entries)
+ *   m, k, l  1 <= k <= l <= m <= 256, m <= n
+ *   q      subspace-iteration steps, 0 <= q <= 8
+ *   omega, s1, prec   as setup_spectral_P
+ *   P      device (n, k) float64, output, P^T P = I
+ *   sigma  device (l,) float64, output: singular values of B, descending
+ *          (estimates of the leading singular values of S)
+ * Synchronises `stream`; returns NLSP_E_RANK when a sketch is numerically of
+ * rank < l or sigma_k <= 1e-6 sigma_1, NLSP_E_NOT_SPD when the final
+ * orthonormalisation fails. */
+int setup_randomized_P(const nlsp_operator* A, const double* S0, int m, int k, double omega,
+                       int s1, const double* Omega, int l, int q, int prec, double* P,
+                       double* sigma, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------- setup: coarse */
 size_t galerkin_coarse_workspace_bytes(const nlsp_operator* A, int k);
 

@@ -59,6 +59,9 @@ SIGNATURES = {
     "setup_spectral_P_workspace_bytes": (c_size_t, [POP, c_int, c_int, c_int]),
     "setup_spectral_P": (c_int, [POP, c_void_p, c_int, c_int, c_double, c_int, c_int, c_void_p,
                                  c_void_p, c_void_p, c_size_t, c_void_p]),
+    "setup_randomized_P_workspace_bytes": (c_size_t, [POP, c_int, c_int, c_int, c_int]),
+    "setup_randomized_P": (c_int, [POP, c_void_p, c_int, c_int, c_double, c_int, c_void_p, c_int, c_int,
+                                   c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "galerkin_coarse_workspace_bytes": (c_size_t, [POP, c_int]),
     "galerkin_coarse": (c_int, [POP, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),

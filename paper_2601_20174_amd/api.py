@@ -175,6 +175,34 @@ def setup_spectral_P(op: Operator, S0: torch.Tensor, k: int, omega: float, s1: i
     return P, sigma
 
 
+def setup_randomized_P_workspace_bytes(op: Operator, m: int, k: int, l: int, prec: int) -> int:
+    return int(_L().setup_randomized_P_workspace_bytes(ctypes.byref(op.c()), m, k, l, prec))
+
+
+def setup_randomized_P(op: Operator, S0: torch.Tensor, k: int, omega: float, s1: int, Omega: torch.Tensor,
+                       q: int = 1, prec: int = FP64, workspace: Optional[torch.Tensor] = None):
+    """Randomized-sketch basis; Omega (m, l) float64 is the caller's random
+    test matrix.  Returns (P (n,k) float64, sigma (l,) float64)."""
+    if S0.dim() != 2 or Omega.dim() != 2:
+        raise ValueError("S0 must be (n, m) and Omega (m, l)")
+    n, m = S0.shape
+    _rows(S0, _op_checked(op).n, "S0", m)
+    _rows(Omega, m, "Omega")
+    l = Omega.shape[1]
+    P = torch.empty((n, k), dtype=torch.float64, device=S0.device)
+    sigma = torch.empty((l,), dtype=torch.float64, device=S0.device)
+    nb = setup_randomized_P_workspace_bytes(op, m, k, l, prec)
+    if nb == 0:
+        raise NlspError("setup_randomized_P_workspace_bytes", E_INVALID)
+    ws = workspace if workspace is not None else _workspace(nb, S0.device)
+    rc = _L().setup_randomized_P(ctypes.byref(op.c()), _dev(S0, torch.float64, "S0"), m, k, float(omega),
+                                 int(s1), _dev(Omega, torch.float64, "Omega"), l, int(q), int(prec),
+                                 _dev(P, torch.float64, "P"), _dev(sigma, torch.float64, "sigma"),
+                                 ws.data_ptr(), ws.numel(), _stream())
+    _check("setup_randomized_P", rc)
+    return P, sigma
+
+
 @dataclasses.dataclass
 class TwoLevel:
     """The solver's coarse-space factors (nlsp_two_level) and A_c, L."""

@@ -567,7 +567,8 @@ __global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ 
 }
 
 // Sort eigenpairs descending; sigma = sqrt(max(lambda, 0)); T = V_k diag(lambda_k^-1/2)
-// (m x k, padded columns zero); info[0] = 1 if lambda_k <= (1e-6 sigma_1)^2.
+// (m x k, padded columns zero; with `unscaled`, T = V_k); info[0] = 1 if
+// lambda_k <= (1e-6 sigma_1)^2.
 // The Gram route resolves singular values only down to about sqrt(eps) sigma_1
 // (the eigenvalues of G = S^T S carry rounding of order m eps lambda_1), so a
 // sigma_k below 1e-6 sigma_1 cannot be told apart from zero: S is then
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ 
 __global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G,
                                                     const double* __restrict__ V, int m, int mreal,
                                                     int k, int kpad, double* __restrict__ sigma,
-                                                    double* __restrict__ T, int* info) {
+                                                    double* __restrict__ T, int* info, int unscaled) {
   __shared__ int order[256];
   __shared__ double lam[256];
   const int t = threadIdx.x;
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G
     double v = 0.0;
     if (j < k) {
       const double l = lam[order[j]];
-      v = (l > 0) ? V[r * m + order[j]] / sqrt(l) : 0.0;
+      v = unscaled ? V[r * m + order[j]] : ((l > 0) ? V[r * m + order[j]] / sqrt(l) : 0.0);
     }
     T[idx] = v;
   }
@@ -615,10 +616,12 @@ __global__ __launch_bounds__(256) void k_eig_finish(const double* __restrict__ G
 
 // Cholesky G = L L^T of an SPD k x k matrix (right-looking, one workgroup);
 // L lower (upper part zero).  Working copy in LDS when LDS = true (k <= 128).
-// info[0] = 1 if a pivot is not positive.
+// info[0] = 1 if a pivot is not above rtol times its original diagonal entry
+// (rtol = 0: not positive; for a Gram matrix X^T X, rtol > 0 flags a column
+// of X that is numerically a combination of the earlier ones).
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ G, int ldg, int k,
-                                                   double* __restrict__ Lg, int ldl, int* info) {
+                                                   double* __restrict__ Lg, int ldl, int* info, double rtol) {
   extern __shared__ double dyn[];
   __shared__ double piv;
   __shared__ int bad;
@@ -634,7 +637,7 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ G,
   for (int j = 0; j < k; ++j) {
     if (t == 0) {
       const double d = L[j * ld + j];
-      if (!(d > 0.0)) bad = 1;
+      if (!(d > 0.0) || !(d > rtol * G[j * ldg + j])) bad = 1;
       piv = (d > 0.0) ? sqrt(d) : 1.0;
       L[j * ld + j] = piv;
     }
@@ -935,14 +938,14 @@ static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, do
 }
 
 static int launch_chol(const double* G, int ldg, int k, double* L, int ldl, int* info,
-                       hipStream_t s) {
+                       hipStream_t s, double rtol = 0.0) {
   if (k <= LDS_DENSE_MAX) {
     const size_t sh = sizeof(double) * k * k;
     NLSP_HIP(hipFuncSetAttribute((const void*)k_cholesky<true>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(1024), sh, s, G, ldg, k, L, ldl, info);
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(1024), sh, s, G, ldg, k, L, ldl, info, rtol);
   } else {
-    hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(1024), 0, s, G, ldg, k, L, ldl, info);
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(1024), 0, s, G, ldg, k, L, ldl, info, rtol);
   }
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;
@@ -1057,6 +1060,39 @@ inline SetupLayout carve_setup(void* ws, int64_t n, int m, int k, int prec) {
   return L;
 }
 
+// CholeskyQR2 in float64 of the (rows, cq) matrix in Pa whose columns past kr
+// are zero: twice G = X^T X, G = L L^T, X <- X L^-T.  On return Pa holds the
+// orthonormal factor (the two buffers are swapped as the passes alternate).
+// info[0], info[1]: a Cholesky pivot of pass 1, 2 not above rtol times its
+// diagonal entry (see k_cholesky).  Uses the layout's part, G, Lk, T and Rinv
+// (sized for cq).
+static int cholqr2(double*& Pa, double*& Pb, int64_t rows, int cq, int kr, const SetupLayout& L, int* info,
+                   hipStream_t s, double rtol = 0.0) {
+  for (int pass = 0; pass < 2; ++pass) {
+    int rc = gram<double>(Pa, Pa, rows, cq, cq, 1, L.part, L.G, cq, s);
+    if (rc) return rc;
+    rc = launch_chol(L.G, cq, kr, L.Lk, cq, info + pass, s, rtol);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L.Lk, cq, kr, L.T, cq);
+    hipLaunchKernelGGL(k_transpose_pad, dim3(ceil_div(cq * cq, 256)), dim3(256), 0, s, L.T, cq, L.Rinv);
+    tsgemm<double>(Pa, rows, cq, L.Rinv, cq, Pb, cq, cq, s);
+    std::swap(Pa, Pb);
+  }
+  return NLSP_OK;
+}
+
+// Pout (n, k) = the first k columns of X (n, ld), each column signed so that
+// its entry of largest magnitude is positive (lowest row on ties).
+static void signed_columns(const double* X, int64_t n, int ld, int k, const SetupLayout& L, double* Pout,
+                           hipStream_t s) {
+  const int64_t rows_per = (n + CS_BLOCKS - 1) / CS_BLOCKS;
+  const int nblk = (int)((n + rows_per - 1) / rows_per);
+  hipLaunchKernelGGL(k_colmax_partial, dim3(nblk), dim3(256), 0, s, X, n, ld, rows_per, L.cmax, L.cidx);
+  hipLaunchKernelGGL(k_colsign_finish, dim3(1), dim3(256), 0, s, X, ld, k, nblk, L.cmax, L.cidx, L.csign);
+  hipLaunchKernelGGL(k_copy_cols_signed, dim3(ceil_div(n * k, 256)), dim3(256), 0, s, X, ld, n, k, L.csign,
+                     Pout, k);
+}
+
 // Copies S0 (n, m) float64 into the padded (n, mp) buffer of element type T.
 template <typename T>
 __global__ void k_load_S0(const double* __restrict__ S0, int64_t n, int m, int mp, T* __restrict__ S) {
@@ -1085,37 +1121,137 @@ static int setup_impl(const OpDev& op, const double* S0, int m, int k, double om
   rc = launch_eig(L.G, L.V, mp, L.rot, L.nsweeps, L.off, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_eig_finish, dim3(1), dim3(256), 0, s, L.G, L.V, mp, m, k, kq, sigma, L.T,
-                     L.info);
+                     L.info, 0);
   // P0 = S T
   tsgemm<T>(Sa, n, mp, L.T, kq, L.P0, kq, kq, s);
   // CholeskyQR2 in float64
   double* Pa = L.P0;
   double* Pb = L.P1;
-  for (int pass = 0; pass < 2; ++pass) {
-    rc = gram<double>(Pa, Pa, n, kq, kq, 1, L.part, L.G, kq, s);
-    if (rc) return rc;
-    rc = launch_chol(L.G, kq, k, L.Lk, kq, L.info + 1 + pass, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L.Lk, kq, k, L.T, kq);
-    hipLaunchKernelGGL(k_transpose_pad, dim3(ceil_div(kq * kq, 256)), dim3(256), 0, s, L.T, kq,
-                       L.Rinv);
-    tsgemm<double>(Pa, n, kq, L.Rinv, kq, Pb, kq, kq, s);
-    std::swap(Pa, Pb);
-  }
-  {
-    const int64_t rows_per = (n + CS_BLOCKS - 1) / CS_BLOCKS;
-    const int nblk = (int)((n + rows_per - 1) / rows_per);
-    hipLaunchKernelGGL(k_colmax_partial, dim3(nblk), dim3(256), 0, s, Pa, n, kq, rows_per, L.cmax, L.cidx);
-    hipLaunchKernelGGL(k_colsign_finish, dim3(1), dim3(256), 0, s, Pa, kq, k, nblk, L.cmax, L.cidx, L.csign);
-    hipLaunchKernelGGL(k_copy_cols_signed, dim3(ceil_div(n * k, 256)), dim3(256), 0, s, Pa, kq, n, k, L.csign,
-                       Pout, k);
-  }
+  rc = cholqr2(Pa, Pb, n, kq, k, L, L.info + 1, s);
+  if (rc) return rc;
+  signed_columns(Pa, n, kq, k, L, Pout, s);
   NLSP_HIP(hipGetLastError());
   int hinfo[4] = {0, 0, 0, 0};
   NLSP_HIP(hipMemcpyAsync(hinfo, L.info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   NLSP_HIP(hipStreamSynchronize(s));
   if (hinfo[1] || hinfo[2]) return NLSP_E_NOT_SPD;
   if (hinfo[0]) return NLSP_E_RANK;
+  return NLSP_OK;
+}
+
+// ------------------------------------------- randomized range finder
+// Basis from a sketch of S (randomized subspace iteration followed by the
+// direct SVD of the small projected matrix), with a caller-drawn test matrix
+// Omega (m x l):
+//   Y = S Omega, Q_Y = orth(Y);  q times: Q_Z = orth(S^T Q_Y), Q_Y = orth(S Q_Z)
+//   C = S^T Q_Y (= B^T, B = Q_Y^T S);  C^T C = B B^T = U_B diag(sigma^2) U_B^T
+//   P0 = Q_Y U_B[:, :k], P = CholeskyQR2(P0), column signs as setup_spectral_P.
+// orth is CholeskyQR2 in float64.  The eigenproblem is l x l instead of m x m.
+struct RandLayout {
+  SetupLayout base;   // carved with k -> l: P0/P1 (n, lq), T (mp, lq), Rinv/Lk (lq, lq)
+  double* Om;         // (mp, lq) padded test matrix
+  double* C;          // (mp, lq) S^T Q_Y
+  double* Cb;         // (mp, lq) its orthonormal factor's ping buffer
+  float* QY32;        // (n, lq) float copy of Q_Y (mixed form)
+  int* info;          // 64 Cholesky / rank flags
+  size_t bytes;
+};
+
+inline RandLayout carve_rand(void* ws, int64_t n, int m, int l, int prec) {
+  RandLayout R;
+  R.base = carve_setup(ws, n, m, l, prec);
+  const int mp = pad16(m) + (pad16(m) % 2), lq = pad16(l);
+  Carver cv(ws);
+  cv.off = R.base.bytes;
+  R.Om = cv.take<double>((size_t)mp * lq);
+  R.C = cv.take<double>((size_t)mp * lq);
+  R.Cb = cv.take<double>((size_t)mp * lq);
+  R.QY32 = cv.take<float>(prec == NLSP_MIXED ? (size_t)n * lq : 1);
+  R.info = cv.take<int>(64);
+  R.bytes = cv.bytes();
+  return R;
+}
+
+// S^T Q_Y (mp x lq) into C; the float form multiplies a float copy of Q_Y.
+template <typename T>
+static int sketch_cross(const T* S, const double* QY, int64_t n, int mp, int lq, const RandLayout& R,
+                        hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    hipLaunchKernelGGL(k_to_f32, dim3(ceil_div(n * lq, 256)), dim3(256), 0, s, QY, R.QY32, n * lq);
+    return gram<float>(S, R.QY32, n, mp, lq, 0, R.base.part, R.C, lq, s);
+  } else {
+    return gram<double>(S, QY, n, mp, lq, 0, R.base.part, R.C, lq, s);
+  }
+}
+
+// A sketch column whose residual after the earlier columns is below 1e-6 of
+// its norm (pivot^2 <= 1e-12 times the diagonal of the Gram matrix) makes the
+// sketch numerically rank-deficient, the same threshold as the rank test on
+// sigma_k / sigma_1.
+constexpr double kSketchRankTol = 1e-12;
+
+template <typename T>
+static int randomized_impl(const OpDev& op, const double* S0, int m, int k, double omega, int s1,
+                           const double* Omega, int l, int q, double* Pout, double* sigma, const RandLayout& R,
+                           hipStream_t s) {
+  const SetupLayout& L = R.base;
+  const int64_t n = op.n;
+  const int mp = pad16(m) + (pad16(m) % 2), kq = pad16(k), lq = pad16(l);
+  T* Sa = static_cast<T*>(L.S0buf);
+  T* Sb = static_cast<T*>(L.S1buf);
+  hipLaunchKernelGGL(k_load_S0<T>, dim3(ceil_div(n * mp, 256)), dim3(256), 0, s, S0, n, m, mp, Sa);
+  for (int it = 0; it < s1; ++it) {
+    launch_cols<T>(op, mp, omega, 0, Sa, Sb, s);
+    std::swap(Sa, Sb);
+  }
+  NLSP_HIP(hipMemsetAsync(R.Om, 0, sizeof(double) * mp * lq, s));
+  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div((int64_t)m * lq, 256)), dim3(256), 0, s, Omega, l, (int64_t)m, l,
+                     R.Om, lq);
+  // Y = S Omega, Q_Y = orth(Y)
+  double* Ya = L.P0;
+  double* Yb = L.P1;
+  int slot = 1;
+  tsgemm<T>(Sa, n, mp, R.Om, lq, Ya, lq, lq, s);
+  int rc = cholqr2(Ya, Yb, n, lq, l, L, R.info + slot, s, kSketchRankTol);
+  slot += 2;
+  if (rc) return rc;
+  for (int it = 0; it < q; ++it) {
+    // Q_Z = orth(S^T Q_Y) (mp x lq, in C / Cb), then Q_Y = orth(S Q_Z)
+    rc = sketch_cross<T>(Sa, Ya, n, mp, lq, R, s);
+    if (rc) return rc;
+    double* Ca = R.C;
+    double* Cb = R.Cb;
+    rc = cholqr2(Ca, Cb, mp, lq, l, L, R.info + slot, s, kSketchRankTol);
+    slot += 2;
+    if (rc) return rc;
+    tsgemm<T>(Sa, n, mp, Ca, lq, Ya, lq, lq, s);
+    rc = cholqr2(Ya, Yb, n, lq, l, L, R.info + slot, s, kSketchRankTol);
+    slot += 2;
+    if (rc) return rc;
+  }
+  // C = S^T Q_Y; C^T C = B B^T and its eigenpairs (l x l)
+  rc = sketch_cross<T>(Sa, Ya, n, mp, lq, R, s);
+  if (rc) return rc;
+  rc = gram<double>(R.C, R.C, mp, lq, lq, 1, L.part, L.G, lq, s);
+  if (rc) return rc;
+  rc = launch_eig(L.G, L.V, lq, L.rot, L.nsweeps, L.off, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_eig_finish, dim3(1), dim3(256), 0, s, L.G, L.V, lq, l, k, kq, sigma, L.T, R.info, 1);
+  // P0 = Q_Y U_B[:, :k] (into the free buffer), CholeskyQR2, signs
+  tsgemm<double>(Ya, n, lq, L.T, kq, Yb, kq, kq, s);
+  double* Pa = Yb;
+  double* Pb = Ya;
+  rc = cholqr2(Pa, Pb, n, kq, k, L, R.info + slot, s);
+  if (rc) return rc;
+  signed_columns(Pa, n, kq, k, L, Pout, s);
+  NLSP_HIP(hipGetLastError());
+  int hinfo[64] = {};
+  NLSP_HIP(hipMemcpyAsync(hinfo, R.info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  NLSP_HIP(hipStreamSynchronize(s));
+  if (hinfo[slot] || hinfo[slot + 1]) return NLSP_E_NOT_SPD;
+  // a sketch that is not of full rank l, or sigma_k lost in rounding
+  for (int i = 0; i < slot; ++i)
+    if (hinfo[i]) return NLSP_E_RANK;
   return NLSP_OK;
 }
 
@@ -1172,6 +1308,29 @@ int setup_spectral_P(const nlsp_operator* A, const double* S0, int m, int k, dou
   NLSP_HIP(hipMemsetAsync(L.info, 0, sizeof(int) * 4, s));
   if (prec == NLSP_FP64) return setup_impl<double>(op, S0, m, k, omega, s1, P, sigma, L, s);
   return setup_impl<float>(op, S0, m, k, omega, s1, P, sigma, L, s);
+}
+
+size_t setup_randomized_P_workspace_bytes(const nlsp_operator* A, int m, int k, int l, int prec) {
+  const int64_t n = op_size(A);
+  if (n < 1 || k < 1 || l < k || m < l || m > 256 || (prec != NLSP_FP64 && prec != NLSP_MIXED)) return 0;
+  return carve_rand(nullptr, n, m, l, prec).bytes;
+}
+
+int setup_randomized_P(const nlsp_operator* A, const double* S0, int m, int k, double omega, int s1,
+                       const double* Omega, int l, int q, int prec, double* P, double* sigma, void* ws,
+                       size_t ws_bytes, void* stream) {
+  const int64_t n = op_size(A);
+  if (n < 1 || !S0 || !Omega || !P || !sigma) return NLSP_E_INVALID;
+  if (k < 1 || l < k || m < l || m > 256 || (int64_t)m > n || s1 < 0 || !(omega > 0)) return NLSP_E_INVALID;
+  if (q < 0 || q > 8 || (prec != NLSP_FP64 && prec != NLSP_MIXED)) return NLSP_E_INVALID;
+  const size_t need = carve_rand(nullptr, n, m, l, prec).bytes;
+  if (!ws_ok(ws, ws_bytes, need)) return NLSP_E_WORKSPACE;
+  const RandLayout R = carve_rand(ws, n, m, l, prec);
+  const OpDev op = make_op(*A);
+  hipStream_t s = as_stream(stream);
+  NLSP_HIP(hipMemsetAsync(R.info, 0, sizeof(int) * 64, s));
+  if (prec == NLSP_FP64) return randomized_impl<double>(op, S0, m, k, omega, s1, Omega, l, q, P, sigma, R, s);
+  return randomized_impl<float>(op, S0, m, k, omega, s1, Omega, l, q, P, sigma, R, s);
 }
 
 size_t galerkin_coarse_workspace_bytes(const nlsp_operator* A, int k) {

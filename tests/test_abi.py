@@ -158,6 +158,20 @@ def test_validation_rejects_before_any_gpu_call(lib):
     assert lib.setup_spectral_P(op, fake, 8, 16, 2 / 3, 10, api.FP64, fake, sig, None, 0, None) == E_INV
     assert lib.setup_spectral_P(op, fake, 32, 16, -1.0, 10, api.FP64, fake, sig, None, 0, None) == E_INV
     assert lib.setup_spectral_P(op, fake, 32, 16, 2 / 3, 10, api.FP64, fake, sig, None, 0, None) == E_WS
+    # randomized sketch: k <= l <= m, 0 <= q <= 8
+    assert lib.setup_randomized_P(op, fake, 32, 16, 2 / 3, 10, fake, 12, 1, api.FP64, fake, sig, None, 0,
+                                  None) == E_INV
+    assert lib.setup_randomized_P(op, fake, 32, 16, 2 / 3, 10, fake, 40, 1, api.FP64, fake, sig, None, 0,
+                                  None) == E_INV
+    assert lib.setup_randomized_P(op, fake, 32, 16, 2 / 3, 10, fake, 24, 9, api.FP64, fake, sig, None, 0,
+                                  None) == E_INV
+    assert lib.setup_randomized_P(op, fake, 32, 16, 2 / 3, 10, None, 24, 1, api.FP64, fake, sig, None, 0,
+                                  None) == E_INV
+    assert lib.setup_randomized_P(op, fake, 32, 16, 2 / 3, 10, fake, 24, 1, api.FP64, fake, sig, None, 0,
+                                  None) == E_WS
+    assert lib.setup_randomized_P_workspace_bytes(op, 32, 16, 12, api.FP64) == 0
+    assert lib.setup_randomized_P_workspace_bytes(op, 32, 16, 24, api.MIXED) > \
+        lib.setup_randomized_P_workspace_bytes(op, 32, 16, 24, api.FP64) // 2
     assert lib.galerkin_coarse(op, fake, 16, 2 / 3, 0, fake, fake, fake, fake, None, None, 0, None) == E_INV
     assert lib.galerkin_coarse(op, fake, 16, 2 / 3, 1, fake, fake, fake, None, None, None, 0, None) == E_INV
     assert lib.galerkin_coarse(op, fake, 16, 2 / 3, 1, fake, fake, fake, fake, None, None, 0, None) == E_WS

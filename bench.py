@@ -66,16 +66,17 @@ def copy_calibration(mib: int):
                                            "launches": 3}}), flush=True)
 
 
-def solver_bytes_per_row(phase: int, kp: int, R: int = 1) -> float:
+def solver_bytes_per_row(phase: int, kp: int, R: int = 1, qbytes: int = 4) -> float:
     """Algorithmic HBM bytes per grid row of one launch of a solver kernel,
-    mixed form, float64 cell coefficient, each array counted once:
-      update (1): read z, p, w, q_old, x, r, a, D^-1 (f32), Q32;
-                  write p, q, x, r_new, z  -> 11 x 8 R + 8 + 4 + 4 kp
-      matvec (2): read z, p, q, a, Qt32; write w  -> 4 x 8 R + 8 + 4 kp
+    mixed form, float64 cell coefficient, each array counted once (qbytes:
+    bytes per stored basis element, 4 for float32, 2 for float16):
+      update (1): read z, p, w, q_old, x, r, a, D^-1 (f32), Q;
+                  write p, q, x, r_new, z  -> 11 x 8 R + 8 + 4 + qbytes kp
+      matvec (2): read z, p, q, a, Qt; write w  -> 4 x 8 R + 8 + qbytes kp
     """
     if phase == 1:
-        return 88.0 * R + 12.0 + 4.0 * kp
-    return 32.0 * R + 8.0 + 4.0 * kp
+        return 88.0 * R + 12.0 + qbytes * kp
+    return 32.0 * R + 8.0 + qbytes * kp
 
 
 def main():
@@ -115,8 +116,8 @@ def main():
     def step(prec, timing=None):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        P, sigma = nl.setup_spectral_P(op, S0, k, c.omega, c.s1, prec, workspace=ws_setup)
-        M = nl.galerkin_coarse(op, P, c.omega, c.nu, q64=(prec == nl.FP64), q32=(prec == nl.MIXED),
+        P, sigma = nl.setup_spectral_P(op, S0, k, c.omega, c.s1, min(prec, nl.MIXED), workspace=ws_setup)
+        M = nl.galerkin_coarse(op, P, c.omega, c.nu, q64=(prec == nl.FP64), q32=(prec != nl.FP64),
                                workspace=ws_gal)
         e1.record()
         u, info, rc = nl.pcg_solve(op, M, f, prec=prec, rtol=c.rtol, workspace=ws_pcg, timing=timing)
@@ -189,6 +190,7 @@ def main():
         s64, p64, inf64 = step(nl.FP64)
         out["fp64"] = {"setup_ms": round(s64, 4), "solve_ms": round(p64, 4), "iters": inf64.iters,
                        "relres": inf64.relres}
+        out["mixed_f16"] = f16_leg(step, nl, n, kp)
         out["spmv"] = spmv_legs(nl, torch, dev)
         out["solve3d"] = solve3d_leg(nl, torch, dev)
         out["training"] = training_legs(nl, torch, dev)
@@ -198,6 +200,26 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, coef, S0h, fh, out.get("fp64", {}).get("iters", out["iters"]))
     print(json.dumps(out), flush=True)
+
+
+def f16_leg(step, nl, n, kp, reps=3):
+    """The headline workload with the float16 basis (Q and Q A_c^-1 stored in
+    float16, scaled by powers of two; products and sums as the mixed form):
+    median solve over `reps`, and the update kernel's event-timed launches
+    against its algorithmic bytes (2 bytes per basis element)."""
+    step(nl.MIXED_F16)
+    runs = [step(nl.MIXED_F16) for _ in range(reps)]
+    tm = {"phase": 1, "every": 8}
+    step(nl.MIXED_F16, tm)
+    launch_ms = tm["total_ms"] / max(1, tm["launches"])
+    bl = solver_bytes_per_row(1, kp, 1, 2) * n
+    ach = bl / (launch_ms * 1e-3) / 1e9
+    return {"solve_ms": round(statistics.median(r[1] for r in runs), 4),
+            "iters": int(statistics.median(r[2].iters for r in runs)),
+            "relres": max(r[2].relres for r in runs),
+            "update_kernel": {"kernel": "nlsp::k_update<_Float16, false>", "launch_us": round(launch_ms * 1e3, 3),
+                              "bytes_per_launch": int(bl), "achieved": round(ach, 1),
+                              "frac": round(ach / HBM_PEAK_GBS, 4)}}
 
 
 def _time_ms(torch, fn, reps=20, warm=3):

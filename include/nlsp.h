@@ -98,9 +98,19 @@ int jacobi_sweep_f32(const nlsp_operator* A, double omega, const float* b, const
 /* --------------------------------------------------------------- precision */
 enum nlsp_precision {
   NLSP_FP64 = 0,     /* everything in float64 */
-  NLSP_MIXED = 1     /* relaxation, smoother and P/Q products in float32; PCG
+  NLSP_MIXED = 1,    /* relaxation, smoother and P/Q products in float32; PCG
                         recurrences, dot products, reductions, Cholesky and the
                         orthonormalisation of P in float64 */
+  NLSP_MIXED_F16 = 2 /* pcg_solve only: as NLSP_MIXED, with the coarse term
+                        Q A_c^-1 Q^T applied as W W^T, W = Q L^-T, and W
+                        stored once in float16, scaled by a power of two so
+                        its largest entry is just below 1 (formed from Q32 and
+                        L^-1 once per solve; products and sums as
+                        NLSP_MIXED).  One rounded matrix serves restriction
+                        and prolongation, so the preconditioner stays
+                        symmetric.  Halves the basis traffic, the largest part
+                        of an iteration's bytes (the paper's rank control as a
+                        bandwidth control, Sec. 4) */
 };
 
 /* ------------------------------------------------------------ setup: P */
@@ -191,7 +201,7 @@ typedef struct {
   int k;                 /* coarse rank (k >= 1) */
   int nu;                /* smoothing sweeps, nu1 = nu2 = nu >= 1 */
   double omega;          /* Jacobi damping used to build Q */
-  int prec;              /* NLSP_FP64 reads Q64, NLSP_MIXED reads Q32 */
+  int prec;              /* NLSP_FP64 reads Q64, NLSP_MIXED and NLSP_MIXED_F16 read Q32 */
   const double* Linv;    /* device (kp, kp) from galerkin_coarse */
   const double* Q64;     /* device (n, kp) or NULL */
   const float* Q32;      /* device (n, kp) or NULL */

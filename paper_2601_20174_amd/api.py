@@ -17,7 +17,7 @@ from . import _lib
 
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOT_SPD, E_BREAKDOWN, E_NONFINITE, E_WORKSPACE, E_HIP, E_RANK = -1, -2, -3, -4, -5, -6, -7
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_F16 = 0, 1, 2
 OP_POISSON5, OP_FV5, OP_FV7, OP_STENCIL9 = 0, 1, 2, 3
 
 
@@ -329,7 +329,7 @@ def pcg_solve(op: Operator, M: TwoLevel, f: torch.Tensor, u: Optional[torch.Tens
         _rows(u, op.n, "u", R)
         u = u.reshape(f2.shape)
     if flexible is None:
-        flexible = prec == MIXED
+        flexible = prec != FP64
     nb = pcg_solve_workspace_bytes(op, M.k, R)
     if nb == 0:
         raise NlspError("pcg_solve_workspace_bytes", E_INVALID)
@@ -366,7 +366,7 @@ def pcg_solve_noalloc(op: Operator, M: TwoLevel, f: torch.Tensor, u: torch.Tenso
     _rows(u, op.n, "u", R)
     _two_level_checked(M, op.n, prec)
     if flexible is None:
-        flexible = prec == MIXED
+        flexible = prec != FP64
     opts = _lib.NlspPcgOpts(float(rtol), int(maxit), 1 if flexible else 0, int(check_every), None)
     info = (_lib.NlspRhsInfo * R)()
     Mc = M.c(prec)
@@ -636,7 +636,7 @@ def pcg_solve_batched(systems: List[System], prec: int = MIXED, rtol: float = 1e
     """Solves every system in place (s.u); returns ([[RhsInfo] per system], status)."""
     arr, R = _systems(systems, prec)
     if flexible is None:
-        flexible = prec == MIXED
+        flexible = prec != FP64
     nb = _L().pcg_solve_batched_workspace_bytes(len(systems), arr, R, int(rows_per_block))
     if nb == 0:
         raise NlspError("pcg_solve_batched_workspace_bytes", E_INVALID)
@@ -657,7 +657,7 @@ def pcg_solve_batched_tune(systems: List[System], prec: int = MIXED, rtol: float
     returns (best rows_per_block, {rows_per_block: ms})."""
     arr, R = _systems(systems, prec)
     if flexible is None:
-        flexible = prec == MIXED
+        flexible = prec != FP64
     ncand = _L().pcg_solve_batched_tune_candidates(R, None)
     cand = (ctypes.c_int * ncand)()
     _L().pcg_solve_batched_tune_candidates(R, cand)

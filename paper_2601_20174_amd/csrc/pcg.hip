@@ -72,8 +72,14 @@ struct SysDev {
   int rw;                  // restriction record width: kp*R + 2R
   int gw;                  // group record width: rw + 4R (the update partials ride along)
   // device pointers (global address space in the device pass)
-  Glob<const void>* Q;     // (n, kp), float or double: prolongation
+  Glob<const void>* Q;     // (n, kp), float, double or float16: prolongation
   Glob<const void>* Qt;    // (n, kp) Q A_c^-1, same type: restriction to coarse coefficients
+  // float16 basis (Q and Qt both point to W s, W = Q L^-T, see run_pcg):
+  // [1 / s, 1 / s], the inverse power-of-two scale folded into c before the
+  // prolongation and into the restriction sums; the float32 Q that W is
+  // formed from (host use only)
+  Glob<const double>* qscale;
+  const void* qsrc;
   Glob<const double>* Linv;  // (kp, kp) inverse Cholesky factor of A_c
   Glob<double>* Ainv;      // (kp, kp) = L^-T L^-1
   Glob<const double>* f;
@@ -83,7 +89,7 @@ struct SysDev {
   Glob<double>* q[2];      // A p, by iteration parity
   Glob<double>* z;         // preconditioned residual (updated in place)
   Glob<double>* w;         // A z
-  Glob<void>* wj[2];       // J_{2nu} r work buffers (nu > 1), element type of Q
+  Glob<void>* wj[2];       // J_{2nu} r work buffers (nu > 1), arithmetic type of Q
   Glob<double>* dinv;
   Glob<float>* dinv32;
   Glob<double>* bpart[2];  // [nblk][4R]  update partials [r^T z | r^T z_old | ||r||^2 | p^T q], by parity
@@ -118,6 +124,21 @@ struct Vec4<float> {
 template <>
 struct Vec4<double> {
   using type = double4;
+};
+
+template <>
+struct Vec4<_Float16> {
+  using type = _Float16 __attribute__((ext_vector_type(4)));
+};
+
+// Arithmetic type of a stored basis element: a float16 basis is used in float.
+template <typename QS>
+struct Arith {
+  using type = QS;
+};
+template <>
+struct Arith<_Float16> {
+  using type = float;
 };
 
 template <typename QT>
@@ -301,10 +322,20 @@ NLSP_DEV QMap q_map(int kp, int R) {
 // rows handled by a thread in a chunk of nrows rows (uniform over the workgroup)
 NLSP_DEV int q_trips(const QMap& m, int nrows) { return (nrows + m.ngr - 1) / m.ngr; }
 
-// NB rows of Q for one thread, issued together so their latencies overlap
+// NB rows of Q for one thread, issued together so their latencies overlap.
+// get() converts an element to the arithmetic type where it is used, so a
+// float16 row stays packed (two registers) until then.
 template <typename QT, int NB>
 struct QBatch {
   QT v[NB][4];
+  NLSP_DEV void load(int w, const QT* p) { load4(p, v[w]); }
+  NLSP_DEV QT get(int w, int u) const { return v[w][u]; }
+};
+template <int NB>
+struct QBatch<_Float16, NB> {
+  typename Vec4<_Float16>::type v[NB];
+  NLSP_DEV void load(int w, const _Float16* p) { v[w] = *reinterpret_cast<const typename Vec4<_Float16>::type*>(p); }
+  NLSP_DEV float get(int w, int u) const { return (float)v[w][u]; }
 };
 
 // Rows past the chunk (and idle row groups) load a clamped row instead of
@@ -316,7 +347,7 @@ NLSP_DEV void q_fetch(const QT* __restrict__ Q, int64_t row0, int nrows, int kp,
 #pragma unroll
   for (int w = 0; w < NB; ++w) {
     const int row = min(m.rg + (w0 + w) * m.ngr, nrows - 1);
-    load4(Q + (row0 + row) * kp + 4 * m.jc, b.v[w]);
+    b.load(w, Q + (row0 + row) * kp + 4 * m.jc);
   }
 }
 
@@ -345,7 +376,7 @@ NLSP_DEV void restrict_rows(const QT* __restrict__ Q, int64_t row0, int nrows, i
       if (m.on && row < nrows) {
         const double r = rv[row * R + m.c];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += prod<QT>(b.v[w][u], r);
+        for (int u = 0; u < 4; ++u) acc[u] += prod<typename Arith<QT>::type>(b.get(w, u), r);
       }
     }
   }
@@ -428,19 +459,20 @@ NLSP_DEV void restrict_finish_x2(const QMap& m, int kp, int R, const double (&ac
 }
 
 // ys[row*R + c] = sum_j Q[row][j] e[j][c] for the chunk rows (prolongation),
-// arithmetic in QT; the lpr lanes of a row add with butterflies.  All lanes
-// run the same trip count (shuffles need the whole wave).
-template <typename QT, int NB>
-NLSP_DEV void prolong_rows(const QT* __restrict__ Q, int64_t row0, int nrows, int kp, int R,
-                           const QMap& m, const QT (&e4)[4], QBatch<QT, NB>& b, QT* ys) {
+// arithmetic in QA (the basis's arithmetic type); the lpr lanes of a row add
+// with butterflies.  All lanes run the same trip count (shuffles need the
+// whole wave).
+template <typename QS, int NB, typename QA = typename Arith<QS>::type>
+NLSP_DEV void prolong_rows(const QS* __restrict__ Q, int64_t row0, int nrows, int kp, int R,
+                           const QMap& m, const QA (&e4)[4], QBatch<QS, NB>& b, QA* ys) {
   const int trips = q_trips(m, nrows);
   for (int w0 = 0; w0 < trips; w0 += NB) {
-    if (w0 > 0) q_fetch<QT, NB>(Q, row0, nrows, kp, m, w0, b);
+    if (w0 > 0) q_fetch<QS, NB>(Q, row0, nrows, kp, m, w0, b);
 #pragma unroll
     for (int w = 0; w < NB; ++w) {
       if (w0 + w >= trips) break;
       const int row = m.rg + (w0 + w) * m.ngr;
-      QT sdot = b.v[w][0] * e4[0] + b.v[w][1] * e4[1] + b.v[w][2] * e4[2] + b.v[w][3] * e4[3];
+      QA sdot = b.get(w, 0) * e4[0] + b.get(w, 1) * e4[1] + b.get(w, 2) * e4[2] + b.get(w, 3) * e4[3];
       sdot = group_sum(sdot, m.lpr);
       if (m.jc == 0 && m.on && row < nrows) ys[row * R + m.c] = sdot;
     }
@@ -451,9 +483,11 @@ template <typename QT>
 struct QB {
   // update kernel: 4 rows of Q per thread in flight (float; measured against
   // 2, 3, 5, 6 and 8 on the 2-D workload); 2 keeps the float64 kernel at 128
-  // VGPRs without spills
-  static constexpr int NB = (sizeof(QT) == 4) ? 4 : 2;
-  static constexpr int NBR = 4;   // matvec and residual kernels (measured against 2, 3, 5 and 6)
+  // VGPRs without spills; float16 rows are half as long, so twice as many
+  // keep the same bytes in flight
+  static constexpr int NB = sizeof(QT) == 8 ? 2 : (sizeof(QT) == 4 ? 4 : 8);
+  // matvec and residual kernels (measured against 2, 3, 5 and 6)
+  static constexpr int NBR = sizeof(QT) == 2 ? 8 : 4;
 };
 
 // ---------------------------------------------- MFMA form of the basis passes
@@ -688,10 +722,21 @@ __global__ __launch_bounds__(256) void k_qtilde(const QT* __restrict__ Q, const 
   }
 }
 
+// A float16 Qt is stored as Qt s_Qt: its restriction sums are multiplied by
+// 1 / s_Qt (a power of two, so exactly as if Qt were stored unscaled).
+template <typename QS, int K>
+NLSP_DEV void unscale_restriction(const SysDev& S, double (&acc)[K]) {
+  if constexpr (sizeof(QS) == 2) {
+    const double is = S.qscale[1];
+#pragma unroll
+    for (int u = 0; u < K; ++u) acc[u] *= is;
+  }
+}
+
 // r = f - A x into `rout` for the RHS in `mask` (others untouched);
 // restriction records [Qt^T r | ||r||^2 | ||f||^2] (Qt^T r = A_c^-1 Q^T r),
 // then the group epilogue.  Used at start-up and for residual replacement.
-template <typename QT>
+template <typename QS>
 __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ sys,
                                                     const int* __restrict__ blk2sys, int nsys,
                                                     unsigned mask, int rout) {
@@ -704,10 +749,10 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
   const bool on = (mask >> c) & 1u;
-  const QT* Qt = static_cast<const QT*>(S.Qt);
+  const QS* Qt = static_cast<const QS*>(S.Qt);
   const QMap m = q_map(S.kp, R);
-  constexpr int NB = QB<QT>::NBR;
-  QBatch<QT, NB> qb;
+  constexpr int NB = QB<QS>::NBR;
+  QBatch<QS, NB> qb;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double rr = 0.0, ff = 0.0;
   double* Rout = S.r[rout];
@@ -715,7 +760,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     const int64_t row0 = chunk_row0(S, ch);
     const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-    q_fetch<QT, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
+    q_fetch<QS, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
     const int64_t i = row0 + t / R;
     double rvv = 0.0;
     if (on && t / R < nrows) {
@@ -732,8 +777,9 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
     __syncthreads();
     rv[t] = rvv;
     __syncthreads();
-    restrict_rows<QT, NB>(Qt, row0, nrows, S.kp, R, m, rv, qb, acc);
+    restrict_rows<QS, NB>(Qt, row0, nrows, S.kp, R, m, rv, qb, acc);
   }
+  unscale_restriction<QS>(S, acc);
   double* rec = S.rpart + (int64_t)lb * S.rw;
   restrict_finish(m, S.kp, R, acc, red, rec);
   const int KR = S.kp * R;
@@ -749,7 +795,7 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
 // by the epilogue.  Nothing here waits for a scalar: every workgroup streams
 // from its first instruction.  In a batch, a system whose right-hand sides
 // have all stopped exits at once.
-template <typename QT, bool MF>
+template <typename QS, bool MF>
 __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it) {
   __shared__ double wv[NT];
@@ -763,10 +809,10 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
   const int na = S.nact[(it + 1) & 1];
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  const QT* Qt = static_cast<const QT*>(S.Qt);
+  const QS* Qt = static_cast<const QS*>(S.Qt);
   const QMap m = q_map(S.kp, R);
-  constexpr int NB = QB<QT>::NBR;
-  QBatch<QT, NB> qb;
+  constexpr int NB = QB<QS>::NBR;
+  QBatch<QS, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
   const double* Z = S.z;
   const double* Pv = S.p;
@@ -782,7 +828,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
       const int64_t row0 = chunk_row0(S, ch);
       const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-      QT a[8];   // A operands of this chunk, loaded before the stencil (rows past the chunk: a clamped row)
+      QS a[8];   // A operands of this chunk, loaded before the stencil (rows past the chunk: a clamped row)
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int rr = min(sl * rps + 4 * min(s, ksteps - 1) + lg, nrows - 1);
@@ -809,6 +855,11 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
 #pragma unroll
       for (int s = 0; s < 8; ++s)
         if (s < ksteps) acc = mf_mma((double)a[s], wv[(sl * rps + 4 * s + lg) * MF_R + lr], acc);
+    }
+    if constexpr (sizeof(QS) == 2) {
+      const double is = S.qscale[1];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] *= is;
     }
     double* rec = S.rpart + (int64_t)lb * S.rw;
     const int KR = S.kp * R;
@@ -838,7 +889,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     const int64_t row0 = chunk_row0(S, ch);
     const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
-    q_fetch<QT, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
+    q_fetch<QS, NB>(Qt, row0, nrows, S.kp, m, 0, qb);
     double wval = 0.0;
     if (t / R < nrows) {
       const int64_t i = row0 + t / R;
@@ -857,8 +908,9 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     __syncthreads();
     wv[t] = wval;
     __syncthreads();
-    restrict_rows<QT, NB>(Qt, row0, nrows, S.kp, R, m, wv, qb, acc);
+    restrict_rows<QS, NB>(Qt, row0, nrows, S.kp, R, m, wv, qb, acc);
   }
+  unscale_restriction<QS>(S, acc);
   double* rec = S.rpart + (int64_t)lb * S.rw;
   const int KR = S.kp * R;
   const double v2[2] = {zw, e1};
@@ -931,10 +983,11 @@ constexpr int PH_Z = 2;     // z = J r_new + Q c_new; partials r^T z, r^T z_old,
 //     update, `init` also takes ||f||^2, and the next iteration uses beta = 0.
 //   phase = PH_UPD only (nu > 1): stops after r_new; phase = PH_Z only, not a
 //     restart: z for the RHS the update phase advanced (stat[(it+1)&1]).
-template <typename QT, bool MF>
+template <typename QS, bool MF>
 __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it,
                                                   int restart, unsigned mask, int init, int phase, int wsrc) {
+  using QT = typename Arith<QS>::type;   // arithmetic of the smoother and the prolongation
   __shared__ QT ws[NT];
   __shared__ QT ys[NT];
   __shared__ QT mfpart[MF ? (NT / WAVE) * 256 : 1];   // MFMA prolongation: per-wave partial tiles
@@ -957,10 +1010,10 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   const bool normal = decide && !restart;
   const int lb = xcd_remap(blockIdx.x - S.blk0, S.nblk);
   const int t = threadIdx.x, R = S.R, c = t % R;
-  const Glob<const QT>* Q = (Glob<const QT>*)S.Q;
+  const Glob<const QS>* Q = (Glob<const QS>*)S.Q;
   const QMap m = q_map(S.kp, R);
-  constexpr int NB = QB<QT>::NB;
-  QBatch<QT, NB> qb;
+  constexpr int NB = QB<QS>::NB;
+  QBatch<QS, NB> qb;
   const ChunkRange cr = my_chunks(S, lb);
   // every load of the prologue is issued before the first wait, and the same
   // number of them on every path (waits complete in issue order, and a count
@@ -1001,16 +1054,19 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   // per block, feeding 4 products
   const int mwave = t / WAVE, mlane = t % WAVE, mlr = mlane & 15, mlg = mlane >> 4;
   const int mRT = mwave & 1, mks = mwave >> 1, mcols = S.kp / 4, mnbk = mcols / 16;
-  QT q4[2][4];
+  QBatch<QS, 2> q4;
   auto mf_fetch = [&](int64_t r0, int nr) {
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk)
-      load4<QT>(Q + (r0 + min(16 * mRT + mlr, nr - 1)) * S.kp + mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg, q4[blk]);
+      q4.load(blk, Q + (r0 + min(16 * mRT + mlr, nr - 1)) * S.kp + mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg);
   };
   if constexpr (MF)
     mf_fetch(row0, nrows);
   else
-    q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+    q_fetch<QS, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+  // float16 basis: c is multiplied by 1 / s_Q before the prolongation
+  double isq = 1.0;
+  if constexpr (sizeof(QS) == 2) isq = S.qscale[0];
   if (normal && nact_cp == 0) {
     // nothing iterates: carry the state over to the next parity
     if (blockIdx.x == S.blk0) {
@@ -1228,10 +1284,10 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     for (int blk = 0; blk < 2; ++blk)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        eb[blk][u] = QT(cvec[(mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg + u) * MF_R + mlr]);
+        eb[blk][u] = QT(cvec[(mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg + u) * MF_R + mlr] * isq);
   } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) e4[u] = QT(cvec[(4 * m.jc + u) * R + m.c]);
+    for (int u = 0; u < 4; ++u) e4[u] = QT(cvec[(4 * m.jc + u) * R + m.c] * isq);
   }
   const QT om = QT(S.omega);
   double gam = 0.0, rzo = 0.0, rr = 0.0, pq = 0.0;
@@ -1243,7 +1299,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         if constexpr (MF)
           mf_fetch(row0, nrows);
         else
-          q_fetch<QT, NB>(Q, row0, nrows, S.kp, m, 0, qb);
+          q_fetch<QS, NB>(Q, row0, nrows, S.kp, m, 0, qb);
       }
     }
     const bool mine = upd && t / R < nrows;
@@ -1304,7 +1360,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         for (int blk = 0; blk < 2; ++blk)
           if (blk < mnbk)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pacc = mf_mma(q4[blk][u], eb[blk][u], pacc);
+            for (int u = 0; u < 4; ++u) pacc = mf_mma(q4.get(blk, u), eb[blk][u], pacc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) mfpart[mwave * 256 + v * 64 + mlane] = pacc[v];
         __syncthreads();
@@ -1317,7 +1373,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
           ys[t] = sum;
         }
       } else {
-        prolong_rows<QT, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
+        prolong_rows<QS, NB>(Q, row0, nrows, S.kp, R, m, e4, qb, ys);
       }
       __syncthreads();
       if (mine) {
@@ -1384,6 +1440,39 @@ __global__ __launch_bounds__(NT) void k_true_finish(const SysDev* __restrict__ s
   if (threadIdx.x < S.R) S.rr_true[threadIdx.x] = buf[threadIdx.x];
 }
 
+// Largest |X| over cnt floats, as the bits of a non-negative float (ordered
+// as unsigned integers): one atomic max per wave into *out (zeroed before).
+// The maximum does not depend on the order, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ X, int64_t cnt, unsigned* out) {
+  float mx = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    mx = fmaxf(mx, fabsf(X[i]));
+  for (int o = WAVE / 2; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, WAVE));
+  if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(out, __float_as_uint(mx));
+}
+
+// Y = float16(X s) with s = 2^-e, e the binary exponent of max |X| (so that
+// |X s| < 1 and the large entries keep float16's 11 significant bits);
+// inv[0] and inv[1] receive 1 / s = 2^e.  s = 1 for an all-zero X.
+__global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ X, int64_t cnt,
+                                                 const unsigned* __restrict__ maxbits, _Float16* __restrict__ Y,
+                                                 double* inv) {
+  const float mx = __uint_as_float(*maxbits);
+  int e = 0;
+  if (mx > 0.f) (void)frexpf(mx, &e);
+  const float sc = ldexpf(1.f, -e);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    Y[i] = (_Float16)(X[i] * sc);
+  if (blockIdx.x == 0 && threadIdx.x < 2) inv[threadIdx.x] = ldexp(1.0, e);
+}
+
+// B = A^T for a (kp, kp) matrix
+__global__ void k_transpose_sq(const double* __restrict__ A, int kp, double* __restrict__ B) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kp * kp) return;
+  B[(idx % kp) * kp + idx / kp] = A[idx];
+}
+
 __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n * R) return;
@@ -1398,6 +1487,8 @@ __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
 struct SolveLayout {
   double *p, *q0, *q1, *z, *w, *cstate0, *cstate1, *gstate0, *gstate1;
   unsigned* ticket;
+  unsigned* qmax;   // [2] max |W| as float bits (float16 basis; one used)
+  double* qscale;   // [2] 1 / s for the restriction and the prolongation (float16 basis)
   double *r0, *r1, *dinv, *bpart0, *bpart1, *rpart, *rgrp, *dpart, *Ainv, *Qt;
   float* dinv32;
   void *wj0, *wj1;
@@ -1481,6 +1572,7 @@ inline void carve_zero(Carver& cv, const SysShape& h, SolveLayout& L) {
   L.gstate0 = cv.take<double>((size_t)h.kp * h.R);
   L.gstate1 = cv.take<double>((size_t)h.kp * h.R);
   L.ticket = cv.take<unsigned>(ticket_words(h.nblk));
+  L.qmax = cv.take<unsigned>(2);
 }
 
 inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
@@ -1500,7 +1592,10 @@ inline void carve_rest(Carver& cv, const SysShape& h, SolveLayout& L) {
   L.rgrp = cv.take<double>((size_t)ticket_groups(h.nblk) * (rw + BW * h.R));
   L.dpart = cv.take<double>((size_t)h.nblk * h.R);
   L.Ainv = cv.take<double>((size_t)h.kp * h.kp);
-  L.Qt = cv.take<double>((size_t)h.n * h.kp);   // sized for float64, used as the type of Q
+  // sized for float64 and used as the type of Q; a float16 basis carves it
+  // into W s (float16, n kp) and W (float32, formed first, at 4 n kp bytes)
+  L.Qt = cv.take<double>((size_t)h.n * h.kp);
+  L.qscale = cv.take<double>(2);
 }
 
 // Carves the whole workspace (base == nullptr: sizes only).  `Ls` receives the
@@ -1550,6 +1645,13 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.gw = hs.rw + BW * R;
   hs.Q = as_glob((M.prec == NLSP_FP64) ? (const void*)M.Q64 : (const void*)M.Q32);
   hs.Qt = as_glob((const void*)L.Qt);
+  hs.qscale = as_glob((const double*)L.qscale);
+  hs.qsrc = M.Q32;
+  if (M.prec == NLSP_MIXED_F16) {
+    // one float16 matrix W s serves the restriction and the prolongation
+    hs.Q = as_glob((const void*)L.Qt);
+    hs.Qt = as_glob((const void*)L.Qt);
+  }
   hs.Linv = as_glob((const double*)M.Linv);
   hs.Ainv = as_glob(L.Ainv);
   hs.f = as_glob(f);
@@ -1596,9 +1698,10 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
 // check_every iterations are captured once in a hipGraph and replayed (their
 // kernels read the iteration only through its parity, and check_every is
 // even).
-template <typename QT>
-static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, const nlsp_pcg_opts* opts,
-                   nlsp_rhs_info* info, bool graph, hipStream_t stream) {
+template <typename QS>
+static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, const std::vector<SolveLayout>& Ls,
+                   const nlsp_pcg_opts* opts, nlsp_rhs_info* info, bool graph, hipStream_t stream) {
+  using QT = typename Arith<QS>::type;
   const int R = hs[0].R;
   int nblk = 0;
   bool mf = true;   // MFMA basis passes when every system has 16 right-hand sides and kp = 64 or 128
@@ -1640,18 +1743,18 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
       if (timed_one) {
         timed(1, [&](hipEvent_t a, hipEvent_t b) {
           if (mf)
-            hipExtLaunchKernelGGL((k_update<QT, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
+            hipExtLaunchKernelGGL((k_update<QS, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
                                   mask, init, phase, wsrc);
           else
-            hipExtLaunchKernelGGL((k_update<QT, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
+            hipExtLaunchKernelGGL((k_update<QS, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
                                   mask, init, phase, wsrc);
         });
       } else {
         if (mf)
-          hipLaunchKernelGGL((k_update<QT, true>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
+          hipLaunchKernelGGL((k_update<QS, true>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
                              phase, wsrc);
         else
-          hipLaunchKernelGGL((k_update<QT, false>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
+          hipLaunchKernelGGL((k_update<QS, false>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
                              phase, wsrc);
       }
     };
@@ -1677,15 +1780,15 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     if (can_time) {
       timed(2, [&](hipEvent_t a, hipEvent_t b) {
         if (mf)
-          hipExtLaunchKernelGGL((k_matvec<QT, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+          hipExtLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
         else
-          hipExtLaunchKernelGGL((k_matvec<QT, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+          hipExtLaunchKernelGGL((k_matvec<QS, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
       });
     } else {
       if (mf)
-        hipLaunchKernelGGL((k_matvec<QT, true>), grid, block, 0, st, dsys, b2s, nsys, it);
+        hipLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, dsys, b2s, nsys, it);
       else
-        hipLaunchKernelGGL((k_matvec<QT, false>), grid, block, 0, st, dsys, b2s, nsys, it);
+        hipLaunchKernelGGL((k_matvec<QS, false>), grid, block, 0, st, dsys, b2s, nsys, it);
     }
   };
   hipGraphExec_t gexec = nullptr;
@@ -1725,14 +1828,38 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
       o.fw32 = nullptr;
       hipLaunchKernelGGL(k_faces, dim3(ceil_div(o.n, NT)), block, 0, stream, o, f64, f32);
     }
-    hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs[i].kp * hs[i].kp, 256)), dim3(256), 0, stream,
-                       (const double*)hs[i].Linv, hs[i].kp, (double*)hs[i].Ainv);
-    hipLaunchKernelGGL(k_qtilde<QT>, dim3(ceil_div(hs[i].op.n, 64)), dim3(256), 0, stream, (const QT*)hs[i].Q,
-                       (const double*)hs[i].Ainv, hs[i].op.n, hs[i].kp, (QT*)hs[i].Qt);
+    if constexpr (sizeof(QS) != 2)
+      hipLaunchKernelGGL(k_coarse_inverse, dim3(ceil_div(hs[i].kp * hs[i].kp, 256)), dim3(256), 0, stream,
+                         (const double*)hs[i].Linv, hs[i].kp, (double*)hs[i].Ainv);
+    if constexpr (sizeof(QS) == 2) {
+      // float16 basis: the coarse term Q A_c^-1 Q^T = W W^T, W = Q L^-T,
+      // formed in float32 (float64 sums), then stored once as W s in
+      // float16 and used by both the restriction (c = W^T r) and the
+      // prolongation (W c).  With one rounded matrix on both sides the
+      // preconditioner stays exactly symmetric; rounding Q and Q A_c^-1
+      // separately made it slightly nonsymmetric, which cost up to 10 % more
+      // iterations on small anisotropic systems.
+      const int64_t cnt = hs[i].op.n * hs[i].kp;
+      const float* q32 = static_cast<const float*>(hs[i].qsrc);
+      _Float16* w16 = reinterpret_cast<_Float16*>(Ls[i].Qt);
+      float* w32 = reinterpret_cast<float*>(w16 + 2 * cnt);
+      double* linvT = Ls[i].Ainv;
+      const dim3 cg((unsigned)std::min<int64_t>(1024, ceil_div(cnt, 256)));
+      hipLaunchKernelGGL(k_transpose_sq, dim3(ceil_div(hs[i].kp * hs[i].kp, 256)), dim3(256), 0, stream,
+                         (const double*)hs[i].Linv, hs[i].kp, linvT);
+      hipLaunchKernelGGL(k_qtilde<float>, dim3(ceil_div(hs[i].op.n, 64)), dim3(256), 0, stream, q32,
+                         (const double*)linvT, hs[i].op.n, hs[i].kp, w32);
+      hipLaunchKernelGGL(k_absmax, cg, dim3(256), 0, stream, (const float*)w32, cnt, Ls[i].qmax);
+      hipLaunchKernelGGL(k_to_half, cg, dim3(256), 0, stream, (const float*)w32, cnt, (const unsigned*)Ls[i].qmax,
+                         w16, Ls[i].qscale);
+    } else {
+      hipLaunchKernelGGL(k_qtilde<QS>, dim3(ceil_div(hs[i].op.n, 64)), dim3(256), 0, stream, (const QS*)hs[i].Q,
+                         (const double*)hs[i].Ainv, hs[i].op.n, hs[i].kp, (QS*)hs[i].Qt);
+    }
   }
   // start-up as iteration -1: r = f - A x into r[0], the update kernel in
   // restart mode (c = Qt^T r, z = M^-1 r), then w = A z
-  hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, b2s, nsys, all, 0);
+  hipLaunchKernelGGL(k_residual<QS>, grid, block, 0, stream, dsys, b2s, nsys, all, 0);
   launch_update(stream, -1, 1, all, 1, true);
   launch_matvec(stream, -1, true);
   NLSP_RUN(hipGetLastError());
@@ -1844,7 +1971,7 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     NLSP_RUN(hipMemcpyAsync(prev_d, hst.data(), sizeof(RhsStatus) * nsys * R, hipMemcpyHostToDevice, stream));
     NLSP_RUN(hipMemcpyAsync(B.counters, cnt.data(), sizeof(int) * 4 * nsys, hipMemcpyHostToDevice, stream));
     NLSP_RUN(hipMemcpyAsync(B.sysdev, hr.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL(k_residual<QT>, grid, block, 0, stream, dsys, b2s, nsys, all, it & 1);
+    hipLaunchKernelGGL(k_residual<QS>, grid, block, 0, stream, dsys, b2s, nsys, all, it & 1);
     launch_update(stream, it - 1, 1, all, 0, true);
     launch_matvec(stream, it - 1, true);
     NLSP_RUN(hipMemcpyAsync(B.sysdev, hs.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, stream));
@@ -1863,7 +1990,8 @@ inline bool system_ok(const nlsp_operator* A, const nlsp_two_level* M, const dou
   const int kp = padded_rank(M->k);
   if (kp < 0 || M->nu < 1 || !(M->omega > 0) || !M->Linv) return false;
   if (kp * R > 2048) return false;  // LDS staging of the coarse vectors
-  if (M->prec == NLSP_FP64 ? !M->Q64 : (M->prec == NLSP_MIXED ? !M->Q32 : true)) return false;
+  if (M->prec == NLSP_FP64 ? !M->Q64 : ((M->prec == NLSP_MIXED || M->prec == NLSP_MIXED_F16) ? !M->Q32 : true))
+    return false;
   if ((int64_t)M->k > n) return false;
   return true;
 }
@@ -1913,8 +2041,9 @@ static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_
     NLSP_HIP(hipMemcpyAsync(B.blk2sys, b2s.data(), sizeof(int) * b2s.size(), hipMemcpyHostToDevice, stream));
   // the host arrays above are locals: their copies must finish before return
   NLSP_HIP(hipStreamSynchronize(stream));
-  if (Ms[0]->prec == NLSP_FP64) return run_pcg<double>(nsys, hs, B, opts, info, graph, stream);
-  return run_pcg<float>(nsys, hs, B, opts, info, graph, stream);
+  if (Ms[0]->prec == NLSP_FP64) return run_pcg<double>(nsys, hs, B, Ls, opts, info, graph, stream);
+  if (Ms[0]->prec == NLSP_MIXED_F16) return run_pcg<_Float16>(nsys, hs, B, Ls, opts, info, graph, stream);
+  return run_pcg<float>(nsys, hs, B, Ls, opts, info, graph, stream);
 }
 
 // ------------------------------------------------ non-allocating solve

@@ -55,7 +55,7 @@ def _systems(nl, batch):
             for (_, op, M, _, f) in batch]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("R", [1, 3, 8])
 def test_default_tile_matches_single_system_bitwise(nl, prec, R):
     batch = _batch(nl, R, zero_col=(R == 3))
@@ -69,7 +69,7 @@ def test_default_tile_matches_single_system_bitwise(nl, prec, R):
             assert (a.iters, a.status, a.relres) == (b.iters, b.status, b.relres)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_sixteen_rhs_matrix_core_batch(nl, prec):
     """16 right-hand sides and kp = 64: the batch takes the matrix-core basis
     passes; with the default tile it reproduces the single-system solves bit
@@ -88,7 +88,7 @@ def test_sixteen_rhs_matrix_core_batch(nl, prec):
             assert true_rel <= 1e-8 * 1.0001, (j, true_rel)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("rows", [128, 512, 2048])
 def test_tiles_against_oracle(nl, prec, rows):
     R = 8
@@ -100,7 +100,7 @@ def test_tiles_against_oracle(nl, prec, rows):
         u = host(s.u)
         Ph = host(P)
         _, L = O.galerkin(A, Ph)
-        res = O.pcg(A, f, make_preconditioner(A, Ph, L, 2 / 3, 1, 1), rtol=1e-8, flexible=(prec == 1))
+        res = O.pcg(A, f, make_preconditioner(A, Ph, L, 2 / 3, 1, 1), rtol=1e-8, flexible=(prec != 0))
         for c in range(R):
             rel = np.linalg.norm(f[:, c] - A @ u[:, c]) / np.linalg.norm(f[:, c])
             assert inf[c].status == nl.OK

@@ -1,8 +1,9 @@
 """GPU parity of the PCG solve against the FP64 oracle, through the C ABI
 (marked gpu).  Bar: iteration count within +-1 of the oracle per RHS and a
-true relative residual <= rtol in the float64 form; in the mixed form the
-true relative residual <= rtol and ||x - x_oracle|| <= 2 rtol ||f|| /
-lambda_min(A)."""
+true relative residual <= rtol in the float64 form; in the mixed forms
+(float32 basis, prec 1; float16 basis, prec 2) the true relative residual
+<= rtol and ||x - x_oracle|| <= 2 rtol ||f|| / lambda_min(A), iterations
+within max(2, 5 %) of the oracle's."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as sla
@@ -34,7 +35,7 @@ def _oracle_solve(A, P, f, omega, nu, rtol, flexible=False):
 
 
 def _check(nl, A, op, P, f, omega=2 / 3, nu=1, rtol=1e-8, prec=0, check_every=8):
-    res = _oracle_solve(A, P, f, omega, nu, rtol, flexible=(prec == 1))
+    res = _oracle_solve(A, P, f, omega, nu, rtol, flexible=(prec != 0))
     M = nl.galerkin_coarse(op, cuda(P), omega, nu)
     u, info, rc = nl.pcg_solve(op, M, cuda(f), prec=prec, rtol=rtol, check_every=check_every)
     u = host(u).reshape(f.shape)
@@ -55,7 +56,7 @@ def _check(nl, A, op, P, f, omega=2 / 3, nu=1, rtol=1e-8, prec=0, check_every=8)
     return info, res
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_cfg1_poisson(nl, prec):
     c = W.Cfg1()
     A, op, n = make_case("poisson", 0, (c.N, c.N))
@@ -67,7 +68,7 @@ def test_cfg1_poisson(nl, prec):
 
 @pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 24), ("q1", (48, 48), 32),
                                          ("fv7", (19, 15), 16), ("grf", (64, 64), 64)])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_kinds(nl, kind, size, k, prec):
     A, op, n = make_case(kind, 11, size)
     S = O.relax(A, np.random.default_rng(12).standard_normal((n, 2 * k)), 2 / 3, 10)
@@ -77,7 +78,7 @@ def test_kinds(nl, kind, size, k, prec):
 
 
 @pytest.mark.parametrize("R", [2, 8, 16])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_multi_rhs(nl, R, prec):
     A, op, n = make_case("fv5", 21, (40, 33))
     S = O.relax(A, np.random.default_rng(22).standard_normal((n, 32)), 2 / 3, 10)
@@ -92,7 +93,7 @@ def test_multi_rhs(nl, R, prec):
 # with ragged chunks, and more than one row chunk per workgroup
 @pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 40), ("fv5", (90, 77), 100), ("fv7", (19, 14), 64),
                                           ("fv7", (32, 11), 64)])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_multi_rhs_mfma(nl, kind, size, k, prec):
     A, op, n = make_case(kind, 24, size)
     S = O.relax(A, np.random.default_rng(25).standard_normal((n, 2 * k)), 2 / 3, 10)
@@ -105,7 +106,7 @@ def test_multi_rhs_mfma(nl, kind, size, k, prec):
 # 3-D grids whose x-lines split into whole chunks (chunk = 512 / R rows)
 # enumerate chunks z fastest, so a workgroup marches through z
 @pytest.mark.parametrize("R,size", [(8, (64, 9)), (16, (32, 13))])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_3d_zmajor_chunks(nl, R, size, prec):
     A, op, n = make_case("fv7", 27, size)
     S = O.relax(A, np.random.default_rng(28).standard_normal((n, 32)), 2 / 3, 10)
@@ -122,6 +123,7 @@ def test_more_sweeps(nl, nu):
     f = np.random.default_rng(33).standard_normal(n)
     _check(nl, A, op, P, f, omega=0.66, nu=nu)
     _check(nl, A, op, P, f, omega=0.66, nu=nu, prec=1)
+    _check(nl, A, op, P, f, omega=0.66, nu=nu, prec=2)
 
 
 def test_statuses(nl):

@@ -9,8 +9,8 @@
 * The 2-D log-normal workload at full size (512 x 512, m = 128, k = 64).
 
 Bars: float64 form, iterations within +-1 of the oracle and a true relative
-residual <= rtol; mixed form, true relative residual <= rtol and
-||x - x_oracle|| <= 2 rtol ||f|| / lambda_min(A)."""
+residual <= rtol; mixed forms (float32 or float16 basis), true relative
+residual <= rtol and ||x - x_oracle|| <= 2 rtol ||f|| / lambda_min(A)."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as sla
@@ -77,7 +77,7 @@ def aniso(nl):
     return c3, out
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_batched_anisotropic_benchmark_configuration(nl, aniso, prec):
     c3, syss = aniso
     systems = [nl.System(s["op"], s["M"], cuda(s["f"]), torch.zeros(s["f"].shape, dtype=torch.float64,
@@ -103,9 +103,9 @@ def test_log_normal_full_size(nl):
     res = O.pcg(A, f, make_preconditioner(A, stg["P"], stg["L"], c.omega, c.nu, c.nu), rtol=c.rtol)
     lam = _lam_min(A)
     S0 = cuda(S0h)
-    for prec in (nl.FP64, nl.MIXED):
+    for prec in (nl.FP64, nl.MIXED, nl.MIXED_F16):
         print(f"log-normal 512^2, prec={prec}", flush=True)
-        P, sigma = nl.setup_spectral_P(op, S0, c.k, c.omega, c.s1, prec)
+        P, sigma = nl.setup_spectral_P(op, S0, c.k, c.omega, c.s1, min(prec, nl.MIXED))
         np.testing.assert_allclose(host(sigma)[:c.k + 1], stg["sigma"][:c.k + 1], rtol=1e-4)
         M = nl.galerkin_coarse(op, P, c.omega, c.nu)
         u, info, rc = nl.pcg_solve(op, M, cuda(f), prec=prec, rtol=c.rtol)

@@ -31,7 +31,7 @@ def _case(nl, kind, seed, size, m, k, R):
     return A, op, M, f
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_noalloc_matches_pcg_solve(nl, prec):
     big = _case(nl, "grf", 60, (96, 96), 32, 16, 3)
     small = _case(nl, "fv5", 63, (40, 30), 16, 8, 2)

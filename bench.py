@@ -29,6 +29,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+BF16_PEAK_FLOPS = 2.5e15   # MI355X dense bfloat16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -192,7 +193,7 @@ def main():
                        "relres": inf64.relres}
         out["mixed_f16"] = f16_leg(step, nl, n, kp)
         out["spmv"] = spmv_legs(nl, torch, dev)
-        out["solve3d"] = solve3d_leg(nl, torch, dev)
+        out["solve3d"] = solve3d_leg(nl, torch, dev, cpu=not a.no_cpu_baseline)
         out["training"] = training_legs(nl, torch, dev)
         out["batched"] = batched_legs(nl, torch, dev)
         out["predictor"] = predictor_leg(nl, torch, dev)
@@ -271,7 +272,7 @@ def spmv_legs(nl, torch, dev):
     return res
 
 
-def solve3d_leg(nl, torch, dev):
+def solve3d_leg(nl, torch, dev, cpu=False):
     """Setup and solve on the 3-D workload (FV7, 128^3 cells, 16^3-cell
     blocks of a in {1, 1e3}, m = 256 relaxed vectors, k = 128, 16 right-hand
     sides solved together: the basis passes run on the matrix cores), mixed
@@ -281,10 +282,11 @@ def solve3d_leg(nl, torch, dev):
     c4 = W.Cfg4()
     n, R, k = c4.n, c4.R, c4.k
     kp = nl.nlsp_padded_rank(k)
-    op = nl.Operator(nl.OP_FV7, c4.N, c4.N, c4.N,
-                     torch.tensor(c4.coef().ravel(), dtype=torch.float64, device=dev))
+    coef = c4.coef()
+    op = nl.Operator(nl.OP_FV7, c4.N, c4.N, c4.N, torch.tensor(coef.ravel(), dtype=torch.float64, device=dev))
     S0 = torch.tensor(c4.S0(), dtype=torch.float64, device=dev)
-    f = torch.tensor(c4.rhs(), dtype=torch.float64, device=dev)
+    fh = c4.rhs()
+    f = torch.tensor(fh, dtype=torch.float64, device=dev)
     res = {"workload": f"FV7 {c4.N}^3 (n={n}), 16^3 blocks of a in {{1, 1e3}}, m={c4.m}, k={k}, R={R}, rtol={c4.rtol}"}
     for name, prec in (("mixed", nl.MIXED), ("fp64", nl.FP64)):
         for rep in range(2):
@@ -306,8 +308,21 @@ def solve3d_leg(nl, torch, dev):
             r["bytes_per_iter"] = by
             r["GBs_per_iter"] = round(by / (solve_ms / max(1, iters)) / 1e6, 1)
             r["frac"] = round(r["GBs_per_iter"] / HBM_PEAK_GBS, 4)
+            # the dominant kernel (the update kernel, matrix-core form): one
+            # event-timed solve, one dispatch in 8 timed
+            tm = {"phase": 1, "every": 8}
+            nl.pcg_solve(op, M, f, prec=prec, rtol=c4.rtol, timing=tm)
+            launch_ms = tm["total_ms"] / max(1, tm["launches"])
+            bl = solver_bytes_per_row(1, kp, R) * n
+            ach = bl / (launch_ms * 1e-3) / 1e9
+            r["roofline"] = {"bound": "hbm", "kernel": "nlsp::k_update<float, true>", "achieved": round(ach, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                             "traffic": None, "launch_us": round(launch_ms * 1e3, 3),
+                             "bytes_per_launch": int(bl), "timed_launches": int(tm["launches"])}
         res[name] = r
         del P, M, u
+    if cpu:
+        res["cpu_baseline"] = cpu_baseline_3d(c4, coef, fh, res["mixed"]["iters_max"])
     return res
 
 
@@ -346,7 +361,7 @@ def training_legs(nl, torch, dev):
     # Galerkin-convergence term J(P) on the relaxed vectors B (forward: read
     # B, P, a, write [AB | AP], then read it and P again for P^T [AB | AP];
     # backward: read [AB | AP], write dJ/dP)
-    J, bad, gsaved = nl.galerkin_term_fwd(op, P, B)
+    J, bad, gsaved, _ = nl.galerkin_term_fwd(op, P, B)
     f_ms = _time_ms(torch, lambda: nl.galerkin_term_fwd(op, P, B))
     b_ms = _time_ms(torch, lambda: nl.galerkin_term_bwd(op, k, m, gsaved, ones))
     fwd_bytes = batch * n * (4 * m + 2 * 4 * k + 8 + 2 * 4 * (m + k))
@@ -433,7 +448,8 @@ def batched_legs(nl, torch, dev, nsys=None):
 def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
     """P-predictor on the training workload (64 log-normal fields of 128^2,
     k = 32, m = 64 relaxed vectors per field, hidden width 32): time of one
-    training step (CNN forward, thin QR, NLSS loss, their backward, Adam),
+    training step (CNN forward, thin QR, NLSS loss + Galerkin-convergence term
+    J / ||A^{1/2} B||_F^2, their backward, Adam),
     then `train_steps` steps and, on held-out fields, PCG iterations
     (float64, rtol 1e-8) with the learned basis against the SVD basis of the
     same relaxed vectors."""
@@ -490,8 +506,10 @@ def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
                                hB[j:j + 1].expand(2, -1, -1).contiguous())
         gaps.append((E[0] - E[1]).cpu().numpy())
     flop = 2.0 * batch * n * 9 * 32 * (33 + 32 + 32 + 32) * 3
-    return {"workload": f"{batch} x FV5 {N}^2, k={k}, m={m}, CNN 4 x 3x3 conv, width 32",
+    return {"workload": f"{batch} x FV5 {N}^2, k={k}, m={m}, CNN 4 x 3x3 conv, width 32; "
+                        f"loss NLSS + J / ||A^1/2 B||_F^2",
             "train_step_ms": round(step_ms, 3), "conv_TFLOPs_est": round(flop / step_ms / 1e9, 2),
+            "conv_frac_bf16_peak": round(flop / (step_ms * 1e-3) / BF16_PEAK_FLOPS, 4),
             "train_steps": train_steps + reps + 1, "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 5),
             "held_out": held_out,
             "pcg_iters_learned_median": float(np.median(it_learned)), "pcg_iters_svd_median": float(np.median(it_svd)),
@@ -523,30 +541,93 @@ def counter_traffic(kname: str, N: int, k: int):
     return None if kr is None else int(kr["traffic"])
 
 
-def cpu_baseline(c, coef, S0h, fh, iters_full):
-    """The FP64 oracle on the host cores, on the whole workload once: operator,
-    setup, then PCG to the same tolerance (about ten seconds of CPU work).
-    value = the oracle's PCG time, the counterpart of the GPU solve time."""
-    import oracle as O
-    from oracle.method import make_preconditioner
+def host_info():
+    """Host CPU model, the cores this process may use, and the threads the
+    BLAS pools use (SciPy's sparse mat-vec is single-threaded)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        ncores = os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        threads = ncores
+    return model, ncores, threads
+
+
+def _oracle_iter_ms(O, A, fcol, Minv, iters, reps, single_thread):
+    """Median over `reps` runs of the oracle PCG's time per iteration, each
+    run stopped after `iters` iterations (maxit)."""
+    from contextlib import nullcontext
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(1) if single_thread else nullcontext()
+    except Exception:  # pragma: no cover
+        ctx = nullcontext()
+    times = []
+    with ctx:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = O.pcg(A, fcol, Minv, rtol=1e-300, maxit=iters)
+            times.append((time.perf_counter() - t0) * 1000.0 / max(1, int(res.iters[0])))
+    return statistics.median(times)
+
+
+def cpu_baseline(c, coef, S0h, fh, iters_full, sample_iters=150, reps=5):
+    """The FP64 oracle on the host: setup once, then a bounded sample of its
+    PCG (runs of `sample_iters` iterations, median of `reps`, with all cores
+    and with one), scaled to the GPU's iteration count.  value = the
+    all-core PCG time to the same tolerance, the counterpart of the GPU
+    solve time."""
+    import oracle as O
+    from oracle.method import make_preconditioner
+    model, ncores, threads = host_info()
     t0 = time.perf_counter()
     A = O.fv_harmonic_2d(coef)
     st = O.setup(A, S0h, c.k, c.omega, c.s1)
     t1 = time.perf_counter()
     Minv = make_preconditioner(A, st["P"], st["L"], c.omega, c.nu, c.nu)
-    res = O.pcg(A, fh, Minv, rtol=c.rtol, maxit=4 * iters_full)
-    t2 = time.perf_counter()
-    it = int(res.iters[0])
-    return {"value": round((t2 - t1) * 1000.0, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
-            "setup_ms": round((t1 - t0) * 1000.0, 1), "iters": it,
-            "ms_per_iter": round((t2 - t1) * 1000.0 / max(1, it), 3),
-            "sample": "the full workload once: oracle setup, then oracle PCG to the same tolerance "
-                      "(value = PCG time only)"}
+    ms_all = _oracle_iter_ms(O, A, fh[:, :1], Minv, sample_iters, reps, False)
+    ms_one = _oracle_iter_ms(O, A, fh[:, :1], Minv, sample_iters, reps, True)
+    return {"value": round(ms_all * iters_full, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
+            "cpu_model": model, "nproc": ncores, "one_core_ms": round(ms_one * iters_full, 1),
+            "ms_per_iter": round(ms_all, 3), "ms_per_iter_one_core": round(ms_one, 3),
+            "setup_ms": round((t1 - t0) * 1000.0, 1), "iters": int(iters_full),
+            "sample": f"oracle setup once, then {reps} oracle PCG runs of {sample_iters} iterations each "
+                      f"with all cores and {reps} with one (threadpoolctl), median time per iteration x "
+                      f"{iters_full} iterations (the GPU's count to the same tolerance); the sparse "
+                      f"mat-vec is single-threaded in either case"}
+
+
+def cpu_baseline_3d(c4, coef, fh, iters_full, sample_iters=3, reps=5):
+    """The FP64 oracle's PCG on the 3-D workload, bounded: the oracle's
+    operator and an orthonormal basis of the same shape (Householder QR of a
+    seeded Gaussian n x k block; the per-iteration work of the oracle does
+    not depend on the basis values), `reps` runs of `sample_iters` iterations
+    on one right-hand side, median time per iteration x iterations x R."""
+    import oracle as O
+    from oracle.method import make_preconditioner
+    import workloads as W
+    model, ncores, threads = host_info()
+    A = O.fv_harmonic_3d(coef)
+    P, _ = np.linalg.qr(W.normal_block(W.seed_for(4, 7), c4.n, c4.k))
+    _, L = O.galerkin(A, P)
+    Minv = make_preconditioner(A, P, L, c4.omega, c4.nu, c4.nu)
+    ms = _oracle_iter_ms(O, A, fh[:, :1], Minv, sample_iters, reps, False)
+    return {"value": round(ms * iters_full * c4.R, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
+            "nproc": ncores, "ms_per_iter_per_rhs": round(ms, 2),
+            "sample": f"{reps} oracle PCG runs of {sample_iters} iterations on one right-hand side (orthonormal "
+                      f"basis of the same shape), median time per iteration x {iters_full} iterations x "
+                      f"{c4.R} right-hand sides (the oracle solves them one after another)"}
 
 if __name__ == "__main__":
     main()

@@ -399,6 +399,9 @@ int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, floa
  *   P      device (batch, n, k) float32      S  device (batch, n, m) float32
  *   J      device (batch) float32            bad device (batch) int: 1 where
  *          P^T A P was not positive definite (J and M of that sample invalid)
+ *   E      device (batch) float32 or NULL: tr(S^T A S) = ||A^{1/2} S||_F^2,
+ *          the value of J with no coarse space (the scale of the term in a
+ *          training loss)
  *   saved  device, galerkin_term_saved_bytes: [A S | A P] (float32) and the
  *          backward's small matrix, written by the forward, read by the
  *          backward (caller-owned, 256-byte aligned)
@@ -408,7 +411,8 @@ int galerkin_bwd(int batch, int n, int k, const float* Y, const float* gAc, floa
 size_t galerkin_term_saved_bytes(int batch, const nlsp_operator* A, int k, int m);
 size_t galerkin_term_workspace_bytes(int batch, const nlsp_operator* A, int k, int m);
 int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const float* S, int k, int m, float* J,
-                      int* bad, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream);
+                      float* E, int* bad, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes,
+                      void* stream);
 /* dL/dP_b = gJ_b dJ_b/dP_b from `saved` (gJ device (batch) float32, gP device
  * (batch, n, k) float32).  Asynchronous on `stream`. */
 int galerkin_term_bwd(int batch, const nlsp_operator* A, int k, int m, const void* saved, const float* gJ,

@@ -87,7 +87,7 @@ SIGNATURES = {
     "galerkin_term_saved_bytes": (c_size_t, [c_int, POP, c_int, c_int]),
     "galerkin_term_workspace_bytes": (c_size_t, [c_int, POP, c_int, c_int]),
     "galerkin_term_fwd": (c_int, [c_int, POP, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
-                                  c_size_t, c_void_p, c_size_t, c_void_p]),
+                                  c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "galerkin_term_bwd": (c_int, [c_int, POP, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pcg_solve_batched_workspace_bytes": (c_size_t, [c_int, ctypes.POINTER(NlspSystem), c_int, c_int]),
     "pcg_solve_batched": (c_int, [c_int, ctypes.POINTER(NlspSystem), c_int, c_int, ctypes.POINTER(NlspPcgOpts),

@@ -536,7 +536,7 @@ def galerkin_term_workspace_bytes(batch: int, op: Operator, k: int, m: int) -> i
 def galerkin_term_fwd(op: Operator, P: torch.Tensor, S: torch.Tensor):
     """J_b = ||A^{1/2}(I - P A_c^{-1} P^T A) S||_F^2 per sample, P (batch, n, k)
     and S (batch, n, m) float32; ``op`` carries the batched coefficients.
-    Returns (J, bad, saved)."""
+    Returns (J, bad, saved, E) with E_b = ||A^{1/2} S_b||_F^2."""
     if P.dim() != 3 or S.dim() != 3 or P.shape[:2] != S.shape[:2]:
         raise ValueError("P must be (batch, n, k) and S (batch, n, m)")
     batch, n, k = P.shape
@@ -551,14 +551,15 @@ def galerkin_term_fwd(op: Operator, P: torch.Tensor, S: torch.Tensor):
     if sb == 0 or nb == 0:
         raise NlspError("galerkin_term_workspace_bytes", E_INVALID)
     J = torch.empty(batch, dtype=torch.float32, device=P.device)
+    E = torch.empty(batch, dtype=torch.float32, device=P.device)
     bad = torch.empty(batch, dtype=torch.int32, device=P.device)
     saved = _workspace(sb, P.device)
     ws = _workspace(nb, P.device)
     rc = _L().galerkin_term_fwd(batch, ctypes.byref(op.c()), _dev(P, torch.float32, "P"),
-                                _dev(S, torch.float32, "S"), k, m, J.data_ptr(), bad.data_ptr(),
+                                _dev(S, torch.float32, "S"), k, m, J.data_ptr(), E.data_ptr(), bad.data_ptr(),
                                 saved.data_ptr(), saved.numel(), ws.data_ptr(), ws.numel(), _stream())
     _check("galerkin_term_fwd", rc)
-    return J, bad, saved
+    return J, bad, saved, E
 
 
 def galerkin_term_bwd(op: Operator, k: int, m: int, saved: torch.Tensor, gJ: torch.Tensor) -> torch.Tensor:
@@ -572,24 +573,25 @@ def galerkin_term_bwd(op: Operator, k: int, m: int, saved: torch.Tensor, gJ: tor
 
 
 class GalerkinTerm(torch.autograd.Function):
-    """J(P) per sample with the library's backward."""
+    """J(P) per sample with the library's backward (E = ||A^{1/2} S||_F^2
+    and the flags receive no gradient)."""
 
     @staticmethod
     def forward(ctx, P, S, op):
-        J, bad, saved = galerkin_term_fwd(op, P.contiguous(), S.contiguous())
+        J, bad, saved, E = galerkin_term_fwd(op, P.contiguous(), S.contiguous())
         ctx.op, ctx.k, ctx.m = op, P.shape[2], S.shape[2]
         ctx.save_for_backward(saved)
-        ctx.mark_non_differentiable(bad)
-        return J, bad
+        ctx.mark_non_differentiable(bad, E)
+        return J, bad, E
 
     @staticmethod
-    def backward(ctx, gJ, gbad):
+    def backward(ctx, gJ, gbad, gE):
         (saved,) = ctx.saved_tensors
         return galerkin_term_bwd(ctx.op, ctx.k, ctx.m, saved, gJ.contiguous().to(torch.float32)), None, None
 
 
 def galerkin_term(P: torch.Tensor, S: torch.Tensor, op: Operator):
-    """Returns (J, bad); J is differentiable in P."""
+    """Returns (J, bad, E); J is differentiable in P."""
     return GalerkinTerm.apply(P, S, op)
 
 

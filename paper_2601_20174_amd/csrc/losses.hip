@@ -803,8 +803,8 @@ __global__ __launch_bounds__(NT) void k_gterm_rows(OpDev op, int64_t cstride, in
 // LDS (dynamic): R and R^-1 (QRK x QRK each), V and Z (k x m each).
 __global__ __launch_bounds__(NT) void k_gterm_finish(Dims d, int m, const double* __restrict__ T64,
                                                      const double* __restrict__ spart, int nspart,
-                                                     float* __restrict__ J, int* __restrict__ bad,
-                                                     float* __restrict__ Msave) {
+                                                     float* __restrict__ J, float* __restrict__ E,
+                                                     int* __restrict__ bad, float* __restrict__ Msave) {
   extern __shared__ double glds[];
   double* G = glds;                 // R (upper), then H = Z Z^T
   double* Xi = G + QRK * QRK;       // R^-1 (upper)
@@ -847,7 +847,10 @@ __global__ __launch_bounds__(NT) void k_gterm_finish(Dims d, int m, const double
     vv += V[e] * V[e];
   }
   vv = block_sum(vv, sh);
-  if (t == 0) J[b] = (float)(tr - vv);
+  if (t == 0) {
+    J[b] = (float)(tr - vv);
+    if (E) E[b] = (float)tr;
+  }
   // H = Z Z^T (k x k) into G
   for (int e = t; e < k * k; e += NT) {
     const int i = e / k, j = e % k;
@@ -1222,7 +1225,8 @@ size_t galerkin_term_workspace_bytes(int batch, const nlsp_operator* A, int k, i
 }
 
 int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const float* S, int k, int m, float* J,
-                      int* bad, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes, void* stream) {
+                      float* E, int* bad, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes,
+                      void* stream) {
   const int64_t n = op_size(A);
   if (n < 1 || !gterm_ok(batch, n, k, m) || !P || !S || !J || !bad || !saved) return NLSP_E_INVALID;
   const GtermSaved G = carve_gterm(nullptr, batch, n, k, m);
@@ -1262,7 +1266,7 @@ int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const f
   const Dims db = gterm_bwd_dims(batch, (int)n, k, m);
   Dims df = d;
   df.cols = db.cols;   // the finishing kernel writes M with the backward's row count
-  hipLaunchKernelGGL(k_gterm_finish, dim3(batch), dim3(NT), lds, s, df, m, L.T64, spart, nb, J, bad, Gs.M);
+  hipLaunchKernelGGL(k_gterm_finish, dim3(batch), dim3(NT), lds, s, df, m, L.T64, spart, nb, J, E, bad, Gs.M);
   NLSP_HIP(hipGetLastError());
   return NLSP_OK;
 }

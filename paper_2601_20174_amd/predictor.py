@@ -4,10 +4,15 @@ loop only; every arithmetic step runs in libnlsp.so kernels).
 One training step on a batch of fields:
     P_hat = CNN(coef; params)           cnn_fwd
     Q     = qf(P_hat)                   qr_thin_fwd (CholeskyQR2)
-    L     = mean_b NLSS(Q_b; B_b)       subspace_loss_fwd with the NLSS column
+    L     = mean_b [ NLSS(Q_b; B_b)     subspace_loss_fwd with the NLSS column
                                         weights (k - j + 1)/k
-and the backward through subspace_loss_bwd, qr_thin_bwd and cnn_bwd, then
-one Adam step (adam_step).  B_b are the relaxed random vectors of field b.
+                   + beta J_b(Q_b) / ||A_b^{1/2} B_b||_F^2 ]
+                                        galerkin_term_fwd (the appendix's
+                                        Galerkin-convergence objective, scaled
+                                        by its value with no coarse space)
+and the backward through subspace_loss_bwd, galerkin_term_bwd, qr_thin_bwd
+and cnn_bwd, then one Adam step (adam_step).  B_b are the relaxed random
+vectors of field b, A_b its operator (2-D finite volumes, coefficient a_b).
 """
 from __future__ import annotations
 
@@ -59,13 +64,21 @@ class Predictor:
         Phat = api.CnnPredictor.apply(p, coef, self.N, self.k, self.hidden, ws)
         return api.thin_q(Phat)
 
-    def loss(self, coef: torch.Tensor, B: torch.Tensor, params: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def loss(self, coef: torch.Tensor, B: torch.Tensor, params: Optional[torch.Tensor] = None,
+             beta: float = 1.0) -> torch.Tensor:
+        """Mean over the batch of NLSS + beta J / ||A^{1/2} B||_F^2 (beta = 0:
+        NLSS alone)."""
         Q = self.basis(coef, params)
-        return api.subspace_loss(Q, B, self.nlss_weights()).mean()
+        L = api.subspace_loss(Q, B, self.nlss_weights())
+        if beta:
+            op = api.Operator(api.OP_FV5, self.N, self.N, 1, coef.reshape(-1))   # batched coefficients
+            J, _, E = api.galerkin_term(Q, B, op)
+            L = L + beta * J / E
+        return L.mean()
 
-    def step(self, coef: torch.Tensor, B: torch.Tensor, lr: float = 1e-3) -> float:
+    def step(self, coef: torch.Tensor, B: torch.Tensor, lr: float = 1e-3, beta: float = 1.0) -> float:
         p = self.params.detach().requires_grad_(True)
-        L = self.loss(coef, B, p)
+        L = self.loss(coef, B, p, beta)
         L.backward()
         self.steps += 1
         api.adam_step(self.params, p.grad, self.m, self.v, lr, self.steps)

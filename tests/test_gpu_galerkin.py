@@ -209,9 +209,9 @@ def test_galerkin_term_fwd_bwd(nl, kind, k, m):
     P32 = np.stack([np.linalg.qr(rng.standard_normal((n, k)))[0] for _ in range(batch)]).astype(np.float32)
     S32 = rng.standard_normal((batch, n, m)).astype(np.float32)
     gJ = torch.linspace(0.5, 1.5, batch, dtype=torch.float32, device="cuda")
-    J, bad, saved = nl.galerkin_term_fwd(op, torch.tensor(P32, device="cuda"), torch.tensor(S32, device="cuda"))
+    J, bad, saved, E = nl.galerkin_term_fwd(op, torch.tensor(P32, device="cuda"), torch.tensor(S32, device="cuda"))
     gP = host(nl.galerkin_term_bwd(op, k, m, saved, gJ))
-    J, bad, gJh = host(J), host(bad), host(gJ)
+    J, bad, gJh, E = host(J), host(bad), host(gJ), host(E)
     assert np.all(bad == 0)
     for b in range(batch):
         A, P, S = As[b], P32[b].astype(np.float64), S32[b].astype(np.float64)
@@ -219,6 +219,10 @@ def test_galerkin_term_fwd_bwd(nl, kind, k, m):
         gref = O.galerkin_term_grad(A, P, S)
         dJ, dg = _gterm_bounds(A, P, S)
         assert abs(J[b] - ref) <= 2 * dJ, (b, J[b], ref, dJ)
+        # E = tr(S^T A S) = J with no coarse space (float32 stencil products)
+        Eref = float(np.sum(S * (A @ S)))
+        dE = np.sum(np.abs(S) * (16 * U32 * (abs(A) @ np.abs(S)))) + U32 * abs(Eref)
+        assert abs(E[b] - Eref) <= 2 * dE, (b, E[b], Eref, dE)
         err = np.abs(gP[b] - gJh[b] * gref)
         assert np.all(err <= 2 * gJh[b] * dg + 1e-30), (b, err.max(), (gJh[b] * dg).max())
 
@@ -234,9 +238,9 @@ def test_galerkin_term_autograd_and_optimum(nl):
     P32 = np.stack([np.linalg.qr(rng.standard_normal((n, k)))[0] for _ in range(2)]).astype(np.float32)
     Pt = torch.tensor(P32, device="cuda", requires_grad=True)
     St = torch.tensor(S32, device="cuda")
-    J, bad = nl.galerkin_term(Pt, St, op)
+    J, bad, _ = nl.galerkin_term(Pt, St, op)
     (J * torch.tensor([1.0, 2.0], device="cuda")).sum().backward()
-    _, _, saved = nl.galerkin_term_fwd(op, Pt.detach(), St)
+    _, _, saved, _ = nl.galerkin_term_fwd(op, Pt.detach(), St)
     assert torch.equal(Pt.grad, nl.galerkin_term_bwd(op, k, m, saved, torch.tensor([1.0, 2.0], device="cuda")))
     # the optimum: P* = A^{-1/2} U_k spans the Galerkin-optimal subspace
     Popt = []

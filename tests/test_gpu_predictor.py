@@ -133,6 +133,71 @@ def test_adam(nl):
     np.testing.assert_allclose(host(pt), pr, rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_training_loss_and_gradient(nl, beta):
+    """The training loss mean_b [NLSS(Q_b; B_b) + beta J_b(Q_b) / ||A_b^{1/2}
+    B_b||_F^2], Q = qf(CNN(a)), and its parameter gradient (library forward
+    and backward of every piece) against the float64 oracle: the oracle's
+    CNN, QR, weighted-energy and Galerkin-term gradients chained by hand
+    (qr_backward, then autograd of its CNN).
+
+    The point is one the training passes through: B relaxed random vectors
+    (each side relaxes the same seeded vectors itself, the GPU in float32),
+    and a network output that is a small correction of Phi (last layer
+    scaled to 0.02; training starts from Phi).  There the Galerkin term's
+    gradient moves by about the relative perturbation of P_hat (a CPU probe:
+    0.1-0.7 % for 1-6e-3 perturbations of the network's part), whereas at a
+    random network far from Phi with unrelaxed B it moves 30-80 times more
+    (J / E near 1, a poorly conditioned comparison).  Bars: the loss to 1 %;
+    each layer's gradient as in test_cnn_backward (5 %: the backward's
+    bfloat16 products)."""
+    from paper_2601_20174_amd.predictor import Predictor
+    N, k, m, batch, hid = 32, 16, 24, 2, 16
+    coefs = _fields(batch, N, 50)
+    S0 = np.stack([W.normal_block(700 + b, N * N, m) for b in range(batch)])
+    pr = _params(k, hid, 7, scale=1.0)
+    co, ci = PR.layer_shapes(k, hid)[3]
+    pr[len(pr) - (co * ci * 9 + co):] *= 0.02
+    ct = torch.tensor(coefs, device="cuda")
+    Bs = []
+    for b in range(batch):
+        op = nl.Operator(nl.OP_FV5, N, N, 1, ct[b].contiguous())
+        x = torch.tensor(S0[b], dtype=torch.float32, device="cuda")
+        zero = torch.zeros_like(x)
+        for _ in range(10):
+            x = nl.jacobi_sweep_f32(op, 2 / 3, zero, x)
+        Bs.append(x)
+    pred = Predictor(N, k, hidden=hid, seed=0)
+    pred.params = torch.tensor(pr, device="cuda")
+    p = pred.params.detach().requires_grad_(True)
+    L = pred.loss(ct, torch.stack(Bs), p, beta=beta)
+    L.backward()
+    g, Lg = host(p.grad), float(L.detach())
+    # oracle
+    w = O.nlss_weights(k)
+    leaf, Phat = PR.cnn_forward(pr.astype(np.float64), coefs, N, k, hid, return_graph=True)
+    Ph = Phat.detach().numpy()
+    Lo, gPhat = 0.0, np.zeros_like(Ph)
+    for b in range(batch):
+        Q, R = PR.qf(Ph[b])
+        A = O.fv_harmonic_2d(coefs[b].reshape(N, N))
+        B = O.relax(A, S0[b].astype(np.float32).astype(np.float64), 2 / 3, 10)
+        E = float(np.sum(B * (A @ B)))
+        Lo += (O.weighted_energy_loss(Q, B, w) + beta * O.galerkin_term(A, Q, B) / E) / batch
+        gQ = (O.weighted_energy_loss_grad(Q, B, w) + beta * O.galerkin_term_grad(A, Q, B) / E) / batch
+        gPhat[b] = PR.qr_backward(Q, R, gQ)
+    (Phat * torch.tensor(gPhat)).sum().backward()
+    gr = leaf.grad.numpy()
+    assert abs(Lg - Lo) <= 1e-2 * abs(Lo), (Lg, Lo)
+    off = 0
+    for co, ci in PR.layer_shapes(k, hid):
+        for size in (co * ci * 9, co):
+            a, r = g[off:off + size], gr[off:off + size]
+            assert np.linalg.norm(a - r) <= 0.05 * np.linalg.norm(r), (off, size, np.linalg.norm(a - r) /
+                                                                        np.linalg.norm(r))
+            off += size
+
+
 def test_training_reduces_nlss_and_gives_a_working_preconditioner(nl):
     """Ten Adam steps on four 32^2 fields lower the NLSS loss, and the learned
     basis (orthonormal by construction) preconditions PCG to 1e-8."""

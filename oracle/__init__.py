@@ -22,7 +22,7 @@ losses     subspace loss, NLSS loss, Galerkin-convergence objective and
            their gradients
 """
 from .operators import (poisson5, fv_harmonic_2d, fv_harmonic_3d, q1_aniso_element,
-                        q1_aniso, jacobi_diag)
+                        q1_aniso, p1_element, p1_fem, jacobi_diag)
 from .method import (relax, spectral_basis, randomized_basis, galerkin, two_grid_apply, pcg, PCGResult,
                      setup, NOT_CONVERGED, OK, E_BREAKDOWN, E_NONFINITE, E_NOT_SPD,
                      E_INVALID)
@@ -34,7 +34,7 @@ from .losses import (subspace_loss, subspace_loss_grad, nlss_loss, nlss_weights,
 
 __all__ = [
     "predictor",
-    "poisson5", "fv_harmonic_2d", "fv_harmonic_3d", "q1_aniso_element", "q1_aniso",
+    "poisson5", "fv_harmonic_2d", "fv_harmonic_3d", "q1_aniso_element", "q1_aniso", "p1_element", "p1_fem",
     "jacobi_diag", "relax", "spectral_basis", "randomized_basis", "galerkin", "two_grid_apply", "pcg",
     "PCGResult", "setup", "OK", "NOT_CONVERGED", "E_BREAKDOWN", "E_NONFINITE",
     "E_NOT_SPD", "E_INVALID", "subspace_loss", "subspace_loss_grad", "nlss_loss",

@@ -15,6 +15,11 @@ same families, each assembled from its defining formula into a
 * ``q1_aniso``       bilinear (Q1) finite elements for -div(K grad u) with a
                      constant tensor K = R(theta) diag(1, eps) R(theta)^T on a
                      uniform grid; boundary nodes eliminated (9-point).
+* ``p1_fem``         the paper's own discretisation (FEM dataset appendix):
+                     linear (P1) elements on a triangulation, stiffness
+                     |T| g_i^T K_T g_j and mass |T|/12 [2 1 1; 1 2 1; 1 1 2]
+                     per triangle, A = sK K + sM M, Dirichlet vertices by
+                     zeroing their rows and columns with a unit diagonal.
 
 Unknowns are ordered x fastest: index = x + nx*(y + ny*z).  No 1/h^2 or area
 scaling is applied (PCG iterates are invariant under A -> cA, f -> cf).
@@ -25,7 +30,7 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["poisson5", "fv_harmonic_2d", "fv_harmonic_3d", "q1_aniso_element",
-           "q1_aniso", "jacobi_diag"]
+           "q1_aniso", "p1_element", "p1_fem", "jacobi_diag"]
 
 
 def poisson5(N: int, Ny: int | None = None) -> sp.csr_matrix:
@@ -144,6 +149,54 @@ def q1_aniso(side: int, eps: float, theta: float) -> sp.csr_matrix:
     Afull = sp.csr_matrix(sp.coo_matrix((v, (r, c)), shape=(nn * nn, nn * nn)))
     interior = node[1:-1, 1:-1].ravel()
     return sp.csr_matrix(Afull[interior][:, interior])
+
+
+def p1_element(p: np.ndarray, K: np.ndarray):
+    """Local stiffness and mass matrices of one linear triangle (FEM dataset
+    appendix): vertices p (3, 2) counter-clockwise, tensor K (2, 2).  The
+    basis gradients are constant: with 2|T| = (x1-x0)(y2-y0) - (x2-x0)(y1-y0),
+    grad phi_a = (y_{a+1} - y_{a+2}, x_{a+2} - x_{a+1}) / (2|T|) (indices mod
+    3).  Returns (K_T (3, 3) = |T| g K g^T, M_T (3, 3) = |T|/12 [2 1 1; 1 2 1;
+    1 1 2])."""
+    x, y = p[:, 0], p[:, 1]
+    a2 = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0])
+    area = 0.5 * a2
+    g = np.empty((3, 2))
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        g[a] = [(y[b] - y[c]) / a2, (x[c] - x[b]) / a2]
+    Ke = np.empty((3, 3))
+    for a in range(3):
+        for b in range(3):
+            Ke[a, b] = area * (g[a] @ K @ g[b])
+    Me = area / 12.0 * np.array([[2.0, 1.0, 1.0], [1.0, 2.0, 1.0], [1.0, 1.0, 2.0]])
+    return Ke, Me
+
+
+def p1_fem(points: np.ndarray, tris: np.ndarray, ktensor: np.ndarray, sK: float, sM: float,
+           boundary: np.ndarray) -> sp.csr_matrix:
+    """A = sK K + sM M assembled over the triangles (element by element, plain
+    sums), then every boundary vertex's row and column set to zero and its
+    diagonal to one (the appendix's Dirichlet treatment).  ktensor (nt, 3)
+    holds [Kxx, Kxy, Kyy] per triangle."""
+    n = points.shape[0]
+    rows, cols, vals = [], [], []
+    for t in range(tris.shape[0]):
+        idx = tris[t]
+        K = np.array([[ktensor[t, 0], ktensor[t, 1]], [ktensor[t, 1], ktensor[t, 2]]])
+        Ke, Me = p1_element(points[idx], K)
+        Ae = sK * Ke + sM * Me
+        for a in range(3):
+            for b in range(3):
+                rows.append(idx[a])
+                cols.append(idx[b])
+                vals.append(Ae[a, b])
+    A = sp.csr_matrix(sp.coo_matrix((vals, (rows, cols)), shape=(n, n)))
+    keep = sp.diags((boundary == 0).astype(np.float64))
+    A = keep @ A @ keep + sp.diags((boundary != 0).astype(np.float64))
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    return A
 
 
 def jacobi_diag(A: sp.spmatrix) -> np.ndarray:

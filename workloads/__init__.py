@@ -20,6 +20,13 @@ benchmark PDEs):
                  system, and a grid side per system.
 * ``checker3d``  a 3-D piecewise-constant coefficient, 16^3-cell blocks drawn
                  i.i.d. from {1, 1e3}.
+* ``p1``         the paper's own families on unstructured meshes (the FEM
+                 dataset appendix): a jittered Delaunay triangulation of the
+                 unit square and, per triangle, the coefficient draws of the
+                 diffusion, anisotropic, screened Poisson, heat and wave
+                 benchmarks.  The mesh and the draws only: assembly of the
+                 stiffness and mass matrices is the method's (oracle and GPU
+                 each do their own).
 """
 from __future__ import annotations
 
@@ -28,8 +35,8 @@ import numpy as np
 
 __all__ = [
     "seed_for", "normal_block", "uniform_block", "grf_field", "lognormal_field",
-    "checkerboard_3d", "aniso_batch", "Cfg1", "Cfg2", "Cfg3", "Cfg4", "Cfg5",
-    "CfgPaper", "CONFIGS",
+    "checkerboard_3d", "aniso_batch", "p1_mesh", "p1_coefficients", "P1_FAMILIES", "Cfg1", "Cfg2",
+    "Cfg3", "Cfg4", "Cfg5", "CfgPaper", "CfgFem", "CONFIGS",
 ]
 
 COEF, S0, RHS = 0, 1, 2
@@ -114,6 +121,73 @@ def aniso_batch(seed: int, nsys: int, sides=ANISO_SIDES):
     eps = 10.0 ** rng.uniform(-3.0, 0.0, size=nsys)
     theta = rng.uniform(0.0, np.pi, size=nsys)
     return side, eps, theta
+
+
+# ------------------------------------------------------ unstructured meshes
+def p1_mesh(seed: int, N: int):
+    """Jittered Delaunay triangulation of [0,1]^2 (the FEM dataset appendix,
+    common mesh setup): the (N+1)^2 grid points (i/N, j/N), vertex index
+    i + (N+1) j; boundary vertices fixed, interior vertex p moved by
+    xi ~ U([-e, e]^2) with e = min(0.35 h, 0.49 d), h = 1/N, d the distance
+    of p to the boundary; Delaunay triangulation of the moved points;
+    triangles of near-zero signed area (|2 area| <= 1e-12 h^2) removed; every
+    triangle ordered counter-clockwise.
+    Returns (points (np, 2) float64, tris (nt, 3) int32, boundary (np,) uint8)."""
+    from scipy.spatial import Delaunay
+    h = 1.0 / N
+    j, i = np.meshgrid(np.arange(N + 1), np.arange(N + 1), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    pts = np.stack([i * h, j * h], axis=1)
+    bnd = ((i == 0) | (i == N) | (j == 0) | (j == N)).astype(np.uint8)
+    d = np.minimum(np.minimum(pts[:, 0], 1.0 - pts[:, 0]), np.minimum(pts[:, 1], 1.0 - pts[:, 1]))
+    e = np.minimum(0.35 * h, 0.49 * d)
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=pts.shape) * e[:, None]
+    pts = pts + xi * (bnd == 0)[:, None]
+    tris = Delaunay(pts).simplices.astype(np.int64)
+    p0, p1, p2 = pts[tris[:, 0]], pts[tris[:, 1]], pts[tris[:, 2]]
+    a2 = (p1[:, 0] - p0[:, 0]) * (p2[:, 1] - p0[:, 1]) - (p2[:, 0] - p0[:, 0]) * (p1[:, 1] - p0[:, 1])
+    keep = np.abs(a2) > 1e-12 * h * h
+    tris, a2 = tris[keep], a2[keep]
+    flip = a2 < 0
+    tris[flip, 1], tris[flip, 2] = tris[flip, 2].copy(), tris[flip, 1].copy()
+    return np.ascontiguousarray(pts), np.ascontiguousarray(tris.astype(np.int32)), bnd
+
+
+P1_FAMILIES = ("diffusion", "anisotropic", "screened_poisson", "heat", "wave")
+
+
+def p1_coefficients(family: str, seed: int, nt: int, N: int):
+    """Per-triangle coefficient draws of one benchmark family (FEM dataset
+    appendix): returns (ktensor (nt, 3) = [Kxx, Kxy, Kyy] of the diffusion
+    tensor per triangle, sK, sM) for the matrix A = sK K(ktensor) + sM M.
+      diffusion         kappa_T = exp(eta), eta ~ N(0, 1.5^2); A = K
+      anisotropic       theta_T ~ U(0, pi), K_T = R diag(1e3, 1) R^T; A = K
+      screened_poisson  kappa_T = exp(N(0, 1)), alpha = 10^U(0, 2); A = K + alpha M
+      heat              kappa_T = exp(N(0, 1)), dt = 10^U(-2, 0); A = M + dt K
+      wave              kappa_T = exp(N(0, 1.5^2)), c = 10^U(2, 3),
+                        dt ~ U(h, 2h); A = M + (c dt)^2 K"""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / N
+    if family == "anisotropic":
+        th = rng.uniform(0.0, np.pi, size=nt)
+        c, s = np.cos(th), np.sin(th)
+        kt = np.stack([1e3 * c * c + s * s, (1e3 - 1.0) * c * s, 1e3 * s * s + c * c], axis=1)
+        return kt, 1.0, 0.0
+    sig = 1.5 if family in ("diffusion", "wave") else 1.0
+    kappa = np.exp(rng.normal(0.0, sig, size=nt))
+    kt = np.stack([kappa, np.zeros(nt), kappa], axis=1)
+    if family == "diffusion":
+        return kt, 1.0, 0.0
+    if family == "screened_poisson":
+        return kt, 1.0, float(10.0 ** rng.uniform(0.0, 2.0))
+    if family == "heat":
+        return kt, float(10.0 ** rng.uniform(-2.0, 0.0)), 1.0
+    if family == "wave":
+        c = 10.0 ** rng.uniform(2.0, 3.0)
+        dt = rng.uniform(h, 2.0 * h)
+        return kt, float((c * dt) ** 2), 1.0
+    raise ValueError(family)
 
 
 # ---------------------------------------------------------------- configurations
@@ -274,4 +348,39 @@ class CfgPaper:
         return normal_block(seed_for(self.cfg, RHS), self.n, self.R)
 
 
-CONFIGS = {1: Cfg1, 2: Cfg2, 3: Cfg3, 4: Cfg4, 5: Cfg5, 9: CfgPaper}
+@dataclasses.dataclass(frozen=True)
+class CfgFem:
+    """The paper's own workload shape: P1 finite elements on a jittered
+    Delaunay mesh of [0,1]^2 with (N+1)^2 vertices (N = 64: n = 4225), one of
+    the five benchmark families, identity rows for the Dirichlet boundary;
+    K = 72 smoothed test vectors, rank k = 48, nu = 5 sweeps with omega = 0.66,
+    relative tolerance 1e-6 (the paper's PCG settings)."""
+    cfg: int = 6
+    N: int = 64
+    m: int = 72
+    k: int = 48
+    s1: int = 10
+    omega: float = 0.66
+    nu: int = 5
+    R: int = 1
+    rtol: float = 1e-6
+
+    @property
+    def n(self):
+        return (self.N + 1) ** 2
+
+    def mesh(self, i: int = 0):
+        return p1_mesh(seed_for(self.cfg, COEF, i), self.N)
+
+    def coefficients(self, family: str, nt: int, i: int = 0):
+        return p1_coefficients(family, seed_for(self.cfg, COEF, i) + 5 + 100 * P1_FAMILIES.index(family), nt,
+                               self.N)
+
+    def S0(self, i: int = 0):
+        return normal_block(seed_for(self.cfg, S0, i), self.n, self.m)
+
+    def rhs(self, i: int = 0):
+        return normal_block(seed_for(self.cfg, RHS, i), self.n, self.R)
+
+
+CONFIGS = {1: Cfg1, 2: Cfg2, 3: Cfg3, 4: Cfg4, 5: Cfg5, 6: CfgFem, 9: CfgPaper}

@@ -45,6 +45,8 @@ def _args():
                     help="solver kernel for the roofline (0 = pick the slowest)")
     ap.add_argument("--spmv-leg", action="store_true",
                     help="only run the stand-alone operator kernels on the 3-D workload and exit")
+    ap.add_argument("--batched-leg", action="store_true",
+                    help="run only the batched anisotropic leg (for profiling it on its own)")
     ap.add_argument("--solve3d-leg", action="store_true",
                     help="only run the 3-D setup + solve leg (mixed and float64) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -100,6 +102,9 @@ def main():
         return
     if a.solve3d_leg:
         print(json.dumps({"solve3d": solve3d_leg(nl, torch, dev)}), flush=True)
+        return
+    if a.batched_leg:
+        print(json.dumps({"batched": batched_legs(nl, torch, dev)}), flush=True)
         return
     c = W.Cfg2(N=a.N)
     n, m, k = c.n, c.m, c.k

@@ -62,14 +62,20 @@ enum nlsp_op_kind {
   NLSP_OP_FV5 = 1,        /* 2-D cell-centred FV for -div(a grad u): face weight = harmonic mean
                              2 a_P a_Q / (a_P + a_Q); wall face 2 a_P.  coef = a, (ny, nx) */
   NLSP_OP_FV7 = 2,        /* the same in 3-D, 7-point; coef = a, (nz, ny, nx) */
-  NLSP_OP_STENCIL9 = 3    /* 2-D constant 9-point stencil; coef = 9 doubles c[(dy+1)*3 + (dx+1)],
+  NLSP_OP_STENCIL9 = 3,   /* 2-D constant 9-point stencil; coef = 9 doubles c[(dy+1)*3 + (dx+1)],
                              (A u)_(x,y) = sum c[..] u_(x+dx, y+dy), terms outside the grid dropped */
+  NLSP_OP_CSR = 4         /* a general sparse SPD matrix in compressed rows (e.g. the P1 finite
+                             elements of p1_assemble): n = nx rows (ny = nz = 1); row_ptr (n + 1)
+                             and col_idx (nnz) int32, coef = values (nnz) float64; every row holds
+                             its diagonal entry, which must be positive */
 };
 
 typedef struct {
   int kind;               /* enum nlsp_op_kind */
-  int nx, ny, nz;         /* unknowns per axis; nz = 1 for 2-D kinds */
+  int nx, ny, nz;         /* unknowns per axis; nz = 1 for 2-D kinds; NLSP_OP_CSR: nx = n, ny = nz = 1 */
   const double* coef;     /* device; see kind; NULL for NLSP_OP_POISSON5 */
+  const int* row_ptr;     /* device, NLSP_OP_CSR only (else ignored) */
+  const int* col_idx;     /* device, NLSP_OP_CSR only (else ignored) */
 } nlsp_operator;
 
 /* Number of unknowns n = nx*ny*nz, or -1 for an invalid descriptor. */
@@ -84,6 +90,41 @@ int64_t nlsp_operator_size(const nlsp_operator* A);
  *   stencil    device, (nsys, 9): output, layout of NLSP_OP_STENCIL9
  * Asynchronous. */
 int q1_aniso_stencil(int nsys, const double* eps_theta, double* stencil, void* stream);
+
+/* ------------------------------------------------- P1 finite elements */
+/* The paper's own discretisation (FEM dataset appendix): linear elements on a
+ * triangulation with per-triangle tensor K_T, local stiffness
+ * |T| g_a^T K_T g_b (g the constant basis gradients) and mass
+ * |T|/12 [2 1 1; 1 2 1; 1 1 2], A = sK K + sM M, Dirichlet vertices by zeroing
+ * their rows and columns and a unit diagonal.  Built in two calls:
+ *
+ * p1_pattern (host): the compressed-row pattern of A and, for every stored
+ * entry, the list of element contributions to it (code 9 t + 3 a + b:
+ * triangle t, local row a, local column b), in increasing triangle order.  A
+ * boundary vertex's row holds only its diagonal; couplings to it are dropped.
+ *   tris      host (nt, 3) vertex indices, counter-clockwise
+ *   boundary  host (np) 1 for a Dirichlet vertex
+ *   nnz, ncontrib   host out: sizes (call with the four arrays NULL first)
+ *   row_ptr (np + 1), col_idx (nnz), cptr (nnz + 1), clist (ncontrib): host
+ *   outputs, or all NULL for the sizes only
+ * Columns of a row ascend.  Returns NLSP_E_INVALID for an index out of range
+ * or sizes beyond int32. */
+int p1_pattern(int np, int nt, const int* tris, const unsigned char* boundary, int64_t* nnz,
+               int64_t* ncontrib, int* row_ptr, int* col_idx, int* cptr, int* clist);
+
+/* p1_assemble (device): the values of A on the pattern above, one thread
+ * per row summing its contributions in the listed order (deterministic;
+ * every local matrix is formed in a form symmetric in a, b, so A is exactly
+ * symmetric).
+ *   points   device (np, 2) float64      tris   device (nt, 3) int32
+ *   ktensor  device (nt, 3) float64: [Kxx, Kxy, Kyy] per triangle
+ *   sK, sM   stiffness and mass scales   boundary device (np) uint8
+ *   row_ptr, col_idx, cptr, clist   device copies of p1_pattern's outputs
+ *   vals     device (nnz) float64, output (coef of an NLSP_OP_CSR operator)
+ * Asynchronous on `stream`. */
+int p1_assemble(int np, int nt, const double* points, const int* tris, const double* ktensor, double sK,
+                double sM, const unsigned char* boundary, const int* row_ptr, const int* col_idx,
+                const int* cptr, const int* clist, double* vals, void* stream);
 
 /* y = A x in float64 for R right-hand sides; x, y device (n, R).  Asynchronous. */
 int apply_operator(const nlsp_operator* A, const double* x, double* y, int R, void* stream);

@@ -17,7 +17,8 @@ c_int, c_double, c_size_t, c_void_p, c_int64 = (ctypes.c_int, ctypes.c_double, c
 
 
 class NlspOperator(ctypes.Structure):
-    _fields_ = [("kind", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("coef", c_void_p)]
+    _fields_ = [("kind", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("coef", c_void_p),
+                ("row_ptr", c_void_p), ("col_idx", c_void_p)]
 
 
 class NlspTwoLevel(ctypes.Structure):
@@ -54,6 +55,10 @@ SIGNATURES = {
     "nlsp_operator_size": (c_int64, [POP]),
     "nlsp_padded_rank": (c_int, [c_int]),
     "q1_aniso_stencil": (c_int, [c_int, c_void_p, c_void_p, c_void_p]),
+    "p1_pattern": (c_int, [c_int, c_int, c_void_p, c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64),
+                           c_void_p, c_void_p, c_void_p, c_void_p]),
+    "p1_assemble": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p,
+                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "apply_operator": (c_int, [POP, c_void_p, c_void_p, c_int, c_void_p]),
     "jacobi_sweep_f32": (c_int, [POP, c_double, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "setup_spectral_P_workspace_bytes": (c_size_t, [POP, c_int, c_int, c_int]),

@@ -18,7 +18,7 @@ from . import _lib
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOT_SPD, E_BREAKDOWN, E_NONFINITE, E_WORKSPACE, E_HIP, E_RANK = -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED, MIXED_F16 = 0, 1, 2
-OP_POISSON5, OP_FV5, OP_FV7, OP_STENCIL9 = 0, 1, 2, 3
+OP_POISSON5, OP_FV5, OP_FV7, OP_STENCIL9, OP_CSR = 0, 1, 2, 3, 4
 
 
 class NlspError(RuntimeError):
@@ -58,6 +58,14 @@ def _op_checked(op: "Operator") -> "Operator":
     kind reads (the library cannot see buffer lengths)."""
     if op.nx < 1 or op.ny < 1 or op.nz < 1:
         raise ValueError(f"operator extents must be positive, got {op.nx} x {op.ny} x {op.nz}")
+    if op.kind == OP_CSR:
+        if op.ny != 1 or op.nz != 1:
+            raise ValueError("a compressed-row operator has nx = n rows and ny = nz = 1")
+        if op.row_ptr is None or op.col_idx is None or op.coef is None:
+            raise ValueError("a compressed-row operator needs row_ptr, col_idx and coef")
+        if op.row_ptr.numel() != op.n + 1 or op.col_idx.numel() != op.coef.numel():
+            raise ValueError(f"compressed rows: row_ptr must hold {op.n + 1} entries and col_idx as many as coef")
+        return op
     per = {OP_FV5: op.n, OP_FV7: op.n, OP_STENCIL9: 9}.get(op.kind)
     if per is not None and (op.coef is None or op.coef.numel() != per):
         got = None if op.coef is None else op.coef.numel()
@@ -88,14 +96,17 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 @dataclasses.dataclass
 class Operator:
-    """Matrix-free operator descriptor (see nlsp_operator).  ``coef`` is a GPU
-    float64 tensor: the cell coefficient a for OP_FV5/OP_FV7, 9 stencil
-    values for OP_STENCIL9, None for OP_POISSON5."""
+    """Operator descriptor (see nlsp_operator).  ``coef`` is a GPU float64
+    tensor: the cell coefficient a for OP_FV5/OP_FV7, 9 stencil values for
+    OP_STENCIL9, None for OP_POISSON5, the values for OP_CSR (with row_ptr
+    (n + 1) and col_idx (nnz) int32 GPU tensors; nx = n, ny = nz = 1)."""
     kind: int
     nx: int
     ny: int
     nz: int = 1
     coef: Optional[torch.Tensor] = None
+    row_ptr: Optional[torch.Tensor] = None
+    col_idx: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
@@ -107,7 +118,9 @@ class Operator:
 
     def c(self) -> _lib.NlspOperator:
         ptr = _dev(self.coef, torch.float64, "coef") if self.coef is not None else None
-        return _lib.NlspOperator(self.kind, self.nx, self.ny, self.nz, ptr)
+        rp = _dev(self.row_ptr, torch.int32, "row_ptr") if self.row_ptr is not None else None
+        ci = _dev(self.col_idx, torch.int32, "col_idx") if self.col_idx is not None else None
+        return _lib.NlspOperator(self.kind, self.nx, self.ny, self.nz, ptr, rp, ci)
 
 
 def nlsp_operator_size(op: Operator) -> int:
@@ -116,6 +129,43 @@ def nlsp_operator_size(op: Operator) -> int:
 
 def nlsp_padded_rank(k: int) -> int:
     return int(_L().nlsp_padded_rank(int(k)))
+
+
+def p1_operator(points, tris, boundary, ktensor: torch.Tensor, sK: float, sM: float, device=None) -> Operator:
+    """The P1 finite-element operator A = sK K + sM M of a triangulation as an
+    OP_CSR descriptor: p1_pattern on the host (points, tris, boundary are
+    numpy arrays: (np, 2) float64, (nt, 3) int32, (np,) uint8), its arrays
+    copied to the GPU, then p1_assemble there.  ktensor (nt, 3) float64 on the
+    GPU: [Kxx, Kxy, Kyy] per triangle."""
+    import numpy as np
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    bnd = np.ascontiguousarray(boundary, dtype=np.uint8)
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    npt, nt = pts.shape[0], tris.shape[0]
+    if pts.shape != (npt, 2) or tris.shape != (nt, 3) or bnd.shape != (npt,):
+        raise ValueError("points (np, 2), tris (nt, 3) and boundary (np,) expected")
+    if tuple(ktensor.shape) != (nt, 3):
+        raise ValueError("ktensor must be (nt, 3)")
+    L = _L()
+    nnz, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check("p1_pattern", L.p1_pattern(npt, nt, tris.ctypes.data, bnd.ctypes.data, ctypes.byref(nnz),
+                                      ctypes.byref(nc), None, None, None, None))
+    rp = np.empty(npt + 1, dtype=np.int32)
+    ci = np.empty(nnz.value, dtype=np.int32)
+    cp = np.empty(nnz.value + 1, dtype=np.int32)
+    cl = np.empty(max(nc.value, 1), dtype=np.int32)
+    _check("p1_pattern", L.p1_pattern(npt, nt, tris.ctypes.data, bnd.ctypes.data, ctypes.byref(nnz),
+                                      ctypes.byref(nc), rp.ctypes.data, ci.ctypes.data, cp.ctypes.data,
+                                      cl.ctypes.data))
+    dev = ktensor.device if device is None else device
+    g = {name: torch.from_numpy(a).to(dev) for name, a in
+         (("rp", rp), ("ci", ci), ("cp", cp), ("cl", cl), ("pts", pts), ("tris", tris), ("bnd", bnd))}
+    vals = torch.empty(nnz.value, dtype=torch.float64, device=dev)
+    _check("p1_assemble", L.p1_assemble(npt, nt, g["pts"].data_ptr(), g["tris"].data_ptr(),
+                                        _dev(ktensor, torch.float64, "ktensor"), float(sK), float(sM),
+                                        g["bnd"].data_ptr(), g["rp"].data_ptr(), g["ci"].data_ptr(),
+                                        g["cp"].data_ptr(), g["cl"].data_ptr(), vals.data_ptr(), _stream()))
+    return Operator(OP_CSR, npt, 1, 1, vals, g["rp"], g["ci"])
 
 
 def q1_aniso_stencil(eps_theta: torch.Tensor) -> torch.Tensor:

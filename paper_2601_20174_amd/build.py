@@ -19,7 +19,7 @@ FLAGS = [
     # with some of their forms)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-SOURCES = ["operators.hip", "pcg.hip", "setup.hip", "losses.hip", "cnn.hip"]
+SOURCES = ["operators.hip", "pcg.hip", "setup.hip", "losses.hip", "cnn.hip", "fem.hip"]
 
 
 def _compile(src: str) -> str:

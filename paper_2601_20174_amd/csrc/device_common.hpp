@@ -70,6 +70,9 @@ struct OpDev {
   // are what op_row would form, bit for bit (the mean is commutative).
   Glob<const double>* fw64;
   Glob<const float>* fw32;
+  // compressed rows (NLSP_OP_CSR): entries rp[i] .. rp[i+1] - 1 of row i
+  Glob<const int>* rp;
+  Glob<const int>* ci;
 };
 
 inline OpDev make_op(const nlsp_operator& a) {
@@ -84,6 +87,8 @@ inline OpDev make_op(const nlsp_operator& a) {
   o.fxy = make_fastdiv((uint32_t)o.nx * (uint32_t)o.ny);
   o.fw64 = nullptr;
   o.fw32 = nullptr;
+  o.rp = (a.kind == NLSP_OP_CSR) ? as_glob(a.row_ptr) : nullptr;
+  o.ci = (a.kind == NLSP_OP_CSR) ? as_glob(a.col_idx) : nullptr;
   return o;
 }
 
@@ -161,6 +166,13 @@ NLSP_DEV T op_row(const OpDev& op, int64_t i, int x, int y, int z, V v, T vzm = 
       }
       return d * v(i) - s;
     }
+    case NLSP_OP_CSR: {
+      // the row's entries in stored order (a data-dependent trip count)
+      const int e0 = op.rp[i], e1 = op.rp[i + 1];
+      T s = T(0);
+      for (int e = e0; e < e1; ++e) s += T(op.coef[e]) * v(op.ci[e]);
+      return s;
+    }
     default: {  // NLSP_OP_STENCIL9
       const auto c = op.coef;
       T s = T(0);
@@ -203,6 +215,13 @@ NLSP_DEV T op_diag(const OpDev& op, int64_t i, int x, int y, int z) {
         face(z > 0, i - sxy);
         face(z < op.nz - 1, i + sxy);
       }
+      return d;
+    }
+    case NLSP_OP_CSR: {
+      const int e0 = op.rp[i], e1 = op.rp[i + 1];
+      T d = T(0);
+      for (int e = e0; e < e1; ++e)
+        if (op.ci[e] == (int)i) d = T(op.coef[e]);
       return d;
     }
     default:

@@ -51,6 +51,9 @@ inline int64_t op_size_raw(const nlsp_operator* A) {
     case NLSP_OP_FV7:
       if (!A->coef || A->nz < 1) return -1;
       return (int64_t)A->nx * A->ny * A->nz;
+    case NLSP_OP_CSR:
+      if (!A->coef || !A->row_ptr || !A->col_idx || A->ny != 1 || A->nz != 1) return -1;
+      return (int64_t)A->nx;
     default:
       return -1;
   }

@@ -652,6 +652,10 @@ inline bool gal_ok(int batch, int64_t n, int k) {
   return d.ntiles <= MAX_TILES && fwd_lds(d) <= LDS_MAX && bwd_lds(gal_bwd_dims(batch, (int)n, k)) <= LDS_MAX;
 }
 
+// Size of a batched operator: the training kernels take structured grids
+// only (a compressed-row operator is rejected).
+inline int64_t batched_op_size(const nlsp_operator* A) { return (A && A->kind == NLSP_OP_CSR) ? -1 : op_size(A); }
+
 // coefficient values per sample of a batched operator
 inline int64_t coef_stride(const nlsp_operator& a, int64_t n) {
   switch (a.kind) {
@@ -1071,14 +1075,14 @@ int captured_energy(int batch, int n, int k, int m, const float* P, const float*
 }
 
 size_t galerkin_fwd_workspace_bytes(int batch, const nlsp_operator* A, int k) {
-  const int64_t n = op_size(A);
+  const int64_t n = batched_op_size(A);
   if (n < 1 || !gal_ok(batch, n, k)) return 0;
   return carve_sub(nullptr, batch, gal_fwd_dims(batch, (int)n, k)).bytes;
 }
 
 int galerkin_fwd(int batch, const nlsp_operator* A, const float* P, int k, float* Ac, float* Y, void* ws,
                  size_t ws_bytes, void* stream) {
-  const int64_t n = op_size(A);
+  const int64_t n = batched_op_size(A);
   if (n < 1 || !gal_ok(batch, n, k) || !P || !Ac || !Y || P == Y) return NLSP_E_INVALID;
   Dims d = gal_fwd_dims(batch, (int)n, k);
   if (!aligned16(P) || !aligned16(Y)) d.vec = 0;
@@ -1212,13 +1216,13 @@ inline GtermSaved carve_gterm(void* saved, int batch, int64_t n, int k, int m) {
 }
 
 size_t galerkin_term_saved_bytes(int batch, const nlsp_operator* A, int k, int m) {
-  const int64_t n = op_size(A);
+  const int64_t n = batched_op_size(A);
   if (n < 1 || !gterm_ok(batch, n, k, m)) return 0;
   return carve_gterm(nullptr, batch, n, k, m).bytes;
 }
 
 size_t galerkin_term_workspace_bytes(int batch, const nlsp_operator* A, int k, int m) {
-  const int64_t n = op_size(A);
+  const int64_t n = batched_op_size(A);
   if (n < 1 || !gterm_ok(batch, n, k, m)) return 0;
   const SubLayout L = carve_sub(nullptr, batch, gterm_fwd_dims(batch, (int)n, k, m));
   return align_up(L.bytes) + align_up((size_t)batch * gterm_apply_blocks(n, k, m) * sizeof(double));
@@ -1227,7 +1231,7 @@ size_t galerkin_term_workspace_bytes(int batch, const nlsp_operator* A, int k, i
 int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const float* S, int k, int m, float* J,
                       float* E, int* bad, void* saved, size_t saved_nbytes, void* ws, size_t ws_bytes,
                       void* stream) {
-  const int64_t n = op_size(A);
+  const int64_t n = batched_op_size(A);
   if (n < 1 || !gterm_ok(batch, n, k, m) || !P || !S || !J || !bad || !saved) return NLSP_E_INVALID;
   const GtermSaved G = carve_gterm(nullptr, batch, n, k, m);
   if (saved_nbytes < G.bytes || reinterpret_cast<uintptr_t>(saved) % WS_ALIGN) return NLSP_E_WORKSPACE;
@@ -1273,7 +1277,7 @@ int galerkin_term_fwd(int batch, const nlsp_operator* A, const float* P, const f
 
 int galerkin_term_bwd(int batch, const nlsp_operator* A, int k, int m, const void* saved, const float* gJ,
                       float* gP, void* stream) {
-  const int64_t n = op_size(A);
+  const int64_t n = batched_op_size(A);
   if (n < 1 || !gterm_ok(batch, n, k, m) || !saved || !gJ || !gP) return NLSP_E_INVALID;
   if (reinterpret_cast<uintptr_t>(saved) % WS_ALIGN) return NLSP_E_WORKSPACE;
   const GtermSaved Gs = carve_gterm(const_cast<void*>(saved), batch, n, k, m);

@@ -503,10 +503,36 @@ inline unsigned plan_rows(const OpDev& op, int TR, BlockMap& bm) {
   return (unsigned)((int64_t)op.ny * op.nz * bm.bpl);
 }
 
+// Compressed-row operators: one thread per (row, right-hand side), the
+// row's entries in stored order, arithmetic in T (float64 values rounded to T
+// for the float32 sweep).  MODE as k_rows.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_csr_rows(OpDev op, int R, T omega, const T* __restrict__ b,
+                                                  const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= op.n * R) return;
+  const int64_t i = g / R;
+  const int c = (int)(g - i * R);
+  const int e0 = op.rp[i], e1 = op.rp[i + 1];
+  T s = T(0), d = T(0);
+  for (int e = e0; e < e1; ++e) {
+    const int j = op.ci[e];
+    const T a = T(op.coef[e]);
+    s += a * x[(int64_t)j * R + c];
+    if (j == (int)i) d = a;
+  }
+  y[g] = (MODE == 0) ? s : x[g] + omega * (b[g] - s) / d;
+}
+
 // launches k_rows for the operator kind with the widest vector the right-hand
 // side count and the pointers allow
 template <typename T, int MODE>
 inline void launch_rows(const OpDev& op, int R, T omega, const T* b, const T* x, T* y, hipStream_t s) {
+  if (op.kind == NLSP_OP_CSR) {
+    hipLaunchKernelGGL((k_csr_rows<T, MODE>), dim3(ceil_div(op.n * R, 256)), dim3(256), 0, s, op, R, omega, b, x,
+                       y);
+    return;
+  }
   if (try_zmarch<T, MODE>(op, R, omega, b, x, y, s)) return;
   constexpr int VMAX = 16 / sizeof(T);
   const bool vec = (R % VMAX == 0) && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&

@@ -171,10 +171,36 @@ __global__ __launch_bounds__(COLS_NT) void k_cols(OpDev op, int mp, int TR, Fast
   }
 }
 
+// The multi-column pass for a compressed-row operator: one wave per row
+// (its entries read once per wave), lanes over the m columns; float64
+// coefficients and sums, modes as k_stencil_cols.
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr_cols(OpDev op, int m, double omega, int mode, const T* __restrict__ in,
+                                                  T* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (i >= op.n) return;
+  const int e0 = op.rp[i], e1 = op.rp[i + 1];
+  double dg = 0.0;
+  for (int e = e0; e < e1; ++e)
+    if (op.ci[e] == (int)i) dg = op.coef[e];
+  const double scale = (mode == 0) ? omega / dg : 0.0;
+  for (int col = lane; col < m; col += 64) {
+    double s = 0.0;
+    for (int e = e0; e < e1; ++e) s += op.coef[e] * (double)in[(int64_t)op.ci[e] * m + col];
+    const double v = (mode == 0) ? (double)in[i * m + col] - scale * s : s;
+    out[i * m + col] = (T)v;
+  }
+}
+
 // the multi-column pass over (n, mp) blocks: k_cols when the rows are whole
-// 16-byte vectors, k_stencil_cols otherwise
+// 16-byte vectors, k_stencil_cols otherwise (k_csr_cols for compressed rows)
 template <typename T>
 inline void launch_cols(const OpDev& op, int mp, double omega, int mode, const T* in, T* out, hipStream_t s) {
+  if (op.kind == NLSP_OP_CSR) {
+    hipLaunchKernelGGL(k_csr_cols<T>, dim3(ceil_div(op.n, 4)), dim3(256), 0, s, op, mp, omega, mode, in, out);
+    return;
+  }
   constexpr int VW = 16 / sizeof(T);
   const bool al = reinterpret_cast<uintptr_t>(in) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
   if (mp % VW != 0 || !al || op.n * mp >= (int64_t(1) << 31)) {

@@ -244,3 +244,49 @@ def test_binding_checks_shapes_before_any_launch(lib):
     sysC = api.System(op, M, torch.zeros(n, 3, dtype=torch.float64), torch.zeros(n, 3, dtype=torch.float64))
     with pytest.raises(ValueError, match="same number"):
         api.pcg_solve_batched([sysA, sysC])
+
+
+def test_p1_pattern_on_the_host(lib):
+    """p1_pattern (host code): the compressed rows hold exactly the couplings
+    of the oracle's assembled P1 matrix, with ascending columns, a lone
+    diagonal in every boundary row, and per entry the element contributions
+    in increasing triangle order (codes 9 t + 3 a + b whose vertex pair is
+    the entry's)."""
+    import numpy as np
+    import oracle as O
+    import workloads as W
+    N = 6
+    pts, tris, bnd = W.p1_mesh(77, N)
+    kt, sK, sM = W.p1_coefficients("screened_poisson", 78, len(tris), N)
+    npt, nt = len(pts), len(tris)
+    nnz, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    assert lib.p1_pattern(npt, nt, tris.ctypes.data, bnd.ctypes.data, ctypes.byref(nnz), ctypes.byref(nc),
+                          None, None, None, None) == 0
+    rp = np.empty(npt + 1, np.int32)
+    ci = np.empty(nnz.value, np.int32)
+    cp = np.empty(nnz.value + 1, np.int32)
+    cl = np.empty(nc.value, np.int32)
+    assert lib.p1_pattern(npt, nt, tris.ctypes.data, bnd.ctypes.data, ctypes.byref(nnz), ctypes.byref(nc),
+                          rp.ctypes.data, ci.ctypes.data, cp.ctypes.data, cl.ctypes.data) == 0
+    A = O.p1_fem(pts, tris, kt, sK, sM, bnd).tocsr()
+    A.sort_indices()
+    assert rp[0] == 0 and rp[-1] == nnz.value and np.all(np.diff(rp) >= 1)
+    for i in range(npt):
+        cols = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cols) > 0)
+        if bnd[i]:
+            assert list(cols) == [i]
+        assert set(A.indices[A.indptr[i]:A.indptr[i + 1]]) <= set(cols)
+        for e in range(rp[i], rp[i + 1]):
+            codes = cl[cp[e]:cp[e + 1]]
+            assert np.all(np.diff(codes) > 0)
+            for code in codes:
+                t, a, b = code // 9, (code % 9) // 3, code % 3
+                assert (tris[t, a], tris[t, b]) == (i, ci[e])
+    inner = bnd == 0
+    assert nc.value == sum(int(inner[v].sum()) ** 2 for v in tris)
+    # a vertex index out of range is rejected
+    bad = tris.copy()
+    bad[0, 0] = npt
+    assert lib.p1_pattern(npt, nt, bad.ctypes.data, bnd.ctypes.data, ctypes.byref(nnz), ctypes.byref(nc),
+                          None, None, None, None) == -1

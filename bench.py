@@ -45,6 +45,7 @@ def _args():
                     help="solver kernel for the roofline (0 = pick the slowest)")
     ap.add_argument("--spmv-leg", action="store_true",
                     help="only run the stand-alone operator kernels on the 3-D workload and exit")
+    ap.add_argument("--fem-leg", action="store_true", help="run only the P1 finite-element leg")
     ap.add_argument("--batched-leg", action="store_true",
                     help="run only the batched anisotropic leg (for profiling it on its own)")
     ap.add_argument("--solve3d-leg", action="store_true",
@@ -105,6 +106,9 @@ def main():
         return
     if a.batched_leg:
         print(json.dumps({"batched": batched_legs(nl, torch, dev)}), flush=True)
+        return
+    if a.fem_leg:
+        print(json.dumps({"fem": fem_leg(nl, torch, dev)}), flush=True)
         return
     c = W.Cfg2(N=a.N)
     n, m, k = c.n, c.m, c.k
@@ -199,6 +203,7 @@ def main():
         out["mixed_f16"] = f16_leg(step, nl, n, kp)
         out["spmv"] = spmv_legs(nl, torch, dev)
         out["solve3d"] = solve3d_leg(nl, torch, dev, cpu=not a.no_cpu_baseline)
+        out["fem"] = fem_leg(nl, torch, dev)
         out["training"] = training_legs(nl, torch, dev)
         out["batched"] = batched_legs(nl, torch, dev)
         out["predictor"] = predictor_leg(nl, torch, dev)
@@ -329,6 +334,67 @@ def solve3d_leg(nl, torch, dev, cpu=False):
     if cpu:
         res["cpu_baseline"] = cpu_baseline_3d(c4, coef, fh, res["mixed"]["iters_max"])
     return res
+
+
+# median PCG iterations of the SVD basis at n_c = 48 in the paper's iteration
+# table (its own meshes and hardware; context only)
+PAPER_SVD_ITERS = {"diffusion": 64, "anisotropic": 55, "screened_poisson": 46, "heat": 45, "wave": 64}
+
+
+def fem_leg(nl, torch, dev, reps=3):
+    """The paper's own workload shape: P1 finite elements on a jittered
+    Delaunay mesh with 65^2 vertices (n = 4225), each of the five benchmark
+    families, identity Dirichlet rows; K = 72 relaxed vectors, k = 48,
+    nu = 5, omega = 0.66, rtol 1e-6.  Per family: GPU assembly, setup (the SVD
+    route and the randomized sketch with l = k + 10, q = 1), Galerkin operator
+    and PCG (float64 and mixed), medians of `reps`; iterations beside the
+    paper's SVD column (context)."""
+    import workloads as W
+    c = W.CfgFem()
+    out = {"workload": f"P1 FEM on a jittered Delaunay mesh, {c.N + 1}^2 vertices (n={c.n}), m={c.m}, k={c.k}, "
+                       f"nu={c.nu}, omega={c.omega}, rtol={c.rtol}"}
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    for fam in W.P1_FAMILIES:
+        pts, tris, bnd = c.mesh(0)
+        kt, sK, sM = c.coefficients(fam, len(tris), 0)
+        ktd = torch.tensor(kt, dtype=torch.float64, device=dev)
+        S0 = torch.tensor(c.S0(0), dtype=torch.float64, device=dev)
+        f = torch.tensor(c.rhs(0), dtype=torch.float64, device=dev)
+        Om = torch.tensor(W.normal_block(W.seed_for(c.cfg, 7), c.m, c.k + 10), dtype=torch.float64, device=dev)
+        r = {"paper_svd_iters": PAPER_SVD_ITERS[fam]}
+        res = {"asm": [], "setup": [], "setup_rand": [], "fp64": [], "mixed": []}
+        for rep in range(reps + 1):
+            e = [ev() for _ in range(6)]
+            e[0].record()
+            op = nl.p1_operator(pts, tris, bnd, ktd, sK, sM)
+            e[1].record()
+            P, _ = nl.setup_spectral_P(op, S0, c.k, c.omega, c.s1, nl.FP64)
+            M = nl.galerkin_coarse(op, P, c.omega, c.nu)
+            e[2].record()
+            Pr, _ = nl.setup_randomized_P(op, S0, c.k, c.omega, c.s1, Om, 1, nl.FP64)
+            Mr = nl.galerkin_coarse(op, Pr, c.omega, c.nu)
+            e[3].record()
+            _, i64, _ = nl.pcg_solve(op, M, f, prec=nl.FP64, rtol=c.rtol)
+            e[4].record()
+            _, imx, _ = nl.pcg_solve(op, M, f, prec=nl.MIXED, rtol=c.rtol)
+            e[5].record()
+            _, irn, _ = nl.pcg_solve(op, Mr, f, prec=nl.FP64, rtol=c.rtol)
+            torch.cuda.synchronize()
+            if rep == 0:
+                continue   # warm-up
+            res["asm"].append(e[0].elapsed_time(e[1]))
+            res["setup"].append(e[1].elapsed_time(e[2]))
+            res["setup_rand"].append(e[2].elapsed_time(e[3]))
+            res["fp64"].append(e[3].elapsed_time(e[4]))
+            res["mixed"].append(e[4].elapsed_time(e[5]))
+        r.update({"assembly_ms": round(statistics.median(res["asm"]), 3),
+                  "setup_ms": round(statistics.median(res["setup"]), 3),
+                  "setup_randomized_ms": round(statistics.median(res["setup_rand"]), 3),
+                  "solve_fp64_ms": round(statistics.median(res["fp64"]), 3), "iters_fp64": i64[0].iters,
+                  "solve_mixed_ms": round(statistics.median(res["mixed"]), 3), "iters_mixed": imx[0].iters,
+                  "iters_randomized": irn[0].iters, "relres_fp64": i64[0].relres})
+        out[fam] = r
+    return out
 
 
 def training_legs(nl, torch, dev):

@@ -126,6 +126,12 @@ int p1_assemble(int np, int nt, const double* points, const int* tris, const dou
                 double sM, const unsigned char* boundary, const int* row_ptr, const int* col_idx,
                 const int* cptr, const int* clist, double* vals, void* stream);
 
+/* dst = src for `bytes` bytes (a multiple of 16; both 16-byte aligned, device):
+ * the plainest streaming kernel (one 16-byte vector per thread, non-temporal
+ * stores), the practical HBM ceiling against which the benchmark reports its
+ * bandwidth-bound kernels.  Asynchronous on `stream`. */
+int stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
 /* y = A x in float64 for R right-hand sides; x, y device (n, R).  Asynchronous. */
 int apply_operator(const nlsp_operator* A, const double* x, double* y, int R, void* stream);
 

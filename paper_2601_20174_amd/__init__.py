@@ -10,7 +10,7 @@ package only marshals torch tensors into it.
 from .api import (  # noqa: F401
     OK, NOT_CONVERGED, E_INVALID, E_NOT_SPD, E_BREAKDOWN, E_NONFINITE, E_WORKSPACE, E_HIP, E_RANK,
     FP64, MIXED, MIXED_F16, OP_POISSON5, OP_FV5, OP_FV7, OP_STENCIL9, OP_CSR, NlspError, Operator, TwoLevel, RhsInfo,
-    status_string, nlsp_operator_size, nlsp_padded_rank, p1_operator, q1_aniso_stencil, apply_operator,
+    status_string, nlsp_operator_size, nlsp_padded_rank, p1_operator, q1_aniso_stencil, stream_copy, apply_operator,
     jacobi_sweep_f32, setup_spectral_P_workspace_bytes, setup_spectral_P, setup_randomized_P_workspace_bytes,
     setup_randomized_P,
     galerkin_coarse_workspace_bytes, galerkin_coarse, setup_many, pcg_solve_workspace_bytes, pcg_solve, pcg_solve_noalloc,

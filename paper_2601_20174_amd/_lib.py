@@ -59,6 +59,7 @@ SIGNATURES = {
                            c_void_p, c_void_p, c_void_p, c_void_p]),
     "p1_assemble": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "stream_copy": (c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
     "apply_operator": (c_int, [POP, c_void_p, c_void_p, c_int, c_void_p]),
     "jacobi_sweep_f32": (c_int, [POP, c_double, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "setup_spectral_P_workspace_bytes": (c_size_t, [POP, c_int, c_int, c_int]),

@@ -177,6 +177,18 @@ def q1_aniso_stencil(eps_theta: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+    """dst = src with the library's plain copy kernel (both contiguous GPU
+    tensors of the same size, a multiple of 16 bytes)."""
+    nb = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous GPU tensors")
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst differ in size")
+    _check("stream_copy", _L().stream_copy(src.data_ptr(), dst.data_ptr(), nb, _stream()))
+    return dst
+
+
 def apply_operator(op: Operator, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
     R = _rows(x, _op_checked(op).n, "x")
     if y is None:

@@ -71,17 +71,18 @@ def copy_calibration(mib: int):
                                            "launches": 3}}), flush=True)
 
 
-def solver_bytes_per_row(phase: int, kp: int, R: int = 1, qbytes: int = 4) -> float:
+def solver_bytes_per_row(phase: int, kp: int, R: int = 1, qbytes: int = 4, cbytes: int = 8) -> float:
     """Algorithmic HBM bytes per grid row of one launch of a solver kernel,
-    mixed form, float64 cell coefficient, each array counted once (qbytes:
-    bytes per stored basis element, 4 for float32, 2 for float16):
+    mixed form, each array counted once (qbytes: bytes per stored basis
+    element, 4 for float32, 2 for float16; cbytes: the cell coefficient, 8,
+    or 0 for an operator whose stencil all rows share):
       update (1): read z, p, w, q_old, x, r, a, D^-1 (f32), Q;
-                  write p, q, x, r_new, z  -> 11 x 8 R + 8 + 4 + qbytes kp
-      matvec (2): read z, p, q, a, Qt; write w  -> 4 x 8 R + 8 + qbytes kp
+                  write p, q, x, r_new, z  -> 11 x 8 R + cbytes + 4 + qbytes kp
+      matvec (2): read z, p, q, a, Qt; write w  -> 4 x 8 R + cbytes + qbytes kp
     """
     if phase == 1:
-        return 88.0 * R + 12.0 + qbytes * kp
-    return 32.0 * R + 8.0 + qbytes * kp
+        return 88.0 * R + cbytes + 4.0 + qbytes * kp
+    return 32.0 * R + cbytes + qbytes * kp
 
 
 def main():
@@ -504,6 +505,13 @@ def batched_legs(nl, torch, dev, nsys=None):
         worst = max(inf.relres for si in infos for inf in si)
     b_ms = statistics.median(times)
     pairs = ns * c3.R
+    # algorithmic bytes of the solve: a system iterates until its last
+    # right-hand side stops; per row and iteration one update and one matvec
+    # launch (9-point stencil: no per-row coefficient)
+    kp = nl.nlsp_padded_rank(c3.k)
+    row_iters = sum(int(side[i]) ** 2 * max(inf.iters for inf in infos[i]) for i in range(ns))
+    per_row = solver_bytes_per_row(1, kp, c3.R, cbytes=0) + solver_bytes_per_row(2, kp, c3.R, cbytes=0)
+    b_bytes = row_iters * per_row
     # plain single-system float64 path on the same systems
     t0 = time.perf_counter()
     f64_iters, f64_worst = [], 0.0
@@ -522,7 +530,10 @@ def batched_legs(nl, torch, dev, nsys=None):
                               "pairs_per_s": round(pairs / (b_ms * 1e-3), 1),
                               "systems_per_s": round(ns / (b_ms * 1e-3), 1),
                               "iters_max": int(max(iters)), "iters_median": float(np.median(iters)),
-                              "relres_max": worst, "tune_ms": {str(k): round(v, 3) for k, v in tune_ms.items()}},
+                              "relres_max": worst, "tune_ms": {str(k): round(v, 3) for k, v in tune_ms.items()},
+                              "row_iterations": row_iters, "bytes_per_row_iteration": per_row,
+                              "GBs": round(b_bytes / (b_ms * 1e-3) / 1e9, 1),
+                              "frac": round(b_bytes / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "single_system_f64": {"solve_ms": round(s_ms, 3), "pairs_per_s": round(pairs / (s_ms * 1e-3), 1),
                                   "iters_max": int(max(f64_iters)), "relres_max": f64_worst},
             "speedup_solve": round(s_ms / b_ms, 2),

@@ -491,18 +491,24 @@ struct QB {
 };
 
 // ---------------------------------------------- MFMA form of the basis passes
-// For R = 16 right-hand sides (one 16 x 16 tile of them) and kp = 64 or 128
-// the passes are 16 x 16 x 4 matrix products on the matrix cores, so every
-// element of Q / Qt is loaded once per pass instead of once per right-hand
-// side.  Operands: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-// the accumulator element v of lane l is D[4 (l / 16) + v][l % 16] for the
-// float32 product and D[4 v + l / 16][l % 16] for the float64 one.
+// For R = 16 right-hand sides (kp = 64 or 128) and R = 8 (kp = 32 or 64) the
+// passes are 16 x 16 x 4 matrix products on the matrix cores, the right-hand
+// sides forming the 16 columns of one tile (with R = 8 the upper 8 columns
+// are zero and their results dropped), so every element of Q / Qt is loaded
+// once per pass instead of once per right-hand side.  Operands: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator element v
+// of lane l is D[4 (l / 16) + v][l % 16] for the float32 product and
+// D[4 v + l / 16][l % 16] for the float64 one.
 //   matvec: (Qt^T w) tile I = sum over rows of Qt[row][16 I + i] w[row][c],
-//     float64 products (as restrict_rows), one column tile per wave.
-//   update: (Q c) for the 32 rows of a chunk in QT, waves = 2 row tiles x 4
-//     slices of kp / 4 columns, the slices added in order through LDS.
-constexpr int MF_R = 16;
-inline bool mf_ok(int R, int kp) { return R == MF_R && (kp == 64 || kp == 128); }
+//     float64 products (as restrict_rows); kp / 16 column tiles, each over
+//     8 / (kp / 16) waves with a slice of the chunk's rows each.
+//   update: (Q c) for the NT / R rows of a chunk in QT, waves = (NT / R) / 16
+//     row tiles x R / 4 slices of 4 kp / R columns (one or two blocks of 16),
+//     the slices added in order through LDS.
+constexpr int MF_T = 16;   // columns of a tile
+inline bool mf_ok(int R, int kp) {
+  return (R == 16 && (kp == 64 || kp == 128)) || (R == 8 && (kp == 32 || kp == 64));
+}
 
 template <typename QT>
 struct MfAcc;
@@ -854,7 +860,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < 8; ++s)
-        if (s < ksteps) acc = mf_mma((double)a[s], wv[(sl * rps + 4 * s + lg) * MF_R + lr], acc);
+        if (s < ksteps) acc = mf_mma((double)a[s], lr < R ? wv[(sl * rps + 4 * s + lg) * R + lr] : 0.0, acc);
     }
     if constexpr (sizeof(QS) == 2) {
       const double is = S.qscale[1];
@@ -865,14 +871,15 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     const int KR = S.kp * R;
     if (WPT == 1) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) store_partial(&rec[(16 * I + 4 * v + lg) * MF_R + lr], acc[v]);
+      for (int v = 0; v < 4; ++v)
+        if (lr < R) store_partial(&rec[(16 * I + 4 * v + lg) * R + lr], acc[v]);
     } else {
       __syncthreads();
 #pragma unroll
       for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + lane] = acc[v];
       __syncthreads();
       for (int idx = t; idx < KR; idx += NT) {
-        const int j = idx / MF_R, cc = idx % MF_R;
+        const int j = idx / R, cc = idx % R;
         double sum = 0.0;
         for (int q = 0; q < WPT; ++q) sum += red[(q * TI + j / 16) * 256 + mf_slot<double>(j % 16, cc)];
         store_partial(&rec[idx], sum);
@@ -1049,11 +1056,12 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   const bool has = cr.c0 < cr.c1;
   int64_t row0 = has ? chunk_row0(S, cr.c0) : 0;
   int nrows = has ? (int)min<int64_t>(S.chunk_rows, S.op.n - row0) : 1;
-  // MFMA prolongation (R = 16): wave = row tile RT x column slice ks of kp/4
-  // columns (nbk blocks of 16); a lane loads 4 consecutive columns of one row
-  // per block, feeding 4 products
+  // MFMA prolongation: wave = row tile RT (of RTN) x column slice ks (of KS)
+  // of kp / KS columns (nbk blocks of 16); a lane loads 4 consecutive columns
+  // of one row per block, feeding 4 products
   const int mwave = t / WAVE, mlane = t % WAVE, mlr = mlane & 15, mlg = mlane >> 4;
-  const int mRT = mwave & 1, mks = mwave >> 1, mcols = S.kp / 4, mnbk = mcols / 16;
+  const int mRTN = S.chunk_rows / 16, mKS = (NT / WAVE) / mRTN;
+  const int mRT = mwave % mRTN, mks = mwave / mRTN, mcols = S.kp / mKS, mnbk = mcols / 16;
   QBatch<QS, 2> q4;
   auto mf_fetch = [&](int64_t r0, int nr) {
 #pragma unroll
@@ -1284,7 +1292,8 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     for (int blk = 0; blk < 2; ++blk)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        eb[blk][u] = QT(cvec[(mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg + u) * MF_R + mlr] * isq);
+        eb[blk][u] = mlr < R ? QT(cvec[(mks * mcols + 16 * min(blk, mnbk - 1) + 4 * mlg + u) * R + mlr] * isq)
+                             : QT(0);
   } else {
 #pragma unroll
     for (int u = 0; u < 4; ++u) e4[u] = QT(cvec[(4 * m.jc + u) * R + m.c] * isq);
@@ -1364,12 +1373,11 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
 #pragma unroll
         for (int v = 0; v < 4; ++v) mfpart[mwave * 256 + v * 64 + mlane] = pacc[v];
         __syncthreads();
-        // ys[row * 16 + c]: the four column slices of row tile row / 16, in order
+        // ys[row * R + c]: the column slices of row tile row / 16, in order
         {
-          const int row = t / MF_R, cc = t % MF_R, slot = mf_slot<QT>(row % 16, cc);
+          const int row = t / R, cc = t % R, slot = mf_slot<QT>(row % 16, cc);
           QT sum = QT(0);
-#pragma unroll
-          for (int k2 = 0; k2 < 4; ++k2) sum += mfpart[(k2 * 2 + row / 16) * 256 + slot];
+          for (int k2 = 0; k2 < mKS; ++k2) sum += mfpart[(k2 * mRTN + row / 16) * 256 + slot];
           ys[t] = sum;
         }
       } else {
@@ -1704,10 +1712,10 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   using QT = typename Arith<QS>::type;
   const int R = hs[0].R;
   int nblk = 0;
-  bool mf = true;   // MFMA basis passes when every system has 16 right-hand sides and kp = 64 or 128
+  bool mf = true;   // MFMA basis passes when every system's (R, kp) has the matrix-core form
   for (const auto& h : hs) {
     nblk += h.nblk;
-    mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / MF_R;
+    mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / h.R;
   }
   // the matrix-core kernels read the face weights of finite-volume operators
   for (const auto& h : hs)

@@ -122,9 +122,9 @@ def test_workspace_queries(lib):
 
 def test_solver_workspace_holds_face_weights_for_matrix_core_form(lib):
     """A finite-volume operator solved in the matrix-core form (16 right-hand
-    sides, k padded to 64 or 128: k in 33 .. 128) gets 3 n float64 + 3 n
-    float32 face weights in the solver workspace; other operators and the
-    other forms do not."""
+    sides with k padded to 64 or 128: k in 33 .. 128; 8 with k padded to 32 or
+    64: k in 17 .. 64) gets 3 n float64 + 3 n float32 face weights in the
+    solver workspace; other operators and the other forms do not."""
     from paper_2601_20174_amd import api
     fake = ctypes.c_void_p(0x1000)  # never dereferenced by the size query
     fv7 = ctypes.byref(_op(api.OP_FV7, 8, 8, 8, fake))       # n = 512
@@ -136,7 +136,10 @@ def test_solver_workspace_holds_face_weights_for_matrix_core_form(lib):
         assert base > 0
         assert lib.pcg_solve_workspace_bytes(fv7, k, 16) == base + 3 * n * (8 + 4)
         assert lib.pcg_solve_workspace_bytes(fv5, k, 16) == base + 3 * n * (8 + 4)
-    for k, R in ((64, 8), (32, 16), (16, 16), (64, 1)):
+    for k in (20, 32, 50, 64):
+        base = lib.pcg_solve_workspace_bytes(p5, k, 8)
+        assert lib.pcg_solve_workspace_bytes(fv7, k, 8) == base + 3 * n * (8 + 4)
+    for k, R in ((100, 8), (16, 8), (32, 16), (16, 16), (64, 1), (64, 4)):
         assert lib.pcg_solve_workspace_bytes(fv7, k, R) == lib.pcg_solve_workspace_bytes(p5, k, R)
 
 

@@ -69,12 +69,14 @@ def test_default_tile_matches_single_system_bitwise(nl, prec, R):
             assert (a.iters, a.status, a.relres) == (b.iters, b.status, b.relres)
 
 
+@pytest.mark.parametrize("R,k", [(16, 50), (8, 30), (8, 50)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_sixteen_rhs_matrix_core_batch(nl, prec):
-    """16 right-hand sides and kp = 64: the batch takes the matrix-core basis
-    passes; with the default tile it reproduces the single-system solves bit
-    for bit, and every right-hand side reaches the tolerance."""
-    batch = _batch(nl, 16, k=50, m=64, sides=[24, 31, 40, 50])
+def test_matrix_core_batch(nl, prec, R, k):
+    """16 right-hand sides with kp = 64, 8 with kp = 32 and 64: the batch takes
+    the matrix-core basis passes; with the default tile it reproduces the
+    single-system solves bit for bit, and every right-hand side reaches the
+    tolerance."""
+    batch = _batch(nl, R, k=k, m=64, sides=[24, 31, 40, 50])
     systems = _systems(nl, batch)
     infos, rc = nl.pcg_solve_batched(systems, prec=prec, rtol=1e-8, check_every=8)
     assert rc == nl.OK

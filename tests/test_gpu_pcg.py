@@ -88,29 +88,32 @@ def test_multi_rhs(nl, R, prec):
     _check(nl, A, op, P, f, prec=prec)
 
 
-# 16 right-hand sides with kp = 64 or 128 take the matrix-core form of the
-# basis passes (one 16 x 16 tile of right-hand sides); 2-D and 3-D grids
-# with ragged chunks, and more than one row chunk per workgroup
-@pytest.mark.parametrize("kind,size,k", [("fv5", (61, 47), 40), ("fv5", (90, 77), 100), ("fv7", (19, 14), 64),
-                                          ("fv7", (32, 11), 64)])
+# 16 right-hand sides with kp = 64 or 128, and 8 with kp = 32 or 64, take the
+# matrix-core form of the basis passes (the right-hand sides as the columns of
+# one 16 x 16 tile); 2-D and 3-D grids with ragged chunks, more than one row
+# chunk per workgroup, the 9-point stencil
+@pytest.mark.parametrize("kind,size,k,R", [("fv5", (61, 47), 40, 16), ("fv5", (90, 77), 100, 16),
+                                            ("fv7", (19, 14), 64, 16), ("fv7", (32, 11), 64, 16),
+                                            ("fv5", (61, 47), 32, 8), ("fv5", (90, 77), 60, 8),
+                                            ("fv7", (19, 14), 32, 8), ("q1", (56, 56), 30, 8)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_multi_rhs_mfma(nl, kind, size, k, prec):
+def test_multi_rhs_mfma(nl, kind, size, k, R, prec):
     A, op, n = make_case(kind, 24, size)
     S = O.relax(A, np.random.default_rng(25).standard_normal((n, 2 * k)), 2 / 3, 10)
     P, _ = O.spectral_basis(S, k)
-    f = np.random.default_rng(26).standard_normal((n, 16))
+    f = np.random.default_rng(26).standard_normal((n, R))
     f[:, 3] *= 1e-4                      # different scales converge at different iterations
     _check(nl, A, op, P, f, prec=prec)
 
 
 # 3-D grids whose x-lines split into whole chunks (chunk = 512 / R rows)
 # enumerate chunks z fastest, so a workgroup marches through z
-@pytest.mark.parametrize("R,size", [(8, (64, 9)), (16, (32, 13))])
+@pytest.mark.parametrize("R,size,k", [(8, (64, 9), 16), (16, (32, 13), 16), (8, (64, 9), 32)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_3d_zmajor_chunks(nl, R, size, prec):
+def test_3d_zmajor_chunks(nl, R, size, k, prec):
     A, op, n = make_case("fv7", 27, size)
-    S = O.relax(A, np.random.default_rng(28).standard_normal((n, 32)), 2 / 3, 10)
-    P, _ = O.spectral_basis(S, 16)
+    S = O.relax(A, np.random.default_rng(28).standard_normal((n, 2 * k)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, k)
     f = np.random.default_rng(29).standard_normal((n, R))
     _check(nl, A, op, P, f, prec=prec)
 

@@ -490,14 +490,18 @@ def batched_legs(nl, torch, dev, nsys=None):
     systems = [nl.System(op, M, f, torch.zeros_like(f)) for op, M, f in zip(ops, Ms, fs)]
     del S0s
     best, tune_ms = nl.pcg_solve_batched_tune(systems, prec=nl.MIXED, rtol=c3.rtol, iters=16)
-    ws = torch.empty(nl.pcg_solve_batched_workspace_bytes(systems, nl.MIXED, best), dtype=torch.uint8, device=dev)
+    # the solves below take the tile the tuner recorded for this batch shape
+    assert nl.pcg_solve_batched_tuned(systems, nl.MIXED) == best
+    ws = torch.empty(nl.pcg_solve_batched_workspace_bytes(systems, nl.MIXED, nl.TUNED), dtype=torch.uint8,
+                     device=dev)
     times, iters, worst = [], [], 0.0
     for rep in range(3):
         for s in systems:
             s.u.zero_()
         torch.cuda.synchronize()
         e0.record()
-        infos, rc = nl.pcg_solve_batched(systems, prec=nl.MIXED, rtol=c3.rtol, rows_per_block=best, workspace=ws)
+        infos, rc = nl.pcg_solve_batched(systems, prec=nl.MIXED, rtol=c3.rtol, rows_per_block=nl.TUNED,
+                                         workspace=ws)
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))

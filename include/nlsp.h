@@ -345,7 +345,9 @@ size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R
  *   sys             host array of nsys descriptors
  *   rows_per_block  rows of a system per workgroup (0 = one workgroup per
  *                   NT / R rows, capped at 512 per system); pick it with
- *                   pcg_solve_batched_tune
+ *                   pcg_solve_batched_tune; -1 = the tile that tuner chose
+ *                   for a batch of this shape on the current device (0 if
+ *                   it has not been tuned in this process)
  *   info            host array of nsys * R records, system-major
  * Returns the worst per-RHS status.  Synchronises `stream`. */
 int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_block,
@@ -363,6 +365,13 @@ size_t pcg_solve_batched_tune_workspace_bytes(int nsys, const nlsp_system* sys, 
 int pcg_solve_batched_tune(int nsys, const nlsp_system* sys, int R, const nlsp_pcg_opts* opts,
                            int iters, int* best_rows_per_block, double* ms, void* ws,
                            size_t ws_bytes, void* stream);
+
+/* The tuner's choice is recorded for the process, keyed by the batch shape:
+ * the current device, the basis precision, R, k, nu and each system's
+ * operator kind and size, in order (a later tune of the same shape replaces
+ * it).  Returns 1 and the recorded tile in *rows_per_block, 0 when this shape
+ * has not been tuned, NLSP_E_INVALID on bad arguments.  Thread-safe. */
+int pcg_solve_batched_tuned(int nsys, const nlsp_system* sys, int R, int* rows_per_block);
 
 /* ------------------------------------------------------- training losses */
 /* Subspace loss of a batch of predicted bases against relaxed samples (Sec. 4,

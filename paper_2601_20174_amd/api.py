@@ -694,10 +694,15 @@ def pcg_solve_batched_workspace_bytes(systems: List[System], prec: int, rows_per
     return int(_L().pcg_solve_batched_workspace_bytes(len(systems), arr, R, int(rows_per_block)))
 
 
+TUNED = -1   # rows_per_block: the tile pcg_solve_batched_tune chose for this batch shape
+
+
 def pcg_solve_batched(systems: List[System], prec: int = MIXED, rtol: float = 1e-8, maxit: int = 10000,
                       flexible: Optional[bool] = None, check_every: int = 32, rows_per_block: int = 0,
                       workspace: Optional[torch.Tensor] = None):
-    """Solves every system in place (s.u); returns ([[RhsInfo] per system], status)."""
+    """Solves every system in place (s.u); returns ([[RhsInfo] per system], status).
+    rows_per_block = TUNED takes the tile recorded by pcg_solve_batched_tune for
+    a batch of this shape (the default plan if there is none)."""
     arr, R = _systems(systems, prec)
     if flexible is None:
         flexible = prec != FP64
@@ -736,6 +741,17 @@ def pcg_solve_batched_tune(systems: List[System], prec: int = MIXED, rtol: float
                                      ws.data_ptr(), ws.numel(), _stream())
     _check("pcg_solve_batched_tune", rc)
     return best.value, {int(cand[i]): float(ms[i]) for i in range(ncand)}
+
+
+def pcg_solve_batched_tuned(systems: List[System], prec: int = MIXED) -> Optional[int]:
+    """The tile recorded by pcg_solve_batched_tune for a batch of this shape
+    on the current device, or None."""
+    arr, R = _systems(systems, prec)
+    rpb = ctypes.c_int(0)
+    rc = _L().pcg_solve_batched_tuned(len(systems), arr, R, ctypes.byref(rpb))
+    if rc < 0:
+        _check("pcg_solve_batched_tuned", rc)
+    return rpb.value if rc == 1 else None
 
 
 # ------------------------------------------------------------ thin QR

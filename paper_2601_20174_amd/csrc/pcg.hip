@@ -38,7 +38,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -1537,17 +1539,9 @@ inline bool use_faces(const nlsp_operator* A, int R, int kp) {
   return mf_ok(R, kp) && (A->kind == NLSP_OP_FV5 || A->kind == NLSP_OP_FV7);
 }
 
-// Workgroups per system: one per chunk of NT / R rows up to a cap (512 for a
-// single system, NLSP_SOLVER_BLOCKS overrides it for tuning), or, in a batch,
-// one per `rows_per_block` rows.
-inline int solver_blocks(int64_t nchunks) {
-  int cap = 512;
-  if (const char* e = std::getenv("NLSP_SOLVER_BLOCKS")) {
-    const int v = std::atoi(e);
-    if (v >= 1 && v <= 65536) cap = v;
-  }
-  return (int)std::min<int64_t>(nchunks, cap);
-}
+// Workgroups per system: one per chunk of NT / R rows up to 512 (two per CU)
+// for a single system, or, in a batch, one per `rows_per_block` rows.
+inline int solver_blocks(int64_t nchunks) { return (int)std::min<int64_t>(nchunks, 512); }
 
 inline int restriction_width(int kp, int R) { return kp * R + 2 * R; }
 
@@ -2008,6 +2002,52 @@ inline bool opts_ok(const nlsp_pcg_opts* o) {
   return o && o->rtol > 0 && o->maxit >= 1 && o->check_every >= 1;
 }
 
+// Tiles chosen by pcg_solve_batched_tune, per batch shape: the device, the
+// basis precision, R, k, nu and every system's operator kind and size, in
+// order.  rows_per_block = -1 in the batched entry points looks the shape up.
+struct TuneKey {
+  int dev, prec, R, k, nu;
+  std::vector<int64_t> sys;   // kind, n for each system
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, prec, R, k, nu, sys) < std::tie(o.dev, o.prec, o.R, o.k, o.nu, o.sys);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tuned;
+
+static bool tune_key(int nsys, const nlsp_system* sys, int R, TuneKey& key) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  key.dev = dev;
+  key.prec = sys[0].M.prec;
+  key.R = R;
+  key.k = sys[0].M.k;
+  key.nu = sys[0].M.nu;
+  key.sys.resize(2 * (size_t)nsys);
+  for (int i = 0; i < nsys; ++i) {
+    key.sys[2 * (size_t)i] = sys[i].A.kind;
+    key.sys[2 * (size_t)i + 1] = op_size(&sys[i].A);
+  }
+  return true;
+}
+
+// rows_per_block -1: the tile recorded for this batch shape on the current
+// device, or 0 (the default plan) when none was; other values unchanged
+static bool tuned_tile(int nsys, const nlsp_system* sys, int R, int* rpb) {
+  TuneKey key;
+  if (!tune_key(nsys, sys, R, key)) return false;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  const auto it = g_tuned.find(key);
+  if (it == g_tuned.end()) return false;
+  *rpb = it->second;
+  return true;
+}
+static int resolve_tile(int nsys, const nlsp_system* sys, int R, int rows_per_block) {
+  int rpb = 0;
+  if (rows_per_block != -1) return rows_per_block;
+  return tuned_tile(nsys, sys, R, &rpb) ? rpb : 0;
+}
+
 // Sets up and runs a batch; nsys = 1 and rows_per_block = 0 is pcg_solve.
 static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_level* const* Ms,
                        const double* const* fs, double* const* us, int R, int rows_per_block,
@@ -2122,7 +2162,8 @@ int pcg_solve_noalloc(const nlsp_operator* A, const nlsp_two_level* M, const dou
 }
 
 size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R, int rows_per_block) {
-  if (nsys < 1 || !sys || R < 1 || R > MAXR || rows_per_block < 0) return 0;
+  if (nsys < 1 || !sys || R < 1 || R > MAXR || rows_per_block < -1) return 0;
+  rows_per_block = resolve_tile(nsys, sys, R, rows_per_block);
   std::vector<SysShape> sh(nsys);
   for (int i = 0; i < nsys; ++i) {
     const int64_t n = op_size(&sys[i].A);
@@ -2135,7 +2176,8 @@ size_t pcg_solve_batched_workspace_bytes(int nsys, const nlsp_system* sys, int R
 
 int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_block, const nlsp_pcg_opts* opts,
                       nlsp_rhs_info* info, void* ws, size_t ws_bytes, void* stream_) {
-  if (nsys < 1 || !sys || !info || !opts_ok(opts) || rows_per_block < 0) return NLSP_E_INVALID;
+  if (nsys < 1 || !sys || !info || !opts_ok(opts) || rows_per_block < -1) return NLSP_E_INVALID;
+  rows_per_block = resolve_tile(nsys, sys, R, rows_per_block);
   std::vector<const nlsp_operator*> As(nsys);
   std::vector<const nlsp_two_level*> Ms(nsys);
   std::vector<const double*> fs(nsys);
@@ -2239,7 +2281,17 @@ int pcg_solve_batched_tune(int nsys, const nlsp_system* sys, int R, const nlsp_p
   (void)hipEventDestroy(e1);
   if (rc != NLSP_OK) return rc;
   *best_rows_per_block = kTuneChunks[best_c] * (NT / R);
+  TuneKey key;
+  if (tune_key(nsys, sys, R, key)) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[key] = *best_rows_per_block;
+  }
   return NLSP_OK;
+}
+
+int pcg_solve_batched_tuned(int nsys, const nlsp_system* sys, int R, int* rows_per_block) {
+  if (nsys < 1 || !sys || R < 1 || R > MAXR || !rows_per_block) return NLSP_E_INVALID;
+  return tuned_tile(nsys, sys, R, rows_per_block) ? 1 : 0;
 }
 
 }  // extern "C"

@@ -126,16 +126,42 @@ def test_deterministic_and_graph_replay_matches_direct_launches(nl):
 
 
 def test_tuner_picks_a_candidate_and_leaves_u(nl):
-    batch = _batch(nl, 8, seed=3)
+    batch = _batch(nl, 8, seed=3, sides=[23, 30, 41, 18])
     systems = _systems(nl, batch)
+    assert nl.pcg_solve_batched_tuned(systems, prec=1) is None
     for s in systems:
         s.u.fill_(0.25)
     best, times = nl.pcg_solve_batched_tune(systems, prec=1, iters=8)
     assert best in times and len(times) >= 4 and all(t > 0 for t in times.values())
     for s in systems:
         assert torch.all(s.u == 0.25)
+    # the choice is recorded for this batch shape (and only for it)
+    assert nl.pcg_solve_batched_tuned(systems, prec=1) == best
+    assert nl.pcg_solve_batched_tuned(systems, prec=0) is None
+    assert nl.pcg_solve_batched_tuned(systems[:3], prec=1) is None
+    assert nl.pcg_solve_batched_tuned(systems[::-1], prec=1) is None
     infos, rc = nl.pcg_solve_batched(systems, prec=1, rows_per_block=best)
     assert rc == nl.OK
+    u_best = [s.u.clone() for s in systems]
+    for s in systems:
+        s.u.zero_()
+    infos2, rc2 = nl.pcg_solve_batched(systems, prec=1, rows_per_block=nl.TUNED)
+    assert rc2 == nl.OK
+    for a, s in zip(u_best, systems):
+        assert torch.equal(a, s.u)
+    for a, b in zip(infos, infos2):
+        assert [(x.iters, x.relres) for x in a] == [(x.iters, x.relres) for x in b]
+    # an untuned shape under TUNED runs the default plan
+    sub = systems[:2]
+    for s in sub:
+        s.u.zero_()
+    i3, _ = nl.pcg_solve_batched(sub, prec=1, rows_per_block=nl.TUNED)
+    u3 = [s.u.clone() for s in sub]
+    for s in sub:
+        s.u.zero_()
+    i4, _ = nl.pcg_solve_batched(sub, prec=1, rows_per_block=0)
+    for a, s in zip(u3, sub):
+        assert torch.equal(a, s.u)
 
 
 def test_invalid(nl):

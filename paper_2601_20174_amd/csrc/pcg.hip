@@ -1379,7 +1379,9 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         {
           const int row = t / R, cc = t % R, slot = mf_slot<QT>(row % 16, cc);
           QT sum = QT(0);
-          for (int k2 = 0; k2 < mKS; ++k2) sum += mfpart[(k2 * mRTN + row / 16) * 256 + slot];
+#pragma unroll
+          for (int k2 = 0; k2 < 4; ++k2)
+            if (k2 < mKS) sum += mfpart[(k2 * mRTN + row / 16) * 256 + slot];
           ys[t] = sum;
         }
       } else {

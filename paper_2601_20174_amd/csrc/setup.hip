@@ -435,6 +435,33 @@ NLSP_DEV void rr_pair(int rnd, int t, int m, int& p, int& q) {
   }
 }
 
+// The rotation (c, s) that annihilates a_pq of the 2 x 2 block [a_pp a_pq;
+// a_pq a_qq] (Golub & Van Loan, the symmetric Schur decomposition: the
+// smaller root of t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq)).
+NLSP_DEV void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (apq != 0.0 && fabs(apq) > 1e-300) {
+    const double tau = (aqq - app) / (2.0 * apq);
+    const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    c = 1.0 / sqrt(1.0 + tt * tt);
+    s = tt * c;
+  }
+}
+
+// The 2 x 2 block of G at rows (pa, qa) and columns (pb, qb) after
+// J_a^T (block) J_b: the column rotation (cb, sb), then the row rotation
+// (ca, sa).
+NLSP_DEV void rotate_block(double ca, double sa, double cb, double sb, double g11, double g12, double g21,
+                           double g22, double& o11, double& o12, double& o21, double& o22) {
+  const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;   // columns: J_b
+  const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
+  o11 = ca * h11 - sa * h21;                                           // rows: J_a
+  o21 = sa * h11 + ca * h21;
+  o12 = ca * h12 - sa * h22;
+  o22 = sa * h12 + ca * h22;
+}
+
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, int m, int max_sweeps,
                                                      double* __restrict__ rot, int* __restrict__ nsweeps,
@@ -467,14 +494,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, in
       if (t < half) {
         int p, q;
         rr_pair(rnd, t, m, p, q);
-        const double apq = G[p * m + q], app = G[p * m + p], aqq = G[q * m + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > 1e-300) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-        }
+        double c, s;
+        jacobi_rotation(G[p * m + p], G[q * m + q], G[p * m + q], c, s);
         cs[t] = c;
         sn[t] = s;
         pp[t] = p;
@@ -493,12 +514,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, in
         const int pa = pp[a], qa = qq[a];
         const double ca = cs[a], sa = sn[a];
         const double g11 = G[pa * m + pb], g12 = G[pa * m + qb], g21 = G[qa * m + pb], g22 = G[qa * m + qb];
-        const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;   // columns: J_b
-        const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
-        G[pa * m + pb] = ca * h11 - sa * h21;                                  // rows: J_a
-        G[qa * m + pb] = sa * h11 + ca * h21;
-        G[pa * m + qb] = ca * h12 - sa * h22;
-        G[qa * m + qb] = sa * h12 + ca * h22;
+        rotate_block(ca, sa, cb, sb, g11, g12, g21, g22, G[pa * m + pb], G[pa * m + qb], G[qa * m + pb],
+                     G[qa * m + qb]);
       }
       wg_sync<LDS>();
     }
@@ -506,6 +523,63 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, in
   if (t == 0) nsweeps[0] = sweep;
   if (LDS)
     for (int idx = t; idx < m * m; idx += nt) Gg[idx] = G[idx];
+}
+
+// Multi-workgroup form for m > 128, where G does not fit in LDS: one launch
+// per round, G_out = J^T G_in J between two buffers, each workgroup forming
+// all m/2 rotations of the round from G_in (workgroup 0 records them) and
+// updating its share of the 2 x 2 blocks; k_jacobi_check opens each sweep.
+// Same rotations, same block arithmetic and same stopping rule as
+// k_jacobi_eig.  ctl: [sweeps recorded, converged].
+constexpr int JR_THREADS = 256;
+__global__ __launch_bounds__(1024) void k_jacobi_check(const double* __restrict__ G, int m, int sweep,
+                                                       int* __restrict__ ctl, double* __restrict__ offnorm) {
+  __shared__ double red[16];
+  const int t = threadIdx.x;
+  double off = 0.0, tot = 0.0;
+  for (int idx = t; idx < m * m; idx += blockDim.x) {
+    const double g = G[idx];
+    tot += g * g;
+    if (idx / m != idx % m) off += g * g;
+  }
+  off = block_sum(off, red);
+  __syncthreads();
+  tot = block_sum(tot, red);
+  if (t == 0) {
+    offnorm[0] = sqrt(off / (tot > 0 ? tot : 1.0));
+    const int conv = off <= 1e-30 * tot;
+    ctl[0] = conv ? sweep : sweep + 1;
+    ctl[1] = conv;
+  }
+}
+
+__global__ __launch_bounds__(JR_THREADS) void k_jacobi_round(const double* __restrict__ Gin,
+                                                             double* __restrict__ Gout, int m, int rnd,
+                                                             double* __restrict__ rs) {
+  __shared__ double cs[128], sn[128];
+  __shared__ int pp[128], qq[128];
+  const int t = threadIdx.x, half = m / 2;
+  for (int u = t; u < half; u += JR_THREADS) {
+    int p, q;
+    rr_pair(rnd, u, m, p, q);
+    double c, s;
+    jacobi_rotation(Gin[p * m + p], Gin[q * m + q], Gin[p * m + q], c, s);
+    cs[u] = c;
+    sn[u] = s;
+    pp[u] = p;
+    qq[u] = q;
+    if (blockIdx.x == 0) {
+      rs[((int64_t)rnd * half + u) * 2] = c;
+      rs[((int64_t)rnd * half + u) * 2 + 1] = s;
+    }
+  }
+  __syncthreads();
+  for (int g = blockIdx.x * JR_THREADS + t; g < half * half; g += gridDim.x * JR_THREADS) {
+    const int a = g / half, b = g - a * half;
+    const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+    rotate_block(cs[a], sn[a], cs[b], sn[b], Gin[pa * m + pb], Gin[pa * m + qb], Gin[qa * m + pb],
+                 Gin[qa * m + qb], Gout[pa * m + pb], Gout[pa * m + qb], Gout[qa * m + pb], Gout[qa * m + qb]);
+  }
 }
 
 // V = J_1 J_2 ... from the recorded rotations.  Each row of V evolves on its
@@ -944,7 +1018,12 @@ inline int eig_threads(int m) {
   return (1024 / l) * l;
 }
 
-static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, double* off, hipStream_t s) {
+// Eigenpairs of the symmetric m x m matrix G: on return G holds the rotated
+// matrix and V the accumulated rotations.  G2 (m x m doubles) is scratch for
+// m > 128, whose rounds run as separate launches; there the host reads the
+// convergence flag after each sweep (one stream synchronisation per sweep).
+static int launch_eig(double* G, double* G2, double* V, int m, double* rot, int* nsweeps, double* off,
+                      hipStream_t s) {
   // m is padded to a multiple of 16
   if (m < 16 || m % 16 != 0 || m > 256 || eig_threads(m) < 64) return NLSP_E_INVALID;
   if (m <= LDS_DENSE_MAX) {
@@ -954,8 +1033,25 @@ static int launch_eig(double* G, double* V, int m, double* rot, int* nsweeps, do
     hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(eig_threads(m)), sh, s, G, m, JACOBI_MAX_SWEEPS, rot,
                        nsweeps, off);
   } else {
-    hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(eig_threads(m)), 0, s, G, m, JACOBI_MAX_SWEEPS, rot,
-                       nsweeps, off);
+    // m - 1 rounds per sweep (odd), so the current matrix alternates between
+    // the buffers from sweep to sweep
+    const int half = m / 2, nwg = ceil_div(half * half, JR_THREADS);
+    double* buf[2] = {G, G2};
+    int sweep = 0;
+    for (; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+      const double* cur = buf[sweep & 1];
+      hipLaunchKernelGGL(k_jacobi_check, dim3(1), dim3(1024), 0, s, cur, m, sweep, nsweeps, off);
+      int ctl[2] = {0, 0};
+      NLSP_HIP(hipMemcpyAsync(ctl, nsweeps, sizeof(ctl), hipMemcpyDeviceToHost, s));
+      NLSP_HIP(hipStreamSynchronize(s));
+      if (ctl[1]) break;
+      double* rs = rot + (size_t)sweep * (m - 1) * half * 2;
+      for (int rnd = 0; rnd < m - 1; ++rnd)
+        hipLaunchKernelGGL(k_jacobi_round, dim3(nwg), dim3(JR_THREADS), 0, s, buf[(sweep + rnd) & 1],
+                           buf[(sweep + rnd + 1) & 1], m, rnd, rs);
+      NLSP_HIP(hipGetLastError());
+    }
+    if (sweep & 1) NLSP_HIP(hipMemcpyAsync(G, G2, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
   }
   hipLaunchKernelGGL(k_jacobi_vecs, dim3(m / 4), dim3(256), sizeof(double) * (4 * m + 4 * JV_PAIRS), s, rot, nsweeps,
                      m, V);
@@ -1144,7 +1240,7 @@ static int setup_impl(const OpDev& op, const double* S0, int m, int k, double om
   // Gram and eigenpairs
   int rc = gram<T>(Sa, Sa, n, mp, mp, 1, L.part, L.G, mp, s);
   if (rc) return rc;
-  rc = launch_eig(L.G, L.V, mp, L.rot, L.nsweeps, L.off, s);
+  rc = launch_eig(L.G, L.part, L.V, mp, L.rot, L.nsweeps, L.off, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_eig_finish, dim3(1), dim3(256), 0, s, L.G, L.V, mp, m, k, kq, sigma, L.T,
                      L.info, 0);
@@ -1260,7 +1356,7 @@ static int randomized_impl(const OpDev& op, const double* S0, int m, int k, doub
   if (rc) return rc;
   rc = gram<double>(R.C, R.C, mp, lq, lq, 1, L.part, L.G, lq, s);
   if (rc) return rc;
-  rc = launch_eig(L.G, L.V, lq, L.rot, L.nsweeps, L.off, s);
+  rc = launch_eig(L.G, L.part, L.V, lq, L.rot, L.nsweeps, L.off, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_eig_finish, dim3(1), dim3(256), 0, s, L.G, L.V, lq, l, k, kq, sigma, L.T, R.info, 1);
   // P0 = Q_Y U_B[:, :k] (into the free buffer), CholeskyQR2, signs

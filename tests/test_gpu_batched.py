@@ -140,6 +140,8 @@ def test_tuner_picks_a_candidate_and_leaves_u(nl):
     assert nl.pcg_solve_batched_tuned(systems, prec=0) is None
     assert nl.pcg_solve_batched_tuned(systems[:3], prec=1) is None
     assert nl.pcg_solve_batched_tuned(systems[::-1], prec=1) is None
+    for s in systems:
+        s.u.zero_()
     infos, rc = nl.pcg_solve_batched(systems, prec=1, rows_per_block=best)
     assert rc == nl.OK
     u_best = [s.u.clone() for s in systems]

@@ -137,8 +137,11 @@ def _sin_theta(U, V):
     return np.linalg.norm(Qu - Qv @ (Qv.T @ Qu), 2)
 
 
+# m above 128: the eigensolver's multi-workgroup form (one launch per round)
 @pytest.mark.parametrize("kind,size,m,k", [("poisson", (32, 32), 32, 16), ("fv5", (45, 38), 48, 20),
-                                           ("q1", (40, 40), 64, 32), ("fv7", (17, 13), 40, 8)])
+                                           ("q1", (40, 40), 64, 32), ("fv7", (17, 13), 40, 8),
+                                           ("fv5", (45, 38), 150, 60), ("q1", (40, 40), 200, 90),
+                                           ("fv7", (17, 13), 256, 64)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_setup_spectral_P(nl, kind, size, m, k, prec):
     A, op, n = make_case(kind, 6, size)

@@ -544,7 +544,7 @@ def batched_legs(nl, torch, dev, nsys=None):
             "speedup_setup_plus_solve": round((setup_ms + s_ms) / (setup_ms + b_ms), 3)}
 
 
-def predictor_leg(nl, torch, dev, train_steps=150, held_out=8):
+def predictor_leg(nl, torch, dev, train_steps=150, held_out=100):
     """P-predictor on the training workload (64 log-normal fields of 128^2,
     k = 32, m = 64 relaxed vectors per field, hidden width 32): time of one
     training step (CNN forward, thin QR, NLSS loss + Galerkin-convergence term

@@ -796,43 +796,76 @@ __global__ __launch_bounds__(256) void k_tri_inv_lower(const double* __restrict_
   }
 }
 
-// C (n, b) = X (n, a) * B (a, b) in float64, B small (dense, row-major).
-// One wave per 16 rows: v_mfma_f64_16x16x4f64 with A[i][kk] = X[r0+i][k0+kk],
-// B[kk][j] = B[k0+kk][16J+j].  a multiple of 4, b multiple of 16.
+// C (n, b) = X (n, a) * B (a, b) in float64 for a b beyond what one LDS copy
+// of B holds (the setup's S V with a = m, CholeskyQR2's X R^-1 with a = k):
+// the columns of B are split into slices of BC = 16 JW columns, and a
+// persistent workgroup (one per CU) keeps its slice in LDS, rows padded by 4
+// doubles so the four 4-row groups that one MFMA reads fall on different
+// banks, then walks blocks of 128 rows, one 16-row tile per wave.  The
+// workgroups of the slices of the same row blocks are consecutive logical
+// blocks (xcd_remap), so they run on one XCD and the repeated reads of X hit
+// its L2.  v_mfma_f64_16x16x4f64: a lane loads 4 consecutive k of its row
+// (16 or 32 bytes) and feeds 4 products with them, the k index permuted the
+// same way for B (MFMA u takes k = k0 + 4 (lane / 16) + u); the next 16 k of
+// X are loaded before the products of the current ones.  a multiple of 16.
+constexpr int TSW_NT = 512, TSW_ROWS = 128;
+constexpr int TSW_LDS = 18432;   // doubles of the B slice in LDS (144 KB)
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_tsgemm(const T* __restrict__ X, int64_t n, int a,
-                                                const double* __restrict__ B, int b,
-                                                double* __restrict__ C, int ldc, int bcols_out) {
-  constexpr int MAXJ = 16;
-  const int lane = threadIdx.x & 63;
-  const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 16;
-  if (r0 >= n) return;
-  const int TB = b / 16;
-  d4_t acc[MAXJ];
-#pragma unroll
-  for (int q = 0; q < MAXJ; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t ra = r0 + li;
-  for (int k0 = 0; k0 < a; k0 += 4) {
-    const double av = (ra < n) ? (double)X[ra * a + k0 + lk] : 0.0;
-#pragma unroll
-    for (int q = 0; q < MAXJ; ++q) {
-      if (q < TB) {
-        const double bv = B[(int64_t)(k0 + lk) * b + 16 * q + li];
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
-      }
-    }
+NLSP_DEV void ld4(const T* p, T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+    const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
   }
+}
+
+template <typename T, int JW>
+__global__ __launch_bounds__(TSW_NT) void k_tsgemm_wide(const T* __restrict__ X, int64_t n, int a,
+                                                        const double* __restrict__ B, int b, int nsplit,
+                                                        double* __restrict__ C, int ldc, int bcols_out) {
+  extern __shared__ double bsl[];   // a rows of LDB
+  constexpr int BC = 16 * JW, LDB = BC + 4;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slice = lb % nsplit, ngrp = gridDim.x / nsplit;
+  const int grp = lb / nsplit, c0 = slice * BC;
+  if (grp >= ngrp) return;   // a remainder block (uniform)
+  for (int idx = threadIdx.x; idx < a * BC; idx += TSW_NT) {
+    const int r = idx / BC, cc = idx - r * BC;
+    bsl[r * LDB + cc] = B[(int64_t)r * b + c0 + cc];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int64_t nblk = (n + TSW_ROWS - 1) / TSW_ROWS;
+  for (int64_t blk = grp; blk < nblk; blk += ngrp) {
+    const int64_t r0 = blk * TSW_ROWS + 16 * w;
+    const T* xr = X + min(r0 + li, n - 1) * a + 4 * lk;   // rows past n: a clamped row, not stored
+    d4_t acc[JW];
 #pragma unroll
-  for (int q = 0; q < MAXJ; ++q) {
-    if (q < TB) {
+    for (int q = 0; q < JW; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+    T xv[4], xn[4];
+    ld4<T>(xr, xv);
+    for (int k0 = 0; k0 < a; k0 += 16) {
+      ld4<T>(xr + min(k0 + 16, a - 16), xn);
+      const double* br = bsl + (k0 + 4 * lk) * LDB + li;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < JW; ++q)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xv[u], br[u * LDB + 16 * q], acc[q], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = xn[u];
+    }
+#pragma unroll
+    for (int q = 0; q < JW; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = r0 + 4 * v + lk;   // float64 MFMA output row order
-        const int col = 16 * q + li;
+        const int col = c0 + 16 * q + li;
         if (row < n && col < bcols_out) C[row * ldc + col] = acc[q][v];
       }
-    }
   }
 }
 
@@ -1128,8 +1161,25 @@ static void tsgemm(const T* X, int64_t n, int a, const double* B, int b, double*
       hipLaunchKernelGGL((k_tsgemm_lds<T, 16>), dim3(wgs), dim3(256), 0, s, X, n, a, B, b, C, ldc, bcols_out);
     return;
   }
-  hipLaunchKernelGGL(k_tsgemm<T>, dim3(ceil_div(tiles, 4)), dim3(256), 0, s, X, n, a, B, b, C, ldc,
-                     bcols_out);
+  // the widest slice of 16, 32, 64 or 128 columns that divides b and fits in LDS
+  int jw = 8;
+  while (jw > 1 && (b % (16 * jw) != 0 || (size_t)a * (16 * jw + 4) > (size_t)TSW_LDS)) jw /= 2;
+  const int nsplit = b / (16 * jw);
+  const size_t sh = sizeof(double) * a * (16 * jw + 4);
+  // one workgroup per CU (LDS), a multiple of nsplit; no more row groups than row blocks
+  const int64_t nblk = (n + TSW_ROWS - 1) / TSW_ROWS;
+  const int ngrp = (int)std::max<int64_t>(1, std::min<int64_t>(256 / nsplit, nblk));
+  const unsigned wgs = (unsigned)(ngrp * nsplit);
+  auto go = [&](auto kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL(kern, dim3(wgs), dim3(TSW_NT), sh, s, X, n, a, B, b, nsplit, C, ldc, bcols_out);
+  };
+  switch (jw) {
+    case 8: go(k_tsgemm_wide<T, 8>); break;
+    case 4: go(k_tsgemm_wide<T, 4>); break;
+    case 2: go(k_tsgemm_wide<T, 2>); break;
+    default: go(k_tsgemm_wide<T, 1>);
+  }
 }
 
 inline int pad16(int v) { return (v + 15) / 16 * 16; }

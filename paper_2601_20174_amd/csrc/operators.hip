@@ -277,16 +277,30 @@ NLSP_DEV P* at_b(P* base, uint32_t off) {
   return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
 }
 
-//   MODE 0: y = A x;  MODE 1: y = x + omega D^-1 (b - A x)  (as k_rows)
-template <typename T, int MODE, int VW, int LPR, int TX, int TY>
-__global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty, int zc, T omega,
+//   MODE 0: y = A x;  MODE 1: y = x + omega D^-1 (b - A x)  (as k_rows);
+//   MODE 2: y = x - (omega / a_ii) (A x)  (the setup's relaxation, b = 0, in
+//   the form of the multi-column setup pass)
+// Storage T, arithmetic AT (the setup relaxes float32 vectors with float64
+// coefficients and sums).  The R = LPR VW values of a row are columns
+// blockIdx.y R .. of rows with stride ld (ld = R for the right-hand-side
+// blocks of the operator entry points; wider for the setup's column blocks).
+template <typename T, int MODE, int VW, int LPR, int TX, int TY, typename AT = T, bool SLAB = false>
+__global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty, int zc, int ld_slab, AT omega,
                                                                    const T* __restrict__ b,
                                                                    const T* __restrict__ x, T* __restrict__ y) {
   using Z = ZTile<LPR, TX, TY>;
   static_assert(Z::NT == 64 * LPR, "launch bound");
+  static_assert(!(SLAB && MODE == 1), "column slabs carry no right-hand side");
   constexpr int NT = Z::NT, R = LPR * VW, IPT = Z::IPT, TYS = Z::TYS, HI = Z::HI, FF = Z::FF;
   constexpr int LW = TX + 2, LSZ = (TY + 2) * LW * R;
   __shared__ T lds[2 * LSZ];
+  // the row stride: R for the right-hand-side blocks (a constant there),
+  // ld_slab for column slabs
+  const int ld = SLAB ? ld_slab : R;
+  if (SLAB) {
+    x += (int64_t)blockIdx.y * R;
+    y += (int64_t)blockIdx.y * R;
+  }
   const int nx = op.nx, ny = op.ny, nz = op.nz;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);   // z-chunk major: an XCD sweeps whole planes
   const int tiles = ntx * nty;
@@ -306,7 +320,7 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
     const int gy = min(yy, ny - 1);
     gyv[u] = gy;
     const uint32_t ci = (uint32_t)gy * nx + gx;
-    vo[u] = (ci * R + j * VW) * (uint32_t)sizeof(T);
+    vo[u] = (ci * (uint32_t)ld + j * VW) * (uint32_t)sizeof(T);
     co[u] = ci * 8u;
     inxy[u][0] = gx > 0;
     inxy[u][1] = gx < nx - 1;
@@ -326,7 +340,7 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
     else { lx = TX; ly = hc - 2 * TX - TY; }
     const int hx = x0 + lx, hy = y0 + ly;
     const bool in = h < Z::HC * LPR && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
-    ho[q] = in ? (((uint32_t)hy * nx + hx) * R + hj * VW) * (uint32_t)sizeof(T) : 0u;
+    ho[q] = in ? (((uint32_t)hy * nx + hx) * (uint32_t)ld + hj * VW) * (uint32_t)sizeof(T) : 0u;
     hl[q] = in ? ((ly + 1) * LW + lx + 1) * R + hj * VW : -1;
   }
   // this lane's faces: z step and the in-plane byte offset of the neighbour's
@@ -343,8 +357,9 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
       fco[u][f] = ((uint32_t)min(max(gyv[u] + dy, 0), ny - 1) * nx + min(max(gx + dx, 0), nx - 1)) * 8u;
   }
   const double* a = op.coef;   // generic pointer of a global buffer: the loads stay global
-  T pl[4][IPT][VW], hb[2][HI][VW], ac[2][IPT], af[2][IPT][FF], bq[2][IPT][VW];
-  const int64_t pstride = (int64_t)sxy * R;
+  T pl[4][IPT][VW], hb[2][HI][VW], bq[2][IPT][VW];
+  AT ac[2][IPT], af[2][IPT][FF];
+  const int64_t pstride = (int64_t)sxy * ld;
   auto plane = [&](const T* base, int z) { return base + (int64_t)min(max(z, 0), nz - 1) * pstride; };
   auto ld_plane = [&](T (&v)[IPT][VW], const T* base, int z) {
     const T* p = plane(base, z);
@@ -356,7 +371,7 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
 #pragma unroll
     for (int q = 0; q < HI; ++q) vload<T, VW>(at_b(p, ho[q]), v[q]);
   };
-  auto ld_coef = [&](T (&ap)[IPT], T (&fp)[IPT][FF], int z) {
+  auto ld_coef = [&](AT (&ap)[IPT], AT (&fp)[IPT][FF], int z) {
     const int zz = min(z, nz - 1), zlo = max(zz - 1, 0);
     const double* pa = a + (int64_t)zz * sxy;
     const double* pb = a + (int64_t)zlo * sxy;
@@ -364,10 +379,10 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
     for (int f = 0; f < FF; ++f) {
       const uint32_t zo = (uint32_t)(min(max(zz + fdz[f], 0), nz - 1) - zlo) * sxy * 8u;
 #pragma unroll
-      for (int u = 0; u < IPT; ++u) fp[u][f] = T(*at_b(pb, zo + fco[u][f]));
+      for (int u = 0; u < IPT; ++u) fp[u][f] = AT(*at_b(pb, zo + fco[u][f]));
     }
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) ap[u] = T(*at_b(pa, co[u]));
+    for (int u = 0; u < IPT; ++u) ap[u] = AT(*at_b(pa, co[u]));
   };
   auto step = [&](auto ph, int z) {
     constexpr int PH = decltype(ph)::value;
@@ -397,17 +412,17 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const bool in[6] = {inxy[u][0], inxy[u][1], inxy[u][2], inxy[u][3], z > 0, z < nz - 1};
-      const T aP = ac[H0][u];
-      T tf[FF];
+      const AT aP = ac[H0][u];
+      AT tf[FF];
 #pragma unroll
-      for (int f = 0; f < FF; ++f) tf[f] = harmonic<T>(aP, af[H0][u][f]);
-      T w[7];
-      T d = T(0);
+      for (int f = 0; f < FF; ++f) tf[f] = harmonic<AT>(aP, af[H0][u][f]);
+      AT w[7];
+      AT d = AT(0);
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
-        const T th = __shfl(tf[s / LPR], gbase + s % LPR);
-        d += in[s] ? th : T(2) * aP;
-        w[1 + s] = in[s] ? -th : T(0);
+        const AT th = __shfl(tf[s / LPR], gbase + s % LPR);
+        d += in[s] ? th : AT(2) * aP;
+        w[1 + s] = in[s] ? -th : AT(0);
       }
       w[0] = d;
       // a missing neighbour reads the centre value with weight 0 (as k_rows)
@@ -426,16 +441,15 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
         v[6][e] = in[5] ? pl[IN][u][e] : pl[IC][u][e];
       }
       T out[VW];
+      const AT sc = (MODE == 2) ? omega / w[0] : AT(0);
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
-        T acc = w[0] * v[0][e];
+        AT acc = w[0] * AT(v[0][e]);
 #pragma unroll
-        for (int s = 0; s < 6; ++s) acc += w[1 + s] * v[1 + s][e];
-        out[e] = acc;
-      }
-      if (MODE == 1) {
-#pragma unroll
-        for (int e = 0; e < VW; ++e) out[e] = v[0][e] + omega * (bq[H0][u][e] - out[e]) / w[0];
+        for (int s = 0; s < 6; ++s) acc += w[1 + s] * AT(v[1 + s][e]);
+        if (MODE == 1) acc = AT(v[0][e]) + omega * (AT(bq[H0][u][e]) - acc) / w[0];
+        if (MODE == 2) acc = AT(v[0][e]) - sc * acc;
+        out[e] = T(acc);
       }
       // non-temporal: y is not read again by this pass, so its lines do not
       // displace the planes and halos that neighbouring tiles still read from
@@ -470,16 +484,17 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
 // R = 16 with non-temporal stores: 32 planes against 16 (float64 apply
 // 0.1155 -> 0.1143 ms, float32 sweep 0.0746 -> 0.0722 ms) and 64 (0.132 /
 // 0.083 ms: too few blocks); a 16 x 16 tile measured slower for float64.
-template <typename T, int MODE, int VW, int LPR>
-inline void launch_zmarch(const OpDev& op, T omega, const T* b, const T* x, T* y, hipStream_t s) {
+template <typename T, int MODE, int VW, int LPR, typename AT = T, bool SLAB = false>
+inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const T* x, T* y, hipStream_t s, int ld = LPR * VW,
+                          int nslab = 1) {
   constexpr int TX = 16, TY = 8;
   using Z = ZTile<LPR, TX, TY>;
   const int ntx = (op.nx + TX - 1) / TX, nty = (op.ny + TY - 1) / TY;
   int zc = Z::NT >= 256 ? 32 : 16;
-  while (zc > 4 && (int64_t)ntx * nty * ((op.nz + zc - 1) / zc) < 512) zc /= 2;
+  while (zc > 4 && (int64_t)ntx * nty * ((op.nz + zc - 1) / zc) * nslab < 512) zc /= 2;
   const unsigned nb = (unsigned)((int64_t)ntx * nty * ((op.nz + zc - 1) / zc));
-  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY>), dim3(nb), dim3(Z::NT), 0, s, op, ntx, nty, zc,
-                     omega, b, x, y);
+  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY, AT, SLAB>), dim3(nb, nslab), dim3(Z::NT), 0, s, op, ntx, nty,
+                     zc, ld, omega, b, x, y);
 }
 
 // the z-march applies to 3-D FV7 operators with 2, 4 or 8 lanes of 16-byte
@@ -501,6 +516,27 @@ inline bool try_zmarch(const OpDev& op, int R, T omega, const T* b, const T* x, 
   }
   return true;
 }
+
+// The setup's multi-column passes over (n, ld) row-major blocks of a 3-D FV7
+// operator as z-marches over column slabs of 8 lanes of 16-byte vectors (32
+// float or 16 double columns, blockIdx.y the slab), float64 arithmetic:
+// mode 0 out = in - omega D^-1 A in, mode 1 out = A in.  False when the
+// shape does not fit (the caller then takes its row-blocked pass).
+template <typename T>
+bool zmarch_cols(const OpDev& op, int mode, double omega, int ld, const T* in, T* out, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T), LPR = 8, W = VW * LPR;
+  if (op.kind != NLSP_OP_FV7 || op.nz < 2 || ld % W != 0 || in == out) return false;
+  const int64_t sxy = (int64_t)op.nx * op.ny;
+  if (sxy * ld * (int64_t)sizeof(T) >= (int64_t(1) << 32) || 3 * sxy * 8 >= (int64_t(1) << 32)) return false;
+  if (reinterpret_cast<uintptr_t>(in) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 16 != 0) return false;
+  if (mode == 0)
+    launch_zmarch<T, 2, VW, LPR, double, true>(op, omega, nullptr, in, out, s, ld, ld / W);
+  else
+    launch_zmarch<T, 0, VW, LPR, double, true>(op, 0.0, nullptr, in, out, s, ld, ld / W);
+  return true;
+}
+template bool zmarch_cols<float>(const OpDev&, int, double, int, const float*, float*, hipStream_t);
+template bool zmarch_cols<double>(const OpDev&, int, double, int, const double*, double*, hipStream_t);
 
 // rows per block: 2048 (row, rhs) pairs, at most TRMAX rows
 inline int rows_per_block(int R) { return R >= 4 ? std::max(16, std::min(TRMAX, 2048 / R)) : TRMAX; }

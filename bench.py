@@ -50,6 +50,8 @@ def _args():
                     help="run only the batched anisotropic leg (for profiling it on its own)")
     ap.add_argument("--solve3d-leg", action="store_true",
                     help="only run the 3-D setup + solve leg (mixed and float64) and exit")
+    ap.add_argument("--predictor-leg", action="store_true",
+                    help="only run the training and predictor legs (for profiling them on their own)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count) and exit")
@@ -105,6 +107,10 @@ def main():
         return
     if a.solve3d_leg:
         print(json.dumps({"solve3d": solve3d_leg(nl, torch, dev)}), flush=True)
+        return
+    if a.predictor_leg:
+        print(json.dumps({"training": training_legs(nl, torch, dev), "predictor": predictor_leg(nl, torch, dev)}),
+              flush=True)
         return
     if a.batched_leg:
         print(json.dumps({"batched": batched_legs(nl, torch, dev)}), flush=True)

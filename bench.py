@@ -715,22 +715,22 @@ def cpu_baseline(c, coef, S0h, fh, iters_full, sample_iters=150, reps=5):
 
 def cpu_baseline_3d(c4, coef, fh, iters_full, sample_iters=3, reps=5):
     """The FP64 oracle's PCG on the 3-D workload, bounded: the oracle's
-    operator and an orthonormal basis of the same shape (Householder QR of a
-    seeded Gaussian n x k block; the per-iteration work of the oracle does
-    not depend on the basis values), `reps` runs of `sample_iters` iterations
-    on one right-hand side, median time per iteration x iterations x R."""
+    operator and a basis of the same shape (a seeded Gaussian n x k block
+    scaled by 1/sqrt(n); the per-iteration work of the oracle does not depend
+    on the basis values), `reps` runs of `sample_iters` iterations on one
+    right-hand side, median time per iteration x iterations x R."""
     import oracle as O
     from oracle.method import make_preconditioner
     import workloads as W
     model, ncores, threads = host_info()
     A = O.fv_harmonic_3d(coef)
-    P, _ = np.linalg.qr(W.normal_block(W.seed_for(4, 7), c4.n, c4.k))
+    P = W.normal_block(W.seed_for(4, 7), c4.n, c4.k) / np.sqrt(c4.n)
     _, L = O.galerkin(A, P)
     Minv = make_preconditioner(A, P, L, c4.omega, c4.nu, c4.nu)
     ms = _oracle_iter_ms(O, A, fh[:, :1], Minv, sample_iters, reps, False)
     return {"value": round(ms * iters_full * c4.R, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
             "nproc": ncores, "ms_per_iter_per_rhs": round(ms, 2),
-            "sample": f"{reps} oracle PCG runs of {sample_iters} iterations on one right-hand side (orthonormal "
+            "sample": f"{reps} oracle PCG runs of {sample_iters} iterations on one right-hand side (a Gaussian "
                       f"basis of the same shape), median time per iteration x {iters_full} iterations x "
                       f"{c4.R} right-hand sides (the oracle solves them one after another)"}
 

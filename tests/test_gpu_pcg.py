@@ -118,6 +118,19 @@ def test_3d_zmajor_chunks(nl, R, size, k, prec):
     _check(nl, A, op, P, f, prec=prec)
 
 
+# 2-D grids whose x-lines split into two or more whole chunks; 5- and
+# 9-point operators, lane-per-RHS and matrix-core forms
+@pytest.mark.parametrize("kind,size,R,k", [("fv5", (128, 41), 8, 16), ("q1", (128, 128), 8, 30),
+                                            ("fv5", (64, 37), 16, 40), ("poisson", (512, 9), 2, 16)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_2d_whole_chunk_lines(nl, kind, size, R, k, prec):
+    A, op, n = make_case(kind, 34, size)
+    S = O.relax(A, np.random.default_rng(35).standard_normal((n, 2 * k)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, k)
+    f = np.random.default_rng(36).standard_normal((n, R))
+    _check(nl, A, op, P, f, prec=prec)
+
+
 @pytest.mark.parametrize("nu", [2, 3])
 def test_more_sweeps(nl, nu):
     A, op, n = make_case("fv5", 31, (50, 41))
@@ -240,3 +253,46 @@ def test_3d_workload_full_size(nl):
         assert true_rel <= c4.rtol * 1.0001, (j, true_rel)
         assert abs(inf.relres - true_rel) <= 1e-3 * c4.rtol + 1e-12
 
+
+
+@pytest.fixture(scope="module")
+def full3d():
+    """The 3-D workload's operator (oracle), right-hand sides and a basis of
+    its shape (a seeded Gaussian block scaled by 1/sqrt(n): full rank, nearly
+    orthonormal; the two-level preconditioner does not need P^T P = I), with
+    the oracle's Galerkin factor."""
+    c4 = W.Cfg4()
+    a = c4.coef()
+    A = O.fv_harmonic_3d(a)
+    P = W.normal_block(W.seed_for(4, 8), c4.n, c4.k) / np.sqrt(c4.n)
+    _, L = O.galerkin(A, P)
+    return c4, a, A, P, L, c4.rhs()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_workload_full_size_first_iterates(nl, full3d, prec):
+    """The PCG iterates at full size in the launch configuration the benchmark
+    times (FV7 128^3, k = 128, 16 right-hand sides, matrix-core basis passes),
+    against the oracle's PCG on the same basis (given to both sides, so they
+    share their input P rather than computing it twice), Galerkin operator
+    formed on each side, three iterations from x0 = 0.  Bar: the float64 form
+    matches the oracle's x_3 to 1e-10 relative per right-hand side (rounding
+    order only); the mixed form (float32 basis and smoother, flexible beta on
+    both sides) to 1e-4 (float32 rounding of the preconditioner)."""
+    c4, a, A, P, L, fh = full3d
+    from tests._cases import gpu_op
+    op = gpu_op(nl.OP_FV7, c4.N, c4.N, c4.N, a)
+    M = nl.galerkin_coarse(op, cuda(P), c4.omega, c4.nu, q64=(prec == 0), q32=(prec == 1))
+    u, info, rc = nl.pcg_solve(op, M, cuda(fh), prec=prec, rtol=1e-30, maxit=3)
+    assert rc == nl.NOT_CONVERGED
+    assert all(inf.iters == 3 for inf in info)
+    u = host(u).reshape(fh.shape)
+    # sampled right-hand sides (the columns are independent; the GPU solved
+    # all 16 together)
+    cols = [0, 5, 10, 15]
+    res = O.pcg(A, fh[:, cols], make_preconditioner(A, P, L, c4.omega, c4.nu, c4.nu), rtol=1e-30, maxit=3,
+                flexible=(prec != 0))
+    tol = 1e-10 if prec == 0 else 1e-4
+    for i, j in enumerate(cols):
+        rel = np.linalg.norm(u[:, j] - res.x[:, i]) / np.linalg.norm(res.x[:, i])
+        assert rel <= tol, (j, rel)

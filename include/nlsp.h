@@ -354,6 +354,27 @@ int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_bloc
                       const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* The batched solve with its loop on the device (for callers that capture
+ * it in a graph or cannot wait on the host): the same kernels as
+ * pcg_solve_batched, but a fixed budget of opts->maxit iterations is enqueued
+ * on `stream` (maxit + 1 update and maxit matvec launches) and nothing is
+ * read back: no host synchronisation, host-to-device copy, memory fill or
+ * allocation happens (descriptors travel as kernel arguments).  A system
+ * whose right-hand sides have all stopped leaves the remaining launches at
+ * their first instructions, so choose maxit near the iterations expected.
+ * There is no residual replacement: a right-hand side whose recursive
+ * residual passed and whose true residual did not is NOT_CONVERGED.
+ *   info_dev  DEVICE array of nsys * R records (system-major), written by the
+ *             last kernel of the solve
+ *   opts->timing must be NULL; check_every is not used
+ * Returns NLSP_OK once everything is enqueued (or NLSP_E_INVALID /
+ * NLSP_E_WORKSPACE / NLSP_E_HIP); the per-RHS statuses are in info_dev.  The
+ * workspace is sized by pcg_solve_batched_workspace_bytes and must not be
+ * shared with another solve in flight. */
+int pcg_solve_batched_async(int nsys, const nlsp_system* sys, int R, int rows_per_block,
+                            const nlsp_pcg_opts* opts, nlsp_rhs_info* info_dev, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Autotuner of the batched solve's tile (rows of a system per workgroup):
  * times `iters` iterations of pcg_solve_batched (on copies of the initial
  * guesses held in the workspace; the caller's u is not modified) for each

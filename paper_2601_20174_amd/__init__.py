@@ -18,6 +18,6 @@ from .api import (  # noqa: F401
     SubspaceLoss, subspace_loss, captured_energy, galerkin_fwd_workspace_bytes, galerkin_bwd_workspace_bytes, galerkin_fwd,
     galerkin_bwd, GalerkinProduct, galerkin_product, galerkin_term_saved_bytes, galerkin_term_workspace_bytes,
     galerkin_term_fwd, galerkin_term_bwd, GalerkinTerm, galerkin_term, System, pcg_solve_batched_workspace_bytes,
-    pcg_solve_batched, pcg_solve_batched_tune, pcg_solve_batched_tuned, TUNED, qr_thin_workspace_bytes, qr_thin_fwd, qr_thin_bwd, ThinQ, thin_q,
+    pcg_solve_batched, pcg_solve_batched_tune, pcg_solve_batched_tuned, TUNED, pcg_solve_batched_async, rhs_info_from_device, qr_thin_workspace_bytes, qr_thin_fwd, qr_thin_bwd, ThinQ, thin_q,
     cnn_param_count, cnn_workspace_bytes, cnn_fwd, cnn_bwd, CnnPredictor, adam_step,
 )

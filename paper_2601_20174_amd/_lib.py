@@ -104,6 +104,8 @@ SIGNATURES = {
                                        c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_void_p,
                                        c_size_t, c_void_p]),
     "pcg_solve_batched_tuned": (c_int, [c_int, ctypes.POINTER(NlspSystem), c_int, ctypes.POINTER(c_int)]),
+    "pcg_solve_batched_async": (c_int, [c_int, ctypes.POINTER(NlspSystem), c_int, c_int, ctypes.POINTER(NlspPcgOpts),
+                                        c_void_p, c_void_p, c_size_t, c_void_p]),
     "qr_thin_workspace_bytes": (c_size_t, [c_int, c_int, c_int]),
     "qr_thin_fwd": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                             c_void_p]),

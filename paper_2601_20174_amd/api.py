@@ -720,6 +720,46 @@ def pcg_solve_batched(systems: List[System], prec: int = MIXED, rtol: float = 1e
     return out, rc
 
 
+RHS_INFO_BYTES = ctypes.sizeof(_lib.NlspRhsInfo)
+
+
+def pcg_solve_batched_async(systems: List[System], prec: int = MIXED, rtol: float = 1e-8, maxit: int = 1000,
+                            flexible: Optional[bool] = None, rows_per_block: int = 0,
+                            workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None):
+    """The batched solve with its loop on the device: enqueues a fixed budget
+    of `maxit` iterations on the current stream and returns at once, so it can
+    be captured in a CUDA/HIP graph (pass `workspace` and `info`, allocated
+    beforehand, to keep the call free of allocations).  Returns the device
+    tensor of per-RHS records (decode with rhs_info_from_device after the
+    stream has run)."""
+    arr, R = _systems(systems, prec)
+    if flexible is None:
+        flexible = prec != FP64
+    nb = _L().pcg_solve_batched_workspace_bytes(len(systems), arr, R, int(rows_per_block))
+    if nb == 0:
+        raise NlspError("pcg_solve_batched_workspace_bytes", E_INVALID)
+    dev = systems[0].f.device
+    ws = workspace if workspace is not None else _workspace(nb, dev)
+    need = len(systems) * R * RHS_INFO_BYTES
+    if info is None:
+        info = torch.empty(need, dtype=torch.uint8, device=dev)
+    if not info.is_cuda or info.dtype != torch.uint8 or info.numel() < need or info.data_ptr() % 8 != 0:
+        raise ValueError(f"info must be a GPU uint8 tensor of at least {need} bytes, 8-byte aligned")
+    opts = _opts(rtol, maxit, flexible, 1)
+    rc = _L().pcg_solve_batched_async(len(systems), arr, R, int(rows_per_block), ctypes.byref(opts),
+                                      info.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check("pcg_solve_batched_async", rc)
+    return info
+
+
+def rhs_info_from_device(info: torch.Tensor, nsys: int, R: int) -> List[List[RhsInfo]]:
+    """Decodes the device records of pcg_solve_batched_async (copies to the host)."""
+    raw = bytes(info[: nsys * R * RHS_INFO_BYTES].cpu().numpy().tobytes())
+    recs = (_lib.NlspRhsInfo * (nsys * R)).from_buffer_copy(raw)
+    return [[RhsInfo(recs[i * R + c].iters, recs[i * R + c].status, recs[i * R + c].relres) for c in range(R)]
+            for i in range(nsys)]
+
+
 def pcg_solve_batched_tune(systems: List[System], prec: int = MIXED, rtol: float = 1e-8, iters: int = 16,
                            flexible: Optional[bool] = None):
     """Times `iters` iterations per candidate tile (u is left untouched);

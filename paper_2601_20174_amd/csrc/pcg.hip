@@ -38,6 +38,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -1491,6 +1492,66 @@ __global__ void k_zero_cols(double* u, int64_t n, int R, unsigned mask) {
   if ((mask >> (g % R)) & 1u) u[g] = 0.0;
 }
 
+// ----------------------------------------- the capturable (device-loop) form
+// Everything the host-polled solve does with copies, fills and reads from the
+// host is done here by kernels whose data travel as kernel arguments, so the
+// whole solve can be enqueued without synchronising (and captured in a graph).
+
+// the columns of u whose right-hand side is zero (||f||^2 = 0 in the status
+// the start-up wrote) are cleared: u = 0 solves them whatever the guess
+__global__ void k_zero_cols_dev(double* u, int64_t n, int R, const RhsStatus* __restrict__ st) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * R) return;
+  if (st[g % R].ff == 0.0) u[g] = 0.0;
+}
+
+__global__ void k_fill_zero(uint32_t* p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// start state: every RHS active with a fresh direction (iteration -1 reads
+// stat[1]); counters nact(0) = 0, nact(1) = R, active = 0
+__global__ void k_init_batch(int nsys, int R, RhsStatus* __restrict__ stat1, int* __restrict__ counters) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < nsys * R) {
+    RhsStatus s{};
+    s.gamma_old = 1.0;
+    s.active = 1;
+    s.restart = 1;
+    s.status = NLSP_NOT_CONVERGED;
+    stat1[g] = s;
+  }
+  if (g < nsys * 4) counters[g] = (g % 4 == 1) ? R : 0;
+}
+
+// a host block (descriptors, block map) carried to device memory as a kernel
+// argument
+constexpr int PUT_BYTES = 2048;
+struct PutChunk {
+  unsigned char b[PUT_BYTES];
+};
+__global__ void k_put_bytes(unsigned char* __restrict__ dst, PutChunk c, int nbytes) {
+  for (int i = threadIdx.x; i < nbytes; i += blockDim.x) dst[i] = c.b[i];
+}
+
+// per RHS: iterations, status and the true relative residual; a RHS whose
+// recursive residual passed but whose true residual did not is reported
+// NOT_CONVERGED (this form has no residual replacement)
+__global__ void k_finalize(const SysDev* __restrict__ sys, int nsys, int R, const RhsStatus* __restrict__ stat,
+                           const double* __restrict__ rr_true, nlsp_rhs_info* __restrict__ info) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nsys * R) return;
+  const RhsStatus s = stat[g];
+  const double rrt = rr_true[g];
+  nlsp_rhs_info o;
+  o.iters = s.iters;
+  o.status = s.status;
+  o.relres = (s.ff > 0.0) ? sqrt(rrt / s.ff) : 0.0;
+  if (s.status == NLSP_OK && s.ff > 0.0 && !(rrt <= sys[g / R].tol2 * s.ff)) o.status = NLSP_NOT_CONVERGED;
+  info[g] = o;
+}
+
 // ------------------------------------------------------------- host side
 // ------------------------------------------------------------------ host side
 // Per-system buffers.  The arrays that must start at zero come first and are
@@ -1704,7 +1765,8 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
 // even).
 template <typename QS>
 static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, const std::vector<SolveLayout>& Ls,
-                   const nlsp_pcg_opts* opts, nlsp_rhs_info* info, bool graph, hipStream_t stream) {
+                   const nlsp_pcg_opts* opts, nlsp_rhs_info* info, bool graph, hipStream_t stream,
+                   nlsp_rhs_info* info_dev = nullptr) {
   using QT = typename Arith<QS>::type;
   const int R = hs[0].R;
   int nblk = 0;
@@ -1867,6 +1929,29 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   launch_update(stream, -1, 1, all, 1, true);
   launch_matvec(stream, -1, true);
   NLSP_RUN(hipGetLastError());
+  if (info_dev) {
+    // device loop: zero right-hand sides cleared on the device, then a fixed
+    // budget of maxit iterations (the decisions of update kernel maxit stop
+    // whatever still iterates), the true residuals and the per-RHS results,
+    // all enqueued without waiting; a system whose right-hand sides have all
+    // stopped leaves the remaining launches at their first instructions
+    for (int i = 0; i < nsys; ++i)
+      hipLaunchKernelGGL(k_zero_cols_dev, dim3(ceil_div(hs[i].op.n * R, 256)), dim3(256), 0, stream, hs[i].x,
+                         hs[i].op.n, R, B.stat0 + (size_t)i * R);
+    const int maxit = hs[0].maxit;
+    for (int it = 0; it <= maxit; ++it) {
+      launch_update(stream, it, 0, 0u, 0, false);
+      if (it < maxit) launch_matvec(stream, it, false);
+    }
+    hipLaunchKernelGGL(k_true_residual, grid, block, 0, stream, dsys, b2s, nsys);
+    hipLaunchKernelGGL(k_true_finish, dim3(nsys), block, 0, stream, dsys);
+    hipLaunchKernelGGL(k_finalize, dim3(ceil_div(nsys * R, 256)), dim3(256), 0, stream, dsys, nsys, R,
+                       ((maxit + 1) & 1) ? (const RhsStatus*)B.stat1 : (const RhsStatus*)B.stat0,
+                       (const double*)B.rr_true, info_dev);
+    NLSP_RUN(hipGetLastError());
+    release();
+    return NLSP_OK;
+  }
   std::vector<RhsStatus> hst((size_t)nsys * R);
   NLSP_RUN(hipMemcpyAsync(hst.data(), B.stat0, sizeof(RhsStatus) * nsys * R, hipMemcpyDeviceToHost, stream));
   NLSP_RUN(hipStreamSynchronize(stream));
@@ -2054,7 +2139,7 @@ static int resolve_tile(int nsys, const nlsp_system* sys, int R, int rows_per_bl
 static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_level* const* Ms,
                        const double* const* fs, double* const* us, int R, int rows_per_block,
                        const nlsp_pcg_opts* opts, nlsp_rhs_info* info, void* ws, size_t ws_bytes, bool graph,
-                       hipStream_t stream) {
+                       hipStream_t stream, nlsp_rhs_info* info_dev = nullptr) {
   std::vector<SysShape> sh(nsys);
   for (int i = 0; i < nsys; ++i)
     sh[i] = shape_of(op_size(As[i]), padded_rank(Ms[i]->k), R, rows_per_block,
@@ -2069,6 +2154,29 @@ static int solve_batch(int nsys, const nlsp_operator* const* As, const nlsp_two_
     hs[i] = make_sysdev(*As[i], *Ms[i], fs[i], us[i], sh[i], Ls[i], B, i, blk0, opts);
     for (int b = 0; b < sh[i].nblk; ++b) b2s.push_back(i);
     blk0 += sh[i].nblk;
+  }
+  if (info_dev) {
+    // device loop: the same start state, written by kernels (no host copy,
+    // no fill, no wait)
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(
+                                             (int64_t)(B.zero_bytes / 4), 256)))),
+                       dim3(256), 0, stream, reinterpret_cast<uint32_t*>(B.zero_begin), (int64_t)(B.zero_bytes / 4));
+    hipLaunchKernelGGL(k_init_batch, dim3(ceil_div(std::max(nsys * R, nsys * 4), 256)), dim3(256), 0, stream, nsys,
+                       R, B.stat1, B.counters);
+    auto put = [&](void* dst, const void* src, size_t bytes) {
+      for (size_t off = 0; off < bytes; off += PUT_BYTES) {
+        PutChunk c;
+        const int nb = (int)std::min<size_t>(PUT_BYTES, bytes - off);
+        std::memcpy(c.b, static_cast<const unsigned char*>(src) + off, nb);
+        hipLaunchKernelGGL(k_put_bytes, dim3(1), dim3(256), 0, stream, static_cast<unsigned char*>(dst) + off, c, nb);
+      }
+    };
+    put(B.sysdev, hs.data(), sizeof(SysDev) * nsys);
+    if (nsys > 1) put(B.blk2sys, b2s.data(), sizeof(int) * b2s.size());
+    NLSP_HIP(hipGetLastError());
+    if (Ms[0]->prec == NLSP_FP64) return run_pcg<double>(nsys, hs, B, Ls, opts, info, false, stream, info_dev);
+    if (Ms[0]->prec == NLSP_MIXED_F16) return run_pcg<_Float16>(nsys, hs, B, Ls, opts, info, false, stream, info_dev);
+    return run_pcg<float>(nsys, hs, B, Ls, opts, info, false, stream, info_dev);
   }
   // iteration -1 reads stat[1]: every RHS starts active with a fresh direction
   std::vector<RhsStatus> st0((size_t)nsys * R);
@@ -2201,6 +2309,32 @@ int pcg_solve_batched(int nsys, const nlsp_system* sys, int R, int rows_per_bloc
   const bool graph = opts->timing == nullptr;
   return solve_batch(nsys, As.data(), Ms.data(), fs.data(), us.data(), R, rows_per_block, opts, info, ws,
                      ws_bytes, graph, as_stream(stream_));
+}
+
+int pcg_solve_batched_async(int nsys, const nlsp_system* sys, int R, int rows_per_block, const nlsp_pcg_opts* opts,
+                            nlsp_rhs_info* info_dev, void* ws, size_t ws_bytes, void* stream_) {
+  if (nsys < 1 || !sys || !info_dev || !opts_ok(opts) || opts->timing || rows_per_block < -1)
+    return NLSP_E_INVALID;
+  rows_per_block = resolve_tile(nsys, sys, R, rows_per_block);
+  std::vector<const nlsp_operator*> As(nsys);
+  std::vector<const nlsp_two_level*> Ms(nsys);
+  std::vector<const double*> fs(nsys);
+  std::vector<double*> us(nsys);
+  int64_t blocks = 0;
+  for (int i = 0; i < nsys; ++i) {
+    const nlsp_system& s = sys[i];
+    const int64_t n = op_size(&s.A);
+    if (!system_ok(&s.A, &s.M, s.f, s.u, R, n)) return NLSP_E_INVALID;
+    if (s.M.prec != sys[0].M.prec || s.M.nu != sys[0].M.nu || s.M.k != sys[0].M.k) return NLSP_E_INVALID;
+    As[i] = &s.A;
+    Ms[i] = &s.M;
+    fs[i] = s.f;
+    us[i] = s.u;
+    blocks += shape_of(n, padded_rank(s.M.k), R, rows_per_block, false).nblk;
+  }
+  if (blocks > (int64_t(1) << 30)) return NLSP_E_INVALID;
+  return solve_batch(nsys, As.data(), Ms.data(), fs.data(), us.data(), R, rows_per_block, opts, nullptr, ws,
+                     ws_bytes, false, as_stream(stream_), info_dev);
 }
 
 // ---------------------------------------------------------------- autotuner

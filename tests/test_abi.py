@@ -194,6 +194,8 @@ def test_validation_rejects_before_any_gpu_call(lib):
     big = ctypes.byref(_op(api.OP_POISSON5, 2048, 1024))
     Mbig = _lib.NlspTwoLevel(128, 1, 2 / 3, api.MIXED, fake, None, fake)
     assert lib.pcg_solve_noalloc(big, ctypes.byref(Mbig), fake, u, 16, ctypes.byref(opts), info, None) == E_WS
+    tm_b = _lib.NlspKernelTiming(1, 1, 0.0, 0)
+    opts_tm_b = _lib.NlspPcgOpts(1e-8, 100, 0, 8, ctypes.pointer(tm_b))
     # batched: tile below -1, the tuned-tile query's arguments
     sysb = (_lib.NlspSystem * 1)(_lib.NlspSystem(_op(api.OP_POISSON5, 16, 16), M, fake, u))
     assert lib.pcg_solve_batched(1, sysb, 1, -2, ctypes.byref(opts), info, None, 0, None) == E_INV
@@ -202,6 +204,10 @@ def test_validation_rejects_before_any_gpu_call(lib):
     assert lib.pcg_solve_batched_tuned(0, sysb, 1, ctypes.byref(rpb)) == E_INV
     assert lib.pcg_solve_batched_tuned(1, sysb, 0, ctypes.byref(rpb)) == E_INV
     assert lib.pcg_solve_batched_tuned(1, sysb, 1, None) == E_INV
+    # device loop: a record array is required, timing is not supported
+    assert lib.pcg_solve_batched_async(1, sysb, 1, 0, ctypes.byref(opts), None, None, 0, None) == E_INV
+    assert lib.pcg_solve_batched_async(1, sysb, 1, 0, ctypes.byref(opts_tm_b), fake, None, 0, None) == E_INV
+    assert lib.pcg_solve_batched_async(1, sysb, 1, 0, ctypes.byref(opts), fake, None, 0, None) == E_WS
     tm = _lib.NlspKernelTiming(1, 1, 0.0, 0)
     opts_tm = _lib.NlspPcgOpts(1e-8, 100, 0, 8, ctypes.pointer(tm))
     assert lib.pcg_solve_noalloc(op, ctypes.byref(M), fake, u, 1, ctypes.byref(opts_tm), info, None) == E_INV

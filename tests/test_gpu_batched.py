@@ -194,3 +194,81 @@ def test_setup_many_matches_sequential_setup(nl):
         M1 = nl.galerkin_coarse(op, P, 2 / 3, 1)
         for a, b in ((M.Ac, M1.Ac), (M.L, M1.L), (M.Linv, M1.Linv), (M.Q64, M1.Q64), (M.Q32, M1.Q32)):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_device_loop_matches_host_polled_solve(nl, prec):
+    """The device-loop form enqueues the same kernels as the host-polled
+    solve up to convergence and then only launches that exit at once: when no
+    residual replacement was needed (equal iteration counts), u and every
+    per-RHS record agree bit for bit, and the zero right-hand side is solved
+    by u = 0 from a nonzero guess."""
+    R = 3
+    batch = _batch(nl, R, seed=5, zero_col=True)
+    s1 = _systems(nl, batch)
+    s2 = _systems(nl, batch)
+    for a, b in zip(s1, s2):
+        a.u.fill_(0.5)
+        b.u.fill_(0.5)
+    infos, rc = nl.pcg_solve_batched(s1, prec=prec, rtol=1e-8)
+    assert rc == nl.OK
+    dev_info = nl.pcg_solve_batched_async(s2, prec=prec, rtol=1e-8, maxit=400)
+    torch.cuda.synchronize()
+    infos2 = nl.rhs_info_from_device(dev_info, len(s2), R)
+    for a, b, ia, ib in zip(s1, s2, infos, infos2):
+        assert [(x.iters, x.status, x.relres) for x in ia] == [(x.iters, x.status, x.relres) for x in ib]
+        assert torch.equal(a.u, b.u)
+    assert torch.all(s2[2].u[:, 1] == 0.0)
+
+
+def test_device_loop_budget_reports_not_converged(nl):
+    """A budget below the iterations needed stops every right-hand side at
+    maxit with NOT_CONVERGED and its true relative residual."""
+    R = 2
+    batch = _batch(nl, R, seed=6, sides=[30, 41])
+    systems = _systems(nl, batch)
+    info = nl.rhs_info_from_device(nl.pcg_solve_batched_async(systems, prec=1, rtol=1e-8, maxit=5), 2, R)
+    for (A, op, M, P, f), s, inf in zip(batch, systems, info):
+        u = host(s.u)
+        for c in range(R):
+            true_rel = np.linalg.norm(f[:, c] - A @ u[:, c]) / np.linalg.norm(f[:, c])
+            assert inf[c].iters == 5 and inf[c].status == nl.NOT_CONVERGED
+            assert abs(inf[c].relres - true_rel) <= 1e-9 * max(1.0, true_rel)
+
+
+def test_device_loop_captured_in_a_graph(nl):
+    """The device-loop solve captured in a graph (workspace and record buffer
+    allocated beforehand) and replayed three times, with eager work and
+    synchronisations between the replays: every replay equals the eager
+    device-loop solve bit for bit."""
+    R = 8
+    batch = _batch(nl, R, seed=7, sides=[24, 31, 40, 50])
+    systems = _systems(nl, batch)
+    nsys = len(systems)
+    nb = nl.pcg_solve_batched_workspace_bytes(systems, nl.MIXED)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    info = torch.empty(nsys * R * nl.api.RHS_INFO_BYTES, dtype=torch.uint8, device="cuda")
+    nl.pcg_solve_batched_async(systems, prec=nl.MIXED, maxit=120, workspace=ws, info=info)
+    torch.cuda.synchronize()
+    u_ref = [s.u.clone() for s in systems]
+    info_ref = info.clone()
+    assert all(x.status == nl.OK for si in nl.rhs_info_from_device(info_ref, nsys, R) for x in si)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for s in systems:
+        s.u.zero_()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        nl.pcg_solve_batched_async(systems, prec=nl.MIXED, maxit=120, workspace=ws, info=info)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for s in systems:
+            s.u.zero_()
+        info.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, s in zip(u_ref, systems):
+            assert torch.equal(a, s.u), rep
+        assert torch.equal(info, info_ref), rep

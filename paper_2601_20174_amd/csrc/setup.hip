@@ -536,9 +536,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ Gg, in
 }
 
 // Multi-workgroup form for m > 128, where G does not fit in LDS: one launch
-// per round, G_out = J^T G_in J between two buffers, each workgroup forming
-// all m/2 rotations of the round from G_in (workgroup 0 records them) and
-// updating its share of the 2 x 2 blocks; k_jacobi_check opens each sweep.
+// per round, G_out = J^T G_in J between two buffers, one thread per 2 x 2
+// block forming the two rotations it needs from G_in; k_jacobi_check opens
+// each sweep.
 // Same rotations, same block arithmetic and same stopping rule as
 // k_jacobi_eig.  ctl: [sweeps recorded, converged].
 constexpr int JR_THREADS = 256;
@@ -566,30 +566,28 @@ __global__ __launch_bounds__(1024) void k_jacobi_check(const double* __restrict_
 __global__ __launch_bounds__(JR_THREADS) void k_jacobi_round(const double* __restrict__ Gin,
                                                              double* __restrict__ Gout, int m, int rnd,
                                                              double* __restrict__ rs) {
-  __shared__ double cs[128], sn[128];
-  __shared__ int pp[128], qq[128];
-  const int t = threadIdx.x, half = m / 2;
-  for (int u = t; u < half; u += JR_THREADS) {
-    int p, q;
-    rr_pair(rnd, u, m, p, q);
-    double c, s;
-    jacobi_rotation(Gin[p * m + p], Gin[q * m + q], Gin[p * m + q], c, s);
-    cs[u] = c;
-    sn[u] = s;
-    pp[u] = p;
-    qq[u] = q;
-    if (blockIdx.x == 0) {
-      rs[((int64_t)rnd * half + u) * 2] = c;
-      rs[((int64_t)rnd * half + u) * 2 + 1] = s;
-    }
+  // each thread forms the two rotations its block needs itself (the pair
+  // indices follow from the round), so every load of the round is issued at
+  // once and no barrier is needed; workgroup 0 records the rotations
+  const int half = m / 2;
+  const int g = blockIdx.x * JR_THREADS + threadIdx.x;
+  if (g >= half * half) return;
+  const int a = g / half, b = g - a * half;
+  int pa, qa, pb, qb;
+  rr_pair(rnd, a, m, pa, qa);
+  rr_pair(rnd, b, m, pb, qb);
+  const double g11 = Gin[pa * m + pb], g12 = Gin[pa * m + qb], g21 = Gin[qa * m + pb], g22 = Gin[qa * m + qb];
+  const double apa = Gin[pa * m + pa], aqa = Gin[qa * m + qa], apqa = Gin[pa * m + qa];
+  const double apb = Gin[pb * m + pb], aqb = Gin[qb * m + qb], apqb = Gin[pb * m + qb];
+  double ca, sa, cb, sb;
+  jacobi_rotation(apa, aqa, apqa, ca, sa);
+  jacobi_rotation(apb, aqb, apqb, cb, sb);
+  if (g < half) {   // a = 0: thread b records rotation b
+    rs[((int64_t)rnd * half + b) * 2] = cb;
+    rs[((int64_t)rnd * half + b) * 2 + 1] = sb;
   }
-  __syncthreads();
-  for (int g = blockIdx.x * JR_THREADS + t; g < half * half; g += gridDim.x * JR_THREADS) {
-    const int a = g / half, b = g - a * half;
-    const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-    rotate_block(cs[a], sn[a], cs[b], sn[b], Gin[pa * m + pb], Gin[pa * m + qb], Gin[qa * m + pb],
-                 Gin[qa * m + qb], Gout[pa * m + pb], Gout[pa * m + qb], Gout[qa * m + pb], Gout[qa * m + qb]);
-  }
+  rotate_block(ca, sa, cb, sb, g11, g12, g21, g22, Gout[pa * m + pb], Gout[pa * m + qb], Gout[qa * m + pb],
+               Gout[qa * m + qb]);
 }
 
 // V = J_1 J_2 ... from the recorded rotations.  Each row of V evolves on its
@@ -766,6 +764,44 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ G,
   if (t == 0) info[0] = bad;
 }
 
+// Inverse of a lower-triangular k x k matrix, 64 < k <= 128, row by row:
+// row i of L^-1 is (e_i - L[i][0:i] L^-1[0:i][:]) / L[i][i].  L and the rows
+// of L^-1 computed so far sit in LDS as packed lower triangles (2 x 66 KB at
+// k = 128); 8 lanes share an entry's sum (strided over c, then a butterfly),
+// one barrier per row.  Written zero-padded to (kp, kp).
+constexpr int TRI_ROWS_MAX = 128;
+inline size_t tri_rows_lds(int k) { return sizeof(double) * (size_t)k * (k + 1); }
+__global__ __launch_bounds__(1024) void k_tri_inv_rows(const double* __restrict__ L, int ldl, int k,
+                                                       double* __restrict__ Li, int kp) {
+  extern __shared__ double tri[];
+  const int tk = k * (k + 1) / 2;
+  double* Lp = tri;          // L[i][c] at i (i + 1) / 2 + c
+  double* Xp = tri + tk;     // (L^-1)[i][c] likewise
+  const int t = threadIdx.x, j = t >> 3, p = t & 7;
+  for (int e = t; e < tk; e += 1024) {
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    Lp[e] = L[(int64_t)i * ldl + (e - i * (i + 1) / 2)];
+  }
+  __syncthreads();
+  for (int i = 0; i < k; ++i) {
+    const double* Li_row = Lp + i * (i + 1) / 2;
+    double s = 0.0;
+    if (j < i)
+      for (int c = j + p; c < i; c += 8) s += Li_row[c] * Xp[c * (c + 1) / 2 + j];
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (p == 0 && j <= i) Xp[i * (i + 1) / 2 + j] = ((j == i ? 1.0 : 0.0) - s) / Li_row[i];
+    __syncthreads();
+  }
+  for (int e = t; e < kp * kp; e += 1024) {
+    const int r = e / kp, c = e % kp;
+    Li[e] = (r < k && c <= r) ? Xp[r * (r + 1) / 2 + c] : 0.0;
+  }
+}
+
 // Inverse of a lower-triangular k x k matrix L, written zero-padded to
 // (kp, kp): column j of L^-1 solves L x = e_j by forward substitution.
 __global__ __launch_bounds__(256) void k_tri_inv_lower(const double* __restrict__ L, int ldl, int k,
@@ -939,7 +975,7 @@ __global__ void k_transpose_pad(const double* __restrict__ A, int kp, double* __
 // coalesced loads (lane t takes column t % ld) and keeps, per column, the
 // first maximum of |P|; k_colsign_finish combines the workgroups in order and
 // stores the column signs, which k_copy_cols_signed applies.
-constexpr int CS_BLOCKS = 256;
+constexpr int CS_BLOCKS = 1024;
 
 __global__ __launch_bounds__(256) void k_colmax_partial(const double* __restrict__ P, int64_t n, int ld,
                                                         int64_t rows_per, double* __restrict__ pv,
@@ -1102,6 +1138,19 @@ static int launch_eig(double* G, double* G2, double* V, int m, double* rot, int*
   return NLSP_OK;
 }
 
+// L^-1 (zero-padded to kp x kp) of the lower-triangular k x k matrix L
+static int launch_tri_inv(const double* L, int ldl, int k, double* Li, int kp, hipStream_t s) {
+  if (k > 64 && k <= TRI_ROWS_MAX) {
+    NLSP_HIP(hipFuncSetAttribute((const void*)k_tri_inv_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)tri_rows_lds(TRI_ROWS_MAX)));
+    hipLaunchKernelGGL(k_tri_inv_rows, dim3(1), dim3(1024), tri_rows_lds(k), s, L, ldl, k, Li, kp);
+  } else {
+    hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L, ldl, k, Li, kp);
+  }
+  NLSP_HIP(hipGetLastError());
+  return NLSP_OK;
+}
+
 static int launch_chol(const double* G, int ldg, int k, double* L, int ldl, int* info,
                        hipStream_t s, double rtol = 0.0) {
   if (k <= LDS_DENSE_MAX) {
@@ -1255,7 +1304,8 @@ static int cholqr2(double*& Pa, double*& Pb, int64_t rows, int cq, int kr, const
     if (rc) return rc;
     rc = launch_chol(L.G, cq, kr, L.Lk, cq, info + pass, s, rtol);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L.Lk, cq, kr, L.T, cq);
+    rc = launch_tri_inv(L.Lk, cq, kr, L.T, cq, s);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_transpose_pad, dim3(ceil_div(cq * cq, 256)), dim3(256), 0, s, L.T, cq, L.Rinv);
     tsgemm<double>(Pa, rows, cq, L.Rinv, cq, Pb, cq, cq, s);
     std::swap(Pa, Pb);
@@ -1545,7 +1595,10 @@ int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega
   rc = launch_chol(L.Acp, kp, k, L.Lp, kp, L.info, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_pad_square, dim3(ceil_div(k * k, 256)), dim3(256), 0, s, L.Lp, kp, k, Lout, k, k);
-  hipLaunchKernelGGL(k_tri_inv_lower, dim3(1), dim3(256), 0, s, L.Lp, kp, k, Linv, kp);
+  {
+    const int rc2 = launch_tri_inv(L.Lp, kp, k, Linv, kp, s);
+    if (rc2) return rc2;
+  }
   // Q = (I - w D^-1 A)^nu P
   double* cur = L.Pp;
   double* bufs[2] = {L.Y, L.Z};

@@ -165,8 +165,10 @@ def test_setup_spectral_P(nl, kind, size, m, k, prec):
         assert P[np.argmax(np.abs(P[:, j])), j] > 0
 
 
+# k above 64: the row-by-row triangular inverse in LDS
 @pytest.mark.parametrize("kind,size,k", [("poisson", (32, 32), 16), ("fv5", (45, 38), 20),
-                                         ("q1", (40, 40), 17), ("fv7", (17, 13), 8)])
+                                         ("q1", (40, 40), 17), ("fv7", (17, 13), 8),
+                                         ("fv5", (45, 38), 100), ("fv7", (17, 13), 128)])
 @pytest.mark.parametrize("nu", [1, 2])
 def test_galerkin_coarse(nl, kind, size, k, nu):
     A, op, n = make_case(kind, 8, size)

@@ -109,6 +109,7 @@ struct SysDev {
   double omega, tol2;
   int maxit, flexible, nu;
   unsigned rmask;          // RHS a restart launch applies to (ANDed with the launch mask)
+  int ylines;              // 2-D line march of the float matrix-core update (chunks ordered y fastest)
 };
 
 // XCD-aware order: hardware places workgroup b on XCD b % 8; give each XCD a
@@ -509,6 +510,9 @@ struct QB {
 //     row tiles x R / 4 slices of 4 kp / R columns (one or two blocks of 16),
 //     the slices added in order through LDS.
 constexpr int MF_T = 16;   // columns of a tile
+// one line of the update kernel's 2-D march: (NT / R + 2) cells x R, at most
+// (64 + 2) x 8 and (32 + 2) x 16
+constexpr int YM_SLOT = 34 * 16;
 inline bool mf_ok(int R, int kp) {
   return (R == 16 && (kp == 64 || kp == 128)) || (R == 8 && (kp == 32 || kp == 64));
 }
@@ -553,6 +557,15 @@ NLSP_DEV int64_t chunk_row0(const SysDev& S, int64_t ch) {
     const int z = (int)(ch - col * nz);
     const int y = (int)(col / nxq), xq = (int)(col - (int64_t)y * nxq);
     return ((int64_t)z * S.op.ny + y) * S.op.nx + (int64_t)xq * cr;
+  }
+  if (S.ylines) {
+    // 2-D 9-point operators with the float matrix-core update march through y
+    // the same way (logical chunk ch is line ch % ny of the x-segment ch /
+    // ny), which that kernel's line ring relies on
+    const int ny = S.op.ny;
+    const int64_t xq = ch / ny;
+    const int y = (int)(ch - xq * ny);
+    return (int64_t)y * S.op.nx + xq * cr;
   }
   return ch * cr;
 }
@@ -993,7 +1006,7 @@ constexpr int PH_Z = 2;     // z = J r_new + Q c_new; partials r^T z, r^T z_old,
 //     update, `init` also takes ||f||^2, and the next iteration uses beta = 0.
 //   phase = PH_UPD only (nu > 1): stops after r_new; phase = PH_Z only, not a
 //     restart: z for the RHS the update phase advanced (stat[(it+1)&1]).
-template <typename QS, bool MF>
+template <typename QS, bool MF, bool YM = false>
 __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it,
                                                   int restart, unsigned mask, int init, int phase, int wsrc) {
@@ -1001,6 +1014,9 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   __shared__ QT ws[NT];
   __shared__ QT ys[NT];
   __shared__ QT mfpart[MF ? (NT / WAVE) * 256 : 1];   // MFMA prolongation: per-wave partial tiles
+  // line ring of the 2-D 9-point march: 4 lines of (segment + 2 halo cells) x R
+  // smoother operands
+  __shared__ QT yring[(YM && MF && sizeof(QT) == 4) ? 4 * YM_SLOT : 1];
   __shared__ double sh[NT + 16];
   // cvec: c_new = A_c^-1 Q^T r_new; gvec: g = A_c^-1 Q^T q; cg: the matvec (or
   // k_residual) group records, summed.  The region serves the final partial
@@ -1303,6 +1319,140 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   }
   const QT om = QT(S.omega);
   double gam = 0.0, rzo = 0.0, rr = 0.0, pq = 0.0;
+  // 2-D 9-point operators, float basis: a march through y with the smoother
+  // operands of three lines in an LDS ring.  The workgroup's chunks are
+  // consecutive lines of one x-segment (chunk_row0), so the rows phase of line
+  // y + 1 runs one chunk ahead of the stencil of line y and leaves each cell's
+  // D^-1 r_new in the ring; only the cells just outside the segment and the
+  // lines before the first and after the last chunk come from the global
+  // vectors.  The gather path reads 27 float64 and 9 float32 values per lane
+  // and chunk through the texture units instead (same values, same sums).
+  bool ym = false;
+  if constexpr (PF2 && YM) {
+    ym = (phase & PH_Z) && wsrc < 0 && S.ylines && cr.c0 < cr.c1 && cr.c0 / S.op.ny == (cr.c1 - 1) / S.op.ny;
+    if (ym) {
+      const int nx = S.op.nx, ny = S.op.ny, crw = S.chunk_rows;
+      const int64_t seg = cr.c0 / ny;
+      const int x0 = (int)(seg * crw);
+      const int xl = t / R;   // this lane's cell of the segment (every chunk is a whole line segment)
+      auto slot = [&](int ly) { return yring + (ly & 3) * YM_SLOT; };
+      auto yglob = [&](int64_t j) { return dj(j) * QT(rnew(j)); };
+      // a line that no lane of this workgroup updates (the one before its
+      // first line, the one after its last)
+      auto line_glob = [&](int ly) {
+        if (ly >= 0 && ly < ny && upd) slot(ly)[(xl + 1) * R + c] = yglob((int64_t)ly * nx + x0 + xl);
+      };
+      // the two cells of a line just outside the segment, lanes t < 2 R
+      auto halo = [&](int ly) {
+        if (ly < 0 || ly >= ny || t >= 2 * R || !upd) return;
+        const int side = t / R, xh = side ? x0 + crw : x0 - 1;
+        if (xh >= 0 && xh < nx) slot(ly)[(side ? crw + 1 : 0) * R + c] = yglob((int64_t)ly * nx + xh);
+      };
+      struct Cur {
+        double ri, zo;
+        QT d;
+      };
+      // the rows of chunk chn from the row vectors in rv: p, q, x, r_new, and
+      // the cell's D^-1 r_new into the ring
+      auto rows_of = [&](int64_t chn, Cur& o) {
+        const int64_t gg = (chunk_row0(S, chn) + xl) * R + c;
+        o.ri = 0.0;
+        o.zo = 0.0;
+        o.d = QT(rv.d);
+        if (!upd) return;
+        o.zo = rv.z;
+        if (full) {
+          const double pi = rs ? o.zo : o.zo + beta * rv.p;
+          const double qi = rs ? rv.w : rv.w + beta * rv.qo;
+          store_partial(&S.p[gg], pi);
+          store_partial(&Qn[gg], qi);
+          store_partial(&S.x[gg], rv.x + alpha * pi);
+          o.ri = rv.r - alpha * qi;
+          pq += pi * qi;
+        } else {
+          o.ri = rv.r;
+        }
+        slot((int)(chn - seg * ny))[(xl + 1) * R + c] = o.d * QT(o.ri);
+      };
+      Cur cur, nxc;
+      {
+        const int ly0 = (int)(cr.c0 - seg * ny);
+        line_glob(ly0 - 1);
+        halo(ly0 - 1);
+        rows_of(cr.c0, cur);
+        halo(ly0);
+        rv = rvn;
+        row_fetch(rvn, min(cr.c0 + 2, last_ch));
+      }
+      for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+        const int ly = (int)(ch - seg * ny);
+        if (ch > cr.c0) {
+          row0 = chunk_row0(S, ch);
+          nrows = crw;
+          mf_fetch(row0, nrows);
+        }
+        if (ch + 1 < cr.c1)
+          rows_of(ch + 1, nxc);
+        else
+          line_glob(ly + 1);
+        halo(ly + 1);
+        __syncthreads();
+        const int64_t g = (row0 + xl) * R + c;
+        QT wjv = QT(0);
+        if (upd) {
+          // the stencil of op_row (dy outer, dx inner, a term outside the
+          // grid dropped by a select), operands from the ring
+          QT ay = QT(0);
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy) {
+            const QT* sl = slot(ly + dy);
+            const bool oky = ly + dy >= 0 && ly + dy < ny;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int xx = x0 + xl + dx;
+              const bool ok = oky && xx >= 0 && xx < nx;
+              const QT vj = sl[(xl + dx + 1) * R + c];
+              ay += ok ? QT(S.op.coef[(dy + 1) * 3 + (dx + 1)]) * vj : QT(0);
+            }
+          }
+          const QT yi = slot(ly)[(xl + 1) * R + c];   // this cell's own operand
+          wjv = QT(2) * om * yi - om * om * cur.d * ay;
+        }
+        __syncthreads();
+        ws[t] = wjv;
+        {
+          typename MfAcc<QT>::type pacc = {QT(0), QT(0), QT(0), QT(0)};
+#pragma unroll
+          for (int blk = 0; blk < 2; ++blk)
+            if (blk < mnbk)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) pacc = mf_mma(q4.get(blk, u), eb[blk][u], pacc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mfpart[mwave * 256 + v * 64 + mlane] = pacc[v];
+          __syncthreads();
+          const int row = t / R, cc = t % R, sl2 = mf_slot<QT>(row % 16, cc);
+          QT sum = QT(0);
+#pragma unroll
+          for (int k2 = 0; k2 < 4; ++k2)
+            if (k2 < mKS) sum += mfpart[(k2 * mRTN + row / 16) * 256 + sl2];
+          ys[t] = sum;
+        }
+        __syncthreads();
+        if (upd) {
+          const double zn = (double)ws[t] + (double)ys[t];
+          if (full) store_partial(&Rout[g], cur.ri);
+          store_partial(&S.z[g], zn);
+          gam += cur.ri * zn;
+          if (S.flexible) rzo += cur.ri * cur.zo;
+          rr += cur.ri * cur.ri;
+        }
+        cur = nxc;
+        rv = rvn;
+        row_fetch(rvn, min(ch + 3, last_ch));
+      }
+    }
+  }
+  if (!ym)
   for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
     if (ch > cr.c0) {
       row0 = chunk_row0(S, ch);
@@ -1753,6 +1903,10 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.maxit = opts->maxit;
   hs.flexible = opts->flexible ? 1 : 0;
   hs.rmask = 0xffffffffu;
+  hs.ylines = (A.kind == NLSP_OP_STENCIL9 && A.nz <= 1 && A.ny > 1 && A.nx % h.chunk_rows == 0 &&
+               M.prec != NLSP_FP64 && mf_ok(R, h.kp) && h.chunk_rows == NT / R)
+                  ? 1
+                  : 0;
   return hs;
 }
 
@@ -1771,10 +1925,15 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   const int R = hs[0].R;
   int nblk = 0;
   bool mf = true;   // MFMA basis passes when every system's (R, kp) has the matrix-core form
+  bool ym = false;  // some system has the update kernel's 2-D line march
   for (const auto& h : hs) {
     nblk += h.nblk;
     mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / h.R;
+    ym = ym || h.ylines;
   }
+  // a separate kernel, so that the others keep its registers
+  constexpr bool YMK = sizeof(QT) == 4;
+  ym = ym && mf && YMK;
   // the matrix-core kernels read the face weights of finite-volume operators
   for (const auto& h : hs)
     if (mf && (h.op.kind == NLSP_OP_FV5 || h.op.kind == NLSP_OP_FV7) && h.op.fw64 == nullptr) return NLSP_E_INVALID;
@@ -1808,7 +1967,10 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     auto upd = [&](int phase, int wsrc, bool timed_one) {
       if (timed_one) {
         timed(1, [&](hipEvent_t a, hipEvent_t b) {
-          if (mf)
+          if (ym)
+            hipExtLaunchKernelGGL((k_update<QS, true, YMK>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it,
+                                  restart, mask, init, phase, wsrc);
+          else if (mf)
             hipExtLaunchKernelGGL((k_update<QS, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it, restart,
                                   mask, init, phase, wsrc);
           else
@@ -1816,7 +1978,10 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
                                   mask, init, phase, wsrc);
         });
       } else {
-        if (mf)
+        if (ym)
+          hipLaunchKernelGGL((k_update<QS, true, YMK>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask,
+                             init, phase, wsrc);
+        else if (mf)
           hipLaunchKernelGGL((k_update<QS, true>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask, init,
                              phase, wsrc);
         else

@@ -817,10 +817,13 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
 // by the epilogue.  Nothing here waits for a scalar: every workgroup streams
 // from its first instruction.  In a batch, a system whose right-hand sides
 // have all stopped exits at once.
-template <typename QS, bool MF>
+template <typename QS, bool MF, bool YM = false>
 __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it) {
   __shared__ double wv[NT];
+  // line ring of the 2-D 9-point march: 4 lines of (segment + 2 halo cells) x R
+  // values of z
+  __shared__ double zring[(YM && MF) ? 4 * YM_SLOT : 1];
   __shared__ double sh[2 * (NT + 16)];
   __shared__ double red[4 * NT + 128];
   __shared__ double buf[2 * MAXR];
@@ -847,6 +850,93 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     const int I = wave % TI, sl = wave / TI, rps = S.chunk_rows / WPT, ksteps = rps / 4;
     typename MfAcc<double>::type acc = {0.0, 0.0, 0.0, 0.0};
     double zw = 0.0, e1 = 0.0;
+    // 2-D 9-point systems marched through y (chunk_row0): z of line y + 1 is
+    // loaded one chunk ahead into an LDS ring and the stencil of line y reads
+    // its 9 operands there (the gather below sums the same terms in the same
+    // order; the two may contract them into FMAs differently); the basis
+    // operands and q, p of the next chunk are loaded ahead too
+    bool ym = false;
+    if constexpr (YM) {
+      ym = S.ylines && cr.c0 < cr.c1 && cr.c0 / S.op.ny == (cr.c1 - 1) / S.op.ny;
+      if (ym) {
+        const int nx = S.op.nx, ny = S.op.ny, crw = S.chunk_rows;
+        const int64_t seg = cr.c0 / ny;
+        const int x0 = (int)(seg * crw);
+        const int xl = t / R;   // this lane's cell of the segment (chunk_rows = NT / R)
+        // lanes t < 2 R also carry the cell just left (t < R) or right of the segment
+        const int hs = t / R, xh = hs ? x0 + crw : x0 - 1;
+        const bool hl = t < 2 * R && xh >= 0 && xh < nx;
+        auto slot = [&](int ly) { return zring + (ly & 3) * YM_SLOT; };
+        double zc = 0.0, zh = 0.0;   // line in flight: this lane's cell and halo cell
+        auto zload = [&](int ly) {
+          if (ly >= 0 && ly < ny) {
+            zc = Z[((int64_t)ly * nx + x0 + xl) * R + c];
+            if (hl) zh = Z[((int64_t)ly * nx + xh) * R + c];
+          }
+        };
+        auto zput = [&](int ly) {
+          if (ly >= 0 && ly < ny) {
+            slot(ly)[(xl + 1) * R + c] = zc;
+            if (hl) slot(ly)[(hs ? crw + 1 : 0) * R + c] = zh;
+          }
+        };
+        QS an[8];
+        double qn = 0.0, pn = 0.0;
+        auto rload = [&](int64_t ch) {
+          const int64_t row0 = chunk_row0(S, ch);
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            an[s] = Qt[(row0 + sl * rps + 4 * min(s, ksteps - 1) + lg) * S.kp + 16 * I + lr];
+          const int64_t g = (row0 + xl) * R + c;
+          qn = Qv[g];
+          pn = Pv[g];
+        };
+        const int ly0 = (int)(cr.c0 - seg * ny);
+        zload(ly0 - 1);
+        zput(ly0 - 1);
+        zload(ly0);
+        zput(ly0);
+        zload(ly0 + 1);
+        rload(cr.c0);
+        if (na == 0) return;   // uniform over the workgroup (one system), before any barrier
+        for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
+          const int ly = (int)(ch - seg * ny);
+          zput(ly + 1);
+          QS a[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) a[s] = an[s];
+          const double qi = qn, pi = pn;
+          if (ch + 1 < cr.c1) {
+            zload(ly + 2);
+            rload(ch + 1);
+          }
+          __syncthreads();
+          double wval = 0.0;
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy) {
+            const double* sv = slot(ly + dy);
+            const bool oky = ly + dy >= 0 && ly + dy < ny;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int xx = x0 + xl + dx;
+              const bool ok = oky && xx >= 0 && xx < nx;
+              const double vj = sv[(xl + dx + 1) * R + c];
+              wval += ok ? S.op.coef[(dy + 1) * 3 + (dx + 1)] * vj : 0.0;
+            }
+          }
+          const double zi = slot(ly)[(xl + 1) * R + c];
+          store_partial(&S.w[(chunk_row0(S, ch) + xl) * R + c], wval);
+          zw += zi * wval;
+          e1 += zi * qi + pi * wval;
+          wv[t] = wval;
+          __syncthreads();
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            if (s < ksteps) acc = mf_mma((double)a[s], lr < R ? wv[(sl * rps + 4 * s + lg) * R + lr] : 0.0, acc);
+        }
+      }
+    }
+    if (!ym)
     for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
       const int64_t row0 = chunk_row0(S, ch);
       const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
@@ -1326,7 +1416,8 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   // D^-1 r_new in the ring; only the cells just outside the segment and the
   // lines before the first and after the last chunk come from the global
   // vectors.  The gather path reads 27 float64 and 9 float32 values per lane
-  // and chunk through the texture units instead (same values, same sums).
+  // and chunk through the texture units instead (the same terms in the same
+  // order; the two may contract them into FMAs differently).
   bool ym = false;
   if constexpr (PF2 && YM) {
     ym = (phase & PH_Z) && wsrc < 0 && S.ylines && cr.c0 < cr.c1 && cr.c0 / S.op.ny == (cr.c1 - 1) / S.op.ny;
@@ -2010,13 +2101,17 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   auto launch_matvec = [&](hipStream_t st, int it, bool can_time) {
     if (can_time) {
       timed(2, [&](hipEvent_t a, hipEvent_t b) {
-        if (mf)
+        if (ym)
+          hipExtLaunchKernelGGL((k_matvec<QS, true, YMK>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+        else if (mf)
           hipExtLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
         else
           hipExtLaunchKernelGGL((k_matvec<QS, false>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
       });
     } else {
-      if (mf)
+      if (ym)
+        hipLaunchKernelGGL((k_matvec<QS, true, YMK>), grid, block, 0, st, dsys, b2s, nsys, it);
+      else if (mf)
         hipLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, dsys, b2s, nsys, it);
       else
         hipLaunchKernelGGL((k_matvec<QS, false>), grid, block, 0, st, dsys, b2s, nsys, it);

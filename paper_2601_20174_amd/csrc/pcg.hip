@@ -109,7 +109,7 @@ struct SysDev {
   double omega, tol2;
   int maxit, flexible, nu;
   unsigned rmask;          // RHS a restart launch applies to (ANDed with the launch mask)
-  int ylines;              // 2-D line march of the float matrix-core update (chunks ordered y fastest)
+  int ylines;              // 2-D line march of the matrix-core kernels (chunks ordered y fastest)
 };
 
 // XCD-aware order: hardware places workgroup b on XCD b % 8; give each XCD a
@@ -559,9 +559,9 @@ NLSP_DEV int64_t chunk_row0(const SysDev& S, int64_t ch) {
     return ((int64_t)z * S.op.ny + y) * S.op.nx + (int64_t)xq * cr;
   }
   if (S.ylines) {
-    // 2-D 9-point operators with the float matrix-core update march through y
-    // the same way (logical chunk ch is line ch % ny of the x-segment ch /
-    // ny), which that kernel's line ring relies on
+    // 2-D 9-point operators with the matrix-core kernels march through y the
+    // same way (logical chunk ch is line ch % ny of the x-segment ch / ny),
+    // which their line rings rely on
     const int ny = S.op.ny;
     const int64_t xq = ch / ny;
     const int y = (int)(ch - xq * ny);
@@ -1995,7 +1995,7 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.flexible = opts->flexible ? 1 : 0;
   hs.rmask = 0xffffffffu;
   hs.ylines = (A.kind == NLSP_OP_STENCIL9 && A.nz <= 1 && A.ny > 1 && A.nx % h.chunk_rows == 0 &&
-               M.prec != NLSP_FP64 && mf_ok(R, h.kp) && h.chunk_rows == NT / R)
+               mf_ok(R, h.kp) && h.chunk_rows == NT / R)
                   ? 1
                   : 0;
   return hs;
@@ -2016,15 +2016,16 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   const int R = hs[0].R;
   int nblk = 0;
   bool mf = true;   // MFMA basis passes when every system's (R, kp) has the matrix-core form
-  bool ym = false;  // some system has the update kernel's 2-D line march
+  bool ym = false;  // some system has the 2-D line march
   for (const auto& h : hs) {
     nblk += h.nblk;
     mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / h.R;
     ym = ym || h.ylines;
   }
-  // a separate kernel, so that the others keep its registers
+  // the marching kernels are separate instantiations, so that the others
+  // keep their registers; the float64 update kernel has none left for a ring
   constexpr bool YMK = sizeof(QT) == 4;
-  ym = ym && mf && YMK;
+  ym = ym && mf;
   // the matrix-core kernels read the face weights of finite-volume operators
   for (const auto& h : hs)
     if (mf && (h.op.kind == NLSP_OP_FV5 || h.op.kind == NLSP_OP_FV7) && h.op.fw64 == nullptr) return NLSP_E_INVALID;
@@ -2058,7 +2059,7 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     auto upd = [&](int phase, int wsrc, bool timed_one) {
       if (timed_one) {
         timed(1, [&](hipEvent_t a, hipEvent_t b) {
-          if (ym)
+          if (ym && YMK)
             hipExtLaunchKernelGGL((k_update<QS, true, YMK>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it,
                                   restart, mask, init, phase, wsrc);
           else if (mf)
@@ -2069,7 +2070,7 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
                                   mask, init, phase, wsrc);
         });
       } else {
-        if (ym)
+        if (ym && YMK)
           hipLaunchKernelGGL((k_update<QS, true, YMK>), grid, block, 0, st, dsys, b2s, nsys, it, restart, mask,
                              init, phase, wsrc);
         else if (mf)
@@ -2102,7 +2103,7 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     if (can_time) {
       timed(2, [&](hipEvent_t a, hipEvent_t b) {
         if (ym)
-          hipExtLaunchKernelGGL((k_matvec<QS, true, YMK>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+          hipExtLaunchKernelGGL((k_matvec<QS, true, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
         else if (mf)
           hipExtLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
         else
@@ -2110,7 +2111,7 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
       });
     } else {
       if (ym)
-        hipLaunchKernelGGL((k_matvec<QS, true, YMK>), grid, block, 0, st, dsys, b2s, nsys, it);
+        hipLaunchKernelGGL((k_matvec<QS, true, true>), grid, block, 0, st, dsys, b2s, nsys, it);
       else if (mf)
         hipLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, dsys, b2s, nsys, it);
       else

@@ -48,6 +48,9 @@ def _args():
     ap.add_argument("--fem-leg", action="store_true", help="run only the P1 finite-element leg")
     ap.add_argument("--batched-leg", action="store_true",
                     help="run only the batched anisotropic leg (for profiling it on its own)")
+    ap.add_argument("--batched-iters", type=int, default=0, metavar="K",
+                    help="only set up the batched anisotropic workload and run K iterations of its mixed "
+                         "solve with every system active (1024 rows per workgroup), for kernel counters")
     ap.add_argument("--solve3d-leg", action="store_true",
                     help="only run the 3-D setup + solve leg (mixed and float64) and exit")
     ap.add_argument("--predictor-leg", action="store_true",
@@ -111,6 +114,9 @@ def main():
     if a.predictor_leg:
         print(json.dumps({"training": training_legs(nl, torch, dev), "predictor": predictor_leg(nl, torch, dev)}),
               flush=True)
+        return
+    if a.batched_iters:
+        print(json.dumps({"batched_iters": batched_iters(nl, torch, dev, a.batched_iters)}), flush=True)
         return
     if a.batched_leg:
         print(json.dumps({"batched": batched_legs(nl, torch, dev)}), flush=True)
@@ -461,6 +467,32 @@ def training_legs(nl, torch, dev):
                             "fwd_GBs": round(fwd_bytes / f_ms / 1e6, 1), "bwd_GBs": round(bwd_bytes / b_ms / 1e6, 1),
                             "bad": int(bad.sum().item())}
     return res
+
+
+def batched_iters(nl, torch, dev, iters):
+    """The batched anisotropic workload (see batched_legs), `iters` iterations
+    of its mixed solve at 1024 rows per workgroup: every system is still
+    active, so each solver launch moves the algorithmic bytes returned here."""
+    import workloads as W
+    c3 = W.Cfg3()
+    side, eps, theta = c3.systems()
+    st = nl.q1_aniso_stencil(torch.tensor(np.stack([eps, theta], 1), dtype=torch.float64, device=dev))
+    ops, S0s, fs = [], [], []
+    for i in range(len(side)):
+        n = int(side[i]) ** 2
+        ops.append(nl.Operator(nl.OP_STENCIL9, int(side[i]), int(side[i]), 1, st[i].contiguous()))
+        S0s.append(torch.tensor(c3.S0(i, n), dtype=torch.float64, device=dev))
+        fs.append(torch.tensor(c3.rhs(i, n), dtype=torch.float64, device=dev))
+    Ms = nl.setup_many(ops, S0s, c3.k, c3.omega, c3.s1, c3.nu, nl.FP64, workers=4)
+    systems = [nl.System(op, M, f, torch.zeros_like(f)) for op, M, f in zip(ops, Ms, fs)]
+    infos, rc = nl.pcg_solve_batched(systems, prec=nl.MIXED, rtol=c3.rtol, maxit=iters, rows_per_block=1024)
+    torch.cuda.synchronize()
+    rows = sum(int(s) ** 2 for s in side)
+    kp = nl.nlsp_padded_rank(c3.k)
+    return {"systems": len(side), "rows": rows, "R": c3.R, "kp": kp, "iters": iters,
+            "min_iters_run": min(inf.iters for si in infos for inf in si),
+            "update_bytes": rows * solver_bytes_per_row(1, kp, c3.R, cbytes=0),
+            "matvec_bytes": rows * solver_bytes_per_row(2, kp, c3.R, cbytes=0)}
 
 
 def batched_legs(nl, torch, dev, nsys=None):

@@ -1473,7 +1473,9 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         rows_of(cr.c0, cur);
         halo(ly0);
         rv = rvn;
-        row_fetch(rvn, min(cr.c0 + 2, last_ch));
+        // a chunk past the run is never used: its loads go to chunk 0, whose
+        // lines every finishing workgroup reads and so stay in the L2
+        row_fetch(rvn, cr.c0 + 2 < cr.c1 ? cr.c0 + 2 : 0);
       }
       for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
         const int ly = (int)(ch - seg * ny);
@@ -1539,7 +1541,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         }
         cur = nxc;
         rv = rvn;
-        row_fetch(rvn, min(ch + 3, last_ch));
+        row_fetch(rvn, ch + 3 < cr.c1 ? ch + 3 : 0);
       }
     }
   }

@@ -224,7 +224,7 @@ size_t galerkin_coarse_workspace_bytes(const nlsp_operator* A, int k);
 
 /* Galerkin coarse operator and the solver's coarse-space factors (algorithm
  * setup; appendix, two-level subspace correction):
- *   A_c  = P^T A P (exactly symmetrised), A_c = L L^T (Cholesky)
+ *   A_c  = P^T A P (exactly symmetric: its upper triangle, mirrored), A_c = L L^T (Cholesky)
  *   Linv = L^{-1}, zero-padded to (kp, kp), kp = nlsp_padded_rank(k)
  *   Q    = (I - w D^-1 A)^nu P, zero-padded to (n, kp)
  * With these the two-grid preconditioner of the algorithm (nu pre- and nu

@@ -254,7 +254,7 @@ struct GsVec {
 // modulo the 256-byte bank row
 __host__ __device__ inline int gs_stride(int a) { return a + ((a * 8) % 256 == 0 ? 16 : 0); }
 inline size_t gs_lds_bytes(int a, int b, int sym) {
-  return sizeof(double) * GS_ROWS * (gs_stride(a) + (sym ? 0 : gs_stride(b)));
+  return sizeof(double) * GS_ROWS * (gs_stride(a) + (sym == 1 ? 0 : gs_stride(b)));
 }
 
 template <typename T, int MAXT>
@@ -265,7 +265,10 @@ __global__ __launch_bounds__(1024) void k_gram_partial(const T* __restrict__ X,
   extern __shared__ double gsh[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int TA = a / 16, TB = b / 16;
-  const int ntiles = sym ? TA * (TA + 1) / 2 : TA * TB;
+  // sym 1: X^T X (Y = X, loaded once); sym 2: X^T Y whose result is known to
+  // be symmetric; both compute the upper triangle of tiles only
+  const bool tri = sym != 0, one = sym == 1;
+  const int ntiles = tri ? TA * (TA + 1) / 2 : TA * TB;
   // tiles in a fixed order (row-major; upper triangle with sym), dealt
   // round-robin: slot q of this wave holds tile wave + q * nwave.  Decoded per
   // slot with a compile-time slot index, so the list stays in registers.
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_gram_partial(const T* __restrict__ X,
   for (int q = 0; q < MAXT; ++q) {
     const int cnt = min(wave + q * nwave, ntiles - 1);
     int I, J;
-    if (sym) {
+    if (tri) {
       int rem = cnt, row = 0;
       while (rem >= TA - row) { rem -= TA - row; ++row; }
       I = row;
@@ -297,10 +300,10 @@ __global__ __launch_bounds__(1024) void k_gram_partial(const T* __restrict__ X,
   // touches fall on alternating bank halves.
   using V = typename GsVec<T>::V;
   constexpr int VE = GsVec<T>::VE;
-  const int sa = gs_stride(a), sb = sym ? 0 : gs_stride(b);
+  const int sa = gs_stride(a), sb = one ? 0 : gs_stride(b);
   double* Xs = gsh;
-  double* Ys = sym ? gsh : gsh + GS_ROWS * sa;
-  const int nva = GS_ROWS * a / VE, nvb = sym ? 0 : GS_ROWS * b / VE;   // vectors per slab
+  double* Ys = one ? gsh : gsh + GS_ROWS * sa;
+  const int nva = GS_ROWS * a / VE, nvb = one ? 0 : GS_ROWS * b / VE;   // vectors per slab
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min(n, r0 + rows_per_wg);
   V reg[GS_MAXV];
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(1024) void k_gram_partial(const T* __restrict__ X,
     }
   };
   const int kr = lane >> 4, kc = lane & 15;
-  const int ldy = sym ? sa : sb;
+  const int ldy = one ? sa : sb;
   if (r0 < r1) {
     fetch(r0);
     stage();
@@ -404,8 +407,12 @@ __global__ __launch_bounds__(GR_NT) void k_gram_reduce(const double* __restrict_
   const double sum = ((sl[lane] + sl[64 + lane]) + sl[128 + lane]) + sl[192 + lane];
   const int i = e / b, j = e % b;
   if (sym && (i / 16) > (j / 16)) return;   // lower tiles are not stored
+  // sym = 2: a diagonal tile is not symmetric in rounding; its upper half is
+  // mirrored too
+  const bool dmirror = sym == 2 && (i / 16) == (j / 16);
+  if (dmirror && i > j) return;
   out[(int64_t)i * lda_out + j] = sum;
-  if (sym && (i / 16) < (j / 16)) out[(int64_t)j * lda_out + i] = sum;
+  if (sym && ((i / 16) < (j / 16) || (dmirror && i < j))) out[(int64_t)j * lda_out + i] = sum;
 }
 
 // ------------------------------------------------- small dense, one WG
@@ -988,14 +995,28 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const double* __restrict
   const int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = min(n, r0 + rows_per);
   double best = -1.0;
   int64_t bidx = r0;
-  if (r < per)
-    for (int64_t i = r0 + r; i < r1; i += per) {
+  if (r < per) {
+    // rows in increasing order, eight loads issued before the first compare
+    int64_t i = r0 + r;
+    for (; i + 7 * per < r1; i += 8 * per) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = fabs(P[(i + u * per) * ld + c]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (v[u] > best) {
+          best = v[u];
+          bidx = i + u * per;
+        }
+    }
+    for (; i < r1; i += per) {
       const double v = fabs(P[i * ld + c]);
       if (v > best) {
         best = v;
         bidx = i;
       }
     }
+  }
   bv[t] = best;
   bi[t] = bidx;
   __syncthreads();
@@ -1025,7 +1046,24 @@ __global__ __launch_bounds__(256) void k_colsign_finish(const double* __restrict
   if (c >= k) return;
   double b = -1.0;
   int64_t bx = 0;
-  for (int w = 0; w < nblk; ++w) {
+  // partials in workgroup order, sixteen loaded before the first compare
+  int w = 0;
+  for (; w + 16 <= nblk; w += 16) {
+    double v[16];
+    int64_t x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      v[u] = pv[(int64_t)(w + u) * ld + c];
+      x[u] = pi[(int64_t)(w + u) * ld + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (v[u] > b || (v[u] == b && x[u] < bx)) {
+        b = v[u];
+        bx = x[u];
+      }
+  }
+  for (; w < nblk; ++w) {
     const double v = pv[(int64_t)w * ld + c];
     const int64_t x = pi[(int64_t)w * ld + c];
     if (v > b || (v == b && x < bx)) {
@@ -1063,16 +1101,6 @@ __global__ void k_pad_square(const double* __restrict__ A, int lda, int k, doubl
   if (idx >= kout * kout) return;
   const int i = idx / kout, j = idx % kout;
   B[i * ldb + j] = (i < k && j < k) ? A[i * lda + j] : 0.0;
-}
-
-__global__ void k_symmetrize(double* __restrict__ A, int k, int ld) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= k * k) return;
-  const int i = idx / k, j = idx % k;
-  if (j <= i) return;
-  const double v = 0.5 * (A[i * ld + j] + A[j * ld + i]);
-  A[i * ld + j] = v;
-  A[j * ld + i] = v;
 }
 
 __global__ void k_to_f32(const double* __restrict__ A, float* __restrict__ B, int64_t cnt) {
@@ -1178,15 +1206,18 @@ inline GramPlan gram_plan(int64_t n) {
 }
 
 // X^T Y (a x b, a, b multiples of 16) into out (leading dim ldo).  `part`
-// holds nwg*a*b doubles.
+// holds nwg*a*b doubles.  sym = 1: Y = X; sym = 2: a product known to be
+// symmetric (X^T A X as P^T (A P)); both form the upper triangle of 16 x 16
+// tiles and mirror it.
 template <typename T>
 static int gram(const T* X, const T* Y, int64_t n, int a, int b, int sym, double* part,
                 double* out, int ldo, hipStream_t s) {
   const GramPlan g = gram_plan(n);
   const int TA = a / 16, TB = b / 16;
+  if (sym == 2 && a != b) return NLSP_E_INVALID;
   const int ntiles = sym ? TA * (TA + 1) / 2 : TA * TB;
   // up to 16 waves, tiles dealt round-robin: 3 slots per wave up to 48 tiles, 9 up to 144
-  const int vecs = GS_ROWS * (a + (sym ? 0 : b)) / GsVec<T>::VE;
+  const int vecs = GS_ROWS * (a + (sym == 1 ? 0 : b)) / GsVec<T>::VE;
   const int waves = std::min(16, std::max({1, ntiles, (vecs + 64 * GS_MAXV - 1) / (64 * GS_MAXV)}));
   const int per_wave = (ntiles + waves - 1) / waves;
   if (per_wave > 9) return NLSP_E_INVALID;
@@ -1585,12 +1616,17 @@ int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega
   const OpDev op = make_op(*A);
   hipStream_t s = as_stream(stream);
   NLSP_HIP(hipMemsetAsync(L.info, 0, sizeof(int) * 4, s));
-  // padded P, Y = A P, A_c = P^T Y
-  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(n * kp, 256)), dim3(256), 0, s, P, k, n, k, L.Pp, kp);
-  launch_cols<double>(op, kp, omega, 1, L.Pp, L.Y, s);
-  int rc = gram<double>(L.Pp, L.Y, n, kp, kp, 0, L.part, L.Acp, kp, s);
+  // padded P (P itself when k is a multiple of 16 and P is 16-byte aligned:
+  // it is only read), Y = A P, A_c = P^T Y (symmetric: the upper tiles,
+  // mirrored)
+  const double* Pp = P;
+  if (kp != k || reinterpret_cast<uintptr_t>(P) % 16 != 0) {
+    hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(n * kp, 256)), dim3(256), 0, s, P, k, n, k, L.Pp, kp);
+    Pp = L.Pp;
+  }
+  launch_cols<double>(op, kp, omega, 1, Pp, L.Y, s);
+  int rc = gram<double>(Pp, L.Y, n, kp, kp, 2, L.part, L.Acp, kp, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_symmetrize, dim3(ceil_div(kp * kp, 256)), dim3(256), 0, s, L.Acp, kp, kp);
   hipLaunchKernelGGL(k_pad_square, dim3(ceil_div(k * k, 256)), dim3(256), 0, s, L.Acp, kp, k, Ac, k, k);
   rc = launch_chol(L.Acp, kp, k, L.Lp, kp, L.info, s);
   if (rc) return rc;
@@ -1600,7 +1636,7 @@ int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega
     if (rc2) return rc2;
   }
   // Q = (I - w D^-1 A)^nu P
-  double* cur = L.Pp;
+  const double* cur = Pp;
   double* bufs[2] = {L.Y, L.Z};
   for (int it = 0; it < nu; ++it) {
     double* dst = bufs[it & 1];

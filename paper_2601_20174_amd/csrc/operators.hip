@@ -165,6 +165,23 @@ NLSP_DEV void vload(const T* p, T (&v)[VW]) {
   for (int u = 0; u < VW; ++u) v[u] = e[u];
 }
 
+// VW values of type TI at p, as T (float64 rows read into float32: two
+// 16-byte loads, each value rounded once)
+template <typename TI, typename T, int VW>
+NLSP_DEV void vload_as(const TI* p, T (&v)[VW]) {
+  if constexpr (std::is_same<TI, T>::value) {
+    vload<T, VW>(p, v);
+  } else {
+    static_assert(std::is_same<TI, double>::value && std::is_same<T, float>::value && VW == 4, "row types");
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = T(a.x);
+    v[1] = T(a.y);
+    v[2] = T(b.x);
+    v[3] = T(b.y);
+  }
+}
+
 template <typename T, int VW>
 NLSP_DEV void vstore(T* p, const T (&v)[VW]) {
   using V = typename VecOf<T, VW>::type;
@@ -280,14 +297,16 @@ NLSP_DEV P* at_b(P* base, uint32_t off) {
 //   MODE 0: y = A x;  MODE 1: y = x + omega D^-1 (b - A x)  (as k_rows);
 //   MODE 2: y = x - (omega / a_ii) (A x)  (the setup's relaxation, b = 0, in
 //   the form of the multi-column setup pass)
-// Storage T, arithmetic AT (the setup relaxes float32 vectors with float64
-// coefficients and sums).  The R = LPR VW values of a row are columns
+// Storage T, arithmetic AT.  The R = LPR VW values of a row are columns
 // blockIdx.y R .. of rows with stride ld (ld = R for the right-hand-side
 // blocks of the operator entry points; wider for the setup's column blocks).
-template <typename T, int MODE, int VW, int LPR, int TX, int TY, typename AT = T, bool SLAB = false>
+// x may be stored as TI (float64 rows relaxed as float32 rows: the setup's
+// first sweep reads its float64 input directly).
+template <typename T, int MODE, int VW, int LPR, int TX, int TY, typename AT = T, bool SLAB = false,
+          typename TI = T>
 __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty, int zc, int ld_slab, AT omega,
                                                                    const T* __restrict__ b,
-                                                                   const T* __restrict__ x, T* __restrict__ y) {
+                                                                   const TI* __restrict__ x, T* __restrict__ y) {
   using Z = ZTile<LPR, TX, TY>;
   static_assert(Z::NT == 64 * LPR, "launch bound");
   static_assert(!(SLAB && MODE == 1), "column slabs carry no right-hand side");
@@ -360,16 +379,19 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
   T pl[4][IPT][VW], hb[2][HI][VW], bq[2][IPT][VW];
   AT ac[2][IPT], af[2][IPT][FF];
   const int64_t pstride = (int64_t)sxy * ld;
-  auto plane = [&](const T* base, int z) { return base + (int64_t)min(max(z, 0), nz - 1) * pstride; };
-  auto ld_plane = [&](T (&v)[IPT][VW], const T* base, int z) {
-    const T* p = plane(base, z);
+  auto plane = [&](auto base, int z) { return base + (int64_t)min(max(z, 0), nz - 1) * pstride; };
+  // byte offsets are formed for T; an input of a wider type scales them
+  auto ld_plane = [&](T (&v)[IPT][VW], auto base, int z) {
+    const auto p = plane(base, z);
+    constexpr uint32_t XS = sizeof(*p) / sizeof(T);
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) vload<T, VW>(at_b(p, vo[u]), v[u]);
+    for (int u = 0; u < IPT; ++u) vload_as(at_b(p, vo[u] * XS), v[u]);
   };
   auto ld_halo = [&](T (&v)[HI][VW], int z) {
-    const T* p = plane(x, z);
+    const TI* p = plane(x, z);
+    constexpr uint32_t XS = sizeof(TI) / sizeof(T);
 #pragma unroll
-    for (int q = 0; q < HI; ++q) vload<T, VW>(at_b(p, ho[q]), v[q]);
+    for (int q = 0; q < HI; ++q) vload_as(at_b(p, ho[q] * XS), v[q]);
   };
   auto ld_coef = [&](AT (&ap)[IPT], AT (&fp)[IPT][FF], int z) {
     const int zz = min(z, nz - 1), zlo = max(zz - 1, 0);
@@ -484,8 +506,8 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
 // R = 16 with non-temporal stores: 32 planes against 16 (float64 apply
 // 0.1155 -> 0.1143 ms, float32 sweep 0.0746 -> 0.0722 ms) and 64 (0.132 /
 // 0.083 ms: too few blocks); a 16 x 16 tile measured slower for float64.
-template <typename T, int MODE, int VW, int LPR, typename AT = T, bool SLAB = false>
-inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const T* x, T* y, hipStream_t s, int ld = LPR * VW,
+template <typename T, int MODE, int VW, int LPR, typename AT = T, bool SLAB = false, typename TI = T>
+inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const TI* x, T* y, hipStream_t s, int ld = LPR * VW,
                           int nslab = 1) {
   constexpr int TX = 16, TY = 8;
   using Z = ZTile<LPR, TX, TY>;
@@ -493,8 +515,8 @@ inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const T* x, T* 
   int zc = Z::NT >= 256 ? 32 : 16;
   while (zc > 4 && (int64_t)ntx * nty * ((op.nz + zc - 1) / zc) * nslab < 512) zc /= 2;
   const unsigned nb = (unsigned)((int64_t)ntx * nty * ((op.nz + zc - 1) / zc));
-  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY, AT, SLAB>), dim3(nb, nslab), dim3(Z::NT), 0, s, op, ntx, nty,
-                     zc, ld, omega, b, x, y);
+  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY, AT, SLAB, TI>), dim3(nb, nslab), dim3(Z::NT), 0, s, op,
+                     ntx, nty, zc, ld, omega, b, x, y);
 }
 
 // the z-march applies to 3-D FV7 operators with 2, 4 or 8 lanes of 16-byte
@@ -539,6 +561,19 @@ bool zmarch_cols(const OpDev& op, int mode, double omega, int ld, const T* in, T
 }
 template bool zmarch_cols<float>(const OpDev&, int, double, int, const float*, float*, hipStream_t);
 template bool zmarch_cols<double>(const OpDev&, int, double, int, const double*, double*, hipStream_t);
+
+// The float32 relaxation sweep (mode 0 above) reading float64 rows: the
+// setup's first sweep takes the float64 S0 directly, each value rounded to
+// float32 as it is loaded (the same values as a rounded copy, one pass less).
+bool zmarch_cols_relax_f64in(const OpDev& op, double omega, int ld, const double* in, float* out, hipStream_t s) {
+  constexpr int VW = 4, LPR = 8, W = VW * LPR;
+  if (op.kind != NLSP_OP_FV7 || op.nz < 2 || ld % W != 0) return false;
+  const int64_t sxy = (int64_t)op.nx * op.ny;
+  if (sxy * ld * (int64_t)sizeof(double) >= (int64_t(1) << 32) || 3 * sxy * 8 >= (int64_t(1) << 32)) return false;
+  if (reinterpret_cast<uintptr_t>(in) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 16 != 0) return false;
+  launch_zmarch<float, 2, VW, LPR, float, true, double>(op, float(omega), nullptr, in, out, s, ld, ld / W);
+  return true;
+}
 
 // rows per block: 2048 (row, rhs) pairs, at most TRMAX rows
 inline int rows_per_block(int R) { return R >= 4 ? std::max(16, std::min(TRMAX, 2048 / R)) : TRMAX; }

@@ -197,6 +197,8 @@ __global__ __launch_bounds__(256) void k_csr_cols(OpDev op, int m, double omega,
 // source): false when the shape does not fit it.
 template <typename T>
 bool zmarch_cols(const OpDev& op, int mode, double omega, int ld, const T* in, T* out, hipStream_t s);
+// its float32 relaxation sweep reading float64 rows
+bool zmarch_cols_relax_f64in(const OpDev& op, double omega, int ld, const double* in, float* out, hipStream_t s);
 
 // the multi-column pass over (n, mp) blocks: the column-slab z-march on 3-D
 // FV7 grids (each row read from HBM once, where k_cols re-reads the z
@@ -1373,8 +1375,20 @@ static int setup_impl(const OpDev& op, const double* S0, int m, int k, double om
   const int mp = pad16(m) + (pad16(m) % 2), kq = pad16(k);
   T* Sa = static_cast<T*>(L.S0buf);
   T* Sb = static_cast<T*>(L.S1buf);
-  hipLaunchKernelGGL(k_load_S0<T>, dim3(ceil_div(n * mp, 256)), dim3(256), 0, s, S0, n, m, mp, Sa);
-  for (int it = 0; it < s1; ++it) {
+  // the first sweep reads S0 itself when it needs no padding (float64; the
+  // float32 z-march rounds each value as it loads it), else a padded copy
+  int it0 = 0;
+  if (s1 > 0 && m == mp && reinterpret_cast<uintptr_t>(S0) % 16 == 0) {
+    if constexpr (std::is_same<T, double>::value) {
+      launch_cols<double>(op, mp, omega, 0, S0, Sb, s);
+      it0 = 1;
+    } else {
+      if (zmarch_cols_relax_f64in(op, omega, mp, S0, Sb, s)) it0 = 1;
+    }
+    if (it0) std::swap(Sa, Sb);
+  }
+  if (it0 == 0) hipLaunchKernelGGL(k_load_S0<T>, dim3(ceil_div(n * mp, 256)), dim3(256), 0, s, S0, n, m, mp, Sa);
+  for (int it = it0; it < s1; ++it) {
     launch_cols<T>(op, mp, omega, 0, Sa, Sb, s);
     std::swap(Sa, Sb);
   }

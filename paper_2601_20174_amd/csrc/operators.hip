@@ -301,12 +301,13 @@ NLSP_DEV P* at_b(P* base, uint32_t off) {
 // blockIdx.y R .. of rows with stride ld (ld = R for the right-hand-side
 // blocks of the operator entry points; wider for the setup's column blocks).
 // x may be stored as TI (float64 rows relaxed as float32 rows: the setup's
-// first sweep reads its float64 input directly).
+// first sweep reads its float64 input directly), y as TO (float64 sums stored
+// as float32: the float32 copy of the smoothed basis formed in the pass).
 template <typename T, int MODE, int VW, int LPR, int TX, int TY, typename AT = T, bool SLAB = false,
-          typename TI = T>
+          typename TI = T, typename TO = T>
 __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty, int zc, int ld_slab, AT omega,
                                                                    const T* __restrict__ b,
-                                                                   const TI* __restrict__ x, T* __restrict__ y) {
+                                                                   const TI* __restrict__ x, TO* __restrict__ y) {
   using Z = ZTile<LPR, TX, TY>;
   static_assert(Z::NT == 64 * LPR, "launch bound");
   static_assert(!(SLAB && MODE == 1), "column slabs carry no right-hand side");
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
         for (int e = 0; e < VW; ++e) buf[hl[q] + e] = hb[H0][q][e];
       }
     lds_barrier();
-    T* const yp = y + (int64_t)z * pstride;
+    TO* const yp = y + (int64_t)z * pstride;
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const bool in[6] = {inxy[u][0], inxy[u][1], inxy[u][2], inxy[u][3], z > 0, z < nz - 1};
@@ -477,11 +478,13 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
       // displace the planes and halos that neighbouring tiles still read from
       // L2 (FV7 128^3, R = 16: float32 sweep 0.079 -> 0.075 ms)
       if (ok[u]) {
-        typedef T EV __attribute__((ext_vector_type(VW)));
+        typedef TO EV __attribute__((ext_vector_type(VW)));
         EV ev;
 #pragma unroll
-        for (int e = 0; e < VW; ++e) ev[e] = out[e];
-        __builtin_nontemporal_store(ev, reinterpret_cast<EV*>(at_b(yp, vo[u])));
+        for (int e = 0; e < VW; ++e) ev[e] = TO(out[e]);
+        // byte offsets are formed for T; an output of another width scales them
+        const uint32_t yo = (uint32_t)(((uint64_t)vo[u] * sizeof(TO)) / sizeof(T));
+        __builtin_nontemporal_store(ev, reinterpret_cast<EV*>(at_b(yp, yo)));
       }
     }
   };
@@ -506,8 +509,9 @@ __global__ __launch_bounds__(64 * LPR) void k_zmarch(OpDev op, int ntx, int nty,
 // R = 16 with non-temporal stores: 32 planes against 16 (float64 apply
 // 0.1155 -> 0.1143 ms, float32 sweep 0.0746 -> 0.0722 ms) and 64 (0.132 /
 // 0.083 ms: too few blocks); a 16 x 16 tile measured slower for float64.
-template <typename T, int MODE, int VW, int LPR, typename AT = T, bool SLAB = false, typename TI = T>
-inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const TI* x, T* y, hipStream_t s, int ld = LPR * VW,
+template <typename T, int MODE, int VW, int LPR, typename AT = T, bool SLAB = false, typename TI = T,
+          typename TO = T>
+inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const TI* x, TO* y, hipStream_t s, int ld = LPR * VW,
                           int nslab = 1) {
   constexpr int TX = 16, TY = 8;
   using Z = ZTile<LPR, TX, TY>;
@@ -515,8 +519,8 @@ inline void launch_zmarch(const OpDev& op, AT omega, const T* b, const TI* x, T*
   int zc = Z::NT >= 256 ? 32 : 16;
   while (zc > 4 && (int64_t)ntx * nty * ((op.nz + zc - 1) / zc) * nslab < 512) zc /= 2;
   const unsigned nb = (unsigned)((int64_t)ntx * nty * ((op.nz + zc - 1) / zc));
-  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY, AT, SLAB, TI>), dim3(nb, nslab), dim3(Z::NT), 0, s, op,
-                     ntx, nty, zc, ld, omega, b, x, y);
+  hipLaunchKernelGGL((k_zmarch<T, MODE, VW, LPR, TX, TY, AT, SLAB, TI, TO>), dim3(nb, nslab), dim3(Z::NT), 0, s,
+                     op, ntx, nty, zc, ld, omega, b, x, y);
 }
 
 // the z-march applies to 3-D FV7 operators with 2, 4 or 8 lanes of 16-byte
@@ -572,6 +576,18 @@ bool zmarch_cols_relax_f64in(const OpDev& op, double omega, int ld, const double
   if (sxy * ld * (int64_t)sizeof(double) >= (int64_t(1) << 32) || 3 * sxy * 8 >= (int64_t(1) << 32)) return false;
   if (reinterpret_cast<uintptr_t>(in) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 16 != 0) return false;
   launch_zmarch<float, 2, VW, LPR, float, true, double>(op, float(omega), nullptr, in, out, s, ld, ld / W);
+  return true;
+}
+
+// The float64 relaxation sweep (mode 0 above) storing its result as float32
+// (the rounded values, as a float64 pass and a rounding copy would give).
+bool zmarch_cols_relax_f32out(const OpDev& op, double omega, int ld, const double* in, float* out, hipStream_t s) {
+  constexpr int VW = 2, LPR = 8, W = VW * LPR;
+  if (op.kind != NLSP_OP_FV7 || op.nz < 2 || ld % W != 0) return false;
+  const int64_t sxy = (int64_t)op.nx * op.ny;
+  if (sxy * ld * (int64_t)sizeof(double) >= (int64_t(1) << 32) || 3 * sxy * 8 >= (int64_t(1) << 32)) return false;
+  if (reinterpret_cast<uintptr_t>(in) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 8 != 0) return false;
+  launch_zmarch<double, 2, VW, LPR, double, true, double, float>(op, omega, nullptr, in, out, s, ld, ld / W);
   return true;
 }
 

@@ -197,8 +197,10 @@ __global__ __launch_bounds__(256) void k_csr_cols(OpDev op, int m, double omega,
 // source): false when the shape does not fit it.
 template <typename T>
 bool zmarch_cols(const OpDev& op, int mode, double omega, int ld, const T* in, T* out, hipStream_t s);
-// its float32 relaxation sweep reading float64 rows
+// its float32 relaxation sweep reading float64 rows, and its float64 sweep
+// storing float32 rows
 bool zmarch_cols_relax_f64in(const OpDev& op, double omega, int ld, const double* in, float* out, hipStream_t s);
+bool zmarch_cols_relax_f32out(const OpDev& op, double omega, int ld, const double* in, float* out, hipStream_t s);
 
 // the multi-column pass over (n, mp) blocks: the column-slab z-march on 3-D
 // FV7 grids (each row read from HBM once, where k_cols re-reads the z
@@ -1652,14 +1654,20 @@ int galerkin_coarse(const nlsp_operator* A, const double* P, int k, double omega
   // Q = (I - w D^-1 A)^nu P
   const double* cur = Pp;
   double* bufs[2] = {L.Y, L.Z};
+  bool q32_done = false;
   for (int it = 0; it < nu; ++it) {
+    // only the float32 Q wanted: the last sweep stores it rounded (3-D FV7)
+    if (it == nu - 1 && !Q64 && zmarch_cols_relax_f32out(op, omega, kp, cur, Q32, s)) {
+      q32_done = true;
+      break;
+    }
     double* dst = bufs[it & 1];
     launch_cols<double>(op, kp, omega, 0, cur, dst, s);
     cur = dst;
   }
   if (Q64)
     NLSP_HIP(hipMemcpyAsync(Q64, cur, sizeof(double) * n * kp, hipMemcpyDeviceToDevice, s));
-  if (Q32)
+  if (Q32 && !q32_done)
     hipLaunchKernelGGL(k_to_f32, dim3(ceil_div(n * kp, 256)), dim3(256), 0, s, cur, Q32, n * kp);
   NLSP_HIP(hipGetLastError());
   int info = 0;

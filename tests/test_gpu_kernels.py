@@ -165,6 +165,22 @@ def test_setup_spectral_P(nl, kind, size, m, k, prec):
         assert P[np.argmax(np.abs(P[:, j])), j] > 0
 
 
+@pytest.mark.parametrize("k", [16, 40])
+@pytest.mark.parametrize("nu", [1, 2])
+def test_galerkin_float_basis_only(nl, k, nu):
+    """Only the float32 smoothed basis asked for: on 3-D FV7 grids the last
+    float64 sweep stores it rounded; it equals the float32 rounding of the
+    float64 basis bit for bit, and the factors are unchanged."""
+    A, op, n = make_case("fv7", 8, (17, 13))
+    S = O.relax(A, np.random.default_rng(9).standard_normal((n, 2 * k)), 2 / 3, 10)
+    Pr, _ = O.spectral_basis(S, k)
+    M = nl.galerkin_coarse(op, cuda(Pr), 2 / 3, nu, q64=True, q32=True)
+    M32 = nl.galerkin_coarse(op, cuda(Pr), 2 / 3, nu, q64=False, q32=True)
+    assert torch.equal(M32.Q32, M.Q64.float())
+    assert torch.equal(M32.Q32, M.Q32)
+    assert torch.equal(M32.Ac, M.Ac) and torch.equal(M32.Linv, M.Linv)
+
+
 # k above 64: the row-by-row triangular inverse in LDS
 @pytest.mark.parametrize("kind,size,k", [("poisson", (32, 32), 16), ("fv5", (45, 38), 20),
                                          ("q1", (40, 40), 17), ("fv7", (17, 13), 8),

@@ -110,6 +110,8 @@ struct SysDev {
   int maxit, flexible, nu;
   unsigned rmask;          // RHS a restart launch applies to (ANDed with the launch mask)
   int ylines;              // 2-D line march of the matrix-core kernels (chunks ordered y fastest)
+  int zorder;              // 3-D chunks ordered z fastest (the x-lines split into whole chunks)
+  int nxq;                 // chunks per x-line when zorder or ylines
 };
 
 // XCD-aware order: hardware places workgroup b on XCD b % 8; give each XCD a
@@ -550,22 +552,22 @@ struct ChunkRange {
 // previous and next chunk) and the workgroups of one XCD hold neighbouring
 // columns.  Otherwise chunks are consecutive row ranges.
 NLSP_DEV int64_t chunk_row0(const SysDev& S, int64_t ch) {
-  const int nz = S.op.nz, cr = S.chunk_rows;
-  if (nz > 1 && S.op.nx % cr == 0) {
-    const int nxq = S.op.nx / cr;
-    const int64_t col = ch / nz;
-    const int z = (int)(ch - col * nz);
-    const int y = (int)(col / nxq), xq = (int)(col - (int64_t)y * nxq);
+  const int cr = S.chunk_rows;
+  // chunk counts fit 32 bits (n R < 2^31 is checked at entry): 32-bit divisions
+  const uint32_t c32 = (uint32_t)ch;
+  if (S.zorder) {
+    const uint32_t nz = (uint32_t)S.op.nz, nxq = (uint32_t)S.nxq;
+    const uint32_t col = c32 / nz, z = c32 - col * nz;
+    const uint32_t y = col / nxq, xq = col - y * nxq;
     return ((int64_t)z * S.op.ny + y) * S.op.nx + (int64_t)xq * cr;
   }
   if (S.ylines) {
     // 2-D 9-point operators with the matrix-core kernels march through y the
     // same way (logical chunk ch is line ch % ny of the x-segment ch / ny),
     // which their line rings rely on
-    const int ny = S.op.ny;
-    const int64_t xq = ch / ny;
-    const int y = (int)(ch - xq * ny);
-    return (int64_t)y * S.op.nx + xq * cr;
+    const uint32_t ny = (uint32_t)S.op.ny;
+    const uint32_t xq = c32 / ny, y = c32 - xq * ny;
+    return (int64_t)y * S.op.nx + (int64_t)xq * cr;
   }
   return ch * cr;
 }
@@ -857,20 +859,30 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
     // operands and q, p of the next chunk are loaded ahead too
     bool ym = false;
     if constexpr (YM) {
-      ym = S.ylines && cr.c0 < cr.c1 && cr.c0 / S.op.ny == (cr.c1 - 1) / S.op.ny;
+      // (chunk indices fit 32 bits)
+      const uint32_t ny32 = (uint32_t)S.op.ny;
+      ym = S.ylines && cr.c0 < cr.c1 && (uint32_t)cr.c0 / ny32 == (uint32_t)(cr.c1 - 1) / ny32;
       if (ym) {
-        const int nx = S.op.nx, ny = S.op.ny, crw = S.chunk_rows;
-        const int64_t seg = cr.c0 / ny;
-        const int x0 = (int)(seg * crw);
+        // descriptor fields and the stencil in registers: the loop's stores
+        // would otherwise make the compiler load them again
+        const int nx = S.op.nx, ny = S.op.ny, crw = S.chunk_rows, kpq = S.kp;
+        double* const Wout = S.w;
+        double cf[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) cf[k] = S.op.coef[k];
+        const int seg = (int)((uint32_t)cr.c0 / ny32);
+        const int x0 = seg * crw;
+        const int ly0 = (int)(cr.c0 - (int64_t)seg * ny), ly1 = ly0 + (int)(cr.c1 - cr.c0);
         const int xl = t / R;   // this lane's cell of the segment (chunk_rows = NT / R)
         // lanes t < 2 R also carry the cell just left (t < R) or right of the segment
         const int hs = t / R, xh = hs ? x0 + crw : x0 - 1;
         const bool hl = t < 2 * R && xh >= 0 && xh < nx;
         auto slot = [&](int ly) { return zring + (ly & 3) * YM_SLOT; };
+        auto row_of = [&](int ly) { return (int64_t)ly * nx + x0; };   // first row of line ly's segment
         double zc = 0.0, zh = 0.0;   // line in flight: this lane's cell and halo cell
         auto zload = [&](int ly) {
           if (ly >= 0 && ly < ny) {
-            zc = Z[((int64_t)ly * nx + x0 + xl) * R + c];
+            zc = Z[(row_of(ly) + xl) * R + c];
             if (hl) zh = Z[((int64_t)ly * nx + xh) * R + c];
           }
         };
@@ -882,33 +894,31 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
         };
         QS an[8];
         double qn = 0.0, pn = 0.0;
-        auto rload = [&](int64_t ch) {
-          const int64_t row0 = chunk_row0(S, ch);
+        auto rload = [&](int ly) {
+          const int64_t row0 = row_of(ly);
 #pragma unroll
           for (int s = 0; s < 8; ++s)
-            an[s] = Qt[(row0 + sl * rps + 4 * min(s, ksteps - 1) + lg) * S.kp + 16 * I + lr];
+            an[s] = Qt[(row0 + sl * rps + 4 * min(s, ksteps - 1) + lg) * kpq + 16 * I + lr];
           const int64_t g = (row0 + xl) * R + c;
           qn = Qv[g];
           pn = Pv[g];
         };
-        const int ly0 = (int)(cr.c0 - seg * ny);
         zload(ly0 - 1);
         zput(ly0 - 1);
         zload(ly0);
         zput(ly0);
         zload(ly0 + 1);
-        rload(cr.c0);
+        rload(ly0);
         if (na == 0) return;   // uniform over the workgroup (one system), before any barrier
-        for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-          const int ly = (int)(ch - seg * ny);
+        for (int ly = ly0; ly < ly1; ++ly) {
           zput(ly + 1);
           QS a[8];
 #pragma unroll
           for (int s = 0; s < 8; ++s) a[s] = an[s];
           const double qi = qn, pi = pn;
-          if (ch + 1 < cr.c1) {
+          if (ly + 1 < ly1) {
             zload(ly + 2);
-            rload(ch + 1);
+            rload(ly + 1);
           }
           __syncthreads();
           double wval = 0.0;
@@ -921,11 +931,11 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
               const int xx = x0 + xl + dx;
               const bool ok = oky && xx >= 0 && xx < nx;
               const double vj = sv[(xl + dx + 1) * R + c];
-              wval += ok ? S.op.coef[(dy + 1) * 3 + (dx + 1)] * vj : 0.0;
+              wval += ok ? cf[(dy + 1) * 3 + (dx + 1)] * vj : 0.0;
             }
           }
           const double zi = slot(ly)[(xl + 1) * R + c];
-          store_partial(&S.w[(chunk_row0(S, ch) + xl) * R + c], wval);
+          store_partial(&Wout[(row_of(ly) + xl) * R + c], wval);
           zw += zi * wval;
           e1 += zi * qi + pi * wval;
           wv[t] = wval;
@@ -1352,8 +1362,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     double z, r, p, w, qo, x;
     float d;   // float inverse diagonal (two-ahead form only)
   } rv{}, rvn{};
-  auto row_fetch = [&](RowVals& o, int64_t ch1) {
-    const int64_t r1 = chunk_row0(S, ch1);
+  auto row_fetch_at = [&](RowVals& o, int64_t r1) {   // the chunk whose first row is r1
     const int nr = (int)min<int64_t>(S.chunk_rows, S.op.n - r1);
     const int64_t row = r1 + min(t / R, nr - 1);
     const int64_t gg = row * R + c;
@@ -1365,6 +1374,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
     o.x = S.x[gg];
     if constexpr (PF2) o.d = S.dinv32[row];
   };
+  auto row_fetch = [&](RowVals& o, int64_t ch1) { row_fetch_at(o, chunk_row0(S, ch1)); };
   // The chunk after the last of this workgroup belongs to the next workgroup;
   // on z-ordered grids it is still the +z plane of that last chunk (rvn is
   // read for r, w, q_old only, which this kernel does not write).
@@ -1420,11 +1430,23 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
   // order; the two may contract them into FMAs differently).
   bool ym = false;
   if constexpr (PF2 && YM) {
-    ym = (phase & PH_Z) && wsrc < 0 && S.ylines && cr.c0 < cr.c1 && cr.c0 / S.op.ny == (cr.c1 - 1) / S.op.ny;
+    // (chunk indices fit 32 bits)
+    const uint32_t ny32 = (uint32_t)S.op.ny;
+    ym = (phase & PH_Z) && wsrc < 0 && S.ylines && cr.c0 < cr.c1 &&
+         (uint32_t)cr.c0 / ny32 == (uint32_t)(cr.c1 - 1) / ny32;
     if (ym) {
+      // descriptor fields in registers: the loop's stores would otherwise
+      // make the compiler load them again
       const int nx = S.op.nx, ny = S.op.ny, crw = S.chunk_rows;
-      const int64_t seg = cr.c0 / ny;
-      const int x0 = (int)(seg * crw);
+      double* const Pw = S.p;
+      double* const Xw = S.x;
+      double* const Zw = S.z;
+      const bool flex = S.flexible != 0;
+      const double* const cf = S.op.coef;   // the stencil (uniform loads)
+      const int seg = (int)((uint32_t)cr.c0 / ny32);
+      const int x0 = seg * crw;
+      const int ly0 = (int)(cr.c0 - (int64_t)seg * ny), ly1 = ly0 + (int)(cr.c1 - cr.c0);
+      auto row_of = [&](int ly) { return (int64_t)ly * nx + x0; };   // first row of line ly's segment
       const int xl = t / R;   // this lane's cell of the segment (every chunk is a whole line segment)
       auto slot = [&](int ly) { return yring + (ly & 3) * YM_SLOT; };
       auto yglob = [&](int64_t j) { return dj(j) * QT(rnew(j)); };
@@ -1443,10 +1465,10 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         double ri, zo;
         QT d;
       };
-      // the rows of chunk chn from the row vectors in rv: p, q, x, r_new, and
+      // the rows of line lyn from the row vectors in rv: p, q, x, r_new, and
       // the cell's D^-1 r_new into the ring
-      auto rows_of = [&](int64_t chn, Cur& o) {
-        const int64_t gg = (chunk_row0(S, chn) + xl) * R + c;
+      auto rows_of = [&](int lyn, Cur& o) {
+        const int64_t gg = (row_of(lyn) + xl) * R + c;
         o.ri = 0.0;
         o.zo = 0.0;
         o.d = QT(rv.d);
@@ -1455,37 +1477,35 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         if (full) {
           const double pi = rs ? o.zo : o.zo + beta * rv.p;
           const double qi = rs ? rv.w : rv.w + beta * rv.qo;
-          store_partial(&S.p[gg], pi);
+          store_partial(&Pw[gg], pi);
           store_partial(&Qn[gg], qi);
-          store_partial(&S.x[gg], rv.x + alpha * pi);
+          store_partial(&Xw[gg], rv.x + alpha * pi);
           o.ri = rv.r - alpha * qi;
           pq += pi * qi;
         } else {
           o.ri = rv.r;
         }
-        slot((int)(chn - seg * ny))[(xl + 1) * R + c] = o.d * QT(o.ri);
+        slot(lyn)[(xl + 1) * R + c] = o.d * QT(o.ri);
       };
       Cur cur, nxc;
       {
-        const int ly0 = (int)(cr.c0 - seg * ny);
         line_glob(ly0 - 1);
         halo(ly0 - 1);
-        rows_of(cr.c0, cur);
+        rows_of(ly0, cur);
         halo(ly0);
         rv = rvn;
-        // a chunk past the run is never used: its loads go to chunk 0, whose
+        // a line past the run is never used: its loads go to row 0, whose
         // lines every finishing workgroup reads and so stay in the L2
-        row_fetch(rvn, cr.c0 + 2 < cr.c1 ? cr.c0 + 2 : 0);
+        row_fetch_at(rvn, ly0 + 2 < ly1 ? row_of(ly0 + 2) : 0);
       }
-      for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
-        const int ly = (int)(ch - seg * ny);
-        if (ch > cr.c0) {
-          row0 = chunk_row0(S, ch);
+      for (int ly = ly0; ly < ly1; ++ly) {
+        if (ly > ly0) {
+          row0 = row_of(ly);
           nrows = crw;
           mf_fetch(row0, nrows);
         }
-        if (ch + 1 < cr.c1)
-          rows_of(ch + 1, nxc);
+        if (ly + 1 < ly1)
+          rows_of(ly + 1, nxc);
         else
           line_glob(ly + 1);
         halo(ly + 1);
@@ -1505,7 +1525,7 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
               const int xx = x0 + xl + dx;
               const bool ok = oky && xx >= 0 && xx < nx;
               const QT vj = sl[(xl + dx + 1) * R + c];
-              ay += ok ? QT(S.op.coef[(dy + 1) * 3 + (dx + 1)]) * vj : QT(0);
+              ay += ok ? QT(cf[(dy + 1) * 3 + (dx + 1)]) * vj : QT(0);
             }
           }
           const QT yi = slot(ly)[(xl + 1) * R + c];   // this cell's own operand
@@ -1534,14 +1554,14 @@ __global__ __launch_bounds__(NT, 4) void k_update(const SysDev* __restrict__ sys
         if (upd) {
           const double zn = (double)ws[t] + (double)ys[t];
           if (full) store_partial(&Rout[g], cur.ri);
-          store_partial(&S.z[g], zn);
+          store_partial(&Zw[g], zn);
           gam += cur.ri * zn;
-          if (S.flexible) rzo += cur.ri * cur.zo;
+          if (flex) rzo += cur.ri * cur.zo;
           rr += cur.ri * cur.ri;
         }
         cur = nxc;
         rv = rvn;
-        row_fetch(rvn, ch + 3 < cr.c1 ? ch + 3 : 0);
+        row_fetch_at(rvn, ly + 3 < ly1 ? row_of(ly + 3) : 0);
       }
     }
   }
@@ -1996,10 +2016,12 @@ inline SysDev make_sysdev(const nlsp_operator& A, const nlsp_two_level& M, const
   hs.maxit = opts->maxit;
   hs.flexible = opts->flexible ? 1 : 0;
   hs.rmask = 0xffffffffu;
+  hs.zorder = (A.nz > 1 && A.nx % h.chunk_rows == 0) ? 1 : 0;
   hs.ylines = (A.kind == NLSP_OP_STENCIL9 && A.nz <= 1 && A.ny > 1 && A.nx % h.chunk_rows == 0 &&
                mf_ok(R, h.kp) && h.chunk_rows == NT / R)
                   ? 1
                   : 0;
+  hs.nxq = A.nx / h.chunk_rows;
   return hs;
 }
 

@@ -181,7 +181,7 @@ def main():
     launch_ms = tm["total_ms"] / max(1, tm["launches"])
     bytes_launch = solver_bytes_per_row(phase, kp) * n
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    kname = {1: "nlsp::k_update<float, false>", 2: "nlsp::k_matvec<float, false>"}[phase]
+    kname = {1: "nlsp::k_update<float, false, false>", 2: "nlsp::k_matvec<float, false, false>"}[phase]
     out = {
         "metric": "PCG time-to-1e-8 rel-residual (ms)",
         "value": round(statistics.median(solve_ms), 4),
@@ -242,7 +242,7 @@ def f16_leg(step, nl, n, kp, reps=3):
     return {"solve_ms": round(statistics.median(r[1] for r in runs), 4),
             "iters": int(statistics.median(r[2].iters for r in runs)),
             "relres": max(r[2].relres for r in runs),
-            "update_kernel": {"kernel": "nlsp::k_update<_Float16, false>", "launch_us": round(launch_ms * 1e3, 3),
+            "update_kernel": {"kernel": "nlsp::k_update<_Float16, false, false>", "launch_us": round(launch_ms * 1e3, 3),
                               "bytes_per_launch": int(bl), "achieved": round(ach, 1),
                               "frac": round(ach / HBM_PEAK_GBS, 4)}}
 
@@ -351,7 +351,7 @@ def solve3d_leg(nl, torch, dev, cpu=False):
             launch_ms = tm["total_ms"] / max(1, tm["launches"])
             bl = solver_bytes_per_row(1, kp, R) * n
             ach = bl / (launch_ms * 1e-3) / 1e9
-            r["roofline"] = {"bound": "hbm", "kernel": "nlsp::k_update<float, true>", "achieved": round(ach, 1),
+            r["roofline"] = {"bound": "hbm", "kernel": "nlsp::k_update<float, true, false>", "achieved": round(ach, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                              "traffic": None, "launch_us": round(launch_ms * 1e3, 3),
                              "bytes_per_launch": int(bl), "timed_launches": int(tm["launches"])}

@@ -18,6 +18,9 @@ FLAGS = [
     # no packed FP32 instructions are generated (wrong results were observed
     # with some of their forms)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the first kernel arguments arrive preloaded in scalar registers (the
+    # code keeps the path that loads them for firmware that does not)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
 ]
 SOURCES = ["operators.hip", "pcg.hip", "setup.hip", "losses.hip", "cnn.hip", "fem.hip"]
 

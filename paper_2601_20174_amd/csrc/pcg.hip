@@ -819,13 +819,13 @@ __global__ __launch_bounds__(NT, 4) void k_residual(const SysDev* __restrict__ s
 // by the epilogue.  Nothing here waits for a scalar: every workgroup streams
 // from its first instruction.  In a batch, a system whose right-hand sides
 // have all stopped exits at once.
-template <typename QS, bool MF, bool YM = false>
+template <typename QS, bool MF, bool YM = false, bool ZM = false>
 __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys,
                                                   const int* __restrict__ blk2sys, int nsys, int it) {
   __shared__ double wv[NT];
   // line ring of the 2-D 9-point march: 4 lines of (segment + 2 halo cells) x R
   // values of z
-  __shared__ double zring[(YM && MF) ? 4 * YM_SLOT : 1];
+  __shared__ double zring[((YM || ZM) && MF) ? 4 * YM_SLOT : 1];
   __shared__ double sh[2 * (NT + 16)];
   __shared__ double red[4 * NT + 128];
   __shared__ double buf[2 * MAXR];
@@ -946,7 +946,112 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
         }
       }
     }
-    if (!ym)
+    // 3-D finite-volume systems marched through z (chunk_row0): a
+    // workgroup's run of chunks is the planes of one (y, x-segment) column.
+    // z of plane z + 1 (and the two cells beside the segment) is loaded one
+    // plane ahead into an LDS ring; the -y and +y neighbours, the cell's face
+    // weights (one per lane, exchanged with lane shuffles) and coefficient
+    // are loaded one plane ahead into registers, so the stencil of op_row
+    // (the same terms in the same order) waits for no load.
+    bool zm = false;
+    if constexpr (ZM) {
+      const uint32_t nz32 = (uint32_t)S.op.nz;
+      zm = S.zorder && S.op.kind == NLSP_OP_FV7 && cr.c0 < cr.c1 &&
+           (uint32_t)cr.c0 / nz32 == (uint32_t)(cr.c1 - 1) / nz32;
+      if (zm) {
+        const int nx = S.op.nx, ny = S.op.ny, nz = S.op.nz, crw = S.chunk_rows, kpq = S.kp;
+        const int64_t n = S.op.n, sxy = (int64_t)nx * ny;
+        double* const Wout = S.w;
+        const double* const FW = S.op.fw64;
+        const double* const AC = S.op.coef;
+        const uint32_t col = (uint32_t)cr.c0 / nz32;
+        const int yq = (int)(col / (uint32_t)S.nxq), x0 = (int)(col - (uint32_t)yq * (uint32_t)S.nxq) * crw;
+        const int z0 = (int)(cr.c0 - (int64_t)col * nz), z1 = z0 + (int)(cr.c1 - cr.c0);
+        const int xl = t / R, px = x0 + xl;   // this lane's cell of the segment (chunk_rows = NT / R)
+        const int hs = t / R, xh = hs ? x0 + crw : x0 - 1;
+        const bool hl = t < 2 * R && xh >= 0 && xh < nx;
+        const bool inx0 = px > 0, inx1 = px < nx - 1, iny0 = yq > 0, iny1 = yq < ny - 1;
+        auto slot = [&](int pz) { return zring + (pz & 3) * YM_SLOT; };
+        auto row_of = [&](int pz) { return ((int64_t)pz * ny + yq) * nx + x0; };   // first row of plane pz's segment
+        // loads take a workgroup-uniform base (the plane's segment) and a
+        // 32-bit lane offset
+        const int lo = xl * R + c, lh = (xh - x0) * R + c, ny_r = nx * R;
+        double zc = 0.0, zh = 0.0;   // plane in flight: this lane's cell and halo cell
+        auto zload = [&](int pz) {
+          if (pz >= 0 && pz < nz) {
+            const double* Zp = Z + row_of(pz) * R;
+            zc = Zp[lo];
+            if (hl) zh = Zp[lh];
+          }
+        };
+        auto zput = [&](int pz) {
+          if (pz >= 0 && pz < nz) {
+            slot(pz)[(xl + 1) * R + c] = zc;
+            if (hl) slot(pz)[(hs ? crw + 1 : 0) * R + c] = zh;
+          }
+        };
+        // per plane: -y and +y neighbours (a missing one reads the cell
+        // itself), the face weight of face c of the cell (lanes c < 6, in
+        // op_row's order and indexing) and the cell's coefficient
+        double ymv = 0.0, ypv = 0.0, fwv = 0.0, apv = 0.0;
+        const int fc = min(c, 5);
+        auto sload = [&](int pz) {
+          const int64_t r0 = row_of(pz);
+          const double* Zp = Z + r0 * R;
+          ymv = Zp[iny0 ? lo - ny_r : lo];
+          ypv = Zp[iny1 ? lo + ny_r : lo];
+          const bool inf = fc == 0 ? inx0 : fc == 2 ? iny0 : fc == 4 ? pz > 0 : true;
+          const int step = fc == 0 ? 1 : fc == 2 ? nx : (int)sxy;
+          fwv = (FW + (int64_t)(fc / 2) * n + r0)[((fc & 1) == 0 && inf) ? xl - step : xl];
+          apv = (AC + r0)[xl];
+        };
+        zload(z0 - 1);
+        zput(z0 - 1);
+        zload(z0);
+        zput(z0);
+        zload(z0 + 1);
+        sload(z0);
+        if (na == 0) return;   // uniform over the workgroup (one system), before any barrier
+        const int sbase = (t & (WAVE - 1)) - c;   // lane of the cell's first right-hand side
+        for (int pz = z0; pz < z1; ++pz) {
+          zput(pz + 1);
+          if (pz + 1 < z1) zload(pz + 2);
+          // this plane's basis operands and q, p: used after the stencil
+          // and the barrier that follows it
+          const int64_t row0 = row_of(pz);
+          const QS* Qp = Qt + row0 * kpq;
+          QS a[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) a[s] = Qp[(sl * rps + 4 * min(s, ksteps - 1) + lg) * kpq + 16 * I + lr];
+          const double qi = (Qv + row0 * R)[lo], pi = (Pv + row0 * R)[lo];
+          __syncthreads();
+          // op_row's face loop: faces -x, +x, -y, +y, -z, +z
+          const bool in[6] = {inx0, inx1, iny0, iny1, pz > 0, pz < nz - 1};
+          const double aP = apv;
+          const double own = slot(pz)[(xl + 1) * R + c];
+          const double vn[6] = {slot(pz)[xl * R + c], slot(pz)[(xl + 2) * R + c], ymv, ypv,
+                                slot(pz - 1)[(xl + 1) * R + c], slot(pz + 1)[(xl + 1) * R + c]};
+          double d = 0.0, sum = 0.0;
+#pragma unroll
+          for (int f = 0; f < 6; ++f) {
+            const double tf = __shfl(fwv, sbase + f);
+            d += in[f] ? tf : 2.0 * aP;
+            sum += in[f] ? tf * vn[f] : 0.0;
+          }
+          const double wval = d * own - sum;
+          if (pz + 1 < z1) sload(pz + 1);
+          store_partial(&(Wout + row0 * R)[lo], wval);
+          zw += own * wval;
+          wv[t] = wval;
+          __syncthreads();
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            if (s < ksteps) acc = mf_mma((double)a[s], lr < R ? wv[(sl * rps + 4 * s + lg) * R + lr] : 0.0, acc);
+          e1 += own * qi + pi * wval;
+        }
+      }
+    }
+    if (!ym && !zm)
     for (int64_t ch = cr.c0; ch < cr.c1; ++ch) {
       const int64_t row0 = chunk_row0(S, ch);
       const int nrows = (int)min<int64_t>(S.chunk_rows, S.op.n - row0);
@@ -2041,7 +2146,9 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
   int nblk = 0;
   bool mf = true;   // MFMA basis passes when every system's (R, kp) has the matrix-core form
   bool ym = false;  // some system has the 2-D line march
+  bool zmk = false; // some system has the 3-D plane march of the matvec kernel
   for (const auto& h : hs) {
+    zmk = zmk || (h.zorder && h.op.kind == NLSP_OP_FV7);
     nblk += h.nblk;
     mf = mf && mf_ok(h.R, h.kp) && h.chunk_rows == NT / h.R;
     ym = ym || h.ylines;
@@ -2128,6 +2235,8 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
       timed(2, [&](hipEvent_t a, hipEvent_t b) {
         if (ym)
           hipExtLaunchKernelGGL((k_matvec<QS, true, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
+        else if (mf && zmk)
+          hipExtLaunchKernelGGL((k_matvec<QS, true, false, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
         else if (mf)
           hipExtLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, a, b, 0, dsys, b2s, nsys, it);
         else
@@ -2136,6 +2245,8 @@ static int run_pcg(int nsys, std::vector<SysDev>& hs, const BatchLayout& B, cons
     } else {
       if (ym)
         hipLaunchKernelGGL((k_matvec<QS, true, true>), grid, block, 0, st, dsys, b2s, nsys, it);
+      else if (mf && zmk)
+        hipLaunchKernelGGL((k_matvec<QS, true, false, true>), grid, block, 0, st, dsys, b2s, nsys, it);
       else if (mf)
         hipLaunchKernelGGL((k_matvec<QS, true>), grid, block, 0, st, dsys, b2s, nsys, it);
       else

@@ -12,7 +12,7 @@ import torch
 import oracle as O
 from oracle.method import make_preconditioner
 import workloads as W
-from tests._cases import make_case, cuda, host
+from tests._cases import make_case, cuda, host, gpu_op
 
 pytestmark = pytest.mark.gpu
 
@@ -115,6 +115,23 @@ def test_3d_zmajor_chunks(nl, R, size, k, prec):
     S = O.relax(A, np.random.default_rng(28).standard_normal((n, 2 * k)), 2 / 3, 10)
     P, _ = O.spectral_basis(S, k)
     f = np.random.default_rng(29).standard_normal((n, R))
+    _check(nl, A, op, P, f, prec=prec)
+
+
+# Matrix-core form on z-ordered 3-D grids with runs of two planes per
+# workgroup, some of which cross from one (y, x-segment) column into the next:
+# the matvec kernel marches a run within one column through z with its
+# operands in an LDS ring and registers, and takes the gather path otherwise
+@pytest.mark.parametrize("R,dims,k", [(16, (32, 6, 101), 64), (8, (64, 4, 131), 32)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_3d_plane_march_runs(nl, R, dims, k, prec):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(41)
+    a = np.where(rng.integers(0, 2, size=(nz, ny, nx)) == 1, 1e3, 1.0)
+    A, op, n = O.fv_harmonic_3d(a), gpu_op(nl.OP_FV7, nx, ny, nz, a), nx * ny * nz
+    S = O.relax(A, np.random.default_rng(42).standard_normal((n, 2 * k)), 2 / 3, 10)
+    P, _ = O.spectral_basis(S, k)
+    f = np.random.default_rng(43).standard_normal((n, R))
     _check(nl, A, op, P, f, prec=prec)
 
 

@@ -181,7 +181,7 @@ def main():
     launch_ms = tm["total_ms"] / max(1, tm["launches"])
     bytes_launch = solver_bytes_per_row(phase, kp) * n
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    kname = {1: "nlsp::k_update<float, false, false>", 2: "nlsp::k_matvec<float, false, false>"}[phase]
+    kname = {1: "nlsp::k_update<float, false, false>", 2: "nlsp::k_matvec<float, false, false, false>"}[phase]
     out = {
         "metric": "PCG time-to-1e-8 rel-residual (ms)",
         "value": round(statistics.median(solve_ms), 4),

@@ -1017,12 +1017,16 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
           zput(pz + 1);
           if (pz + 1 < z1) zload(pz + 2);
           // this plane's basis operands and q, p: used after the stencil
-          // and the barrier that follows it
+          // and the barrier that follows it (a float64 basis is loaded after
+          // the stencil instead: its operands take twice the registers)
           const int64_t row0 = row_of(pz);
           const QS* Qp = Qt + row0 * kpq;
           QS a[8];
+          auto aload = [&]() {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) a[s] = Qp[(sl * rps + 4 * min(s, ksteps - 1) + lg) * kpq + 16 * I + lr];
+            for (int s = 0; s < 8; ++s) a[s] = Qp[(sl * rps + 4 * min(s, ksteps - 1) + lg) * kpq + 16 * I + lr];
+          };
+          if constexpr (sizeof(QS) != 8) aload();
           const double qi = (Qv + row0 * R)[lo], pi = (Pv + row0 * R)[lo];
           __syncthreads();
           // op_row's face loop: faces -x, +x, -y, +y, -z, +z
@@ -1040,6 +1044,7 @@ __global__ __launch_bounds__(NT, 4) void k_matvec(const SysDev* __restrict__ sys
           }
           const double wval = d * own - sum;
           if (pz + 1 < z1) sload(pz + 1);
+          if constexpr (sizeof(QS) == 8) aload();
           store_partial(&(Wout + row0 * R)[lo], wval);
           zw += own * wval;
           wv[t] = wval;

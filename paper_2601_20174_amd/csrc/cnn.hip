@@ -7,8 +7,9 @@
 //
 // Four 3x3 convolutions ('same', zero padding), hidden width CH, erf-GELU
 // after the first three.  Activations are NHWC bfloat16 with channel counts
-// padded to multiples of 16; products are v_mfma_f32_16x16x16_bf16 with
-// float32 accumulation.  Layer l stores its pre-activation z_l; the next
+// padded to multiples of 16; products are v_mfma_f32_16x16x32_bf16 (two
+// 16-deep slices of the contraction per instruction; v_mfma_f32_16x16x16_bf16
+// for an odd last slice) with float32 accumulation.  Layer l stores its pre-activation z_l; the next
 // layer applies GELU while staging its input, and the backward multiplies by
 // GELU'(z_l) in the epilogue of the data gradient, so no activation is
 // stored twice.  Master parameters, gradients and the optimiser are float32.
@@ -27,9 +28,21 @@ constexpr int TILE = 16;            // 16 x 16 output pixels per workgroup
 constexpr int HALO = TILE + 2;
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 NLSP_DEV f4 mfma_bf16(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+// Two 16-deep products in one instruction.  Lane l of the 32-deep form holds
+// contraction slots 8 (l / 16) .. 8 (l / 16) + 7 of its row (A) or column
+// (B); filling the low half of both operands from one 16-deep slice and the
+// high half from another puts the same contraction index in the same slot of
+// A and B, so the result is the sum of the two 16-deep products.
+NLSP_DEV s8 cat(s4 lo, s4 hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7); }
+NLSP_DEV f4 mfma_bf16x2(s4 a0, s4 a1, s4 b0, s4 b1, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, cat(a0, a1)), __builtin_bit_cast(bf8, cat(b0, b1)),
+                                                 c, 0, 0, 0);
+}
 
 // float <-> bfloat16 (round to nearest even; inputs are finite)
 NLSP_DEV unsigned short to_bf16(float x) {
@@ -134,8 +147,9 @@ __global__ __launch_bounds__(NT) void k_prep_weights(const float* __restrict__ W
 // One 16 x 16 pixel tile of one field per workgroup, all OC output channels
 // (OCT = OC / 16 tiles).  D (16 oc x 16 pixels) = sum over taps and input
 // channels of Wk[tap][oc][ic] X[pixel + tap][ic]: A = weights (lane: oc =
-// l % 16, 4 consecutive ic), B = input (lane: pixel = l % 16, 4 consecutive
-// ic), so each lane holds 4 consecutive output channels of one pixel.
+// l % 16, 4 consecutive ic of each of two 16-channel slices), B = input
+// (lane: pixel = l % 16, the same ic), so each lane holds 4 consecutive
+// output channels of one pixel.
 // Wave w owns output rows 4 w .. 4 w + 3 of the tile.
 //   IN_GELU   input value = GELU(stored value)
 //   MODE 0    out bf16 z = D + bias                           (hidden layers)
@@ -191,14 +205,29 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
     for (int t = 0; t < OCT; ++t) acc[r][t] = f4{0.f, 0.f, 0.f, 0.f};
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3, dx = tap % 3;     // halo offsets (0..2)
-    for (int ic0 = 0; ic0 < ICp; ic0 += 16) {
-      s4 a[OCT], bv[4];
+    const unsigned short* wrow = Ws + (tap * OC + lp) * xs + 4 * lg;
+    const unsigned short* xrow = Xs + ((4 * w + dy) * HALO + lp + dx) * xs + 4 * lg;
+    int ic0 = 0;
+    for (; ic0 + 32 <= ICp; ic0 += 32) {
+      s4 a[2][OCT], bv[2][4];
 #pragma unroll
-      for (int t = 0; t < OCT; ++t)
-        a[t] = *reinterpret_cast<const s4*>(Ws + (tap * OC + 16 * t + lp) * xs + ic0 + 4 * lg);
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int t = 0; t < OCT; ++t) a[h][t] = *reinterpret_cast<const s4*>(wrow + 16 * t * xs + ic0 + 16 * h);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[h][r] = *reinterpret_cast<const s4*>(xrow + r * HALO * xs + ic0 + 16 * h);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        bv[r] = *reinterpret_cast<const s4*>(Xs + ((4 * w + r + dy) * HALO + lp + dx) * xs + ic0 + 4 * lg);
+#pragma unroll
+        for (int t = 0; t < OCT; ++t) acc[r][t] = mfma_bf16x2(a[0][t], a[1][t], bv[0][r], bv[1][r], acc[r][t]);
+    }
+    if (ic0 < ICp) {   // ICp = 32 j + 16: the last 16 channels
+      s4 a[OCT], bv[4];
+#pragma unroll
+      for (int t = 0; t < OCT; ++t) a[t] = *reinterpret_cast<const s4*>(wrow + 16 * t * xs + ic0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[r] = *reinterpret_cast<const s4*>(xrow + r * HALO * xs + ic0);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -206,6 +235,7 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
     }
   }
   // epilogue: lane holds oc = 16 t + 4 lg + v of pixel (row 4 w + r, column lp)
+  const bool vec4 = MODE == 1 && (k & 3) == 0 && ((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(phi)) & 15) == 0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int y = ty0 + 4 * w + r, x = tx0 + lp;
@@ -222,8 +252,17 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
       } else if (MODE == 1) {
         float* P = static_cast<float*>(out);
         const int64_t pl = (int64_t)y * N + x;
-        for (int v = 0; v < 4; ++v)
-          if (oc0 + v < k) P[pix * k + oc0 + v] = phi[pl * k + oc0 + v] + acc[r][t][v] + bias[oc0 + v];
+        if (vec4) {   // the lane's 4 channels as one 16-byte load of Phi and one store of P
+          if (oc0 < k) {
+            const float4 ph = *reinterpret_cast<const float4*>(phi + pl * k + oc0);
+            *reinterpret_cast<float4*>(P + pix * k + oc0) =
+                make_float4(ph.x + acc[r][t][0] + bias[oc0], ph.y + acc[r][t][1] + bias[oc0 + 1],
+                            ph.z + acc[r][t][2] + bias[oc0 + 2], ph.w + acc[r][t][3] + bias[oc0 + 3]);
+          }
+        } else {
+          for (int v = 0; v < 4; ++v)
+            if (oc0 + v < k) P[pix * k + oc0 + v] = phi[pl * k + oc0 + v] + acc[r][t][v] + bias[oc0 + v];
+        }
       } else {
         const uint2 zz = *reinterpret_cast<const uint2*>(zprev + pix * OC + oc0);
         const unsigned short zh[4] = {(unsigned short)(zz.x & 0xffff), (unsigned short)(zz.x >> 16),
@@ -242,7 +281,8 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
 // dZ[p][oc] X[p + tap][ic] and db[oc] = sum dZ[p][oc].  D (16 oc x 16 ic)
 // per (tap, oc-tile, ic-tile); the contraction runs over 16 pixels of one
 // image row per step: A = dZ^T (lane: oc = l % 16, 4 consecutive pixels),
-// B = shifted X (lane: 4 consecutive pixels, ic = l % 16).  Both tiles are
+// B = shifted X (lane: 4 consecutive pixels, ic = l % 16), two image rows per
+// 32-deep instruction.  Both tiles are
 // staged channel-major.  Tiles of the 9 x OCT x ICT outputs are dealt to the
 // 4 waves; a wave holds at most MAXT accumulators.
 constexpr int WG_TILES = 8;          // pixel tiles per workgroup
@@ -329,8 +369,8 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
           const unsigned short* xr = xb + row * HALO;
           bv[u] = s4{(short)xr[0], (short)xr[1], (short)xr[2], (short)xr[3]};
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[s] = mfma_bf16(a[u], bv[u], acc[s]);
+        acc[s] = mfma_bf16x2(a[0], a[1], bv[0], bv[1], acc[s]);
+        acc[s] = mfma_bf16x2(a[2], a[3], bv[2], bv[3], acc[s]);
       }
     }
   }

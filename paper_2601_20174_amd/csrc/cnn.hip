@@ -357,7 +357,11 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
       const int ot = rem / ICT, it = rem % ICT;
       const int dy = tap / 3, dx = tap % 3;
       const unsigned short* dr = Dt + (16 * ot + lp) * DS + 4 * lg;
-      const unsigned short* xb = Xt + (16 * it + lp) * HS + dy * HALO + 4 * lg + dx;
+      // the lane's 4 pixels start at element dx of an even-aligned group of 6:
+      // three aligned dwords, realigned by 2 bytes where dx is odd
+      const uint32_t* xb = reinterpret_cast<const uint32_t*>(Xt + (16 * it + lp) * HS + dy * HALO + 4 * lg);
+      const bool d2 = dx >= 2;
+      const uint32_t sh = (uint32_t)(dx & 1) * 2;
       for (int row0 = 0; row0 < TILE; row0 += 4) {
         // pixels 4 lg .. 4 lg + 3 of output rows row0 .. row0 + 3: all operand
         // reads first, then the four products
@@ -366,8 +370,11 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
         for (int u = 0; u < 4; ++u) {
           const int row = row0 + u;
           a[u] = *reinterpret_cast<const s4*>(dr + row * TILE);
-          const unsigned short* xr = xb + row * HALO;
-          bv[u] = s4{(short)xr[0], (short)xr[1], (short)xr[2], (short)xr[3]};
+          const uint32_t* xr = xb + row * (HALO / 2);
+          const uint32_t w0 = xr[0], w1 = xr[1], w2 = xr[2];
+          const uint32_t lo = __builtin_amdgcn_alignbyte(d2 ? w2 : w1, d2 ? w1 : w0, sh);
+          const uint32_t hi = __builtin_amdgcn_alignbyte(w2, d2 ? w2 : w1, sh);
+          bv[u] = __builtin_bit_cast(s4, make_uint2(lo, hi));
         }
         acc[s] = mfma_bf16x2(a[0], a[1], bv[0], bv[1], acc[s]);
         acc[s] = mfma_bf16x2(a[2], a[3], bv[2], bv[3], acc[s]);

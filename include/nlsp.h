@@ -526,7 +526,9 @@ int qr_thin_bwd(int batch, int n, int k, const float* Q, const double* R, const 
  * Parameters (float32, one vector): for l = 1..4, W_l (Cout, Cin, 3, 3) then
  * b_l (Cout).  Arithmetic: bfloat16 activations and weights in the
  * convolutions, float32 accumulation, float32 output and gradients.
- * Limits: k and hidden multiples of 16, <= 64; N >= 16. */
+ * Limits: k and hidden multiples of 16, <= 64; N >= 16;
+ * ceil((1 + k) / 16) * hidden / 16 <= 16 (so k = 64 with hidden = 64 is
+ * rejected). */
 typedef struct {
   int batch;             /* fields */
   int N;                 /* cells per side */

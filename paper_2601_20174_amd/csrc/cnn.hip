@@ -283,8 +283,11 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
 // image row per step: A = dZ^T (lane: oc = l % 16, 4 consecutive pixels),
 // B = shifted X (lane: 4 consecutive pixels, ic = l % 16), two image rows per
 // 32-deep instruction.  Both tiles are
-// staged channel-major.  Tiles of the 9 x OCT x ICT outputs are dealt to the
-// 4 waves; a wave holds at most MAXT accumulators.
+// staged channel-major.  The 9 x OCT x ICT output tiles form 3 x OCT x ICT
+// groups (dy, oc-tile, ic-tile) of the three taps dx = 0, 1, 2, which share
+// their A operand and the staged words their B operands come from; groups are
+// dealt to the 4 waves, and a wave holds at most MAXT (a multiple of 3)
+// accumulators.
 constexpr int WG_TILES = 8;          // pixel tiles per workgroup
 template <int MAXT, bool IN_GELU>
 __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int ntiles_total,
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lp = lane & 15, lg = lane >> 4;
   const int ICT = ICp / 16, OCT = OCp / 16;
-  const int nout = 9 * OCT * ICT;
+  const int ngrp = 3 * OCT * ICT;
   f4 acc[MAXT];
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
@@ -350,47 +353,52 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(int N, int ICp, int OCp, int 
     if (bsl < nsl)
       for (int p = bsl; p < TILE * TILE; p += nsl) dbias += from_bf16(Dt[boc * DS + p]);
 #pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-      const int o = w + 4 * s;
-      if (o >= nout) break;
-      const int tap = o / (OCT * ICT), rem = o % (OCT * ICT);
+    for (int s = 0; s < MAXT / 3; ++s) {
+      const int g = w + 4 * s;
+      if (g >= ngrp) break;
+      const int dy = g / (OCT * ICT), rem = g % (OCT * ICT);
       const int ot = rem / ICT, it = rem % ICT;
-      const int dy = tap / 3, dx = tap % 3;
       const unsigned short* dr = Dt + (16 * ot + lp) * DS + 4 * lg;
-      // the lane's 4 pixels start at element dx of an even-aligned group of 6:
-      // three aligned dwords, realigned by 2 bytes where dx is odd
+      // the lane's 4 pixels of tap dx start at element dx of an even-aligned
+      // group of 6: three aligned dwords serve all three taps (realigned by 2
+      // bytes for dx = 1)
       const uint32_t* xb = reinterpret_cast<const uint32_t*>(Xt + (16 * it + lp) * HS + dy * HALO + 4 * lg);
-      const bool d2 = dx >= 2;
-      const uint32_t sh = (uint32_t)(dx & 1) * 2;
       for (int row0 = 0; row0 < TILE; row0 += 4) {
         // pixels 4 lg .. 4 lg + 3 of output rows row0 .. row0 + 3: all operand
-        // reads first, then the four products
-        s4 a[4], bv[4];
+        // reads first, then the products
+        s4 a[4], bv[3][4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int row = row0 + u;
           a[u] = *reinterpret_cast<const s4*>(dr + row * TILE);
           const uint32_t* xr = xb + row * (HALO / 2);
           const uint32_t w0 = xr[0], w1 = xr[1], w2 = xr[2];
-          const uint32_t lo = __builtin_amdgcn_alignbyte(d2 ? w2 : w1, d2 ? w1 : w0, sh);
-          const uint32_t hi = __builtin_amdgcn_alignbyte(w2, d2 ? w2 : w1, sh);
-          bv[u] = __builtin_bit_cast(s4, make_uint2(lo, hi));
+          bv[0][u] = __builtin_bit_cast(s4, make_uint2(w0, w1));
+          bv[1][u] = __builtin_bit_cast(s4, make_uint2(__builtin_amdgcn_alignbyte(w1, w0, 2),
+                                                       __builtin_amdgcn_alignbyte(w2, w1, 2)));
+          bv[2][u] = __builtin_bit_cast(s4, make_uint2(w1, w2));
         }
-        acc[s] = mfma_bf16x2(a[0], a[1], bv[0], bv[1], acc[s]);
-        acc[s] = mfma_bf16x2(a[2], a[3], bv[2], bv[3], acc[s]);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          acc[3 * s + dx] = mfma_bf16x2(a[0], a[1], bv[dx][0], bv[dx][1], acc[3 * s + dx]);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          acc[3 * s + dx] = mfma_bf16x2(a[2], a[3], bv[dx][2], bv[dx][3], acc[3 * s + dx]);
       }
     }
   }
   // partial record of this workgroup: [9][OCp][ICp] then [OCp]
   float* rec = part + (int64_t)blockIdx.x * (9 * OCp * ICp + OCp);
 #pragma unroll
-  for (int s = 0; s < MAXT; ++s) {
-    const int o = w + 4 * s;
-    if (o >= nout) break;
-    const int tap = o / (OCT * ICT), rem = o % (OCT * ICT);
+  for (int s = 0; s < MAXT / 3; ++s) {
+    const int g = w + 4 * s;
+    if (g >= ngrp) break;
+    const int dy = g / (OCT * ICT), rem = g % (OCT * ICT);
     const int ot = rem / ICT, it = rem % ICT;
-    for (int v = 0; v < 4; ++v)
-      rec[((int64_t)tap * OCp + 16 * ot + 4 * lg + v) * ICp + 16 * it + lp] = acc[s][v];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+      for (int v = 0; v < 4; ++v)
+        rec[((int64_t)(3 * dy + dx) * OCp + 16 * ot + 4 * lg + v) * ICp + 16 * it + lp] = acc[3 * s + dx][v];
   }
   __syncthreads();
   float* sb = reinterpret_cast<float*>(lds);   // staging area is free now
@@ -485,6 +493,8 @@ inline int r16(int v) { return (v + 15) / 16 * 16; }
 inline bool make_net(const nlsp_cnn_shape* s, Net& t) {
   if (!s || s->batch < 1 || s->N < TILE || s->k < 1 || s->k > 64 || s->hidden < 1 || s->hidden > 64) return false;
   if (s->k % 16 || s->hidden % 16) return false;
+  // the weight gradient holds at most 16 (oc-tile, ic-tile) pairs per layer
+  if ((r16(1 + s->k) / 16) * (s->hidden / 16) > 16) return false;
   if ((int64_t)s->batch * s->N * s->N * 64 >= (int64_t(1) << 31)) return false;
   t.batch = s->batch;
   t.N = s->N;
@@ -602,7 +612,9 @@ inline int wgrad(const Net& t, int l, const unsigned short* X, const unsigned sh
   const int tx = (t.N + TILE - 1) / TILE;
   const int tiles = t.batch * tx * tx;
   const size_t lds = wgrad_lds(ICp, OCp);
-  const int need = (9 * (OCp / 16) * (ICp / 16) + 3) / 4;
+  // accumulators per wave: three per (dy, oc-tile, ic-tile) group, groups dealt to 4 waves
+  const int need = 3 * ((3 * (OCp / 16) * (ICp / 16) + 3) / 4);
+  if (need > 36) return NLSP_E_INVALID;
   auto go = [&](auto kern) -> int {
     if (allow(kern, lds) != hipSuccess) return NLSP_E_HIP;
     hipLaunchKernelGGL(kern, dim3(groups), dim3(NT), lds, s, t.N, ICp, OCp, tiles, X, dZ, part);

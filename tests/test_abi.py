@@ -120,6 +120,20 @@ def test_workspace_queries(lib):
     assert lib.pcg_solve_workspace_bytes(op, 256, 16) == 0                      # kp * R > 2048
 
 
+def test_cnn_shape_limits(lib):
+    """Predictor shapes the library accepts: k and the hidden width multiples
+    of 16 up to 64, and at most 16 (16-channel output, 16-channel input)
+    tile pairs in the first layer's weight gradient."""
+    from paper_2601_20174_amd import api
+    assert api.cnn_param_count(2, 32, 32, 32) == (33 * 32 + 32 * 32 * 2 + 32 * 32) * 9 + 3 * 32 + 32
+    assert api.cnn_param_count(2, 32, 48, 64) > 0          # 4 x 4 tile pairs
+    assert api.cnn_param_count(2, 32, 64, 48) > 0          # 3 x 5
+    assert api.cnn_param_count(2, 32, 64, 64) == -1        # 4 x 5
+    assert api.cnn_workspace_bytes(2, 32, 64, 64) == 0
+    assert api.cnn_param_count(2, 32, 24, 32) == -1        # k not a multiple of 16
+    assert api.cnn_param_count(2, 8, 32, 32) == -1         # grid smaller than a tile
+
+
 def test_solver_workspace_holds_face_weights_for_matrix_core_form(lib):
     """A finite-volume operator solved in the matrix-core form (16 right-hand
     sides with k padded to 64 or 128: k in 33 .. 128; 8 with k padded to 32 or

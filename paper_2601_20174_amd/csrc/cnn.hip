@@ -203,35 +203,47 @@ __global__ __launch_bounds__(NT) void k_conv(int N, int ICp, int k, const unsign
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int t = 0; t < OCT; ++t) acc[r][t] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int tap = 0; tap < 9; ++tap) {
-    const int dy = tap / 3, dx = tap % 3;     // halo offsets (0..2)
-    const unsigned short* wrow = Ws + (tap * OC + lp) * xs + 4 * lg;
-    const unsigned short* xrow = Xs + ((4 * w + dy) * HALO + lp + dx) * xs + 4 * lg;
+  // for one column offset dx the three row offsets dy read rows 4 w + r + dy
+  // of the staged tile: the six rows are loaded once and serve all three
+  for (int dx = 0; dx < 3; ++dx) {
+    const unsigned short* xcol = Xs + (4 * w * HALO + lp + dx) * xs + 4 * lg;
+    const unsigned short* wcol = Ws + (dx * OC + lp) * xs + 4 * lg;   // tap 3 dy + dx: + 3 dy OC rows
     int ic0 = 0;
     for (; ic0 + 32 <= ICp; ic0 += 32) {
-      s4 a[2][OCT], bv[2][4];
+      s4 bv[2][6];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int t = 0; t < OCT; ++t) a[h][t] = *reinterpret_cast<const s4*>(wrow + 16 * t * xs + ic0 + 16 * h);
+        for (int q = 0; q < 6; ++q) bv[h][q] = *reinterpret_cast<const s4*>(xcol + q * HALO * xs + ic0 + 16 * h);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bv[h][r] = *reinterpret_cast<const s4*>(xrow + r * HALO * xs + ic0 + 16 * h);
+      for (int dy = 0; dy < 3; ++dy) {
+        s4 a[2][OCT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int t = 0; t < OCT; ++t)
+            a[h][t] = *reinterpret_cast<const s4*>(wcol + (3 * dy * OC + 16 * t) * xs + ic0 + 16 * h);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int t = 0; t < OCT; ++t)
+            acc[r][t] = mfma_bf16x2(a[0][t], a[1][t], bv[0][r + dy], bv[1][r + dy], acc[r][t]);
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int t = 0; t < OCT; ++t) acc[r][t] = mfma_bf16x2(a[0][t], a[1][t], bv[0][r], bv[1][r], acc[r][t]);
     }
     if (ic0 < ICp) {   // ICp = 32 j + 16: the last 16 channels
-      s4 a[OCT], bv[4];
+      s4 bv[6];
 #pragma unroll
-      for (int t = 0; t < OCT; ++t) a[t] = *reinterpret_cast<const s4*>(wrow + 16 * t * xs + ic0);
+      for (int q = 0; q < 6; ++q) bv[q] = *reinterpret_cast<const s4*>(xcol + q * HALO * xs + ic0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bv[r] = *reinterpret_cast<const s4*>(xrow + r * HALO * xs + ic0);
+      for (int dy = 0; dy < 3; ++dy) {
+        s4 a[OCT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+        for (int t = 0; t < OCT; ++t) a[t] = *reinterpret_cast<const s4*>(wcol + (3 * dy * OC + 16 * t) * xs + ic0);
 #pragma unroll
-        for (int t = 0; t < OCT; ++t) acc[r][t] = mfma_bf16(a[t], bv[r], acc[r][t]);
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int t = 0; t < OCT; ++t) acc[r][t] = mfma_bf16(a[t], bv[r + dy], acc[r][t]);
+      }
     }
   }
   // epilogue: lane holds oc = 16 t + 4 lg + v of pixel (row 4 w + r, column lp)

@@ -541,7 +541,7 @@ size_t cnn_workspace_bytes(const nlsp_cnn_shape* shape);
 
 /* P_hat (batch, N*N, k) float32 from params and the cell coefficients
  * coef (batch, N*N) float64 (device).  The workspace keeps the activations
- * for cnn_bwd.  Synchronises `stream`. */
+ * for cnn_bwd.  Asynchronous on `stream`. */
 int cnn_fwd(const nlsp_cnn_shape* shape, const float* params, const double* coef, float* Phat,
             void* ws, size_t ws_bytes, void* stream);
 

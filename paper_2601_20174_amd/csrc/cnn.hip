@@ -59,15 +59,18 @@ NLSP_DEV float gelu_grad(float x) {
 }
 
 // ------------------------------------------------------------- inputs
-// per field: mean and standard deviation of log a (float64)
+// per field: mean and standard deviation of log a (float64); log a itself is
+// kept for the input kernel
 __global__ __launch_bounds__(NT) void k_field_stats(const double* __restrict__ coef, int n,
-                                                    double* __restrict__ stats) {
+                                                    double* __restrict__ stats, double* __restrict__ loga) {
   __shared__ double sh[NT / 64];
   const int b = blockIdx.x;
   const double* a = coef + (int64_t)b * n;
+  double* la = loga + (int64_t)b * n;
   double s = 0.0, s2 = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) {
     const double l = log(a[i]);
+    la[i] = l;
     s += l;
     s2 += l * l;
   }
@@ -83,39 +86,43 @@ __global__ __launch_bounds__(NT) void k_field_stats(const double* __restrict__ c
 
 // Phi (n x k, float32): the k sine modes sin(i pi x) sin(j pi y) of the unit
 // square with the smallest i^2 + j^2 (ties by i), at the cell centres
-// ((c + 1/2)/N), scaled to unit 2-norm on the grid.  modes: (k x 2) int pairs.
-__global__ __launch_bounds__(NT) void k_sine_modes(int N, int k, const int* __restrict__ modes,
-                                                   float* __restrict__ phi) {
+// ((c + 1/2)/N), scaled to unit 2-norm on the grid.  modes: (k x 2) int pairs,
+// passed by value (k <= 64).
+struct ModeTable {
+  int ij[128];
+};
+__global__ __launch_bounds__(NT) void k_sine_modes(int N, int k, const ModeTable modes, float* __restrict__ phi) {
   const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (g >= (int64_t)N * N * k) return;
   const int j = (int)(g % k);
   const int64_t p = g / k;
   const int x = (int)(p % N), y = (int)(p / N);
   const double h = 1.0 / N;
-  const double v = sin(modes[2 * j] * M_PI * (x + 0.5) * h) * sin(modes[2 * j + 1] * M_PI * (y + 0.5) * h);
+  const double v = sin(modes.ij[2 * j] * M_PI * (x + 0.5) * h) * sin(modes.ij[2 * j + 1] * M_PI * (y + 0.5) * h);
   phi[g] = (float)(v * 2.0 * h);   // sum over the grid of sin^2 sin^2 = N^2 / 4
 }
 
 // x0[b][pixel][c]: c = 0 standardised log a, c = 1..k Phi, zero up to C0p;
-// one thread per pixel (one logarithm), 8-byte stores of 4 channels
-__global__ __launch_bounds__(NT) void k_cnn_input(const double* __restrict__ coef, const double* __restrict__ stats,
+// one thread per 4 channels of one pixel, so a wave's 8-byte stores (and its
+// Phi loads) are contiguous
+__global__ __launch_bounds__(NT) void k_cnn_input(const double* __restrict__ loga, const double* __restrict__ stats,
                                                   const float* __restrict__ phi, int n, int k, int C0p,
                                                   unsigned short* __restrict__ x0) {
   const int b = blockIdx.y;
-  const int p = blockIdx.x * NT + threadIdx.x;
-  if (p >= n) return;
-  const float a0 = (float)((log(coef[(int64_t)b * n + p]) - stats[2 * b]) / stats[2 * b + 1]);
-  unsigned short* dst = x0 + ((int64_t)b * n + p) * C0p;
+  const uint32_t q4 = (uint32_t)C0p / 4;
+  const uint32_t g = blockIdx.x * NT + threadIdx.x;   // n * q4 < 2^31 (shape check)
+  if (g >= (uint32_t)n * q4) return;
+  const int p = (int)(g / q4);
+  const int c0 = 4 * (int)(g - (uint32_t)p * q4);
+  const float a0 = c0 == 0 ? (float)((loga[(int64_t)b * n + p] - stats[2 * b]) / stats[2 * b + 1]) : 0.f;
   const float* ph = phi + (int64_t)p * k;
-  for (int c0 = 0; c0 < C0p; c0 += 4) {
-    unsigned short h[4];
-    for (int u = 0; u < 4; ++u) {
-      const int c = c0 + u;
-      h[u] = to_bf16(c == 0 ? a0 : (c <= k ? ph[c - 1] : 0.f));
-    }
-    *reinterpret_cast<uint2*>(dst + c0) =
-        make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+  unsigned short h[4];
+  for (int u = 0; u < 4; ++u) {
+    const int c = c0 + u;
+    h[u] = to_bf16(c == 0 ? a0 : (c <= k ? ph[c - 1] : 0.f));
   }
+  *reinterpret_cast<uint2*>(x0 + ((int64_t)b * n + p) * C0p + c0) =
+      make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
 }
 
 // --------------------------------------------------------- weight layouts
@@ -467,14 +474,26 @@ __global__ __launch_bounds__(NT) void k_wgrad_reduce(int nsl, int ICp, int OCp, 
     gb[g - nW] = (float)s;
 }
 
-// float32 -> bfloat16 with channel padding: (rows, C) -> (rows, Cp)
-__global__ __launch_bounds__(NT) void k_pad_bf16(int64_t rows, int C, int Cp, const float* __restrict__ src,
+// float32 -> bfloat16 with channel padding: (rows, C) -> (rows, Cp); one
+// thread per 4 output channels of one row (one 8-byte store), with one
+// 16-byte load where C = Cp and src is 16-byte aligned (vec)
+__global__ __launch_bounds__(NT) void k_pad_bf16(int64_t rows, int C, int Cp, int vec, const float* __restrict__ src,
                                                  unsigned short* __restrict__ dst) {
-  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (g >= rows * Cp) return;
-  const int c = (int)(g % Cp);
-  const int64_t r = g / Cp;
-  dst[g] = to_bf16(c < C ? src[r * C + c] : 0.f);
+  const uint32_t q4 = (uint32_t)Cp / 4;
+  const uint32_t g = blockIdx.x * NT + threadIdx.x;   // rows * q4 < 2^31 (shape check)
+  if (g >= (uint32_t)rows * q4) return;
+  const uint32_t r = g / q4;
+  const int c0 = 4 * (int)(g - r * q4);
+  float v[4];
+  if (vec) {
+    const float4 f = *reinterpret_cast<const float4*>(src + (int64_t)r * C + c0);
+    v[0] = f.x, v[1] = f.y, v[2] = f.z, v[3] = f.w;
+  } else {
+    for (int u = 0; u < 4; ++u) v[u] = c0 + u < C ? src[(int64_t)r * C + c0 + u] : 0.f;
+  }
+  *reinterpret_cast<uint2*>(dst + (int64_t)r * Cp + c0) =
+      make_uint2((unsigned)to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16),
+                 (unsigned)to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16));
 }
 
 // Adam (bias-corrected) on float32 parameters
@@ -532,7 +551,7 @@ inline bool make_net(const nlsp_cnn_shape* s, Net& t) {
 
 struct NetLayout {
   double* stats;                 // (batch, 2)
-  int* modes;                    // (k, 2)
+  double* loga;                  // (batch n) log of the cell coefficients
   float* phi;                    // (n, k)
   unsigned short* x0;            // (batch n, cinp[0])
   unsigned short* z[3];          // (batch n, ch) pre-activations of layers 1..3
@@ -553,7 +572,7 @@ inline NetLayout carve_net(void* ws, const Net& t) {
   Carver c(ws);
   NetLayout L;
   L.stats = c.take<double>(2 * t.batch);
-  L.modes = c.take<int>(2 * t.k);
+  L.loga = c.take<double>(t.batch * t.n);
   L.phi = c.take<float>(t.n * t.k);
   const int64_t bn = t.batch * t.n;
   L.x0 = c.take<unsigned short>(bn * t.cinp[0]);
@@ -682,11 +701,12 @@ int cnn_fwd(const nlsp_cnn_shape* shape, const float* params, const double* coef
   const NetLayout L = carve_net(ws, t);
   hipStream_t s = as_stream(stream);
   const std::vector<int> modes = smooth_modes(t.k);
-  NLSP_HIP(hipMemcpyAsync(L.modes, modes.data(), sizeof(int) * modes.size(), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_sine_modes, dim3(ceil_div(t.n * t.k, NT)), dim3(NT), 0, s, t.N, t.k, L.modes, L.phi);
-  hipLaunchKernelGGL(k_field_stats, dim3(t.batch), dim3(NT), 0, s, coef, (int)t.n, L.stats);
-  hipLaunchKernelGGL(k_cnn_input, dim3(ceil_div(t.n, NT), t.batch), dim3(NT), 0, s, coef, L.stats, L.phi,
-                     (int)t.n, t.k, t.cinp[0], L.x0);
+  ModeTable tab{};
+  std::copy(modes.begin(), modes.end(), tab.ij);
+  hipLaunchKernelGGL(k_sine_modes, dim3(ceil_div(t.n * t.k, NT)), dim3(NT), 0, s, t.N, t.k, tab, L.phi);
+  hipLaunchKernelGGL(k_field_stats, dim3(t.batch), dim3(NT), 0, s, coef, (int)t.n, L.stats, L.loga);
+  hipLaunchKernelGGL(k_cnn_input, dim3(ceil_div(t.n * (t.cinp[0] / 4), NT), t.batch), dim3(NT), 0, s, L.loga,
+                     L.stats, L.phi, (int)t.n, t.k, t.cinp[0], L.x0);
   for (int l = 0; l < 4; ++l)
     hipLaunchKernelGGL(k_prep_weights, dim3(ceil_div(9 * t.coutp[l] * t.cinp[l], NT)), dim3(NT), 0, s,
                        params + t.woff[l], t.cin[l], t.cout[l], t.cinp[l], t.coutp[l], L.wf[l], L.wb[l]);
@@ -696,8 +716,6 @@ int cnn_fwd(const nlsp_cnn_shape* shape, const float* params, const double* coef
   if (rc == NLSP_OK) rc = conv<true, 1>(t, t.ch, t.k, L.z[2], L.wf[3], params + t.boff[3], L.phi, nullptr, Phat, s);
   if (rc != NLSP_OK) return rc;
   NLSP_HIP(hipGetLastError());
-  // the modes table is a host local: its copy must finish before return
-  NLSP_HIP(hipStreamSynchronize(s));
   return NLSP_OK;
 }
 
@@ -712,8 +730,9 @@ int cnn_bwd(const nlsp_cnn_shape* shape, const float* params, const float* gPhat
   hipStream_t s = as_stream(stream);
   const int64_t bn = t.batch * t.n;
   // dz4 = dP_hat (the residual Phi and the bias add pass gradients through)
-  hipLaunchKernelGGL(k_pad_bf16, dim3(ceil_div(bn * t.coutp[3], NT)), dim3(NT), 0, s, bn, t.k, t.coutp[3], gPhat,
-                     L.dz[3]);
+  const int vec = t.k == t.coutp[3] && (reinterpret_cast<uintptr_t>(gPhat) & 15) == 0;
+  hipLaunchKernelGGL(k_pad_bf16, dim3(ceil_div(bn * (t.coutp[3] / 4), NT)), dim3(NT), 0, s, bn, t.k, t.coutp[3], vec,
+                     gPhat, L.dz[3]);
   int rc = wgrad<true>(t, 3, L.z[2], L.dz[3], L.part, gparams + t.woff[3], gparams + t.boff[3], s);
   // dz3 = (W4^T * dz4) GELU'(z3), and so on down to layer 1
   for (int l = 3; l >= 1 && rc == NLSP_OK; --l) {
